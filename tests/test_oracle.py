@@ -1,0 +1,324 @@
+"""Pins of the CPU oracle against things other than itself (no GPU).
+
+Each test checks the oracle (Brandes in C, and the plain transcription of
+Algorithms 1-3) against brute-force enumeration, closed forms, invariants, a
+hand-derived worked example, or an independent library, so that a dropped
+term, a wrong sign or index, or a transposed operand in the oracle fails here.
+"""
+import itertools
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute, mfbc_ref
+from oracle.frontier import forward_frontiers, backward_heights
+from paper_1609_07008_amd import graphgen as gg
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def rel_close(a, b, tol):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    assert a.shape == b.shape
+    zero = b == 0
+    assert np.all(a[zero] == 0), "zeros must be exact"
+    if (~zero).any():
+        err = np.abs(a[~zero] - b[~zero]) / np.abs(b[~zero])
+        assert err.max() <= tol, f"max rel err {err.max()}"
+
+
+SMALL = [(n, p, seed, wr) for n, p, seed, wr in [
+    (6, 0.5, 1, None), (7, 0.6, 2, (1, 3)), (8, 0.4, 3, None), (8, 0.5, 4, (1, 2)),
+    (9, 0.35, 5, (1, 4)), (10, 0.3, 6, None), (10, 0.3, 7, (1, 5)), (11, 0.25, 8, (1, 3)),
+    (12, 0.2, 9, None), (12, 0.22, 10, (2, 6)), (5, 1.0, 11, None), (7, 1.0, 12, (1, 2)),
+]]
+
+
+@pytest.mark.parametrize("n,p,seed,wr", SMALL)
+def test_brandes_matches_brute_force(n, p, seed, wr):
+    g = gg.random_small_graph(n, p, seed, wr)
+    per, lam = brute.brute_bc(g, range(n))
+    r = oracle.brandes(g, np.arange(n), nthreads=2)
+    for s in range(n):
+        tau = [(-1 if t is None else t) for t in per[s]["tau"]]
+        assert r["dist"][s].tolist() == tau
+        assert r["sigma"][s].tolist() == [float(x) for x in per[s]["sigma"]]
+        rel_close(r["delta"][s], [float(x) for x in per[s]["delta"]], 1e-13)
+        hb = brute.dag_heights(g, s, per[s]["tau"])
+        assert r["height"][s].tolist() == [(-1 if h is None else h) for h in hb]
+    rel_close(r["lambda"], [float(x) for x in lam], 1e-13)
+
+
+@pytest.mark.parametrize("n,p,seed,wr", SMALL)
+def test_algorithms_1_to_3_match_brute_force(n, p, seed, wr):
+    g = gg.random_small_graph(n, p, seed, wr)
+    per, lam = brute.brute_bc(g, range(n))
+    src = np.arange(n)
+    f = mfbc_ref.mfbf(g, src)
+    b = mfbc_ref.mfbr(g, src, f["dist"], f["sigma"])
+    for s in range(n):
+        assert f["dist"][s].tolist() == [(-1 if t is None else t) for t in per[s]["tau"]]
+        assert f["sigma"][s].tolist() == [float(x) for x in per[s]["sigma"]]
+        dep = b["zeta"][s] * f["sigma"][s]
+        dep[s] = 0.0
+        rel_close(dep, [float(x) for x in per[s]["delta"]], 1e-13)
+    for batch in (1, 3, n):
+        rel_close(mfbc_ref.mfbc(g, src, batch), [float(x) for x in lam], 1e-13)
+
+
+def _load_golden(name):
+    spec = {"edges": [], "sources": {}}
+    cur = None
+    with open(os.path.join(HERE, "golden", name)) as fh:
+        for line in fh:
+            line = line.split("#", 1)[0].strip()
+            if not line:
+                continue
+            key, *rest = line.split()
+            if key == "n":
+                spec["n"] = int(rest[0])
+            elif key == "edge":
+                spec["edges"].append(tuple(int(x) for x in rest))
+            elif key == "source":
+                cur = spec["sources"].setdefault(int(rest[0]), {"frontier": {}})
+            elif key == "frontier":
+                cur["frontier"][int(rest[0])] = [int(x) for x in rest[1:]]
+            elif key == "lambda":
+                spec["lambda"] = [Fraction(x) for x in rest]
+            elif key in ("dist", "sigma", "height"):
+                cur[key] = [int(x) for x in rest]
+            elif key == "delta":
+                cur[key] = [Fraction(x) for x in rest]
+    u, v, w = zip(*spec["edges"])
+    spec["graph"] = gg.csr_from_edges(spec["n"], u, v, w, name)
+    return spec
+
+
+def test_golden_weighted5():
+    spec = _load_golden("weighted5.txt")
+    g = spec["graph"]
+    srcs = sorted(spec["sources"])
+    r = oracle.brandes(g, srcs)
+    f = mfbc_ref.mfbf(g, srcs)
+    b = mfbc_ref.mfbr(g, srcs, f["dist"], f["sigma"])
+    for i, s in enumerate(srcs):
+        want = spec["sources"][s]
+        assert r["dist"][i].tolist() == want["dist"]
+        assert f["dist"][i].tolist() == want["dist"]
+        assert r["sigma"][i].tolist() == want["sigma"]
+        assert f["sigma"][i].tolist() == want["sigma"]
+        rel_close(r["delta"][i], [float(x) for x in want["delta"]], 1e-15)
+        dep = b["zeta"][i] * f["sigma"][i]
+        dep[s] = 0
+        rel_close(dep, [float(x) for x in want["delta"]], 1e-15)
+        if "height" in want:
+            assert r["height"][i].tolist() == want["height"]
+            assert b["step"][i].tolist() == want["height"]
+        if want["frontier"]:
+            J = max(want["frontier"])
+            fr = forward_frontiers(g, s)
+            assert len(fr) == J
+            for j, verts in want["frontier"].items():
+                assert np.flatnonzero(fr[j - 1]).tolist() == verts
+                assert np.flatnonzero(f["frontiers"][j - 1][i]).tolist() == verts
+    rel_close(r["lambda"], [float(x) for x in spec["lambda"]], 1e-15)
+    rel_close(mfbc_ref.mfbc(g, srcs, 1), [float(x) for x in spec["lambda"]], 1e-15)
+
+
+# ----------------------------------------------------------------- closed forms
+def _bc(g):
+    return oracle.brandes(g, np.arange(g.n), per_source=False)["lambda"]
+
+
+@pytest.mark.parametrize("n", [2, 3, 7, 12])
+def test_path_closed_form(n):
+    want = [2 * i * (n - 1 - i) for i in range(n)]
+    assert _bc(gg.path_graph(n)).tolist() == want
+    assert _bc(gg.path_graph(n, w=7)).tolist() == want          # weights don't matter on trees
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 9])
+def test_star_closed_form(k):
+    lam = _bc(gg.star_graph(k))
+    assert lam[0] == k * (k - 1) and np.all(lam[1:] == 0)
+
+
+@pytest.mark.parametrize("n", [3, 4, 5, 6, 9, 10])
+def test_cycle_closed_form(n):
+    r = n // 2
+    want = r * (r - 1) if n % 2 else (r - 1) ** 2
+    rel_close(_bc(gg.cycle_graph(n)), np.full(n, float(want)), 1e-14)
+
+
+@pytest.mark.parametrize("n", [2, 5, 9])
+def test_complete_graph_zero(n):
+    assert np.all(_bc(gg.complete_graph(n)) == 0)
+    assert np.all(_bc(gg.complete_graph(n, w=3)) == 0)
+
+
+@pytest.mark.parametrize("a,b", [(1, 4), (2, 3), (3, 5), (4, 4)])
+def test_complete_bipartite_closed_form(a, b):
+    lam = _bc(gg.complete_bipartite_graph(a, b))
+    rel_close(lam[:a], np.full(a, b * (b - 1) / a), 1e-14)
+    rel_close(lam[a:], np.full(b, a * (a - 1) / b), 1e-14)
+
+
+def test_grid_path_counts_are_binomials():
+    a, b = 6, 9
+    r = oracle.brandes(gg.grid_graph(a, b), [0])
+    f = mfbc_ref.mfbf(gg.grid_graph(a, b), [0], trace=False)
+    want = [math.comb(i + j, i) for i in range(a) for j in range(b)]
+    assert r["sigma"][0].tolist() == want
+    assert f["sigma"][0].tolist() == want
+
+
+def test_diamond_chain_counts_are_powers_of_two():
+    k = 60                                     # 2**60 > 2**53: still exact (a power of two)
+    g = gg.diamond_chain(k)
+    r = oracle.brandes(g, [0])
+    assert r["sigma"][0][3 * k] == 2.0 ** k
+    assert all(r["sigma"][0][3 * i] == 2.0 ** i for i in range(k + 1))
+
+
+def test_layered_bipartite_counts_are_powers():
+    L, wdt = 6, 5
+    g = gg.layered_bipartite(L, wdt)
+    r = oracle.brandes(g, [0])
+    for layer in range(L):
+        ids = range(1 + layer * wdt, 1 + (layer + 1) * wdt)
+        assert all(r["sigma"][0][v] == wdt ** layer for v in ids)
+
+
+# ----------------------------------------------------------------- invariants
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_unweighted_sum_invariant(seed):
+    """Unweighted: sum_v lambda_S(v) = sum_{s in S} sum_{t reachable, t != s} (d(s,t) - 1)."""
+    g = gg.rmat_graph(9, 4, seed)
+    src = gg.pick_sources(g, 40, seed)
+    r = oracle.brandes(g, src)
+    d = r["dist"]
+    want = np.where(d > 0, d - 1, 0).sum()
+    assert abs(r["lambda"].sum() - want) <= 1e-9 * want
+
+
+def test_weight_scaling_and_relabel_invariance():
+    g = gg.er_graph(300, 6, 5, (1, 9))
+    lam = _bc(g)
+    rel_close(_bc(gg.scale_weights(g, 3)), lam, 1e-12)
+    perm = np.random.default_rng(0).permutation(g.n)
+    lam2 = _bc(gg.relabel(g, perm))
+    rel_close(lam2[perm], lam, 1e-12)
+
+
+def test_isolated_and_disconnected():
+    g = gg.csr_from_edges(7, [0, 1, 4], [1, 2, 5], None)      # 3, 6 isolated
+    r = oracle.brandes(g, np.arange(7))
+    assert r["lambda"].tolist() == [0, 2, 0, 0, 0, 0, 0]
+    assert r["dist"][3].tolist() == [-1, -1, -1, 0, -1, -1, -1]
+    assert r["sigma"][0].tolist() == [1, 1, 1, 0, 0, 0, 0]
+
+
+def test_threads_do_not_change_result():
+    g = gg.er_graph(500, 8, 2, (1, 100))
+    src = np.arange(0, 500, 3)
+    a = oracle.brandes(g, src, nthreads=1)
+    b = oracle.brandes(g, src, nthreads=4)
+    assert np.array_equal(a["dist"], b["dist"]) and np.array_equal(a["sigma"], b["sigma"])
+    rel_close(b["lambda"], a["lambda"], 1e-13)
+
+
+def test_networkx_cross_check():
+    nx = pytest.importorskip("networkx")
+    for g in (gg.er_graph(120, 5, 3, (1, 20)), gg.rmat_graph(7, 4, 4)):
+        G = nx.Graph()
+        G.add_nodes_from(range(g.n))
+        u, v, w = g.edges()
+        for i in range(u.size):
+            G.add_edge(int(u[i]), int(v[i]), weight=1 if w is None else int(w[i]))
+        ref = nx.betweenness_centrality(G, normalized=False,
+                                        weight=None if g.w is None else "weight")
+        ref = np.array([ref[i] for i in range(g.n)]) * 2          # ordered pairs
+        rel_close(_bc(g), ref, 1e-10)
+
+
+def test_duplicate_sources_count_twice():
+    g = gg.er_graph(50, 4, 9, (1, 5))
+    a = oracle.brandes(g, [3, 7], per_source=False)["lambda"]
+    b = oracle.brandes(g, [3, 7, 7], per_source=False)["lambda"]
+    c = oracle.brandes(g, [7], per_source=False)["lambda"]
+    rel_close(b, a + c, 1e-13)
+
+
+# ----------------------------------------------------------------- frontiers
+@pytest.mark.parametrize("n,p,seed,wr", SMALL[:8])
+def test_forward_frontier_closed_form_matches_walk_enumeration(n, p, seed, wr):
+    g = gg.random_small_graph(n, p, seed, wr)
+    for s in range(0, n, 3):
+        fr = forward_frontiers(g, s)
+        ell, _ = brute.walk_minima(g, s, len(fr))
+        best = [ell[0][v] for v in range(n)]
+        for j in range(1, len(fr) + 1):
+            want = [ell[j][v] is not None and (best[v] is None or ell[j][v] <= best[v])
+                    for v in range(n)]
+            assert fr[j - 1].tolist() == want
+            best = [b if e is None else (e if b is None else min(b, e))
+                    for b, e in zip(best, ell[j])]
+        assert not fr[-1].any()
+
+
+@pytest.mark.parametrize("wr", [None, (1, 100), (1, 3)])
+def test_algorithm_1_frontiers_match_closed_form(wr):
+    g = gg.er_graph(200, 5, 21, wr)
+    src = np.arange(0, 200, 13)
+    f = mfbc_ref.mfbf(g, src)
+    for i, s in enumerate(src):
+        fr = forward_frontiers(g, int(s))
+        assert len(fr) <= f["products"]
+        for j in range(f["products"]):
+            want = fr[j] if j < len(fr) else np.zeros(g.n, bool)
+            assert np.array_equal(f["frontiers"][j][i], want)
+    assert f["products"] == max(len(forward_frontiers(g, int(s))) for s in src)
+
+
+def test_unweighted_frontiers_are_bfs_levels():
+    g = gg.rmat_graph(8, 6, 2)
+    src = gg.pick_sources(g, 10, 3)
+    r = oracle.brandes(g, src)
+    f = mfbc_ref.mfbf(g, src)
+    for i in range(src.size):
+        for j, F in enumerate(f["frontiers"], start=1):
+            assert np.array_equal(F[i], r["dist"][i] == j)
+    # one product per BFS level plus the product that finds nothing new
+    assert f["products"] == r["dist"].max() + 1
+
+
+@pytest.mark.parametrize("wr", [None, (1, 100)])
+def test_algorithm_2_steps_are_dag_heights(wr):
+    g = gg.er_graph(200, 5, 22, wr)
+    src = np.arange(0, 200, 17)
+    r = oracle.brandes(g, src)
+    f = mfbc_ref.mfbf(g, src, trace=False)
+    b = mfbc_ref.mfbr(g, src, f["dist"], f["sigma"])
+    assert np.array_equal(b["step"], r["height"])
+    # counting product + one product per height level (the last finds nothing)
+    assert b["products"] == 1 + r["height"].max() + 1
+    for i in range(src.size):
+        B = backward_heights(r["height"][i])
+        for k, Bk in enumerate(B):
+            assert np.array_equal(b["step"][i] == k, Bk)
+
+
+def test_unweighted_product_bound():
+    """<= 2d+1 products per batch once the two idle closing products are dropped (Thm. 2)."""
+    g = gg.rmat_graph(8, 6, 7)
+    src = gg.pick_sources(g, 16, 1)
+    r = oracle.brandes(g, src)
+    f = mfbc_ref.mfbf(g, src, trace=False)
+    b = mfbc_ref.mfbr(g, src, f["dist"], f["sigma"], trace=False)
+    d = int(r["dist"].max())
+    assert (f["products"] - 1) + (b["products"] - 1) <= 2 * d + 1
