@@ -1,0 +1,181 @@
+/*
+ * mfbc.h -- C ABI of libmfbc: maximal frontier betweenness centrality (MFBC)
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Solomonik, Besta, Vella, Hoefler, "Scaling Betweenness Centrality
+ * using Communication-Efficient Sparse Matrix Multiplication", SC17.
+ *   - MFBF (Section 4.1, Algorithm 1): shortest distances and path counts of
+ *     a batch of sources by repeated products of a frontier of multpaths
+ *     (weight, multiplicity) with the adjacency matrix; the multpath monoid
+ *     keeps the least weight and adds the multiplicities of ties; the next
+ *     frontier keeps the entries no heavier than what is already known.
+ *   - MFBr (Section 4.2, Algorithm 2): partial centrality factors
+ *     zeta = delta / sigma by products of centpath frontiers (weight, partial
+ *     centrality, counter) with the transposed adjacency, a vertex joining
+ *     the frontier once all its shortest-path successors have reported.
+ *   - MFBC (Section 4.3, Algorithm 3): lambda accumulated batch by batch.
+ * Definitions (Section 2.4, Table 1): tau(s,v) distance, sigma(s,v) number
+ * of shortest paths, delta(s,v) = sum_t sigma(s,t,v)/sigma(s,t) with
+ * sigma(s,t,s) = sigma(s,t,t) = 0, lambda(v) = sum_s delta(s,v) over ordered
+ * pairs, no halving or normalisation.
+ *
+ * Conventions shared by every call
+ *   - Status: every int-returning call returns MFBC_OK (0) or a negative
+ *     MFBC_E* code; mfbc_last_error() then describes the failure (a
+ *     thread-local string, valid until the next call on that thread).
+ *     Arguments are validated before any device work; on an error no output
+ *     has been written.
+ *   - Device pointers ("d_") are caller-owned device memory of the current
+ *     HIP device (for example torch tensors); host pointers ("h_") are plain
+ *     host memory.  The library owns only the graph and its workspace.
+ *   - hip_stream is a hipStream_t (NULL = the default stream).  Calls are
+ *     ordered on that stream and return after their outputs are complete
+ *     (they synchronise on the stream to read frontier sizes).
+ *   - Source-major outputs are row-major [nb][n]: entry (s, v) at s*n + v,
+ *     where s indexes the listed sources.
+ *   - A graph handle may be used by one thread at a time.
+ */
+#ifndef MFBC_H
+#define MFBC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MFBC_INF_DIST 0x7fffffff /* distance of an unreachable vertex */
+
+enum mfbc_status {
+    MFBC_OK = 0,
+    MFBC_EINVAL = -1,    /* malformed argument, graph or source          */
+    MFBC_ENOMEM = -2,    /* device or host allocation failed              */
+    MFBC_EDEVICE = -3,   /* a HIP runtime call or kernel launch failed    */
+    MFBC_EOVERFLOW = -4  /* distances could exceed int32, or a path count */
+                         /* overflowed binary64                           */
+};
+
+enum mfbc_flags {
+    MFBC_UNDIRECTED = 1, /* symmetric CSR required and checked            */
+    MFBC_DIRECTED = 2    /* CSR lists out-arcs; distances follow arcs     */
+};
+
+typedef struct mfbc_graph mfbc_graph;
+
+/*
+ * mfbc_load_graph -- copy a graph to the device (the adjacency matrix A of
+ * Section 2.1: A(u,v) = weight of arc u->v, absent arcs are infinite).
+ *   n        vertices, 1 <= n < 2^31 - 1.
+ *   n_arcs   number of arcs (2m for an undirected graph with m edges).
+ *   h_row_ptr[n+1], h_col_idx[n_arcs]: host CSR of out-arcs; row_ptr[0] = 0,
+ *            non-decreasing, row_ptr[n] = n_arcs; each row's columns strictly
+ *            increasing (no duplicate arcs), in [0,n), no self-loops.
+ *   h_weight[n_arcs]: host integer weights >= 1, or NULL (every weight 1).
+ *            Zero or negative weights are rejected (zero-weight cycles would
+ *            give infinitely many shortest walks).
+ *   flags    MFBC_UNDIRECTED (the CSR must be symmetric with equal weights on
+ *            both arcs) or MFBC_DIRECTED.
+ *   out      receives the handle.
+ * Errors: EINVAL (malformed CSR, weight <= 0, asymmetric undirected input),
+ * EOVERFLOW (n * max weight >= 2^31 - 1), ENOMEM, EDEVICE.
+ */
+int mfbc_load_graph(int32_t n, int64_t n_arcs, const int64_t *h_row_ptr,
+                    const int32_t *h_col_idx, const int32_t *h_weight,
+                    uint32_t flags, void *hip_stream, mfbc_graph **out);
+
+/* Release a graph and its device workspace (NULL is accepted). */
+int mfbc_free_graph(mfbc_graph *g);
+
+/*
+ * mfbc_forward -- MFBF (Algorithm 1) for nb sources: tau and sigma.
+ *   d_sources[nb]  device, vertex ids in [0,n); repeats allowed.
+ *   d_dist[nb][n]  device out: tau(s,v), MFBC_INF_DIST if unreachable,
+ *                  0 at the source.
+ *   d_sigma[nb][n] device out: sigma(s,v) in binary64 (1 at the source,
+ *                  0 if unreachable).
+ *   h_products     host out (nullable): number of frontier products.
+ * Errors: EINVAL (nb < 1, bad source), EOVERFLOW (a path count became
+ * infinite), ENOMEM, EDEVICE.
+ */
+int mfbc_forward(mfbc_graph *g, const int32_t *d_sources, int32_t nb,
+                 int32_t *d_dist, double *d_sigma, int32_t *h_products,
+                 void *hip_stream);
+
+/*
+ * mfbc_backward -- MFBr (Algorithm 2) from a forward result: dependencies.
+ *   d_sources[nb], d_dist[nb][n], d_sigma[nb][n]: as produced by
+ *                  mfbc_forward for the same sources (device).
+ *   d_delta[nb][n] device out: delta(s,v) = zeta(s,v) * sigma(s,v); 0 at the
+ *                  source itself, at leaves and at unreachable vertices.
+ *   h_products     host out (nullable): backward products, counting product
+ *                  included.
+ * Errors: EINVAL, ENOMEM, EDEVICE.
+ */
+int mfbc_backward(mfbc_graph *g, const int32_t *d_sources, int32_t nb,
+                  const int32_t *d_dist, const double *d_sigma, double *d_delta,
+                  int32_t *h_products, void *hip_stream);
+
+/*
+ * mfbc_bc -- MFBC (Algorithm 3): lambda over a list of sources.
+ *   d_sources[n_sources] device; each occurrence counts once (a repeated
+ *                  source contributes twice).  The full vertex set gives
+ *                  exact betweenness; a subset gives the unscaled partial
+ *                  sum sum_{s in S} delta(s,.).
+ *   batch          sources per batch (n_b of Section 4); the last batch may
+ *                  be smaller.  The result does not depend on it beyond
+ *                  rounding.
+ *   d_bc[n]        device out, overwritten.
+ * Errors: EINVAL (n_sources < 0, batch < 1, bad source), EOVERFLOW,
+ * ENOMEM, EDEVICE.
+ */
+int mfbc_bc(mfbc_graph *g, const int32_t *d_sources, int64_t n_sources,
+            int32_t batch, double *d_bc, void *hip_stream);
+
+/*
+ * mfbc_forward_trace -- mfbc_forward that also records frontier membership.
+ *   d_fmask[nb][n] device out (uint64): bit j-1 is set when v is in the
+ *                  frontier produced by product j for source s (first
+ *                  frontier = the source itself, before product 1); only
+ *                  products 1..64 are recorded.
+ *   h_nnz[max_products] host out (nullable): total frontier entries produced
+ *                  by each product (all sources); entries past the last
+ *                  product are left untouched.
+ */
+int mfbc_forward_trace(mfbc_graph *g, const int32_t *d_sources, int32_t nb,
+                       int32_t *d_dist, double *d_sigma, uint64_t *d_fmask,
+                       int64_t *h_nnz, int32_t max_products,
+                       int32_t *h_products, void *hip_stream);
+
+/*
+ * mfbc_backward_trace -- mfbc_backward that also records, for every
+ * reachable (s,v), the index k of the backward frontier B_k it entered
+ * (k = 0: leaves found by the counting product); -1 for unreachable.
+ *   d_step[nb][n]  device out (int32).
+ */
+int mfbc_backward_trace(mfbc_graph *g, const int32_t *d_sources, int32_t nb,
+                        const int32_t *d_dist, const double *d_sigma,
+                        double *d_delta, int32_t *d_step,
+                        int32_t *h_products, void *hip_stream);
+
+/* Work counters of the last forward/backward/bc call on a graph. */
+typedef struct mfbc_stats {
+    int64_t fwd_products;   /* forward products over all batches          */
+    int64_t bwd_products;   /* backward products (counting ones included)  */
+    int64_t fwd_entries;    /* sum over products of frontier entries       */
+    int64_t bwd_entries;    /* sum over backward frontiers of entries      */
+    int64_t batches;
+} mfbc_stats;
+
+int mfbc_get_stats(const mfbc_graph *g, mfbc_stats *out);
+
+/* Graph facts: vertices, arcs, maximum weight. */
+int mfbc_graph_info(const mfbc_graph *g, int32_t *n, int64_t *n_arcs,
+                    int32_t *max_weight);
+
+/* Human-readable description of the last failure on this thread. */
+const char *mfbc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MFBC_H */

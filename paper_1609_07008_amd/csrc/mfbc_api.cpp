@@ -1,0 +1,481 @@
+// C ABI of libmfbc (declared in include/mfbc.h): validation, device memory,
+// and the host loops of Algorithms 1-3 around the HIP kernels.
+//
+// Per batch (Algorithm 3): initialise T and the first frontier (the sources
+// themselves), then repeat the forward product until a product yields an
+// empty frontier (Algorithm 1's loop condition, over all columns of the
+// batch); then the counting product and the backward products until the
+// backward frontier is empty (Algorithm 2); lambda parts are accumulated by
+// the kernels as entries complete.  The size of each new frontier is read
+// back after every product (a 256-byte copy and a stream synchronisation);
+// that is the only host round trip of the loop.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mfbc_internal.h"
+
+using namespace mfbc;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(MFBC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+        else prev = -1;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+template <typename T>
+int dalloc(T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(MFBC_ENOMEM, std::string("device allocation of ") +
+                                     std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+    return MFBC_OK;
+}
+
+template <typename T>
+void dfree(T *&p) {
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+void free_workspace(Workspace &ws) {
+    dfree(ws.tdist);
+    dfree(ws.tsig);
+    for (int i = 0; i < 2; i++) {
+        dfree(ws.fdist[i]);
+        dfree(ws.fsig[i]);
+        dfree(ws.fbits[i]);
+        dfree(ws.abits[i]);
+    }
+    dfree(ws.pd);
+    dfree(ws.pm);
+    dfree(ws.counters);
+    dfree(ws.flags);
+    dfree(ws.lam);
+    dfree(ws.src);
+    dfree(ws.fmask);
+    if (ws.h_counters) (void)hipHostFree(ws.h_counters);
+    ws.h_counters = nullptr;
+    ws.ncg = 0;
+    ws.fmask_ncg = 0;
+}
+
+void free_plan(Plan &p) {
+    dfree(p.tasks);
+    dfree(p.hubs);
+    p.ntasks = p.nhubs = p.nslots = 0;
+}
+
+int upload_plan(int32_t n, const int64_t *h_rp, const TaskParams &prm, Plan &plan) {
+    std::vector<Task> tasks;
+    std::vector<Hub> hubs;
+    int32_t nslots = 0;
+    build_plan(n, h_rp, prm, tasks, hubs, nslots);
+    free_plan(plan);
+    int rc;
+    if ((rc = dalloc(&plan.tasks, tasks.size()))) return rc;
+    if ((rc = dalloc(&plan.hubs, hubs.size()))) return rc;
+    if (!tasks.empty())
+        HIP_TRY(hipMemcpy(plan.tasks, tasks.data(), tasks.size() * sizeof(Task), hipMemcpyHostToDevice));
+    if (!hubs.empty())
+        HIP_TRY(hipMemcpy(plan.hubs, hubs.data(), hubs.size() * sizeof(Hub), hipMemcpyHostToDevice));
+    plan.ntasks = (int32_t)tasks.size();
+    plan.nhubs = (int32_t)hubs.size();
+    plan.nslots = nslots;
+    return MFBC_OK;
+}
+
+// Grow the workspace to `ncg` column groups (and the trace mask if asked).
+int ensure_workspace(mfbc_graph *g, int ncg, bool trace) {
+    Workspace &ws = g->ws;
+    if (ws.ncg < ncg) {
+        free_workspace(ws);
+        const size_t n = (size_t)g->n;
+        const size_t tile = n * kWave * (size_t)ncg;
+        const size_t nwords = (n + 31) / 32;
+        const size_t slots =
+            (size_t)std::max(g->plan_in.nslots, g->plan_out.nslots) * kWave * (size_t)ncg;
+        int rc = MFBC_OK;
+        if ((rc = dalloc(&ws.tdist, tile)) || (rc = dalloc(&ws.tsig, tile)) ||
+            (rc = dalloc(&ws.fdist[0], tile)) || (rc = dalloc(&ws.fdist[1], tile)) ||
+            (rc = dalloc(&ws.fsig[0], tile)) || (rc = dalloc(&ws.fsig[1], tile)) ||
+            (rc = dalloc(&ws.fbits[0], n * ncg)) || (rc = dalloc(&ws.fbits[1], n * ncg)) ||
+            (rc = dalloc(&ws.abits[0], nwords)) || (rc = dalloc(&ws.abits[1], nwords)) ||
+            (rc = dalloc(&ws.pd, slots)) || (rc = dalloc(&ws.pm, slots)) ||
+            (rc = dalloc(&ws.counters, (size_t)kCounterRing * kCounterSlots)) ||
+            (rc = dalloc(&ws.flags, 4)) || (rc = dalloc(&ws.lam, n * ncg)) ||
+            (rc = dalloc(&ws.src, (size_t)ncg * kWave))) {
+            free_workspace(ws);
+            return rc;
+        }
+        if (hipHostMalloc((void **)&ws.h_counters,
+                          sizeof(unsigned long long) * kCounterRing * kCounterSlots) != hipSuccess) {
+            ws.h_counters = nullptr;
+            free_workspace(ws);
+            return fail(MFBC_ENOMEM, "pinned host allocation failed");
+        }
+        ws.ncg = ncg;
+    }
+    if (trace && ws.fmask_ncg < ncg) {
+        dfree(ws.fmask);
+        int rc = dalloc(&ws.fmask, (size_t)g->n * kWave * (size_t)ncg);
+        if (rc) return rc;
+        ws.fmask_ncg = ncg;
+    }
+    return MFBC_OK;
+}
+
+int read_counter(mfbc_graph *g, int idx, hipStream_t s, int64_t *out) {
+    Workspace &ws = g->ws;
+    const size_t off = (size_t)(idx % kCounterRing) * kCounterSlots;
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(ws.h_counters + off, ws.counters + off,
+                           sizeof(unsigned long long) * kCounterSlots, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    unsigned long long t = 0;
+    for (int i = 0; i < kCounterSlots; i++) t += ws.h_counters[off + i];
+    *out = (int64_t)t;
+    return MFBC_OK;
+}
+
+int check_sources(mfbc_graph *g, const int32_t *d_sources, int64_t count, hipStream_t s) {
+    if (count == 0) return MFBC_OK;
+    if (!d_sources) return fail(MFBC_EINVAL, "sources pointer is NULL");
+    std::vector<int32_t> h((size_t)count);
+    HIP_TRY(hipMemcpyAsync(h.data(), d_sources, (size_t)count * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int64_t i = 0; i < count; i++)
+        if (h[(size_t)i] < 0 || h[(size_t)i] >= g->n)
+            return fail(MFBC_EINVAL, "source " + std::to_string(h[(size_t)i]) + " at position " +
+                                         std::to_string(i) + " is outside [0, n)");
+    return MFBC_OK;
+}
+
+// Algorithm 1 on the batch whose sources are already in ws.src.
+int run_forward(mfbc_graph *g, int ncg, int nb, bool trace, int64_t *h_nnz, int max_products,
+                int32_t *products, hipStream_t s) {
+    launch_fwd_init(g, ncg, nb, s);
+    int64_t nnz = 0;
+    int j = 0;
+    do {
+        j++;
+        if (j > g->n + 1) return fail(MFBC_EDEVICE, "forward products did not converge");
+        launch_fwd_product(g, ncg, j, trace, s);
+        int rc = read_counter(g, j, s, &nnz);
+        if (rc) return rc;
+        if (h_nnz && j <= max_products) h_nnz[j - 1] = nnz;
+        g->stats.fwd_entries += nnz;
+    } while (nnz > 0);
+    g->stats.fwd_products += j;
+    if (products) *products = j;
+    int32_t flag = 0;
+    HIP_TRY(hipMemcpyAsync(&flag, g->ws.flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (flag) return fail(MFBC_EOVERFLOW, "a shortest-path count overflowed binary64");
+    return MFBC_OK;
+}
+
+// Algorithm 2 on the batch whose T is in the workspace.
+int run_backward(mfbc_graph *g, int ncg, int32_t *products, hipStream_t s) {
+    launch_bwd_count(g, ncg, s, false);
+    int64_t nnz = 0;
+    int rc = read_counter(g, 0, s, &nnz);
+    if (rc) return rc;
+    g->stats.bwd_entries += nnz;
+    int k = 0;
+    while (nnz > 0) {
+        k++;
+        if (k > g->n + 1) return fail(MFBC_EDEVICE, "backward products did not converge");
+        launch_bwd_product(g, ncg, k, false, s);
+        if ((rc = read_counter(g, k, s, &nnz))) return rc;
+        g->stats.bwd_entries += nnz;
+    }
+    g->stats.bwd_products += k + 1;
+    if (products) *products = k + 1;
+    return MFBC_OK;
+}
+
+int forward_impl(mfbc_graph *g, const int32_t *d_sources, int32_t nb, int32_t *d_dist,
+                 double *d_sigma, uint64_t *d_fmask, int64_t *h_nnz, int32_t max_products,
+                 int32_t *h_products, void *stream) {
+    if (!g) return fail(MFBC_EINVAL, "graph handle is NULL");
+    if (nb < 1) return fail(MFBC_EINVAL, "nb must be >= 1");
+    if (!d_dist || !d_sigma) return fail(MFBC_EINVAL, "output pointer is NULL");
+    if (h_nnz && max_products < 0) return fail(MFBC_EINVAL, "max_products must be >= 0");
+    DeviceGuard dg(g->device);
+    hipStream_t s = (hipStream_t)stream;
+    int rc = check_sources(g, d_sources, nb, s);
+    if (rc) return rc;
+    const int ncg = (nb + kWave - 1) / kWave;
+    if ((rc = ensure_workspace(g, ncg, d_fmask != nullptr))) return rc;
+    g->stats = mfbc_stats{};
+    launch_set_sources(g, ncg, nb, d_sources, s);
+    if ((rc = run_forward(g, ncg, nb, d_fmask != nullptr, h_nnz, max_products, h_products, s)))
+        return rc;
+    g->stats.batches = 1;
+    launch_export_forward(g, ncg, nb, d_dist, d_sigma, d_fmask, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    return MFBC_OK;
+}
+
+int backward_impl(mfbc_graph *g, const int32_t *d_sources, int32_t nb, const int32_t *d_dist,
+                  const double *d_sigma, double *d_delta, int32_t *d_step, int32_t *h_products,
+                  void *stream) {
+    if (!g) return fail(MFBC_EINVAL, "graph handle is NULL");
+    if (nb < 1) return fail(MFBC_EINVAL, "nb must be >= 1");
+    if (!d_dist || !d_sigma || !d_delta) return fail(MFBC_EINVAL, "array pointer is NULL");
+    DeviceGuard dg(g->device);
+    hipStream_t s = (hipStream_t)stream;
+    int rc = check_sources(g, d_sources, nb, s);
+    if (rc) return rc;
+    const int ncg = (nb + kWave - 1) / kWave;
+    if ((rc = ensure_workspace(g, ncg, false))) return rc;
+    g->stats = mfbc_stats{};
+    launch_set_sources(g, ncg, nb, d_sources, s);
+    launch_import_forward(g, ncg, nb, d_dist, d_sigma, s);
+    if ((rc = run_backward(g, ncg, h_products, s))) return rc;
+    g->stats.batches = 1;
+    launch_export_backward(g, ncg, nb, d_delta, d_step, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    return MFBC_OK;
+}
+
+// Symmetry check of an undirected CSR: the transpose must equal the CSR.
+bool build_transpose(int32_t n, int64_t arcs, const int64_t *rp, const int32_t *col,
+                     const int32_t *w, std::vector<int64_t> &rpt, std::vector<int32_t> &colt,
+                     std::vector<int32_t> &wt) {
+    rpt.assign((size_t)n + 1, 0);
+    for (int64_t e = 0; e < arcs; e++) rpt[(size_t)col[e] + 1]++;
+    for (int32_t v = 0; v < n; v++) rpt[(size_t)v + 1] += rpt[(size_t)v];
+    colt.assign((size_t)arcs, 0);
+    if (w) wt.assign((size_t)arcs, 0);
+    std::vector<int64_t> pos(rpt.begin(), rpt.end() - 1);
+    for (int32_t u = 0; u < n; u++)
+        for (int64_t e = rp[u]; e < rp[u + 1]; e++) {
+            const int64_t p = pos[(size_t)col[e]]++;
+            colt[(size_t)p] = u;
+            if (w) wt[(size_t)p] = w[e];
+        }
+    return true;
+}
+
+int upload_csr(int32_t n, int64_t arcs, const int64_t *rp, const int32_t *col, const int32_t *w,
+               Csr &c) {
+    int rc;
+    if ((rc = dalloc(&c.rp, (size_t)n + 1)) || (rc = dalloc(&c.col, (size_t)arcs))) return rc;
+    HIP_TRY(hipMemcpy(c.rp, rp, ((size_t)n + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+    if (arcs) HIP_TRY(hipMemcpy(c.col, col, (size_t)arcs * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (w) {
+        if ((rc = dalloc(&c.w, (size_t)arcs))) return rc;
+        if (arcs) HIP_TRY(hipMemcpy(c.w, w, (size_t)arcs * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    return MFBC_OK;
+}
+
+void free_graph_memory(mfbc_graph *g) {
+    free_workspace(g->ws);
+    free_plan(g->plan_in);
+    free_plan(g->plan_out);
+    const bool alias = g->in.rp == g->out.rp;
+    dfree(g->out.rp);
+    dfree(g->out.col);
+    dfree(g->out.w);
+    if (!alias) {
+        dfree(g->in.rp);
+        dfree(g->in.col);
+        dfree(g->in.w);
+    }
+    g->in = Csr{};
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mfbc_last_error(void) { return g_err.c_str(); }
+
+int mfbc_load_graph(int32_t n, int64_t n_arcs, const int64_t *h_row_ptr, const int32_t *h_col_idx,
+                    const int32_t *h_weight, uint32_t flags, void *hip_stream, mfbc_graph **out) {
+    if (!out) return fail(MFBC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || n == INT32_MAX) return fail(MFBC_EINVAL, "n must be in [1, 2^31 - 2]");
+    if (n_arcs < 0) return fail(MFBC_EINVAL, "n_arcs must be >= 0");
+    if (!h_row_ptr) return fail(MFBC_EINVAL, "row_ptr is NULL");
+    if (n_arcs > 0 && !h_col_idx) return fail(MFBC_EINVAL, "col_idx is NULL");
+    if (flags != MFBC_UNDIRECTED && flags != MFBC_DIRECTED)
+        return fail(MFBC_EINVAL, "flags must be MFBC_UNDIRECTED or MFBC_DIRECTED");
+    if (h_row_ptr[0] != 0 || h_row_ptr[n] != n_arcs)
+        return fail(MFBC_EINVAL, "row_ptr[0] must be 0 and row_ptr[n] must equal n_arcs");
+    int32_t maxw = 1;
+    for (int32_t v = 0; v < n; v++) {
+        if (h_row_ptr[v + 1] < h_row_ptr[v] || h_row_ptr[v + 1] > n_arcs)
+            return fail(MFBC_EINVAL, "row_ptr must be non-decreasing and end at n_arcs");
+        for (int64_t e = h_row_ptr[v]; e < h_row_ptr[v + 1]; e++) {
+            const int32_t c = h_col_idx[e];
+            if (c < 0 || c >= n) return fail(MFBC_EINVAL, "column index out of range");
+            if (c == v) return fail(MFBC_EINVAL, "self-loop at vertex " + std::to_string(v));
+            if (e > h_row_ptr[v] && h_col_idx[e - 1] >= c)
+                return fail(MFBC_EINVAL, "row " + std::to_string(v) +
+                                             " is not strictly increasing (duplicate arc?)");
+            if (h_weight) {
+                if (h_weight[e] < 1) return fail(MFBC_EINVAL, "weights must be >= 1");
+                maxw = std::max(maxw, h_weight[e]);
+            }
+        }
+    }
+    if ((int64_t)n * (int64_t)maxw >= (int64_t)INT32_MAX)
+        return fail(MFBC_EOVERFLOW, "n * max weight does not fit int32 distances");
+    std::vector<int64_t> rpt;
+    std::vector<int32_t> colt, wt;
+    build_transpose(n, n_arcs, h_row_ptr, h_col_idx, h_weight, rpt, colt, wt);
+    const bool directed = flags == MFBC_DIRECTED;
+    if (!directed) {
+        if (!std::equal(rpt.begin(), rpt.end(), h_row_ptr) ||
+            !std::equal(colt.begin(), colt.end(), h_col_idx) ||
+            (h_weight && !std::equal(wt.begin(), wt.end(), h_weight)))
+            return fail(MFBC_EINVAL, "undirected graph must have a symmetric CSR with equal weights");
+    }
+    mfbc_graph *g = new (std::nothrow) mfbc_graph();
+    if (!g) return fail(MFBC_ENOMEM, "host allocation failed");
+    if (hipGetDevice(&g->device) != hipSuccess) {
+        delete g;
+        return fail(MFBC_EDEVICE, "no HIP device");
+    }
+    g->n = n;
+    g->arcs = n_arcs;
+    g->maxw = maxw;
+    g->weighted = h_weight != nullptr;
+    g->directed = directed;
+    int rc = upload_csr(n, n_arcs, h_row_ptr, h_col_idx, h_weight, g->out);
+    if (!rc) {
+        if (directed)
+            rc = upload_csr(n, n_arcs, rpt.data(), colt.data(), h_weight ? wt.data() : nullptr, g->in);
+        else
+            g->in = g->out;
+    }
+    g->h_rp_out.assign(h_row_ptr, h_row_ptr + (size_t)n + 1);
+    g->h_rp_in = directed ? rpt : g->h_rp_out;
+    if (!rc) rc = upload_plan(n, g->h_rp_out.data(), g->params, g->plan_out);
+    if (!rc) rc = upload_plan(n, g->h_rp_in.data(), g->params, g->plan_in);
+    if (rc) {
+        free_graph_memory(g);
+        delete g;
+        return rc;
+    }
+    (void)hip_stream;
+    *out = g;
+    return MFBC_OK;
+}
+
+int mfbc_free_graph(mfbc_graph *g) {
+    if (!g) return MFBC_OK;
+    DeviceGuard dg(g->device);
+    (void)hipDeviceSynchronize();
+    free_graph_memory(g);
+    delete g;
+    return MFBC_OK;
+}
+
+int mfbc_forward(mfbc_graph *g, const int32_t *d_sources, int32_t nb, int32_t *d_dist,
+                 double *d_sigma, int32_t *h_products, void *hip_stream) {
+    return forward_impl(g, d_sources, nb, d_dist, d_sigma, nullptr, nullptr, 0, h_products,
+                        hip_stream);
+}
+
+int mfbc_forward_trace(mfbc_graph *g, const int32_t *d_sources, int32_t nb, int32_t *d_dist,
+                       double *d_sigma, uint64_t *d_fmask, int64_t *h_nnz, int32_t max_products,
+                       int32_t *h_products, void *hip_stream) {
+    if (!d_fmask) return fail(MFBC_EINVAL, "d_fmask is NULL");
+    return forward_impl(g, d_sources, nb, d_dist, d_sigma, d_fmask, h_nnz, max_products,
+                        h_products, hip_stream);
+}
+
+int mfbc_backward(mfbc_graph *g, const int32_t *d_sources, int32_t nb, const int32_t *d_dist,
+                  const double *d_sigma, double *d_delta, int32_t *h_products, void *hip_stream) {
+    return backward_impl(g, d_sources, nb, d_dist, d_sigma, d_delta, nullptr, h_products,
+                         hip_stream);
+}
+
+int mfbc_backward_trace(mfbc_graph *g, const int32_t *d_sources, int32_t nb, const int32_t *d_dist,
+                        const double *d_sigma, double *d_delta, int32_t *d_step,
+                        int32_t *h_products, void *hip_stream) {
+    if (!d_step) return fail(MFBC_EINVAL, "d_step is NULL");
+    return backward_impl(g, d_sources, nb, d_dist, d_sigma, d_delta, d_step, h_products,
+                         hip_stream);
+}
+
+int mfbc_bc(mfbc_graph *g, const int32_t *d_sources, int64_t n_sources, int32_t batch,
+            double *d_bc, void *hip_stream) {
+    if (!g) return fail(MFBC_EINVAL, "graph handle is NULL");
+    if (n_sources < 0) return fail(MFBC_EINVAL, "n_sources must be >= 0");
+    if (batch < 1) return fail(MFBC_EINVAL, "batch must be >= 1");
+    if (!d_bc) return fail(MFBC_EINVAL, "d_bc is NULL");
+    DeviceGuard dg(g->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    int rc = check_sources(g, d_sources, n_sources, s);
+    if (rc) return rc;
+    const int64_t width = std::max<int64_t>(1, std::min<int64_t>(batch, n_sources));
+    const int ncg = (int)((width + kWave - 1) / kWave);
+    if ((rc = ensure_workspace(g, ncg, false))) return rc;
+    g->stats = mfbc_stats{};
+    launch_lambda_zero(g, ncg, s);
+    for (int64_t b0 = 0; b0 < n_sources; b0 += batch) {
+        const int nb = (int)std::min<int64_t>(batch, n_sources - b0);
+        const int bcg = (nb + kWave - 1) / kWave;
+        launch_set_sources(g, bcg, nb, d_sources + b0, s);
+        if ((rc = run_forward(g, bcg, nb, false, nullptr, 0, nullptr, s))) return rc;
+        if ((rc = run_backward(g, bcg, nullptr, s))) return rc;
+        g->stats.batches++;
+    }
+    launch_lambda_reduce(g, ncg, d_bc, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    return MFBC_OK;
+}
+
+int mfbc_get_stats(const mfbc_graph *g, mfbc_stats *out) {
+    if (!g || !out) return fail(MFBC_EINVAL, "NULL argument");
+    *out = g->stats;
+    return MFBC_OK;
+}
+
+int mfbc_graph_info(const mfbc_graph *g, int32_t *n, int64_t *n_arcs, int32_t *max_weight) {
+    if (!g) return fail(MFBC_EINVAL, "graph handle is NULL");
+    if (n) *n = g->n;
+    if (n_arcs) *n_arcs = g->arcs;
+    if (max_weight) *max_weight = g->maxw;
+    return MFBC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,128 @@
+// Internal declarations of libmfbc (not part of the C ABI).
+//
+// Layout of the per-batch state in HBM ("column-group tiles"): the n_b
+// source columns of a batch are cut into groups of 64, one per wavefront
+// lane, and every per-(source, vertex) array is stored [cg][v][64]:
+// element (cg, v, lane) at ((cg * n) + v) * 64 + lane.  A wave that owns
+// (v, cg) touches 64 contiguous entries (256 B of int32, 512 B of double),
+// and a launch that walks the column groups one after another keeps the
+// working set of one group (n * 64 entries) hot in the 256 MB
+// infinity cache.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/mfbc.h"
+
+namespace mfbc {
+
+constexpr int kWave = 64;                // lanes per wavefront on CDNA
+constexpr int kWavesPerBlock = 4;        // 256-thread workgroups
+constexpr int kBlock = kWave * kWavesPerBlock;
+constexpr int32_t kInf = MFBC_INF_DIST;
+constexpr int kCounterSlots = 32;        // spread of the frontier-size counters
+constexpr int kCounterRing = 4;          // products whose counters are live at once
+
+// A unit of pull work for one wave (and one column group):
+//  * hub < 0: the whole adjacency rows of vertices [v0, v1), arcs [e0, e1);
+//  * hub >= 0: the slice [e0, e1) of vertex v0's row, written as partial
+//    number `part`; a merge kernel combines the parts of the hub.
+struct Task {
+    int32_t v0, v1;
+    int32_t hub, part;
+    int64_t e0, e1;
+};
+
+struct Hub {
+    int32_t v;       // vertex id
+    int32_t first;   // first partial slot
+    int32_t nparts;  // number of slices
+    int32_t pad;
+};
+
+// Tunables of the work decomposition (chosen by the autotuner; defaults
+// are used when none is set).
+struct TaskParams {
+    int run_arcs = 512;   // arcs per light run
+    int run_verts = 64;   // vertices per light run (<= 64)
+    int heavy = 1024;     // degree above which a row is split
+    int slice = 512;      // arcs per slice of a split row
+};
+
+// Work decomposition of one CSR orientation.
+struct Plan {
+    Task *tasks = nullptr;   // device
+    Hub *hubs = nullptr;     // device
+    int32_t ntasks = 0, nhubs = 0, nslots = 0;
+};
+
+// Device CSR of one orientation (out-arcs or in-arcs).
+struct Csr {
+    int64_t *rp = nullptr;
+    int32_t *col = nullptr;
+    int32_t *w = nullptr;    // nullptr: unweighted (all 1)
+};
+
+struct Workspace {
+    int ncg = 0;                       // capacity in column groups
+    int32_t *tdist = nullptr;          // T.w      [cg][n][64]
+    double *tsig = nullptr;            // T.m      [cg][n][64]
+    int32_t *fdist[2] = {nullptr, nullptr};  // frontier weights (double-buffered)
+    double *fsig[2] = {nullptr, nullptr};    // frontier multiplicities
+    uint64_t *fbits[2] = {nullptr, nullptr}; // frontier lane masks [cg][n]
+    uint32_t *abits[2] = {nullptr, nullptr}; // any-column activity bitmaps [n/32]
+    int32_t *pd = nullptr;             // partial weights / counters [cg][slots][64]
+    double *pm = nullptr;              // partial multiplicities / sums
+    unsigned long long *counters = nullptr;  // [ring][slots]
+    int32_t *flags = nullptr;          // [0]: path count overflow
+    double *lam = nullptr;             // per-column-group lambda parts [cg][n]
+    int32_t *src = nullptr;            // column -> source vertex, -1 = padding
+    uint64_t *fmask = nullptr;         // trace: forward membership [cg][n][64]
+    int fmask_ncg = 0;
+    unsigned long long *h_counters = nullptr;  // pinned host copy
+};
+
+}  // namespace mfbc
+
+struct mfbc_graph {
+    int device = 0;
+    int32_t n = 0;
+    int64_t arcs = 0;
+    int32_t maxw = 1;
+    bool weighted = false;
+    bool directed = false;
+    mfbc::Csr out;          // out-arcs (backward products, counting product)
+    mfbc::Csr in;           // in-arcs (forward products); aliases `out` if undirected
+    mfbc::Plan plan_out, plan_in;
+    mfbc::TaskParams params;
+    mfbc::Workspace ws;
+    mfbc_stats stats{};
+    std::vector<int64_t> h_rp_out, h_rp_in;   // host copies for re-planning
+};
+
+namespace mfbc {
+
+// ---- launchers (kernels.hip) ----
+void launch_fwd_init(mfbc_graph *g, int ncg, int nb, hipStream_t s);
+void launch_fwd_product(mfbc_graph *g, int ncg, int j, bool trace, hipStream_t s);
+void launch_bwd_count(mfbc_graph *g, int ncg, hipStream_t s, bool trace);
+void launch_bwd_product(mfbc_graph *g, int ncg, int k, bool trace, hipStream_t s);
+void launch_lambda_zero(mfbc_graph *g, int ncg, hipStream_t s);
+void launch_lambda_reduce(mfbc_graph *g, int ncg, double *d_bc, hipStream_t s);
+void launch_export_forward(mfbc_graph *g, int ncg, int nb, int32_t *d_dist, double *d_sigma,
+                           uint64_t *d_fmask, hipStream_t s);
+void launch_import_forward(mfbc_graph *g, int ncg, int nb, const int32_t *d_dist,
+                           const double *d_sigma, hipStream_t s);
+void launch_export_backward(mfbc_graph *g, int ncg, int nb, double *d_delta, int32_t *d_step,
+                            hipStream_t s);
+void launch_set_sources(mfbc_graph *g, int ncg, int nb, const int32_t *d_sources, hipStream_t s);
+
+// ---- host helpers (graph.cpp) ----
+int build_plan(int32_t n, const int64_t *rp, const TaskParams &p, std::vector<Task> &tasks,
+               std::vector<Hub> &hubs, int32_t &nslots);
+
+}  // namespace mfbc

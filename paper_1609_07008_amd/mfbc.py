@@ -1,0 +1,188 @@
+"""Thin ctypes binding of ``libmfbc.so`` (C ABI in ``include/mfbc.h``).
+
+Argument marshalling only: torch supplies device memory and the current HIP
+stream; every step of MFBF, MFBr and MFBC runs in the library's HIP kernels.
+There is no fallback: if the library is missing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmfbc.so")
+
+MFBC_OK, MFBC_EINVAL, MFBC_ENOMEM, MFBC_EDEVICE, MFBC_EOVERFLOW = 0, -1, -2, -3, -4
+MFBC_UNDIRECTED, MFBC_DIRECTED = 1, 2
+INF_DIST = 0x7FFFFFFF
+
+# Every entry point declared in include/mfbc.h, with its ctypes signature.
+_P = ctypes.c_void_p
+_I32, _I64, _U32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+SIGNATURES = {
+    "mfbc_load_graph": ([_I32, _I64, _P, _P, _P, _U32, _P, ctypes.POINTER(_P)], ctypes.c_int),
+    "mfbc_free_graph": ([_P], ctypes.c_int),
+    "mfbc_forward": ([_P, _P, _I32, _P, _P, _P, _P], ctypes.c_int),
+    "mfbc_backward": ([_P, _P, _I32, _P, _P, _P, _P, _P], ctypes.c_int),
+    "mfbc_bc": ([_P, _P, _I64, _I32, _P, _P], ctypes.c_int),
+    "mfbc_forward_trace": ([_P, _P, _I32, _P, _P, _P, _P, _I32, _P, _P], ctypes.c_int),
+    "mfbc_backward_trace": ([_P, _P, _I32, _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "mfbc_get_stats": ([_P, _P], ctypes.c_int),
+    "mfbc_graph_info": ([_P, _P, _P, _P], ctypes.c_int),
+    "mfbc_last_error": ([], ctypes.c_char_p),
+}
+
+
+class MfbcStats(ctypes.Structure):
+    _fields_ = [("fwd_products", _I64), ("bwd_products", _I64), ("fwd_entries", _I64),
+                ("bwd_entries", _I64), ("batches", _I64)]
+
+
+class MfbcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"mfbc error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libmfbc.so and declare its signatures (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    for name, (args, res) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != MFBC_OK:
+        msg = load_library().mfbc_last_error().decode(errors="replace")
+        raise MfbcError(rc, msg)
+
+
+def _stream(torch, stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+class DeviceGraph:
+    """A graph resident on the current HIP device (handle of ``mfbc_load_graph``)."""
+
+    def __init__(self, g, directed: Optional[bool] = None):
+        import torch
+        self._torch = torch
+        lib = load_library()
+        if directed is None:
+            directed = type(g).__name__ == "DiGraph"
+        rp = np.ascontiguousarray(g.row_ptr, dtype=np.int64)
+        col = np.ascontiguousarray(g.col, dtype=np.int32)
+        w = None if g.w is None else np.ascontiguousarray(g.w, dtype=np.int32)
+        h = ctypes.c_void_p()
+        rc = lib.mfbc_load_graph(
+            int(g.n), int(rp[-1]), rp.ctypes.data_as(_P), col.ctypes.data_as(_P),
+            None if w is None else w.ctypes.data_as(_P),
+            MFBC_DIRECTED if directed else MFBC_UNDIRECTED, _stream(torch), ctypes.byref(h))
+        _check(rc)
+        self.handle = h
+        self.n = int(g.n)
+        self.arcs = int(rp[-1])
+        self.m = self.arcs if directed else self.arcs // 2
+        self.directed = bool(directed)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().mfbc_free_graph(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _src(self, sources):
+        t = self._torch
+        if isinstance(sources, t.Tensor):
+            assert sources.dtype == t.int32 and sources.is_cuda and sources.is_contiguous()
+            return sources
+        return t.as_tensor(np.asarray(sources, dtype=np.int32), device="cuda")
+
+    def forward(self, sources, trace: bool = False, max_products: int = 4096, stream=None):
+        """MFBF for a batch: dist int32[nb][n], sigma float64[nb][n], products."""
+        t = self._torch
+        lib = load_library()
+        src = self._src(sources)
+        nb = src.numel()
+        dist = t.empty((nb, self.n), dtype=t.int32, device="cuda")
+        sigma = t.empty((nb, self.n), dtype=t.float64, device="cuda")
+        prods = ctypes.c_int32(0)
+        out = {"dist": dist, "sigma": sigma}
+        if trace:
+            fmask = t.empty((nb, self.n), dtype=t.int64, device="cuda")
+            nnz = np.zeros(max_products, dtype=np.int64)
+            rc = lib.mfbc_forward_trace(self.handle, _ptr(src), nb, _ptr(dist), _ptr(sigma),
+                                        _ptr(fmask), nnz.ctypes.data_as(_P), max_products,
+                                        ctypes.byref(prods), _stream(t, stream))
+            out.update(fmask=fmask, nnz=nnz)
+        else:
+            rc = lib.mfbc_forward(self.handle, _ptr(src), nb, _ptr(dist), _ptr(sigma),
+                                  ctypes.byref(prods), _stream(t, stream))
+        _check(rc)
+        out["products"] = prods.value
+        if trace:
+            out["nnz"] = out["nnz"][:prods.value]
+        return out
+
+    def backward(self, sources, dist, sigma, trace: bool = False, stream=None):
+        """MFBr from a forward result: delta float64[nb][n], products."""
+        t = self._torch
+        lib = load_library()
+        src = self._src(sources)
+        nb = src.numel()
+        delta = t.empty((nb, self.n), dtype=t.float64, device="cuda")
+        prods = ctypes.c_int32(0)
+        out = {"delta": delta}
+        if trace:
+            step = t.empty((nb, self.n), dtype=t.int32, device="cuda")
+            rc = lib.mfbc_backward_trace(self.handle, _ptr(src), nb, _ptr(dist), _ptr(sigma),
+                                         _ptr(delta), _ptr(step), ctypes.byref(prods),
+                                         _stream(t, stream))
+            out["step"] = step
+        else:
+            rc = lib.mfbc_backward(self.handle, _ptr(src), nb, _ptr(dist), _ptr(sigma),
+                                   _ptr(delta), ctypes.byref(prods), _stream(t, stream))
+        _check(rc)
+        out["products"] = prods.value
+        return out
+
+    def bc(self, sources, batch: int, out=None, stream=None):
+        """MFBC: lambda float64[n] over the listed sources in batches of ``batch``."""
+        t = self._torch
+        src = self._src(sources)
+        if out is None:
+            out = t.empty(self.n, dtype=t.float64, device="cuda")
+        rc = load_library().mfbc_bc(self.handle, _ptr(src), src.numel(), int(batch), _ptr(out),
+                                    _stream(t, stream))
+        _check(rc)
+        return out
+
+    def stats(self) -> dict:
+        s = MfbcStats()
+        _check(load_library().mfbc_get_stats(self.handle, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in MfbcStats._fields_}

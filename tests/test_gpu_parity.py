@@ -1,0 +1,258 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bars: distances, frontier membership, backward frontier indices and product
+counts bit-exact; sigma within relative 1e-12; delta and lambda within
+relative 1e-10 elementwise, zeros exact.  Inputs are seeded graphs of the
+paper's workload families (R-MAT, Erdos-Renyi, weighted and unweighted) plus
+small structured graphs and edge cases.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mfbc_ref
+from paper_1609_07008_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+SIGMA_TOL = 1e-12
+DELTA_TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def torch():
+    t = pytest.importorskip("torch")
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def mfbc(torch):
+    from paper_1609_07008_amd import mfbc as m
+    m.load_library()
+    return m
+
+
+def rel_close(got, want, tol, what=""):
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray(want, dtype=np.float64)
+    assert got.shape == want.shape, what
+    zero = want == 0
+    bad = np.flatnonzero(got[zero] != 0)
+    assert bad.size == 0, f"{what}: {bad.size} entries should be exactly 0"
+    if (~zero).any():
+        err = np.abs(got[~zero] - want[~zero]) / np.abs(want[~zero])
+        assert err.max() <= tol, f"{what}: max rel err {err.max():.3e}"
+
+
+def host_dist(d, inf):
+    d = d.cpu().numpy().astype(np.int64)
+    d[d == inf] = -1
+    return d
+
+
+def graphs():
+    u, v, w = zip(*[(0, 1, 1), (0, 2, 1), (1, 3, 1), (2, 3, 1), (3, 4, 2), (0, 4, 5), (1, 4, 3)])
+    two = gg.er_graph(150, 4, 31, (1, 9))
+    u2, v2, w2 = two.edges()
+    disc = gg.csr_from_edges(2 * 150 + 5, np.concatenate([u2, u2 + 150]),
+                             np.concatenate([v2, v2 + 150]), np.concatenate([w2, w2]), "disconnected")
+    return {
+        "golden5": gg.csr_from_edges(5, u, v, w, "golden5"),
+        "er1024_w100": gg.er_graph(1024, 8, 1, (1, 100)),
+        "er600_unw": gg.er_graph(600, 10, 2),
+        "rmat10_unw": gg.rmat_graph(10, 8, 5),
+        "rmat11_w255": gg.rmat_graph(11, 16, 6, wrange=(1, 255)),
+        "rmat12_w3": gg.rmat_graph(12, 16, 7, wrange=(1, 3)),
+        "grid20x30": gg.grid_graph(20, 30),
+        "path300": gg.path_graph(300, w=4),
+        "star200": gg.star_graph(200),
+        "diamonds40": gg.diamond_chain(40),
+        "disconnected": disc,
+    }
+
+
+GRAPHS = graphs()
+NB = [1, 5, 64, 65, 130]
+
+
+@pytest.fixture(scope="module")
+def dgraphs(mfbc):
+    out = {k: mfbc.DeviceGraph(g) for k, g in GRAPHS.items()}
+    yield out
+    for d in out.values():
+        d.close()
+
+
+def pick(g, nb, seed):
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, g.n, size=nb).astype(np.int32)     # repeats allowed
+
+
+@pytest.mark.parametrize("name", list(GRAPHS))
+@pytest.mark.parametrize("nb", NB)
+def test_forward_parity(torch, mfbc, dgraphs, name, nb):
+    g = GRAPHS[name]
+    src = pick(g, nb, 100 + nb)
+    print(f"[forward] {name} nb={nb}", flush=True)
+    f = dgraphs[name].forward(src, trace=True)
+    ref = oracle.brandes(g, src)
+    assert np.array_equal(host_dist(f["dist"], mfbc.INF_DIST), ref["dist"])
+    rel_close(f["sigma"].cpu().numpy(), ref["sigma"], SIGMA_TOL, "sigma")
+    alg = mfbc_ref.mfbf(g, src)
+    assert f["products"] == alg["products"]
+    fm = f["fmask"].cpu().numpy().view(np.uint64)
+    for j in range(1, min(alg["products"], 64) + 1):
+        got = ((fm >> np.uint64(j - 1)) & np.uint64(1)).astype(bool)
+        assert np.array_equal(got, alg["frontiers"][j - 1]), f"frontier {j}"
+    want_nnz = [int(F.sum()) for F in alg["frontiers"]]
+    assert f["nnz"].tolist() == want_nnz
+
+
+@pytest.mark.parametrize("name", list(GRAPHS))
+@pytest.mark.parametrize("nb", [1, 64, 130])
+def test_backward_parity(torch, mfbc, dgraphs, name, nb):
+    g = GRAPHS[name]
+    src = pick(g, nb, 200 + nb)
+    print(f"[backward] {name} nb={nb}", flush=True)
+    ref = oracle.brandes(g, src)
+    f = dgraphs[name].forward(src)
+    b = dgraphs[name].backward(src, f["dist"], f["sigma"], trace=True)
+    rel_close(b["delta"].cpu().numpy(), ref["delta"], DELTA_TOL, "delta")
+    assert np.array_equal(b["step"].cpu().numpy(), ref["height"])
+    # the oracle's Algorithm 2 also puts the source in its last frontier and
+    # then runs one product that finds nothing; the kernels leave the source
+    # out of the frontier (it has no predecessor), so they stop one earlier
+    alg = mfbc_ref.mfbr(g, src, ref["dist"], ref["sigma"], trace=False)
+    assert b["products"] == alg["products"] - 1
+
+
+@pytest.mark.parametrize("name", list(GRAPHS))
+def test_backward_from_oracle_forward(torch, mfbc, dgraphs, name):
+    """MFBr alone, fed the oracle's tau and sigma."""
+    g = GRAPHS[name]
+    src = pick(g, 70, 7)
+    ref = oracle.brandes(g, src)
+    d = ref["dist"].copy()
+    d[d < 0] = mfbc.INF_DIST
+    dist = torch.as_tensor(d.astype(np.int32), device="cuda")
+    sig = torch.as_tensor(ref["sigma"], device="cuda")
+    b = dgraphs[name].backward(src, dist, sig, trace=True)
+    rel_close(b["delta"].cpu().numpy(), ref["delta"], DELTA_TOL, "delta")
+    assert np.array_equal(b["step"].cpu().numpy(), ref["height"])
+
+
+@pytest.mark.parametrize("name", list(GRAPHS))
+@pytest.mark.parametrize("batch", [1, 7, 64, 100, 256])
+def test_bc_parity(torch, mfbc, dgraphs, name, batch):
+    g = GRAPHS[name]
+    src = np.arange(g.n, dtype=np.int32) if g.n <= 1100 else pick(g, 600, 3)
+    if batch == 1 and src.size > 200:
+        src = src[:200]
+    print(f"[bc] {name} batch={batch} sources={src.size}", flush=True)
+    lam = dgraphs[name].bc(src, batch).cpu().numpy()
+    ref = oracle.brandes(g, src, per_source=False)["lambda"]
+    rel_close(lam, ref, DELTA_TOL, "lambda")
+
+
+def test_bc_deterministic_and_batch_invariant(torch, mfbc, dgraphs):
+    g = GRAPHS["rmat11_w255"]
+    dg = dgraphs["rmat11_w255"]
+    src = pick(g, 300, 9)
+    a = dg.bc(src, 128).cpu().numpy()
+    b = dg.bc(src, 128).cpu().numpy()
+    assert np.array_equal(a, b), "same call must give bitwise-equal lambda"
+    c = dg.bc(src, 37).cpu().numpy()
+    rel_close(c, a, 1e-12, "batch invariance")
+
+
+def test_duplicate_sources_count_per_occurrence(torch, mfbc, dgraphs):
+    g = GRAPHS["er1024_w100"]
+    dg = dgraphs["er1024_w100"]
+    src = np.array([5, 9, 5, 5, 700], dtype=np.int32)
+    lam = dg.bc(src, 2).cpu().numpy()
+    rel_close(lam, oracle.brandes(g, src, per_source=False)["lambda"], DELTA_TOL, "dups")
+
+
+def test_empty_source_list_gives_zero(torch, mfbc, dgraphs):
+    dg = dgraphs["golden5"]
+    lam = dg.bc(torch.empty(0, dtype=torch.int32, device="cuda"), 4).cpu().numpy()
+    assert np.all(lam == 0)
+
+
+@pytest.mark.parametrize("g", [
+    gg.csr_from_edges(1, [], [], None, "single"),
+    gg.csr_from_edges(2, [0], [1], [7], "edge"),
+    gg.csr_from_edges(6, [], [], None, "no_arcs"),
+    gg.complete_graph(9, w=2),
+], ids=lambda g: g.name)
+def test_tiny_and_degenerate_graphs(torch, mfbc, g):
+    dg = mfbc.DeviceGraph(g)
+    src = np.arange(g.n, dtype=np.int32)
+    ref = oracle.brandes(g, src)
+    f = dg.forward(src)
+    assert np.array_equal(host_dist(f["dist"], mfbc.INF_DIST), ref["dist"])
+    rel_close(f["sigma"].cpu().numpy(), ref["sigma"], SIGMA_TOL, "sigma")
+    b = dg.backward(src, f["dist"], f["sigma"])
+    rel_close(b["delta"].cpu().numpy(), ref["delta"], DELTA_TOL, "delta")
+    rel_close(dg.bc(src, 3).cpu().numpy(), ref["lambda"], DELTA_TOL, "lambda")
+    dg.close()
+
+
+def test_directed_graph(torch, mfbc):
+    g = gg.directed_rmat_graph(10, 8, 12, wrange=(1, 50))
+    dg = mfbc.DeviceGraph(g, directed=True)
+    src = pick(g, 150, 4)
+    ref = oracle.brandes(g, src)
+    f = dg.forward(src, trace=True)
+    assert np.array_equal(host_dist(f["dist"], mfbc.INF_DIST), ref["dist"])
+    rel_close(f["sigma"].cpu().numpy(), ref["sigma"], SIGMA_TOL, "sigma")
+    alg = mfbc_ref.mfbf(g, src)
+    assert f["products"] == alg["products"]
+    b = dg.backward(src, f["dist"], f["sigma"], trace=True)
+    rel_close(b["delta"].cpu().numpy(), ref["delta"], DELTA_TOL, "delta")
+    assert np.array_equal(b["step"].cpu().numpy(), ref["height"])
+    rel_close(dg.bc(src, 64).cpu().numpy(), ref["lambda"], DELTA_TOL, "lambda")
+    dg.close()
+
+
+def test_hub_rows_are_split_and_merged(torch, mfbc):
+    """Stars and a dense hub exercise the sliced-row path (rows > 1024 arcs)."""
+    k = 5000
+    star = gg.star_graph(k)
+    extra = gg.er_graph(k + 1, 3, 8, None)
+    u1, v1, _ = star.edges()
+    u2, v2, _ = extra.edges()
+    key = np.unique(np.minimum(np.concatenate([u1, u2]), np.concatenate([v1, v2])) * (k + 1) +
+                    np.maximum(np.concatenate([u1, u2]), np.concatenate([v1, v2])))
+    rng = np.random.default_rng(1)
+    g = gg.csr_from_edges(k + 1, key // (k + 1), key % (k + 1),
+                          rng.integers(1, 4, size=key.size), "hubby")
+    dg = mfbc.DeviceGraph(g)
+    src = np.concatenate([[0], pick(g, 99, 2)]).astype(np.int32)
+    ref = oracle.brandes(g, src)
+    f = dg.forward(src)
+    assert np.array_equal(host_dist(f["dist"], mfbc.INF_DIST), ref["dist"])
+    rel_close(f["sigma"].cpu().numpy(), ref["sigma"], SIGMA_TOL, "sigma")
+    b = dg.backward(src, f["dist"], f["sigma"], trace=True)
+    rel_close(b["delta"].cpu().numpy(), ref["delta"], DELTA_TOL, "delta")
+    assert np.array_equal(b["step"].cpu().numpy(), ref["height"])
+    rel_close(dg.bc(src, 64).cpu().numpy(), ref["lambda"], DELTA_TOL, "lambda")
+    dg.close()
+
+
+def test_errors_are_reported(torch, mfbc, dgraphs):
+    dg = dgraphs["golden5"]
+    with pytest.raises(mfbc.MfbcError) as e:
+        dg.forward(np.array([0, 5], dtype=np.int32))
+    assert e.value.code == mfbc.MFBC_EINVAL
+    with pytest.raises(mfbc.MfbcError) as e:
+        dg.bc(np.array([1, -1], dtype=np.int32), 2)
+    assert e.value.code == mfbc.MFBC_EINVAL
+    with pytest.raises(mfbc.MfbcError) as e:
+        dg.bc(np.array([1], dtype=np.int32), 0)
+    assert e.value.code == mfbc.MFBC_EINVAL
+    # the handle still works after rejected calls
+    f = dg.forward(np.array([0], dtype=np.int32))
+    assert f["dist"].cpu().numpy().tolist() == [[0, 1, 1, 2, 4]]
