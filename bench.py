@@ -1,0 +1,201 @@
+#!/usr/bin/env python
+"""MFBC benchmark on one MI355X: betweenness-centrality TEPS.
+
+A *step* is one MFBC run (Algorithm 3) over the workload's whole source
+list: every batch's forward products, counting product and backward
+products, and the lambda reduction, all in libmfbc's HIP kernels.  The graph
+and the source list are resident in HBM before the timed region; graph
+generation and loading are not timed.
+
+    TEPS = n_sources * m / (seconds per step),  m = unique undirected edges.
+
+The JSON line also carries the roofline of the dominant kernel (algorithmic
+bytes of its launches, from the frontier counters, over its HIP-event time)
+and the CPU oracle's TEPS on a bounded sample of the same sources.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, AMD published
+
+WORKLOADS = {
+    # weighted R-MAT scale 20 (the headline): 1024 sources in batches of 256
+    "rmat20_w255": dict(kind="rmat", scale=20, ef=16, wrange=(1, 255), seed=3,
+                        n_sources=1024, source_seed=103, batch=256, cpu_sample=128),
+    # dense Erdos-Renyi, same weights and sources
+    "er32k_k512_w255": dict(kind="er", n=32768, k=512, wrange=(1, 255), seed=4,
+                            n_sources=1024, source_seed=104, batch=256, cpu_sample=96),
+    # unweighted R-MAT scale 16, approximate BC from 4096 sources
+    "rmat16_unw": dict(kind="rmat", scale=16, ef=16, wrange=None, seed=2,
+                       n_sources=4096, source_seed=102, batch=512, cpu_sample=4096),
+    # Erdos-Renyi n=1024, exact BC over all sources in batches of 64
+    "er1024_w100": dict(kind="er", n=1024, k=8, wrange=(1, 100), seed=1,
+                        n_sources=None, source_seed=None, batch=64, cpu_sample=None),
+}
+
+
+def make_graph(spec):
+    from paper_1609_07008_amd import graphgen as gg
+    if spec["kind"] == "rmat":
+        return gg.rmat_graph(spec["scale"], spec["ef"], spec["seed"], wrange=spec["wrange"])
+    return gg.er_graph(spec["n"], spec["k"], spec["seed"], spec["wrange"])
+
+
+def make_sources(g, spec):
+    import numpy as np
+    from paper_1609_07008_amd import graphgen as gg
+    if spec["n_sources"] is None:
+        return np.arange(g.n, dtype=np.int32)
+    return gg.pick_sources(g, spec["n_sources"], spec["source_seed"])
+
+
+def kernel_sha():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "mfbc_internal.h"):
+        with open(os.path.join(ROOT, "paper_1609_07008_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(workload, kernel):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if still valid."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_sha") != kernel_sha():
+        return None            # the kernel changed since the counters were taken
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(g, src, sample, m):
+    import numpy as np
+    import oracle
+    k = src.size if sample is None else min(sample, src.size)
+    s = np.ascontiguousarray(src[:k])
+    threads = oracle.brandes_threads()
+    t0 = time.perf_counter()
+    oracle.brandes(g, s, per_source=False, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": k * m / dt, "unit": "TEPS", "cores": threads, "kind": "oracle",
+            "sample": f"{k} of the workload's {src.size} sources (C Brandes, FP64, "
+                      f"OpenMP over sources), {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rmat20_w255", choices=sorted(WORKLOADS))
+    ap.add_argument("--batch", type=int, default=None, help="override the batch size")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--stats", action="store_true", help="print per-kernel stats to stderr")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the hot path runs on a single MI355X; "
+              "a multi-GPU run (source batches sharded over GPUs, one allreduce of lambda) "
+              "is not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1609_07008_amd import mfbc
+
+    spec = WORKLOADS[args.workload]
+    batch = args.batch or spec["batch"]
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    g = make_graph(spec)
+    src = make_sources(g, spec)
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    dg = mfbc.DeviceGraph(g)
+    d_src = torch.as_tensor(src, device="cuda")
+    out = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t_load = time.perf_counter() - t0
+    print(f"[bench] {args.workload}: n={g.n} m={g.m} arcs={g.arcs} sources={src.size} "
+          f"batch={batch} gen {t_gen:.1f}s load {t_load:.1f}s", file=sys.stderr, flush=True)
+
+    for i in range(args.warmup):
+        dg.bc(d_src, batch, out=out)
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+
+    dg.enable_timing(True)
+    tot = {}
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        dg.bc(d_src, batch, out=out)
+        st = dg.stats()
+        for k, v in st.items():
+            tot[k] = tot.get(k, 0) + v
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    dg.enable_timing(False)
+    print(f"[bench] {args.steps} steps in {elapsed:.3f}s", file=sys.stderr, flush=True)
+
+    ms_step = elapsed / args.steps * 1e3
+    teps = src.size * g.m / (elapsed / args.steps)
+
+    kernels = {
+        "k_fwd_pull": (tot["fwd_pull_ms"], tot["fwd_alg_bytes"], tot["fwd_pull_launches"]),
+        "k_bwd_pull": (tot["bwd_pull_ms"], tot["bwd_alg_bytes"], tot["bwd_pull_launches"]),
+        "k_bwd_count": (tot["count_ms"], tot["count_alg_bytes"], tot["count_launches"]),
+    }
+    dom = max(kernels, key=lambda k: kernels[k][0])
+    ms, alg, launches = kernels[dom]
+    achieved = alg / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    traffic = stored_traffic(args.workload, dom)
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "launches": int(launches),
+                "avg_launch_us": round(ms / max(launches, 1) * 1e3, 2),
+                "alg_bytes_per_launch": round(alg / max(launches, 1))}
+    if args.stats:
+        for k, (kms, kb, kl) in kernels.items():
+            print(f"[bench] {k}: {kms / args.steps:.2f} ms/step over {kl // args.steps} launches, "
+                  f"{kb / max(kms, 1e-9) / 1e6:.1f} GB/s algorithmic", file=sys.stderr)
+        print("[bench] stats " + json.dumps({k: v / args.steps for k, v in tot.items()}),
+              file=sys.stderr)
+
+    line = {
+        "metric": "BC TEPS (sources x edges / s) at 1 GPU",
+        "value": teps,
+        "unit": "TEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "graph": g.name, "n": g.n, "m": g.m,
+                   "arcs": g.arcs, "weights": None if spec["wrange"] is None else list(spec["wrange"]),
+                   "n_sources": int(src.size), "batch": batch,
+                   "fwd_products_per_step": tot["fwd_products"] / args.steps,
+                   "bwd_products_per_step": tot["bwd_products"] / args.steps},
+        "roofline": roofline,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(g, src, spec["cpu_sample"], g.m)
+    dg.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -157,14 +157,45 @@ int mfbc_backward_trace(mfbc_graph *g, const int32_t *d_sources, int32_t nb,
                         double *d_delta, int32_t *d_step,
                         int32_t *h_products, void *hip_stream);
 
-/* Work counters of the last forward/backward/bc call on a graph. */
+/*
+ * Work counters of the last forward/backward/bc call on a graph (sums over
+ * its products).  "Entries" are frontier entries produced; "outputs" are
+ * product entries that received a candidate; "active vertices/arcs" are the
+ * vertices of the frontier a product read and the arcs of their rows.  The
+ * *_ms fields are kernel times measured with HIP events recorded on the
+ * call's stream around each launch; they are filled only while timing is
+ * enabled (mfbc_enable_timing).  The *_alg_bytes fields are the bytes the
+ * method must move (each frontier tuple, adjacency row and touched output
+ * once per product; see the documentation of the measurement model).
+ */
 typedef struct mfbc_stats {
     int64_t fwd_products;   /* forward products over all batches          */
     int64_t bwd_products;   /* backward products (counting ones included)  */
-    int64_t fwd_entries;    /* sum over products of frontier entries       */
-    int64_t bwd_entries;    /* sum over backward frontiers of entries      */
+    int64_t fwd_entries;    /* frontier entries produced, forward          */
+    int64_t bwd_entries;    /* frontier entries produced, backward         */
     int64_t batches;
+    int64_t fwd_outputs;
+    int64_t bwd_outputs;
+    int64_t fwd_active_vertices;
+    int64_t fwd_active_arcs;
+    int64_t bwd_active_vertices;
+    int64_t bwd_active_arcs;
+    int64_t fwd_pull_launches;
+    int64_t bwd_pull_launches;
+    int64_t count_launches;
+    double fwd_pull_ms;     /* forward product kernel                      */
+    double fwd_merge_ms;    /* merge of split rows, forward                */
+    double count_ms;        /* counting product (both kernels)             */
+    double bwd_pull_ms;     /* backward product kernel                     */
+    double bwd_merge_ms;
+    double other_ms;        /* initialisation and lambda reduction         */
+    double fwd_alg_bytes;
+    double bwd_alg_bytes;
+    double count_alg_bytes;
 } mfbc_stats;
+
+/* Enable (1) or disable (0) the per-launch kernel timing of a graph. */
+int mfbc_enable_timing(mfbc_graph *g, int enable);
 
 int mfbc_get_stats(const mfbc_graph *g, mfbc_stats *out);
 

@@ -21,6 +21,6 @@ Parity status: every function here is pinned by a ``-m "not gpu"`` test
 "parity unpinned" except sigma values beyond 2**53 on irregular graphs, where
 binary64 summation order matters and only a relative bound applies.
 """
-from .brandes import brandes, build_library, library_path  # noqa: F401
+from .brandes import brandes, brandes_threads, build_library, library_path  # noqa: F401
 from .frontier import forward_frontiers, backward_heights  # noqa: F401
 from . import brute, mfbc_ref  # noqa: F401,E402

@@ -81,3 +81,11 @@ def brandes(g, sources, per_source: bool = True, nthreads: int = 0) -> dict:
     if rc != 0:
         raise ValueError("oracle_bc failed (bad source or out of memory)")
     return out
+
+
+def brandes_threads() -> int:
+    """Host threads available to this process (the CPU affinity mask)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1

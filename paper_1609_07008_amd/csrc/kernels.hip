@@ -67,17 +67,50 @@ __device__ __forceinline__ double wave_sum(double x) {
     return x;
 }
 
-// Block-level sum of lane-0 counts, then one atomic into a spread slot.
-__device__ __forceinline__ void flush_count(unsigned long long mine, unsigned long long *ctr) {
-    __shared__ unsigned long long s_cnt[kWavesPerBlock];
+// Counters of one product, kCounterSlots-wide arrays (spread to avoid a
+// single hot address): [0] frontier entries produced, [1] output entries
+// that received a candidate, [2] active vertices read, [3] arcs of their rows.
+// Block-level sum of per-thread counts, then one atomic per array.
+__device__ __forceinline__ void flush_counts(unsigned long long c0, unsigned long long c1,
+                                             unsigned long long c2, unsigned long long c3,
+                                             unsigned long long *ctr) {
+    __shared__ unsigned long long s_cnt[4][kWavesPerBlock];
+    unsigned long long v[4] = {c0, c1, c2, c3};
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v[k] += __shfl_xor(v[k], off, kWave);
+    }
     const int lane = threadIdx.x & (kWave - 1);
-    if (lane == 0) s_cnt[threadIdx.x >> 6] = mine;
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) s_cnt[k][threadIdx.x >> 6] = v[k];
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 4) {
         unsigned long long t = 0;
 #pragma unroll
-        for (int i = 0; i < kWavesPerBlock; i++) t += s_cnt[i];
-        if (t) atomicAdd(ctr + (blockIdx.x & (kCounterSlots - 1)), t);
+        for (int i = 0; i < kWavesPerBlock; i++) t += s_cnt[threadIdx.x][i];
+        if (t) atomicAdd(ctr + threadIdx.x * kCounterSlots + (blockIdx.x & (kCounterSlots - 1)), t);
+    }
+}
+
+// Clear a vertex bitmap while counting its set bits and their row lengths.
+__device__ __forceinline__ void clear_and_count(uint32_t *bits, int words, const int64_t *rp,
+                                                unsigned long long &nv, unsigned long long &na) {
+    const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int i = gtid; i < words; i += gridDim.x * blockDim.x) {
+        uint32_t w = bits[i];
+        if (w) {
+            nv += __popc(w);
+            while (w) {
+                const int b = __ffs(w) - 1;
+                w &= w - 1;
+                const int u = i * 32 + b;
+                na += (unsigned long long)(rp[u + 1] - rp[u]);
+            }
+            bits[i] = 0u;
+        }
     }
 }
 
@@ -119,10 +152,12 @@ struct FwdArgs {
 // T := T (+) G at (v, cg); writes the next frontier row.  Returns the lane
 // mask of the frontier entries produced.
 __device__ __forceinline__ uint64_t fwd_finalize(const FwdArgs &a, size_t cgv, int v, int bd,
-                                                 double bm, int lane) {
+                                                 double bm, int lane, unsigned long long &outs) {
     const bool has = bd != kInf;
     uint64_t bits = 0;
-    if (ballot(has)) {
+    const uint64_t hm = ballot(has);
+    if (lane == 0) outs += __popcll(hm);
+    if (hm) {
         const size_t idx = (cgv + (size_t)v) * kWave + lane;
         bool keep = false;
         if (has) {
@@ -155,7 +190,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_pull(FwdArgs a) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const int cg = wid / a.ntasks;                       // column-group major
-    unsigned long long produced = 0;
+    unsigned long long produced = 0, outs = 0;
     if (cg < a.ncg) {
         const Task *tp = a.tasks + (wid - cg * a.ntasks);
         const int v0 = uni(tp->v0), v1 = uni(tp->v1), hub = uni(tp->hub), part = uni(tp->part);
@@ -183,7 +218,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_pull(FwdArgs a) {
                 const int j0 = __ffsll((unsigned long long)am) - 1;
                 if (hub < 0) {
                     while (e + j0 >= vend) {
-                        const uint64_t b = fwd_finalize(a, cgv, v, bd, bm, lane);
+                        const uint64_t b = fwd_finalize(a, cgv, v, bd, bm, lane, outs);
                         produced += __popcll(b);
                         if (b) run_act |= 1ull << (v - v0);
                         ++v;
@@ -231,7 +266,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_pull(FwdArgs a) {
         }
         if (hub < 0) {
             while (v < v1) {
-                const uint64_t b = fwd_finalize(a, cgv, v, bd, bm, lane);
+                const uint64_t b = fwd_finalize(a, cgv, v, bd, bm, lane, outs);
                 produced += __popcll(b);
                 if (b) run_act |= 1ull << (v - v0);
                 ++v;
@@ -245,18 +280,19 @@ __global__ __launch_bounds__(kBlock) void k_fwd_pull(FwdArgs a) {
             a.pm[pidx] = bm;
         }
     }
-    flush_count(produced, a.ctr);
+    flush_counts(produced, outs, 0, 0, a.ctr);
 }
 
 // Combine the slices of split rows (fixed slice order) and finish them;
 // also clears the previous frontier's bitmap and the next product's counters.
 __global__ __launch_bounds__(kBlock) void k_fwd_merge(FwdArgs a) {
     const int gtid = blockIdx.x * kBlock + threadIdx.x;
-    for (int i = gtid; i < a.clear_words; i += gridDim.x * kBlock) a.clear_bits[i] = 0u;
-    if (gtid < kCounterSlots) a.clear_ctr[gtid] = 0ull;
+    unsigned long long nv = 0, na = 0;
+    clear_and_count(a.clear_bits, a.clear_words, a.rp, nv, na);
+    if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    unsigned long long produced = 0;
+    unsigned long long produced = 0, outs = 0;
     const int cg = a.nhubs ? wid / a.nhubs : a.ncg;
     if (cg < a.ncg) {
         const Hub *hp = a.hubs + (wid - cg * a.nhubs);
@@ -275,11 +311,11 @@ __global__ __launch_bounds__(kBlock) void k_fwd_merge(FwdArgs a) {
                 bm += m;
             }
         }
-        const uint64_t b = fwd_finalize(a, cgv, v, bd, bm, lane);
+        const uint64_t b = fwd_finalize(a, cgv, v, bd, bm, lane, outs);
         produced += __popcll(b);
         if (b && lane == 0) atomicOr(a.abits_n + (v >> 5), 1u << (v & 31));
     }
-    flush_count(produced, a.ctr);
+    flush_counts(produced, outs, nv, na, a.ctr);
 }
 
 // ===================================================================== backward
@@ -384,13 +420,13 @@ __global__ __launch_bounds__(kBlock) void k_bwd_count(BwdArgs a) {
         }
         if (hub < 0 && lane == 0 && run_act) or_run_bits(a.abits_n, v0, run_act);
     }
-    flush_count(produced, a.ctr);
+    flush_counts(produced, 0, 0, 0, a.ctr);
 }
 
 __global__ __launch_bounds__(kBlock) void k_bwd_count_merge(BwdArgs a) {
     const int gtid = blockIdx.x * kBlock + threadIdx.x;
     for (int i = gtid; i < a.clear_words; i += gridDim.x * kBlock) a.clear_bits[i] = 0u;
-    if (gtid < kCounterSlots) a.clear_ctr[gtid] = 0ull;
+    if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     unsigned long long produced = 0;
@@ -406,15 +442,18 @@ __global__ __launch_bounds__(kBlock) void k_bwd_count_merge(BwdArgs a) {
         produced += __popcll(b);
         if (b && lane == 0) atomicOr(a.abits_n + (x >> 5), 1u << (x & 31));
     }
-    flush_count(produced, a.ctr);
+    flush_counts(produced, 0, 0, 0, a.ctr);
 }
 
 // Finish (s, x) after a backward product contributed `acc` from `got`
 // frontier successors.  Returns the lane mask of new frontier entries.
 __device__ __forceinline__ uint64_t bwd_finalize(const BwdArgs &a, size_t cgv, int cg, int x,
-                                                 int cx, double acc, int got, int lane) {
+                                                 int cx, double acc, int got, int lane,
+                                                 unsigned long long &outs) {
     uint64_t bits = 0;
-    if (ballot(got > 0)) {
+    const uint64_t gm = ballot(got > 0);
+    if (lane == 0) outs += __popcll(gm);
+    if (gm) {
         const size_t idx = (cgv + (size_t)x) * kWave + lane;
         bool done = false, front = false;
         double dep = 0.0;
@@ -450,7 +489,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_pull(BwdArgs a) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const int cg = wid / a.ntasks;
-    unsigned long long produced = 0;
+    unsigned long long produced = 0, outs = 0;
     if (cg < a.ncg) {
         const Task *tp = a.tasks + (wid - cg * a.ntasks);
         const int v0 = uni(tp->v0), v1 = uni(tp->v1), hub = uni(tp->hub), part = uni(tp->part);
@@ -480,7 +519,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_pull(BwdArgs a) {
                 if (hub < 0) {
                     while (e + j0 >= vend) {
                         if (loaded) {
-                            const uint64_t b = bwd_finalize(a, cgv, cg, x, cx, acc, got, lane);
+                            const uint64_t b = bwd_finalize(a, cgv, cg, x, cx, acc, got, lane, outs);
                             produced += __popcll(b);
                             if (b) run_act |= 1ull << (x - v0);
                         } else if (lane == 0) {
@@ -542,7 +581,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_pull(BwdArgs a) {
         if (hub < 0) {
             while (x < v1) {
                 if (loaded) {
-                    const uint64_t b = bwd_finalize(a, cgv, cg, x, cx, acc, got, lane);
+                    const uint64_t b = bwd_finalize(a, cgv, cg, x, cx, acc, got, lane, outs);
                     produced += __popcll(b);
                     if (b) run_act |= 1ull << (x - v0);
                 } else if (lane == 0) {
@@ -560,16 +599,17 @@ __global__ __launch_bounds__(kBlock) void k_bwd_pull(BwdArgs a) {
             a.pm[pidx] = acc;
         }
     }
-    flush_count(produced, a.ctr);
+    flush_counts(produced, outs, 0, 0, a.ctr);
 }
 
 __global__ __launch_bounds__(kBlock) void k_bwd_merge(BwdArgs a) {
     const int gtid = blockIdx.x * kBlock + threadIdx.x;
-    for (int i = gtid; i < a.clear_words; i += gridDim.x * kBlock) a.clear_bits[i] = 0u;
-    if (gtid < kCounterSlots) a.clear_ctr[gtid] = 0ull;
+    unsigned long long nv = 0, na = 0;
+    clear_and_count(a.clear_bits, a.clear_words, a.rp, nv, na);
+    if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    unsigned long long produced = 0;
+    unsigned long long produced = 0, outs = 0;
     const int cg = a.nhubs ? wid / a.nhubs : a.ncg;
     if (cg < a.ncg) {
         const Hub *hp = a.hubs + (wid - cg * a.nhubs);
@@ -583,11 +623,11 @@ __global__ __launch_bounds__(kBlock) void k_bwd_merge(BwdArgs a) {
             acc += a.pm[pidx];
         }
         const int cx = a.cnt[(cgv + (size_t)x) * kWave + lane];
-        const uint64_t b = bwd_finalize(a, cgv, cg, x, cx, acc, got, lane);
+        const uint64_t b = bwd_finalize(a, cgv, cg, x, cx, acc, got, lane, outs);
         produced += __popcll(b);
         if (b && lane == 0) atomicOr(a.abits_n + (x >> 5), 1u << (x & 31));
     }
-    flush_count(produced, a.ctr);
+    flush_counts(produced, outs, nv, na, a.ctr);
 }
 
 // ===================================================================== setup / io
@@ -739,12 +779,12 @@ static FwdArgs fwd_args(mfbc_graph *g, int ncg, int j, bool trace) {
     a.fsig_n = ws.fsig[b ^ 1];
     a.pd = ws.pd;
     a.pm = ws.pm;
-    a.ctr = ws.counters + (size_t)(j % kCounterRing) * kCounterSlots;
+    a.ctr = ws.counters + (size_t)(j % kCounterRing) * 4 * kCounterSlots;
     a.flags = ws.flags;
     a.fmask = trace ? ws.fmask : nullptr;
     a.clear_bits = ws.abits[b];
     a.clear_words = (g->n + 31) / 32;
-    a.clear_ctr = ws.counters + (size_t)((j + 1) % kCounterRing) * kCounterSlots;
+    a.clear_ctr = ws.counters + (size_t)((j + 1) % kCounterRing) * 4 * kCounterSlots;
     return a;
 }
 
@@ -760,25 +800,29 @@ void launch_fwd_init(mfbc_graph *g, int ncg, int nb, hipStream_t s) {
     const int nwords = (g->n + 31) / 32;
     hipLaunchKernelGGL(k_fwd_fill, dim3(blocks_for(total, 256, 65536)), dim3(256), 0, s, ws.tdist,
                        ws.tsig, total, ws.fbits[0], (size_t)ncg * g->n, ws.abits[0], ws.abits[1],
-                       nwords, ws.counters, kCounterRing * kCounterSlots, ws.flags,
+                       nwords, ws.counters, kCounterRing * 4 * kCounterSlots, ws.flags,
                        ws.fmask && ws.fmask_ncg >= ncg ? ws.fmask : nullptr);
     hipLaunchKernelGGL(k_fwd_seed, dim3(blocks_for(nb, 256)), dim3(256), 0, s, ws.src, nb, g->n,
                        ws.tdist, ws.tsig, ws.fdist[0], ws.fsig[0], ws.fbits[0], ws.abits[0]);
 }
 
-void launch_fwd_product(mfbc_graph *g, int ncg, int j, bool trace, hipStream_t s) {
+void launch_fwd_product(mfbc_graph *g, int ncg, int j, bool trace, hipStream_t s,
+                        hipEvent_t *ev) {
     FwdArgs a = fwd_args(g, ncg, j, trace);
+    if (ev) hipEventRecord(ev[0], s);
     const size_t waves = (size_t)a.ntasks * ncg;
     const int grid = blocks_for(waves, kWavesPerBlock, 0x7fffffff);
     if (g->in.w)
         hipLaunchKernelGGL(k_fwd_pull<true>, dim3(grid), dim3(kBlock), 0, s, a);
     else
         hipLaunchKernelGGL(k_fwd_pull<false>, dim3(grid), dim3(kBlock), 0, s, a);
+    if (ev) hipEventRecord(ev[1], s);
     const size_t mw = (size_t)a.nhubs * ncg;
     int mgrid = blocks_for(mw, kWavesPerBlock, 0x7fffffff);
     const int cgrid = blocks_for((size_t)a.clear_words, kBlock, 1024);
     if (cgrid > mgrid) mgrid = cgrid;
     hipLaunchKernelGGL(k_fwd_merge, dim3(mgrid), dim3(kBlock), 0, s, a);
+    if (ev) hipEventRecord(ev[2], s);
 }
 
 static BwdArgs bwd_args(mfbc_graph *g, int ncg, int k) {
@@ -812,22 +856,23 @@ static BwdArgs bwd_args(mfbc_graph *g, int ncg, int k) {
     a.lam = ws.lam;
     a.pd = ws.pd;
     a.pm = ws.pm;
-    a.ctr = ws.counters + (size_t)(k % kCounterRing) * kCounterSlots;
+    a.ctr = ws.counters + (size_t)(k % kCounterRing) * 4 * kCounterSlots;
     a.clear_bits = ws.abits[b];
     a.clear_words = (g->n + 31) / 32;
-    a.clear_ctr = ws.counters + (size_t)((k + 1) % kCounterRing) * kCounterSlots;
+    a.clear_ctr = ws.counters + (size_t)((k + 1) % kCounterRing) * 4 * kCounterSlots;
     return a;
 }
 
-void launch_bwd_count(mfbc_graph *g, int ncg, hipStream_t s, bool /*trace*/) {
+void launch_bwd_count(mfbc_graph *g, int ncg, hipStream_t s, hipEvent_t *ev) {
     Workspace &ws = g->ws;
     // the counting product writes B_0 into buffer 0: clear its bitmap and
     // this product's counters first
     const int nwords = (g->n + 31) / 32;
     hipMemsetAsync(ws.abits[0], 0, (size_t)nwords * 4, s);
     hipMemsetAsync(ws.abits[1], 0, (size_t)nwords * 4, s);
-    hipMemsetAsync(ws.counters, 0, sizeof(unsigned long long) * kCounterRing * kCounterSlots, s);
+    hipMemsetAsync(ws.counters, 0, sizeof(unsigned long long) * kCounterRing * 4 * kCounterSlots, s);
     BwdArgs a = bwd_args(g, ncg, 0);
+    if (ev) hipEventRecord(ev[0], s);
     const size_t waves = (size_t)a.ntasks * ncg;
     const int grid = blocks_for(waves, kWavesPerBlock, 0x7fffffff);
     if (g->out.w)
@@ -838,20 +883,27 @@ void launch_bwd_count(mfbc_graph *g, int ncg, hipStream_t s, bool /*trace*/) {
     const int cgrid = blocks_for((size_t)a.clear_words, kBlock, 1024);
     if (cgrid > mgrid) mgrid = cgrid;
     hipLaunchKernelGGL(k_bwd_count_merge, dim3(mgrid), dim3(kBlock), 0, s, a);
+    if (ev) {
+        hipEventRecord(ev[1], s);
+        hipEventRecord(ev[2], s);
+    }
 }
 
-void launch_bwd_product(mfbc_graph *g, int ncg, int k, bool /*trace*/, hipStream_t s) {
+void launch_bwd_product(mfbc_graph *g, int ncg, int k, hipStream_t s, hipEvent_t *ev) {
     BwdArgs a = bwd_args(g, ncg, k);
+    if (ev) hipEventRecord(ev[0], s);
     const size_t waves = (size_t)a.ntasks * ncg;
     const int grid = blocks_for(waves, kWavesPerBlock, 0x7fffffff);
     if (g->out.w)
         hipLaunchKernelGGL(k_bwd_pull<true>, dim3(grid), dim3(kBlock), 0, s, a);
     else
         hipLaunchKernelGGL(k_bwd_pull<false>, dim3(grid), dim3(kBlock), 0, s, a);
+    if (ev) hipEventRecord(ev[1], s);
     int mgrid = blocks_for((size_t)a.nhubs * ncg, kWavesPerBlock, 0x7fffffff);
     const int cgrid = blocks_for((size_t)a.clear_words, kBlock, 1024);
     if (cgrid > mgrid) mgrid = cgrid;
     hipLaunchKernelGGL(k_bwd_merge, dim3(mgrid), dim3(kBlock), 0, s, a);
+    if (ev) hipEventRecord(ev[2], s);
 }
 
 void launch_lambda_zero(mfbc_graph *g, int ncg, hipStream_t s) {

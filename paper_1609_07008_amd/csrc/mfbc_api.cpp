@@ -130,14 +130,14 @@ int ensure_workspace(mfbc_graph *g, int ncg, bool trace) {
             (rc = dalloc(&ws.fbits[0], n * ncg)) || (rc = dalloc(&ws.fbits[1], n * ncg)) ||
             (rc = dalloc(&ws.abits[0], nwords)) || (rc = dalloc(&ws.abits[1], nwords)) ||
             (rc = dalloc(&ws.pd, slots)) || (rc = dalloc(&ws.pm, slots)) ||
-            (rc = dalloc(&ws.counters, (size_t)kCounterRing * kCounterSlots)) ||
+            (rc = dalloc(&ws.counters, (size_t)kCounterRing * 4 * kCounterSlots)) ||
             (rc = dalloc(&ws.flags, 4)) || (rc = dalloc(&ws.lam, n * ncg)) ||
             (rc = dalloc(&ws.src, (size_t)ncg * kWave))) {
             free_workspace(ws);
             return rc;
         }
         if (hipHostMalloc((void **)&ws.h_counters,
-                          sizeof(unsigned long long) * kCounterRing * kCounterSlots) != hipSuccess) {
+                          sizeof(unsigned long long) * kCounterRing * 4 * kCounterSlots) != hipSuccess) {
             ws.h_counters = nullptr;
             free_workspace(ws);
             return fail(MFBC_ENOMEM, "pinned host allocation failed");
@@ -153,17 +153,34 @@ int ensure_workspace(mfbc_graph *g, int ncg, bool trace) {
     return MFBC_OK;
 }
 
-int read_counter(mfbc_graph *g, int idx, hipStream_t s, int64_t *out) {
+struct Counts {
+    int64_t produced = 0, outputs = 0, active_vertices = 0, active_arcs = 0;
+};
+
+// Wait for product `idx` and read its counters (see flush_counts).
+int read_counts(mfbc_graph *g, int idx, hipStream_t s, Counts *out) {
     Workspace &ws = g->ws;
-    const size_t off = (size_t)(idx % kCounterRing) * kCounterSlots;
+    const size_t off = (size_t)(idx % kCounterRing) * 4 * kCounterSlots;
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(ws.h_counters + off, ws.counters + off,
-                           sizeof(unsigned long long) * kCounterSlots, hipMemcpyDeviceToHost, s));
+                           sizeof(unsigned long long) * 4 * kCounterSlots, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    unsigned long long t = 0;
-    for (int i = 0; i < kCounterSlots; i++) t += ws.h_counters[off + i];
-    *out = (int64_t)t;
+    int64_t t[4] = {0, 0, 0, 0};
+    for (int k = 0; k < 4; k++)
+        for (int i = 0; i < kCounterSlots; i++) t[k] += (int64_t)ws.h_counters[off + k * kCounterSlots + i];
+    out->produced = t[0];
+    out->outputs = t[1];
+    out->active_vertices = t[2];
+    out->active_arcs = t[3];
     return MFBC_OK;
+}
+
+// Kernel times of the last product (events recorded by the launchers).
+void add_times(mfbc_graph *g, double *a, double *b) {
+    if (!g->timing) return;
+    float t0 = 0.f, t1 = 0.f;
+    if (hipEventElapsedTime(&t0, g->ev[0], g->ev[1]) == hipSuccess) *a += t0;
+    if (hipEventElapsedTime(&t1, g->ev[1], g->ev[2]) == hipSuccess) *b += t1;
 }
 
 int check_sources(mfbc_graph *g, const int32_t *d_sources, int64_t count, hipStream_t s) {
@@ -184,17 +201,29 @@ int check_sources(mfbc_graph *g, const int32_t *d_sources, int64_t count, hipStr
 int run_forward(mfbc_graph *g, int ncg, int nb, bool trace, int64_t *h_nnz, int max_products,
                 int32_t *products, hipStream_t s) {
     launch_fwd_init(g, ncg, nb, s);
-    int64_t nnz = 0;
+    hipEvent_t *ev = g->timing ? g->ev : nullptr;
+    const double arc_bytes = g->weighted ? 8.0 : 4.0;
+    int64_t prev = nb;           // the first frontier: one entry per source column
+    Counts c;
     int j = 0;
     do {
         j++;
         if (j > g->n + 1) return fail(MFBC_EDEVICE, "forward products did not converge");
-        launch_fwd_product(g, ncg, j, trace, s);
-        int rc = read_counter(g, j, s, &nnz);
+        launch_fwd_product(g, ncg, j, trace, s, ev);
+        int rc = read_counts(g, j, s, &c);
         if (rc) return rc;
-        if (h_nnz && j <= max_products) h_nnz[j - 1] = nnz;
-        g->stats.fwd_entries += nnz;
-    } while (nnz > 0);
+        if (h_nnz && j <= max_products) h_nnz[j - 1] = c.produced;
+        mfbc_stats &st = g->stats;
+        st.fwd_entries += c.produced;
+        st.fwd_outputs += c.outputs;
+        st.fwd_active_vertices += c.active_vertices;
+        st.fwd_active_arcs += c.active_arcs;
+        st.fwd_pull_launches++;
+        st.fwd_alg_bytes += 8.0 * c.active_vertices + arc_bytes * c.active_arcs +
+                            12.0 * (double)(prev + c.outputs + c.produced);
+        add_times(g, &st.fwd_pull_ms, &st.fwd_merge_ms);
+        prev = c.produced;
+    } while (c.produced > 0);
     g->stats.fwd_products += j;
     if (products) *products = j;
     int32_t flag = 0;
@@ -205,21 +234,39 @@ int run_forward(mfbc_graph *g, int ncg, int nb, bool trace, int64_t *h_nnz, int 
 }
 
 // Algorithm 2 on the batch whose T is in the workspace.
-int run_backward(mfbc_graph *g, int ncg, int32_t *products, hipStream_t s) {
-    launch_bwd_count(g, ncg, s, false);
-    int64_t nnz = 0;
-    int rc = read_counter(g, 0, s, &nnz);
+int run_backward(mfbc_graph *g, int ncg, int nb, int32_t *products, hipStream_t s) {
+    hipEvent_t *ev = g->timing ? g->ev : nullptr;
+    const double arc_bytes = g->weighted ? 8.0 : 4.0;
+    mfbc_stats &st = g->stats;
+    launch_bwd_count(g, ncg, s, ev);
+    Counts c;
+    int rc = read_counts(g, 0, s, &c);
     if (rc) return rc;
-    g->stats.bwd_entries += nnz;
+    st.bwd_entries += c.produced;
+    st.count_launches++;
+    st.count_alg_bytes += arc_bytes * (double)g->arcs + 8.0 * g->n + 8.0 * (double)g->n * nb;
+    if (g->timing) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, g->ev[0], g->ev[2]) == hipSuccess) st.count_ms += t;
+    }
+    int64_t prev = c.produced;
     int k = 0;
-    while (nnz > 0) {
+    while (c.produced > 0) {
         k++;
         if (k > g->n + 1) return fail(MFBC_EDEVICE, "backward products did not converge");
-        launch_bwd_product(g, ncg, k, false, s);
-        if ((rc = read_counter(g, k, s, &nnz))) return rc;
-        g->stats.bwd_entries += nnz;
+        launch_bwd_product(g, ncg, k, s, ev);
+        if ((rc = read_counts(g, k, s, &c))) return rc;
+        st.bwd_entries += c.produced;
+        st.bwd_outputs += c.outputs;
+        st.bwd_active_vertices += c.active_vertices;
+        st.bwd_active_arcs += c.active_arcs;
+        st.bwd_pull_launches++;
+        st.bwd_alg_bytes += 8.0 * c.active_vertices + arc_bytes * c.active_arcs +
+                            12.0 * (double)prev + 24.0 * (double)c.outputs;
+        add_times(g, &st.bwd_pull_ms, &st.bwd_merge_ms);
+        prev = c.produced;
     }
-    g->stats.bwd_products += k + 1;
+    st.bwd_products += k + 1;
     if (products) *products = k + 1;
     return MFBC_OK;
 }
@@ -263,7 +310,7 @@ int backward_impl(mfbc_graph *g, const int32_t *d_sources, int32_t nb, const int
     g->stats = mfbc_stats{};
     launch_set_sources(g, ncg, nb, d_sources, s);
     launch_import_forward(g, ncg, nb, d_dist, d_sigma, s);
-    if ((rc = run_backward(g, ncg, h_products, s))) return rc;
+    if ((rc = run_backward(g, ncg, nb, h_products, s))) return rc;
     g->stats.batches = 1;
     launch_export_backward(g, ncg, nb, d_delta, d_step, s);
     HIP_TRY(hipGetLastError());
@@ -304,6 +351,11 @@ int upload_csr(int32_t n, int64_t arcs, const int64_t *rp, const int32_t *col, c
 }
 
 void free_graph_memory(mfbc_graph *g) {
+    for (auto &e : g->ev) {
+        if (e) (void)hipEventDestroy(e);
+        e = nullptr;
+    }
+    g->timing = false;
     free_workspace(g->ws);
     free_plan(g->plan_in);
     free_plan(g->plan_out);
@@ -455,12 +507,22 @@ int mfbc_bc(mfbc_graph *g, const int32_t *d_sources, int64_t n_sources, int32_t 
         const int bcg = (nb + kWave - 1) / kWave;
         launch_set_sources(g, bcg, nb, d_sources + b0, s);
         if ((rc = run_forward(g, bcg, nb, false, nullptr, 0, nullptr, s))) return rc;
-        if ((rc = run_backward(g, bcg, nullptr, s))) return rc;
+        if ((rc = run_backward(g, bcg, nb, nullptr, s))) return rc;
         g->stats.batches++;
     }
     launch_lambda_reduce(g, ncg, d_bc, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
+    return MFBC_OK;
+}
+
+int mfbc_enable_timing(mfbc_graph *g, int enable) {
+    if (!g) return fail(MFBC_EINVAL, "graph handle is NULL");
+    DeviceGuard dg(g->device);
+    if (enable && !g->ev[0]) {
+        for (auto &e : g->ev) HIP_TRY(hipEventCreate(&e));
+    }
+    g->timing = enable != 0 && g->ev[0] != nullptr;
     return MFBC_OK;
 }
 

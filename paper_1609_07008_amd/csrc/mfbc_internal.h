@@ -77,7 +77,7 @@ struct Workspace {
     uint32_t *abits[2] = {nullptr, nullptr}; // any-column activity bitmaps [n/32]
     int32_t *pd = nullptr;             // partial weights / counters [cg][slots][64]
     double *pm = nullptr;              // partial multiplicities / sums
-    unsigned long long *counters = nullptr;  // [ring][slots]
+    unsigned long long *counters = nullptr;  // [ring][4][slots]
     int32_t *flags = nullptr;          // [0]: path count overflow
     double *lam = nullptr;             // per-column-group lambda parts [cg][n]
     int32_t *src = nullptr;            // column -> source vertex, -1 = padding
@@ -102,15 +102,19 @@ struct mfbc_graph {
     mfbc::Workspace ws;
     mfbc_stats stats{};
     std::vector<int64_t> h_rp_out, h_rp_in;   // host copies for re-planning
+    bool timing = false;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
 };
 
 namespace mfbc {
 
 // ---- launchers (kernels.hip) ----
 void launch_fwd_init(mfbc_graph *g, int ncg, int nb, hipStream_t s);
-void launch_fwd_product(mfbc_graph *g, int ncg, int j, bool trace, hipStream_t s);
-void launch_bwd_count(mfbc_graph *g, int ncg, hipStream_t s, bool trace);
-void launch_bwd_product(mfbc_graph *g, int ncg, int k, bool trace, hipStream_t s);
+// `ev` (nullable): three events recorded before the product kernel, between
+// it and the merge kernel, and after the merge.
+void launch_fwd_product(mfbc_graph *g, int ncg, int j, bool trace, hipStream_t s, hipEvent_t *ev);
+void launch_bwd_count(mfbc_graph *g, int ncg, hipStream_t s, hipEvent_t *ev);
+void launch_bwd_product(mfbc_graph *g, int ncg, int k, hipStream_t s, hipEvent_t *ev);
 void launch_lambda_zero(mfbc_graph *g, int ncg, hipStream_t s);
 void launch_lambda_reduce(mfbc_graph *g, int ncg, double *d_bc, hipStream_t s);
 void launch_export_forward(mfbc_graph *g, int ncg, int nb, int32_t *d_dist, double *d_sigma,

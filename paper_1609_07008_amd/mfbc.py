@@ -31,14 +31,20 @@ SIGNATURES = {
     "mfbc_forward_trace": ([_P, _P, _I32, _P, _P, _P, _P, _I32, _P, _P], ctypes.c_int),
     "mfbc_backward_trace": ([_P, _P, _I32, _P, _P, _P, _P, _P, _P], ctypes.c_int),
     "mfbc_get_stats": ([_P, _P], ctypes.c_int),
+    "mfbc_enable_timing": ([_P, ctypes.c_int], ctypes.c_int),
     "mfbc_graph_info": ([_P, _P, _P, _P], ctypes.c_int),
     "mfbc_last_error": ([], ctypes.c_char_p),
 }
 
 
 class MfbcStats(ctypes.Structure):
-    _fields_ = [("fwd_products", _I64), ("bwd_products", _I64), ("fwd_entries", _I64),
-                ("bwd_entries", _I64), ("batches", _I64)]
+    _fields_ = [(k, _I64) for k in (
+        "fwd_products", "bwd_products", "fwd_entries", "bwd_entries", "batches",
+        "fwd_outputs", "bwd_outputs", "fwd_active_vertices", "fwd_active_arcs",
+        "bwd_active_vertices", "bwd_active_arcs", "fwd_pull_launches", "bwd_pull_launches",
+        "count_launches")] + [(k, ctypes.c_double) for k in (
+        "fwd_pull_ms", "fwd_merge_ms", "count_ms", "bwd_pull_ms", "bwd_merge_ms", "other_ms",
+        "fwd_alg_bytes", "bwd_alg_bytes", "count_alg_bytes")]
 
 
 class MfbcError(RuntimeError):
@@ -181,6 +187,10 @@ class DeviceGraph:
                                     _stream(t, stream))
         _check(rc)
         return out
+
+    def enable_timing(self, on: bool = True):
+        """Time every product kernel with HIP events on the call's stream."""
+        _check(load_library().mfbc_enable_timing(self.handle, 1 if on else 0))
 
     def stats(self) -> dict:
         s = MfbcStats()
