@@ -70,12 +70,15 @@ __device__ __forceinline__ double wave_sum(double x) {
 // Counters of one product, kCounterSlots-wide arrays (spread to avoid a
 // single hot address): [0] frontier entries produced, [1] output entries
 // that received a candidate, [2] active vertices read, [3] arcs of their rows.
-// Block-level sum of per-thread counts, then one atomic per array.
+// c0 and c1 are wave-uniform (every lane holds the wave's count; lane 0's
+// is used), c2 and c3 are per-thread.  Block-level sum, then one atomic per
+// array.
 __device__ __forceinline__ void flush_counts(unsigned long long c0, unsigned long long c1,
                                              unsigned long long c2, unsigned long long c3,
                                              unsigned long long *ctr) {
     __shared__ unsigned long long s_cnt[4][kWavesPerBlock];
-    unsigned long long v[4] = {c0, c1, c2, c3};
+    const bool first = (threadIdx.x & (kWave - 1)) == 0;
+    unsigned long long v[4] = {first ? c0 : 0ull, first ? c1 : 0ull, c2, c3};
 #pragma unroll
     for (int k = 0; k < 4; k++) {
 #pragma unroll
