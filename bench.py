@@ -100,7 +100,20 @@ def main():
     ap.add_argument("--batch", type=int, default=None, help="override the batch size")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--stats", action="store_true", help="print per-kernel stats to stderr")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (calibrates the "
+                         "HBM byte counters of rocprofv3) and exit")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        torch.cuda.set_device(0)
+        a = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": a.numel() * 4}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the hot path runs on a single MI355X; "
               "a multi-GPU run (source batches sharded over GPUs, one allreduce of lambda) "
