@@ -98,12 +98,21 @@ __device__ __forceinline__ void flush_counts(unsigned long long c0, unsigned lon
     }
 }
 
-// Clear a vertex bitmap while counting its set bits and their row lengths.
-__device__ __forceinline__ void clear_and_count(uint32_t *bits, int words, const int64_t *rp,
-                                                unsigned long long &nv, unsigned long long &na) {
+// Clear `planes` vertex bitmaps of `words` words each while counting the
+// vertices set in any of them and the arcs of their rows.
+__device__ __forceinline__ void clear_and_count(uint32_t *bits, int words, int planes,
+                                                const int64_t *rp, unsigned long long &nv,
+                                                unsigned long long &na) {
     const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
     for (int i = gtid; i < words; i += gridDim.x * blockDim.x) {
-        uint32_t w = bits[i];
+        uint32_t w = 0u;
+        for (int p = 0; p < planes; p++) {
+            const uint32_t x = bits[(size_t)p * words + i];
+            if (x) {
+                w |= x;
+                bits[(size_t)p * words + i] = 0u;
+            }
+        }
         if (w) {
             nv += __popc(w);
             while (w) {
@@ -112,7 +121,6 @@ __device__ __forceinline__ void clear_and_count(uint32_t *bits, int words, const
                 const int u = i * 32 + b;
                 na += (unsigned long long)(rp[u + 1] - rp[u]);
             }
-            bits[i] = 0u;
         }
     }
 }
@@ -125,30 +133,59 @@ __device__ __forceinline__ uint64_t owner_mask(int64_t e, int64_t vend) {
 }
 
 // ===================================================================== forward
+//
+// Frontier tuples are packed into 32 bits: (weight << mb) | m, where the
+// multiplicity m is stored inline when 1 <= m < 2^mb and m = 0 means "read
+// the binary64 multiplicity from the escape array".  mb is chosen per graph
+// from the largest possible frontier weight, (n - 1) * max weight (a frontier
+// entry is a least-weight walk no heavier than any shorter one, hence a simple
+// path).  kSent marks a lane that is not in the frontier.  A row of 64 lanes
+// is 256 B; with integer weights drawn from a wide range almost every
+// multiplicity is small, so the 8-byte escape is rarely read.
+constexpr uint32_t kSent = 0xffffffffu;
+
+// Arc access: AM = 0 unweighted (col), 1 packed (col | w << cb), 2 separate arrays.
+struct ArcSrc {
+    const int32_t *col;
+    const int32_t *w;
+    const uint32_t *pk;
+    int cb;
+    uint32_t cmask;
+};
+
+template <int AM>
+__device__ __forceinline__ void load_arc(const ArcSrc &s, int64_t e, int &u, int &wt) {
+    if (AM == 1) {
+        const uint32_t p = s.pk[e];
+        u = (int)(p & s.cmask);
+        wt = (int)(p >> s.cb);
+    } else {
+        u = s.col[e];
+        wt = AM == 2 ? s.w[e] : 1;
+    }
+}
+
 struct FwdArgs {
     const Task *tasks;
     const Hub *hubs;
-    int ntasks, nhubs, nslots, ncg, n, j;
+    int ntasks, nhubs, nslots, ncg, n, j, nwords;
+    int mb;                    // inline multiplicity bits
     const int64_t *rp;
-    const int32_t *col;
-    const int32_t *w;
-    const uint32_t *abits;     // frontier F_{j-1}
-    const uint64_t *fbits;
-    const int32_t *fdist;
-    const double *fsig;
+    ArcSrc arcs;
+    const uint32_t *abits;     // frontier F_{j-1}: [cg][nwords] activity bitmaps
+    const uint32_t *ftup;      //   packed tuples [cg][n][64]
+    const double *fsig;        //   escaped multiplicities
     int32_t *tdist;            // T
     double *tsig;
     uint32_t *abits_n;         // frontier F_j
-    uint64_t *fbits_n;
-    int32_t *fdist_n;
+    uint32_t *ftup_n;
     double *fsig_n;
     int32_t *pd;               // hub partials
     double *pm;
     unsigned long long *ctr;   // counter slots of product j
     int32_t *flags;
     uint64_t *fmask;           // trace (nullable)
-    uint32_t *clear_bits;      // merge: bitmap to clear (F_{j-1}'s)
-    int clear_words;
+    uint32_t *clear_bits;      // merge: bitmaps to clear (F_{j-1}'s), ncg planes
     unsigned long long *clear_ctr;  // merge: counter slots of product j+1
 };
 
@@ -159,7 +196,7 @@ __device__ __forceinline__ uint64_t fwd_finalize(const FwdArgs &a, size_t cgv, i
     const bool has = bd != kInf;
     uint64_t bits = 0;
     const uint64_t hm = ballot(has);
-    if (lane == 0) outs += __popcll(hm);
+    outs += __popcll(hm);
     if (hm) {
         const size_t idx = (cgv + (size_t)v) * kWave + lane;
         bool keep = false;
@@ -176,19 +213,26 @@ __device__ __forceinline__ uint64_t fwd_finalize(const FwdArgs &a, size_t cgv, i
                 keep = true;
                 if (__builtin_isinf(s)) a.flags[0] = 1;
             }
-            if (keep) {
-                a.fdist_n[idx] = bd;
-                a.fsig_n[idx] = bm;
-                if (a.fmask && a.j <= 64) a.fmask[idx] |= 1ull << (a.j - 1);
-            }
         }
         bits = ballot(keep);
+        if (bits) {
+            uint32_t t = kSent;
+            if (keep) {
+                const double mmax = (double)((1u << a.mb) - 1u);
+                const uint32_t ms = bm <= mmax ? (uint32_t)bm : 0u;
+                if (ms == 0u) a.fsig_n[idx] = bm;
+                t = ((uint32_t)bd << a.mb) | ms;
+                if (a.fmask && a.j <= 64) a.fmask[idx] |= 1ull << (a.j - 1);
+            }
+            a.ftup_n[idx] = t;
+        }
     }
-    if (lane == 0) a.fbits_n[cgv + (size_t)v] = bits;
     return bits;
 }
 
-template <bool W>
+constexpr int kFwdUnroll = 8;
+
+template <int AM>
 __global__ __launch_bounds__(kBlock) void k_fwd_pull(FwdArgs a) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
@@ -199,9 +243,10 @@ __global__ __launch_bounds__(kBlock) void k_fwd_pull(FwdArgs a) {
         const int v0 = uni(tp->v0), v1 = uni(tp->v1), hub = uni(tp->hub), part = uni(tp->part);
         const int64_t e0 = uni64(tp->e0), e1 = uni64(tp->e1);
         const size_t cgv = (size_t)cg * (size_t)a.n;
-        const int32_t *Fd = a.fdist + cgv * kWave;
+        const uint32_t *Ft = a.ftup + cgv * kWave;
         const double *Fm = a.fsig + cgv * kWave;
-        const uint64_t *Fb = a.fbits + cgv;
+        const uint32_t *Ab = a.abits + (size_t)cg * a.nwords;
+        const uint32_t mmask = (1u << a.mb) - 1u;
         int v = v0;
         int64_t vend = hub >= 0 ? e1 : a.rp[v0 + 1];
         int bd = kInf;
@@ -210,13 +255,12 @@ __global__ __launch_bounds__(kBlock) void k_fwd_pull(FwdArgs a) {
         for (int64_t e = e0; e < e1; e += kWave) {
             const int64_t my = e + lane;
             int u = 0, wt = 1;
-            uint64_t fb = 0;
+            bool act = false;
             if (my < e1) {
-                u = a.col[my];
-                if (W) wt = a.w[my];
-                if ((a.abits[u >> 5] >> (u & 31)) & 1u) fb = Fb[u];
+                load_arc<AM>(a.arcs, my, u, wt);
+                act = (Ab[u >> 5] >> (u & 31)) & 1u;
             }
-            uint64_t am = ballot(fb != 0);
+            uint64_t am = ballot(act);
             while (am) {
                 const int j0 = __ffsll((unsigned long long)am) - 1;
                 if (hub < 0) {
@@ -230,39 +274,47 @@ __global__ __launch_bounds__(kBlock) void k_fwd_pull(FwdArgs a) {
                         bm = 0.0;
                     }
                 }
-                // up to four active arcs of the same owner, loads issued together
+                // up to kFwdUnroll active arcs of the same owner, loads issued together
                 uint64_t cand = am & owner_mask(e, vend);
-                int js[4];
+                int js[kFwdUnroll];
 #pragma unroll
-                for (int k = 0; k < 4; k++) {
+                for (int k = 0; k < kFwdUnroll; k++) {
                     js[k] = cand ? __ffsll((unsigned long long)cand) - 1 : -1;
                     cand &= cand - 1;
                 }
-                int dk[4];
-                double mk[4];
+                uint32_t tk[kFwdUnroll];
+                int uk[kFwdUnroll], wk[kFwdUnroll];
 #pragma unroll
-                for (int k = 0; k < 4; k++) {
-                    dk[k] = kInf;
-                    mk[k] = 0.0;
+                for (int k = 0; k < kFwdUnroll; k++) {
+                    tk[k] = kSent;
+                    uk[k] = 0;
+                    wk[k] = 0;
                     if (js[k] >= 0) {
                         am &= ~(1ull << js[k]);
-                        const int uj = rdlane(u, js[k]);
-                        const int wj = W ? rdlane(wt, js[k]) : 1;
-                        const uint64_t fbj = rdlane64(fb, js[k]);
-                        if ((fbj >> lane) & 1ull) {
-                            const size_t idx = (size_t)uj * kWave + lane;
-                            dk[k] = Fd[idx] + wj;
-                            mk[k] = Fm[idx];
-                        }
+                        uk[k] = rdlane(u, js[k]);
+                        wk[k] = AM ? rdlane(wt, js[k]) : 1;
+                        tk[k] = Ft[(size_t)uk[k] * kWave + lane];
+                    }
+                }
+                double mk[kFwdUnroll];
+#pragma unroll
+                for (int k = 0; k < kFwdUnroll; k++) {
+                    mk[k] = 0.0;
+                    if (tk[k] != kSent) {
+                        const uint32_t ms = tk[k] & mmask;
+                        mk[k] = ms ? (double)ms : Fm[(size_t)uk[k] * kWave + lane];
                     }
                 }
 #pragma unroll
-                for (int k = 0; k < 4; k++) {
-                    if (dk[k] < bd) {
-                        bd = dk[k];
-                        bm = mk[k];
-                    } else if (dk[k] == bd && dk[k] != kInf) {
-                        bm += mk[k];
+                for (int k = 0; k < kFwdUnroll; k++) {
+                    if (tk[k] != kSent) {
+                        const int d = (int)(tk[k] >> a.mb) + wk[k];
+                        if (d < bd) {
+                            bd = d;
+                            bm = mk[k];
+                        } else if (d == bd) {
+                            bm += mk[k];
+                        }
                     }
                 }
             }
@@ -276,7 +328,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_pull(FwdArgs a) {
                 bd = kInf;
                 bm = 0.0;
             }
-            if (lane == 0 && run_act) or_run_bits(a.abits_n, v0, run_act);
+            if (lane == 0 && run_act) or_run_bits(a.abits_n + (size_t)cg * a.nwords, v0, run_act);
         } else {
             const size_t pidx = ((size_t)cg * a.nslots + part) * kWave + lane;
             a.pd[pidx] = bd;
@@ -287,11 +339,12 @@ __global__ __launch_bounds__(kBlock) void k_fwd_pull(FwdArgs a) {
 }
 
 // Combine the slices of split rows (fixed slice order) and finish them;
-// also clears the previous frontier's bitmap and the next product's counters.
+// also clears the previous frontier's bitmaps (counting the vertices active
+// in some column and their arcs) and the next product's counters.
 __global__ __launch_bounds__(kBlock) void k_fwd_merge(FwdArgs a) {
     const int gtid = blockIdx.x * kBlock + threadIdx.x;
     unsigned long long nv = 0, na = 0;
-    clear_and_count(a.clear_bits, a.clear_words, a.rp, nv, na);
+    clear_and_count(a.clear_bits, a.nwords, a.ncg, a.rp, nv, na);
     if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
@@ -316,7 +369,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_merge(FwdArgs a) {
         }
         const uint64_t b = fwd_finalize(a, cgv, v, bd, bm, lane, outs);
         produced += __popcll(b);
-        if (b && lane == 0) atomicOr(a.abits_n + (v >> 5), 1u << (v & 31));
+        if (b && lane == 0) atomicOr(a.abits_n + (size_t)cg * a.nwords + (v >> 5), 1u << (v & 31));
     }
     flush_counts(produced, outs, nv, na, a.ctr);
 }
@@ -325,15 +378,15 @@ __global__ __launch_bounds__(kBlock) void k_fwd_merge(FwdArgs a) {
 struct BwdArgs {
     const Task *tasks;
     const Hub *hubs;
-    int ntasks, nhubs, nslots, ncg, n, k;
+    int ntasks, nhubs, nslots, ncg, n, k, nwords;
     const int64_t *rp;         // out-arcs
     const int32_t *col;
     const int32_t *w;
     const int32_t *src;        // column -> source vertex (-1 = padding)
     const int32_t *tdist;      // tau
     const double *tsig;        // sigma
-    const uint32_t *abits;     // frontier B_{k-1}
-    const uint64_t *fbits;
+    const uint32_t *abits;     // frontier B_{k-1}: [cg][nwords] activity bitmaps
+    const uint64_t *fbits;     //   lane masks [cg][n]
     uint32_t *abits_n;         // frontier B_k
     uint64_t *fbits_n;
     int32_t *cnt;              // counters (> 0 pending, -1 finished or unreachable)
@@ -344,8 +397,7 @@ struct BwdArgs {
     int32_t *pd;
     double *pm;
     unsigned long long *ctr;
-    uint32_t *clear_bits;
-    int clear_words;
+    uint32_t *clear_bits;      // ncg planes
     unsigned long long *clear_ctr;
 };
 
@@ -421,14 +473,14 @@ __global__ __launch_bounds__(kBlock) void k_bwd_count(BwdArgs a) {
                 if (b) run_act |= 1ull << (x - v0);
             }
         }
-        if (hub < 0 && lane == 0 && run_act) or_run_bits(a.abits_n, v0, run_act);
+        if (hub < 0 && lane == 0 && run_act)
+            or_run_bits(a.abits_n + (size_t)cg * a.nwords, v0, run_act);
     }
     flush_counts(produced, 0, 0, 0, a.ctr);
 }
 
 __global__ __launch_bounds__(kBlock) void k_bwd_count_merge(BwdArgs a) {
     const int gtid = blockIdx.x * kBlock + threadIdx.x;
-    for (int i = gtid; i < a.clear_words; i += gridDim.x * kBlock) a.clear_bits[i] = 0u;
     if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
@@ -443,7 +495,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_count_merge(BwdArgs a) {
         const int dx = a.tdist[(cgv + (size_t)x) * kWave + lane];
         const uint64_t b = count_finalize(a, cgv, cg, x, dx, c, lane);
         produced += __popcll(b);
-        if (b && lane == 0) atomicOr(a.abits_n + (x >> 5), 1u << (x & 31));
+        if (b && lane == 0) atomicOr(a.abits_n + (size_t)cg * a.nwords + (x >> 5), 1u << (x & 31));
     }
     flush_counts(produced, 0, 0, 0, a.ctr);
 }
@@ -501,6 +553,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_pull(BwdArgs a) {
         const int32_t *Td = a.tdist + cgv * kWave;
         const double *Q = a.q + cgv * kWave;
         const uint64_t *Fb = a.fbits + cgv;
+        const uint32_t *Ab = a.abits + (size_t)cg * a.nwords;
         int x = v0;
         int64_t vend = hub >= 0 ? e1 : a.rp[v0 + 1];
         bool loaded = false;
@@ -514,7 +567,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_pull(BwdArgs a) {
             if (my < e1) {
                 y = a.col[my];
                 if (W) wt = a.w[my];
-                if ((a.abits[y >> 5] >> (y & 31)) & 1u) fb = Fb[y];
+                if ((Ab[y >> 5] >> (y & 31)) & 1u) fb = Fb[y];
             }
             uint64_t am = ballot(fb != 0);
             while (am) {
@@ -595,7 +648,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_pull(BwdArgs a) {
                 got = 0;
                 acc = 0.0;
             }
-            if (lane == 0 && run_act) or_run_bits(a.abits_n, v0, run_act);
+            if (lane == 0 && run_act) or_run_bits(a.abits_n + (size_t)cg * a.nwords, v0, run_act);
         } else {
             const size_t pidx = ((size_t)cg * a.nslots + part) * kWave + lane;
             a.pd[pidx] = got;
@@ -608,7 +661,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_pull(BwdArgs a) {
 __global__ __launch_bounds__(kBlock) void k_bwd_merge(BwdArgs a) {
     const int gtid = blockIdx.x * kBlock + threadIdx.x;
     unsigned long long nv = 0, na = 0;
-    clear_and_count(a.clear_bits, a.clear_words, a.rp, nv, na);
+    clear_and_count(a.clear_bits, a.nwords, a.ncg, a.rp, nv, na);
     if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
@@ -628,7 +681,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_merge(BwdArgs a) {
         const int cx = a.cnt[(cgv + (size_t)x) * kWave + lane];
         const uint64_t b = bwd_finalize(a, cgv, cg, x, cx, acc, got, lane, outs);
         produced += __popcll(b);
-        if (b && lane == 0) atomicOr(a.abits_n + (x >> 5), 1u << (x & 31));
+        if (b && lane == 0) atomicOr(a.abits_n + (size_t)cg * a.nwords + (x >> 5), 1u << (x & 31));
     }
     flush_counts(produced, outs, nv, na, a.ctr);
 }
@@ -639,10 +692,10 @@ __global__ void k_set_sources(int32_t *src, int total, int nb, const int32_t *in
     if (i < total) src[i] = i < nb ? in[i] : -1;
 }
 
-// T = (INF, 0) everywhere, frontier F_0 cleared, bitmaps and counters zeroed.
-__global__ void k_fwd_fill(int32_t *tdist, double *tsig, size_t total, uint64_t *fbits0, size_t nbits,
-                           uint32_t *ab0, uint32_t *ab1, int nwords, unsigned long long *ctr, int nctr,
-                           int32_t *flags, uint64_t *fmask) {
+// T = (INF, 0) everywhere, both frontier bitmaps cleared, counters zeroed.
+__global__ void k_fwd_fill(int32_t *tdist, double *tsig, size_t total, uint32_t *ab0, uint32_t *ab1,
+                           size_t nab, unsigned long long *ctr, int nctr, int32_t *flags,
+                           uint64_t *fmask) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (size_t i = t0; i < total; i += stride) {
@@ -650,8 +703,7 @@ __global__ void k_fwd_fill(int32_t *tdist, double *tsig, size_t total, uint64_t 
         tsig[i] = 0.0;
         if (fmask) fmask[i] = 0ull;
     }
-    for (size_t i = t0; i < nbits; i += stride) fbits0[i] = 0ull;
-    for (size_t i = t0; i < (size_t)nwords; i += stride) {
+    for (size_t i = t0; i < nab; i += stride) {
         ab0[i] = 0u;
         ab1[i] = 0u;
     }
@@ -659,9 +711,18 @@ __global__ void k_fwd_fill(int32_t *tdist, double *tsig, size_t total, uint64_t 
     if (t0 == 0) flags[0] = 0;
 }
 
-// The sources themselves: T(s, s) = (0, 1) and the first frontier {s}.
-__global__ void k_fwd_seed(const int32_t *src, int nb, int n, int32_t *tdist, double *tsig,
-                           int32_t *fdist, double *fsig, uint64_t *fbits, uint32_t *abits) {
+// Rows of the sources in the first frontier start with every lane absent.
+__global__ void k_fwd_seed_rows(const int32_t *src, int nb, int n, uint32_t *ftup) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nb) return;
+    const size_t row = ((size_t)(c / kWave) * n + src[c]) * kWave;
+    for (int l = 0; l < kWave; l++) ftup[row + l] = kSent;
+}
+
+// The sources themselves: T(s, s) = (0, 1) and the first frontier {s}
+// carrying (0, 1).
+__global__ void k_fwd_seed(const int32_t *src, int nb, int n, int nwords, int32_t *tdist,
+                           double *tsig, uint32_t *ftup, uint32_t *abits) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nb) return;
     const int v = src[c];
@@ -669,10 +730,8 @@ __global__ void k_fwd_seed(const int32_t *src, int nb, int n, int32_t *tdist, do
     const size_t idx = ((size_t)cg * n + v) * kWave + lane;
     tdist[idx] = 0;
     tsig[idx] = 1.0;
-    fdist[idx] = 0;
-    fsig[idx] = 1.0;
-    atomicOr((unsigned long long *)(fbits + (size_t)cg * n + v), 1ull << lane);
-    atomicOr(abits + (v >> 5), 1u << (v & 31));
+    ftup[idx] = 1u;                      // weight 0, multiplicity 1 inline
+    atomicOr(abits + (size_t)cg * nwords + (v >> 5), 1u << (v & 31));
 }
 
 __global__ void k_zero_f64(double *p, size_t total) {
@@ -755,6 +814,18 @@ inline int blocks_for(size_t work, int per_block, int cap = 1 << 20) {
 }  // namespace
 
 // ===================================================================== launchers
+static ArcSrc arc_src(const Csr &c) {
+    ArcSrc r{};
+    r.col = c.col;
+    r.w = c.w;
+    r.pk = c.pk;
+    r.cb = c.cb;
+    r.cmask = c.cb >= 32 ? 0xffffffffu : ((1u << c.cb) - 1u);
+    return r;
+}
+
+static int arc_mode(const Csr &c) { return c.w == nullptr ? 0 : (c.pk ? 1 : 2); }
+
 static FwdArgs fwd_args(mfbc_graph *g, int ncg, int j, bool trace) {
     Workspace &ws = g->ws;
     const int b = (j - 1) & 1;  // buffer holding F_{j-1}
@@ -767,18 +838,17 @@ static FwdArgs fwd_args(mfbc_graph *g, int ncg, int j, bool trace) {
     a.ncg = ncg;
     a.n = g->n;
     a.j = j;
+    a.nwords = (g->n + 31) / 32;
+    a.mb = g->mb;
     a.rp = g->in.rp;
-    a.col = g->in.col;
-    a.w = g->in.w;
+    a.arcs = arc_src(g->in);
     a.abits = ws.abits[b];
-    a.fbits = ws.fbits[b];
-    a.fdist = ws.fdist[b];
+    a.ftup = (const uint32_t *)ws.fdist[b];
     a.fsig = ws.fsig[b];
     a.tdist = ws.tdist;
     a.tsig = ws.tsig;
     a.abits_n = ws.abits[b ^ 1];
-    a.fbits_n = ws.fbits[b ^ 1];
-    a.fdist_n = ws.fdist[b ^ 1];
+    a.ftup_n = (uint32_t *)ws.fdist[b ^ 1];
     a.fsig_n = ws.fsig[b ^ 1];
     a.pd = ws.pd;
     a.pm = ws.pm;
@@ -786,7 +856,6 @@ static FwdArgs fwd_args(mfbc_graph *g, int ncg, int j, bool trace) {
     a.flags = ws.flags;
     a.fmask = trace ? ws.fmask : nullptr;
     a.clear_bits = ws.abits[b];
-    a.clear_words = (g->n + 31) / 32;
     a.clear_ctr = ws.counters + (size_t)((j + 1) % kCounterRing) * 4 * kCounterSlots;
     return a;
 }
@@ -802,11 +871,13 @@ void launch_fwd_init(mfbc_graph *g, int ncg, int nb, hipStream_t s) {
     const size_t total = (size_t)ncg * g->n * kWave;
     const int nwords = (g->n + 31) / 32;
     hipLaunchKernelGGL(k_fwd_fill, dim3(blocks_for(total, 256, 65536)), dim3(256), 0, s, ws.tdist,
-                       ws.tsig, total, ws.fbits[0], (size_t)ncg * g->n, ws.abits[0], ws.abits[1],
-                       nwords, ws.counters, kCounterRing * 4 * kCounterSlots, ws.flags,
+                       ws.tsig, total, ws.abits[0], ws.abits[1], (size_t)ncg * nwords,
+                       ws.counters, kCounterRing * 4 * kCounterSlots, ws.flags,
                        ws.fmask && ws.fmask_ncg >= ncg ? ws.fmask : nullptr);
+    hipLaunchKernelGGL(k_fwd_seed_rows, dim3(blocks_for(nb, 256)), dim3(256), 0, s, ws.src, nb,
+                       g->n, (uint32_t *)ws.fdist[0]);
     hipLaunchKernelGGL(k_fwd_seed, dim3(blocks_for(nb, 256)), dim3(256), 0, s, ws.src, nb, g->n,
-                       ws.tdist, ws.tsig, ws.fdist[0], ws.fsig[0], ws.fbits[0], ws.abits[0]);
+                       nwords, ws.tdist, ws.tsig, (uint32_t *)ws.fdist[0], ws.abits[0]);
 }
 
 void launch_fwd_product(mfbc_graph *g, int ncg, int j, bool trace, hipStream_t s,
@@ -815,14 +886,15 @@ void launch_fwd_product(mfbc_graph *g, int ncg, int j, bool trace, hipStream_t s
     if (ev) hipEventRecord(ev[0], s);
     const size_t waves = (size_t)a.ntasks * ncg;
     const int grid = blocks_for(waves, kWavesPerBlock, 0x7fffffff);
-    if (g->in.w)
-        hipLaunchKernelGGL(k_fwd_pull<true>, dim3(grid), dim3(kBlock), 0, s, a);
-    else
-        hipLaunchKernelGGL(k_fwd_pull<false>, dim3(grid), dim3(kBlock), 0, s, a);
+    switch (arc_mode(g->in)) {
+        case 0: hipLaunchKernelGGL(k_fwd_pull<0>, dim3(grid), dim3(kBlock), 0, s, a); break;
+        case 1: hipLaunchKernelGGL(k_fwd_pull<1>, dim3(grid), dim3(kBlock), 0, s, a); break;
+        default: hipLaunchKernelGGL(k_fwd_pull<2>, dim3(grid), dim3(kBlock), 0, s, a); break;
+    }
     if (ev) hipEventRecord(ev[1], s);
     const size_t mw = (size_t)a.nhubs * ncg;
     int mgrid = blocks_for(mw, kWavesPerBlock, 0x7fffffff);
-    const int cgrid = blocks_for((size_t)a.clear_words, kBlock, 1024);
+    const int cgrid = blocks_for((size_t)a.nwords, kBlock, 1024);
     if (cgrid > mgrid) mgrid = cgrid;
     hipLaunchKernelGGL(k_fwd_merge, dim3(mgrid), dim3(kBlock), 0, s, a);
     if (ev) hipEventRecord(ev[2], s);
@@ -860,8 +932,8 @@ static BwdArgs bwd_args(mfbc_graph *g, int ncg, int k) {
     a.pd = ws.pd;
     a.pm = ws.pm;
     a.ctr = ws.counters + (size_t)(k % kCounterRing) * 4 * kCounterSlots;
+    a.nwords = (g->n + 31) / 32;
     a.clear_bits = ws.abits[b];
-    a.clear_words = (g->n + 31) / 32;
     a.clear_ctr = ws.counters + (size_t)((k + 1) % kCounterRing) * 4 * kCounterSlots;
     return a;
 }
@@ -871,8 +943,8 @@ void launch_bwd_count(mfbc_graph *g, int ncg, hipStream_t s, hipEvent_t *ev) {
     // the counting product writes B_0 into buffer 0: clear its bitmap and
     // this product's counters first
     const int nwords = (g->n + 31) / 32;
-    hipMemsetAsync(ws.abits[0], 0, (size_t)nwords * 4, s);
-    hipMemsetAsync(ws.abits[1], 0, (size_t)nwords * 4, s);
+    hipMemsetAsync(ws.abits[0], 0, (size_t)nwords * ncg * 4, s);
+    hipMemsetAsync(ws.abits[1], 0, (size_t)nwords * ncg * 4, s);
     hipMemsetAsync(ws.counters, 0, sizeof(unsigned long long) * kCounterRing * 4 * kCounterSlots, s);
     BwdArgs a = bwd_args(g, ncg, 0);
     if (ev) hipEventRecord(ev[0], s);
@@ -883,7 +955,7 @@ void launch_bwd_count(mfbc_graph *g, int ncg, hipStream_t s, hipEvent_t *ev) {
     else
         hipLaunchKernelGGL(k_bwd_count<false>, dim3(grid), dim3(kBlock), 0, s, a);
     int mgrid = blocks_for((size_t)a.nhubs * ncg, kWavesPerBlock, 0x7fffffff);
-    const int cgrid = blocks_for((size_t)a.clear_words, kBlock, 1024);
+    const int cgrid = blocks_for((size_t)a.nwords, kBlock, 1024);
     if (cgrid > mgrid) mgrid = cgrid;
     hipLaunchKernelGGL(k_bwd_count_merge, dim3(mgrid), dim3(kBlock), 0, s, a);
     if (ev) {
@@ -903,7 +975,7 @@ void launch_bwd_product(mfbc_graph *g, int ncg, int k, hipStream_t s, hipEvent_t
         hipLaunchKernelGGL(k_bwd_pull<false>, dim3(grid), dim3(kBlock), 0, s, a);
     if (ev) hipEventRecord(ev[1], s);
     int mgrid = blocks_for((size_t)a.nhubs * ncg, kWavesPerBlock, 0x7fffffff);
-    const int cgrid = blocks_for((size_t)a.clear_words, kBlock, 1024);
+    const int cgrid = blocks_for((size_t)a.nwords, kBlock, 1024);
     if (cgrid > mgrid) mgrid = cgrid;
     hipLaunchKernelGGL(k_bwd_merge, dim3(mgrid), dim3(kBlock), 0, s, a);
     if (ev) hipEventRecord(ev[2], s);

@@ -128,7 +128,7 @@ int ensure_workspace(mfbc_graph *g, int ncg, bool trace) {
             (rc = dalloc(&ws.fdist[0], tile)) || (rc = dalloc(&ws.fdist[1], tile)) ||
             (rc = dalloc(&ws.fsig[0], tile)) || (rc = dalloc(&ws.fsig[1], tile)) ||
             (rc = dalloc(&ws.fbits[0], n * ncg)) || (rc = dalloc(&ws.fbits[1], n * ncg)) ||
-            (rc = dalloc(&ws.abits[0], nwords)) || (rc = dalloc(&ws.abits[1], nwords)) ||
+            (rc = dalloc(&ws.abits[0], nwords * ncg)) || (rc = dalloc(&ws.abits[1], nwords * ncg)) ||
             (rc = dalloc(&ws.pd, slots)) || (rc = dalloc(&ws.pm, slots)) ||
             (rc = dalloc(&ws.counters, (size_t)kCounterRing * 4 * kCounterSlots)) ||
             (rc = dalloc(&ws.flags, 4)) || (rc = dalloc(&ws.lam, n * ncg)) ||
@@ -337,8 +337,19 @@ bool build_transpose(int32_t n, int64_t arcs, const int64_t *rp, const int32_t *
     return true;
 }
 
+int bits_for(int64_t x) {
+    int b = 0;
+    while (x > 0) {
+        b++;
+        x >>= 1;
+    }
+    return b;
+}
+
+// Device copy of one CSR orientation; weighted rows also get the packed
+// (column | weight << cb) words when both fit 32 bits, halving arc traffic.
 int upload_csr(int32_t n, int64_t arcs, const int64_t *rp, const int32_t *col, const int32_t *w,
-               Csr &c) {
+               int32_t maxw, Csr &c) {
     int rc;
     if ((rc = dalloc(&c.rp, (size_t)n + 1)) || (rc = dalloc(&c.col, (size_t)arcs))) return rc;
     HIP_TRY(hipMemcpy(c.rp, rp, ((size_t)n + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
@@ -346,6 +357,17 @@ int upload_csr(int32_t n, int64_t arcs, const int64_t *rp, const int32_t *col, c
     if (w) {
         if ((rc = dalloc(&c.w, (size_t)arcs))) return rc;
         if (arcs) HIP_TRY(hipMemcpy(c.w, w, (size_t)arcs * sizeof(int32_t), hipMemcpyHostToDevice));
+        const int cb = std::max(1, bits_for((int64_t)n - 1));
+        if (cb + bits_for(maxw) <= 32) {
+            std::vector<uint32_t> pk((size_t)arcs);
+            for (int64_t e = 0; e < arcs; e++)
+                pk[(size_t)e] = (uint32_t)col[e] | ((uint32_t)w[e] << cb);
+            if ((rc = dalloc(&c.pk, (size_t)arcs))) return rc;
+            if (arcs)
+                HIP_TRY(hipMemcpy(c.pk, pk.data(), (size_t)arcs * sizeof(uint32_t),
+                                  hipMemcpyHostToDevice));
+            c.cb = cb;
+        }
     }
     return MFBC_OK;
 }
@@ -363,10 +385,12 @@ void free_graph_memory(mfbc_graph *g) {
     dfree(g->out.rp);
     dfree(g->out.col);
     dfree(g->out.w);
+    dfree(g->out.pk);
     if (!alias) {
         dfree(g->in.rp);
         dfree(g->in.col);
         dfree(g->in.w);
+        dfree(g->in.pk);
     }
     g->in = Csr{};
 }
@@ -429,10 +453,14 @@ int mfbc_load_graph(int32_t n, int64_t n_arcs, const int64_t *h_row_ptr, const i
     g->maxw = maxw;
     g->weighted = h_weight != nullptr;
     g->directed = directed;
-    int rc = upload_csr(n, n_arcs, h_row_ptr, h_col_idx, h_weight, g->out);
+    // packed frontier tuples: weight bits for (n - 1) * max weight (+1 so that
+    // no tuple equals the all-ones "absent" marker), the rest for multiplicities
+    g->mb = 32 - bits_for((int64_t)(n - 1) * maxw + 1);
+    int rc = upload_csr(n, n_arcs, h_row_ptr, h_col_idx, h_weight, maxw, g->out);
     if (!rc) {
         if (directed)
-            rc = upload_csr(n, n_arcs, rpt.data(), colt.data(), h_weight ? wt.data() : nullptr, g->in);
+            rc = upload_csr(n, n_arcs, rpt.data(), colt.data(), h_weight ? wt.data() : nullptr,
+                            maxw, g->in);
         else
             g->in = g->out;
     }

@@ -65,6 +65,8 @@ struct Csr {
     int64_t *rp = nullptr;
     int32_t *col = nullptr;
     int32_t *w = nullptr;    // nullptr: unweighted (all 1)
+    uint32_t *pk = nullptr;  // col | w << cb when both fit 32 bits (weighted only)
+    int cb = 32;             // bits of a column index in pk
 };
 
 struct Workspace {
@@ -74,7 +76,7 @@ struct Workspace {
     int32_t *fdist[2] = {nullptr, nullptr};  // frontier weights (double-buffered)
     double *fsig[2] = {nullptr, nullptr};    // frontier multiplicities
     uint64_t *fbits[2] = {nullptr, nullptr}; // frontier lane masks [cg][n]
-    uint32_t *abits[2] = {nullptr, nullptr}; // any-column activity bitmaps [n/32]
+    uint32_t *abits[2] = {nullptr, nullptr}; // activity bitmaps [cg][n/32] (backward: plane 0)
     int32_t *pd = nullptr;             // partial weights / counters [cg][slots][64]
     double *pm = nullptr;              // partial multiplicities / sums
     unsigned long long *counters = nullptr;  // [ring][4][slots]
@@ -98,6 +100,7 @@ struct mfbc_graph {
     mfbc::Csr out;          // out-arcs (backward products, counting product)
     mfbc::Csr in;           // in-arcs (forward products); aliases `out` if undirected
     mfbc::Plan plan_out, plan_in;
+    int mb = 1;             // inline multiplicity bits of a packed frontier tuple
     mfbc::TaskParams params;
     mfbc::Workspace ws;
     mfbc_stats stats{};
