@@ -12,6 +12,17 @@
 
 namespace mfbc {
 
+TaskParams default_params(int32_t n, int64_t arcs) {
+    // Aim for enough tasks to fill the GPU many times over (256 CUs x 64
+    // waves), shrinking runs on small graphs where a long serial run would
+    // make one product latency-bound.
+    constexpr int64_t kTarget = 16384;
+    TaskParams p;
+    p.run_verts = (int)std::min<int64_t>(64, std::max<int64_t>(1, (n + kTarget - 1) / kTarget));
+    p.run_arcs = (int)std::min<int64_t>(512, std::max<int64_t>(64, (arcs + kTarget - 1) / kTarget));
+    return p;
+}
+
 int build_plan(int32_t n, const int64_t *rp, const TaskParams &p, std::vector<Task> &tasks,
                std::vector<Hub> &hubs, int32_t &nslots) {
     tasks.clear();

@@ -606,32 +606,31 @@ __global__ __launch_bounds__(kBlock) void k_bwd_pull(BwdArgs a) {
                     js[k] = cand ? __ffsll((unsigned long long)cand) - 1 : -1;
                     cand &= cand - 1;
                 }
-                int dy[4], wk[4];
-                double qy[4];
+                // distances first; the frontier value q is loaded only for
+                // lanes whose arc is a shortest-path arc (few per row)
+                int dy[4], wk[4], yk[4];
 #pragma unroll
                 for (int k = 0; k < 4; k++) {
                     dy[k] = kInf;
                     wk[k] = 0;
-                    qy[k] = 0.0;
+                    yk[k] = 0;
                     if (js[k] >= 0) {
                         am &= ~(1ull << js[k]);
-                        const int yj = rdlane(y, js[k]);
+                        yk[k] = rdlane(y, js[k]);
                         wk[k] = W ? rdlane(wt, js[k]) : 1;
                         const uint64_t fbj = rdlane64(fb, js[k]);
-                        if (pend && ((fbj >> lane) & 1ull)) {
-                            const size_t idx = (size_t)yj * kWave + lane;
-                            dy[k] = Td[idx];
-                            qy[k] = Q[idx];
-                        }
+                        if (pend && ((fbj >> lane) & 1ull)) dy[k] = Td[(size_t)yk[k] * kWave + lane];
                     }
                 }
+                double qy[4];
 #pragma unroll
                 for (int k = 0; k < 4; k++) {
-                    if (dy[k] != kInf && dy[k] == dx + wk[k]) {
-                        acc += qy[k];
-                        got++;
-                    }
+                    const bool tight = dy[k] != kInf && dy[k] == dx + wk[k];
+                    qy[k] = tight ? Q[(size_t)yk[k] * kWave + lane] : 0.0;
+                    if (tight) got++;
                 }
+#pragma unroll
+                for (int k = 0; k < 4; k++) acc += qy[k];
             }
         }
         if (hub < 0) {

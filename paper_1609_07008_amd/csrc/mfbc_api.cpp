@@ -464,6 +464,7 @@ int mfbc_load_graph(int32_t n, int64_t n_arcs, const int64_t *h_row_ptr, const i
         else
             g->in = g->out;
     }
+    g->params = default_params(n, n_arcs);
     g->h_rp_out.assign(h_row_ptr, h_row_ptr + (size_t)n + 1);
     g->h_rp_in = directed ? rpt : g->h_rp_out;
     if (!rc) rc = upload_plan(n, g->h_rp_out.data(), g->params, g->plan_out);

@@ -129,6 +129,7 @@ void launch_export_backward(mfbc_graph *g, int ncg, int nb, double *d_delta, int
 void launch_set_sources(mfbc_graph *g, int ncg, int nb, const int32_t *d_sources, hipStream_t s);
 
 // ---- host helpers (graph.cpp) ----
+TaskParams default_params(int32_t n, int64_t arcs);
 int build_plan(int32_t n, const int64_t *rp, const TaskParams &p, std::vector<Task> &tasks,
                std::vector<Hub> &hubs, int32_t &nslots);
 
