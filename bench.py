@@ -39,6 +39,9 @@ WORKLOADS = {
     # Erdos-Renyi n=1024, exact BC over all sources in batches of 64
     "er1024_w100": dict(kind="er", n=1024, k=8, wrange=(1, 100), seed=1,
                         n_sources=None, source_seed=None, batch=64, cpu_sample=None),
+    # batched form: 256 ER / R-MAT graphs, n log-uniform in [200, 20000], average
+    # degree uniform in [4, 64], weights 1..100, exact BC of every graph
+    "batched256": dict(kind="many", count=256, seed0=1000, cpu_sample=48),
 }
 
 
@@ -59,7 +62,7 @@ def make_sources(g, spec):
 
 def kernel_sha():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "mfbc_internal.h"):
+    for f in ("kernels.hip", "products.h", "mfbc_internal.h"):
         with open(os.path.join(ROOT, "paper_1609_07008_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -91,6 +94,74 @@ def cpu_baseline(g, src, sample, m):
                       f"OpenMP over sources), {dt:.2f} s"}
 
 
+def run_many(args, spec):
+    """Batched form: one persistent launch over every graph, against one
+    mfbc_bc launch sequence per graph (batch 64) on the same GPU."""
+    import numpy as np
+    import torch
+    from paper_1609_07008_amd import graphgen as gg
+    from paper_1609_07008_amd import mfbc
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    gs = gg.batched_suite(spec["count"], spec["seed0"])
+    dgs = [mfbc.DeviceGraph(g) for g in gs]
+    srcs = [torch.arange(g.n, dtype=torch.int32, device="cuda") for g in gs]
+    outs = [torch.empty(g.n, dtype=torch.float64, device="cuda") for g in gs]
+    work = sum(g.n * g.m for g in gs)
+    print(f"[bench] batched: {len(gs)} graphs, sum n = {sum(g.n for g in gs)}, "
+          f"sum n*m = {work:.3e}, setup {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    cfg = dict(block_threads=args.block_threads or 512, blocks=args.blocks or 0)
+    for _ in range(args.warmup):
+        mfbc.bc_many(dgs, srcs, outs=outs, **cfg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        mfbc.bc_many(dgs, srcs, outs=outs, **cfg)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.steps
+    st = mfbc.bc_many.last_stats
+    # the plain per-graph method on the same GPU
+    for d, s, o in zip(dgs, srcs, outs):
+        d.bc(s, 64, out=o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for d, s, o in zip(dgs, srcs, outs):
+        d.bc(s, 64, out=o)
+    torch.cuda.synchronize()
+    el_plain = time.perf_counter() - t0
+    line = {
+        "metric": "BC TEPS (sources x edges / s) at 1 GPU", "value": work / el, "unit": "TEPS",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": el * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "batched256", "graphs": len(gs), "sum_n": int(sum(g.n for g in gs)),
+                   "sum_m": int(sum(g.m for g in gs)), "block_threads": cfg["block_threads"],
+                   "fwd_products": st["fwd_products"], "bwd_products": st["bwd_products"]},
+        "per_graph_baseline": {"value": work / el_plain, "unit": "TEPS", "ms": el_plain * 1e3,
+                               "method": "one mfbc_bc launch sequence per graph, batch 64"},
+        "speedup_vs_per_graph": el_plain / el,
+        "roofline": None, "cpu_baseline": None,
+    }
+    if not args.no_cpu:
+        import oracle
+        rng = np.random.default_rng(5)
+        pick = rng.choice(len(gs), size=min(spec["cpu_sample"], len(gs)), replace=False)
+        threads = oracle.brandes_threads()
+        t0 = time.perf_counter()
+        w = 0
+        for i in pick:
+            g = gs[int(i)]
+            oracle.brandes(g, np.arange(g.n, dtype=np.int32), per_source=False, nthreads=threads)
+            w += g.n * g.m
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": w / dt, "unit": "TEPS", "cores": threads, "kind": "oracle",
+                                "sample": f"{len(pick)} of the {len(gs)} graphs, all sources, {dt:.2f} s"}
+    for d in dgs:
+        d.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +174,8 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (calibrates the "
                          "HBM byte counters of rocprofv3) and exit")
+    ap.add_argument("--block-threads", type=int, default=0, help="batched form: threads per workgroup")
+    ap.add_argument("--blocks", type=int, default=0, help="batched form: persistent workgroups")
     args = ap.parse_args()
     if args.copy_probe:
         import torch
@@ -125,6 +198,9 @@ def main():
     from paper_1609_07008_amd import mfbc
 
     spec = WORKLOADS[args.workload]
+    if spec["kind"] == "many":
+        run_many(args, spec)
+        return
     batch = args.batch or spec["batch"]
     torch.cuda.set_device(0)
     t0 = time.perf_counter()

@@ -203,6 +203,37 @@ int mfbc_get_stats(const mfbc_graph *g, mfbc_stats *out);
 int mfbc_graph_info(const mfbc_graph *g, int32_t *n, int64_t *n_arcs,
                     int32_t *max_weight);
 
+/*
+ * mfbc_bc_many -- batched form: MFBC over many independent graphs in one
+ * persistent launch.  Each workgroup takes (graph, 64-source) jobs from a
+ * device queue and runs Algorithms 1-3 for its job with no host round trip
+ * per product; jobs are issued largest first.  Per graph the result equals
+ * mfbc_bc(graphs[i], d_sources[i], h_n_sources[i], 64, d_bc[i]) up to
+ * rounding (the per-job parts are summed in job order, so repeated calls
+ * are bitwise identical).
+ *   graphs[n_graphs]      host array of loaded graphs (same device).
+ *   d_sources[n_graphs]   host array of device pointers to each graph's
+ *                         source list; h_n_sources[n_graphs] their lengths.
+ *   d_bc[n_graphs]        host array of device pointers, each [n_i], out.
+ *   config (nullable)     launch shape: block_threads in {256, 512, 1024}
+ *                         (0 = 1024), blocks = persistent workgroups
+ *                         (0 = two per compute unit); the block count is
+ *                         capped so that the per-workgroup state fits a
+ *                         quarter of the free device memory.
+ *   h_stats (nullable)    out: products over all jobs.
+ * The library keeps a grow-only workspace per device for this call.
+ * Errors: EINVAL, ENOMEM, EOVERFLOW, EDEVICE.
+ */
+typedef struct mfbc_many_config {
+    int32_t block_threads;
+    int32_t blocks;
+} mfbc_many_config;
+
+int mfbc_bc_many(int32_t n_graphs, mfbc_graph *const *graphs,
+                 const int32_t *const *d_sources, const int64_t *h_n_sources,
+                 double *const *d_bc, const mfbc_many_config *config,
+                 mfbc_stats *h_stats, void *hip_stream);
+
 /* Human-readable description of the last failure on this thread. */
 const char *mfbc_last_error(void);
 

@@ -1,0 +1,475 @@
+// Batched form: MFBC over many graphs in one persistent launch.
+//
+// A job is (graph, up to 64 sources); each workgroup takes jobs from a
+// device-side queue (one atomic per job) and runs the whole of Algorithm 3
+// for its job -- forward products until the frontier empties, the counting
+// product, backward products until the backward frontier empties -- with
+// only workgroup barriers between products: no kernel launch and no host
+// round trip per product, which is what dominates the per-graph launch
+// sequence on graphs of a few thousand vertices.  The products are the same
+// task and hub functions as the grid-wide kernels (products.h), scheduled
+// over the workgroup's waves.  Each job's state lives in its workgroup's slot
+// of a scratch area sized for the largest graph; each job's lambda goes to
+// its own slice and the slices of a graph are summed in job order, so the
+// result does not depend on which workgroup ran which job.
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "products.h"
+
+namespace mfbc {
+
+struct GraphDesc {
+    int32_t n, nwords, mb, am;        // am: arc mode of both orientations
+    int32_t ntasks_in, nhubs_in, nslots_in, ntasks_out;
+    int32_t nhubs_out, nslots_out, pad0, pad1;
+    const int64_t *rp_in, *rp_out;
+    ArcSrc arcs_in, arcs_out;
+    const Task *tasks_in, *tasks_out;
+    const Hub *hubs_in, *hubs_out;
+};
+
+struct JobDesc {
+    int32_t g, nsrc;
+    const int32_t *src;        // device pointer to this job's first source
+    int64_t lam_off;           // offset of this job's lambda slice
+};
+
+struct ManyArgs {
+    const GraphDesc *graphs;
+    const JobDesc *jobs;
+    int32_t njobs, n_max, slots_max, pad;
+    unsigned int *queue;
+    char *scratch;
+    size_t slot_stride;
+    double *lam_jobs;
+    int32_t *flags;                  // [0] overflow, [1] no convergence
+    unsigned long long *stats;       // [0] forward products, [1] backward products
+};
+
+namespace {
+
+constexpr int kManyMaxThreads = 512;
+
+__device__ __forceinline__ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Slot {
+    int32_t *tdist;
+    double *tsig;
+    uint32_t *ftup[2];
+    double *fsig[2];
+    uint64_t *fbits[2];
+    uint32_t *abits[2];
+    int32_t *pd;
+    double *pm;
+    int32_t *src;
+};
+
+__device__ __forceinline__ Slot carve(char *base, int n_max, int slots_max) {
+    Slot s;
+    const size_t nw = (size_t)n_max * kWave;
+    const size_t words = ((size_t)n_max + 31) / 32;
+    size_t off = 0;
+    s.tdist = (int32_t *)(base + off); off = align256(off + nw * 4);
+    s.tsig = (double *)(base + off); off = align256(off + nw * 8);
+    for (int b = 0; b < 2; b++) {
+        s.ftup[b] = (uint32_t *)(base + off); off = align256(off + nw * 4);
+        s.fsig[b] = (double *)(base + off); off = align256(off + nw * 8);
+        s.fbits[b] = (uint64_t *)(base + off); off = align256(off + (size_t)n_max * 8);
+        s.abits[b] = (uint32_t *)(base + off); off = align256(off + words * 4);
+    }
+    s.pd = (int32_t *)(base + off); off = align256(off + (size_t)slots_max * kWave * 4);
+    s.pm = (double *)(base + off); off = align256(off + (size_t)slots_max * kWave * 8);
+    s.src = (int32_t *)(base + off);
+    return s;
+}
+
+// AM: arc encoding shared by every graph of the launch (see load_arc).
+template <int AM>
+__global__ __launch_bounds__(kManyMaxThreads) void k_bc_many(ManyArgs m) {
+    __shared__ int s_job;
+    __shared__ unsigned long long s_cnt[3];
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int wave = tid >> 6, nwaves = nthr >> 6;
+    const bool lead = (tid & (kWave - 1)) == 0;
+    const Slot sl = carve(m.scratch + (size_t)blockIdx.x * m.slot_stride, m.n_max, m.slots_max);
+    for (;;) {
+        if (tid == 0) s_job = (int)atomicAdd(m.queue, 1u);
+        if (tid < 3) s_cnt[tid] = 0ull;
+        __syncthreads();
+        const int job = s_job;
+        if (job >= m.njobs) break;
+        const JobDesc jd = m.jobs[job];
+        const GraphDesc gd = m.graphs[jd.g];
+        const int n = gd.n, nw = gd.nwords;
+        double *lam = m.lam_jobs + jd.lam_off;
+        // ---- Algorithm 1 initialisation: T = (INF, 0), first frontier {s}
+        if (tid < kWave) sl.src[tid] = tid < jd.nsrc ? jd.src[tid] : -1;
+        for (int i = tid; i < n * kWave; i += nthr) {
+            sl.tdist[i] = kInf;
+            sl.tsig[i] = 0.0;
+        }
+        for (int i = tid; i < nw; i += nthr) {
+            sl.abits[0][i] = 0u;
+            sl.abits[1][i] = 0u;
+        }
+        for (int i = tid; i < n; i += nthr) lam[i] = 0.0;
+        __syncthreads();
+        if (tid < jd.nsrc) {
+            const int v = sl.src[tid];
+            for (int l = 0; l < kWave; l++) sl.ftup[0][(size_t)v * kWave + l] = kSent;
+        }
+        __syncthreads();
+        if (tid < jd.nsrc) {
+            const int v = sl.src[tid];
+            const size_t idx = (size_t)v * kWave + tid;
+            sl.tdist[idx] = 0;
+            sl.tsig[idx] = 1.0;
+            sl.ftup[0][idx] = 1u;
+            atomicOr(sl.abits[0] + (v >> 5), 1u << (v & 31));
+        }
+        __syncthreads();
+        // ---- Algorithm 1 loop
+        FwdArgs a{};
+        a.tasks = gd.tasks_in;
+        a.hubs = gd.hubs_in;
+        a.ntasks = gd.ntasks_in;
+        a.nhubs = gd.nhubs_in;
+        a.nslots = gd.nslots_in;
+        a.ncg = 1;
+        a.n = n;
+        a.nwords = nw;
+        a.mb = gd.mb;
+        a.rp = gd.rp_in;
+        a.arcs = gd.arcs_in;
+        a.tdist = sl.tdist;
+        a.tsig = sl.tsig;
+        a.pd = sl.pd;
+        a.pm = sl.pm;
+        a.flags = m.flags;
+        int j = 0;
+        for (;;) {
+            ++j;
+            const int b = (j - 1) & 1;
+            a.j = j;
+            a.abits = sl.abits[b];
+            a.ftup = sl.ftup[b];
+            a.fsig = sl.fsig[b];
+            a.abits_n = sl.abits[b ^ 1];
+            a.ftup_n = sl.ftup[b ^ 1];
+            a.fsig_n = sl.fsig[b ^ 1];
+            if (tid == 0) s_cnt[(j + 1) % 3] = 0ull;
+            unsigned long long produced = 0, outs = 0;
+            for (int t = wave; t < a.ntasks; t += nwaves) fwd_task<AM>(a, 0, t, produced, outs);
+            __syncthreads();
+            for (int h = wave; h < a.nhubs; h += nwaves) fwd_hub(a, 0, h, produced, outs);
+            for (int i = tid; i < nw; i += nthr) sl.abits[b][i] = 0u;
+            if (lead && produced) atomicAdd(&s_cnt[j % 3], produced);
+            __syncthreads();
+            if (s_cnt[j % 3] == 0ull) break;
+            if (j > n + 1) {
+                if (tid == 0) m.flags[1] = 1;
+                break;
+            }
+        }
+        __syncthreads();   // every thread has read the last forward count
+        // ---- Algorithm 2: counting product, then backward products
+        BwdArgs c{};
+        c.tasks = gd.tasks_out;
+        c.hubs = gd.hubs_out;
+        c.ntasks = gd.ntasks_out;
+        c.nhubs = gd.nhubs_out;
+        c.nslots = gd.nslots_out;
+        c.ncg = 1;
+        c.n = n;
+        c.nwords = nw;
+        c.rp = gd.rp_out;
+        c.arcs = gd.arcs_out;
+        c.src = sl.src;
+        c.tdist = sl.tdist;
+        c.tsig = sl.tsig;
+        c.cnt = (int32_t *)sl.ftup[0];
+        c.zeta = sl.fsig[0];
+        c.q = sl.fsig[1];
+        c.step = (int32_t *)sl.ftup[1];
+        c.lam = lam;
+        c.pd = sl.pd;
+        c.pm = sl.pm;
+        for (int i = tid; i < nw; i += nthr) {
+            sl.abits[0][i] = 0u;
+            sl.abits[1][i] = 0u;
+        }
+        if (tid == 0) {
+            s_cnt[0] = 0ull;
+            s_cnt[1] = 0ull;
+            s_cnt[2] = 0ull;
+        }
+        __syncthreads();
+        int k = 0;
+        for (;;) {
+            const int bn = k & 1;
+            c.k = k;
+            c.abits = sl.abits[bn ^ 1];
+            c.fbits = sl.fbits[bn ^ 1];
+            c.abits_n = sl.abits[bn];
+            c.fbits_n = sl.fbits[bn];
+            if (tid == 0) s_cnt[(k + 1) % 3] = 0ull;
+            unsigned long long produced = 0, outs = 0;
+            if (k == 0) {
+                for (int t = wave; t < c.ntasks; t += nwaves) count_task<AM>(c, 0, t, produced);
+            } else {
+                for (int t = wave; t < c.ntasks; t += nwaves) bwd_task<AM>(c, 0, t, produced, outs);
+            }
+            __syncthreads();
+            if (k == 0) {
+                for (int h = wave; h < c.nhubs; h += nwaves) count_hub(c, 0, h, produced);
+            } else {
+                for (int h = wave; h < c.nhubs; h += nwaves) bwd_hub(c, 0, h, produced, outs);
+                for (int i = tid; i < nw; i += nthr) sl.abits[bn ^ 1][i] = 0u;
+            }
+            if (lead && produced) atomicAdd(&s_cnt[k % 3], produced);
+            __syncthreads();
+            const bool done = s_cnt[k % 3] == 0ull;
+            ++k;
+            if (done) break;
+            if (k > n + 1) {
+                if (tid == 0) m.flags[1] = 1;
+                break;
+            }
+        }
+        if (tid == 0) {
+            atomicAdd(m.stats + 0, (unsigned long long)j);
+            atomicAdd(m.stats + 1, (unsigned long long)k);
+        }
+        __syncthreads();
+    }
+}
+
+// lambda of graph g: the job slices summed in job order.
+__global__ void k_many_reduce(const double *lam_jobs, const int64_t *job_off, const int32_t *jbeg,
+                              const int32_t *jcnt, const int32_t *order, int n, double *out) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    double t = 0.0;
+    for (int i = 0; i < jcnt[0]; i++) t += lam_jobs[job_off[order[jbeg[0] + i]] + v];
+    out[v] = t;
+}
+
+}  // namespace
+
+// Host side -----------------------------------------------------------------
+
+struct ManyWorkspace {
+    char *scratch = nullptr;
+    size_t scratch_bytes = 0;
+    double *lam_jobs = nullptr;
+    size_t lam_bytes = 0;
+    void *meta = nullptr;
+    size_t meta_bytes = 0;
+};
+
+ManyWorkspace &many_workspace(int device) {
+    static std::mutex mu;
+    static std::vector<ManyWorkspace *> per_device;
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)per_device.size() <= device) per_device.resize((size_t)device + 1, nullptr);
+    if (!per_device[(size_t)device]) per_device[(size_t)device] = new ManyWorkspace();
+    return *per_device[(size_t)device];
+}
+
+static size_t host_align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t many_slot_bytes(int n_max, int slots_max) {
+    const size_t nw = (size_t)n_max * kWave;
+    const size_t words = ((size_t)n_max + 31) / 32;
+    size_t off = 0;
+    off = host_align256(off + nw * 4);
+    off = host_align256(off + nw * 8);
+    for (int b = 0; b < 2; b++) {
+        off = host_align256(off + nw * 4);
+        off = host_align256(off + nw * 8);
+        off = host_align256(off + (size_t)n_max * 8);
+        off = host_align256(off + words * 4);
+    }
+    off = host_align256(off + (size_t)slots_max * kWave * 4);
+    off = host_align256(off + (size_t)slots_max * kWave * 8);
+    off = host_align256(off + kWave * 4);
+    return off;
+}
+
+static ArcSrc host_arc_src(const Csr &c) {
+    ArcSrc r{};
+    r.col = c.col;
+    r.w = c.w;
+    r.pk = c.pk;
+    r.cb = c.cb;
+    r.cmask = c.cb >= 32 ? 0xffffffffu : ((1u << c.cb) - 1u);
+    return r;
+}
+
+static int host_arc_mode(const Csr &c) { return c.w == nullptr ? 0 : (c.pk ? 1 : 2); }
+
+int launch_bc_many(std::vector<mfbc_graph *> &graphs, const std::vector<const int32_t *> &d_src,
+                   const std::vector<int64_t> &n_src, const std::vector<double *> &d_bc,
+                   int block_threads, int blocks, hipStream_t s, ManyWorkspace &ws,
+                   unsigned long long *h_stats, int32_t *h_flags, std::string &err) {
+    const int G = (int)graphs.size();
+    std::vector<GraphDesc> gds((size_t)G);
+    int n_max = 1, slots_max = 1;
+    for (int i = 0; i < G; i++) {
+        mfbc_graph *g = graphs[(size_t)i];
+        GraphDesc &d = gds[(size_t)i];
+        d = GraphDesc{};
+        d.n = g->n;
+        d.nwords = (g->n + 31) / 32;
+        d.mb = g->mb;
+        d.am = host_arc_mode(g->in);
+        if (host_arc_mode(g->out) != d.am || d.am != host_arc_mode(graphs[0]->in)) {
+            err = "graphs of one launch must share one arc encoding";
+            return MFBC_EINVAL;
+        }
+        d.ntasks_in = g->plan_in.ntasks;
+        d.nhubs_in = g->plan_in.nhubs;
+        d.nslots_in = g->plan_in.nslots;
+        d.ntasks_out = g->plan_out.ntasks;
+        d.nhubs_out = g->plan_out.nhubs;
+        d.nslots_out = g->plan_out.nslots;
+        d.rp_in = g->in.rp;
+        d.rp_out = g->out.rp;
+        d.arcs_in = host_arc_src(g->in);
+        d.arcs_out = host_arc_src(g->out);
+        d.tasks_in = g->plan_in.tasks;
+        d.tasks_out = g->plan_out.tasks;
+        d.hubs_in = g->plan_in.hubs;
+        d.hubs_out = g->plan_out.hubs;
+        n_max = std::max(n_max, g->n);
+        slots_max = std::max({slots_max, g->plan_in.nslots, g->plan_out.nslots});
+    }
+    // jobs: 64 sources each; scheduled largest first (longest-processing-time
+    // order) so that small jobs fill in at the end
+    std::vector<JobDesc> jobs;
+    std::vector<double> cost;
+    std::vector<std::vector<int32_t>> per_graph((size_t)G);
+    int64_t lam_total = 0;
+    for (int i = 0; i < G; i++) {
+        const double c = (double)graphs[(size_t)i]->n * (double)(graphs[(size_t)i]->arcs + 1);
+        for (int64_t b0 = 0; b0 < n_src[(size_t)i]; b0 += kWave) {
+            JobDesc jd{};
+            jd.g = i;
+            jd.nsrc = (int32_t)std::min<int64_t>(kWave, n_src[(size_t)i] - b0);
+            jd.src = d_src[(size_t)i] + b0;
+            jd.lam_off = lam_total;
+            lam_total += graphs[(size_t)i]->n;
+            jobs.push_back(jd);
+            cost.push_back(c);
+        }
+    }
+    std::vector<int32_t> order(jobs.size());
+    for (size_t i = 0; i < order.size(); i++) order[i] = (int32_t)i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t x, int32_t y) { return cost[(size_t)x] > cost[(size_t)y]; });
+    std::vector<JobDesc> sorted(jobs.size());
+    for (size_t i = 0; i < order.size(); i++) sorted[i] = jobs[(size_t)order[i]];
+    // reduction order: for each graph, its jobs in source order
+    std::vector<int64_t> job_off(jobs.size());
+    for (size_t i = 0; i < jobs.size(); i++) job_off[i] = jobs[i].lam_off;
+    std::vector<int32_t> jbeg((size_t)G), jcnt((size_t)G), jidx;
+    for (int i = 0; i < G; i++) {
+        jbeg[(size_t)i] = (int32_t)jidx.size();
+        for (size_t q = 0; q < jobs.size(); q++)
+            if (jobs[q].g == i) jidx.push_back((int32_t)q);
+        jcnt[(size_t)i] = (int32_t)jidx.size() - jbeg[(size_t)i];
+    }
+    const int njobs = (int)jobs.size();
+    blocks = std::max(1, std::min(blocks, std::max(njobs, 1)));
+    const size_t slot = many_slot_bytes(n_max, slots_max);
+    const size_t need_scratch = slot * (size_t)blocks;
+    const size_t need_lam = (size_t)std::max<int64_t>(lam_total, 1) * sizeof(double);
+    // metadata block: graphs, jobs, queue, flags, stats, offsets
+    size_t moff = 0;
+    const size_t o_graphs = moff; moff = host_align256(moff + gds.size() * sizeof(GraphDesc));
+    const size_t o_jobs = moff; moff = host_align256(moff + std::max<size_t>(1, sorted.size()) * sizeof(JobDesc));
+    const size_t o_queue = moff; moff = host_align256(moff + 16);
+    const size_t o_flags = moff; moff = host_align256(moff + 16);
+    const size_t o_stats = moff; moff = host_align256(moff + 16);
+    const size_t o_joff = moff; moff = host_align256(moff + std::max<size_t>(1, job_off.size()) * 8);
+    const size_t o_jidx = moff; moff = host_align256(moff + std::max<size_t>(1, jidx.size()) * 4);
+    const size_t o_jbeg = moff; moff = host_align256(moff + (size_t)G * 4);
+    const size_t o_jcnt = moff; moff = host_align256(moff + (size_t)G * 4);
+    auto grow = [&](void **p, size_t &have, size_t need) -> int {
+        if (have >= need) return MFBC_OK;
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+        have = 0;
+        if (hipMalloc(p, need) != hipSuccess) {
+            (void)hipGetLastError();
+            *p = nullptr;
+            err = "device allocation of " + std::to_string(need) + " bytes failed";
+            return MFBC_ENOMEM;
+        }
+        have = need;
+        return MFBC_OK;
+    };
+    int rc;
+    if ((rc = grow((void **)&ws.scratch, ws.scratch_bytes, need_scratch))) return rc;
+    if ((rc = grow((void **)&ws.lam_jobs, ws.lam_bytes, need_lam))) return rc;
+    if ((rc = grow(&ws.meta, ws.meta_bytes, moff))) return rc;
+    char *meta = (char *)ws.meta;
+    std::vector<char> h(moff, 0);
+    memcpy(h.data() + o_graphs, gds.data(), gds.size() * sizeof(GraphDesc));
+    if (!sorted.empty()) memcpy(h.data() + o_jobs, sorted.data(), sorted.size() * sizeof(JobDesc));
+    if (!job_off.empty()) memcpy(h.data() + o_joff, job_off.data(), job_off.size() * 8);
+    if (!jidx.empty()) memcpy(h.data() + o_jidx, jidx.data(), jidx.size() * 4);
+    memcpy(h.data() + o_jbeg, jbeg.data(), (size_t)G * 4);
+    memcpy(h.data() + o_jcnt, jcnt.data(), (size_t)G * 4);
+    if (hipMemcpyAsync(meta, h.data(), moff, hipMemcpyHostToDevice, s) != hipSuccess) {
+        err = "metadata upload failed";
+        return MFBC_EDEVICE;
+    }
+    ManyArgs m{};
+    m.graphs = (const GraphDesc *)(meta + o_graphs);
+    m.jobs = (const JobDesc *)(meta + o_jobs);
+    m.njobs = njobs;
+    m.n_max = n_max;
+    m.slots_max = slots_max;
+    m.queue = (unsigned int *)(meta + o_queue);
+    m.scratch = ws.scratch;
+    m.slot_stride = slot;
+    m.lam_jobs = ws.lam_jobs;
+    m.flags = (int32_t *)(meta + o_flags);
+    m.stats = (unsigned long long *)(meta + o_stats);
+    if (njobs > 0) {
+        switch (gds[0].am) {
+            case 0: hipLaunchKernelGGL(k_bc_many<0>, dim3(blocks), dim3(block_threads), 0, s, m); break;
+            case 1: hipLaunchKernelGGL(k_bc_many<1>, dim3(blocks), dim3(block_threads), 0, s, m); break;
+            default: hipLaunchKernelGGL(k_bc_many<2>, dim3(blocks), dim3(block_threads), 0, s, m); break;
+        }
+    }
+    for (int i = 0; i < G; i++) {
+        const int n = graphs[(size_t)i]->n;
+        hipLaunchKernelGGL(k_many_reduce, dim3((n + 255) / 256), dim3(256), 0, s, ws.lam_jobs,
+                           (const int64_t *)(meta + o_joff), (const int32_t *)(meta + o_jbeg) + i,
+                           (const int32_t *)(meta + o_jcnt) + i, (const int32_t *)(meta + o_jidx),
+                           n, d_bc[(size_t)i]);
+    }
+    if (hipGetLastError() != hipSuccess) {
+        err = "kernel launch failed";
+        return MFBC_EDEVICE;
+    }
+    if (hipMemcpyAsync(h_stats, meta + o_stats, 16, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(h_flags, meta + o_flags, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        err = "batched launch failed";
+        return MFBC_EDEVICE;
+    }
+    return MFBC_OK;
+}
+
+}  // namespace mfbc
+
+namespace mfbc {
+size_t ws_scratch_bytes_impl(const ManyWorkspace &ws) { return ws.scratch_bytes; }
+}  // namespace mfbc

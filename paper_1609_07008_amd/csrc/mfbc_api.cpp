@@ -555,6 +555,89 @@ int mfbc_enable_timing(mfbc_graph *g, int enable) {
     return MFBC_OK;
 }
 
+int mfbc_bc_many(int32_t n_graphs, mfbc_graph *const *graphs, const int32_t *const *d_sources,
+                 const int64_t *h_n_sources, double *const *d_bc, const mfbc_many_config *config,
+                 mfbc_stats *h_stats, void *hip_stream) {
+    if (n_graphs < 0) return fail(MFBC_EINVAL, "n_graphs must be >= 0");
+    if (n_graphs == 0) return MFBC_OK;
+    if (!graphs || !d_sources || !h_n_sources || !d_bc)
+        return fail(MFBC_EINVAL, "array argument is NULL");
+    const int dev = graphs[0] ? graphs[0]->device : 0;
+    std::vector<mfbc_graph *> gs((size_t)n_graphs);
+    std::vector<const int32_t *> src((size_t)n_graphs);
+    std::vector<int64_t> ns((size_t)n_graphs);
+    std::vector<double *> out((size_t)n_graphs);
+    for (int32_t i = 0; i < n_graphs; i++) {
+        if (!graphs[i]) return fail(MFBC_EINVAL, "graph " + std::to_string(i) + " is NULL");
+        if (graphs[i]->device != dev) return fail(MFBC_EINVAL, "graphs live on different devices");
+        if (h_n_sources[i] < 0) return fail(MFBC_EINVAL, "negative source count");
+        if (!d_bc[i]) return fail(MFBC_EINVAL, "output " + std::to_string(i) + " is NULL");
+        gs[(size_t)i] = graphs[i];
+        src[(size_t)i] = d_sources[i];
+        ns[(size_t)i] = h_n_sources[i];
+        out[(size_t)i] = d_bc[i];
+    }
+    int block_threads = config && config->block_threads ? config->block_threads : 1024;
+    if (block_threads != 256 && block_threads != 512 && block_threads != 1024)
+        return fail(MFBC_EINVAL, "block_threads must be 256, 512 or 1024");
+    DeviceGuard dg(dev);
+    hipStream_t s = (hipStream_t)hip_stream;
+    int rc;
+    for (int32_t i = 0; i < n_graphs; i++)
+        if ((rc = check_sources(gs[(size_t)i], src[(size_t)i], ns[(size_t)i], s))) return rc;
+    int blocks = config && config->blocks > 0 ? config->blocks : 0;
+    if (blocks == 0) {
+        hipDeviceProp_t prop;
+        HIP_TRY(hipGetDeviceProperties(&prop, dev));
+        blocks = 2 * prop.multiProcessorCount;
+    }
+    int n_max = 1, slots_max = 1;
+    for (auto *g : gs) {
+        n_max = std::max(n_max, g->n);
+        slots_max = std::max({slots_max, g->plan_in.nslots, g->plan_out.nslots});
+    }
+    size_t free_b = 0, total_b = 0;
+    HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    const size_t slot = many_slot_bytes(n_max, slots_max);
+    ManyWorkspace &ws = many_workspace(dev);
+    const size_t budget = free_b / 4 + ws_scratch_bytes(ws);
+    const int cap = (int)std::max<size_t>(1, budget / std::max<size_t>(slot, 1));
+    blocks = std::min(blocks, cap);
+    // one persistent launch per arc encoding (unweighted, packed, separate)
+    unsigned long long tot[2] = {0, 0};
+    for (int mode = 0; mode < 3; mode++) {
+        std::vector<mfbc_graph *> g2;
+        std::vector<const int32_t *> s2;
+        std::vector<int64_t> n2;
+        std::vector<double *> o2;
+        for (size_t i = 0; i < gs.size(); i++) {
+            const Csr &c = gs[i]->in;
+            const int m = c.w == nullptr ? 0 : (c.pk ? 1 : 2);
+            if (m != mode) continue;
+            g2.push_back(gs[i]);
+            s2.push_back(src[i]);
+            n2.push_back(ns[i]);
+            o2.push_back(out[i]);
+        }
+        if (g2.empty()) continue;
+        unsigned long long st[2] = {0, 0};
+        int32_t flags[2] = {0, 0};
+        std::string err;
+        rc = launch_bc_many(g2, s2, n2, o2, block_threads, blocks, s, ws, st, flags, err);
+        if (rc) return fail(rc, err);
+        if (flags[1]) return fail(MFBC_EDEVICE, "products did not converge");
+        if (flags[0]) return fail(MFBC_EOVERFLOW, "a shortest-path count overflowed binary64");
+        tot[0] += st[0];
+        tot[1] += st[1];
+    }
+    if (h_stats) {
+        *h_stats = mfbc_stats{};
+        h_stats->fwd_products = (int64_t)tot[0];
+        h_stats->bwd_products = (int64_t)tot[1];
+    }
+    return MFBC_OK;
+}
+
 int mfbc_get_stats(const mfbc_graph *g, mfbc_stats *out) {
     if (!g || !out) return fail(MFBC_EINVAL, "NULL argument");
     *out = g->stats;

@@ -128,9 +128,23 @@ void launch_export_backward(mfbc_graph *g, int ncg, int nb, double *d_delta, int
                             hipStream_t s);
 void launch_set_sources(mfbc_graph *g, int ncg, int nb, const int32_t *d_sources, hipStream_t s);
 
+// ---- batched form (batched.hip) ----
+struct ManyWorkspace;
+size_t many_slot_bytes(int n_max, int slots_max);
+int launch_bc_many(std::vector<mfbc_graph *> &graphs, const std::vector<const int32_t *> &d_src,
+                   const std::vector<int64_t> &n_src, const std::vector<double *> &d_bc,
+                   int block_threads, int blocks, hipStream_t s, ManyWorkspace &ws,
+                   unsigned long long *h_stats, int32_t *h_flags, std::string &err);
+ManyWorkspace &many_workspace(int device);
+
 // ---- host helpers (graph.cpp) ----
 TaskParams default_params(int32_t n, int64_t arcs);
 int build_plan(int32_t n, const int64_t *rp, const TaskParams &p, std::vector<Task> &tasks,
                std::vector<Hub> &hubs, int32_t &nslots);
 
 }  // namespace mfbc
+
+namespace mfbc {
+size_t ws_scratch_bytes_impl(const ManyWorkspace &ws);
+}
+inline size_t ws_scratch_bytes(const mfbc::ManyWorkspace &ws) { return mfbc::ws_scratch_bytes_impl(ws); }

@@ -1,0 +1,622 @@
+// Device-side building blocks of the MFBC products, shared by the
+// grid-wide kernels (kernels.hip) and the persistent multi-graph kernel
+// (batched.hip).  Each product is cut into tasks (Task: a run of light rows
+// or a slice of a hub row) processed by one wave for one column group, plus
+// a per-hub merge in fixed slice order; the callers decide how tasks are
+// scheduled (one grid per product, or a workgroup looping over them).
+#pragma once
+
+#include "mfbc_internal.h"
+
+namespace mfbc {
+namespace {
+
+
+__device__ __forceinline__ int rdlane(int x, int j) { return __builtin_amdgcn_readlane(x, j); }
+
+__device__ __forceinline__ uint64_t rdlane64(uint64_t x, int j) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, j);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), j);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+__device__ __forceinline__ int64_t uni64(int64_t x) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// Set the bits of `mask` (bit i = vertex v0 + i) in a vertex bitmap.
+__device__ __forceinline__ void or_run_bits(uint32_t *bm, int v0, uint64_t mask) {
+    const int w0 = v0 >> 5, sh = v0 & 31;
+    const uint64_t lo = mask << sh;
+    const uint32_t hi = sh ? (uint32_t)(mask >> (64 - sh)) : 0u;
+    if ((uint32_t)lo) atomicOr(bm + w0, (uint32_t)lo);
+    if ((uint32_t)(lo >> 32)) atomicOr(bm + w0 + 1, (uint32_t)(lo >> 32));
+    if (hi) atomicOr(bm + w0 + 2, hi);
+}
+
+// Sum of a per-lane double over the wave in a fixed butterfly order.
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, kWave);
+    return x;
+}
+
+// Counters of one product, kCounterSlots-wide arrays (spread to avoid a
+// single hot address): [0] frontier entries produced, [1] output entries
+// that received a candidate, [2] active vertices read, [3] arcs of their rows.
+// c0 and c1 are wave-uniform (every lane holds the wave's count; lane 0's
+// is used), c2 and c3 are per-thread.  Block-level sum, then one atomic per
+// array.
+__device__ __forceinline__ void flush_counts(unsigned long long c0, unsigned long long c1,
+                                             unsigned long long c2, unsigned long long c3,
+                                             unsigned long long *ctr) {
+    __shared__ unsigned long long s_cnt[4][kWavesPerBlock];
+    const bool first = (threadIdx.x & (kWave - 1)) == 0;
+    unsigned long long v[4] = {first ? c0 : 0ull, first ? c1 : 0ull, c2, c3};
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v[k] += __shfl_xor(v[k], off, kWave);
+    }
+    const int lane = threadIdx.x & (kWave - 1);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) s_cnt[k][threadIdx.x >> 6] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        unsigned long long t = 0;
+#pragma unroll
+        for (int i = 0; i < kWavesPerBlock; i++) t += s_cnt[threadIdx.x][i];
+        if (t) atomicAdd(ctr + threadIdx.x * kCounterSlots + (blockIdx.x & (kCounterSlots - 1)), t);
+    }
+}
+
+// Clear `planes` vertex bitmaps of `words` words each while counting the
+// vertices set in any of them and the arcs of their rows.
+__device__ __forceinline__ void clear_and_count(uint32_t *bits, int words, int planes,
+                                                const int64_t *rp, unsigned long long &nv,
+                                                unsigned long long &na) {
+    const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int i = gtid; i < words; i += gridDim.x * blockDim.x) {
+        uint32_t w = 0u;
+        for (int p = 0; p < planes; p++) {
+            const uint32_t x = bits[(size_t)p * words + i];
+            if (x) {
+                w |= x;
+                bits[(size_t)p * words + i] = 0u;
+            }
+        }
+        if (w) {
+            nv += __popc(w);
+            while (w) {
+                const int b = __ffs(w) - 1;
+                w &= w - 1;
+                const int u = i * 32 + b;
+                na += (unsigned long long)(rp[u + 1] - rp[u]);
+            }
+        }
+    }
+}
+
+// Arcs of the current 64-arc chunk that belong to the owner whose row ends
+// at `vend` (chunk starts at arc e).
+__device__ __forceinline__ uint64_t owner_mask(int64_t e, int64_t vend) {
+    const int64_t k = vend - e;
+    return k >= 64 ? ~0ull : ((1ull << k) - 1ull);
+}
+
+// ===================================================================== forward
+//
+// Frontier tuples are packed into 32 bits: (weight << mb) | m, where the
+// multiplicity m is stored inline when 1 <= m < 2^mb and m = 0 means "read
+// the binary64 multiplicity from the escape array".  mb is chosen per graph
+// from the largest possible frontier weight, (n - 1) * max weight (a frontier
+// entry is a least-weight walk no heavier than any shorter one, hence a simple
+// path).  kSent marks a lane that is not in the frontier.  A row of 64 lanes
+// is 256 B; with integer weights drawn from a wide range almost every
+// multiplicity is small, so the 8-byte escape is rarely read.
+constexpr uint32_t kSent = 0xffffffffu;
+
+// Arc access: AM = 0 unweighted (col), 1 packed (col | w << cb), 2 separate arrays.
+struct ArcSrc {
+    const int32_t *col;
+    const int32_t *w;
+    const uint32_t *pk;
+    int cb;
+    uint32_t cmask;
+};
+
+template <int AM>
+__device__ __forceinline__ void load_arc(const ArcSrc &s, int64_t e, int &u, int &wt) {
+    if (AM == 1) {
+        const uint32_t p = s.pk[e];
+        u = (int)(p & s.cmask);
+        wt = (int)(p >> s.cb);
+    } else {
+        u = s.col[e];
+        wt = AM == 2 ? s.w[e] : 1;
+    }
+}
+
+struct FwdArgs {
+    const Task *tasks;
+    const Hub *hubs;
+    int ntasks, nhubs, nslots, ncg, n, j, nwords;
+    int mb;                    // inline multiplicity bits
+    const int64_t *rp;
+    ArcSrc arcs;
+    const uint32_t *abits;     // frontier F_{j-1}: [cg][nwords] activity bitmaps
+    const uint32_t *ftup;      //   packed tuples [cg][n][64]
+    const double *fsig;        //   escaped multiplicities
+    int32_t *tdist;            // T
+    double *tsig;
+    uint32_t *abits_n;         // frontier F_j
+    uint32_t *ftup_n;
+    double *fsig_n;
+    int32_t *pd;               // hub partials
+    double *pm;
+    unsigned long long *ctr;   // counter slots of product j
+    int32_t *flags;
+    uint64_t *fmask;           // trace (nullable)
+    uint32_t *clear_bits;      // merge: bitmaps to clear (F_{j-1}'s), ncg planes
+    unsigned long long *clear_ctr;  // merge: counter slots of product j+1
+};
+
+// T := T (+) G at (v, cg); writes the next frontier row.  Returns the lane
+// mask of the frontier entries produced.
+__device__ __forceinline__ uint64_t fwd_finalize(const FwdArgs &a, size_t cgv, int v, int bd,
+                                                 double bm, int lane, unsigned long long &outs) {
+    const bool has = bd != kInf;
+    uint64_t bits = 0;
+    const uint64_t hm = ballot(has);
+    outs += __popcll(hm);
+    if (hm) {
+        const size_t idx = (cgv + (size_t)v) * kWave + lane;
+        bool keep = false;
+        if (has) {
+            const int td = a.tdist[idx];
+            if (bd < td) {
+                a.tdist[idx] = bd;
+                a.tsig[idx] = bm;
+                keep = true;
+                if (__builtin_isinf(bm)) a.flags[0] = 1;
+            } else if (bd == td) {
+                const double s = a.tsig[idx] + bm;
+                a.tsig[idx] = s;
+                keep = true;
+                if (__builtin_isinf(s)) a.flags[0] = 1;
+            }
+        }
+        bits = ballot(keep);
+        if (bits) {
+            uint32_t t = kSent;
+            if (keep) {
+                const double mmax = (double)((1u << a.mb) - 1u);
+                const uint32_t ms = bm <= mmax ? (uint32_t)bm : 0u;
+                if (ms == 0u) a.fsig_n[idx] = bm;
+                t = ((uint32_t)bd << a.mb) | ms;
+                if (a.fmask && a.j <= 64) a.fmask[idx] |= 1ull << (a.j - 1);
+            }
+            a.ftup_n[idx] = t;
+        }
+    }
+    return bits;
+}
+
+constexpr int kFwdUnroll = 8;
+
+// One pull task of the forward product (see Task) for column group cg.
+template <int AM>
+__device__ __forceinline__ void fwd_task(const FwdArgs &a, int cg, int t, unsigned long long &produced, unsigned long long &outs) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const Task *tp = a.tasks + t;
+    const int v0 = uni(tp->v0), v1 = uni(tp->v1), hub = uni(tp->hub), part = uni(tp->part);
+    const int64_t e0 = uni64(tp->e0), e1 = uni64(tp->e1);
+    const size_t cgv = (size_t)cg * (size_t)a.n;
+    const uint32_t *Ft = a.ftup + cgv * kWave;
+    const double *Fm = a.fsig + cgv * kWave;
+    const uint32_t *Ab = a.abits + (size_t)cg * a.nwords;
+    const uint32_t mmask = (1u << a.mb) - 1u;
+    int v = v0;
+    int64_t vend = hub >= 0 ? e1 : a.rp[v0 + 1];
+    int bd = kInf;
+    double bm = 0.0;
+    uint64_t run_act = 0;
+    for (int64_t e = e0; e < e1; e += kWave) {
+        const int64_t my = e + lane;
+        int u = 0, wt = 1;
+        bool act = false;
+        if (my < e1) {
+            load_arc<AM>(a.arcs, my, u, wt);
+            act = (Ab[u >> 5] >> (u & 31)) & 1u;
+        }
+        uint64_t am = ballot(act);
+        while (am) {
+            const int j0 = __ffsll((unsigned long long)am) - 1;
+            if (hub < 0) {
+                while (e + j0 >= vend) {
+                    const uint64_t b = fwd_finalize(a, cgv, v, bd, bm, lane, outs);
+                    produced += __popcll(b);
+                    if (b) run_act |= 1ull << (v - v0);
+                    ++v;
+                    vend = a.rp[v + 1];
+                    bd = kInf;
+                    bm = 0.0;
+                }
+            }
+            // up to kFwdUnroll active arcs of the same owner, loads issued together
+            uint64_t cand = am & owner_mask(e, vend);
+            int js[kFwdUnroll];
+#pragma unroll
+            for (int k = 0; k < kFwdUnroll; k++) {
+                js[k] = cand ? __ffsll((unsigned long long)cand) - 1 : -1;
+                cand &= cand - 1;
+            }
+            uint32_t tk[kFwdUnroll];
+            int uk[kFwdUnroll], wk[kFwdUnroll];
+#pragma unroll
+            for (int k = 0; k < kFwdUnroll; k++) {
+                tk[k] = kSent;
+                uk[k] = 0;
+                wk[k] = 0;
+                if (js[k] >= 0) {
+                    am &= ~(1ull << js[k]);
+                    uk[k] = rdlane(u, js[k]);
+                    wk[k] = AM ? rdlane(wt, js[k]) : 1;
+                    tk[k] = Ft[(size_t)uk[k] * kWave + lane];
+                }
+            }
+            double mk[kFwdUnroll];
+#pragma unroll
+            for (int k = 0; k < kFwdUnroll; k++) {
+                mk[k] = 0.0;
+                if (tk[k] != kSent) {
+                    const uint32_t ms = tk[k] & mmask;
+                    mk[k] = ms ? (double)ms : Fm[(size_t)uk[k] * kWave + lane];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kFwdUnroll; k++) {
+                if (tk[k] != kSent) {
+                    const int d = (int)(tk[k] >> a.mb) + wk[k];
+                    if (d < bd) {
+                        bd = d;
+                        bm = mk[k];
+                    } else if (d == bd) {
+                        bm += mk[k];
+                    }
+                }
+            }
+        }
+    }
+    if (hub < 0) {
+        while (v < v1) {
+            const uint64_t b = fwd_finalize(a, cgv, v, bd, bm, lane, outs);
+            produced += __popcll(b);
+            if (b) run_act |= 1ull << (v - v0);
+            ++v;
+            bd = kInf;
+            bm = 0.0;
+        }
+        if (lane == 0 && run_act) or_run_bits(a.abits_n + (size_t)cg * a.nwords, v0, run_act);
+    } else {
+        const size_t pidx = ((size_t)cg * a.nslots + part) * kWave + lane;
+        a.pd[pidx] = bd;
+        a.pm[pidx] = bm;
+    }
+}
+
+// Combine the slices of split row h (fixed slice order) and finish it.
+// The merge kernel also clears the previous frontier's bitmaps (counting
+// the vertices active in some column and their arcs) and the next
+// product's counters.
+__device__ __forceinline__ void fwd_hub(const FwdArgs &a, int cg, int h, unsigned long long &produced, unsigned long long &outs) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const Hub *hp = a.hubs + h;
+    const int v = uni(hp->v), first = uni(hp->first), np = uni(hp->nparts);
+    const size_t cgv = (size_t)cg * (size_t)a.n;
+    int bd = kInf;
+    double bm = 0.0;
+    for (int p = first; p < first + np; p++) {
+        const size_t pidx = ((size_t)cg * a.nslots + p) * kWave + lane;
+        const int d = a.pd[pidx];
+        const double m = a.pm[pidx];
+        if (d < bd) {
+            bd = d;
+            bm = m;
+        } else if (d == bd && d != kInf) {
+            bm += m;
+        }
+    }
+    const uint64_t b = fwd_finalize(a, cgv, v, bd, bm, lane, outs);
+    produced += __popcll(b);
+    if (b && lane == 0) atomicOr(a.abits_n + (size_t)cg * a.nwords + (v >> 5), 1u << (v & 31));
+}
+
+// ===================================================================== backward
+struct BwdArgs {
+    const Task *tasks;
+    const Hub *hubs;
+    int ntasks, nhubs, nslots, ncg, n, k, nwords;
+    const int64_t *rp;         // out-arcs
+    ArcSrc arcs;
+    const int32_t *src;        // column -> source vertex (-1 = padding)
+    const int32_t *tdist;      // tau
+    const double *tsig;        // sigma
+    const uint32_t *abits;     // frontier B_{k-1}: [cg][nwords] activity bitmaps
+    const uint64_t *fbits;     //   lane masks [cg][n]
+    uint32_t *abits_n;         // frontier B_k
+    uint64_t *fbits_n;
+    int32_t *cnt;              // counters (> 0 pending, -1 finished or unreachable)
+    double *zeta;              // partial centrality factors
+    double *q;                 // frontier values zeta + 1/sigma
+    int32_t *step;             // index of the backward frontier entered
+    double *lam;               // [cg][n] lambda parts
+    int32_t *pd;
+    double *pm;
+    unsigned long long *ctr;
+    uint32_t *clear_bits;      // ncg planes
+    unsigned long long *clear_ctr;
+};
+
+// Per-vertex finish of the counting product: counters, leaves, zeta = 0.
+__device__ __forceinline__ uint64_t count_finalize(const BwdArgs &a, size_t cgv, int cg, int x,
+                                                   int dx, int c, int lane) {
+    const size_t idx = (cgv + (size_t)x) * kWave + lane;
+    const bool reach = dx != kInf;
+    const bool leaf = reach && c == 0;
+    const bool front = leaf && a.src[cg * kWave + lane] != x;
+    a.cnt[idx] = (reach && c > 0) ? c : -1;
+    a.zeta[idx] = 0.0;
+    a.step[idx] = leaf ? 0 : -1;
+    if (leaf) a.q[idx] = 1.0 / a.tsig[idx];
+    const uint64_t bits = ballot(front);
+    if (lane == 0) a.fbits_n[cgv + (size_t)x] = bits;
+    return bits;
+}
+
+// One task of the counting product: for every arc x -> y the lane test
+// tau(y) == tau(x) + w, eight arcs' loads in flight.
+template <int AM>
+__device__ __forceinline__ void count_task(const BwdArgs &a, int cg, int t, unsigned long long &produced) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const Task *tp = a.tasks + t;
+    const int v0 = uni(tp->v0), v1 = uni(tp->v1), hub = uni(tp->hub), part = uni(tp->part);
+    const int64_t e0 = uni64(tp->e0), e1 = uni64(tp->e1);
+    const size_t cgv = (size_t)cg * (size_t)a.n;
+    const int32_t *Td = a.tdist + cgv * kWave;
+    uint64_t run_act = 0;
+    const int xa = v0, xb = hub >= 0 ? v0 + 1 : v1;
+    for (int x = xa; x < xb; x++) {
+        const int dx = Td[(size_t)x * kWave + lane];
+        const bool reach = dx != kInf;
+        const int64_t ea = hub >= 0 ? e0 : a.rp[x];
+        const int64_t eb = hub >= 0 ? e1 : a.rp[x + 1];
+        int c = 0;
+        if (ballot(reach)) {
+            for (int64_t e = ea; e < eb; e += kWave) {
+                const int64_t my = e + lane;
+                int y = 0, wt = 1;
+                if (my < eb) load_arc<AM>(a.arcs, my, y, wt);
+                const int cnt = (int)((eb - e) < kWave ? (eb - e) : kWave);
+                for (int j = 0; j < cnt; j += 8) {
+                    int dy[8], wj[8];
+#pragma unroll
+                    for (int k = 0; k < 8; k++) {
+                        dy[k] = kInf;
+                        wj[k] = 0;
+                        if (j + k < cnt) {
+                            const int yk = rdlane(y, j + k);
+                            wj[k] = AM ? rdlane(wt, j + k) : 1;
+                            if (reach) dy[k] = Td[(size_t)yk * kWave + lane];
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < 8; k++)
+                        if (reach && dy[k] != kInf && dy[k] == dx + wj[k]) c++;
+                }
+            }
+        }
+        if (hub >= 0) {
+            a.pd[((size_t)cg * a.nslots + part) * kWave + lane] = c;
+        } else {
+            const uint64_t b = count_finalize(a, cgv, cg, x, dx, c, lane);
+            produced += __popcll(b);
+            if (b) run_act |= 1ull << (x - v0);
+        }
+    }
+    if (hub < 0 && lane == 0 && run_act)
+        or_run_bits(a.abits_n + (size_t)cg * a.nwords, v0, run_act);
+}
+
+__device__ __forceinline__ void count_hub(const BwdArgs &a, int cg, int h, unsigned long long &produced) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const Hub *hp = a.hubs + h;
+    const int x = uni(hp->v), first = uni(hp->first), np = uni(hp->nparts);
+    const size_t cgv = (size_t)cg * (size_t)a.n;
+    int c = 0;
+    for (int p = first; p < first + np; p++) c += a.pd[((size_t)cg * a.nslots + p) * kWave + lane];
+    const int dx = a.tdist[(cgv + (size_t)x) * kWave + lane];
+    const uint64_t b = count_finalize(a, cgv, cg, x, dx, c, lane);
+    produced += __popcll(b);
+    if (b && lane == 0) atomicOr(a.abits_n + (size_t)cg * a.nwords + (x >> 5), 1u << (x & 31));
+}
+
+// Finish (s, x) after a backward product contributed `acc` from `got`
+// frontier successors.  Returns the lane mask of new frontier entries.
+__device__ __forceinline__ uint64_t bwd_finalize(const BwdArgs &a, size_t cgv, int cg, int x,
+                                                 int cx, double acc, int got, int lane,
+                                                 unsigned long long &outs) {
+    uint64_t bits = 0;
+    const uint64_t gm = ballot(got > 0);
+    if (lane == 0) outs += __popcll(gm);
+    if (gm) {
+        const size_t idx = (cgv + (size_t)x) * kWave + lane;
+        bool done = false, front = false;
+        double dep = 0.0;
+        if (got > 0) {
+            const int c = cx - got;
+            const double z = a.zeta[idx] + acc;
+            a.zeta[idx] = z;
+            if (c == 0) {
+                const double sg = a.tsig[idx];
+                a.q[idx] = z + 1.0 / sg;
+                a.cnt[idx] = -1;
+                a.step[idx] = a.k;
+                done = true;
+                const bool self = a.src[cg * kWave + lane] == x;
+                front = !self;
+                if (!self) dep = z * sg;
+            } else {
+                a.cnt[idx] = c;
+            }
+        }
+        bits = ballot(front);
+        if (ballot(done)) {
+            const double t = wave_sum(dep);
+            if (lane == 0 && t != 0.0) a.lam[cgv + (size_t)x] += t;
+        }
+    }
+    if (lane == 0) a.fbits_n[cgv + (size_t)x] = bits;
+    return bits;
+}
+
+// One pull task of a backward product for column group cg.
+template <int AM>
+__device__ __forceinline__ void bwd_task(const BwdArgs &a, int cg, int t, unsigned long long &produced, unsigned long long &outs) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const Task *tp = a.tasks + t;
+    const int v0 = uni(tp->v0), v1 = uni(tp->v1), hub = uni(tp->hub), part = uni(tp->part);
+    const int64_t e0 = uni64(tp->e0), e1 = uni64(tp->e1);
+    const size_t cgv = (size_t)cg * (size_t)a.n;
+    const int32_t *Td = a.tdist + cgv * kWave;
+    const double *Q = a.q + cgv * kWave;
+    const uint64_t *Fb = a.fbits + cgv;
+    const uint32_t *Ab = a.abits + (size_t)cg * a.nwords;
+    int x = v0;
+    int64_t vend = hub >= 0 ? e1 : a.rp[v0 + 1];
+    bool loaded = false;
+    int cx = -1, dx = kInf, got = 0;
+    double acc = 0.0;
+    uint64_t run_act = 0;
+    for (int64_t e = e0; e < e1; e += kWave) {
+        const int64_t my = e + lane;
+        int y = 0, wt = 1;
+        uint64_t fb = 0;
+        if (my < e1) {
+            load_arc<AM>(a.arcs, my, y, wt);
+            if ((Ab[y >> 5] >> (y & 31)) & 1u) fb = Fb[y];
+        }
+        uint64_t am = ballot(fb != 0);
+        while (am) {
+            const int j0 = __ffsll((unsigned long long)am) - 1;
+            if (hub < 0) {
+                while (e + j0 >= vend) {
+                    if (loaded) {
+                        const uint64_t b = bwd_finalize(a, cgv, cg, x, cx, acc, got, lane, outs);
+                        produced += __popcll(b);
+                        if (b) run_act |= 1ull << (x - v0);
+                    } else if (lane == 0) {
+                        a.fbits_n[cgv + (size_t)x] = 0ull;
+                    }
+                    ++x;
+                    vend = a.rp[x + 1];
+                    loaded = false;
+                    got = 0;
+                    acc = 0.0;
+                }
+            }
+            if (!loaded) {
+                const size_t idx = (cgv + (size_t)x) * kWave + lane;
+                cx = a.cnt[idx];
+                dx = Td[(size_t)x * kWave + lane];
+                loaded = true;
+            }
+            const bool pend = cx > 0;
+            uint64_t cand = am & owner_mask(e, vend);
+            if (!ballot(pend)) {
+                am &= ~cand;            // nothing of x is pending: skip its arcs here
+                continue;
+            }
+            int js[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                js[k] = cand ? __ffsll((unsigned long long)cand) - 1 : -1;
+                cand &= cand - 1;
+            }
+            // distances first; the frontier value q is loaded only for
+            // lanes whose arc is a shortest-path arc (few per row)
+            int dy[4], wk[4], yk[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                dy[k] = kInf;
+                wk[k] = 0;
+                yk[k] = 0;
+                if (js[k] >= 0) {
+                    am &= ~(1ull << js[k]);
+                    yk[k] = rdlane(y, js[k]);
+                    wk[k] = AM ? rdlane(wt, js[k]) : 1;
+                    const uint64_t fbj = rdlane64(fb, js[k]);
+                    if (pend && ((fbj >> lane) & 1ull)) dy[k] = Td[(size_t)yk[k] * kWave + lane];
+                }
+            }
+            double qy[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const bool tight = dy[k] != kInf && dy[k] == dx + wk[k];
+                qy[k] = tight ? Q[(size_t)yk[k] * kWave + lane] : 0.0;
+                if (tight) got++;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; k++) acc += qy[k];
+        }
+    }
+    if (hub < 0) {
+        while (x < v1) {
+            if (loaded) {
+                const uint64_t b = bwd_finalize(a, cgv, cg, x, cx, acc, got, lane, outs);
+                produced += __popcll(b);
+                if (b) run_act |= 1ull << (x - v0);
+            } else if (lane == 0) {
+                a.fbits_n[cgv + (size_t)x] = 0ull;
+            }
+            ++x;
+            loaded = false;
+            got = 0;
+            acc = 0.0;
+        }
+        if (lane == 0 && run_act) or_run_bits(a.abits_n + (size_t)cg * a.nwords, v0, run_act);
+    } else {
+        const size_t pidx = ((size_t)cg * a.nslots + part) * kWave + lane;
+        a.pd[pidx] = got;
+        a.pm[pidx] = acc;
+    }
+}
+
+__device__ __forceinline__ void bwd_hub(const BwdArgs &a, int cg, int h, unsigned long long &produced, unsigned long long &outs) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const Hub *hp = a.hubs + h;
+    const int x = uni(hp->v), first = uni(hp->first), np = uni(hp->nparts);
+    const size_t cgv = (size_t)cg * (size_t)a.n;
+    int got = 0;
+    double acc = 0.0;
+    for (int p = first; p < first + np; p++) {
+        const size_t pidx = ((size_t)cg * a.nslots + p) * kWave + lane;
+        got += a.pd[pidx];
+        acc += a.pm[pidx];
+    }
+    const int cx = a.cnt[(cgv + (size_t)x) * kWave + lane];
+    const uint64_t b = bwd_finalize(a, cgv, cg, x, cx, acc, got, lane, outs);
+    produced += __popcll(b);
+    if (b && lane == 0) atomicOr(a.abits_n + (size_t)cg * a.nwords + (x >> 5), 1u << (x & 31));
+}
+
+}  // namespace
+}  // namespace mfbc

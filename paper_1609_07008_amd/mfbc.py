@@ -33,6 +33,7 @@ SIGNATURES = {
     "mfbc_get_stats": ([_P, _P], ctypes.c_int),
     "mfbc_enable_timing": ([_P, ctypes.c_int], ctypes.c_int),
     "mfbc_graph_info": ([_P, _P, _P, _P], ctypes.c_int),
+    "mfbc_bc_many": ([_I32, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
     "mfbc_last_error": ([], ctypes.c_char_p),
 }
 
@@ -45,6 +46,10 @@ class MfbcStats(ctypes.Structure):
         "count_launches")] + [(k, ctypes.c_double) for k in (
         "fwd_pull_ms", "fwd_merge_ms", "count_ms", "bwd_pull_ms", "bwd_merge_ms", "other_ms",
         "fwd_alg_bytes", "bwd_alg_bytes", "count_alg_bytes")]
+
+
+class MfbcManyConfig(ctypes.Structure):
+    _fields_ = [("block_threads", _I32), ("blocks", _I32)]
 
 
 class MfbcError(RuntimeError):
@@ -196,3 +201,29 @@ class DeviceGraph:
         s = MfbcStats()
         _check(load_library().mfbc_get_stats(self.handle, ctypes.byref(s)))
         return {k: getattr(s, k) for k, _ in MfbcStats._fields_}
+
+
+def bc_many(graphs, sources, block_threads: int = 0, blocks: int = 0, outs=None, stream=None):
+    """Batched form: lambda of every graph over its source list, one persistent launch.
+
+    ``graphs``: DeviceGraph list; ``sources``: one int32 source list (numpy
+    or CUDA tensor) per graph.  Returns a list of float64[n_i] tensors.
+    """
+    import torch
+    lib = load_library()
+    G = len(graphs)
+    srcs = [g._src(s) for g, s in zip(graphs, sources)]
+    if outs is None:
+        outs = [torch.empty(g.n, dtype=torch.float64, device="cuda") for g in graphs]
+    handles = (ctypes.c_void_p * G)(*[g.handle.value for g in graphs])
+    sp = (ctypes.c_void_p * G)(*[t.data_ptr() for t in srcs])
+    ns = (ctypes.c_int64 * G)(*[t.numel() for t in srcs])
+    op = (ctypes.c_void_p * G)(*[t.data_ptr() for t in outs])
+    cfg = MfbcManyConfig(block_threads, blocks)
+    st = MfbcStats()
+    rc = lib.mfbc_bc_many(G, ctypes.cast(handles, _P), ctypes.cast(sp, _P), ctypes.cast(ns, _P),
+                          ctypes.cast(op, _P), ctypes.byref(cfg), ctypes.byref(st),
+                          _stream(torch, stream))
+    _check(rc)
+    bc_many.last_stats = {"fwd_products": st.fwd_products, "bwd_products": st.bwd_products}
+    return outs
