@@ -215,8 +215,8 @@ int mfbc_graph_info(const mfbc_graph *g, int32_t *n, int64_t *n_arcs,
  *   d_sources[n_graphs]   host array of device pointers to each graph's
  *                         source list; h_n_sources[n_graphs] their lengths.
  *   d_bc[n_graphs]        host array of device pointers, each [n_i], out.
- *   config (nullable)     launch shape: block_threads in {256, 512, 1024}
- *                         (0 = 1024), blocks = persistent workgroups
+ *   config (nullable)     launch shape: block_threads in {256, 512}
+ *                         (0 = 512), blocks = persistent workgroups
  *                         (0 = two per compute unit); the block count is
  *                         capped so that the per-workgroup state fits a
  *                         quarter of the free device memory.

@@ -577,9 +577,9 @@ int mfbc_bc_many(int32_t n_graphs, mfbc_graph *const *graphs, const int32_t *con
         ns[(size_t)i] = h_n_sources[i];
         out[(size_t)i] = d_bc[i];
     }
-    int block_threads = config && config->block_threads ? config->block_threads : 1024;
-    if (block_threads != 256 && block_threads != 512 && block_threads != 1024)
-        return fail(MFBC_EINVAL, "block_threads must be 256, 512 or 1024");
+    int block_threads = config && config->block_threads ? config->block_threads : 512;
+    if (block_threads != 256 && block_threads != 512)
+        return fail(MFBC_EINVAL, "block_threads must be 256 or 512");
     DeviceGuard dg(dev);
     hipStream_t s = (hipStream_t)hip_stream;
     int rc;

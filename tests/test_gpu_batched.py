@@ -77,4 +77,7 @@ def test_bc_many_rejects_bad_sources(mfbc):
     with pytest.raises(mfbc.MfbcError) as e:
         mfbc.bc_many([dg], [np.array([0, 50], dtype=np.int32)])
     assert e.value.code == mfbc.MFBC_EINVAL
+    with pytest.raises(mfbc.MfbcError) as e:
+        mfbc.bc_many([dg], [np.array([0, 1], dtype=np.int32)], block_threads=1024)
+    assert e.value.code == mfbc.MFBC_EINVAL
     dg.close()
