@@ -111,7 +111,18 @@ def run_many(args, spec):
     work = sum(g.n * g.m for g in gs)
     print(f"[bench] batched: {len(gs)} graphs, sum n = {sum(g.n for g in gs)}, "
           f"sum n*m = {work:.3e}, setup {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
-    cfg = dict(block_threads=args.block_threads or 512, blocks=args.blocks or 0)
+    from paper_1609_07008_amd import autotune
+    cache = autotune.load_cache()
+    if args.tune or "many" not in cache:
+        pick = list(range(0, len(gs), 4))           # every fourth graph
+        autotune.tune_many([dgs[i] for i in pick], [srcs[i] for i in pick], cache=cache,
+                           verbose=True)
+        autotune.save_cache(cache)
+    cfg = autotune.many_config(cache)
+    if args.block_threads:
+        cfg["block_threads"] = args.block_threads
+    if args.blocks:
+        cfg["blocks"] = args.blocks
     for _ in range(args.warmup):
         mfbc.bc_many(dgs, srcs, outs=outs, **cfg)
     torch.cuda.synchronize()
@@ -136,7 +147,7 @@ def run_many(args, spec):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "batched256", "graphs": len(gs), "sum_n": int(sum(g.n for g in gs)),
-                   "sum_m": int(sum(g.m for g in gs)), "block_threads": cfg["block_threads"],
+                   "sum_m": int(sum(g.m for g in gs)), "launch": cfg,
                    "fwd_products": st["fwd_products"], "bwd_products": st["bwd_products"]},
         "per_graph_baseline": {"value": work / el_plain, "unit": "TEPS", "ms": el_plain * 1e3,
                                "method": "one mfbc_bc launch sequence per graph, batch 64"},
@@ -174,6 +185,7 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (calibrates the "
                          "HBM byte counters of rocprofv3) and exit")
+    ap.add_argument("--tune", action="store_true", help="re-run the autotuner before timing")
     ap.add_argument("--block-threads", type=int, default=0, help="batched form: threads per workgroup")
     ap.add_argument("--blocks", type=int, default=0, help="batched form: persistent workgroups")
     args = ap.parse_args()
@@ -209,6 +221,11 @@ def main():
     t_gen = time.perf_counter() - t0
     t0 = time.perf_counter()
     dg = mfbc.DeviceGraph(g)
+    from paper_1609_07008_amd import autotune
+    cache = autotune.load_cache()
+    if args.tune or not autotune.apply_plan(dg, g, cache):
+        best, _ = autotune.tune_plan(dg, g, src, batch, cache=cache, verbose=True)
+        autotune.save_cache(cache)
     d_src = torch.as_tensor(src, device="cuda")
     out = torch.empty(g.n, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()

@@ -194,6 +194,16 @@ typedef struct mfbc_stats {
     double count_alg_bytes;
 } mfbc_stats;
 
+/*
+ * mfbc_set_plan -- choose the work decomposition of a graph's products (a
+ * tuning knob; results do not depend on it).  Light rows are grouped into
+ * runs of at most run_verts (1..64) rows and about run_arcs arcs; rows with
+ * more than `heavy` arcs are cut into slices of `slice` arcs, merged in slice
+ * order.  Any argument <= 0 restores the size-based default for that knob.
+ */
+int mfbc_set_plan(mfbc_graph *g, int32_t run_arcs, int32_t run_verts, int32_t heavy,
+                  int32_t slice);
+
 /* Enable (1) or disable (0) the per-launch kernel timing of a graph. */
 int mfbc_enable_timing(mfbc_graph *g, int enable);
 
@@ -233,6 +243,62 @@ int mfbc_bc_many(int32_t n_graphs, mfbc_graph *const *graphs,
                  const int32_t *const *d_sources, const int64_t *h_n_sources,
                  double *const *d_bc, const mfbc_many_config *config,
                  mfbc_stats *h_stats, void *hip_stream);
+
+/*
+ * Served form: continuous batching of source columns over a resident graph.
+ *
+ * A server owns `width` source columns (a positive multiple of 64) of one
+ * graph; each column holds one source and moves through its own phase
+ * (forward loop, counting product, backward loop, done).  A step advances
+ * every active column by one product of its phase; a column depends only on
+ * its own column of the frontier (the products act column by column,
+ * Section 3), so new sources join free columns between steps while other
+ * columns are mid-loop.  Finished columns are harvested into the caller's
+ * buffers and become free.  All calls on one server must come from one
+ * thread, in the order admit / step_launch / step_finish / harvest; the
+ * stream argument must be the same for a step's launch and finish.
+ */
+typedef struct mfbc_server mfbc_server;
+
+/* HBM bytes a server of `width` columns on graph g allocates. */
+int mfbc_server_footprint(const mfbc_graph *g, int32_t width, int64_t *bytes);
+
+/* Create a server (allocates its state; the graph must outlive it). */
+int mfbc_server_create(mfbc_graph *g, int32_t width, mfbc_server **out);
+int mfbc_server_free(mfbc_server *s);
+
+/* Number of free columns / columns in a forward, counting or backward phase
+ * (>= 0), or a negative status. */
+int mfbc_server_free_columns(const mfbc_server *s);
+int mfbc_server_active_columns(const mfbc_server *s);
+
+/* Place `count` sources (host, in [0,n)) into free columns; h_columns[i]
+ * receives the column of source i.  EINVAL if fewer columns are free. */
+int mfbc_server_admit(mfbc_server *s, const int32_t *h_sources, int32_t count,
+                      int32_t *h_columns, void *hip_stream);
+
+/* Enqueue one step on the stream (does not wait). */
+int mfbc_server_step_launch(mfbc_server *s, void *hip_stream);
+
+/* Wait for the step and update the column phases; h_done[width] receives
+ * the columns that finished in this step, *h_ndone their number. */
+int mfbc_server_step_finish(mfbc_server *s, int32_t *h_done, int32_t *h_ndone,
+                            void *hip_stream);
+
+/* Harvest finished columns into lambda-style sums:
+ * d_dest[i][v] += delta(source of h_columns[i], v) for every v (device
+ * buffers of n doubles; several columns may share one destination, which is
+ * then updated in list order).  The columns become free. */
+int mfbc_server_harvest_bc(mfbc_server *s, const int32_t *h_columns, int32_t count,
+                           double *const *d_dest, void *hip_stream);
+
+/* Harvest finished columns as dependencies at target vertices:
+ * d_out[i][t] = delta(source of h_columns[i], d_targets[t]) (d_targets:
+ * device int32[ntargets]; d_out[i]: device double[ntargets]).  The columns
+ * become free. */
+int mfbc_server_harvest_dep(mfbc_server *s, const int32_t *h_columns, int32_t count,
+                            const int32_t *d_targets, int32_t ntargets,
+                            double *const *d_out, void *hip_stream);
 
 /* Human-readable description of the last failure on this thread. */
 const char *mfbc_last_error(void);

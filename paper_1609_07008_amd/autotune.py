@@ -1,0 +1,127 @@
+"""Autotuner for the work decomposition and launch shapes, measured on the device.
+
+Knobs (none changes results, only speed):
+  * per graph: the pull-task decomposition of ``mfbc_set_plan`` -- light rows
+    grouped into runs of at most ``run_verts`` rows and about ``run_arcs``
+    arcs (hub rows are always cut into slices);
+  * batched form: threads per workgroup and persistent workgroups of
+    ``mfbc_bc_many``.
+
+Choices are cached per device architecture and graph-size bucket (vertex
+count, average degree, weighted or not) in ``tuned_<arch>.json`` next to
+this module, so a later run applies them without measuring again.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+PLAN_CANDIDATES = [(64, 1), (128, 4), (256, 16), (512, 64), (256, 64), (512, 16)]
+MANY_CANDIDATES = [(256, 4), (256, 2), (512, 2), (512, 1)]      # (threads, workgroups per CU)
+
+
+def _arch() -> str:
+    import torch
+    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+
+def cache_path(arch: str = None) -> str:
+    return os.path.join(_HERE, f"tuned_{arch or _arch()}.json")
+
+
+def load_cache(arch: str = None) -> dict:
+    p = cache_path(arch)
+    if not os.path.exists(p):
+        return {}
+    with open(p) as fh:
+        return json.load(fh)
+
+
+def save_cache(cache: dict, arch: str = None):
+    p = cache_path(arch)
+    tmp = p + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(cache, fh, indent=1, sort_keys=True)
+    os.replace(tmp, p)
+
+
+def bucket(n: int, arcs: int, weighted: bool) -> str:
+    k = max(arcs / max(n, 1), 1.0)
+    return f"n2^{int(math.ceil(math.log2(max(n, 2))))}_k2^{int(round(math.log2(k)))}_{'w' if weighted else 'u'}"
+
+
+def graph_bucket(g) -> str:
+    return bucket(g.n, g.arcs, g.w is not None)
+
+
+def _time(fn, reps: int) -> float:
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t0)
+    return best
+
+
+def tune_plan(dg, g, sources, batch: int, reps: int = 2, cache: dict = None, verbose=False):
+    """Pick the run sizes of one graph by timing mfbc_bc on one batch of sources."""
+    import torch
+    src = torch.as_tensor(np.ascontiguousarray(sources[:batch], dtype=np.int32), device="cuda")
+    res = {}
+    for ra, rv in PLAN_CANDIDATES:
+        dg.set_plan(run_arcs=ra, run_verts=rv)
+        res[(ra, rv)] = _time(lambda: dg.bc(src, batch), reps)
+        if verbose:
+            print(f"[tune] {g.name} run_arcs={ra} run_verts={rv}: {res[(ra, rv)] * 1e3:.2f} ms")
+    best = min(res, key=res.get)
+    dg.set_plan(run_arcs=best[0], run_verts=best[1])
+    if cache is not None:
+        cache.setdefault("plan", {})[graph_bucket(g)] = {"run_arcs": best[0], "run_verts": best[1],
+                                                         "ms": res[best] * 1e3}
+    return best, res
+
+
+def apply_plan(dg, g, cache: dict) -> bool:
+    """Set a graph's plan from the cache (returns False if its bucket is unknown)."""
+    e = cache.get("plan", {}).get(graph_bucket(g))
+    if not e:
+        return False
+    dg.set_plan(run_arcs=e["run_arcs"], run_verts=e["run_verts"])
+    return True
+
+
+def tune_many(dgs, srcs, reps: int = 1, cache: dict = None, verbose=False):
+    """Pick the launch shape of the batched form on (a sample of) its graphs."""
+    import torch
+    from . import mfbc
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    outs = [torch.empty(d.n, dtype=torch.float64, device="cuda") for d in dgs]
+    res = {}
+    for threads, per_cu in MANY_CANDIDATES:
+        cfg = dict(block_threads=threads, blocks=per_cu * cus)
+        res[(threads, per_cu)] = _time(lambda: mfbc.bc_many(dgs, srcs, outs=outs, **cfg), reps)
+        if verbose:
+            print(f"[tune] many threads={threads} per_cu={per_cu}: {res[(threads, per_cu)]:.3f} s")
+    best = min(res, key=res.get)
+    if cache is not None:
+        cache["many"] = {"block_threads": best[0], "per_cu": best[1], "s": res[best]}
+    return best, res
+
+
+def many_config(cache: dict) -> dict:
+    import torch
+    e = cache.get("many")
+    if not e:
+        return {}
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    return {"block_threads": e["block_threads"], "blocks": e["per_cu"] * cus}

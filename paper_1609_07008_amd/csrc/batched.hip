@@ -93,7 +93,8 @@ __global__ __launch_bounds__(kManyMaxThreads) void k_bc_many(ManyArgs m) {
     __shared__ int s_job;
     __shared__ unsigned long long s_cnt[3];
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const int wave = tid >> 6, nwaves = nthr >> 6;
+    // wave index as a uniform (scalar) value, so the task loops stay uniform
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), nwaves = nthr >> 6;
     const bool lead = (tid & (kWave - 1)) == 0;
     const Slot sl = carve(m.scratch + (size_t)blockIdx.x * m.slot_stride, m.n_max, m.slots_max);
     for (;;) {
@@ -163,7 +164,7 @@ __global__ __launch_bounds__(kManyMaxThreads) void k_bc_many(ManyArgs m) {
             a.fsig_n = sl.fsig[b ^ 1];
             if (tid == 0) s_cnt[(j + 1) % 3] = 0ull;
             unsigned long long produced = 0, outs = 0;
-            for (int t = wave; t < a.ntasks; t += nwaves) fwd_task<AM>(a, 0, t, produced, outs);
+            for (int t = wave; t < a.ntasks; t += nwaves) fwd_task<AM, 4>(a, 0, t, produced, outs);
             __syncthreads();
             for (int h = wave; h < a.nhubs; h += nwaves) fwd_hub(a, 0, h, produced, outs);
             for (int i = tid; i < nw; i += nthr) sl.abits[b][i] = 0u;

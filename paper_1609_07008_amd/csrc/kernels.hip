@@ -31,68 +31,6 @@
 
 namespace mfbc {
 namespace {
-// ===================================================================== grid kernels
-template <int AM>
-__global__ __launch_bounds__(kBlock) void k_fwd_pull(FwdArgs a) {
-    const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    const int cg = wid / a.ntasks;                       // column-group major
-    unsigned long long produced = 0, outs = 0;
-    if (cg < a.ncg) fwd_task<AM>(a, cg, wid - cg * a.ntasks, produced, outs);
-    flush_counts(produced, outs, 0, 0, a.ctr);
-}
-
-__global__ __launch_bounds__(kBlock) void k_fwd_merge(FwdArgs a) {
-    const int gtid = blockIdx.x * kBlock + threadIdx.x;
-    unsigned long long nv = 0, na = 0;
-    clear_and_count(a.clear_bits, a.nwords, a.ncg, a.rp, nv, na);
-    if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
-    const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    unsigned long long produced = 0, outs = 0;
-    const int cg = a.nhubs ? wid / a.nhubs : a.ncg;
-    if (cg < a.ncg) fwd_hub(a, cg, wid - cg * a.nhubs, produced, outs);
-    flush_counts(produced, outs, nv, na, a.ctr);
-}
-
-template <int AM>
-__global__ __launch_bounds__(kBlock) void k_bwd_count(BwdArgs a) {
-    const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    const int cg = wid / a.ntasks;                       // column-group major
-    unsigned long long produced = 0;
-    if (cg < a.ncg) count_task<AM>(a, cg, wid - cg * a.ntasks, produced);
-    flush_counts(produced, 0, 0, 0, a.ctr);
-}
-
-__global__ __launch_bounds__(kBlock) void k_bwd_count_merge(BwdArgs a) {
-    const int gtid = blockIdx.x * kBlock + threadIdx.x;
-    if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
-    const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    unsigned long long produced = 0;
-    const int cg = a.nhubs ? wid / a.nhubs : a.ncg;
-    if (cg < a.ncg) count_hub(a, cg, wid - cg * a.nhubs, produced);
-    flush_counts(produced, 0, 0, 0, a.ctr);
-}
-
-template <int AM>
-__global__ __launch_bounds__(kBlock) void k_bwd_pull(BwdArgs a) {
-    const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    const int cg = wid / a.ntasks;                       // column-group major
-    unsigned long long produced = 0, outs = 0;
-    if (cg < a.ncg) bwd_task<AM>(a, cg, wid - cg * a.ntasks, produced, outs);
-    flush_counts(produced, outs, 0, 0, a.ctr);
-}
-
-__global__ __launch_bounds__(kBlock) void k_bwd_merge(BwdArgs a) {
-    const int gtid = blockIdx.x * kBlock + threadIdx.x;
-    unsigned long long nv = 0, na = 0;
-    clear_and_count(a.clear_bits, a.nwords, a.ncg, a.rp, nv, na);
-    if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
-    const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    unsigned long long produced = 0, outs = 0;
-    const int cg = a.nhubs ? wid / a.nhubs : a.ncg;
-    if (cg < a.ncg) bwd_hub(a, cg, wid - cg * a.nhubs, produced, outs);
-    flush_counts(produced, outs, nv, na, a.ctr);
-}
-
 // ===================================================================== setup / io
 __global__ void k_set_sources(int32_t *src, int total, int nb, const int32_t *in) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;

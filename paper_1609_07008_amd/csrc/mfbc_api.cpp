@@ -28,6 +28,12 @@ int fail(int code, const std::string &msg) {
     return code;
 }
 
+}  // namespace
+
+int mfbc::set_error(int code, const std::string &msg) { return fail(code, msg); }
+
+namespace {
+
 #define HIP_TRY(expr)                                                                        \
     do {                                                                                     \
         hipError_t e_ = (expr);                                                              \
@@ -542,6 +548,27 @@ int mfbc_bc(mfbc_graph *g, const int32_t *d_sources, int64_t n_sources, int32_t 
     launch_lambda_reduce(g, ncg, d_bc, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
+    return MFBC_OK;
+}
+
+int mfbc_set_plan(mfbc_graph *g, int32_t run_arcs, int32_t run_verts, int32_t heavy,
+                  int32_t slice) {
+    if (!g) return fail(MFBC_EINVAL, "graph handle is NULL");
+    if (run_verts > 64) return fail(MFBC_EINVAL, "run_verts must be <= 64");
+    DeviceGuard dg(g->device);
+    TaskParams p = default_params(g->n, g->arcs);
+    if (run_arcs > 0) p.run_arcs = run_arcs;
+    if (run_verts > 0) p.run_verts = run_verts;
+    if (heavy > 0) p.heavy = heavy;
+    if (slice > 0) p.slice = slice;
+    HIP_TRY(hipDeviceSynchronize());
+    const int32_t old_slots = std::max(g->plan_in.nslots, g->plan_out.nslots);
+    g->params = p;
+    int rc = upload_plan(g->n, g->h_rp_out.data(), p, g->plan_out);
+    if (!rc) rc = upload_plan(g->n, g->h_rp_in.data(), p, g->plan_in);
+    if (rc) return rc;
+    // the partial buffers are sized by the slot count: regrow on next use
+    if (std::max(g->plan_in.nslots, g->plan_out.nslots) > old_slots) free_workspace(g->ws);
     return MFBC_OK;
 }
 

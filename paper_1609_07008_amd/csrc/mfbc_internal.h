@@ -137,6 +137,9 @@ int launch_bc_many(std::vector<mfbc_graph *> &graphs, const std::vector<const in
                    unsigned long long *h_stats, int32_t *h_flags, std::string &err);
 ManyWorkspace &many_workspace(int device);
 
+// Record the message of a failure for mfbc_last_error(); returns `code`.
+int set_error(int code, const std::string &msg);
+
 // ---- host helpers (graph.cpp) ----
 TaskParams default_params(int32_t n, int64_t arcs);
 int build_plan(int32_t n, const int64_t *rp, const TaskParams &p, std::vector<Task> &tasks,

@@ -112,6 +112,14 @@ __device__ __forceinline__ uint64_t owner_mask(int64_t e, int64_t vend) {
     return k >= 64 ? ~0ull : ((1ull << k) - 1ull);
 }
 
+// Record the columns of group cg that produced frontier entries (one atomic
+// per wave, spread over 32 copies that the host ORs together).
+__device__ __forceinline__ void flush_colmask(unsigned long long *colmask, int ncg, int cg,
+                                              uint64_t any) {
+    if (colmask && any && (threadIdx.x & (kWave - 1)) == 0)
+        atomicOr(colmask + (size_t)(blockIdx.x & 31) * ncg + cg, (unsigned long long)any);
+}
+
 // ===================================================================== forward
 //
 // Frontier tuples are packed into 32 bits: (weight << mb) | m, where the
@@ -167,6 +175,7 @@ struct FwdArgs {
     uint64_t *fmask;           // trace (nullable)
     uint32_t *clear_bits;      // merge: bitmaps to clear (F_{j-1}'s), ncg planes
     unsigned long long *clear_ctr;  // merge: counter slots of product j+1
+    unsigned long long *colmask;    // nullable: [32][ncg] columns that produced entries
 };
 
 // T := T (+) G at (v, cg); writes the next frontier row.  Returns the lane
@@ -213,9 +222,11 @@ __device__ __forceinline__ uint64_t fwd_finalize(const FwdArgs &a, size_t cgv, i
 constexpr int kFwdUnroll = 8;
 
 // One pull task of the forward product (see Task) for column group cg.
-template <int AM>
+// U: active arcs whose tuple loads are issued together.
+template <int AM, int U = kFwdUnroll>
 __device__ __forceinline__ void fwd_task(const FwdArgs &a, int cg, int t, unsigned long long &produced, unsigned long long &outs) {
     const int lane = threadIdx.x & (kWave - 1);
+    uint64_t colany = 0;
     const Task *tp = a.tasks + t;
     const int v0 = uni(tp->v0), v1 = uni(tp->v1), hub = uni(tp->hub), part = uni(tp->part);
     const int64_t e0 = uni64(tp->e0), e1 = uni64(tp->e1);
@@ -244,6 +255,7 @@ __device__ __forceinline__ void fwd_task(const FwdArgs &a, int cg, int t, unsign
                 while (e + j0 >= vend) {
                     const uint64_t b = fwd_finalize(a, cgv, v, bd, bm, lane, outs);
                     produced += __popcll(b);
+                    colany |= b;
                     if (b) run_act |= 1ull << (v - v0);
                     ++v;
                     vend = a.rp[v + 1];
@@ -251,18 +263,18 @@ __device__ __forceinline__ void fwd_task(const FwdArgs &a, int cg, int t, unsign
                     bm = 0.0;
                 }
             }
-            // up to kFwdUnroll active arcs of the same owner, loads issued together
+            // up to U active arcs of the same owner, loads issued together
             uint64_t cand = am & owner_mask(e, vend);
-            int js[kFwdUnroll];
+            int js[U];
 #pragma unroll
-            for (int k = 0; k < kFwdUnroll; k++) {
+            for (int k = 0; k < U; k++) {
                 js[k] = cand ? __ffsll((unsigned long long)cand) - 1 : -1;
                 cand &= cand - 1;
             }
-            uint32_t tk[kFwdUnroll];
-            int uk[kFwdUnroll], wk[kFwdUnroll];
+            uint32_t tk[U];
+            int uk[U], wk[U];
 #pragma unroll
-            for (int k = 0; k < kFwdUnroll; k++) {
+            for (int k = 0; k < U; k++) {
                 tk[k] = kSent;
                 uk[k] = 0;
                 wk[k] = 0;
@@ -273,9 +285,9 @@ __device__ __forceinline__ void fwd_task(const FwdArgs &a, int cg, int t, unsign
                     tk[k] = Ft[(size_t)uk[k] * kWave + lane];
                 }
             }
-            double mk[kFwdUnroll];
+            double mk[U];
 #pragma unroll
-            for (int k = 0; k < kFwdUnroll; k++) {
+            for (int k = 0; k < U; k++) {
                 mk[k] = 0.0;
                 if (tk[k] != kSent) {
                     const uint32_t ms = tk[k] & mmask;
@@ -283,7 +295,7 @@ __device__ __forceinline__ void fwd_task(const FwdArgs &a, int cg, int t, unsign
                 }
             }
 #pragma unroll
-            for (int k = 0; k < kFwdUnroll; k++) {
+            for (int k = 0; k < U; k++) {
                 if (tk[k] != kSent) {
                     const int d = (int)(tk[k] >> a.mb) + wk[k];
                     if (d < bd) {
@@ -300,6 +312,7 @@ __device__ __forceinline__ void fwd_task(const FwdArgs &a, int cg, int t, unsign
         while (v < v1) {
             const uint64_t b = fwd_finalize(a, cgv, v, bd, bm, lane, outs);
             produced += __popcll(b);
+            colany |= b;
             if (b) run_act |= 1ull << (v - v0);
             ++v;
             bd = kInf;
@@ -311,6 +324,7 @@ __device__ __forceinline__ void fwd_task(const FwdArgs &a, int cg, int t, unsign
         a.pd[pidx] = bd;
         a.pm[pidx] = bm;
     }
+    flush_colmask(a.colmask, a.ncg, cg, colany);
 }
 
 // Combine the slices of split row h (fixed slice order) and finish it.
@@ -319,6 +333,7 @@ __device__ __forceinline__ void fwd_task(const FwdArgs &a, int cg, int t, unsign
 // product's counters.
 __device__ __forceinline__ void fwd_hub(const FwdArgs &a, int cg, int h, unsigned long long &produced, unsigned long long &outs) {
     const int lane = threadIdx.x & (kWave - 1);
+    uint64_t colany = 0;
     const Hub *hp = a.hubs + h;
     const int v = uni(hp->v), first = uni(hp->first), np = uni(hp->nparts);
     const size_t cgv = (size_t)cg * (size_t)a.n;
@@ -337,7 +352,9 @@ __device__ __forceinline__ void fwd_hub(const FwdArgs &a, int cg, int h, unsigne
     }
     const uint64_t b = fwd_finalize(a, cgv, v, bd, bm, lane, outs);
     produced += __popcll(b);
+    colany |= b;
     if (b && lane == 0) atomicOr(a.abits_n + (size_t)cg * a.nwords + (v >> 5), 1u << (v & 31));
+    flush_colmask(a.colmask, a.ncg, cg, colany);
 }
 
 // ===================================================================== backward
@@ -364,21 +381,31 @@ struct BwdArgs {
     unsigned long long *ctr;
     uint32_t *clear_bits;      // ncg planes
     unsigned long long *clear_ctr;
+    unsigned long long *colmask;    // nullable: [32][ncg] columns that produced entries
+    const uint64_t *cmask;     // counting product: nullable per-group lane mask of the
+                               // columns to count (others are left untouched)
 };
 
 // Per-vertex finish of the counting product: counters, leaves, zeta = 0.
 __device__ __forceinline__ uint64_t count_finalize(const BwdArgs &a, size_t cgv, int cg, int x,
                                                    int dx, int c, int lane) {
+    const uint64_t mask = a.cmask ? a.cmask[cg] : ~0ull;
+    const bool mine = (mask >> lane) & 1ull;
     const size_t idx = (cgv + (size_t)x) * kWave + lane;
     const bool reach = dx != kInf;
     const bool leaf = reach && c == 0;
-    const bool front = leaf && a.src[cg * kWave + lane] != x;
-    a.cnt[idx] = (reach && c > 0) ? c : -1;
-    a.zeta[idx] = 0.0;
-    a.step[idx] = leaf ? 0 : -1;
-    if (leaf) a.q[idx] = 1.0 / a.tsig[idx];
+    const bool front = mine && leaf && a.src[cg * kWave + lane] != x;
+    if (mine) {
+        a.cnt[idx] = (reach && c > 0) ? c : -1;
+        a.zeta[idx] = 0.0;
+        if (a.step) a.step[idx] = leaf ? 0 : -1;
+        if (leaf) a.q[idx] = 1.0 / a.tsig[idx];
+    }
     const uint64_t bits = ballot(front);
-    if (lane == 0) a.fbits_n[cgv + (size_t)x] = bits;
+    if (lane == 0) {
+        uint64_t *row = a.fbits_n + cgv + (size_t)x;
+        *row = a.cmask ? ((*row & ~mask) | bits) : bits;
+    }
     return bits;
 }
 
@@ -387,6 +414,7 @@ __device__ __forceinline__ uint64_t count_finalize(const BwdArgs &a, size_t cgv,
 template <int AM>
 __device__ __forceinline__ void count_task(const BwdArgs &a, int cg, int t, unsigned long long &produced) {
     const int lane = threadIdx.x & (kWave - 1);
+    uint64_t colany = 0;
     const Task *tp = a.tasks + t;
     const int v0 = uni(tp->v0), v1 = uni(tp->v1), hub = uni(tp->hub), part = uni(tp->part);
     const int64_t e0 = uni64(tp->e0), e1 = uni64(tp->e1);
@@ -396,7 +424,8 @@ __device__ __forceinline__ void count_task(const BwdArgs &a, int cg, int t, unsi
     const int xa = v0, xb = hub >= 0 ? v0 + 1 : v1;
     for (int x = xa; x < xb; x++) {
         const int dx = Td[(size_t)x * kWave + lane];
-        const bool reach = dx != kInf;
+        // lanes outside the counting mask skip their loads (their state is kept)
+        const bool reach = dx != kInf && (!a.cmask || ((a.cmask[cg] >> lane) & 1ull));
         const int64_t ea = hub >= 0 ? e0 : a.rp[x];
         const int64_t eb = hub >= 0 ? e1 : a.rp[x + 1];
         int c = 0;
@@ -429,15 +458,18 @@ __device__ __forceinline__ void count_task(const BwdArgs &a, int cg, int t, unsi
         } else {
             const uint64_t b = count_finalize(a, cgv, cg, x, dx, c, lane);
             produced += __popcll(b);
+            colany |= b;
             if (b) run_act |= 1ull << (x - v0);
         }
     }
     if (hub < 0 && lane == 0 && run_act)
         or_run_bits(a.abits_n + (size_t)cg * a.nwords, v0, run_act);
+    flush_colmask(a.colmask, a.ncg, cg, colany);
 }
 
 __device__ __forceinline__ void count_hub(const BwdArgs &a, int cg, int h, unsigned long long &produced) {
     const int lane = threadIdx.x & (kWave - 1);
+    uint64_t colany = 0;
     const Hub *hp = a.hubs + h;
     const int x = uni(hp->v), first = uni(hp->first), np = uni(hp->nparts);
     const size_t cgv = (size_t)cg * (size_t)a.n;
@@ -446,7 +478,9 @@ __device__ __forceinline__ void count_hub(const BwdArgs &a, int cg, int h, unsig
     const int dx = a.tdist[(cgv + (size_t)x) * kWave + lane];
     const uint64_t b = count_finalize(a, cgv, cg, x, dx, c, lane);
     produced += __popcll(b);
+    colany |= b;
     if (b && lane == 0) atomicOr(a.abits_n + (size_t)cg * a.nwords + (x >> 5), 1u << (x & 31));
+    flush_colmask(a.colmask, a.ncg, cg, colany);
 }
 
 // Finish (s, x) after a backward product contributed `acc` from `got`
@@ -469,7 +503,7 @@ __device__ __forceinline__ uint64_t bwd_finalize(const BwdArgs &a, size_t cgv, i
                 const double sg = a.tsig[idx];
                 a.q[idx] = z + 1.0 / sg;
                 a.cnt[idx] = -1;
-                a.step[idx] = a.k;
+                if (a.step) a.step[idx] = a.k;
                 done = true;
                 const bool self = a.src[cg * kWave + lane] == x;
                 front = !self;
@@ -481,7 +515,7 @@ __device__ __forceinline__ uint64_t bwd_finalize(const BwdArgs &a, size_t cgv, i
         bits = ballot(front);
         if (ballot(done)) {
             const double t = wave_sum(dep);
-            if (lane == 0 && t != 0.0) a.lam[cgv + (size_t)x] += t;
+            if (lane == 0 && t != 0.0 && a.lam) a.lam[cgv + (size_t)x] += t;
         }
     }
     if (lane == 0) a.fbits_n[cgv + (size_t)x] = bits;
@@ -492,6 +526,7 @@ __device__ __forceinline__ uint64_t bwd_finalize(const BwdArgs &a, size_t cgv, i
 template <int AM>
 __device__ __forceinline__ void bwd_task(const BwdArgs &a, int cg, int t, unsigned long long &produced, unsigned long long &outs) {
     const int lane = threadIdx.x & (kWave - 1);
+    uint64_t colany = 0;
     const Task *tp = a.tasks + t;
     const int v0 = uni(tp->v0), v1 = uni(tp->v1), hub = uni(tp->hub), part = uni(tp->part);
     const int64_t e0 = uni64(tp->e0), e1 = uni64(tp->e1);
@@ -522,6 +557,7 @@ __device__ __forceinline__ void bwd_task(const BwdArgs &a, int cg, int t, unsign
                     if (loaded) {
                         const uint64_t b = bwd_finalize(a, cgv, cg, x, cx, acc, got, lane, outs);
                         produced += __popcll(b);
+                        colany |= b;
                         if (b) run_act |= 1ull << (x - v0);
                     } else if (lane == 0) {
                         a.fbits_n[cgv + (size_t)x] = 0ull;
@@ -583,6 +619,7 @@ __device__ __forceinline__ void bwd_task(const BwdArgs &a, int cg, int t, unsign
             if (loaded) {
                 const uint64_t b = bwd_finalize(a, cgv, cg, x, cx, acc, got, lane, outs);
                 produced += __popcll(b);
+                colany |= b;
                 if (b) run_act |= 1ull << (x - v0);
             } else if (lane == 0) {
                 a.fbits_n[cgv + (size_t)x] = 0ull;
@@ -598,10 +635,12 @@ __device__ __forceinline__ void bwd_task(const BwdArgs &a, int cg, int t, unsign
         a.pd[pidx] = got;
         a.pm[pidx] = acc;
     }
+    flush_colmask(a.colmask, a.ncg, cg, colany);
 }
 
 __device__ __forceinline__ void bwd_hub(const BwdArgs &a, int cg, int h, unsigned long long &produced, unsigned long long &outs) {
     const int lane = threadIdx.x & (kWave - 1);
+    uint64_t colany = 0;
     const Hub *hp = a.hubs + h;
     const int x = uni(hp->v), first = uni(hp->first), np = uni(hp->nparts);
     const size_t cgv = (size_t)cg * (size_t)a.n;
@@ -615,8 +654,73 @@ __device__ __forceinline__ void bwd_hub(const BwdArgs &a, int cg, int h, unsigne
     const int cx = a.cnt[(cgv + (size_t)x) * kWave + lane];
     const uint64_t b = bwd_finalize(a, cgv, cg, x, cx, acc, got, lane, outs);
     produced += __popcll(b);
+    colany |= b;
     if (b && lane == 0) atomicOr(a.abits_n + (size_t)cg * a.nwords + (x >> 5), 1u << (x & 31));
+    flush_colmask(a.colmask, a.ncg, cg, colany);
 }
+
+// ===================================================================== grid kernels
+template <int AM>
+__global__ __launch_bounds__(kBlock) void k_fwd_pull(FwdArgs a) {
+    const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const int cg = wid / a.ntasks;                       // column-group major
+    unsigned long long produced = 0, outs = 0;
+    if (cg < a.ncg) fwd_task<AM>(a, cg, wid - cg * a.ntasks, produced, outs);
+    flush_counts(produced, outs, 0, 0, a.ctr);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fwd_merge(FwdArgs a) {
+    const int gtid = blockIdx.x * kBlock + threadIdx.x;
+    unsigned long long nv = 0, na = 0;
+    clear_and_count(a.clear_bits, a.nwords, a.ncg, a.rp, nv, na);
+    if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
+    const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    unsigned long long produced = 0, outs = 0;
+    const int cg = a.nhubs ? wid / a.nhubs : a.ncg;
+    if (cg < a.ncg) fwd_hub(a, cg, wid - cg * a.nhubs, produced, outs);
+    flush_counts(produced, outs, nv, na, a.ctr);
+}
+
+template <int AM>
+__global__ __launch_bounds__(kBlock) void k_bwd_count(BwdArgs a) {
+    const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const int cg = wid / a.ntasks;                       // column-group major
+    unsigned long long produced = 0;
+    if (cg < a.ncg) count_task<AM>(a, cg, wid - cg * a.ntasks, produced);
+    flush_counts(produced, 0, 0, 0, a.ctr);
+}
+
+__global__ __launch_bounds__(kBlock) void k_bwd_count_merge(BwdArgs a) {
+    const int gtid = blockIdx.x * kBlock + threadIdx.x;
+    if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
+    const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    unsigned long long produced = 0;
+    const int cg = a.nhubs ? wid / a.nhubs : a.ncg;
+    if (cg < a.ncg) count_hub(a, cg, wid - cg * a.nhubs, produced);
+    flush_counts(produced, 0, 0, 0, a.ctr);
+}
+
+template <int AM>
+__global__ __launch_bounds__(kBlock) void k_bwd_pull(BwdArgs a) {
+    const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const int cg = wid / a.ntasks;                       // column-group major
+    unsigned long long produced = 0, outs = 0;
+    if (cg < a.ncg) bwd_task<AM>(a, cg, wid - cg * a.ntasks, produced, outs);
+    flush_counts(produced, outs, 0, 0, a.ctr);
+}
+
+__global__ __launch_bounds__(kBlock) void k_bwd_merge(BwdArgs a) {
+    const int gtid = blockIdx.x * kBlock + threadIdx.x;
+    unsigned long long nv = 0, na = 0;
+    clear_and_count(a.clear_bits, a.nwords, a.ncg, a.rp, nv, na);
+    if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
+    const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    unsigned long long produced = 0, outs = 0;
+    const int cg = a.nhubs ? wid / a.nhubs : a.ncg;
+    if (cg < a.ncg) bwd_hub(a, cg, wid - cg * a.nhubs, produced, outs);
+    flush_counts(produced, outs, nv, na, a.ctr);
+}
+
 
 }  // namespace
 }  // namespace mfbc

@@ -1,0 +1,598 @@
+// Served form: continuous batching of source columns over a resident graph.
+//
+// A server owns `width` source columns (a multiple of 64) of one graph.  Each
+// column holds one source of some request and moves through its own phase:
+// FWD (Algorithm 1's loop), CNT (the counting product of Algorithm 2), BWD
+// (Algorithm 2's loop), DONE (ready to harvest), FREE.  Column s of every
+// product depends only on column s of its frontier (the product's output
+// column is a function of the same input column, Section 3), so columns can
+// join and leave at product boundaries while other columns are mid-loop:
+// one step runs at most one forward product (every FWD column), one backward
+// product (every BWD column) and one counting product (the columns that just
+// finished their forward loop), with the same kernels as the plain path.
+// The forward and backward states have separate buffers here, because
+// columns of one 64-column group can be in different phases.
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "products.h"
+
+namespace mfbc {
+namespace {
+
+enum Phase : uint8_t { kFree = 0, kFwd = 1, kCnt = 2, kBwd = 3, kDone = 4 };
+
+// New columns: T = (INF, 0), counters off, backward frontier bits cleared.
+__global__ void k_srv_reset_cols(int n, const uint64_t *newmask, int32_t *tdist, double *tsig,
+                                 int32_t *cnt, double *zeta, uint64_t *bb0, uint64_t *bb1) {
+    const int cg = blockIdx.y;
+    const uint64_t m = newmask[cg];
+    if (!m) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const bool mine = (m >> lane) & 1ull;
+    const int v0 = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int stride = (gridDim.x * blockDim.x) >> 6;
+    for (int v = v0; v < n; v += stride) {
+        const size_t idx = ((size_t)cg * n + v) * kWave + lane;
+        if (mine) {
+            tdist[idx] = kInf;
+            tsig[idx] = 0.0;
+            cnt[idx] = -1;
+            zeta[idx] = 0.0;
+        }
+        if (lane == 0) {
+            bb0[(size_t)cg * n + v] &= ~m;
+            bb1[(size_t)cg * n + v] &= ~m;
+        }
+    }
+}
+
+// Rows of new sources that are not yet in the current forward frontier
+// start with every lane absent.
+__global__ void k_srv_seed_rows(int n, int nwords, const int32_t *cols, int count,
+                                const int32_t *src, uint32_t *ftup, const uint32_t *abits) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const int c = cols[i], v = src[c], cg = c / kWave;
+    if ((abits[(size_t)cg * nwords + (v >> 5)] >> (v & 31)) & 1u) return;
+    const size_t row = ((size_t)cg * n + v) * kWave;
+    for (int l = 0; l < kWave; l++) ftup[row + l] = kSent;
+}
+
+__global__ void k_srv_seed(int n, int nwords, const int32_t *cols, int count, const int32_t *src,
+                           int32_t *tdist, double *tsig, uint32_t *ftup, uint32_t *abits) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const int c = cols[i], v = src[c], cg = c / kWave, lane = c % kWave;
+    const size_t idx = ((size_t)cg * n + v) * kWave + lane;
+    tdist[idx] = 0;
+    tsig[idx] = 1.0;
+    ftup[idx] = 1u;
+    atomicOr(abits + (size_t)cg * nwords + (v >> 5), 1u << (v & 31));
+}
+
+// dest_i[v] += delta(column cols[i], v) for every listed column, in list
+// order (one thread per vertex, so a destination shared by several columns
+// is updated without races and in a fixed order).
+__global__ void k_srv_harvest_bc(int n, const int32_t *cols, int count, const int32_t *src,
+                                 double *const *dest, const int32_t *tdist, const double *tsig,
+                                 const double *zeta) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    for (int i = 0; i < count; i++) {
+        const int c = cols[i], cg = c / kWave, lane = c % kWave;
+        const size_t idx = ((size_t)cg * n + v) * kWave + lane;
+        if (tdist[idx] != kInf && v != src[c]) dest[i][v] += zeta[idx] * tsig[idx];
+    }
+}
+
+// out_i[t] = delta(column cols[i], targets[t]).
+__global__ void k_srv_harvest_dep(int n, const int32_t *cols, int count, const int32_t *src,
+                                  const int32_t *targets, int ntargets, double *const *out,
+                                  const int32_t *tdist, const double *tsig, const double *zeta) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count * ntargets) return;
+    const int i = k / ntargets, t = k % ntargets;
+    const int c = cols[i], cg = c / kWave, lane = c % kWave, v = targets[t];
+    const size_t idx = ((size_t)cg * n + v) * kWave + lane;
+    out[i][t] = (tdist[idx] != kInf && v != src[c]) ? zeta[idx] * tsig[idx] : 0.0;
+}
+
+inline int nblocks(size_t work, int per, int cap = 1 << 20) {
+    size_t b = (work + per - 1) / per;
+    return (int)std::max<size_t>(1, std::min<size_t>(b, (size_t)cap));
+}
+
+}  // namespace
+}  // namespace mfbc
+
+using namespace mfbc;
+
+struct mfbc_server {
+    mfbc_graph *g = nullptr;
+    int width = 0, ncg = 0, nwords = 0;
+    int cur_f = 0, cur_b = 0, kfwd = 0, kbwd = 0;
+    int32_t *tdist = nullptr;
+    double *tsig = nullptr;
+    uint32_t *ftup[2] = {nullptr, nullptr};
+    double *fsig[2] = {nullptr, nullptr};
+    uint32_t *abf[2] = {nullptr, nullptr};
+    int32_t *cnt = nullptr;
+    double *zeta = nullptr, *q = nullptr;
+    uint64_t *bb[2] = {nullptr, nullptr};
+    uint32_t *abb[2] = {nullptr, nullptr};
+    int32_t *pd = nullptr;
+    double *pm = nullptr;
+    int32_t *src = nullptr;
+    unsigned long long *ctr = nullptr;      // [2][4][32]: product counters, then the block
+                                            // the merge kernels zero (sizes are not used here)
+    unsigned long long *colmask = nullptr;  // [3][32][ncg]: forward, counting, backward
+    uint64_t *cmask = nullptr;              // [ncg] counting mask
+    uint64_t *newmask = nullptr;            // [ncg] columns being admitted
+    int32_t *flags = nullptr;
+    char *meta = nullptr;                   // staging for harvest/admit lists
+    size_t meta_bytes = 0;
+    unsigned long long *h_colmask = nullptr;  // pinned
+    std::vector<int32_t> h_src;
+    std::vector<uint8_t> phase;
+    std::vector<uint8_t> ran_f, ran_b, ran_c; // columns taking part in the launched step
+    bool launched = false, any_f = false, any_b = false, any_c = false;
+};
+
+namespace {
+
+int sfail(int code, const std::string &m) { return set_error(code, m); }
+
+template <typename T>
+int salloc(T **p, size_t count) {
+    *p = nullptr;
+    if (hipMalloc((void **)p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return MFBC_ENOMEM;
+    }
+    return MFBC_OK;
+}
+
+template <typename T>
+void sfree(T *&p) {
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+void free_server(mfbc_server *s) {
+    sfree(s->tdist);
+    sfree(s->tsig);
+    for (int b = 0; b < 2; b++) {
+        sfree(s->ftup[b]);
+        sfree(s->fsig[b]);
+        sfree(s->abf[b]);
+        sfree(s->bb[b]);
+        sfree(s->abb[b]);
+    }
+    sfree(s->cnt);
+    sfree(s->zeta);
+    sfree(s->q);
+    sfree(s->pd);
+    sfree(s->pm);
+    sfree(s->src);
+    sfree(s->ctr);
+    sfree(s->colmask);
+    sfree(s->cmask);
+    sfree(s->newmask);
+    sfree(s->flags);
+    sfree(s->meta);
+    if (s->h_colmask) (void)hipHostFree(s->h_colmask);
+    s->h_colmask = nullptr;
+}
+
+ArcSrc srv_arc_src(const Csr &c) {
+    ArcSrc r{};
+    r.col = c.col;
+    r.w = c.w;
+    r.pk = c.pk;
+    r.cb = c.cb;
+    r.cmask = c.cb >= 32 ? 0xffffffffu : ((1u << c.cb) - 1u);
+    return r;
+}
+
+int srv_mode(const Csr &c) { return c.w == nullptr ? 0 : (c.pk ? 1 : 2); }
+
+int stage(mfbc_server *s, size_t bytes) {
+    if (s->meta_bytes >= bytes) return MFBC_OK;
+    sfree(s->meta);
+    s->meta_bytes = 0;
+    if (salloc(&s->meta, bytes)) return sfail(MFBC_ENOMEM, "staging allocation failed");
+    s->meta_bytes = bytes;
+    return MFBC_OK;
+}
+
+#define SHIP(expr)                                                                     \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return sfail(MFBC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+int mfbc_server_footprint(const mfbc_graph *g, int32_t width, int64_t *bytes) {
+    if (!g || !bytes || width < 64 || width % 64) return sfail(MFBC_EINVAL, "bad arguments");
+    const int64_t n = g->n, ncg = width / 64;
+    const int64_t slots = std::max(g->plan_in.nslots, g->plan_out.nslots);
+    const int64_t nw = (n + 31) / 32;
+    *bytes = n * width * (4 + 8 + 2 * 4 + 2 * 8 + 4 + 8 + 8) + 2 * ncg * n * 8 + 4 * ncg * nw * 4 +
+             slots * width * 12;
+    return MFBC_OK;
+}
+
+int mfbc_server_create(mfbc_graph *g, int32_t width, mfbc_server **out) {
+    if (!g || !out) return sfail(MFBC_EINVAL, "NULL argument");
+    if (width < 64 || width % 64) return sfail(MFBC_EINVAL, "width must be a positive multiple of 64");
+    *out = nullptr;
+    mfbc_server *s = new (std::nothrow) mfbc_server();
+    if (!s) return sfail(MFBC_ENOMEM, "host allocation failed");
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(g->device);
+    s->g = g;
+    s->width = width;
+    s->ncg = width / 64;
+    s->nwords = (g->n + 31) / 32;
+    const size_t n = (size_t)g->n, tile = n * (size_t)width, ncg = (size_t)s->ncg;
+    const size_t slots = (size_t)std::max(g->plan_in.nslots, g->plan_out.nslots) * (size_t)width;
+    int rc = MFBC_OK;
+    if (salloc(&s->tdist, tile) || salloc(&s->tsig, tile) || salloc(&s->ftup[0], tile) ||
+        salloc(&s->ftup[1], tile) || salloc(&s->fsig[0], tile) || salloc(&s->fsig[1], tile) ||
+        salloc(&s->abf[0], ncg * s->nwords) || salloc(&s->abf[1], ncg * s->nwords) ||
+        salloc(&s->cnt, tile) || salloc(&s->zeta, tile) || salloc(&s->q, tile) ||
+        salloc(&s->bb[0], ncg * n) || salloc(&s->bb[1], ncg * n) ||
+        salloc(&s->abb[0], ncg * s->nwords) || salloc(&s->abb[1], ncg * s->nwords) ||
+        salloc(&s->pd, slots) || salloc(&s->pm, slots) || salloc(&s->src, (size_t)width) ||
+        salloc(&s->ctr, (size_t)8 * kCounterSlots) || salloc(&s->colmask, 3 * 32 * ncg) ||
+        salloc(&s->cmask, ncg) || salloc(&s->newmask, ncg) || salloc(&s->flags, 4))
+        rc = MFBC_ENOMEM;
+    if (!rc && hipHostMalloc((void **)&s->h_colmask, 3 * 32 * ncg * 8) != hipSuccess) rc = MFBC_ENOMEM;
+    if (!rc) {
+        // every column free: counters off, no frontier anywhere
+        hipStream_t st = nullptr;
+        if (hipMemsetAsync(s->cnt, 0xff, tile * 4, st) != hipSuccess ||
+            hipMemsetAsync(s->bb[0], 0, ncg * n * 8, st) != hipSuccess ||
+            hipMemsetAsync(s->bb[1], 0, ncg * n * 8, st) != hipSuccess ||
+            hipMemsetAsync(s->abf[0], 0, ncg * s->nwords * 4, st) != hipSuccess ||
+            hipMemsetAsync(s->abf[1], 0, ncg * s->nwords * 4, st) != hipSuccess ||
+            hipMemsetAsync(s->abb[0], 0, ncg * s->nwords * 4, st) != hipSuccess ||
+            hipMemsetAsync(s->abb[1], 0, ncg * s->nwords * 4, st) != hipSuccess ||
+            hipMemsetAsync(s->src, 0xff, (size_t)width * 4, st) != hipSuccess ||
+            hipMemsetAsync(s->flags, 0, 16, st) != hipSuccess ||
+            hipDeviceSynchronize() != hipSuccess)
+            rc = MFBC_EDEVICE;
+    }
+    if (prev >= 0) (void)hipSetDevice(prev);
+    if (rc) {
+        free_server(s);
+        delete s;
+        return sfail(rc, rc == MFBC_ENOMEM ? "device allocation failed" : "initialisation failed");
+    }
+    s->h_src.assign((size_t)width, -1);
+    s->phase.assign((size_t)width, kFree);
+    s->ran_f.assign((size_t)width, 0);
+    s->ran_b.assign((size_t)width, 0);
+    s->ran_c.assign((size_t)width, 0);
+    *out = s;
+    return MFBC_OK;
+}
+
+int mfbc_server_free(mfbc_server *s) {
+    if (!s) return MFBC_OK;
+    (void)hipDeviceSynchronize();
+    free_server(s);
+    delete s;
+    return MFBC_OK;
+}
+
+int mfbc_server_free_columns(const mfbc_server *s) {
+    if (!s) return sfail(MFBC_EINVAL, "NULL server");
+    int f = 0;
+    for (uint8_t p : s->phase) f += p == kFree;
+    return f;
+}
+
+int mfbc_server_active_columns(const mfbc_server *s) {
+    if (!s) return sfail(MFBC_EINVAL, "NULL server");
+    int f = 0;
+    for (uint8_t p : s->phase) f += p == kFwd || p == kCnt || p == kBwd;
+    return f;
+}
+
+int mfbc_server_admit(mfbc_server *s, const int32_t *h_sources, int32_t count, int32_t *h_columns,
+                      void *hip_stream) {
+    if (!s || (count > 0 && (!h_sources || !h_columns))) return sfail(MFBC_EINVAL, "NULL argument");
+    if (s->launched) return sfail(MFBC_EINVAL, "a step is in flight");
+    if (count <= 0) return MFBC_OK;
+    for (int i = 0; i < count; i++)
+        if (h_sources[i] < 0 || h_sources[i] >= s->g->n) return sfail(MFBC_EINVAL, "source out of range");
+    std::vector<int32_t> cols;
+    for (int c = 0; c < s->width && (int)cols.size() < count; c++)
+        if (s->phase[(size_t)c] == kFree) cols.push_back(c);
+    if ((int)cols.size() < count) return sfail(MFBC_EINVAL, "not enough free columns");
+    hipStream_t st = (hipStream_t)hip_stream;
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(s->g->device);
+    std::vector<uint64_t> nm((size_t)s->ncg, 0);
+    for (int i = 0; i < count; i++) {
+        const int c = cols[(size_t)i];
+        h_columns[i] = c;
+        s->h_src[(size_t)c] = h_sources[i];
+        s->phase[(size_t)c] = kFwd;
+        nm[(size_t)(c / 64)] |= 1ull << (c % 64);
+    }
+    int rc = stage(s, (size_t)count * 4 + 256);
+    if (rc) return rc;
+    SHIP(hipMemcpyAsync(s->meta, cols.data(), (size_t)count * 4, hipMemcpyHostToDevice, st));
+    SHIP(hipMemcpyAsync(s->newmask, nm.data(), (size_t)s->ncg * 8, hipMemcpyHostToDevice, st));
+    SHIP(hipMemcpyAsync(s->src, s->h_src.data(), (size_t)s->width * 4, hipMemcpyHostToDevice, st));
+    const int n = s->g->n;
+    hipLaunchKernelGGL(k_srv_reset_cols, dim3(nblocks((size_t)n * 64, 256, 4096), s->ncg), dim3(256),
+                       0, st, n, (const uint64_t *)s->newmask, s->tdist, s->tsig, s->cnt, s->zeta,
+                       s->bb[0], s->bb[1]);
+    hipLaunchKernelGGL(k_srv_seed_rows, dim3(nblocks((size_t)count, 256)), dim3(256), 0, st, n,
+                       s->nwords, (const int32_t *)s->meta, count, (const int32_t *)s->src,
+                       s->ftup[s->cur_f], (const uint32_t *)s->abf[s->cur_f]);
+    hipLaunchKernelGGL(k_srv_seed, dim3(nblocks((size_t)count, 256)), dim3(256), 0, st, n,
+                       s->nwords, (const int32_t *)s->meta, count, (const int32_t *)s->src,
+                       s->tdist, s->tsig, s->ftup[s->cur_f], s->abf[s->cur_f]);
+    SHIP(hipGetLastError());
+    SHIP(hipStreamSynchronize(st));
+    if (prev >= 0) (void)hipSetDevice(prev);
+    return MFBC_OK;
+}
+
+int mfbc_server_step_launch(mfbc_server *s, void *hip_stream) {
+    if (!s) return sfail(MFBC_EINVAL, "NULL server");
+    if (s->launched) return sfail(MFBC_EINVAL, "a step is already in flight");
+    hipStream_t st = (hipStream_t)hip_stream;
+    mfbc_graph *g = s->g;
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(g->device);
+    s->any_f = s->any_b = s->any_c = false;
+    std::vector<uint64_t> cm((size_t)s->ncg, 0);
+    for (int c = 0; c < s->width; c++) {
+        const uint8_t p = s->phase[(size_t)c];
+        s->ran_f[(size_t)c] = p == kFwd;
+        s->ran_b[(size_t)c] = p == kBwd;
+        s->ran_c[(size_t)c] = p == kCnt;
+        s->any_f |= p == kFwd;
+        s->any_b |= p == kBwd;
+        if (p == kCnt) {
+            s->any_c = true;
+            cm[(size_t)(c / 64)] |= 1ull << (c % 64);
+        }
+    }
+    const size_t ncg = (size_t)s->ncg;
+    SHIP(hipMemsetAsync(s->colmask, 0, 3 * 32 * ncg * 8, st));
+    const int nw = s->nwords;
+    if (s->any_f) {
+        // one forward product over every FWD column
+        const int b = s->cur_f;
+        FwdArgs a{};
+        a.tasks = g->plan_in.tasks;
+        a.hubs = g->plan_in.hubs;
+        a.ntasks = g->plan_in.ntasks;
+        a.nhubs = g->plan_in.nhubs;
+        a.nslots = g->plan_in.nslots;
+        a.ncg = s->ncg;
+        a.n = g->n;
+        a.j = ++s->kfwd;
+        a.nwords = nw;
+        a.mb = g->mb;
+        a.rp = g->in.rp;
+        a.arcs = srv_arc_src(g->in);
+        a.abits = s->abf[b];
+        a.ftup = s->ftup[b];
+        a.fsig = s->fsig[b];
+        a.tdist = s->tdist;
+        a.tsig = s->tsig;
+        a.abits_n = s->abf[b ^ 1];
+        a.ftup_n = s->ftup[b ^ 1];
+        a.fsig_n = s->fsig[b ^ 1];
+        a.pd = s->pd;
+        a.pm = s->pm;
+        a.ctr = s->ctr;
+        a.flags = s->flags;
+        a.clear_bits = s->abf[b];
+        a.clear_ctr = s->ctr + 4 * kCounterSlots;   // second block of 4 x 32 slots
+        a.colmask = s->colmask;
+        const int grid = nblocks((size_t)a.ntasks * ncg, kWavesPerBlock, 0x7fffffff);
+        switch (srv_mode(g->in)) {
+            case 0: hipLaunchKernelGGL(k_fwd_pull<0>, dim3(grid), dim3(kBlock), 0, st, a); break;
+            case 1: hipLaunchKernelGGL(k_fwd_pull<1>, dim3(grid), dim3(kBlock), 0, st, a); break;
+            default: hipLaunchKernelGGL(k_fwd_pull<2>, dim3(grid), dim3(kBlock), 0, st, a); break;
+        }
+        const int mgrid = std::max(nblocks((size_t)a.nhubs * ncg, kWavesPerBlock, 0x7fffffff),
+                                   nblocks((size_t)nw, kBlock, 1024));
+        hipLaunchKernelGGL(k_fwd_merge, dim3(mgrid), dim3(kBlock), 0, st, a);
+        s->cur_f ^= 1;
+    }
+    BwdArgs c{};
+    c.tasks = g->plan_out.tasks;
+    c.hubs = g->plan_out.hubs;
+    c.ntasks = g->plan_out.ntasks;
+    c.nhubs = g->plan_out.nhubs;
+    c.nslots = g->plan_out.nslots;
+    c.ncg = s->ncg;
+    c.n = g->n;
+    c.nwords = nw;
+    c.rp = g->out.rp;
+    c.arcs = srv_arc_src(g->out);
+    c.src = s->src;
+    c.tdist = s->tdist;
+    c.tsig = s->tsig;
+    c.cnt = s->cnt;
+    c.zeta = s->zeta;
+    c.q = s->q;
+    c.step = nullptr;
+    c.lam = nullptr;
+    c.pd = s->pd;
+    c.pm = s->pm;
+    c.ctr = s->ctr;
+    c.clear_ctr = s->ctr + 4 * kCounterSlots;
+    const int mode = srv_mode(g->out);
+    if (s->any_b) {
+        // one backward product over every BWD column: reads cur_b, writes the other
+        const int b = s->cur_b;
+        c.k = ++s->kbwd;
+        c.abits = s->abb[b];
+        c.fbits = s->bb[b];
+        c.abits_n = s->abb[b ^ 1];
+        c.fbits_n = s->bb[b ^ 1];
+        c.clear_bits = s->abb[b];
+        c.colmask = s->colmask + 2 * 32 * ncg;
+        c.cmask = nullptr;
+        const int grid = nblocks((size_t)c.ntasks * ncg, kWavesPerBlock, 0x7fffffff);
+        switch (mode) {
+            case 0: hipLaunchKernelGGL(k_bwd_pull<0>, dim3(grid), dim3(kBlock), 0, st, c); break;
+            case 1: hipLaunchKernelGGL(k_bwd_pull<1>, dim3(grid), dim3(kBlock), 0, st, c); break;
+            default: hipLaunchKernelGGL(k_bwd_pull<2>, dim3(grid), dim3(kBlock), 0, st, c); break;
+        }
+        const int mgrid = std::max(nblocks((size_t)c.nhubs * ncg, kWavesPerBlock, 0x7fffffff),
+                                   nblocks((size_t)nw, kBlock, 1024));
+        hipLaunchKernelGGL(k_bwd_merge, dim3(mgrid), dim3(kBlock), 0, st, c);
+        s->cur_b ^= 1;
+    }
+    if (s->any_c) {
+        // counting product of the columns whose forward loop just ended; their
+        // first backward frontier joins the buffer the next backward product reads
+        SHIP(hipMemcpyAsync(s->cmask, cm.data(), ncg * 8, hipMemcpyHostToDevice, st));
+        c.k = 0;
+        c.abits_n = s->abb[s->cur_b];
+        c.fbits_n = s->bb[s->cur_b];
+        c.abits = s->abb[s->cur_b ^ 1];
+        c.fbits = s->bb[s->cur_b ^ 1];
+        c.colmask = s->colmask + 32 * ncg;
+        c.cmask = s->cmask;
+        const int grid = nblocks((size_t)c.ntasks * ncg, kWavesPerBlock, 0x7fffffff);
+        switch (mode) {
+            case 0: hipLaunchKernelGGL(k_bwd_count<0>, dim3(grid), dim3(kBlock), 0, st, c); break;
+            case 1: hipLaunchKernelGGL(k_bwd_count<1>, dim3(grid), dim3(kBlock), 0, st, c); break;
+            default: hipLaunchKernelGGL(k_bwd_count<2>, dim3(grid), dim3(kBlock), 0, st, c); break;
+        }
+        const int mgrid = nblocks((size_t)c.nhubs * ncg, kWavesPerBlock, 0x7fffffff);
+        hipLaunchKernelGGL(k_bwd_count_merge, dim3(mgrid), dim3(kBlock), 0, st, c);
+    }
+    SHIP(hipGetLastError());
+    SHIP(hipMemcpyAsync(s->h_colmask, s->colmask, 3 * 32 * ncg * 8, hipMemcpyDeviceToHost, st));
+    s->launched = true;
+    if (prev >= 0) (void)hipSetDevice(prev);
+    return MFBC_OK;
+}
+
+int mfbc_server_step_finish(mfbc_server *s, int32_t *h_done, int32_t *h_ndone, void *hip_stream) {
+    if (!s || !h_done || !h_ndone) return sfail(MFBC_EINVAL, "NULL argument");
+    if (!s->launched) return sfail(MFBC_EINVAL, "no step in flight");
+    SHIP(hipStreamSynchronize((hipStream_t)hip_stream));
+    s->launched = false;
+    const size_t ncg = (size_t)s->ncg;
+    std::vector<uint64_t> mf(ncg, 0), mc(ncg, 0), mb(ncg, 0);
+    for (size_t k = 0; k < 32; k++)
+        for (size_t c = 0; c < ncg; c++) {
+            mf[c] |= s->h_colmask[k * ncg + c];
+            mc[c] |= s->h_colmask[32 * ncg + k * ncg + c];
+            mb[c] |= s->h_colmask[64 * ncg + k * ncg + c];
+        }
+    int nd = 0;
+    for (int c = 0; c < s->width; c++) {
+        const bool bit_f = (mf[(size_t)(c / 64)] >> (c % 64)) & 1ull;
+        const bool bit_c = (mc[(size_t)(c / 64)] >> (c % 64)) & 1ull;
+        const bool bit_b = (mb[(size_t)(c / 64)] >> (c % 64)) & 1ull;
+        uint8_t &p = s->phase[(size_t)c];
+        if (s->ran_f[(size_t)c] && p == kFwd && !bit_f) p = kCnt;
+        else if (s->ran_c[(size_t)c] && p == kCnt) p = bit_c ? kBwd : kDone;
+        else if (s->ran_b[(size_t)c] && p == kBwd && !bit_b) p = kDone;
+        if (p == kDone && (s->ran_b[(size_t)c] || s->ran_c[(size_t)c])) h_done[nd++] = c;
+    }
+    *h_ndone = nd;
+    return MFBC_OK;
+}
+
+static int harvest_common(mfbc_server *s, const int32_t *h_columns, int32_t count) {
+    for (int i = 0; i < count; i++) {
+        const int c = h_columns[i];
+        if (c < 0 || c >= s->width || s->phase[(size_t)c] != kDone)
+            return sfail(MFBC_EINVAL, "column " + std::to_string(c) + " is not finished");
+    }
+    return MFBC_OK;
+}
+
+static void release(mfbc_server *s, const int32_t *h_columns, int32_t count) {
+    for (int i = 0; i < count; i++) {
+        s->phase[(size_t)h_columns[i]] = kFree;
+        s->h_src[(size_t)h_columns[i]] = -1;
+    }
+}
+
+int mfbc_server_harvest_bc(mfbc_server *s, const int32_t *h_columns, int32_t count,
+                           double *const *d_dest, void *hip_stream) {
+    if (!s || (count > 0 && (!h_columns || !d_dest))) return sfail(MFBC_EINVAL, "NULL argument");
+    if (count <= 0) return MFBC_OK;
+    int rc = harvest_common(s, h_columns, count);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    if ((rc = stage(s, (size_t)count * 12 + 256))) return rc;
+    std::vector<char> h((size_t)count * 12 + 256, 0);
+    const size_t o_ptr = 0, o_col = (size_t)count * 8;
+    memcpy(h.data() + o_ptr, d_dest, (size_t)count * 8);
+    memcpy(h.data() + o_col, h_columns, (size_t)count * 4);
+    SHIP(hipMemcpyAsync(s->meta, h.data(), (size_t)count * 12, hipMemcpyHostToDevice, st));
+    const int n = s->g->n;
+    hipLaunchKernelGGL(k_srv_harvest_bc, dim3(nblocks((size_t)n, 256)), dim3(256), 0, st, n,
+                       (const int32_t *)(s->meta + o_col), count, (const int32_t *)s->src,
+                       (double *const *)(s->meta + o_ptr), (const int32_t *)s->tdist,
+                       (const double *)s->tsig, (const double *)s->zeta);
+    SHIP(hipGetLastError());
+    SHIP(hipStreamSynchronize(st));
+    release(s, h_columns, count);
+    return MFBC_OK;
+}
+
+int mfbc_server_harvest_dep(mfbc_server *s, const int32_t *h_columns, int32_t count,
+                            const int32_t *d_targets, int32_t ntargets, double *const *d_out,
+                            void *hip_stream) {
+    if (!s || (count > 0 && (!h_columns || !d_out)) || ntargets < 0 || (ntargets > 0 && !d_targets))
+        return sfail(MFBC_EINVAL, "bad argument");
+    if (count <= 0) return MFBC_OK;
+    int rc = harvest_common(s, h_columns, count);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    std::vector<int32_t> ht((size_t)ntargets);
+    if (ntargets) {
+        SHIP(hipMemcpyAsync(ht.data(), d_targets, (size_t)ntargets * 4, hipMemcpyDeviceToHost, st));
+        SHIP(hipStreamSynchronize(st));
+        for (int32_t t : ht)
+            if (t < 0 || t >= s->g->n) return sfail(MFBC_EINVAL, "target out of range");
+    }
+    if ((rc = stage(s, (size_t)count * 12 + 256))) return rc;
+    std::vector<char> h((size_t)count * 12 + 256, 0);
+    const size_t o_ptr = 0, o_col = (size_t)count * 8;
+    memcpy(h.data() + o_ptr, d_out, (size_t)count * 8);
+    memcpy(h.data() + o_col, h_columns, (size_t)count * 4);
+    SHIP(hipMemcpyAsync(s->meta, h.data(), (size_t)count * 12, hipMemcpyHostToDevice, st));
+    if (ntargets)
+        hipLaunchKernelGGL(k_srv_harvest_dep, dim3(nblocks((size_t)count * ntargets, 256)), dim3(256),
+                           0, st, s->g->n, (const int32_t *)(s->meta + o_col), count,
+                           (const int32_t *)s->src, d_targets, ntargets,
+                           (double *const *)(s->meta + o_ptr), (const int32_t *)s->tdist,
+                           (const double *)s->tsig, (const double *)s->zeta);
+    SHIP(hipGetLastError());
+    SHIP(hipStreamSynchronize(st));
+    release(s, h_columns, count);
+    return MFBC_OK;
+}
+
+}  // extern "C"

@@ -32,6 +32,7 @@ SIGNATURES = {
     "mfbc_backward_trace": ([_P, _P, _I32, _P, _P, _P, _P, _P, _P], ctypes.c_int),
     "mfbc_get_stats": ([_P, _P], ctypes.c_int),
     "mfbc_enable_timing": ([_P, ctypes.c_int], ctypes.c_int),
+    "mfbc_set_plan": ([_P, _I32, _I32, _I32, _I32], ctypes.c_int),
     "mfbc_graph_info": ([_P, _P, _P, _P], ctypes.c_int),
     "mfbc_bc_many": ([_I32, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
     "mfbc_last_error": ([], ctypes.c_char_p),
@@ -192,6 +193,10 @@ class DeviceGraph:
                                     _stream(t, stream))
         _check(rc)
         return out
+
+    def set_plan(self, run_arcs: int = 0, run_verts: int = 0, heavy: int = 0, slice: int = 0):
+        """Work decomposition of the products (0 = size-based default)."""
+        _check(load_library().mfbc_set_plan(self.handle, run_arcs, run_verts, heavy, slice))
 
     def enable_timing(self, on: bool = True):
         """Time every product kernel with HIP events on the call's stream."""

@@ -25,7 +25,8 @@ def test_library_exports_every_declared_symbol():
     assert len(names) >= 10
     for name in names:
         assert hasattr(lib, name), name
-    assert set(names) == set(mfbc.SIGNATURES)
+    from paper_1609_07008_amd import serve
+    assert set(names) == set(mfbc.SIGNATURES) | set(serve.SERVER_SIGNATURES)
 
 
 def test_library_is_built_for_gfx950():

@@ -1,0 +1,93 @@
+"""Served form: continuous batching of source columns over resident graphs.
+
+Every request's result is checked against the CPU oracle, and the same
+request served alone against it served in a mix with others (the bar of the
+served form: equal within the stated tolerance)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1609_07008_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    t = pytest.importorskip("torch")
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1609_07008_amd import mfbc, serve
+    mfbc.load_library()
+    graphs = [gg.rmat_graph(10, 8, 21, wrange=(1, 255)), gg.er_graph(700, 6, 22, (1, 50)),
+              gg.rmat_graph(9, 16, 23)]
+    dgs = [mfbc.DeviceGraph(g) for g in graphs]
+    yield t, mfbc, serve, graphs, dgs
+    for d in dgs:
+        d.close()
+
+
+def rel_close(got, want, tol, what=""):
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray(want, dtype=np.float64)
+    zero = want == 0
+    assert np.count_nonzero(got[zero]) == 0, f"{what}: zeros must be exact"
+    if (~zero).any():
+        err = np.abs(got[~zero] - want[~zero]) / np.abs(want[~zero])
+        assert err.max() <= tol, f"{what}: max rel err {err.max():.3e}"
+
+
+def reference(graphs, r):
+    g = graphs[r.graph]
+    if r.kind == "bc":
+        return oracle.brandes(g, r.sources, per_source=False)["lambda"]
+    d = oracle.brandes(g, r.sources)["delta"]
+    return d[:, r.targets]
+
+
+def test_served_results_match_oracle_and_alone(env):
+    t, mfbc, serve, graphs, dgs = env
+    reqs = serve.make_requests(graphs, 24, rate=1e9, seed=5, smin=3, smax=150)
+    eng = serve.ServeEngine(dgs, [128, 64, 192])
+    eng.run(reqs, realtime=False)
+    for r in reqs:
+        assert r.done >= 0
+        rel_close(r.out.cpu().numpy(), reference(graphs, r), 1e-10, f"request {r.rid} ({r.kind})")
+    # each request alone gives the same result as in the mix
+    for r in reqs[:8]:
+        alone = serve.Request(r.rid, r.graph, r.kind, r.sources, r.targets, 0.0)
+        eng.run([alone], realtime=False)
+        rel_close(alone.out.cpu().numpy(), r.out.cpu().numpy(), 1e-12, f"alone vs mix {r.rid}")
+    eng.close()
+
+
+def test_served_requests_wider_than_the_server(env):
+    """A request with more sources than columns is admitted piece by piece."""
+    t, mfbc, serve, graphs, dgs = env
+    g = graphs[0]
+    src = gg.pick_sources(g, 300, 8)
+    r = serve.Request(0, 0, "bc", src, None, 0.0)
+    eng = serve.ServeEngine(dgs[:1], [64])
+    eng.run([r], realtime=False)
+    rel_close(r.out.cpu().numpy(), oracle.brandes(g, src, per_source=False)["lambda"], 1e-10)
+    eng.close()
+
+
+def test_fifo_reference_schedule(env):
+    t, mfbc, serve, graphs, dgs = env
+    reqs = serve.make_requests(graphs, 6, rate=1e9, seed=9, smin=4, smax=40)
+    serve.run_fifo(dgs, reqs, batch=64, realtime=False)
+    for r in reqs:
+        rel_close(r.out.cpu().numpy(), reference(graphs, r), 1e-10, f"fifo {r.rid}")
+
+
+def test_server_rejects_misuse(env):
+    t, mfbc, serve, graphs, dgs = env
+    s = serve.ColumnServer(dgs[1], 64)
+    with pytest.raises(mfbc.MfbcError):
+        s.admit(np.arange(65, dtype=np.int32))            # more sources than columns
+    with pytest.raises(mfbc.MfbcError):
+        s.admit(np.array([graphs[1].n], dtype=np.int32))  # out of range
+    with pytest.raises(mfbc.MfbcError):
+        s.step_finish()                                   # nothing in flight
+    s.close()
