@@ -42,6 +42,11 @@ WORKLOADS = {
     # batched form: 256 ER / R-MAT graphs, n log-uniform in [200, 20000], average
     # degree uniform in [4, 64], weights 1..100, exact BC of every graph
     "batched256": dict(kind="many", count=256, seed0=1000, cpu_sample=48),
+    # served form: 8 resident weighted R-MAT graphs (scales 14..20 and a second
+    # 17), Poisson requests for BC contributions or dependencies of 16..1024
+    # sources, continuous batching of source columns vs one request at a time
+    "served8": dict(kind="serve", scales=(14, 15, 16, 17, 18, 19, 20, 17), seed0=2000,
+                    trace_seed=2100, width=256),
 }
 
 
@@ -173,6 +178,71 @@ def run_many(args, spec):
     print(json.dumps(line), flush=True)
 
 
+def run_serve(args, spec):
+    import numpy as np
+    import torch
+    from paper_1609_07008_amd import graphgen as gg
+    from paper_1609_07008_amd import mfbc, serve
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    gs = [gg.rmat_graph(sc, 16, spec["seed0"] + i, wrange=(1, 255))
+          for i, sc in enumerate(spec["scales"])]
+    dgs = [mfbc.DeviceGraph(g) for g in gs]
+    foot = sum(serve.footprint(d, spec["width"]) for d in dgs)
+    print(f"[bench] served: {len(gs)} graphs, server state {foot / 2**30:.1f} GiB, "
+          f"setup {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    nreq = args.requests
+
+    def trace(rate, seed):
+        return serve.make_requests(gs, nreq, rate, seed)
+
+    def work(reqs):
+        return sum(r.sources.size * gs[r.graph].m for r in reqs)
+
+    # saturation rate of the plain method: every request queued at time 0
+    sat = trace(1e9, spec["trace_seed"])
+    for r in sat:
+        r.arrival = 0.0
+    serve.run_fifo(dgs, sat[: min(40, nreq)], realtime=False)          # warm-up
+    t1 = time.perf_counter()
+    serve.run_fifo(dgs, sat, realtime=False)
+    rate_sat = nreq / (time.perf_counter() - t1)
+    print(f"[bench] plain method saturates at {rate_sat:.2f} requests/s", file=sys.stderr, flush=True)
+    eng = serve.ServeEngine(dgs, [spec["width"]] * len(dgs))
+    out = {}
+    for frac in (0.5, 0.9):
+        reqs = trace(frac * rate_sat, spec["trace_seed"] + int(frac * 10))
+        t1 = time.perf_counter()
+        eng.run(reqs)
+        el = time.perf_counter() - t1
+        res = {"served": dict(serve.latency_stats(reqs), teps=work(reqs) / el, wall_s=el)}
+        print(f"[bench] load {frac}: served p50/p99 {res['served']['p50_ms']:.1f}/"
+              f"{res['served']['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+        reqs2 = trace(frac * rate_sat, spec["trace_seed"] + int(frac * 10))
+        t1 = time.perf_counter()
+        serve.run_fifo(dgs, reqs2)
+        el2 = time.perf_counter() - t1
+        res["fifo"] = dict(serve.latency_stats(reqs2), teps=work(reqs2) / el2, wall_s=el2)
+        print(f"[bench] load {frac}: fifo p50/p99 {res['fifo']['p50_ms']:.1f}/"
+              f"{res['fifo']['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+        out[f"load_{frac}"] = res
+    eng.close()
+    main_res = out["load_0.9"]["served"]
+    line = {
+        "metric": "BC TEPS (sources x edges / s) at 1 GPU; serving p50/p99 latency",
+        "value": main_res["teps"], "unit": "TEPS", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": main_res["wall_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "served8", "graphs": [g.name for g in gs], "requests": nreq,
+                   "width": spec["width"], "saturation_rate_plain": rate_sat},
+        "serving": out, "roofline": None, "cpu_baseline": None,
+    }
+    for d in dgs:
+        d.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -186,6 +256,7 @@ def main():
                     help="only run a plain device-to-device copy of BYTES (calibrates the "
                          "HBM byte counters of rocprofv3) and exit")
     ap.add_argument("--tune", action="store_true", help="re-run the autotuner before timing")
+    ap.add_argument("--requests", type=int, default=400, help="served form: requests per trace")
     ap.add_argument("--block-threads", type=int, default=0, help="batched form: threads per workgroup")
     ap.add_argument("--blocks", type=int, default=0, help="batched form: persistent workgroups")
     args = ap.parse_args()
@@ -212,6 +283,9 @@ def main():
     spec = WORKLOADS[args.workload]
     if spec["kind"] == "many":
         run_many(args, spec)
+        return
+    if spec["kind"] == "serve":
+        run_serve(args, spec)
         return
     batch = args.batch or spec["batch"]
     torch.cuda.set_device(0)

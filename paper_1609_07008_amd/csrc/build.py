@@ -33,6 +33,10 @@ def _compile(src: str) -> str:
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
+    warn = [ln for ln in r.stderr.splitlines()
+            if "warning:" in ln and "packed-fp32-ops" not in ln]
+    if warn:
+        print(f"[build] {src}: " + "\n".join(warn), flush=True)
     return obj
 
 

@@ -228,7 +228,7 @@ void launch_fwd_init(mfbc_graph *g, int ncg, int nb, hipStream_t s) {
 void launch_fwd_product(mfbc_graph *g, int ncg, int j, bool trace, hipStream_t s,
                         hipEvent_t *ev) {
     FwdArgs a = fwd_args(g, ncg, j, trace);
-    if (ev) hipEventRecord(ev[0], s);
+    if (ev) (void)hipEventRecord(ev[0], s);
     const size_t waves = (size_t)a.ntasks * ncg;
     const int grid = blocks_for(waves, kWavesPerBlock, 0x7fffffff);
     switch (arc_mode(g->in)) {
@@ -236,13 +236,13 @@ void launch_fwd_product(mfbc_graph *g, int ncg, int j, bool trace, hipStream_t s
         case 1: hipLaunchKernelGGL(k_fwd_pull<1>, dim3(grid), dim3(kBlock), 0, s, a); break;
         default: hipLaunchKernelGGL(k_fwd_pull<2>, dim3(grid), dim3(kBlock), 0, s, a); break;
     }
-    if (ev) hipEventRecord(ev[1], s);
+    if (ev) (void)hipEventRecord(ev[1], s);
     const size_t mw = (size_t)a.nhubs * ncg;
     int mgrid = blocks_for(mw, kWavesPerBlock, 0x7fffffff);
     const int cgrid = blocks_for((size_t)a.nwords, kBlock, 1024);
     if (cgrid > mgrid) mgrid = cgrid;
     hipLaunchKernelGGL(k_fwd_merge, dim3(mgrid), dim3(kBlock), 0, s, a);
-    if (ev) hipEventRecord(ev[2], s);
+    if (ev) (void)hipEventRecord(ev[2], s);
 }
 
 static BwdArgs bwd_args(mfbc_graph *g, int ncg, int k) {
@@ -287,11 +287,11 @@ void launch_bwd_count(mfbc_graph *g, int ncg, hipStream_t s, hipEvent_t *ev) {
     // the counting product writes B_0 into buffer 0: clear its bitmap and
     // this product's counters first
     const int nwords = (g->n + 31) / 32;
-    hipMemsetAsync(ws.abits[0], 0, (size_t)nwords * ncg * 4, s);
-    hipMemsetAsync(ws.abits[1], 0, (size_t)nwords * ncg * 4, s);
-    hipMemsetAsync(ws.counters, 0, sizeof(unsigned long long) * kCounterRing * 4 * kCounterSlots, s);
+    (void)hipMemsetAsync(ws.abits[0], 0, (size_t)nwords * ncg * 4, s);
+    (void)hipMemsetAsync(ws.abits[1], 0, (size_t)nwords * ncg * 4, s);
+    (void)hipMemsetAsync(ws.counters, 0, sizeof(unsigned long long) * kCounterRing * 4 * kCounterSlots, s);
     BwdArgs a = bwd_args(g, ncg, 0);
-    if (ev) hipEventRecord(ev[0], s);
+    if (ev) (void)hipEventRecord(ev[0], s);
     const size_t waves = (size_t)a.ntasks * ncg;
     const int grid = blocks_for(waves, kWavesPerBlock, 0x7fffffff);
     switch (arc_mode(g->out)) {
@@ -304,14 +304,14 @@ void launch_bwd_count(mfbc_graph *g, int ncg, hipStream_t s, hipEvent_t *ev) {
     if (cgrid > mgrid) mgrid = cgrid;
     hipLaunchKernelGGL(k_bwd_count_merge, dim3(mgrid), dim3(kBlock), 0, s, a);
     if (ev) {
-        hipEventRecord(ev[1], s);
-        hipEventRecord(ev[2], s);
+        (void)hipEventRecord(ev[1], s);
+        (void)hipEventRecord(ev[2], s);
     }
 }
 
 void launch_bwd_product(mfbc_graph *g, int ncg, int k, hipStream_t s, hipEvent_t *ev) {
     BwdArgs a = bwd_args(g, ncg, k);
-    if (ev) hipEventRecord(ev[0], s);
+    if (ev) (void)hipEventRecord(ev[0], s);
     const size_t waves = (size_t)a.ntasks * ncg;
     const int grid = blocks_for(waves, kWavesPerBlock, 0x7fffffff);
     switch (arc_mode(g->out)) {
@@ -319,12 +319,12 @@ void launch_bwd_product(mfbc_graph *g, int ncg, int k, hipStream_t s, hipEvent_t
         case 1: hipLaunchKernelGGL(k_bwd_pull<1>, dim3(grid), dim3(kBlock), 0, s, a); break;
         default: hipLaunchKernelGGL(k_bwd_pull<2>, dim3(grid), dim3(kBlock), 0, s, a); break;
     }
-    if (ev) hipEventRecord(ev[1], s);
+    if (ev) (void)hipEventRecord(ev[1], s);
     int mgrid = blocks_for((size_t)a.nhubs * ncg, kWavesPerBlock, 0x7fffffff);
     const int cgrid = blocks_for((size_t)a.nwords, kBlock, 1024);
     if (cgrid > mgrid) mgrid = cgrid;
     hipLaunchKernelGGL(k_bwd_merge, dim3(mgrid), dim3(kBlock), 0, s, a);
-    if (ev) hipEventRecord(ev[2], s);
+    if (ev) (void)hipEventRecord(ev[2], s);
 }
 
 void launch_lambda_zero(mfbc_graph *g, int ncg, hipStream_t s) {

@@ -1,0 +1,131 @@
+"""The oracle's pins catch plausible mistakes (CPU only).
+
+Each test plants one mistake in a copy of the oracle -- a dropped term, a
+wrong comparison, a missing exclusion, a wrong monoid rule -- and checks that
+the brute-force pin used by tests/test_oracle.py rejects the mutant.  This is
+what makes the pins worth trusting: a pin that cannot tell a broken oracle
+from the real one proves nothing.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import brute, mfbc_ref
+from paper_1609_07008_amd import graphgen as gg
+
+ORACLE_C = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle",
+                        "brandes.c")
+
+GRAPHS = [gg.random_small_graph(8, 0.45, 4, (1, 2)), gg.random_small_graph(9, 0.4, 5, None),
+          gg.random_small_graph(10, 0.3, 7, (1, 5))]
+
+
+def brute_ref(g):
+    per, lam = brute.brute_bc(g, range(g.n))
+    dist = np.array([[(-1 if t is None else t) for t in p["tau"]] for p in per])
+    sigma = np.array([[float(x) for x in p["sigma"]] for p in per])
+    delta = np.array([[float(x) for x in p["delta"]] for p in per])
+    return dist, sigma, delta, np.array([float(x) for x in lam])
+
+
+def agrees(g, dist, sigma, delta, lam):
+    d0, s0, de0, l0 = brute_ref(g)
+    return (np.array_equal(dist, d0) and np.allclose(sigma, s0, rtol=1e-12, atol=0)
+            and np.allclose(delta, de0, rtol=1e-12, atol=1e-14)
+            and np.allclose(lam, l0, rtol=1e-12, atol=1e-14))
+
+
+def build_mutant(tmp_path, old, new):
+    src = open(ORACLE_C).read()
+    assert old in src, old
+    path = tmp_path / "mutant.c"
+    path.write_text(src.replace(old, new, 1))
+    lib = tmp_path / "libmutant.so"
+    subprocess.run(["gcc", "-O1", "-fopenmp", "-fPIC", "-shared", "-o", str(lib), str(path)],
+                   check=True, capture_output=True)
+    return ctypes.CDLL(str(lib))
+
+
+def run_c(lib, g):
+    n = g.n
+    P = ctypes.c_void_p
+    rp = np.ascontiguousarray(g.row_ptr, np.int64)
+    col = np.ascontiguousarray(g.col, np.int32)
+    w = None if g.w is None else np.ascontiguousarray(g.w, np.int32)
+    src = np.arange(n, dtype=np.int32)
+    lam = np.zeros(n)
+    dist = np.empty((n, n), np.int64)
+    sigma = np.empty((n, n))
+    delta = np.empty((n, n))
+    height = np.empty((n, n), np.int32)
+    f = lib.oracle_bc
+    f.argtypes = [ctypes.c_int32, P, P, P, P, ctypes.c_int64, P, P, P, P, P, ctypes.c_int32]
+    f.restype = ctypes.c_int
+    rc = f(n, rp.ctypes.data_as(P), col.ctypes.data_as(P),
+           None if w is None else w.ctypes.data_as(P), src.ctypes.data_as(P), n,
+           lam.ctypes.data_as(P), dist.ctypes.data_as(P), sigma.ctypes.data_as(P),
+           delta.ctypes.data_as(P), height.ctypes.data_as(P), 1)
+    assert rc == 0
+    return dist, sigma, delta, lam
+
+
+C_MUTATIONS = {
+    "dependency drops the 1": ("(1.0 + k->delta[x])", "(k->delta[x])"),
+    "relaxation uses <=": ("if (nd < k->dist[x]) {", "if (nd <= k->dist[x]) {"),
+    "source not excluded": ("if (v != s) my[v] += k.delta[v];", "my[v] += k.delta[v];"),
+    "bfs overwrites counts": ("if (k->dist[x] == dn) k->sigma[x] += k->sigma[v];",
+                              "if (k->dist[x] == dn) k->sigma[x] = k->sigma[v];"),
+    "ties not counted": ("} else if (nd == k->dist[x]) {\n                    k->sigma[x] += k->sigma[v];",
+                         "} else if (nd == k->dist[x]) {\n                    k->sigma[x] += 0.0;"),
+    "successor test off by one": ("k->dist[v] + wt == k->dist[x]", "k->dist[v] + wt + 1 == k->dist[x]"),
+}
+
+
+def test_unmutated_c_oracle_agrees(tmp_path):
+    lib = build_mutant(tmp_path, "int oracle_max_threads", "int oracle_max_threads")
+    for g in GRAPHS:
+        assert agrees(g, *run_c(lib, g))
+
+
+@pytest.mark.parametrize("name", sorted(C_MUTATIONS))
+def test_c_oracle_mutants_are_caught(tmp_path, name):
+    old, new = C_MUTATIONS[name]
+    lib = build_mutant(tmp_path, old, new)
+    assert not all(agrees(g, *run_c(lib, g)) for g in GRAPHS), f"pin missed mutant: {name}"
+
+
+def _ref_alg(g):
+    src = np.arange(g.n)
+    f = mfbc_ref.mfbf(g, src, trace=False)
+    b = mfbc_ref.mfbr(g, src, f["dist"], f["sigma"], trace=False)
+    dep = b["zeta"] * f["sigma"]
+    dep[src, src] = 0.0
+    return f["dist"], f["sigma"], dep, dep.sum(axis=0)
+
+
+def test_algorithm_mutants_are_caught(monkeypatch):
+    """Mistakes in the monoids of Algorithms 1-2 are caught by the same pin."""
+    for g in GRAPHS:
+        assert agrees(g, *_ref_alg(g))
+    orig_acc = mfbc_ref._multpath_accumulate
+    orig_cacc = mfbc_ref._centpath_accumulate
+
+    def no_tie_sum(Tw, Tm, Gw, Gm):               # multpath monoid without the tie rule
+        less = Gw < Tw
+        return np.minimum(Tw, Gw), np.where(less, Gm, Tm)
+
+    def min_instead_of_max(Zw, Zp, Zc, Cw, Cp, Cc):   # centpath monoid keeping the lighter
+        more = (Cw < Zw) & (Cw > -mfbc_ref.INF)
+        tie = (Cw == Zw) & (Cw > -mfbc_ref.INF)
+        return (np.where(more, Cw, Zw), np.where(more, Cp, np.where(tie, Zp + Cp, Zp)),
+                np.where(more, Cc, np.where(tie, Zc + Cc, Zc)))
+
+    for name, attr, fn in [("no tie sum", "_multpath_accumulate", no_tie_sum),
+                           ("min for max", "_centpath_accumulate", min_instead_of_max)]:
+        monkeypatch.setattr(mfbc_ref, attr, fn)
+        assert not all(agrees(g, *_ref_alg(g)) for g in GRAPHS), f"pin missed {name}"
+        monkeypatch.setattr(mfbc_ref, "_multpath_accumulate", orig_acc)
+        monkeypatch.setattr(mfbc_ref, "_centpath_accumulate", orig_cacc)
