@@ -67,6 +67,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     global _lib
     if _lib is not None:
         return _lib
+    try:
+        # load torch's HIP runtime first, so that the library binds to the same
+        # one (a second runtime in the process would not share devices/streams)
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is not built; run __graft_entry__.build()")
     lib = ctypes.CDLL(path)
