@@ -189,13 +189,8 @@ struct FwdArgs {
 
 // T := T (+) G at (v, cg); writes the next frontier row.  Returns the lane
 // mask of the frontier entries produced.
-// `td`: T's weight at (v, lane) if the caller has loaded it (any lane with a
-// candidate was loaded), or kLoadTd to load it here.
-constexpr int kLoadTd = -1;
-
 __device__ __forceinline__ uint64_t fwd_finalize(const FwdArgs &a, size_t cgv, int v, int bd,
-                                                 double bm, int tdin, int lane,
-                                                 unsigned long long &outs) {
+                                                 double bm, int lane, unsigned long long &outs) {
     const bool has = bd != kInf;
     uint64_t bits = 0;
     const uint64_t hm = ballot(has);
@@ -204,7 +199,7 @@ __device__ __forceinline__ uint64_t fwd_finalize(const FwdArgs &a, size_t cgv, i
         const size_t idx = (cgv + (size_t)v) * kWave + lane;
         bool keep = false;
         if (has) {
-            const int td = tdin == kLoadTd ? ld_nt(a.tdist + idx) : tdin;
+            const int td = ld_nt(a.tdist + idx);
             if (bd < td) {
                 st_nt(a.tdist + idx, bd);
                 st_nt(a.tsig + idx, bm);
@@ -238,9 +233,7 @@ constexpr int kFwdUnroll = 8;
 // One pull task of the forward product (see Task) for column group cg.
 // U: active arcs whose tuple loads are issued together.
 template <int AM, int U = kFwdUnroll>
-__device__ __forceinline__ void fwd_task(const FwdArgs &a, int cg, int t,
-                                         unsigned long long &produced,
-                                         unsigned long long &outs) {
+__device__ __forceinline__ void fwd_task(const FwdArgs &a, int cg, int t, unsigned long long &produced, unsigned long long &outs) {
     const int lane = threadIdx.x & (kWave - 1);
     uint64_t colany = 0;
     const Task *tp = a.tasks + t;
@@ -255,10 +248,6 @@ __device__ __forceinline__ void fwd_task(const FwdArgs &a, int cg, int t,
     int64_t vend = hub >= 0 ? e1 : a.rp[v0 + 1];
     int bd = kInf;
     double bm = 0.0;
-    // T's weight row of the current owner, loaded when its first candidate
-    // arrives so that the load overlaps the rest of its arcs
-    int td = kInf;
-    bool tpre = false;
     uint64_t run_act = 0;
     for (int64_t e = e0; e < e1; e += kWave) {
         const int64_t my = e + lane;
@@ -270,12 +259,26 @@ __device__ __forceinline__ void fwd_task(const FwdArgs &a, int cg, int t,
         }
         uint64_t am = ballot(act);
         while (am) {
-            // the next U active arcs (possibly of several owners), loads issued together
+            const int j0 = __ffsll((unsigned long long)am) - 1;
+            if (hub < 0) {
+                while (e + j0 >= vend) {
+                    const uint64_t b = fwd_finalize(a, cgv, v, bd, bm, lane, outs);
+                    produced += __popcll(b);
+                    colany |= b;
+                    if (b) run_act |= 1ull << (v - v0);
+                    ++v;
+                    vend = a.rp[v + 1];
+                    bd = kInf;
+                    bm = 0.0;
+                }
+            }
+            // up to U active arcs of the same owner, loads issued together
+            uint64_t cand = am & owner_mask(e, vend);
             int js[U];
 #pragma unroll
             for (int k = 0; k < U; k++) {
-                js[k] = am ? __ffsll((unsigned long long)am) - 1 : -1;
-                am &= am - 1;
+                js[k] = cand ? __ffsll((unsigned long long)cand) - 1 : -1;
+                cand &= cand - 1;
             }
             uint32_t tk[U];
             int uk[U], wk[U];
@@ -285,6 +288,7 @@ __device__ __forceinline__ void fwd_task(const FwdArgs &a, int cg, int t,
                 uk[k] = 0;
                 wk[k] = 0;
                 if (js[k] >= 0) {
+                    am &= ~(1ull << js[k]);
                     uk[k] = rdlane(u, js[k]);
                     wk[k] = AM ? rdlane(wt, js[k]) : 1;
                     tk[k] = Ft[(size_t)uk[k] * kWave + lane];
@@ -299,58 +303,29 @@ __device__ __forceinline__ void fwd_task(const FwdArgs &a, int cg, int t,
                     mk[k] = ms ? (double)ms : Fm[(size_t)uk[k] * kWave + lane];
                 }
             }
-            // combine in arc order, finishing each owner when its arcs end; a
-            // real loop (the finalize is emitted once) over register arrays that
-            // shift down by one each step, so that every index stays static
-#pragma unroll 1
-            for (int it = 0; it < U && js[0] >= 0; it++) {
-                if (hub < 0) {
-                    while (e + js[0] >= vend) {
-                        const uint64_t b = fwd_finalize(a, cgv, v, bd, bm, td, lane, outs);
-                        produced += __popcll(b);
-                        colany |= b;
-                        if (b) run_act |= 1ull << (v - v0);
-                        ++v;
-                        vend = a.rp[v + 1];
-                        bd = kInf;
-                        bm = 0.0;
-                        tpre = false;
-                    }
-                    if (!tpre) {
-                        td = ld_nt(a.tdist + (cgv + (size_t)v) * kWave + lane);
-                        tpre = true;
-                    }
-                }
-                if (tk[0] != kSent) {
-                    const int d = (int)(tk[0] >> a.mb) + wk[0];
+#pragma unroll
+            for (int k = 0; k < U; k++) {
+                if (tk[k] != kSent) {
+                    const int d = (int)(tk[k] >> a.mb) + wk[k];
                     if (d < bd) {
                         bd = d;
-                        bm = mk[0];
+                        bm = mk[k];
                     } else if (d == bd) {
-                        bm += mk[0];
+                        bm += mk[k];
                     }
                 }
-#pragma unroll
-                for (int q = 0; q + 1 < U; q++) {
-                    js[q] = js[q + 1];
-                    tk[q] = tk[q + 1];
-                    wk[q] = wk[q + 1];
-                    mk[q] = mk[q + 1];
-                }
-                js[U - 1] = -1;
             }
         }
     }
     if (hub < 0) {
         while (v < v1) {
-            const uint64_t b = fwd_finalize(a, cgv, v, bd, bm, td, lane, outs);
+            const uint64_t b = fwd_finalize(a, cgv, v, bd, bm, lane, outs);
             produced += __popcll(b);
             colany |= b;
             if (b) run_act |= 1ull << (v - v0);
             ++v;
             bd = kInf;
             bm = 0.0;
-            td = kInf;
         }
         if (lane == 0 && run_act) or_run_bits(a.abits_n + (size_t)cg * a.nwords, v0, run_act);
     } else {
@@ -384,7 +359,7 @@ __device__ __forceinline__ void fwd_hub(const FwdArgs &a, int cg, int h, unsigne
             bm += m;
         }
     }
-    const uint64_t b = fwd_finalize(a, cgv, v, bd, bm, kLoadTd, lane, outs);
+    const uint64_t b = fwd_finalize(a, cgv, v, bd, bm, lane, outs);
     produced += __popcll(b);
     colany |= b;
     if (b && lane == 0) atomicOr(a.abits_n + (size_t)cg * a.nwords + (v >> 5), 1u << (v & 31));
