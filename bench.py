@@ -218,7 +218,7 @@ def run_serve(args, spec):
         el = time.perf_counter() - t1
         res = {"served": dict(serve.latency_stats(reqs), teps=work(reqs) / el, wall_s=el)}
         print(f"[bench] load {frac}: served p50/p99 {res['served']['p50_ms']:.1f}/"
-              f"{res['served']['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+              f"{res['served']['p99_ms']:.1f} ms ({eng.steps} steps so far)", file=sys.stderr, flush=True)
         reqs2 = trace(frac * rate_sat, spec["trace_seed"] + int(frac * 10))
         t1 = time.perf_counter()
         serve.run_fifo(dgs, reqs2)

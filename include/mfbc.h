@@ -248,13 +248,17 @@ int mfbc_bc_many(int32_t n_graphs, mfbc_graph *const *graphs,
  * Served form: continuous batching of source columns over a resident graph.
  *
  * A server owns `width` source columns (a positive multiple of 64) of one
- * graph; each column holds one source and moves through its own phase
- * (forward loop, counting product, backward loop, done).  A step advances
- * every active column by one product of its phase; a column depends only on
- * its own column of the frontier (the products act column by column,
- * Section 3), so new sources join free columns between steps while other
- * columns are mid-loop.  Finished columns are harvested into the caller's
- * buffers and become free.  All calls on one server must come from one
+ * graph; each column holds one source and moves through the phases forward
+ * loop, counting product, backward loop, done.  A step advances every active
+ * column by one product of its phase; a column depends only on its own
+ * column of the frontier (the products act column by column, Section 3), so
+ * new sources start between steps while other columns are mid-loop.  The
+ * unit of admission is a group of 64 columns: a group takes new sources
+ * (from any number of requests) only while all of its columns are free or
+ * until the step after its first admission is launched, and it leaves the
+ * forward loop when all of its lanes have, so each group follows the plain
+ * path's per-batch schedule.  Finished columns are harvested into the
+ * caller's buffers and become free.  All calls on one server must come from one
  * thread, in the order admit / step_launch / step_finish / harvest; the
  * stream argument must be the same for a step's launch and finish.
  */
@@ -267,18 +271,24 @@ int mfbc_server_footprint(const mfbc_graph *g, int32_t width, int64_t *bytes);
 int mfbc_server_create(mfbc_graph *g, int32_t width, mfbc_server **out);
 int mfbc_server_free(mfbc_server *s);
 
-/* Number of free columns / columns in a forward, counting or backward phase
- * (>= 0), or a negative status. */
+/* Number of columns that can be admitted now (free columns of groups that
+ * admit) / columns in a forward, counting or backward phase (>= 0), or a
+ * negative status. */
 int mfbc_server_free_columns(const mfbc_server *s);
 int mfbc_server_active_columns(const mfbc_server *s);
 
-/* Place `count` sources (host, in [0,n)) into free columns; h_columns[i]
- * receives the column of source i.  EINVAL if fewer columns are free. */
+/* Place `count` sources (host, in [0,n)) into admissible columns (groups
+ * already opened since the last launch first); h_columns[i] receives the
+ * column of source i.  EINVAL if fewer columns can be admitted. */
 int mfbc_server_admit(mfbc_server *s, const int32_t *h_sources, int32_t count,
                       int32_t *h_columns, void *hip_stream);
 
 /* Enqueue one step on the stream (does not wait). */
 int mfbc_server_step_launch(mfbc_server *s, void *hip_stream);
+
+/* 1 if no step is in flight or the launched one has completed, 0 if it is
+ * still running, or a negative status (does not wait). */
+int mfbc_server_step_query(mfbc_server *s);
 
 /* Wait for the step and update the column phases; h_done[width] receives
  * the columns that finished in this step, *h_ndone their number. */

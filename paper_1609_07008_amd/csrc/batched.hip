@@ -141,6 +141,7 @@ __global__ __launch_bounds__(kManyMaxThreads) void k_bc_many(ManyArgs m) {
         a.nhubs = gd.nhubs_in;
         a.nslots = gd.nslots_in;
         a.ncg = 1;
+        a.ncg_all = 1;
         a.n = n;
         a.nwords = nw;
         a.mb = gd.mb;
@@ -185,6 +186,7 @@ __global__ __launch_bounds__(kManyMaxThreads) void k_bc_many(ManyArgs m) {
         c.nhubs = gd.nhubs_out;
         c.nslots = gd.nslots_out;
         c.ncg = 1;
+        c.ncg_all = 1;
         c.n = n;
         c.nwords = nw;
         c.rp = gd.rp_out;

@@ -181,6 +181,7 @@ static FwdArgs fwd_args(mfbc_graph *g, int ncg, int j, bool trace) {
     a.nhubs = g->plan_in.nhubs;
     a.nslots = g->plan_in.nslots;
     a.ncg = ncg;
+    a.ncg_all = ncg;
     a.n = g->n;
     a.j = j;
     a.nwords = (g->n + 31) / 32;
@@ -232,16 +233,16 @@ void launch_fwd_product(mfbc_graph *g, int ncg, int j, bool trace, hipStream_t s
     const size_t waves = (size_t)a.ntasks * ncg;
     const int grid = blocks_for(waves, kWavesPerBlock, 0x7fffffff);
     switch (arc_mode(g->in)) {
-        case 0: hipLaunchKernelGGL(k_fwd_pull<0>, dim3(grid), dim3(kBlock), 0, s, a); break;
-        case 1: hipLaunchKernelGGL(k_fwd_pull<1>, dim3(grid), dim3(kBlock), 0, s, a); break;
-        default: hipLaunchKernelGGL(k_fwd_pull<2>, dim3(grid), dim3(kBlock), 0, s, a); break;
+        case 0: hipLaunchKernelGGL((k_fwd_pull<0, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
+        case 1: hipLaunchKernelGGL((k_fwd_pull<1, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_fwd_pull<2, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
     }
     if (ev) (void)hipEventRecord(ev[1], s);
     const size_t mw = (size_t)a.nhubs * ncg;
     int mgrid = blocks_for(mw, kWavesPerBlock, 0x7fffffff);
     const int cgrid = blocks_for((size_t)a.nwords, kBlock, 1024);
     if (cgrid > mgrid) mgrid = cgrid;
-    hipLaunchKernelGGL(k_fwd_merge, dim3(mgrid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_fwd_merge<false>, dim3(mgrid), dim3(kBlock), 0, s, a);
     if (ev) (void)hipEventRecord(ev[2], s);
 }
 
@@ -257,6 +258,7 @@ static BwdArgs bwd_args(mfbc_graph *g, int ncg, int k) {
     a.nhubs = g->plan_out.nhubs;
     a.nslots = g->plan_out.nslots;
     a.ncg = ncg;
+    a.ncg_all = ncg;
     a.n = g->n;
     a.k = k;
     a.rp = g->out.rp;
@@ -295,14 +297,14 @@ void launch_bwd_count(mfbc_graph *g, int ncg, hipStream_t s, hipEvent_t *ev) {
     const size_t waves = (size_t)a.ntasks * ncg;
     const int grid = blocks_for(waves, kWavesPerBlock, 0x7fffffff);
     switch (arc_mode(g->out)) {
-        case 0: hipLaunchKernelGGL(k_bwd_count<0>, dim3(grid), dim3(kBlock), 0, s, a); break;
-        case 1: hipLaunchKernelGGL(k_bwd_count<1>, dim3(grid), dim3(kBlock), 0, s, a); break;
-        default: hipLaunchKernelGGL(k_bwd_count<2>, dim3(grid), dim3(kBlock), 0, s, a); break;
+        case 0: hipLaunchKernelGGL((k_bwd_count<0, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
+        case 1: hipLaunchKernelGGL((k_bwd_count<1, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_bwd_count<2, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
     }
     int mgrid = blocks_for((size_t)a.nhubs * ncg, kWavesPerBlock, 0x7fffffff);
     const int cgrid = blocks_for((size_t)a.nwords, kBlock, 1024);
     if (cgrid > mgrid) mgrid = cgrid;
-    hipLaunchKernelGGL(k_bwd_count_merge, dim3(mgrid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_bwd_count_merge<false>, dim3(mgrid), dim3(kBlock), 0, s, a);
     if (ev) {
         (void)hipEventRecord(ev[1], s);
         (void)hipEventRecord(ev[2], s);
@@ -315,15 +317,15 @@ void launch_bwd_product(mfbc_graph *g, int ncg, int k, hipStream_t s, hipEvent_t
     const size_t waves = (size_t)a.ntasks * ncg;
     const int grid = blocks_for(waves, kWavesPerBlock, 0x7fffffff);
     switch (arc_mode(g->out)) {
-        case 0: hipLaunchKernelGGL(k_bwd_pull<0>, dim3(grid), dim3(kBlock), 0, s, a); break;
-        case 1: hipLaunchKernelGGL(k_bwd_pull<1>, dim3(grid), dim3(kBlock), 0, s, a); break;
-        default: hipLaunchKernelGGL(k_bwd_pull<2>, dim3(grid), dim3(kBlock), 0, s, a); break;
+        case 0: hipLaunchKernelGGL((k_bwd_pull<0, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
+        case 1: hipLaunchKernelGGL((k_bwd_pull<1, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_bwd_pull<2, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
     }
     if (ev) (void)hipEventRecord(ev[1], s);
     int mgrid = blocks_for((size_t)a.nhubs * ncg, kWavesPerBlock, 0x7fffffff);
     const int cgrid = blocks_for((size_t)a.nwords, kBlock, 1024);
     if (cgrid > mgrid) mgrid = cgrid;
-    hipLaunchKernelGGL(k_bwd_merge, dim3(mgrid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_bwd_merge<false>, dim3(mgrid), dim3(kBlock), 0, s, a);
     if (ev) (void)hipEventRecord(ev[2], s);
 }
 

@@ -184,13 +184,20 @@ struct FwdArgs {
     uint64_t *fmask;           // trace (nullable)
     uint32_t *clear_bits;      // merge: bitmaps to clear (F_{j-1}'s), ncg planes
     unsigned long long *clear_ctr;  // merge: counter slots of product j+1
-    unsigned long long *colmask;    // nullable: [32][ncg] columns that produced entries
+    unsigned long long *colmask;    // nullable: [32][ncg_all] columns that produced entries
+    const int32_t *cglist;     // nullable: the ncg column groups of this launch (else 0..ncg-1)
+    int ncg_all;               // column groups of the state (strides of colmask, bitmap planes)
 };
 
 // T := T (+) G at (v, cg); writes the next frontier row.  Returns the lane
 // mask of the frontier entries produced.
+// `tdin`: T's weight at (v, lane) if the caller loaded it already (it must
+// have, for every owner that received a candidate), else kLoadTd.
+constexpr int kLoadTd = -1;
+
 __device__ __forceinline__ uint64_t fwd_finalize(const FwdArgs &a, size_t cgv, int v, int bd,
-                                                 double bm, int lane, unsigned long long &outs) {
+                                                 double bm, int tdin, int lane,
+                                                 unsigned long long &outs) {
     const bool has = bd != kInf;
     uint64_t bits = 0;
     const uint64_t hm = ballot(has);
@@ -199,7 +206,7 @@ __device__ __forceinline__ uint64_t fwd_finalize(const FwdArgs &a, size_t cgv, i
         const size_t idx = (cgv + (size_t)v) * kWave + lane;
         bool keep = false;
         if (has) {
-            const int td = ld_nt(a.tdist + idx);
+            const int td = tdin == kLoadTd ? ld_nt(a.tdist + idx) : tdin;
             if (bd < td) {
                 st_nt(a.tdist + idx, bd);
                 st_nt(a.tsig + idx, bm);
@@ -248,21 +255,26 @@ __device__ __forceinline__ void fwd_task(const FwdArgs &a, int cg, int t, unsign
     int64_t vend = hub >= 0 ? e1 : a.rp[v0 + 1];
     int bd = kInf;
     double bm = 0.0;
+    // T's weight row of the current owner, loaded together with the tuple
+    // loads of its first active arcs (one round trip fewer per owner)
+    int td = kInf;
+    bool tpre = false;
     uint64_t run_act = 0;
+    // the arc words of the next 64-arc chunk are loaded while the current
+    // chunk is processed
+    int un = 0, wn = 1;
+    if (e0 + lane < e1) load_arc<AM>(a.arcs, e0 + lane, un, wn);
     for (int64_t e = e0; e < e1; e += kWave) {
         const int64_t my = e + lane;
-        int u = 0, wt = 1;
-        bool act = false;
-        if (my < e1) {
-            load_arc<AM>(a.arcs, my, u, wt);
-            act = (Ab[u >> 5] >> (u & 31)) & 1u;
-        }
+        const int u = un, wt = wn;
+        const bool act = my < e1 && ((Ab[u >> 5] >> (u & 31)) & 1u);
+        if (my + kWave < e1) load_arc<AM>(a.arcs, my + kWave, un, wn);
         uint64_t am = ballot(act);
         while (am) {
             const int j0 = __ffsll((unsigned long long)am) - 1;
             if (hub < 0) {
                 while (e + j0 >= vend) {
-                    const uint64_t b = fwd_finalize(a, cgv, v, bd, bm, lane, outs);
+                    const uint64_t b = fwd_finalize(a, cgv, v, bd, bm, td, lane, outs);
                     produced += __popcll(b);
                     colany |= b;
                     if (b) run_act |= 1ull << (v - v0);
@@ -270,6 +282,11 @@ __device__ __forceinline__ void fwd_task(const FwdArgs &a, int cg, int t, unsign
                     vend = a.rp[v + 1];
                     bd = kInf;
                     bm = 0.0;
+                    tpre = false;
+                }
+                if (!tpre) {
+                    td = ld_nt(a.tdist + (cgv + (size_t)v) * kWave + lane);
+                    tpre = true;
                 }
             }
             // up to U active arcs of the same owner, loads issued together
@@ -319,13 +336,14 @@ __device__ __forceinline__ void fwd_task(const FwdArgs &a, int cg, int t, unsign
     }
     if (hub < 0) {
         while (v < v1) {
-            const uint64_t b = fwd_finalize(a, cgv, v, bd, bm, lane, outs);
+            const uint64_t b = fwd_finalize(a, cgv, v, bd, bm, td, lane, outs);
             produced += __popcll(b);
             colany |= b;
             if (b) run_act |= 1ull << (v - v0);
             ++v;
             bd = kInf;
             bm = 0.0;
+            td = kInf;
         }
         if (lane == 0 && run_act) or_run_bits(a.abits_n + (size_t)cg * a.nwords, v0, run_act);
     } else {
@@ -333,7 +351,7 @@ __device__ __forceinline__ void fwd_task(const FwdArgs &a, int cg, int t, unsign
         a.pd[pidx] = bd;
         a.pm[pidx] = bm;
     }
-    flush_colmask(a.colmask, a.ncg, cg, colany);
+    flush_colmask(a.colmask, a.ncg_all, cg, colany);
 }
 
 // Combine the slices of split row h (fixed slice order) and finish it.
@@ -359,11 +377,11 @@ __device__ __forceinline__ void fwd_hub(const FwdArgs &a, int cg, int h, unsigne
             bm += m;
         }
     }
-    const uint64_t b = fwd_finalize(a, cgv, v, bd, bm, lane, outs);
+    const uint64_t b = fwd_finalize(a, cgv, v, bd, bm, kLoadTd, lane, outs);
     produced += __popcll(b);
     colany |= b;
     if (b && lane == 0) atomicOr(a.abits_n + (size_t)cg * a.nwords + (v >> 5), 1u << (v & 31));
-    flush_colmask(a.colmask, a.ncg, cg, colany);
+    flush_colmask(a.colmask, a.ncg_all, cg, colany);
 }
 
 // ===================================================================== backward
@@ -390,9 +408,11 @@ struct BwdArgs {
     unsigned long long *ctr;
     uint32_t *clear_bits;      // ncg planes
     unsigned long long *clear_ctr;
-    unsigned long long *colmask;    // nullable: [32][ncg] columns that produced entries
+    unsigned long long *colmask;    // nullable: [32][ncg_all] columns that produced entries
     const uint64_t *cmask;     // counting product: nullable per-group lane mask of the
                                // columns to count (others are left untouched)
+    const int32_t *cglist;     // nullable: the ncg column groups of this launch (else 0..ncg-1)
+    int ncg_all;               // column groups of the state (strides of colmask, bitmap planes)
 };
 
 // Per-vertex finish of the counting product: counters, leaves, zeta = 0.
@@ -473,7 +493,7 @@ __device__ __forceinline__ void count_task(const BwdArgs &a, int cg, int t, unsi
     }
     if (hub < 0 && lane == 0 && run_act)
         or_run_bits(a.abits_n + (size_t)cg * a.nwords, v0, run_act);
-    flush_colmask(a.colmask, a.ncg, cg, colany);
+    flush_colmask(a.colmask, a.ncg_all, cg, colany);
 }
 
 __device__ __forceinline__ void count_hub(const BwdArgs &a, int cg, int h, unsigned long long &produced) {
@@ -489,7 +509,7 @@ __device__ __forceinline__ void count_hub(const BwdArgs &a, int cg, int h, unsig
     produced += __popcll(b);
     colany |= b;
     if (b && lane == 0) atomicOr(a.abits_n + (size_t)cg * a.nwords + (x >> 5), 1u << (x & 31));
-    flush_colmask(a.colmask, a.ncg, cg, colany);
+    flush_colmask(a.colmask, a.ncg_all, cg, colany);
 }
 
 // Finish (s, x) after a backward product contributed `acc` from `got`
@@ -644,7 +664,7 @@ __device__ __forceinline__ void bwd_task(const BwdArgs &a, int cg, int t, unsign
         a.pd[pidx] = got;
         a.pm[pidx] = acc;
     }
-    flush_colmask(a.colmask, a.ncg, cg, colany);
+    flush_colmask(a.colmask, a.ncg_all, cg, colany);
 }
 
 __device__ __forceinline__ void bwd_hub(const BwdArgs &a, int cg, int h, unsigned long long &produced, unsigned long long &outs) {
@@ -665,71 +685,90 @@ __device__ __forceinline__ void bwd_hub(const BwdArgs &a, int cg, int h, unsigne
     produced += __popcll(b);
     colany |= b;
     if (b && lane == 0) atomicOr(a.abits_n + (size_t)cg * a.nwords + (x >> 5), 1u << (x & 31));
-    flush_colmask(a.colmask, a.ncg, cg, colany);
+    flush_colmask(a.colmask, a.ncg_all, cg, colany);
 }
 
 // ===================================================================== grid kernels
-template <int AM>
-__global__ __launch_bounds__(kBlock) void k_fwd_pull(FwdArgs a) {
+// The pull kernels are latency bound, so waves in flight matter most.  A SIMD
+// holds 800 scalar registers, handed out in granules, so eight waves per SIMD
+// fit only when a wave takes at most 96 of them in all (VCC included); the
+// budget below (which yields that total) makes the compiler keep to it,
+// spilling the odd uniform value to a vector lane, where it would otherwise
+// use a few more and silently drop to seven waves.
+#define MFBC_PULL_SGPRS __attribute__((amdgpu_num_sgpr(98)))
+
+// L: the launch covers the ncg column groups listed in a.cglist (served form)
+// rather than groups 0..ncg-1; a separate instantiation keeps the plain path's
+// code free of the list.
+template <bool L>
+__device__ __forceinline__ int pick_cg(const int32_t *cglist, int cg) {
+    if constexpr (L) return cglist[cg];
+    return cg;
+}
+
+template <int AM, bool L>
+__global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_fwd_pull(FwdArgs a) {
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const int cg = wid / a.ntasks;                       // column-group major
     unsigned long long produced = 0, outs = 0;
-    if (cg < a.ncg) fwd_task<AM>(a, cg, wid - cg * a.ntasks, produced, outs);
+    if (cg < a.ncg) fwd_task<AM>(a, pick_cg<L>(a.cglist, cg), wid - cg * a.ntasks, produced, outs);
     flush_counts(produced, outs, 0, 0, a.ctr);
 }
 
-[[maybe_unused]] __global__ __launch_bounds__(kBlock) void k_fwd_merge(FwdArgs a) {
+template <bool L>
+__global__ __launch_bounds__(kBlock) void k_fwd_merge(FwdArgs a) {
     const int gtid = blockIdx.x * kBlock + threadIdx.x;
     unsigned long long nv = 0, na = 0;
-    clear_and_count(a.clear_bits, a.nwords, a.ncg, a.rp, nv, na);
+    clear_and_count(a.clear_bits, a.nwords, a.ncg_all, a.rp, nv, na);
     if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     unsigned long long produced = 0, outs = 0;
     const int cg = a.nhubs ? wid / a.nhubs : a.ncg;
-    if (cg < a.ncg) fwd_hub(a, cg, wid - cg * a.nhubs, produced, outs);
+    if (cg < a.ncg) fwd_hub(a, pick_cg<L>(a.cglist, cg), wid - cg * a.nhubs, produced, outs);
     flush_counts(produced, outs, nv, na, a.ctr);
 }
 
-template <int AM>
-__global__ __launch_bounds__(kBlock) void k_bwd_count(BwdArgs a) {
+template <int AM, bool L>
+__global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_bwd_count(BwdArgs a) {
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const int cg = wid / a.ntasks;                       // column-group major
     unsigned long long produced = 0;
-    if (cg < a.ncg) count_task<AM>(a, cg, wid - cg * a.ntasks, produced);
+    if (cg < a.ncg) count_task<AM>(a, pick_cg<L>(a.cglist, cg), wid - cg * a.ntasks, produced);
     flush_counts(produced, 0, 0, 0, a.ctr);
 }
 
-[[maybe_unused]] __global__ __launch_bounds__(kBlock) void k_bwd_count_merge(BwdArgs a) {
+template <bool L>
+__global__ __launch_bounds__(kBlock) void k_bwd_count_merge(BwdArgs a) {
     const int gtid = blockIdx.x * kBlock + threadIdx.x;
     if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     unsigned long long produced = 0;
     const int cg = a.nhubs ? wid / a.nhubs : a.ncg;
-    if (cg < a.ncg) count_hub(a, cg, wid - cg * a.nhubs, produced);
+    if (cg < a.ncg) count_hub(a, pick_cg<L>(a.cglist, cg), wid - cg * a.nhubs, produced);
     flush_counts(produced, 0, 0, 0, a.ctr);
 }
 
-template <int AM>
-__global__ __launch_bounds__(kBlock) void k_bwd_pull(BwdArgs a) {
+template <int AM, bool L>
+__global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_bwd_pull(BwdArgs a) {
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const int cg = wid / a.ntasks;                       // column-group major
     unsigned long long produced = 0, outs = 0;
-    if (cg < a.ncg) bwd_task<AM>(a, cg, wid - cg * a.ntasks, produced, outs);
+    if (cg < a.ncg) bwd_task<AM>(a, pick_cg<L>(a.cglist, cg), wid - cg * a.ntasks, produced, outs);
     flush_counts(produced, outs, 0, 0, a.ctr);
 }
 
-[[maybe_unused]] __global__ __launch_bounds__(kBlock) void k_bwd_merge(BwdArgs a) {
+template <bool L>
+__global__ __launch_bounds__(kBlock) void k_bwd_merge(BwdArgs a) {
     const int gtid = blockIdx.x * kBlock + threadIdx.x;
     unsigned long long nv = 0, na = 0;
-    clear_and_count(a.clear_bits, a.nwords, a.ncg, a.rp, nv, na);
+    clear_and_count(a.clear_bits, a.nwords, a.ncg_all, a.rp, nv, na);
     if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     unsigned long long produced = 0, outs = 0;
     const int cg = a.nhubs ? wid / a.nhubs : a.ncg;
-    if (cg < a.ncg) bwd_hub(a, cg, wid - cg * a.nhubs, produced, outs);
+    if (cg < a.ncg) bwd_hub(a, pick_cg<L>(a.cglist, cg), wid - cg * a.nhubs, produced, outs);
     flush_counts(produced, outs, nv, na, a.ctr);
 }
-
 
 }  // namespace
 }  // namespace mfbc

@@ -1,17 +1,27 @@
 // Served form: continuous batching of source columns over a resident graph.
 //
 // A server owns `width` source columns (a multiple of 64) of one graph.  Each
-// column holds one source of some request and moves through its own phase:
-// FWD (Algorithm 1's loop), CNT (the counting product of Algorithm 2), BWD
+// column holds one source of some request and moves through the phases FWD
+// (Algorithm 1's loop), CNT (the counting product of Algorithm 2), BWD
 // (Algorithm 2's loop), DONE (ready to harvest), FREE.  Column s of every
 // product depends only on column s of its frontier (the product's output
 // column is a function of the same input column, Section 3), so columns can
 // join and leave at product boundaries while other columns are mid-loop:
 // one step runs at most one forward product (every FWD column), one backward
-// product (every BWD column) and one counting product (the columns that just
-// finished their forward loop), with the same kernels as the plain path.
-// The forward and backward states have separate buffers here, because
-// columns of one 64-column group can be in different phases.
+// product (every BWD column) and one counting product (every CNT column),
+// each launched only over the 64-column groups that have columns in it, with
+// the same kernels as the plain path.
+//
+// The unit of admission is the 64-column group (a cohort): a product's cost
+// per group is set by the union of its lanes' frontiers and its full pass
+// over the arcs in the counting product, whatever the number of lanes, so a
+// group admits new sources only when all of its columns are free (from
+// several requests at once, until the next step is launched), leaves the
+// forward loop when every one of its lanes has an empty frontier, and runs
+// one counting product -- exactly the per-batch schedule of the plain path,
+// while different groups sit in different phases.  Columns that finish the
+// backward loop become DONE one by one.  The forward and backward states
+// have separate buffers, since one step holds groups in both loops.
 #include <algorithm>
 #include <cstring>
 #include <string>
@@ -131,13 +141,18 @@ struct mfbc_server {
     unsigned long long *colmask = nullptr;  // [3][32][ncg]: forward, counting, backward
     uint64_t *cmask = nullptr;              // [ncg] counting mask
     uint64_t *newmask = nullptr;            // [ncg] columns being admitted
+    int32_t *cglists = nullptr;             // [3][ncg]: groups with forward / backward /
+                                            // counting columns this step
     int32_t *flags = nullptr;
     char *meta = nullptr;                   // staging for harvest/admit lists
     size_t meta_bytes = 0;
     unsigned long long *h_colmask = nullptr;  // pinned
+    hipEvent_t done_ev = nullptr;             // recorded at the end of a launched step
     std::vector<int32_t> h_src;
     std::vector<uint8_t> phase;
     std::vector<uint8_t> ran_f, ran_b, ran_c; // columns taking part in the launched step
+    std::vector<uint8_t> open;                // [ncg] groups admitting since the last launch
+    int32_t *h_stage = nullptr;               // pinned: [3][ncg] group lists, then [ncg] masks
     bool launched = false, any_f = false, any_b = false, any_c = false;
 };
 
@@ -182,10 +197,15 @@ void free_server(mfbc_server *s) {
     sfree(s->colmask);
     sfree(s->cmask);
     sfree(s->newmask);
+    sfree(s->cglists);
     sfree(s->flags);
     sfree(s->meta);
     if (s->h_colmask) (void)hipHostFree(s->h_colmask);
     s->h_colmask = nullptr;
+    if (s->h_stage) (void)hipHostFree(s->h_stage);
+    s->h_stage = nullptr;
+    if (s->done_ev) (void)hipEventDestroy(s->done_ev);
+    s->done_ev = nullptr;
 }
 
 ArcSrc srv_arc_src(const Csr &c) {
@@ -254,9 +274,13 @@ int mfbc_server_create(mfbc_graph *g, int32_t width, mfbc_server **out) {
         salloc(&s->abb[0], ncg * s->nwords) || salloc(&s->abb[1], ncg * s->nwords) ||
         salloc(&s->pd, slots) || salloc(&s->pm, slots) || salloc(&s->src, (size_t)width) ||
         salloc(&s->ctr, (size_t)8 * kCounterSlots) || salloc(&s->colmask, 3 * 32 * ncg) ||
-        salloc(&s->cmask, ncg) || salloc(&s->newmask, ncg) || salloc(&s->flags, 4))
+        salloc(&s->cmask, ncg) || salloc(&s->newmask, ncg) || salloc(&s->cglists, 3 * ncg) ||
+        salloc(&s->flags, 4))
         rc = MFBC_ENOMEM;
     if (!rc && hipHostMalloc((void **)&s->h_colmask, 3 * 32 * ncg * 8) != hipSuccess) rc = MFBC_ENOMEM;
+    if (!rc && hipHostMalloc((void **)&s->h_stage, 3 * ncg * 4 + ncg * 8) != hipSuccess) rc = MFBC_ENOMEM;
+    if (!rc && hipEventCreateWithFlags(&s->done_ev, hipEventDisableTiming) != hipSuccess)
+        rc = MFBC_EDEVICE;
     if (!rc) {
         // every column free: counters off, no frontier anywhere
         hipStream_t st = nullptr;
@@ -283,6 +307,7 @@ int mfbc_server_create(mfbc_graph *g, int32_t width, mfbc_server **out) {
     s->ran_f.assign((size_t)width, 0);
     s->ran_b.assign((size_t)width, 0);
     s->ran_c.assign((size_t)width, 0);
+    s->open.assign(ncg, 0);
     *out = s;
     return MFBC_OK;
 }
@@ -295,10 +320,22 @@ int mfbc_server_free(mfbc_server *s) {
     return MFBC_OK;
 }
 
+// A group admits sources if it was opened since the last launch or if every
+// one of its columns is free.
+static bool group_admits(const mfbc_server *s, int cg) {
+    if (s->open[(size_t)cg]) return true;
+    for (int l = 0; l < kWave; l++)
+        if (s->phase[(size_t)cg * kWave + l] != kFree) return false;
+    return true;
+}
+
 int mfbc_server_free_columns(const mfbc_server *s) {
     if (!s) return sfail(MFBC_EINVAL, "NULL server");
     int f = 0;
-    for (uint8_t p : s->phase) f += p == kFree;
+    for (int cg = 0; cg < s->ncg; cg++) {
+        if (!group_admits(s, cg)) continue;
+        for (int l = 0; l < kWave; l++) f += s->phase[(size_t)cg * kWave + l] == kFree;
+    }
     return f;
 }
 
@@ -316,9 +353,15 @@ int mfbc_server_admit(mfbc_server *s, const int32_t *h_sources, int32_t count, i
     if (count <= 0) return MFBC_OK;
     for (int i = 0; i < count; i++)
         if (h_sources[i] < 0 || h_sources[i] >= s->g->n) return sfail(MFBC_EINVAL, "source out of range");
+    // fill the groups opened since the last launch first, then whole free groups
     std::vector<int32_t> cols;
-    for (int c = 0; c < s->width && (int)cols.size() < count; c++)
-        if (s->phase[(size_t)c] == kFree) cols.push_back(c);
+    for (int pass = 0; pass < 2 && (int)cols.size() < count; pass++)
+        for (int cg = 0; cg < s->ncg && (int)cols.size() < count; cg++) {
+            if (pass == 0 ? !s->open[(size_t)cg] : (s->open[(size_t)cg] || !group_admits(s, cg)))
+                continue;
+            for (int l = 0; l < kWave && (int)cols.size() < count; l++)
+                if (s->phase[(size_t)cg * kWave + l] == kFree) cols.push_back(cg * kWave + l);
+        }
     if ((int)cols.size() < count) return sfail(MFBC_EINVAL, "not enough free columns");
     hipStream_t st = (hipStream_t)hip_stream;
     int prev = -1;
@@ -330,6 +373,7 @@ int mfbc_server_admit(mfbc_server *s, const int32_t *h_sources, int32_t count, i
         h_columns[i] = c;
         s->h_src[(size_t)c] = h_sources[i];
         s->phase[(size_t)c] = kFwd;
+        s->open[(size_t)(c / 64)] = 1;
         nm[(size_t)(c / 64)] |= 1ull << (c % 64);
     }
     int rc = stage(s, (size_t)count * 4 + 256);
@@ -362,7 +406,10 @@ int mfbc_server_step_launch(mfbc_server *s, void *hip_stream) {
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(g->device);
     s->any_f = s->any_b = s->any_c = false;
-    std::vector<uint64_t> cm((size_t)s->ncg, 0);
+    std::fill(s->open.begin(), s->open.end(), 0);   // admitted groups are now running
+    uint64_t *cm = (uint64_t *)(s->h_stage + 3 * (size_t)s->ncg);
+    std::fill(cm, cm + s->ncg, 0ull);
+    std::vector<uint8_t> gf((size_t)s->ncg, 0), gb((size_t)s->ncg, 0), gc((size_t)s->ncg, 0);
     for (int c = 0; c < s->width; c++) {
         const uint8_t p = s->phase[(size_t)c];
         s->ran_f[(size_t)c] = p == kFwd;
@@ -370,12 +417,25 @@ int mfbc_server_step_launch(mfbc_server *s, void *hip_stream) {
         s->ran_c[(size_t)c] = p == kCnt;
         s->any_f |= p == kFwd;
         s->any_b |= p == kBwd;
+        if (p == kFwd) gf[(size_t)(c / 64)] = 1;
+        if (p == kBwd) gb[(size_t)(c / 64)] = 1;
         if (p == kCnt) {
             s->any_c = true;
+            gc[(size_t)(c / 64)] = 1;
             cm[(size_t)(c / 64)] |= 1ull << (c % 64);
         }
     }
     const size_t ncg = (size_t)s->ncg;
+    // each product runs only over the column groups that have columns in its
+    // phase (a product's cost is per group, whatever the number of columns)
+    int32_t *lists = s->h_stage;
+    int nf = 0, nbk = 0, nc = 0;
+    for (size_t g2 = 0; g2 < ncg; g2++) {
+        if (gf[g2]) lists[(size_t)nf++] = (int32_t)g2;
+        if (gb[g2]) lists[ncg + (size_t)nbk++] = (int32_t)g2;
+        if (gc[g2]) lists[2 * ncg + (size_t)nc++] = (int32_t)g2;
+    }
+    SHIP(hipMemcpyAsync(s->cglists, lists, 3 * ncg * 4, hipMemcpyHostToDevice, st));
     SHIP(hipMemsetAsync(s->colmask, 0, 3 * 32 * ncg * 8, st));
     const int nw = s->nwords;
     if (s->any_f) {
@@ -387,7 +447,9 @@ int mfbc_server_step_launch(mfbc_server *s, void *hip_stream) {
         a.ntasks = g->plan_in.ntasks;
         a.nhubs = g->plan_in.nhubs;
         a.nslots = g->plan_in.nslots;
-        a.ncg = s->ncg;
+        a.ncg = nf;
+        a.ncg_all = s->ncg;
+        a.cglist = s->cglists;
         a.n = g->n;
         a.j = ++s->kfwd;
         a.nwords = nw;
@@ -409,15 +471,15 @@ int mfbc_server_step_launch(mfbc_server *s, void *hip_stream) {
         a.clear_bits = s->abf[b];
         a.clear_ctr = s->ctr + 4 * kCounterSlots;   // second block of 4 x 32 slots
         a.colmask = s->colmask;
-        const int grid = nblocks((size_t)a.ntasks * ncg, kWavesPerBlock, 0x7fffffff);
+        const int grid = nblocks((size_t)a.ntasks * nf, kWavesPerBlock, 0x7fffffff);
         switch (srv_mode(g->in)) {
-            case 0: hipLaunchKernelGGL(k_fwd_pull<0>, dim3(grid), dim3(kBlock), 0, st, a); break;
-            case 1: hipLaunchKernelGGL(k_fwd_pull<1>, dim3(grid), dim3(kBlock), 0, st, a); break;
-            default: hipLaunchKernelGGL(k_fwd_pull<2>, dim3(grid), dim3(kBlock), 0, st, a); break;
+            case 0: hipLaunchKernelGGL((k_fwd_pull<0, true>), dim3(grid), dim3(kBlock), 0, st, a); break;
+            case 1: hipLaunchKernelGGL((k_fwd_pull<1, true>), dim3(grid), dim3(kBlock), 0, st, a); break;
+            default: hipLaunchKernelGGL((k_fwd_pull<2, true>), dim3(grid), dim3(kBlock), 0, st, a); break;
         }
-        const int mgrid = std::max(nblocks((size_t)a.nhubs * ncg, kWavesPerBlock, 0x7fffffff),
+        const int mgrid = std::max(nblocks((size_t)a.nhubs * nf, kWavesPerBlock, 0x7fffffff),
                                    nblocks((size_t)nw, kBlock, 1024));
-        hipLaunchKernelGGL(k_fwd_merge, dim3(mgrid), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL(k_fwd_merge<true>, dim3(mgrid), dim3(kBlock), 0, st, a);
         s->cur_f ^= 1;
     }
     BwdArgs c{};
@@ -426,7 +488,7 @@ int mfbc_server_step_launch(mfbc_server *s, void *hip_stream) {
     c.ntasks = g->plan_out.ntasks;
     c.nhubs = g->plan_out.nhubs;
     c.nslots = g->plan_out.nslots;
-    c.ncg = s->ncg;
+    c.ncg_all = s->ncg;
     c.n = g->n;
     c.nwords = nw;
     c.rp = g->out.rp;
@@ -455,21 +517,23 @@ int mfbc_server_step_launch(mfbc_server *s, void *hip_stream) {
         c.clear_bits = s->abb[b];
         c.colmask = s->colmask + 2 * 32 * ncg;
         c.cmask = nullptr;
-        const int grid = nblocks((size_t)c.ntasks * ncg, kWavesPerBlock, 0x7fffffff);
+        c.ncg = nbk;
+        c.cglist = s->cglists + ncg;
+        const int grid = nblocks((size_t)c.ntasks * nbk, kWavesPerBlock, 0x7fffffff);
         switch (mode) {
-            case 0: hipLaunchKernelGGL(k_bwd_pull<0>, dim3(grid), dim3(kBlock), 0, st, c); break;
-            case 1: hipLaunchKernelGGL(k_bwd_pull<1>, dim3(grid), dim3(kBlock), 0, st, c); break;
-            default: hipLaunchKernelGGL(k_bwd_pull<2>, dim3(grid), dim3(kBlock), 0, st, c); break;
+            case 0: hipLaunchKernelGGL((k_bwd_pull<0, true>), dim3(grid), dim3(kBlock), 0, st, c); break;
+            case 1: hipLaunchKernelGGL((k_bwd_pull<1, true>), dim3(grid), dim3(kBlock), 0, st, c); break;
+            default: hipLaunchKernelGGL((k_bwd_pull<2, true>), dim3(grid), dim3(kBlock), 0, st, c); break;
         }
-        const int mgrid = std::max(nblocks((size_t)c.nhubs * ncg, kWavesPerBlock, 0x7fffffff),
+        const int mgrid = std::max(nblocks((size_t)c.nhubs * nbk, kWavesPerBlock, 0x7fffffff),
                                    nblocks((size_t)nw, kBlock, 1024));
-        hipLaunchKernelGGL(k_bwd_merge, dim3(mgrid), dim3(kBlock), 0, st, c);
+        hipLaunchKernelGGL(k_bwd_merge<true>, dim3(mgrid), dim3(kBlock), 0, st, c);
         s->cur_b ^= 1;
     }
     if (s->any_c) {
         // counting product of the columns whose forward loop just ended; their
         // first backward frontier joins the buffer the next backward product reads
-        SHIP(hipMemcpyAsync(s->cmask, cm.data(), ncg * 8, hipMemcpyHostToDevice, st));
+        SHIP(hipMemcpyAsync(s->cmask, cm, ncg * 8, hipMemcpyHostToDevice, st));
         c.k = 0;
         c.abits_n = s->abb[s->cur_b];
         c.fbits_n = s->bb[s->cur_b];
@@ -477,20 +541,32 @@ int mfbc_server_step_launch(mfbc_server *s, void *hip_stream) {
         c.fbits = s->bb[s->cur_b ^ 1];
         c.colmask = s->colmask + 32 * ncg;
         c.cmask = s->cmask;
-        const int grid = nblocks((size_t)c.ntasks * ncg, kWavesPerBlock, 0x7fffffff);
+        c.ncg = nc;
+        c.cglist = s->cglists + 2 * ncg;
+        const int grid = nblocks((size_t)c.ntasks * nc, kWavesPerBlock, 0x7fffffff);
         switch (mode) {
-            case 0: hipLaunchKernelGGL(k_bwd_count<0>, dim3(grid), dim3(kBlock), 0, st, c); break;
-            case 1: hipLaunchKernelGGL(k_bwd_count<1>, dim3(grid), dim3(kBlock), 0, st, c); break;
-            default: hipLaunchKernelGGL(k_bwd_count<2>, dim3(grid), dim3(kBlock), 0, st, c); break;
+            case 0: hipLaunchKernelGGL((k_bwd_count<0, true>), dim3(grid), dim3(kBlock), 0, st, c); break;
+            case 1: hipLaunchKernelGGL((k_bwd_count<1, true>), dim3(grid), dim3(kBlock), 0, st, c); break;
+            default: hipLaunchKernelGGL((k_bwd_count<2, true>), dim3(grid), dim3(kBlock), 0, st, c); break;
         }
-        const int mgrid = nblocks((size_t)c.nhubs * ncg, kWavesPerBlock, 0x7fffffff);
-        hipLaunchKernelGGL(k_bwd_count_merge, dim3(mgrid), dim3(kBlock), 0, st, c);
+        const int mgrid = nblocks((size_t)c.nhubs * nc, kWavesPerBlock, 0x7fffffff);
+        hipLaunchKernelGGL(k_bwd_count_merge<true>, dim3(mgrid), dim3(kBlock), 0, st, c);
     }
     SHIP(hipGetLastError());
     SHIP(hipMemcpyAsync(s->h_colmask, s->colmask, 3 * 32 * ncg * 8, hipMemcpyDeviceToHost, st));
+    SHIP(hipEventRecord(s->done_ev, st));
     s->launched = true;
     if (prev >= 0) (void)hipSetDevice(prev);
     return MFBC_OK;
+}
+
+int mfbc_server_step_query(mfbc_server *s) {
+    if (!s) return sfail(MFBC_EINVAL, "NULL server");
+    if (!s->launched) return 1;
+    const hipError_t e = hipEventQuery(s->done_ev);
+    if (e == hipSuccess) return 1;
+    if (e == hipErrorNotReady) return 0;
+    return sfail(MFBC_EDEVICE, std::string("hipEventQuery: ") + hipGetErrorString(e));
 }
 
 int mfbc_server_step_finish(mfbc_server *s, int32_t *h_done, int32_t *h_ndone, void *hip_stream) {
@@ -508,11 +584,12 @@ int mfbc_server_step_finish(mfbc_server *s, int32_t *h_done, int32_t *h_ndone, v
         }
     int nd = 0;
     for (int c = 0; c < s->width; c++) {
-        const bool bit_f = (mf[(size_t)(c / 64)] >> (c % 64)) & 1ull;
+        // a group leaves the forward loop when none of its lanes produced
+        const bool grp_f = mf[(size_t)(c / 64)] != 0ull;
         const bool bit_c = (mc[(size_t)(c / 64)] >> (c % 64)) & 1ull;
         const bool bit_b = (mb[(size_t)(c / 64)] >> (c % 64)) & 1ull;
         uint8_t &p = s->phase[(size_t)c];
-        if (s->ran_f[(size_t)c] && p == kFwd && !bit_f) p = kCnt;
+        if (s->ran_f[(size_t)c] && p == kFwd && !grp_f) p = kCnt;
         else if (s->ran_c[(size_t)c] && p == kCnt) p = bit_c ? kBwd : kDone;
         else if (s->ran_b[(size_t)c] && p == kBwd && !bit_b) p = kDone;
         if (p == kDone && (s->ran_b[(size_t)c] || s->ran_c[(size_t)c])) h_done[nd++] = c;

@@ -4,12 +4,13 @@ Requests ask for the betweenness contribution of a source set S on one graph
 (``kind="bc"``: lambda_S(v) = sum_{s in S} delta(s, v), f64[n]) or for the
 dependencies of S at a few target vertices (``kind="dep"``: delta(s, t),
 f64[|S|][T]).  Every resident graph has a column server (``mfbc_server_*`` in
-``include/mfbc.h``): its columns move independently through the forward
-loop, the counting product and the backward loop, so the sources of a request
-that arrives while others are running are placed into columns as they free
-up and share every product with them.  Admission is by device memory: the
-servers' widths are chosen so that their footprints fit a budget; requests
-then wait in a FIFO per graph for free columns.
+``include/mfbc.h``): its 64-column groups move independently through the
+forward loop, the counting product and the backward loop, so the sources of
+requests that arrive while others are running fill a group as soon as one is
+free (several small requests share one group) and share every launch with
+the groups already running.  Admission is by device memory: the servers'
+widths are chosen so that their footprints fit a budget; requests then wait
+in a FIFO per graph for a free group.
 
 The loop is host code (Python) around the C ABI; all product work runs in the
 library's HIP kernels.  ``run_fifo`` is the reference schedule: one request
@@ -38,6 +39,7 @@ SERVER_SIGNATURES = {
     "mfbc_server_active_columns": ([_P], ctypes.c_int),
     "mfbc_server_admit": ([_P, _P, _I32, _P, _P], ctypes.c_int),
     "mfbc_server_step_launch": ([_P, _P], ctypes.c_int),
+    "mfbc_server_step_query": ([_P], ctypes.c_int),
     "mfbc_server_step_finish": ([_P, _P, _P, _P], ctypes.c_int),
     "mfbc_server_harvest_bc": ([_P, _P, _I32, _P, _P], ctypes.c_int),
     "mfbc_server_harvest_dep": ([_P, _P, _I32, _P, _I32, _P, _P], ctypes.c_int),
@@ -73,6 +75,7 @@ class ColumnServer:
         h = ctypes.c_void_p()
         _m._check(_lib().mfbc_server_create(dg.handle, width, ctypes.byref(h)))
         self.h = h
+        self.launched = False
         self._done = np.zeros(width, dtype=np.int32)
 
     def _s(self):
@@ -110,26 +113,46 @@ class ColumnServer:
 
     def step_launch(self):
         _m._check(_lib().mfbc_server_step_launch(self.h, self._s()))
+        self.launched = True
+
+    def ready(self) -> bool:
+        r = _lib().mfbc_server_step_query(self.h)
+        if r < 0:
+            _m._check(r)
+        return r == 1
 
     def step_finish(self) -> np.ndarray:
+        self.launched = False
         nd = ctypes.c_int32(0)
         _m._check(_lib().mfbc_server_step_finish(self.h, self._done.ctypes.data_as(_P),
                                                  ctypes.byref(nd), self._s()))
         return self._done[:nd.value].copy()
 
+    def _order_after_caller(self):
+        # destination buffers are produced (zeroed) on the caller's stream
+        self.stream.wait_stream(self.torch.cuda.current_stream())
+
+    def _order_before_caller(self):
+        # ... and consumed there once harvested
+        self.torch.cuda.current_stream().wait_stream(self.stream)
+
     def harvest_bc(self, cols, dests):
         cols = np.ascontiguousarray(cols, dtype=np.int32)
         ptrs = (ctypes.c_void_p * len(dests))(*[d.data_ptr() for d in dests])
+        self._order_after_caller()
         _m._check(_lib().mfbc_server_harvest_bc(self.h, cols.ctypes.data_as(_P), cols.size,
                                                 ctypes.cast(ptrs, _P), self._s()))
+        self._order_before_caller()
 
     def harvest_dep(self, cols, targets, outs):
         cols = np.ascontiguousarray(cols, dtype=np.int32)
         ptrs = (ctypes.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
+        self._order_after_caller()
         _m._check(_lib().mfbc_server_harvest_dep(self.h, cols.ctypes.data_as(_P), cols.size,
                                                  ctypes.c_void_p(targets.data_ptr()),
                                                  targets.numel(), ctypes.cast(ptrs, _P),
                                                  self._s()))
+        self._order_before_caller()
 
 
 @dataclass
@@ -172,7 +195,13 @@ class ServeEngine:
             r._targets = t.as_tensor(np.ascontiguousarray(r.targets, dtype=np.int32), device="cuda")
 
     def run(self, requests: List[Request], realtime: bool = True, on_step=None):
-        """Serve `requests` (arrival times in seconds); returns them with `done` set."""
+        """Serve `requests` (arrival times in seconds); returns them with `done` set.
+
+        Each graph's server advances on its own: whenever its step has
+        completed, finished columns are harvested, queued sources take the
+        free columns and the next step is launched -- a small graph never
+        waits for a step of a large one.
+        """
         t = self.torch
         pending = sorted(requests, key=lambda r: r.arrival)
         nxt = 0
@@ -182,16 +211,21 @@ class ServeEngine:
         t.cuda.synchronize()
         t0 = time.perf_counter()
         while left:
-            now = time.perf_counter() - t0
-            if not realtime:
-                now = float("inf")
+            now = time.perf_counter() - t0 if realtime else float("inf")
             while nxt < len(pending) and pending[nxt].arrival <= now:
                 r = pending[nxt]
                 self._alloc(r)
                 queues[r.graph].append(r)
                 nxt += 1
-            # place queued sources into free columns, oldest request first
+            busy = False
             for gi, srv in enumerate(self.servers):
+                if srv.launched:
+                    if not srv.ready():
+                        busy = True
+                        continue
+                    done = srv.step_finish()
+                    if done.size:
+                        left -= self._harvest(srv, gi, done, owner, t0)
                 q = queues[gi]
                 free = srv.free_columns()
                 while q and free:
@@ -205,43 +239,41 @@ class ServeEngine:
                     free -= k
                     if r.placed == r.sources.size:
                         q.popleft()
-            active = [s for s in self.servers if s.active_columns() > 0]
-            if not active:
-                if nxt < len(pending):
-                    wait = pending[nxt].arrival - (time.perf_counter() - t0)
-                    if wait > 0:
-                        time.sleep(min(wait, 0.002))
-                continue
-            for s in active:
-                s.step_launch()
-            self.steps += 1
-            for s in active:
-                gi = self.servers.index(s)
-                done = s.step_finish()
-                if done.size == 0:
-                    continue
-                by_req = {}
-                for c in done:
-                    r = owner[gi].pop(int(c))
-                    by_req.setdefault(id(r), (r, []))[1].append(int(c))
-                bc_cols, bc_dest = [], []
-                for r, cols in by_req.values():
-                    if r.kind == "bc":
-                        bc_cols += cols
-                        bc_dest += [r.out] * len(cols)
-                    else:
-                        s.harvest_dep(cols, r._targets, [r.out[r.cols[c]] for c in cols])
-                    r.harvested += len(cols)
-                if bc_cols:
-                    s.harvest_bc(bc_cols, bc_dest)
-                tnow = time.perf_counter() - t0
-                for r, cols in by_req.values():
-                    if r.harvested == r.sources.size:
-                        r.done = tnow
-                        left -= 1
+                if srv.active_columns() > 0:
+                    srv.step_launch()
+                    self.steps += 1
+                    busy = True
             if on_step is not None:
                 on_step(self)
+            if not busy and nxt < len(pending):
+                wait = pending[nxt].arrival - (time.perf_counter() - t0)
+                if wait > 0:
+                    time.sleep(min(wait, 0.002))
         return requests
+
+    def _harvest(self, srv, gi, done, owner, t0) -> int:
+        """Harvest finished columns; returns the number of requests completed."""
+        by_req = {}
+        for c in done:
+            r = owner[gi].pop(int(c))
+            by_req.setdefault(id(r), (r, []))[1].append(int(c))
+        bc_cols, bc_dest = [], []
+        for r, cols in by_req.values():
+            if r.kind == "bc":
+                bc_cols += cols
+                bc_dest += [r.out] * len(cols)
+            else:
+                srv.harvest_dep(cols, r._targets, [r.out[r.cols[c]] for c in cols])
+            r.harvested += len(cols)
+        if bc_cols:
+            srv.harvest_bc(bc_cols, bc_dest)
+        tnow = time.perf_counter() - t0
+        finished = 0
+        for r, cols in by_req.values():
+            if r.harvested == r.sources.size:
+                r.done = tnow
+                finished += 1
+        return finished
 
 
 def run_fifo(dgraphs, requests: List[Request], batch: int = 256, realtime: bool = True):

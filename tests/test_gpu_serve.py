@@ -91,3 +91,46 @@ def test_server_rejects_misuse(env):
     with pytest.raises(mfbc.MfbcError):
         s.step_finish()                                   # nothing in flight
     s.close()
+
+
+def test_cohort_admission(env):
+    """Sources join a 64-column group only until its first step is launched;
+    a running group takes none, a free group next to it does, and both give
+    the oracle's results."""
+    t, mfbc, serve, graphs, dgs = env
+    g = graphs[1]
+    s = serve.ColumnServer(dgs[1], 128)
+    a_src = gg.pick_sources(g, 10, 31)
+    b_src = gg.pick_sources(g, 64, 32)
+    assert s.free_columns() == 128
+    ca = s.admit(a_src[:4])
+    ca = np.concatenate([ca, s.admit(a_src[4:])])          # same group, before the launch
+    assert np.all(ca // 64 == ca[0] // 64)
+    assert s.free_columns() == 128 - 10
+    s.step_launch()
+    done = list(s.step_finish())
+    assert s.free_columns() == 64                           # the running group is closed
+    with pytest.raises(mfbc.MfbcError):
+        s.admit(b_src[:1].repeat(65))
+    cb = s.admit(b_src)                                     # the other group, mid-loop of the first
+    assert np.all(cb // 64 != ca[0] // 64)
+    out_a = t.zeros(g.n, dtype=t.float64, device="cuda")
+    out_b = t.zeros(g.n, dtype=t.float64, device="cuda")
+    owner = {int(c): out_a for c in ca}
+    owner.update({int(c): out_b for c in cb})
+    left = set(owner)
+    for _ in range(10 * g.n):
+        fin = [c for c in done if c in left]
+        if fin:
+            s.harvest_bc(fin, [owner[c] for c in fin])
+            left -= set(fin)
+        if not left:
+            break
+        s.step_launch()
+        done = list(s.step_finish())
+    assert not left
+    t.cuda.synchronize()
+    rel_close(out_a.cpu().numpy(), oracle.brandes(g, a_src, per_source=False)["lambda"], 1e-10, "a")
+    rel_close(out_b.cpu().numpy(), oracle.brandes(g, b_src, per_source=False)["lambda"], 1e-10, "b")
+    assert s.free_columns() == 128
+    s.close()
