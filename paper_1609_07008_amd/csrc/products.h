@@ -235,11 +235,22 @@ __device__ __forceinline__ uint64_t fwd_finalize(const FwdArgs &a, size_t cgv, i
     return bits;
 }
 
-constexpr int kFwdUnroll = 8;
+// Active arcs per batch and whether a batch's escaped multiplicities are
+// read together up front: with weights drawn from a wide range escapes are
+// rare and are read lazily, only where they count (leaving registers for a
+// larger batch); unweighted graphs tie often and escape often.
+template <int AM> constexpr int kFwdBatch = AM == 0 ? 4 : 6;
+template <int AM> constexpr bool kFwdEscBatch = AM == 0;
 
 // One pull task of the forward product (see Task) for column group cg.
-// U: active arcs whose tuple loads are issued together.
-template <int AM, int U = kFwdUnroll>
+//
+// The arcs of the task are read 64 at a time; the active ones (source row in
+// the frontier of some lane) are taken U at a time in arc order, whatever
+// rows they belong to, and their tuple loads -- plus the T row of every
+// owner that starts in the batch -- are issued together, so one memory round
+// trip serves several short rows.  The batch is then folded in arc order,
+// each owner being finished when the next arc belongs to a later one.
+template <int AM, int U = kFwdBatch<AM>>
 __device__ __forceinline__ void fwd_task(const FwdArgs &a, int cg, int t, unsigned long long &produced, unsigned long long &outs) {
     const int lane = threadIdx.x & (kWave - 1);
     uint64_t colany = 0;
@@ -249,17 +260,23 @@ __device__ __forceinline__ void fwd_task(const FwdArgs &a, int cg, int t, unsign
     const size_t cgv = (size_t)cg * (size_t)a.n;
     const uint32_t *Ft = a.ftup + cgv * kWave;
     const double *Fm = a.fsig + cgv * kWave;
+    const int32_t *Td = a.tdist + (cgv + (size_t)v0) * kWave + lane;
     const uint32_t *Ab = a.abits + (size_t)cg * a.nwords;
     const uint32_t mmask = (1u << a.mb) - 1u;
-    int v = v0;
-    int64_t vend = hub >= 0 ? e1 : a.rp[v0 + 1];
-    int bd = kInf;
+    // end of each owner's arcs, one owner per lane (a run has at most 64
+    // rows); the owner of arc p is the number of rows ending at or before p.
+    // A slice of a hub row has the one owner.
+    const int64_t rend = (hub < 0 && v0 + lane < v1) ? a.rp[v0 + lane + 1] : INT64_MAX;
+    int cur = -1;            // owner (offset from v0) of the open accumulation
+    int bd = kInf, td = kInf;
     double bm = 0.0;
-    // T's weight row of the current owner, loaded together with the tuple
-    // loads of its first active arcs (one round trip fewer per owner)
-    int td = kInf;
-    bool tpre = false;
     uint64_t run_act = 0;
+    auto close = [&](int o) {
+        const uint64_t b = fwd_finalize(a, cgv, v0 + o, bd, bm, td, lane, outs);
+        produced += __popcll(b);
+        colany |= b;
+        if (b) run_act |= 1ull << o;
+    };
     // the arc words of the next 64-arc chunk are loaded while the current
     // chunk is processed
     int un = 0, wn = 1;
@@ -271,80 +288,71 @@ __device__ __forceinline__ void fwd_task(const FwdArgs &a, int cg, int t, unsign
         if (my + kWave < e1) load_arc<AM>(a.arcs, my + kWave, un, wn);
         uint64_t am = ballot(act);
         while (am) {
-            const int j0 = __ffsll((unsigned long long)am) - 1;
-            if (hub < 0) {
-                while (e + j0 >= vend) {
-                    const uint64_t b = fwd_finalize(a, cgv, v, bd, bm, td, lane, outs);
-                    produced += __popcll(b);
-                    colany |= b;
-                    if (b) run_act |= 1ull << (v - v0);
-                    ++v;
-                    vend = a.rp[v + 1];
-                    bd = kInf;
-                    bm = 0.0;
-                    tpre = false;
-                }
-                if (!tpre) {
-                    td = ld_nt(a.tdist + (cgv + (size_t)v) * kWave + lane);
-                    tpre = true;
-                }
-            }
-            // up to U active arcs of the same owner, loads issued together
-            uint64_t cand = am & owner_mask(e, vend);
-            int js[U];
-#pragma unroll
-            for (int k = 0; k < U; k++) {
-                js[k] = cand ? __ffsll((unsigned long long)cand) - 1 : -1;
-                cand &= cand - 1;
-            }
+            int ow[U], wk[U], uk[U], tn[U];
             uint32_t tk[U];
-            int uk[U], wk[U];
+            int prev = cur;
 #pragma unroll
             for (int k = 0; k < U; k++) {
-                tk[k] = kSent;
+                const int j = am ? __ffsll((unsigned long long)am) - 1 : -1;
+                am &= am - 1;
+                ow[k] = -1;
                 uk[k] = 0;
                 wk[k] = 0;
-                if (js[k] >= 0) {
-                    am &= ~(1ull << js[k]);
-                    uk[k] = rdlane(u, js[k]);
-                    wk[k] = AM ? rdlane(wt, js[k]) : 1;
+                tk[k] = kSent;
+                tn[k] = kInf;
+                if (j >= 0) {
+                    uk[k] = rdlane(u, j);
+                    wk[k] = AM ? rdlane(wt, j) : 1;
                     tk[k] = Ft[(size_t)uk[k] * kWave + lane];
+                    ow[k] = __popcll(ballot(rend <= e + j));
+                    if (hub < 0 && ow[k] != prev) tn[k] = ld_nt(Td + (size_t)ow[k] * kWave);
+                    prev = ow[k];
                 }
             }
-            double mk[U];
+            // escaped multiplicities of the batch, read together (rare when
+            // weights are drawn from a wide range; common in unweighted graphs)
+            double em[U];
 #pragma unroll
-            for (int k = 0; k < U; k++) {
-                mk[k] = 0.0;
-                if (tk[k] != kSent) {
-                    const uint32_t ms = tk[k] & mmask;
-                    mk[k] = ms ? (double)ms : Fm[(size_t)uk[k] * kWave + lane];
+            for (int k = 0; k < U; k++) em[k] = 0.0;
+            if constexpr (kFwdEscBatch<AM>) {
+                bool esc = false;
+#pragma unroll
+                for (int k = 0; k < U; k++) esc |= tk[k] != kSent && (tk[k] & mmask) == 0u;
+                if (ballot(esc)) {
+#pragma unroll
+                    for (int k = 0; k < U; k++)
+                        if (tk[k] != kSent && (tk[k] & mmask) == 0u)
+                            em[k] = Fm[(size_t)uk[k] * kWave + lane];
                 }
             }
 #pragma unroll
             for (int k = 0; k < U; k++) {
-                if (tk[k] != kSent) {
+                if (ow[k] >= 0) {
+                    if (ow[k] != cur) {
+                        if (cur >= 0 && hub < 0) close(cur);
+                        cur = ow[k];
+                        bd = kInf;
+                        bm = 0.0;
+                        td = tn[k];
+                    }
                     const int d = (int)(tk[k] >> a.mb) + wk[k];
-                    if (d < bd) {
-                        bd = d;
-                        bm = mk[k];
-                    } else if (d == bd) {
-                        bm += mk[k];
+                    if (tk[k] != kSent && d <= bd) {
+                        const uint32_t ms = tk[k] & mmask;
+                        double m = (double)ms;
+                        if (!ms) m = kFwdEscBatch<AM> ? em[k] : Fm[(size_t)uk[k] * kWave + lane];
+                        if (d < bd) {
+                            bd = d;
+                            bm = m;
+                        } else {
+                            bm += m;
+                        }
                     }
                 }
             }
         }
     }
     if (hub < 0) {
-        while (v < v1) {
-            const uint64_t b = fwd_finalize(a, cgv, v, bd, bm, td, lane, outs);
-            produced += __popcll(b);
-            colany |= b;
-            if (b) run_act |= 1ull << (v - v0);
-            ++v;
-            bd = kInf;
-            bm = 0.0;
-            td = kInf;
-        }
+        if (cur >= 0) close(cur);
         if (lane == 0 && run_act) or_run_bits(a.abits_n + (size_t)cg * a.nwords, v0, run_act);
     } else {
         const size_t pidx = ((size_t)cg * a.nslots + part) * kWave + lane;
