@@ -199,7 +199,8 @@ typedef struct mfbc_stats {
  * tuning knob; results do not depend on it).  Light rows are grouped into
  * runs of at most run_verts (1..64) rows and about run_arcs arcs; rows with
  * more than `heavy` arcs are cut into slices of `slice` arcs, merged in slice
- * order.  Any argument <= 0 restores the size-based default for that knob.
+ * order.  Any argument <= 0 restores the size-based default for that knob;
+ * run_arcs, heavy and slice above 2^24 are rejected (EINVAL).
  */
 int mfbc_set_plan(mfbc_graph *g, int32_t run_arcs, int32_t run_verts, int32_t heavy,
                   int32_t slice);

@@ -555,6 +555,9 @@ int mfbc_set_plan(mfbc_graph *g, int32_t run_arcs, int32_t run_verts, int32_t he
                   int32_t slice) {
     if (!g) return fail(MFBC_EINVAL, "graph handle is NULL");
     if (run_verts > 64) return fail(MFBC_EINVAL, "run_verts must be <= 64");
+    // a run's arcs are addressed with 32-bit offsets in the kernels
+    if (run_arcs > (1 << 24) || heavy > (1 << 24) || slice > (1 << 24))
+        return fail(MFBC_EINVAL, "run_arcs, heavy and slice must be <= 2^24");
     DeviceGuard dg(g->device);
     TaskParams p = default_params(g->n, g->arcs);
     if (run_arcs > 0) p.run_arcs = run_arcs;

@@ -256,3 +256,32 @@ def test_errors_are_reported(torch, mfbc, dgraphs):
     # the handle still works after rejected calls
     f = dg.forward(np.array([0], dtype=np.int32))
     assert f["dist"].cpu().numpy().tolist() == [[0, 1, 1, 2, 4]]
+
+
+PLANS = [(64, 1, 0, 0), (4096, 64, 0, 0), (0, 0, 8, 4), (0, 0, 64, 16), (1, 64, 2, 1), (700, 3, 40, 7)]
+
+
+@pytest.mark.parametrize("name", ["rmat12_w3", "er600_unw", "star200"])
+def test_results_do_not_depend_on_plan(torch, mfbc, name):
+    """Work decompositions (runs of 1..64 rows, rows sliced down to 1 arc)
+    give the same results: every plan against the oracle."""
+    g = GRAPHS[name]
+    dg = mfbc.DeviceGraph(g)
+    src = pick(g, 130, 41)
+    ref = oracle.brandes(g, src)
+    lam_ref = oracle.brandes(g, src, per_source=False)["lambda"]
+    for plan in PLANS:
+        print(f"[plan] {name} {plan}", flush=True)
+        dg.set_plan(*plan)
+        f = dg.forward(src)
+        assert np.array_equal(host_dist(f["dist"], mfbc.INF_DIST), ref["dist"]), plan
+        rel_close(f["sigma"].cpu().numpy(), ref["sigma"], SIGMA_TOL, f"sigma {plan}")
+        b = dg.backward(src, f["dist"], f["sigma"], trace=True)
+        rel_close(b["delta"].cpu().numpy(), ref["delta"], DELTA_TOL, f"delta {plan}")
+        assert np.array_equal(b["step"].cpu().numpy(), ref["height"]), plan
+        rel_close(dg.bc(src, 64).cpu().numpy(), lam_ref, DELTA_TOL, f"lambda {plan}")
+    for bad in [(0, 65, 0, 0), (0, 0, (1 << 24) + 1, 0), ((1 << 24) + 1, 0, 0, 0)]:
+        with pytest.raises(mfbc.MfbcError) as e:
+            dg.set_plan(*bad)
+        assert e.value.code == mfbc.MFBC_EINVAL
+    dg.close()
