@@ -30,15 +30,6 @@ __device__ __forceinline__ int64_t uni64(int64_t x) {
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
-// Streaming accesses (each element touched once per product: adjacency, T,
-// counters) use non-temporal loads and stores so that they do not evict the
-// frontier rows, which are gathered once per arc and are worth keeping in
-// L2 and the infinity cache.
-template <typename T>
-__device__ __forceinline__ T ld_nt(const T *p) { return __builtin_nontemporal_load(p); }
-template <typename T>
-__device__ __forceinline__ void st_nt(T *p, T v) { __builtin_nontemporal_store(v, p); }
-
 // Set the bits of `mask` (bit i = vertex v0 + i) in a vertex bitmap.
 __device__ __forceinline__ void or_run_bits(uint32_t *bm, int v0, uint64_t mask) {
     const int w0 = v0 >> 5, sh = v0 & 31;
@@ -153,12 +144,12 @@ struct ArcSrc {
 template <int AM>
 __device__ __forceinline__ void load_arc(const ArcSrc &s, int64_t e, int &u, int &wt) {
     if (AM == 1) {
-        const uint32_t p = ld_nt(s.pk + e);
+        const uint32_t p = s.pk[e];
         u = (int)(p & s.cmask);
         wt = (int)(p >> s.cb);
     } else {
-        u = ld_nt(s.col + e);
-        wt = AM == 2 ? ld_nt(s.w + e) : 1;
+        u = s.col[e];
+        wt = AM == 2 ? s.w[e] : 1;
     }
 }
 
@@ -206,15 +197,15 @@ __device__ __forceinline__ uint64_t fwd_finalize(const FwdArgs &a, size_t cgv, i
         const size_t idx = (cgv + (size_t)v) * kWave + lane;
         bool keep = false;
         if (has) {
-            const int td = tdin == kLoadTd ? ld_nt(a.tdist + idx) : tdin;
+            const int td = tdin == kLoadTd ? a.tdist[idx] : tdin;
             if (bd < td) {
-                st_nt(a.tdist + idx, bd);
-                st_nt(a.tsig + idx, bm);
+                a.tdist[idx] = bd;
+                a.tsig[idx] = bm;
                 keep = true;
                 if (__builtin_isinf(bm)) a.flags[0] = 1;
             } else if (bd == td) {
-                const double s = ld_nt(a.tsig + idx) + bm;
-                st_nt(a.tsig + idx, s);
+                const double s = a.tsig[idx] + bm;
+                a.tsig[idx] = s;
                 keep = true;
                 if (__builtin_isinf(s)) a.flags[0] = 1;
             }
@@ -305,7 +296,7 @@ __device__ __forceinline__ void fwd_task(const FwdArgs &a, int cg, int t, unsign
                     wk[k] = AM ? rdlane(wt, j) : 1;
                     tk[k] = Ft[(size_t)uk[k] * kWave + lane];
                     ow[k] = __popcll(ballot(rend <= e + j));
-                    if (hub < 0 && ow[k] != prev) tn[k] = ld_nt(Td + (size_t)ow[k] * kWave);
+                    if (hub < 0 && ow[k] != prev) tn[k] = Td[(size_t)ow[k] * kWave];
                     prev = ow[k];
                 }
             }
