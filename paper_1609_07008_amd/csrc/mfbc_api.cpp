@@ -87,6 +87,7 @@ void free_workspace(Workspace &ws) {
     dfree(ws.flags);
     dfree(ws.lam);
     dfree(ws.src);
+    dfree(ws.dag);
     dfree(ws.fmask);
     if (ws.h_counters) (void)hipHostFree(ws.h_counters);
     ws.h_counters = nullptr;
@@ -138,6 +139,7 @@ int ensure_workspace(mfbc_graph *g, int ncg, bool trace) {
             (rc = dalloc(&ws.pd, slots)) || (rc = dalloc(&ws.pm, slots)) ||
             (rc = dalloc(&ws.counters, (size_t)kCounterRing * 4 * kCounterSlots)) ||
             (rc = dalloc(&ws.flags, 4)) || (rc = dalloc(&ws.lam, n * ncg)) ||
+            (rc = dalloc(&ws.dag, (size_t)std::max<int64_t>(g->arcs, 1) * ncg)) ||
             (rc = dalloc(&ws.src, (size_t)ncg * kWave))) {
             free_workspace(ws);
             return rc;
@@ -250,7 +252,10 @@ int run_backward(mfbc_graph *g, int ncg, int nb, int32_t *products, hipStream_t 
     if (rc) return rc;
     st.bwd_entries += c.produced;
     st.count_launches++;
-    st.count_alg_bytes += arc_bytes * (double)g->arcs + 8.0 * g->n + 8.0 * (double)g->n * nb;
+    // adjacency, tau of every (column, vertex) read once, and the stored DAG
+    // (one 8-byte lane mask per arc and column group) written
+    st.count_alg_bytes += arc_bytes * (double)g->arcs + 8.0 * g->n + 8.0 * (double)g->n * nb +
+                          8.0 * (double)g->arcs * ncg;
     if (g->timing) {
         float t = 0.f;
         if (hipEventElapsedTime(&t, g->ev[0], g->ev[2]) == hipSuccess) st.count_ms += t;
@@ -267,7 +272,8 @@ int run_backward(mfbc_graph *g, int ncg, int nb, int32_t *products, hipStream_t 
         st.bwd_active_vertices += c.active_vertices;
         st.bwd_active_arcs += c.active_arcs;
         st.bwd_pull_launches++;
-        st.bwd_alg_bytes += 8.0 * c.active_vertices + arc_bytes * c.active_arcs +
+        // + the DAG lane mask of every arc with an active head (8 B)
+        st.bwd_alg_bytes += 8.0 * c.active_vertices + (arc_bytes + 8.0) * c.active_arcs +
                             12.0 * (double)prev + 24.0 * (double)c.outputs;
         add_times(g, &st.bwd_pull_ms, &st.bwd_merge_ms);
         prev = c.produced;

@@ -83,6 +83,7 @@ struct Workspace {
     int32_t *flags = nullptr;          // [0]: path count overflow
     double *lam = nullptr;             // per-column-group lambda parts [cg][n]
     int32_t *src = nullptr;            // column -> source vertex, -1 = padding
+    uint64_t *dag = nullptr;           // shortest-path DAG: lane mask per out-arc [cg][arcs]
     uint64_t *fmask = nullptr;         // trace: forward membership [cg][n][64]
     int fmask_ncg = 0;
     unsigned long long *h_counters = nullptr;  // pinned host copy

@@ -412,6 +412,9 @@ struct BwdArgs {
                                // columns to count (others are left untouched)
     const int32_t *cglist;     // nullable: the ncg column groups of this launch (else 0..ncg-1)
     int ncg_all;               // column groups of the state (strides of colmask, bitmap planes)
+    uint64_t *dag;             // nullable: the shortest-path DAG, one lane mask per out-arc
+    int64_t narcs;             //   [cg][narcs]; written by the counting product, read by the
+                               //   backward products in place of the distance test
 };
 
 // Per-vertex finish of the counting product: counters, leaves, zeta = 0.
@@ -449,6 +452,7 @@ __device__ __forceinline__ void count_task(const BwdArgs &a, int cg, int t, unsi
     const size_t cgv = (size_t)cg * (size_t)a.n;
     const int32_t *Td = a.tdist + cgv * kWave;
     uint64_t run_act = 0;
+    uint64_t *Dg = a.dag ? a.dag + (size_t)cg * a.narcs : nullptr;
     const int xa = v0, xb = hub >= 0 ? v0 + 1 : v1;
     for (int x = xa; x < xb; x++) {
         const int dx = Td[(size_t)x * kWave + lane];
@@ -463,6 +467,7 @@ __device__ __forceinline__ void count_task(const BwdArgs &a, int cg, int t, unsi
                 int y = 0, wt = 1;
                 if (my < eb) load_arc<AM>(a.arcs, my, y, wt);
                 const int cnt = (int)((eb - e) < kWave ? (eb - e) : kWave);
+                uint64_t mine = 0;          // this lane's arc: its shortest-path lanes
                 for (int j = 0; j < cnt; j += 8) {
                     int dy[8], wj[8];
 #pragma unroll
@@ -476,10 +481,20 @@ __device__ __forceinline__ void count_task(const BwdArgs &a, int cg, int t, unsi
                         }
                     }
 #pragma unroll
-                    for (int k = 0; k < 8; k++)
-                        if (reach && dy[k] != kInf && dy[k] == dx + wj[k]) c++;
+                    for (int k = 0; k < 8; k++) {
+                        const bool tight = reach && dy[k] != kInf && dy[k] == dx + wj[k];
+                        if (tight) c++;
+                        if (Dg) {
+                            const uint64_t tm = ballot(tight);
+                            if (lane == j + k) mine = tm;
+                        }
+                    }
                 }
+                if (Dg && my < eb) Dg[my] = mine;
             }
+        } else if (Dg) {
+            // no lane reaches x: none of its arcs is on a shortest path
+            for (int64_t e = ea + lane; e < eb; e += kWave) Dg[e] = 0ull;
         }
         if (hub >= 0) {
             a.pd[((size_t)cg * a.nslots + part) * kWave + lane] = c;
@@ -666,6 +681,106 @@ __device__ __forceinline__ void bwd_task(const BwdArgs &a, int cg, int t, unsign
     flush_colmask(a.colmask, a.ncg_all, cg, colany);
 }
 
+// One pull task of a backward product for column group cg, with the
+// shortest-path DAG stored by the counting product: an arc x -> y counts in
+// lane s iff y is in the frontier of s and the arc is on a shortest path from
+// s, which is the AND of two lane masks -- so neither distance is read, every
+// counted arc belongs to a pending owner, and only the frontier values q(s, y)
+// of counted arcs are gathered (together with the owner's counter).
+template <int AM>
+__device__ __forceinline__ void bwd_task_dag(const BwdArgs &a, int cg, int t, unsigned long long &produced, unsigned long long &outs) {
+    const int lane = threadIdx.x & (kWave - 1);
+    uint64_t colany = 0;
+    const Task *tp = a.tasks + t;
+    const int v0 = uni(tp->v0), v1 = uni(tp->v1), hub = uni(tp->hub), part = uni(tp->part);
+    const int64_t e0 = uni64(tp->e0), e1 = uni64(tp->e1);
+    const size_t cgv = (size_t)cg * (size_t)a.n;
+    const double *Q = a.q + cgv * kWave;
+    const uint64_t *Fb = a.fbits + cgv;
+    const uint64_t *Dg = a.dag + (size_t)cg * a.narcs;
+    const uint32_t *Ab = a.abits + (size_t)cg * a.nwords;
+    int x = v0;
+    int64_t vend = hub >= 0 ? e1 : a.rp[v0 + 1];
+    bool loaded = false;
+    int cx = -1, got = 0;
+    double acc = 0.0;
+    uint64_t run_act = 0;
+    for (int64_t e = e0; e < e1; e += kWave) {
+        const int64_t my = e + lane;
+        int y = 0, wt = 1;
+        uint64_t live = 0;
+        if (my < e1) {
+            load_arc<AM>(a.arcs, my, y, wt);
+            if ((Ab[y >> 5] >> (y & 31)) & 1u) live = Fb[y] & Dg[my];
+        }
+        uint64_t am = ballot(live != 0);
+        while (am) {
+            const int j0 = __ffsll((unsigned long long)am) - 1;
+            if (hub < 0) {
+                while (e + j0 >= vend) {
+                    if (loaded) {
+                        const uint64_t b = bwd_finalize(a, cgv, cg, x, cx, acc, got, lane, outs);
+                        produced += __popcll(b);
+                        colany |= b;
+                        if (b) run_act |= 1ull << (x - v0);
+                    } else if (lane == 0) {
+                        a.fbits_n[cgv + (size_t)x] = 0ull;
+                    }
+                    ++x;
+                    vend = a.rp[x + 1];
+                    loaded = false;
+                    got = 0;
+                    acc = 0.0;
+                }
+            }
+            uint64_t cand = am & owner_mask(e, vend);
+            double qy[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                qy[k] = 0.0;
+                if (cand) {
+                    const int j = __ffsll((unsigned long long)cand) - 1;
+                    cand &= cand - 1;
+                    am &= ~(1ull << j);
+                    const int yk = rdlane(y, j);
+                    if ((rdlane64(live, j) >> lane) & 1ull) {
+                        qy[k] = Q[(size_t)yk * kWave + lane];
+                        got++;
+                    }
+                }
+            }
+            if (!loaded) {
+                cx = a.cnt[(cgv + (size_t)x) * kWave + lane];
+                loaded = true;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; k++) acc += qy[k];
+        }
+    }
+    if (hub < 0) {
+        while (x < v1) {
+            if (loaded) {
+                const uint64_t b = bwd_finalize(a, cgv, cg, x, cx, acc, got, lane, outs);
+                produced += __popcll(b);
+                colany |= b;
+                if (b) run_act |= 1ull << (x - v0);
+            } else if (lane == 0) {
+                a.fbits_n[cgv + (size_t)x] = 0ull;
+            }
+            ++x;
+            loaded = false;
+            got = 0;
+            acc = 0.0;
+        }
+        if (lane == 0 && run_act) or_run_bits(a.abits_n + (size_t)cg * a.nwords, v0, run_act);
+    } else {
+        const size_t pidx = ((size_t)cg * a.nslots + part) * kWave + lane;
+        a.pd[pidx] = got;
+        a.pm[pidx] = acc;
+    }
+    flush_colmask(a.colmask, a.ncg_all, cg, colany);
+}
+
 __device__ __forceinline__ void bwd_hub(const BwdArgs &a, int cg, int h, unsigned long long &produced, unsigned long long &outs) {
     const int lane = threadIdx.x & (kWave - 1);
     uint64_t colany = 0;
@@ -747,12 +862,18 @@ __global__ __launch_bounds__(kBlock) void k_bwd_count_merge(BwdArgs a) {
     flush_counts(produced, 0, 0, 0, a.ctr);
 }
 
-template <int AM, bool L>
+// D: the shortest-path DAG is stored (a.dag) and replaces the distance test.
+template <int AM, bool L, bool D>
 __global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_bwd_pull(BwdArgs a) {
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const int cg = wid / a.ntasks;                       // column-group major
     unsigned long long produced = 0, outs = 0;
-    if (cg < a.ncg) bwd_task<AM>(a, pick_cg<L>(a.cglist, cg), wid - cg * a.ntasks, produced, outs);
+    if (cg < a.ncg) {
+        if constexpr (D)
+            bwd_task_dag<AM>(a, pick_cg<L>(a.cglist, cg), wid - cg * a.ntasks, produced, outs);
+        else
+            bwd_task<AM>(a, pick_cg<L>(a.cglist, cg), wid - cg * a.ntasks, produced, outs);
+    }
     flush_counts(produced, outs, 0, 0, a.ctr);
 }
 
