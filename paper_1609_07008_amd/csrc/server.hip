@@ -144,6 +144,8 @@ struct mfbc_server {
     int32_t *cglists = nullptr;             // [3][ncg]: groups with forward / backward /
                                             // counting columns this step
     int32_t *flags = nullptr;
+    uint64_t *dag = nullptr;                // [ncg][arcs] shortest-path lane masks of each
+                                            // group's cohort (counting product writes)
     char *meta = nullptr;                   // staging for harvest/admit lists
     size_t meta_bytes = 0;
     unsigned long long *h_colmask = nullptr;  // pinned
@@ -199,6 +201,7 @@ void free_server(mfbc_server *s) {
     sfree(s->newmask);
     sfree(s->cglists);
     sfree(s->flags);
+    sfree(s->dag);
     sfree(s->meta);
     if (s->h_colmask) (void)hipHostFree(s->h_colmask);
     s->h_colmask = nullptr;
@@ -246,7 +249,7 @@ int mfbc_server_footprint(const mfbc_graph *g, int32_t width, int64_t *bytes) {
     const int64_t slots = std::max(g->plan_in.nslots, g->plan_out.nslots);
     const int64_t nw = (n + 31) / 32;
     *bytes = n * width * (4 + 8 + 2 * 4 + 2 * 8 + 4 + 8 + 8) + 2 * ncg * n * 8 + 4 * ncg * nw * 4 +
-             slots * width * 12;
+             slots * width * 12 + ncg * std::max<int64_t>(g->arcs, 1) * 8;
     return MFBC_OK;
 }
 
@@ -275,7 +278,7 @@ int mfbc_server_create(mfbc_graph *g, int32_t width, mfbc_server **out) {
         salloc(&s->pd, slots) || salloc(&s->pm, slots) || salloc(&s->src, (size_t)width) ||
         salloc(&s->ctr, (size_t)8 * kCounterSlots) || salloc(&s->colmask, 3 * 32 * ncg) ||
         salloc(&s->cmask, ncg) || salloc(&s->newmask, ncg) || salloc(&s->cglists, 3 * ncg) ||
-        salloc(&s->flags, 4))
+        salloc(&s->flags, 4) || salloc(&s->dag, ncg * (size_t)std::max<int64_t>(g->arcs, 1)))
         rc = MFBC_ENOMEM;
     if (!rc && hipHostMalloc((void **)&s->h_colmask, 3 * 32 * ncg * 8) != hipSuccess) rc = MFBC_ENOMEM;
     if (!rc && hipHostMalloc((void **)&s->h_stage, 3 * ncg * 4 + ncg * 8) != hipSuccess) rc = MFBC_ENOMEM;
@@ -505,6 +508,11 @@ int mfbc_server_step_launch(mfbc_server *s, void *hip_stream) {
     c.pm = s->pm;
     c.ctr = s->ctr;
     c.clear_ctr = s->ctr + 4 * kCounterSlots;
+    // a group's columns reach the counting product together (cohort
+    // admission), so its DAG masks are written whole and stay valid for its
+    // backward loop
+    c.dag = s->dag;
+    c.narcs = g->arcs;
     const int mode = srv_mode(g->out);
     if (s->any_b) {
         // one backward product over every BWD column: reads cur_b, writes the other
@@ -521,9 +529,9 @@ int mfbc_server_step_launch(mfbc_server *s, void *hip_stream) {
         c.cglist = s->cglists + ncg;
         const int grid = nblocks((size_t)c.ntasks * nbk, kWavesPerBlock, 0x7fffffff);
         switch (mode) {
-            case 0: hipLaunchKernelGGL((k_bwd_pull<0, true, false>), dim3(grid), dim3(kBlock), 0, st, c); break;
-            case 1: hipLaunchKernelGGL((k_bwd_pull<1, true, false>), dim3(grid), dim3(kBlock), 0, st, c); break;
-            default: hipLaunchKernelGGL((k_bwd_pull<2, true, false>), dim3(grid), dim3(kBlock), 0, st, c); break;
+            case 0: hipLaunchKernelGGL((k_bwd_pull<0, true, true>), dim3(grid), dim3(kBlock), 0, st, c); break;
+            case 1: hipLaunchKernelGGL((k_bwd_pull<1, true, true>), dim3(grid), dim3(kBlock), 0, st, c); break;
+            default: hipLaunchKernelGGL((k_bwd_pull<2, true, true>), dim3(grid), dim3(kBlock), 0, st, c); break;
         }
         const int mgrid = std::max(nblocks((size_t)c.nhubs * nbk, kWavesPerBlock, 0x7fffffff),
                                    nblocks((size_t)nw, kBlock, 1024));
