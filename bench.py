@@ -39,6 +39,12 @@ WORKLOADS = {
     # Erdos-Renyi n=1024, exact BC over all sources in batches of 64
     "er1024_w100": dict(kind="er", n=1024, k=8, wrange=(1, 100), seed=1,
                         n_sources=None, source_seed=None, batch=64, cpu_sample=None),
+    # monoid fixpoints on the headline graph and sources: shortest distances
+    # (min, +w) and hop levels (min, +1) from 1024 sources in batches of 256
+    "sssp_rmat20_w255": dict(kind="fixpoint", op="sssp", scale=20, ef=16, wrange=(1, 255), seed=3,
+                             n_sources=1024, source_seed=103, batch=256, cpu_sample=2),
+    "bfs_rmat20": dict(kind="fixpoint", op="bfs", scale=20, ef=16, wrange=(1, 255), seed=3,
+                       n_sources=1024, source_seed=103, batch=256, cpu_sample=2),
     # batched form: 256 ER / R-MAT graphs, n log-uniform in [200, 20000], average
     # degree uniform in [4, 64], weights 1..100, exact BC of every graph
     "batched256": dict(kind="many", count=256, seed0=1000, cpu_sample=48),
@@ -52,7 +58,7 @@ WORKLOADS = {
 
 def make_graph(spec):
     from paper_1609_07008_amd import graphgen as gg
-    if spec["kind"] == "rmat":
+    if spec["kind"] in ("rmat", "fixpoint"):
         return gg.rmat_graph(spec["scale"], spec["ef"], spec["seed"], wrange=spec["wrange"])
     return gg.er_graph(spec["n"], spec["k"], spec["seed"], spec["wrange"])
 
@@ -243,6 +249,79 @@ def run_serve(args, spec):
     print(json.dumps(line), flush=True)
 
 
+def run_fixpoint(args, spec):
+    """Monoid fixpoint (mfbc_fixpoint) over the workload's sources, batch by batch."""
+    import numpy as np
+    import torch
+    from paper_1609_07008_amd import autotune, mfbc
+
+    torch.cuda.set_device(0)
+    g = make_graph(spec)
+    src = make_sources(g, spec)
+    batch = args.batch or spec["batch"]
+    dg = mfbc.DeviceGraph(g)
+    autotune.apply_plan(dg, g, autotune.load_cache())
+    d_src = torch.as_tensor(src, device="cuda")
+    out = torch.empty((batch, g.n), dtype=torch.int32, device="cuda")
+    print(f"[bench] {args.workload}: n={g.n} m={g.m} sources={src.size} batch={batch}",
+          file=sys.stderr, flush=True)
+
+    def step(stats):
+        prods = 0
+        for b0 in range(0, src.size, batch):
+            sb = d_src[b0:b0 + batch]
+            _, p = dg.fixpoint(sb, spec["op"], out=out[:sb.numel()])
+            prods += p
+            if stats is not None:
+                for k, v in dg.stats().items():
+                    stats[k] = stats.get(k, 0) + v
+        return prods
+
+    for i in range(args.warmup):
+        step(None)
+        torch.cuda.synchronize()
+    dg.enable_timing(True)
+    tot = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        prods = step(tot)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    dg.enable_timing(False)
+    print(f"[bench] {args.steps} steps in {elapsed:.3f}s, {prods} products per step",
+          file=sys.stderr, flush=True)
+    ms, alg, launches = tot["fwd_pull_ms"], tot["fwd_alg_bytes"], tot["fwd_pull_launches"]
+    achieved = alg / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    line = {
+        "metric": f"{spec['op'].upper()} TEPS (sources x edges / s) at 1 GPU",
+        "value": src.size * g.m / (elapsed / args.steps), "unit": "TEPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "graph": g.name, "n": g.n, "m": g.m,
+                   "n_sources": int(src.size), "batch": batch, "op": spec["op"]},
+        "roofline": {"bound": "hbm", "kernel": "k_mono_pull", "achieved": round(achieved, 2),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": stored_traffic(args.workload, "k_mono_pull"),
+                     "launches": int(launches), "avg_launch_us": round(ms / max(launches, 1) * 1e3, 2),
+                     "alg_bytes_per_launch": round(alg / max(launches, 1))},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu:
+        from oracle.frontier import fixpoint
+        k = min(spec["cpu_sample"], src.size)
+        t1 = time.perf_counter()
+        for s in src[:k]:
+            fixpoint(g, int(s), spec["op"])
+        dt = time.perf_counter() - t1
+        line["cpu_baseline"] = {"value": k * g.m / dt, "unit": "TEPS", "cores": 1, "kind": "oracle",
+                                "sample": f"{k} of the workload's {src.size} sources (numpy "
+                                          f"relaxation to the fixpoint, one source at a time), {dt:.2f} s"}
+    dg.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -286,6 +365,9 @@ def main():
         return
     if spec["kind"] == "serve":
         run_serve(args, spec)
+        return
+    if spec["kind"] == "fixpoint":
+        run_fixpoint(args, spec)
         return
     batch = args.batch or spec["batch"]
     torch.cuda.set_device(0)

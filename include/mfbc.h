@@ -140,6 +140,27 @@ int mfbc_bc(mfbc_graph *g, const int32_t *d_sources, int64_t n_sources,
             int32_t batch, double *d_bc, void *hip_stream);
 
 /*
+ * mfbc_fixpoint -- the paper's monoid product (Section 3: C = A (+).f B with a
+ * commutative monoid (+) and an action f of an arc on an entry) iterated over
+ * maximal frontiers as in Algorithm 1, for other graph problems.  Values are
+ * int32, (+) = min, and
+ *   op = MFBC_OP_SSSP: f(a, w) = a + w  -> shortest-path distances;
+ *   op = MFBC_OP_BFS:  f(a, w) = a + 1  -> hop levels (weights ignored).
+ * T(s,s) = 0; product j relaxes the arcs of the entries that product j-1
+ * lowered (the sources for j = 1); the loop ends after the first product
+ * that lowers nothing.
+ *   d_sources[nb]  device, vertex ids in [0,n) (repeats allowed), nb >= 1.
+ *   d_out[nb][n]   device out, row-major; MFBC_INF_DIST where unreachable.
+ *   h_products     host out (nullable): products run, the last one included.
+ * Errors: EINVAL (op unknown, nb < 1, NULL output, bad source), ENOMEM,
+ * EDEVICE.
+ */
+#define MFBC_OP_SSSP 0
+#define MFBC_OP_BFS 1
+int mfbc_fixpoint(mfbc_graph *g, int32_t op, const int32_t *d_sources, int32_t nb,
+                  int32_t *d_out, int32_t *h_products, void *hip_stream);
+
+/*
  * mfbc_forward_trace -- mfbc_forward that also records frontier membership.
  *   d_fmask[nb][n] device out (uint64): bit j-1 is set when v is in the
  *                  frontier produced by product j for source s (first

@@ -53,3 +53,39 @@ def backward_heights(height_row: np.ndarray) -> list:
     h = np.asarray(height_row)
     top = int(h.max()) if h.size else -1
     return [h == k for k in range(top + 1)]
+
+
+def fixpoint(g, s: int, op: str = "sssp", max_products: int = 1 << 20):
+    """Relaxation to a fixpoint with (+) = min over strict-improvement frontiers.
+
+    Section 3's product C = A (+).f B with (+) = min and the action
+    f(a, w) = a + w ("sssp") or a + 1 ("bfs"), iterated as Algorithm 1
+    iterates it but without multiplicities, so an entry joins frontier j only
+    when product j lowers it:  F_j = { v : l_j(v) < L_{j-1}(v) }  with l_j,
+    L_j as above (arc weights, or 1 for "bfs").  Returns (L, products): the
+    final values (INF where unreachable) and the index of the first product
+    whose frontier is empty.  After an empty F_j every later one is empty
+    too (l_{j+1}(v) >= min_u L_{j-1}(u) + w(u, v) >= L_j(v)).
+    """
+    n = g.n
+    u = np.repeat(np.arange(n, dtype=np.int64), np.diff(g.row_ptr))
+    v = g.col.astype(np.int64)
+    if op == "bfs" or g.w is None:
+        w = np.ones(u.size, np.int64)
+    elif op == "sssp":
+        w = g.w.astype(np.int64)
+    else:
+        raise ValueError(op)
+    ell = np.full(n, INF, dtype=np.int64)
+    ell[s] = 0
+    L = ell.copy()
+    for j in range(1, max_products + 1):
+        cand = np.where(ell[u] < INF, ell[u] + w, INF)
+        nxt = np.full(n, INF, dtype=np.int64)
+        np.minimum.at(nxt, v, cand)
+        F = nxt < L
+        L = np.minimum(L, nxt)
+        ell = nxt
+        if not F.any():
+            return L, j
+    raise RuntimeError("fixpoint not reached")

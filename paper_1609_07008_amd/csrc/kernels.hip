@@ -354,6 +354,12 @@ void launch_export_forward(mfbc_graph *g, int ncg, int nb, int32_t *d_dist, doub
                            (const uint64_t *)g->ws.fmask, d_fmask, g->n, nb);
 }
 
+void launch_export_tiles_i32(mfbc_graph *g, int ncg, int nb, const int32_t *tiles, int32_t *d_rows,
+                             hipStream_t s) {
+    dim3 grid((g->n + 63) / 64, ncg);
+    hipLaunchKernelGGL(k_tiles_to_rows<int32_t>, grid, dim3(kBlock), 0, s, tiles, d_rows, g->n, nb);
+}
+
 void launch_import_forward(mfbc_graph *g, int ncg, int nb, const int32_t *d_dist,
                            const double *d_sigma, hipStream_t s) {
     dim3 grid((g->n + 63) / 64, ncg);

@@ -506,6 +506,53 @@ int mfbc_forward(mfbc_graph *g, const int32_t *d_sources, int32_t nb, int32_t *d
                         hip_stream);
 }
 
+int mfbc_fixpoint(mfbc_graph *g, int32_t op, const int32_t *d_sources, int32_t nb,
+                  int32_t *d_out, int32_t *h_products, void *hip_stream) {
+    if (!g) return fail(MFBC_EINVAL, "graph handle is NULL");
+    if (op != MFBC_OP_SSSP && op != MFBC_OP_BFS) return fail(MFBC_EINVAL, "unknown operation");
+    if (nb < 1) return fail(MFBC_EINVAL, "nb must be >= 1");
+    if (!d_out) return fail(MFBC_EINVAL, "output pointer is NULL");
+    DeviceGuard dg(g->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    int rc = check_sources(g, d_sources, nb, s);
+    if (rc) return rc;
+    const int ncg = (nb + kWave - 1) / kWave;
+    if ((rc = ensure_workspace(g, ncg, false))) return rc;
+    g->stats = mfbc_stats{};
+    launch_set_sources(g, ncg, nb, d_sources, s);
+    launch_mono_init(g, ncg, nb, s);
+    hipEvent_t *ev = g->timing ? g->ev : nullptr;
+    const double arc_bytes = g->weighted && op == MFBC_OP_SSSP ? 8.0 : 4.0;
+    mfbc_stats &st = g->stats;
+    int64_t prev = nb;
+    Counts c;
+    int j = 0;
+    do {
+        j++;
+        if (j > g->n + 1) return fail(MFBC_EDEVICE, "fixpoint products did not converge");
+        launch_mono_product(g, op, ncg, j, s, ev);
+        if ((rc = read_counts(g, j, s, &c))) return rc;
+        st.fwd_entries += c.produced;
+        st.fwd_outputs += c.outputs;
+        st.fwd_active_vertices += c.active_vertices;
+        st.fwd_active_arcs += c.active_arcs;
+        st.fwd_pull_launches++;
+        // adjacency of the active rows, frontier values read once, T read
+        // where a candidate arrived, T and the next frontier written per entry
+        st.fwd_alg_bytes += 8.0 * c.active_vertices + arc_bytes * c.active_arcs +
+                            4.0 * (double)(prev + c.outputs) + 8.0 * (double)c.produced;
+        add_times(g, &st.fwd_pull_ms, &st.fwd_merge_ms);
+        prev = c.produced;
+    } while (c.produced > 0);
+    st.fwd_products = j;
+    st.batches = 1;
+    if (h_products) *h_products = j;
+    launch_export_tiles_i32(g, ncg, nb, g->ws.tdist, d_out, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    return MFBC_OK;
+}
+
 int mfbc_forward_trace(mfbc_graph *g, const int32_t *d_sources, int32_t nb, int32_t *d_dist,
                        double *d_sigma, uint64_t *d_fmask, int64_t *h_nnz, int32_t max_products,
                        int32_t *h_products, void *hip_stream) {

@@ -128,6 +128,12 @@ void launch_import_forward(mfbc_graph *g, int ncg, int nb, const int32_t *d_dist
 void launch_export_backward(mfbc_graph *g, int ncg, int nb, double *d_delta, int32_t *d_step,
                             hipStream_t s);
 void launch_set_sources(mfbc_graph *g, int ncg, int nb, const int32_t *d_sources, hipStream_t s);
+void launch_export_tiles_i32(mfbc_graph *g, int ncg, int nb, const int32_t *tiles, int32_t *d_rows,
+                             hipStream_t s);
+
+// ---- monoid fixpoints (monoid.hip) ----
+void launch_mono_init(mfbc_graph *g, int ncg, int nb, hipStream_t s);
+void launch_mono_product(mfbc_graph *g, int op, int ncg, int j, hipStream_t s, hipEvent_t *ev);
 
 // ---- batched form (batched.hip) ----
 struct ManyWorkspace;

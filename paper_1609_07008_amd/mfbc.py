@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libmfbc.so")
 MFBC_OK, MFBC_EINVAL, MFBC_ENOMEM, MFBC_EDEVICE, MFBC_EOVERFLOW = 0, -1, -2, -3, -4
 MFBC_UNDIRECTED, MFBC_DIRECTED = 1, 2
 INF_DIST = 0x7FFFFFFF
+OP_SSSP, OP_BFS = 0, 1
 
 # Every entry point declared in include/mfbc.h, with its ctypes signature.
 _P = ctypes.c_void_p
@@ -35,6 +36,7 @@ SIGNATURES = {
     "mfbc_set_plan": ([_P, _I32, _I32, _I32, _I32], ctypes.c_int),
     "mfbc_graph_info": ([_P, _P, _P, _P], ctypes.c_int),
     "mfbc_bc_many": ([_I32, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "mfbc_fixpoint": ([_P, _I32, _P, _I32, _P, _P, _P], ctypes.c_int),
     "mfbc_last_error": ([], ctypes.c_char_p),
 }
 
@@ -166,6 +168,20 @@ class DeviceGraph:
         if trace:
             out["nnz"] = out["nnz"][:prods.value]
         return out
+
+    def fixpoint(self, sources, op: str = "sssp", out=None, stream=None):
+        """Monoid relaxation to a fixpoint (mfbc_fixpoint): int32[nb][n]
+        distances (op="sssp") or hop levels (op="bfs"), and the product count."""
+        t = self._torch
+        code = {"sssp": OP_SSSP, "bfs": OP_BFS}[op]
+        src = self._src(sources)
+        nb = src.numel()
+        if out is None:
+            out = t.empty((nb, self.n), dtype=t.int32, device="cuda")
+        prods = ctypes.c_int32(0)
+        _check(load_library().mfbc_fixpoint(self.handle, code, _ptr(src), nb, _ptr(out),
+                                            ctypes.byref(prods), _stream(t, stream)))
+        return out, prods.value
 
     def backward(self, sources, dist, sigma, trace: bool = False, stream=None):
         """MFBr from a forward result: delta float64[nb][n], products."""

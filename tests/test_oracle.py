@@ -322,3 +322,62 @@ def test_unweighted_product_bound():
     b = mfbc_ref.mfbr(g, src, f["dist"], f["sigma"], trace=False)
     d = int(r["dist"].max())
     assert (f["products"] - 1) + (b["products"] - 1) <= 2 * d + 1
+
+
+# ------------------------------------------------------------------ monoid fixpoints
+from oracle.frontier import fixpoint  # noqa: E402
+
+
+def _strip_weights(g):
+    u, v, _ = g.edges()
+    return gg.csr_from_edges(g.n, u, v, None, g.name + "_unw")
+
+
+@pytest.mark.parametrize("n,p,seed,wr", SMALL)
+def test_fixpoint_values_are_distances(n, p, seed, wr):
+    """SSSP fixpoint = shortest distances of the brute-force pin; BFS = hop counts."""
+    g = gg.random_small_graph(n, p, seed, wr)
+    per, _ = brute.brute_bc(g, range(g.n))
+    hops, _ = brute.brute_bc(_strip_weights(g), range(g.n))
+    for s in range(g.n):
+        d, _ = fixpoint(g, s, "sssp")
+        want = [(-1 if t is None else t) for t in per[s]["tau"]]
+        assert [(-1 if x >= (1 << 60) else int(x)) for x in d] == want
+        h, _ = fixpoint(g, s, "bfs")
+        want = [(-1 if t is None else t) for t in hops[s]["tau"]]
+        assert [(-1 if x >= (1 << 60) else int(x)) for x in h] == want
+
+
+@pytest.mark.parametrize("n,p,seed,wr", SMALL)
+def test_fixpoint_products_from_walk_minima(n, p, seed, wr):
+    """The product count follows the strict-improvement frontier definition,
+    recomputed from exhaustively enumerated walks; for BFS it is the
+    eccentricity plus one (the last product finds nothing)."""
+    g = gg.random_small_graph(n, p, seed, wr)
+    for s in range(g.n):
+        ell, _ = brute.walk_minima(g, s, g.n + 1)
+        best = [None] * g.n
+        best[s] = 0
+        expect = None
+        for j in range(1, g.n + 2):
+            lower = [v for v in range(g.n) if ell[j][v] is not None
+                     and (best[v] is None or ell[j][v] < best[v])]
+            for v in lower:
+                best[v] = ell[j][v]
+            if not lower:
+                expect = j
+                break
+        assert fixpoint(g, s, "sssp")[1] == expect
+        h, prods = fixpoint(g, s, "bfs")
+        assert prods == int(h[h < (1 << 60)].max()) + 1
+
+
+def test_fixpoint_closed_forms():
+    path = gg.path_graph(40, w=3)
+    d, k = fixpoint(path, 0, "sssp")
+    assert d.tolist() == [3 * i for i in range(40)] and k == 40
+    h, k = fixpoint(path, 7, "bfs")
+    assert h.tolist() == [abs(i - 7) for i in range(40)] and k == 33
+    star = gg.star_graph(30)
+    h, k = fixpoint(star, 5, "bfs")
+    assert h[0] == 1 and h[5] == 0 and all(h[i] == 2 for i in range(1, 31) if i != 5) and k == 3
