@@ -42,6 +42,7 @@ struct ManyArgs {
     const GraphDesc *graphs;
     const JobDesc *jobs;
     int32_t njobs, n_max, slots_max, pad;
+    int64_t arcs_max;                // largest out-arc count: the slot's DAG masks
     unsigned int *queue;
     char *scratch;
     size_t slot_stride;
@@ -66,9 +67,10 @@ struct Slot {
     int32_t *pd;
     double *pm;
     int32_t *src;
+    uint64_t *dag;             // shortest-path lane mask per out-arc
 };
 
-__device__ __forceinline__ Slot carve(char *base, int n_max, int slots_max) {
+__device__ __forceinline__ Slot carve(char *base, int n_max, int slots_max, int64_t arcs_max) {
     Slot s;
     const size_t nw = (size_t)n_max * kWave;
     const size_t words = ((size_t)n_max + 31) / 32;
@@ -83,8 +85,17 @@ __device__ __forceinline__ Slot carve(char *base, int n_max, int slots_max) {
     }
     s.pd = (int32_t *)(base + off); off = align256(off + (size_t)slots_max * kWave * 4);
     s.pm = (double *)(base + off); off = align256(off + (size_t)slots_max * kWave * 8);
-    s.src = (int32_t *)(base + off);
+    s.src = (int32_t *)(base + off); off = align256(off + kWave * 4);
+    s.dag = (uint64_t *)(base + off);
+    (void)arcs_max;
     return s;
+}
+
+// Pointer of buffer b (0 or 1) without indexing an array by a runtime value
+// (which would put the pair in scratch memory).
+template <typename T>
+__device__ __forceinline__ T *pick(T *const (&p)[2], int b) {
+    return b ? p[1] : p[0];
 }
 
 // AM: arc encoding shared by every graph of the launch (see load_arc).
@@ -96,7 +107,8 @@ __global__ __launch_bounds__(kManyMaxThreads) void k_bc_many(ManyArgs m) {
     // wave index as a uniform (scalar) value, so the task loops stay uniform
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), nwaves = nthr >> 6;
     const bool lead = (tid & (kWave - 1)) == 0;
-    const Slot sl = carve(m.scratch + (size_t)blockIdx.x * m.slot_stride, m.n_max, m.slots_max);
+    const Slot sl = carve(m.scratch + (size_t)blockIdx.x * m.slot_stride, m.n_max, m.slots_max,
+                          m.arcs_max);
     for (;;) {
         if (tid == 0) s_job = (int)atomicAdd(m.queue, 1u);
         if (tid < 3) s_cnt[tid] = 0ull;
@@ -157,18 +169,18 @@ __global__ __launch_bounds__(kManyMaxThreads) void k_bc_many(ManyArgs m) {
             ++j;
             const int b = (j - 1) & 1;
             a.j = j;
-            a.abits = sl.abits[b];
-            a.ftup = sl.ftup[b];
-            a.fsig = sl.fsig[b];
-            a.abits_n = sl.abits[b ^ 1];
-            a.ftup_n = sl.ftup[b ^ 1];
-            a.fsig_n = sl.fsig[b ^ 1];
+            a.abits = pick(sl.abits, b);
+            a.ftup = pick(sl.ftup, b);
+            a.fsig = pick(sl.fsig, b);
+            a.abits_n = pick(sl.abits, b ^ 1);
+            a.ftup_n = pick(sl.ftup, b ^ 1);
+            a.fsig_n = pick(sl.fsig, b ^ 1);
             if (tid == 0) s_cnt[(j + 1) % 3] = 0ull;
             unsigned long long produced = 0, outs = 0;
             for (int t = wave; t < a.ntasks; t += nwaves) fwd_task<AM, 4>(a, 0, t, produced, outs);
             __syncthreads();
             for (int h = wave; h < a.nhubs; h += nwaves) fwd_hub(a, 0, h, produced, outs);
-            for (int i = tid; i < nw; i += nthr) sl.abits[b][i] = 0u;
+            for (int i = tid; i < nw; i += nthr) pick(sl.abits, b)[i] = 0u;
             if (lead && produced) atomicAdd(&s_cnt[j % 3], produced);
             __syncthreads();
             if (s_cnt[j % 3] == 0ull) break;
@@ -201,6 +213,8 @@ __global__ __launch_bounds__(kManyMaxThreads) void k_bc_many(ManyArgs m) {
         c.lam = lam;
         c.pd = sl.pd;
         c.pm = sl.pm;
+        c.dag = sl.dag;            // the counting product stores the DAG, the
+        c.narcs = 0;               // backward products read it (one column group)
         for (int i = tid; i < nw; i += nthr) {
             sl.abits[0][i] = 0u;
             sl.abits[1][i] = 0u;
@@ -215,23 +229,23 @@ __global__ __launch_bounds__(kManyMaxThreads) void k_bc_many(ManyArgs m) {
         for (;;) {
             const int bn = k & 1;
             c.k = k;
-            c.abits = sl.abits[bn ^ 1];
-            c.fbits = sl.fbits[bn ^ 1];
-            c.abits_n = sl.abits[bn];
-            c.fbits_n = sl.fbits[bn];
+            c.abits = pick(sl.abits, bn ^ 1);
+            c.fbits = pick(sl.fbits, bn ^ 1);
+            c.abits_n = pick(sl.abits, bn);
+            c.fbits_n = pick(sl.fbits, bn);
             if (tid == 0) s_cnt[(k + 1) % 3] = 0ull;
             unsigned long long produced = 0, outs = 0;
             if (k == 0) {
                 for (int t = wave; t < c.ntasks; t += nwaves) count_task<AM>(c, 0, t, produced);
             } else {
-                for (int t = wave; t < c.ntasks; t += nwaves) bwd_task<AM>(c, 0, t, produced, outs);
+                for (int t = wave; t < c.ntasks; t += nwaves) bwd_task_dag<AM>(c, 0, t, produced, outs);
             }
             __syncthreads();
             if (k == 0) {
                 for (int h = wave; h < c.nhubs; h += nwaves) count_hub(c, 0, h, produced);
             } else {
                 for (int h = wave; h < c.nhubs; h += nwaves) bwd_hub(c, 0, h, produced, outs);
-                for (int i = tid; i < nw; i += nthr) sl.abits[bn ^ 1][i] = 0u;
+                for (int i = tid; i < nw; i += nthr) pick(sl.abits, bn ^ 1)[i] = 0u;
             }
             if (lead && produced) atomicAdd(&s_cnt[k % 3], produced);
             __syncthreads();
@@ -285,7 +299,7 @@ ManyWorkspace &many_workspace(int device) {
 
 static size_t host_align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t many_slot_bytes(int n_max, int slots_max) {
+size_t many_slot_bytes(int n_max, int slots_max, int64_t arcs_max) {
     const size_t nw = (size_t)n_max * kWave;
     const size_t words = ((size_t)n_max + 31) / 32;
     size_t off = 0;
@@ -300,6 +314,7 @@ size_t many_slot_bytes(int n_max, int slots_max) {
     off = host_align256(off + (size_t)slots_max * kWave * 4);
     off = host_align256(off + (size_t)slots_max * kWave * 8);
     off = host_align256(off + kWave * 4);
+    off = host_align256(off + (size_t)std::max<int64_t>(arcs_max, 1) * 8);
     return off;
 }
 
@@ -322,6 +337,7 @@ int launch_bc_many(std::vector<mfbc_graph *> &graphs, const std::vector<const in
     const int G = (int)graphs.size();
     std::vector<GraphDesc> gds((size_t)G);
     int n_max = 1, slots_max = 1;
+    int64_t arcs_max = 1;
     for (int i = 0; i < G; i++) {
         mfbc_graph *g = graphs[(size_t)i];
         GraphDesc &d = gds[(size_t)i];
@@ -350,6 +366,7 @@ int launch_bc_many(std::vector<mfbc_graph *> &graphs, const std::vector<const in
         d.hubs_out = g->plan_out.hubs;
         n_max = std::max(n_max, g->n);
         slots_max = std::max({slots_max, g->plan_in.nslots, g->plan_out.nslots});
+        arcs_max = std::max<int64_t>(arcs_max, g->arcs);
     }
     // jobs: 64 sources each; scheduled largest first (longest-processing-time
     // order) so that small jobs fill in at the end
@@ -388,7 +405,7 @@ int launch_bc_many(std::vector<mfbc_graph *> &graphs, const std::vector<const in
     }
     const int njobs = (int)jobs.size();
     blocks = std::max(1, std::min(blocks, std::max(njobs, 1)));
-    const size_t slot = many_slot_bytes(n_max, slots_max);
+    const size_t slot = many_slot_bytes(n_max, slots_max, arcs_max);
     const size_t need_scratch = slot * (size_t)blocks;
     const size_t need_lam = (size_t)std::max<int64_t>(lam_total, 1) * sizeof(double);
     // metadata block: graphs, jobs, queue, flags, stats, offsets
@@ -438,6 +455,7 @@ int launch_bc_many(std::vector<mfbc_graph *> &graphs, const std::vector<const in
     m.njobs = njobs;
     m.n_max = n_max;
     m.slots_max = slots_max;
+    m.arcs_max = arcs_max;
     m.queue = (unsigned int *)(meta + o_queue);
     m.scratch = ws.scratch;
     m.slot_stride = slot;

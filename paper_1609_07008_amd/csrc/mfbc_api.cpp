@@ -675,13 +675,15 @@ int mfbc_bc_many(int32_t n_graphs, mfbc_graph *const *graphs, const int32_t *con
         blocks = 2 * prop.multiProcessorCount;
     }
     int n_max = 1, slots_max = 1;
+    int64_t arcs_max = 1;
     for (auto *g : gs) {
         n_max = std::max(n_max, g->n);
         slots_max = std::max({slots_max, g->plan_in.nslots, g->plan_out.nslots});
+        arcs_max = std::max<int64_t>(arcs_max, g->arcs);
     }
     size_t free_b = 0, total_b = 0;
     HIP_TRY(hipMemGetInfo(&free_b, &total_b));
-    const size_t slot = many_slot_bytes(n_max, slots_max);
+    const size_t slot = many_slot_bytes(n_max, slots_max, arcs_max);
     ManyWorkspace &ws = many_workspace(dev);
     const size_t budget = free_b / 4 + ws_scratch_bytes(ws);
     const int cap = (int)std::max<size_t>(1, budget / std::max<size_t>(slot, 1));
