@@ -238,7 +238,7 @@ __global__ __launch_bounds__(kManyMaxThreads) void k_bc_many(ManyArgs m) {
             if (k == 0) {
                 for (int t = wave; t < c.ntasks; t += nwaves) count_task<AM>(c, 0, t, produced);
             } else {
-                for (int t = wave; t < c.ntasks; t += nwaves) bwd_task_dag<AM>(c, 0, t, produced, outs);
+                for (int t = wave; t < c.ntasks; t += nwaves) bwd_task<AM>(c, 0, t, produced, outs);
             }
             __syncthreads();
             if (k == 0) {

@@ -319,9 +319,9 @@ void launch_bwd_product(mfbc_graph *g, int ncg, int k, hipStream_t s, hipEvent_t
     const size_t waves = (size_t)a.ntasks * ncg;
     const int grid = blocks_for(waves, kWavesPerBlock, 0x7fffffff);
     switch (arc_mode(g->out)) {
-        case 0: hipLaunchKernelGGL((k_bwd_pull<0, false, true>), dim3(grid), dim3(kBlock), 0, s, a); break;
-        case 1: hipLaunchKernelGGL((k_bwd_pull<1, false, true>), dim3(grid), dim3(kBlock), 0, s, a); break;
-        default: hipLaunchKernelGGL((k_bwd_pull<2, false, true>), dim3(grid), dim3(kBlock), 0, s, a); break;
+        case 0: hipLaunchKernelGGL((k_bwd_pull<0, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
+        case 1: hipLaunchKernelGGL((k_bwd_pull<1, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_bwd_pull<2, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
     }
     if (ev) (void)hipEventRecord(ev[1], s);
     int mgrid = blocks_for((size_t)a.nhubs * ncg, kWavesPerBlock, 0x7fffffff);

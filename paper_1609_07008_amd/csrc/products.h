@@ -412,9 +412,9 @@ struct BwdArgs {
                                // columns to count (others are left untouched)
     const int32_t *cglist;     // nullable: the ncg column groups of this launch (else 0..ncg-1)
     int ncg_all;               // column groups of the state (strides of colmask, bitmap planes)
-    uint64_t *dag;             // nullable: the shortest-path DAG, one lane mask per out-arc
-    int64_t narcs;             //   [cg][narcs]; written by the counting product, read by the
-                               //   backward products in place of the distance test
+    uint64_t *dag;             // the shortest-path DAG, one lane mask per out-arc, [cg][narcs]:
+    int64_t narcs;             //   written by the counting product (skipped if NULL), read by
+                               //   the backward products in place of the distance test
 };
 
 // Per-vertex finish of the counting product: counters, leaves, zeta = 0.
@@ -565,130 +565,14 @@ __device__ __forceinline__ uint64_t bwd_finalize(const BwdArgs &a, size_t cgv, i
     return bits;
 }
 
-// One pull task of a backward product for column group cg.
-template <int AM>
-__device__ __forceinline__ void bwd_task(const BwdArgs &a, int cg, int t, unsigned long long &produced, unsigned long long &outs) {
-    const int lane = threadIdx.x & (kWave - 1);
-    uint64_t colany = 0;
-    const Task *tp = a.tasks + t;
-    const int v0 = uni(tp->v0), v1 = uni(tp->v1), hub = uni(tp->hub), part = uni(tp->part);
-    const int64_t e0 = uni64(tp->e0), e1 = uni64(tp->e1);
-    const size_t cgv = (size_t)cg * (size_t)a.n;
-    const int32_t *Td = a.tdist + cgv * kWave;
-    const double *Q = a.q + cgv * kWave;
-    const uint64_t *Fb = a.fbits + cgv;
-    const uint32_t *Ab = a.abits + (size_t)cg * a.nwords;
-    int x = v0;
-    int64_t vend = hub >= 0 ? e1 : a.rp[v0 + 1];
-    bool loaded = false;
-    int cx = -1, dx = kInf, got = 0;
-    double acc = 0.0;
-    uint64_t run_act = 0;
-    for (int64_t e = e0; e < e1; e += kWave) {
-        const int64_t my = e + lane;
-        int y = 0, wt = 1;
-        uint64_t fb = 0;
-        if (my < e1) {
-            load_arc<AM>(a.arcs, my, y, wt);
-            if ((Ab[y >> 5] >> (y & 31)) & 1u) fb = Fb[y];
-        }
-        uint64_t am = ballot(fb != 0);
-        while (am) {
-            const int j0 = __ffsll((unsigned long long)am) - 1;
-            if (hub < 0) {
-                while (e + j0 >= vend) {
-                    if (loaded) {
-                        const uint64_t b = bwd_finalize(a, cgv, cg, x, cx, acc, got, lane, outs);
-                        produced += __popcll(b);
-                        colany |= b;
-                        if (b) run_act |= 1ull << (x - v0);
-                    } else if (lane == 0) {
-                        a.fbits_n[cgv + (size_t)x] = 0ull;
-                    }
-                    ++x;
-                    vend = a.rp[x + 1];
-                    loaded = false;
-                    got = 0;
-                    acc = 0.0;
-                }
-            }
-            if (!loaded) {
-                const size_t idx = (cgv + (size_t)x) * kWave + lane;
-                cx = a.cnt[idx];
-                dx = Td[(size_t)x * kWave + lane];
-                loaded = true;
-            }
-            const bool pend = cx > 0;
-            uint64_t cand = am & owner_mask(e, vend);
-            if (!ballot(pend)) {
-                am &= ~cand;            // nothing of x is pending: skip its arcs here
-                continue;
-            }
-            int js[4];
-#pragma unroll
-            for (int k = 0; k < 4; k++) {
-                js[k] = cand ? __ffsll((unsigned long long)cand) - 1 : -1;
-                cand &= cand - 1;
-            }
-            // distances first; the frontier value q is loaded only for
-            // lanes whose arc is a shortest-path arc (few per row)
-            int dy[4], wk[4], yk[4];
-#pragma unroll
-            for (int k = 0; k < 4; k++) {
-                dy[k] = kInf;
-                wk[k] = 0;
-                yk[k] = 0;
-                if (js[k] >= 0) {
-                    am &= ~(1ull << js[k]);
-                    yk[k] = rdlane(y, js[k]);
-                    wk[k] = AM ? rdlane(wt, js[k]) : 1;
-                    const uint64_t fbj = rdlane64(fb, js[k]);
-                    if (pend && ((fbj >> lane) & 1ull)) dy[k] = Td[(size_t)yk[k] * kWave + lane];
-                }
-            }
-            double qy[4];
-#pragma unroll
-            for (int k = 0; k < 4; k++) {
-                const bool tight = dy[k] != kInf && dy[k] == dx + wk[k];
-                qy[k] = tight ? Q[(size_t)yk[k] * kWave + lane] : 0.0;
-                if (tight) got++;
-            }
-#pragma unroll
-            for (int k = 0; k < 4; k++) acc += qy[k];
-        }
-    }
-    if (hub < 0) {
-        while (x < v1) {
-            if (loaded) {
-                const uint64_t b = bwd_finalize(a, cgv, cg, x, cx, acc, got, lane, outs);
-                produced += __popcll(b);
-                colany |= b;
-                if (b) run_act |= 1ull << (x - v0);
-            } else if (lane == 0) {
-                a.fbits_n[cgv + (size_t)x] = 0ull;
-            }
-            ++x;
-            loaded = false;
-            got = 0;
-            acc = 0.0;
-        }
-        if (lane == 0 && run_act) or_run_bits(a.abits_n + (size_t)cg * a.nwords, v0, run_act);
-    } else {
-        const size_t pidx = ((size_t)cg * a.nslots + part) * kWave + lane;
-        a.pd[pidx] = got;
-        a.pm[pidx] = acc;
-    }
-    flush_colmask(a.colmask, a.ncg_all, cg, colany);
-}
-
-// One pull task of a backward product for column group cg, with the
-// shortest-path DAG stored by the counting product: an arc x -> y counts in
+// One pull task of a backward product for column group cg.  The counting
+// product stored the shortest-path DAG: an arc x -> y counts in
 // lane s iff y is in the frontier of s and the arc is on a shortest path from
 // s, which is the AND of two lane masks -- so neither distance is read, every
 // counted arc belongs to a pending owner, and only the frontier values q(s, y)
 // of counted arcs are gathered (together with the owner's counter).
 template <int AM>
-__device__ __forceinline__ void bwd_task_dag(const BwdArgs &a, int cg, int t, unsigned long long &produced, unsigned long long &outs) {
+__device__ __forceinline__ void bwd_task(const BwdArgs &a, int cg, int t, unsigned long long &produced, unsigned long long &outs) {
     const int lane = threadIdx.x & (kWave - 1);
     uint64_t colany = 0;
     const Task *tp = a.tasks + t;
@@ -862,18 +746,12 @@ __global__ __launch_bounds__(kBlock) void k_bwd_count_merge(BwdArgs a) {
     flush_counts(produced, 0, 0, 0, a.ctr);
 }
 
-// D: the shortest-path DAG is stored (a.dag) and replaces the distance test.
-template <int AM, bool L, bool D>
+template <int AM, bool L>
 __global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_bwd_pull(BwdArgs a) {
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const int cg = wid / a.ntasks;                       // column-group major
     unsigned long long produced = 0, outs = 0;
-    if (cg < a.ncg) {
-        if constexpr (D)
-            bwd_task_dag<AM>(a, pick_cg<L>(a.cglist, cg), wid - cg * a.ntasks, produced, outs);
-        else
-            bwd_task<AM>(a, pick_cg<L>(a.cglist, cg), wid - cg * a.ntasks, produced, outs);
-    }
+    if (cg < a.ncg) bwd_task<AM>(a, pick_cg<L>(a.cglist, cg), wid - cg * a.ntasks, produced, outs);
     flush_counts(produced, outs, 0, 0, a.ctr);
 }
 

@@ -529,9 +529,9 @@ int mfbc_server_step_launch(mfbc_server *s, void *hip_stream) {
         c.cglist = s->cglists + ncg;
         const int grid = nblocks((size_t)c.ntasks * nbk, kWavesPerBlock, 0x7fffffff);
         switch (mode) {
-            case 0: hipLaunchKernelGGL((k_bwd_pull<0, true, true>), dim3(grid), dim3(kBlock), 0, st, c); break;
-            case 1: hipLaunchKernelGGL((k_bwd_pull<1, true, true>), dim3(grid), dim3(kBlock), 0, st, c); break;
-            default: hipLaunchKernelGGL((k_bwd_pull<2, true, true>), dim3(grid), dim3(kBlock), 0, st, c); break;
+            case 0: hipLaunchKernelGGL((k_bwd_pull<0, true>), dim3(grid), dim3(kBlock), 0, st, c); break;
+            case 1: hipLaunchKernelGGL((k_bwd_pull<1, true>), dim3(grid), dim3(kBlock), 0, st, c); break;
+            default: hipLaunchKernelGGL((k_bwd_pull<2, true>), dim3(grid), dim3(kBlock), 0, st, c); break;
         }
         const int mgrid = std::max(nblocks((size_t)c.nhubs * nbk, kWavesPerBlock, 0x7fffffff),
                                    nblocks((size_t)nw, kBlock, 1024));
