@@ -321,7 +321,9 @@ int mfbc_server_step_launch(mfbc_server *s, void *hip_stream);
 int mfbc_server_step_query(mfbc_server *s);
 
 /* Wait for the step and update the column phases; h_done[width] receives
- * the columns that finished in this step, *h_ndone their number. */
+ * the columns that finished in this step, *h_ndone their number.
+ * EOVERFLOW if a shortest-path count of some column exceeded binary64: the
+ * columns in flight then hold invalid results (free the server). */
 int mfbc_server_step_finish(mfbc_server *s, int32_t *h_done, int32_t *h_ndone,
                             void *hip_stream);
 

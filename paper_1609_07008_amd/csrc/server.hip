@@ -155,6 +155,7 @@ struct mfbc_server {
     std::vector<uint8_t> ran_f, ran_b, ran_c; // columns taking part in the launched step
     std::vector<uint8_t> open;                // [ncg] groups admitting since the last launch
     int32_t *h_stage = nullptr;               // pinned: [3][ncg] group lists, then [ncg] masks
+    int32_t *h_flags = nullptr;               // pinned copy of flags[0] (path count overflow)
     bool launched = false, any_f = false, any_b = false, any_c = false;
 };
 
@@ -207,6 +208,8 @@ void free_server(mfbc_server *s) {
     s->h_colmask = nullptr;
     if (s->h_stage) (void)hipHostFree(s->h_stage);
     s->h_stage = nullptr;
+    if (s->h_flags) (void)hipHostFree(s->h_flags);
+    s->h_flags = nullptr;
     if (s->done_ev) (void)hipEventDestroy(s->done_ev);
     s->done_ev = nullptr;
 }
@@ -282,6 +285,7 @@ int mfbc_server_create(mfbc_graph *g, int32_t width, mfbc_server **out) {
         rc = MFBC_ENOMEM;
     if (!rc && hipHostMalloc((void **)&s->h_colmask, 3 * 32 * ncg * 8) != hipSuccess) rc = MFBC_ENOMEM;
     if (!rc && hipHostMalloc((void **)&s->h_stage, 3 * ncg * 4 + ncg * 8) != hipSuccess) rc = MFBC_ENOMEM;
+    if (!rc && hipHostMalloc((void **)&s->h_flags, 16) != hipSuccess) rc = MFBC_ENOMEM;
     if (!rc && hipEventCreateWithFlags(&s->done_ev, hipEventDisableTiming) != hipSuccess)
         rc = MFBC_EDEVICE;
     if (!rc) {
@@ -562,6 +566,7 @@ int mfbc_server_step_launch(mfbc_server *s, void *hip_stream) {
     }
     SHIP(hipGetLastError());
     SHIP(hipMemcpyAsync(s->h_colmask, s->colmask, 3 * 32 * ncg * 8, hipMemcpyDeviceToHost, st));
+    SHIP(hipMemcpyAsync(s->h_flags, s->flags, 4, hipMemcpyDeviceToHost, st));
     SHIP(hipEventRecord(s->done_ev, st));
     s->launched = true;
     if (prev >= 0) (void)hipSetDevice(prev);
@@ -582,6 +587,9 @@ int mfbc_server_step_finish(mfbc_server *s, int32_t *h_done, int32_t *h_ndone, v
     if (!s->launched) return sfail(MFBC_EINVAL, "no step in flight");
     SHIP(hipStreamSynchronize((hipStream_t)hip_stream));
     s->launched = false;
+    if (s->h_flags[0])
+        return sfail(MFBC_EOVERFLOW, "a shortest-path count overflowed binary64; the results of "
+                                     "the columns in flight are invalid");
     const size_t ncg = (size_t)s->ncg;
     std::vector<uint64_t> mf(ncg, 0), mc(ncg, 0), mb(ncg, 0);
     for (size_t k = 0; k < 32; k++)

@@ -285,3 +285,27 @@ def test_results_do_not_depend_on_plan(torch, mfbc, name):
             dg.set_plan(*bad)
         assert e.value.code == mfbc.MFBC_EINVAL
     dg.close()
+
+
+def test_path_count_overflow_is_reported(torch, mfbc):
+    """1100 diamonds in series: 2^1100 shortest paths end to end, past
+    binary64.  MFBF and MFBC report EOVERFLOW; the fixpoint, which carries no
+    counts, still gives the distances."""
+    g = gg.diamond_chain(1100)
+    dg = mfbc.DeviceGraph(g)
+    src = np.array([0], dtype=np.int32)
+    with pytest.raises(mfbc.MfbcError) as e:
+        dg.forward(src)
+    assert e.value.code == mfbc.MFBC_EOVERFLOW
+    with pytest.raises(mfbc.MfbcError) as e:
+        dg.bc(src, 64)
+    assert e.value.code == mfbc.MFBC_EOVERFLOW
+    d, _ = dg.fixpoint(src, "sssp")
+    assert host_dist(d, mfbc.INF_DIST)[0, 3 * 1100] == 2 * 1100
+    # a chain of 1000 diamonds (2^1000 paths) stays finite and exact
+    g2 = gg.diamond_chain(1000)
+    dg2 = mfbc.DeviceGraph(g2)
+    f = dg2.forward(src)
+    assert f["sigma"].cpu().numpy()[0, 3 * 1000] == 2.0 ** 1000
+    dg.close()
+    dg2.close()

@@ -134,3 +134,18 @@ def test_cohort_admission(env):
     rel_close(out_b.cpu().numpy(), oracle.brandes(g, b_src, per_source=False)["lambda"], 1e-10, "b")
     assert s.free_columns() == 128
     s.close()
+
+
+def test_server_reports_path_count_overflow(env):
+    t, mfbc, serve, graphs, dgs = env
+    g = gg.diamond_chain(1100)
+    dg = mfbc.DeviceGraph(g)
+    s = serve.ColumnServer(dg, 64)
+    s.admit(np.array([0], dtype=np.int32))
+    with pytest.raises(mfbc.MfbcError) as e:
+        for _ in range(3 * 1100 + 10):
+            s.step_launch()
+            s.step_finish()
+    assert e.value.code == mfbc.MFBC_EOVERFLOW
+    s.close()
+    dg.close()
