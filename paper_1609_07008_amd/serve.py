@@ -215,7 +215,11 @@ class ServeEngine:
             while nxt < len(pending) and pending[nxt].arrival <= now:
                 r = pending[nxt]
                 self._alloc(r)
-                queues[r.graph].append(r)
+                if r.sources.size == 0:          # nothing to compute: the zero result
+                    r.done = time.perf_counter() - t0
+                    left -= 1
+                else:
+                    queues[r.graph].append(r)
                 nxt += 1
             busy = False
             for gi, srv in enumerate(self.servers):
@@ -301,7 +305,8 @@ def run_fifo(dgraphs, requests: List[Request], batch: int = 256, realtime: bool 
                 d = dg.backward(bs, f["dist"], f["sigma"])["delta"]
                 rows.append(d[:, tg])
                 del f, d
-            r.out = torch.cat(rows, dim=0)
+            r.out = torch.cat(rows, dim=0) if rows else \
+                torch.zeros((0, tg.numel()), dtype=torch.float64, device="cuda")
         torch.cuda.synchronize()
         r.done = time.perf_counter() - t0
     return requests

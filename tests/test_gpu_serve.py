@@ -149,3 +149,17 @@ def test_server_reports_path_count_overflow(env):
     assert e.value.code == mfbc.MFBC_EOVERFLOW
     s.close()
     dg.close()
+
+
+def test_empty_requests_complete(env):
+    t, mfbc, serve, graphs, dgs = env
+    reqs = [serve.Request(0, 0, "bc", np.zeros(0, dtype=np.int32), None, 0.0),
+            serve.Request(1, 1, "dep", np.zeros(0, dtype=np.int32), np.array([1, 2], dtype=np.int32), 0.0),
+            serve.Request(2, 1, "bc", gg.pick_sources(graphs[1], 5, 3), None, 0.0)]
+    eng = serve.ServeEngine(dgs[:2], [64, 64])
+    eng.run(reqs, realtime=False)
+    assert all(r.done >= 0 for r in reqs)
+    assert float(reqs[0].out.abs().sum()) == 0.0 and tuple(reqs[1].out.shape) == (0, 2)
+    rel_close(reqs[2].out.cpu().numpy(),
+              oracle.brandes(graphs[1], reqs[2].sources, per_source=False)["lambda"], 1e-10)
+    eng.close()
