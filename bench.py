@@ -73,7 +73,7 @@ def make_sources(g, spec):
 
 def kernel_sha():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "products.h", "mfbc_internal.h"):
+    for f in ("kernels.hip", "monoid.hip", "products.h", "mfbc_internal.h"):
         with open(os.path.join(ROOT, "paper_1609_07008_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
