@@ -72,10 +72,16 @@ def make_sources(g, spec):
 
 
 def kernel_sha():
+    """Hash of the kernel sources with comments and blank space removed (so a
+    record of measured traffic outlives edits that do not change the code)."""
+    import re
     h = hashlib.sha256()
     for f in ("kernels.hip", "monoid.hip", "products.h", "mfbc_internal.h"):
-        with open(os.path.join(ROOT, "paper_1609_07008_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1609_07008_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -16,17 +16,23 @@
 //    Under the centpath monoid (greatest weight wins, ties add) applied to
 //    g(a, w) = (a.w - w, ...) only successors reach weight tau(s,x); all other
 //    neighbours are lighter, so the product reduces to this equality test.
+//    The counting product also stores the shortest-path DAG: for every arc,
+//    the lane mask of the sources for which the arc is on a shortest path.
 //  * Backward product (Algorithm 2, loop): for each pending (s, x), the sum of
 //    the frontier values q(s,y) = zeta(s,y) + 1/sigma(s,y) over frontier
 //    successors y, and the number of them, which is taken off x's counter;
-//    x joins the next frontier when its counter reaches zero.
+//    x joins the next frontier when its counter reaches zero.  An arc x -> y
+//    counts in lane s iff y's frontier lane mask and the arc's DAG mask both
+//    have bit s.
 //  * lambda (Algorithm 3): delta(s,x) = zeta(s,x) * sigma(s,x) is added to a
 //    per-(column group, vertex) partial when (s,x) completes; the source's
 //    own entry is excluded (sigma(s,t,s) = 0 in Section 2.4).
 //
-// Activity filter: a one-bit-per-vertex bitmap (any column active) is
-// checked per arc first (n/8 bytes, resident in L2), then the 64-bit lane
-// mask of (u, cg); only lanes whose bit is set load the frontier tuple.
+// Activity filter: a one-bit-per-vertex bitmap per column group (any of its
+// 64 columns active; n/8 bytes, resident in L2) is checked per arc first.
+// The forward product then reads the neighbour's whole 256-B tuple row
+// (absent lanes hold a sentinel); the backward product reads the 64-bit
+// lane masks and gathers q only for the lanes that count.
 #include "products.h"
 
 namespace mfbc {

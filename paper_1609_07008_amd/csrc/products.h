@@ -441,7 +441,8 @@ __device__ __forceinline__ uint64_t count_finalize(const BwdArgs &a, size_t cgv,
 }
 
 // One task of the counting product: for every arc x -> y the lane test
-// tau(y) == tau(x) + w, eight arcs' loads in flight.
+// tau(y) == tau(x) + w, eight arcs' loads in flight; the lane masks of the
+// arcs that pass form the stored shortest-path DAG.
 template <int AM>
 __device__ __forceinline__ void count_task(const BwdArgs &a, int cg, int t, unsigned long long &produced) {
     const int lane = threadIdx.x & (kWave - 1);
