@@ -31,11 +31,10 @@
  *   - Workspace: a batch of nb sources (ceil(nb/64) groups of 64 columns)
  *     takes about 37 B per (column, vertex) -- T and two frontier buffers,
  *     which the backward state reuses -- plus 8 B per (group of 64 columns,
- *     arc) for the
- *     shortest-path DAG that the counting product stores for the backward
- *     products (1 GiB at 2^25 arcs and 256 columns).  It grows to the
- *     largest batch seen and is freed with the graph; ENOMEM if it does not
- *     fit.
+ *     arc) for the shortest-path DAG that the counting product stores for
+ *     the backward products (1 GiB at 2^25 arcs and 256 columns).  It grows
+ *     to the largest batch seen and is freed with the graph; ENOMEM if it
+ *     does not fit.
  *   - hip_stream is a hipStream_t (NULL = the default stream).  Calls are
  *     ordered on that stream and return after their outputs are complete
  *     (they synchronise on the stream to read frontier sizes).
@@ -187,8 +186,8 @@ int mfbc_backward_trace(mfbc_graph *g, const int32_t *d_sources, int32_t nb,
                         int32_t *h_products, void *hip_stream);
 
 /*
- * Work counters of the last forward/backward/bc call on a graph (sums over
- * its products).  "Entries" are frontier entries produced; "outputs" are
+ * Work counters of the last forward/backward/bc/fixpoint call on a graph
+ * (sums over its products; a fixpoint fills the forward fields).  "Entries" are frontier entries produced; "outputs" are
  * product entries that received a candidate; "active vertices/arcs" are the
  * vertices of the frontier a product read and the arcs of their rows.  The
  * *_ms fields are kernel times measured with HIP events recorded on the
