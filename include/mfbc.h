@@ -256,9 +256,10 @@ int mfbc_graph_info(const mfbc_graph *g, int32_t *n, int64_t *n_arcs,
  *   d_bc[n_graphs]        host array of device pointers, each [n_i], out.
  *   config (nullable)     launch shape: block_threads in {256, 512}
  *                         (0 = 512), blocks = persistent workgroups
- *                         (0 = two per compute unit); the block count is
- *                         capped so that the per-workgroup state fits a
- *                         quarter of the free device memory.
+ *                         (0 = enough for eight waves per SIMD on every
+ *                         compute unit: 2048 / block_threads per CU); the
+ *                         block count is capped so that the per-workgroup
+ *                         state fits a quarter of the free device memory.
  *   h_stats (nullable)    out: products over all jobs.
  * The library keeps a grow-only workspace per device for this call.
  * Errors: EINVAL, ENOMEM, EOVERFLOW, EDEVICE.

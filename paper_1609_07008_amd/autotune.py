@@ -24,7 +24,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 
 PLAN_CANDIDATES = [(64, 1), (128, 4), (256, 16), (512, 16), (256, 64), (512, 64), (1024, 64),
                    (2048, 64)]
-MANY_CANDIDATES = [(256, 4), (256, 2), (512, 2), (512, 1)]      # (threads, workgroups per CU)
+MANY_CANDIDATES = [(512, 4), (256, 8), (256, 6), (512, 2)]      # (threads, workgroups per CU)
 
 
 def _arch() -> str:

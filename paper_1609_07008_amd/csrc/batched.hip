@@ -99,8 +99,12 @@ __device__ __forceinline__ T *pick(T *const (&p)[2], int b) {
 }
 
 // AM: arc encoding shared by every graph of the launch (see load_arc).
+// Eight waves per SIMD: the loop is bound by the latency of its dependent
+// gathers, and more resident waves hide more of it than the spills (uniform
+// state kept in VGPR lanes and a small private segment) cost.
 template <int AM>
-__global__ __launch_bounds__(kManyMaxThreads) void k_bc_many(ManyArgs m) {
+__global__ __launch_bounds__(kManyMaxThreads) __attribute__((amdgpu_waves_per_eu(8)))
+void k_bc_many(ManyArgs m) {
     __shared__ int s_job;
     __shared__ unsigned long long s_cnt[3];
     const int tid = threadIdx.x, nthr = blockDim.x;

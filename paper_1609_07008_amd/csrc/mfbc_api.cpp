@@ -672,7 +672,7 @@ int mfbc_bc_many(int32_t n_graphs, mfbc_graph *const *graphs, const int32_t *con
     if (blocks == 0) {
         hipDeviceProp_t prop;
         HIP_TRY(hipGetDeviceProperties(&prop, dev));
-        blocks = 2 * prop.multiProcessorCount;
+        blocks = (2048 / block_threads) * prop.multiProcessorCount;   // 8 waves per SIMD
     }
     int n_max = 1, slots_max = 1;
     int64_t arcs_max = 1;
