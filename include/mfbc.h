@@ -64,7 +64,8 @@ enum mfbc_status {
 
 enum mfbc_flags {
     MFBC_UNDIRECTED = 1, /* symmetric CSR required and checked            */
-    MFBC_DIRECTED = 2    /* CSR lists out-arcs; distances follow arcs     */
+    MFBC_DIRECTED = 2,   /* CSR lists out-arcs; distances follow arcs     */
+    MFBC_KEEP_ORDER = 4  /* or-ed in: store vertices in the caller's order */
 };
 
 typedef struct mfbc_graph mfbc_graph;
@@ -81,7 +82,14 @@ typedef struct mfbc_graph mfbc_graph;
  *            Zero or negative weights are rejected (zero-weight cycles would
  *            give infinitely many shortest walks).
  *   flags    MFBC_UNDIRECTED (the CSR must be symmetric with equal weights on
- *            both arcs) or MFBC_DIRECTED.
+ *            both arcs) or MFBC_DIRECTED, optionally or-ed with
+ *            MFBC_KEEP_ORDER.  Without it the device copy numbers vertices
+ *            by descending degree (ties in the caller's order), which packs
+ *            the frontier rows gathered most often into fewer memory pages;
+ *            the renumbering is internal: every entry point takes and
+ *            returns the caller's vertex ids and per-vertex arrays in the
+ *            caller's order, and results equal those of MFBC_KEEP_ORDER up
+ *            to the summation order of floating-point sums.
  *   out      receives the handle.
  * Errors: EINVAL (malformed CSR, weight <= 0, asymmetric undirected input),
  * EOVERFLOW (n * max weight >= 2^31 - 1), ENOMEM, EDEVICE.

@@ -30,6 +30,7 @@ struct GraphDesc {
     ArcSrc arcs_in, arcs_out;
     const Task *tasks_in, *tasks_out;
     const Hub *hubs_in, *hubs_out;
+    const int32_t *perm;       // caller id -> device id (nullable)
 };
 
 struct JobDesc {
@@ -124,7 +125,8 @@ void k_bc_many(ManyArgs m) {
         const int n = gd.n, nw = gd.nwords;
         double *lam = m.lam_jobs + jd.lam_off;
         // ---- Algorithm 1 initialisation: T = (INF, 0), first frontier {s}
-        if (tid < kWave) sl.src[tid] = tid < jd.nsrc ? jd.src[tid] : -1;
+        if (tid < kWave)
+            sl.src[tid] = tid < jd.nsrc ? (gd.perm ? gd.perm[jd.src[tid]] : jd.src[tid]) : -1;
         for (int i = tid; i < n * kWave; i += nthr) {
             sl.tdist[i] = kInf;
             sl.tsig[i] = 0.0;
@@ -269,13 +271,15 @@ void k_bc_many(ManyArgs m) {
     }
 }
 
-// lambda of graph g: the job slices summed in job order.
+// lambda of graph g at caller vertex v: the job slices summed in job order.
 __global__ void k_many_reduce(const double *lam_jobs, const int64_t *job_off, const int32_t *jbeg,
-                              const int32_t *jcnt, const int32_t *order, int n, double *out) {
+                              const int32_t *jcnt, const int32_t *order, int n, double *out,
+                              const int32_t *perm) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
+    const int d = perm ? perm[v] : v;
     double t = 0.0;
-    for (int i = 0; i < jcnt[0]; i++) t += lam_jobs[job_off[order[jbeg[0] + i]] + v];
+    for (int i = 0; i < jcnt[0]; i++) t += lam_jobs[job_off[order[jbeg[0] + i]] + d];
     out[v] = t;
 }
 
@@ -368,6 +372,7 @@ int launch_bc_many(std::vector<mfbc_graph *> &graphs, const std::vector<const in
         d.tasks_out = g->plan_out.tasks;
         d.hubs_in = g->plan_in.hubs;
         d.hubs_out = g->plan_out.hubs;
+        d.perm = g->perm;
         n_max = std::max(n_max, g->n);
         slots_max = std::max({slots_max, g->plan_in.nslots, g->plan_out.nslots});
         arcs_max = std::max<int64_t>(arcs_max, g->arcs);
@@ -478,7 +483,7 @@ int launch_bc_many(std::vector<mfbc_graph *> &graphs, const std::vector<const in
         hipLaunchKernelGGL(k_many_reduce, dim3((n + 255) / 256), dim3(256), 0, s, ws.lam_jobs,
                            (const int64_t *)(meta + o_joff), (const int32_t *)(meta + o_jbeg) + i,
                            (const int32_t *)(meta + o_jcnt) + i, (const int32_t *)(meta + o_jidx),
-                           n, d_bc[(size_t)i]);
+                           n, d_bc[(size_t)i], (const int32_t *)graphs[(size_t)i]->perm);
     }
     if (hipGetLastError() != hipSuccess) {
         err = "kernel launch failed";

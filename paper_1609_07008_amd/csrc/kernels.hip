@@ -38,9 +38,14 @@
 namespace mfbc {
 namespace {
 // ===================================================================== setup / io
-__global__ void k_set_sources(int32_t *src, int total, int nb, const int32_t *in) {
+// In every kernel here `perm` (nullable) maps a caller vertex id to the
+// device numbering; the products themselves only see device ids.
+__device__ __forceinline__ int dev_id(const int32_t *perm, int v) { return perm ? perm[v] : v; }
+
+__global__ void k_set_sources(int32_t *src, int total, int nb, const int32_t *in,
+                              const int32_t *perm) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < total) src[i] = i < nb ? in[i] : -1;
+    if (i < total) src[i] = i < nb ? dev_id(perm, in[i]) : -1;
 }
 
 // T = (INF, 0) everywhere, both frontier bitmaps cleared, counters zeroed.
@@ -90,24 +95,31 @@ __global__ void k_zero_f64(double *p, size_t total) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) p[i] = 0.0;
 }
 
-__global__ void k_lambda_reduce(const double *lam, int ncg, int n, double *bc) {
+// bc[v] for caller vertex v (written in caller order, coalesced).
+__global__ void k_lambda_reduce(const double *lam, int ncg, int n, double *bc,
+                                const int32_t *perm) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
+    const int d = dev_id(perm, v);
     double t = 0.0;
-    for (int cg = 0; cg < ncg; cg++) t += lam[(size_t)cg * n + v];
+    for (int cg = 0; cg < ncg; cg++) t += lam[(size_t)cg * n + d];
     bc[v] = t;
 }
 
-// Tile transposes between [cg][v][64] tiles and source-major rows [s][v],
-// 64 x 64 per block through LDS (padded against bank conflicts).
+// Tile transposes between [cg][v][64] tiles (device numbering) and
+// source-major rows [s][v] (caller numbering), 64 x 64 per block through LDS
+// (padded against bank conflicts).  A block covers 64 consecutive caller
+// vertices: the row side stays coalesced, the tile side moves whole 256-B
+// tile rows.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_tiles_to_rows(const T *tiles, T *rows, int n, int nb) {
+__global__ __launch_bounds__(kBlock) void k_tiles_to_rows(const T *tiles, T *rows, int n, int nb,
+                                                          const int32_t *perm) {
     __shared__ T sh[64][65];
     const int cg = blockIdx.y, v0 = blockIdx.x * 64;
     const int c = threadIdx.x & 63, r0 = threadIdx.x >> 6;
     for (int r = r0; r < 64; r += 4) {
         const int v = v0 + r;
-        if (v < n) sh[r][c] = tiles[((size_t)cg * n + v) * 64 + c];
+        if (v < n) sh[r][c] = tiles[((size_t)cg * n + dev_id(perm, v)) * 64 + c];
     }
     __syncthreads();
     for (int r = r0; r < 64; r += 4) {
@@ -118,7 +130,7 @@ __global__ __launch_bounds__(kBlock) void k_tiles_to_rows(const T *tiles, T *row
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_rows_to_tiles(const T *rows, T *tiles, int n, int nb,
-                                                          T pad) {
+                                                          T pad, const int32_t *perm) {
     __shared__ T sh[64][65];
     const int cg = blockIdx.y, v0 = blockIdx.x * 64;
     const int c = threadIdx.x & 63, r0 = threadIdx.x >> 6;
@@ -129,22 +141,24 @@ __global__ __launch_bounds__(kBlock) void k_rows_to_tiles(const T *rows, T *tile
     __syncthreads();
     for (int r = r0; r < 64; r += 4) {
         const int v = v0 + r;
-        if (v < n) tiles[((size_t)cg * n + v) * 64 + c] = sh[r][c];
+        if (v < n) tiles[((size_t)cg * n + dev_id(perm, v)) * 64 + c] = sh[r][c];
     }
 }
 
 // delta(s, v) = zeta(s, v) * sigma(s, v), 0 at the source and where unreachable.
 __global__ __launch_bounds__(kBlock) void k_delta_rows(const double *zeta, const double *tsig,
                                                        const int32_t *tdist, const int32_t *src,
-                                                       double *rows, int n, int nb) {
+                                                       double *rows, int n, int nb,
+                                                       const int32_t *perm) {
     __shared__ double sh[64][65];
     const int cg = blockIdx.y, v0 = blockIdx.x * 64;
     const int c = threadIdx.x & 63, r0 = threadIdx.x >> 6;
     for (int r = r0; r < 64; r += 4) {
         const int v = v0 + r;
         if (v < n) {
-            const size_t idx = ((size_t)cg * n + v) * 64 + c;
-            const bool ok = tdist[idx] != kInf && src[cg * 64 + c] != v;
+            const int d = dev_id(perm, v);
+            const size_t idx = ((size_t)cg * n + d) * 64 + c;
+            const bool ok = tdist[idx] != kInf && src[cg * 64 + c] != d;
             sh[r][c] = ok ? zeta[idx] * tsig[idx] : 0.0;
         }
     }
@@ -215,7 +229,7 @@ static FwdArgs fwd_args(mfbc_graph *g, int ncg, int j, bool trace) {
 void launch_set_sources(mfbc_graph *g, int ncg, int nb, const int32_t *d_sources, hipStream_t s) {
     const int total = ncg * kWave;
     hipLaunchKernelGGL(k_set_sources, dim3(blocks_for(total, 256)), dim3(256), 0, s, g->ws.src,
-                       total, nb, d_sources);
+                       total, nb, d_sources, (const int32_t *)g->perm);
 }
 
 void launch_fwd_init(mfbc_graph *g, int ncg, int nb, hipStream_t s) {
@@ -345,34 +359,37 @@ void launch_lambda_zero(mfbc_graph *g, int ncg, hipStream_t s) {
 
 void launch_lambda_reduce(mfbc_graph *g, int ncg, double *d_bc, hipStream_t s) {
     hipLaunchKernelGGL(k_lambda_reduce, dim3(blocks_for(g->n, 256)), dim3(256), 0, s, g->ws.lam,
-                       ncg, g->n, d_bc);
+                       ncg, g->n, d_bc, (const int32_t *)g->perm);
 }
 
 void launch_export_forward(mfbc_graph *g, int ncg, int nb, int32_t *d_dist, double *d_sigma,
                            uint64_t *d_fmask, hipStream_t s) {
     dim3 grid((g->n + 63) / 64, ncg);
+    const int32_t *perm = g->perm;
     hipLaunchKernelGGL(k_tiles_to_rows<int32_t>, grid, dim3(kBlock), 0, s, g->ws.tdist, d_dist,
-                       g->n, nb);
+                       g->n, nb, perm);
     hipLaunchKernelGGL(k_tiles_to_rows<double>, grid, dim3(kBlock), 0, s, g->ws.tsig, d_sigma,
-                       g->n, nb);
+                       g->n, nb, perm);
     if (d_fmask)
         hipLaunchKernelGGL(k_tiles_to_rows<uint64_t>, grid, dim3(kBlock), 0, s,
-                           (const uint64_t *)g->ws.fmask, d_fmask, g->n, nb);
+                           (const uint64_t *)g->ws.fmask, d_fmask, g->n, nb, perm);
 }
 
 void launch_export_tiles_i32(mfbc_graph *g, int ncg, int nb, const int32_t *tiles, int32_t *d_rows,
                              hipStream_t s) {
     dim3 grid((g->n + 63) / 64, ncg);
-    hipLaunchKernelGGL(k_tiles_to_rows<int32_t>, grid, dim3(kBlock), 0, s, tiles, d_rows, g->n, nb);
+    hipLaunchKernelGGL(k_tiles_to_rows<int32_t>, grid, dim3(kBlock), 0, s, tiles, d_rows, g->n, nb,
+                       (const int32_t *)g->perm);
 }
 
 void launch_import_forward(mfbc_graph *g, int ncg, int nb, const int32_t *d_dist,
                            const double *d_sigma, hipStream_t s) {
     dim3 grid((g->n + 63) / 64, ncg);
+    const int32_t *perm = g->perm;
     hipLaunchKernelGGL(k_rows_to_tiles<int32_t>, grid, dim3(kBlock), 0, s, d_dist, g->ws.tdist,
-                       g->n, nb, (int32_t)kInf);
+                       g->n, nb, (int32_t)kInf, perm);
     hipLaunchKernelGGL(k_rows_to_tiles<double>, grid, dim3(kBlock), 0, s, d_sigma, g->ws.tsig,
-                       g->n, nb, 0.0);
+                       g->n, nb, 0.0, perm);
 }
 
 void launch_export_backward(mfbc_graph *g, int ncg, int nb, double *d_delta, int32_t *d_step,
@@ -380,10 +397,11 @@ void launch_export_backward(mfbc_graph *g, int ncg, int nb, double *d_delta, int
     dim3 grid((g->n + 63) / 64, ncg);
     hipLaunchKernelGGL(k_delta_rows, grid, dim3(kBlock), 0, s, (const double *)g->ws.fsig[0],
                        (const double *)g->ws.tsig, (const int32_t *)g->ws.tdist,
-                       (const int32_t *)g->ws.src, d_delta, g->n, nb);
+                       (const int32_t *)g->ws.src, d_delta, g->n, nb, (const int32_t *)g->perm);
     if (d_step)
         hipLaunchKernelGGL(k_tiles_to_rows<int32_t>, grid, dim3(kBlock), 0, s,
-                           (const int32_t *)g->ws.fdist[1], d_step, g->n, nb);
+                           (const int32_t *)g->ws.fdist[1], d_step, g->n, nb,
+                           (const int32_t *)g->perm);
 }
 
 }  // namespace mfbc

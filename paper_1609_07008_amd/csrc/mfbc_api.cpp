@@ -349,6 +349,43 @@ bool build_transpose(int32_t n, int64_t arcs, const int64_t *rp, const int32_t *
     return true;
 }
 
+// Descending-degree vertex order (in- plus out-degree, ties by id):
+// perm[v] = position of caller vertex v, iperm = its inverse.
+void degree_order(int32_t n, int64_t arcs, const int64_t *rp, const int32_t *col,
+                  std::vector<int32_t> &perm, std::vector<int32_t> &iperm) {
+    std::vector<int64_t> key((size_t)n, 0);
+    for (int32_t v = 0; v < n; v++) key[(size_t)v] += rp[v + 1] - rp[v];
+    for (int64_t e = 0; e < arcs; e++) key[(size_t)col[e]]++;
+    iperm.resize((size_t)n);
+    for (int32_t v = 0; v < n; v++) iperm[(size_t)v] = v;
+    std::stable_sort(iperm.begin(), iperm.end(),
+                     [&](int32_t a, int32_t b) { return key[(size_t)a] > key[(size_t)b]; });
+    perm.resize((size_t)n);
+    for (int32_t r = 0; r < n; r++) perm[(size_t)iperm[(size_t)r]] = r;
+}
+
+// Reverse graph in the new numbering: row perm[x] lists perm[u] for every
+// arc u -> x, ascending (rows are visited in new-id order), with the weights.
+void relabel_reverse(int32_t n, int64_t arcs, const int64_t *rp, const int32_t *col,
+                     const int32_t *w, const std::vector<int32_t> &perm,
+                     const std::vector<int32_t> &iperm, std::vector<int64_t> &rpr,
+                     std::vector<int32_t> &colr, std::vector<int32_t> &wr) {
+    rpr.assign((size_t)n + 1, 0);
+    for (int64_t e = 0; e < arcs; e++) rpr[(size_t)perm[(size_t)col[e]] + 1]++;
+    for (int32_t v = 0; v < n; v++) rpr[(size_t)v + 1] += rpr[(size_t)v];
+    colr.assign((size_t)arcs, 0);
+    if (w) wr.assign((size_t)arcs, 0);
+    std::vector<int64_t> pos(rpr.begin(), rpr.end() - 1);
+    for (int32_t r = 0; r < n; r++) {
+        const int32_t u = iperm[(size_t)r];
+        for (int64_t e = rp[u]; e < rp[u + 1]; e++) {
+            const int64_t p = pos[(size_t)perm[(size_t)col[e]]]++;
+            colr[(size_t)p] = r;
+            if (w) wr[(size_t)p] = w[e];
+        }
+    }
+}
+
 int bits_for(int64_t x) {
     int b = 0;
     while (x > 0) {
@@ -405,6 +442,8 @@ void free_graph_memory(mfbc_graph *g) {
         dfree(g->in.pk);
     }
     g->in = Csr{};
+    dfree(g->perm);
+    g->h_perm.clear();
 }
 
 }  // namespace
@@ -421,8 +460,10 @@ int mfbc_load_graph(int32_t n, int64_t n_arcs, const int64_t *h_row_ptr, const i
     if (n_arcs < 0) return fail(MFBC_EINVAL, "n_arcs must be >= 0");
     if (!h_row_ptr) return fail(MFBC_EINVAL, "row_ptr is NULL");
     if (n_arcs > 0 && !h_col_idx) return fail(MFBC_EINVAL, "col_idx is NULL");
-    if (flags != MFBC_UNDIRECTED && flags != MFBC_DIRECTED)
-        return fail(MFBC_EINVAL, "flags must be MFBC_UNDIRECTED or MFBC_DIRECTED");
+    const uint32_t kind = flags & ~(uint32_t)MFBC_KEEP_ORDER;
+    if (kind != MFBC_UNDIRECTED && kind != MFBC_DIRECTED)
+        return fail(MFBC_EINVAL, "flags must be MFBC_UNDIRECTED or MFBC_DIRECTED "
+                                 "(optionally | MFBC_KEEP_ORDER)");
     if (h_row_ptr[0] != 0 || h_row_ptr[n] != n_arcs)
         return fail(MFBC_EINVAL, "row_ptr[0] must be 0 and row_ptr[n] must equal n_arcs");
     int32_t maxw = 1;
@@ -447,12 +488,33 @@ int mfbc_load_graph(int32_t n, int64_t n_arcs, const int64_t *h_row_ptr, const i
     std::vector<int64_t> rpt;
     std::vector<int32_t> colt, wt;
     build_transpose(n, n_arcs, h_row_ptr, h_col_idx, h_weight, rpt, colt, wt);
-    const bool directed = flags == MFBC_DIRECTED;
+    const bool directed = kind == MFBC_DIRECTED;
     if (!directed) {
         if (!std::equal(rpt.begin(), rpt.end(), h_row_ptr) ||
             !std::equal(colt.begin(), colt.end(), h_col_idx) ||
             (h_weight && !std::equal(wt.begin(), wt.end(), h_weight)))
             return fail(MFBC_EINVAL, "undirected graph must have a symmetric CSR with equal weights");
+    }
+    // device numbering: out-arcs (rp_o, col_o, w_o) and in-arcs (rpt, colt, wt)
+    const int64_t *rp_o = h_row_ptr;
+    const int32_t *col_o = h_col_idx, *w_o = h_weight;
+    std::vector<int32_t> perm, iperm;
+    std::vector<int64_t> rpo;
+    std::vector<int32_t> colo, wo;
+    if (!(flags & MFBC_KEEP_ORDER)) {
+        degree_order(n, n_arcs, h_row_ptr, h_col_idx, perm, iperm);
+        relabel_reverse(n, n_arcs, h_row_ptr, h_col_idx, h_weight, perm, iperm, rpt, colt, wt);
+        if (directed) {
+            build_transpose(n, n_arcs, rpt.data(), colt.data(), h_weight ? wt.data() : nullptr,
+                            rpo, colo, wo);
+            rp_o = rpo.data();
+            col_o = colo.data();
+            w_o = h_weight ? wo.data() : nullptr;
+        } else {
+            rp_o = rpt.data();
+            col_o = colt.data();
+            w_o = h_weight ? wt.data() : nullptr;
+        }
     }
     mfbc_graph *g = new (std::nothrow) mfbc_graph();
     if (!g) return fail(MFBC_ENOMEM, "host allocation failed");
@@ -468,7 +530,7 @@ int mfbc_load_graph(int32_t n, int64_t n_arcs, const int64_t *h_row_ptr, const i
     // packed frontier tuples: weight bits for (n - 1) * max weight (+1 so that
     // no tuple equals the all-ones "absent" marker), the rest for multiplicities
     g->mb = 32 - bits_for((int64_t)(n - 1) * maxw + 1);
-    int rc = upload_csr(n, n_arcs, h_row_ptr, h_col_idx, h_weight, maxw, g->out);
+    int rc = upload_csr(n, n_arcs, rp_o, col_o, w_o, maxw, g->out);
     if (!rc) {
         if (directed)
             rc = upload_csr(n, n_arcs, rpt.data(), colt.data(), h_weight ? wt.data() : nullptr,
@@ -476,8 +538,16 @@ int mfbc_load_graph(int32_t n, int64_t n_arcs, const int64_t *h_row_ptr, const i
         else
             g->in = g->out;
     }
+    if (!rc && !perm.empty()) {
+        if (!(rc = dalloc(&g->perm, (size_t)n))) {
+            if (hipMemcpy(g->perm, perm.data(), (size_t)n * sizeof(int32_t),
+                          hipMemcpyHostToDevice) != hipSuccess)
+                rc = fail(MFBC_EDEVICE, "copy of the vertex order failed");
+            g->h_perm = std::move(perm);
+        }
+    }
     g->params = default_params(n, n_arcs);
-    g->h_rp_out.assign(h_row_ptr, h_row_ptr + (size_t)n + 1);
+    g->h_rp_out.assign(rp_o, rp_o + (size_t)n + 1);
     g->h_rp_in = directed ? rpt : g->h_rp_out;
     if (!rc) rc = upload_plan(n, g->h_rp_out.data(), g->params, g->plan_out);
     if (!rc) rc = upload_plan(n, g->h_rp_in.data(), g->params, g->plan_in);

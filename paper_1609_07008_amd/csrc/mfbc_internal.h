@@ -106,6 +106,11 @@ struct mfbc_graph {
     mfbc::Workspace ws;
     mfbc_stats stats{};
     std::vector<int64_t> h_rp_out, h_rp_in;   // host copies for re-planning
+    // Vertex order of the device copy: caller id v is stored as vertex perm[v]
+    // (null / empty when the caller's order is kept).  Every entry point maps
+    // sources through it and gathers per-vertex outputs back.
+    int32_t *perm = nullptr;
+    std::vector<int32_t> h_perm;
     bool timing = false;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
 };

@@ -84,28 +84,32 @@ __global__ void k_srv_seed(int n, int nwords, const int32_t *cols, int count, co
 }
 
 // dest_i[v] += delta(column cols[i], v) for every listed column, in list
-// order (one thread per vertex, so a destination shared by several columns
-// is updated without races and in a fixed order).
+// order (one thread per caller vertex v, so a destination shared by several
+// columns is updated without races and in a fixed order).  `perm`
+// (nullable) maps caller ids to the device numbering of the tiles.
 __global__ void k_srv_harvest_bc(int n, const int32_t *cols, int count, const int32_t *src,
                                  double *const *dest, const int32_t *tdist, const double *tsig,
-                                 const double *zeta) {
+                                 const double *zeta, const int32_t *perm) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
+    const int d = perm ? perm[v] : v;
     for (int i = 0; i < count; i++) {
         const int c = cols[i], cg = c / kWave, lane = c % kWave;
-        const size_t idx = ((size_t)cg * n + v) * kWave + lane;
-        if (tdist[idx] != kInf && v != src[c]) dest[i][v] += zeta[idx] * tsig[idx];
+        const size_t idx = ((size_t)cg * n + d) * kWave + lane;
+        if (tdist[idx] != kInf && d != src[c]) dest[i][v] += zeta[idx] * tsig[idx];
     }
 }
 
-// out_i[t] = delta(column cols[i], targets[t]).
+// out_i[t] = delta(column cols[i], targets[t]) (targets in caller ids).
 __global__ void k_srv_harvest_dep(int n, const int32_t *cols, int count, const int32_t *src,
                                   const int32_t *targets, int ntargets, double *const *out,
-                                  const int32_t *tdist, const double *tsig, const double *zeta) {
+                                  const int32_t *tdist, const double *tsig, const double *zeta,
+                                  const int32_t *perm) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= count * ntargets) return;
     const int i = k / ntargets, t = k % ntargets;
-    const int c = cols[i], cg = c / kWave, lane = c % kWave, v = targets[t];
+    const int c = cols[i], cg = c / kWave, lane = c % kWave;
+    const int v = perm ? perm[targets[t]] : targets[t];
     const size_t idx = ((size_t)cg * n + v) * kWave + lane;
     out[i][t] = (tdist[idx] != kInf && v != src[c]) ? zeta[idx] * tsig[idx] : 0.0;
 }
@@ -378,7 +382,9 @@ int mfbc_server_admit(mfbc_server *s, const int32_t *h_sources, int32_t count, i
     for (int i = 0; i < count; i++) {
         const int c = cols[(size_t)i];
         h_columns[i] = c;
-        s->h_src[(size_t)c] = h_sources[i];
+        // columns hold device vertex ids
+        s->h_src[(size_t)c] = s->g->h_perm.empty() ? h_sources[i]
+                                                   : s->g->h_perm[(size_t)h_sources[i]];
         s->phase[(size_t)c] = kFwd;
         s->open[(size_t)(c / 64)] = 1;
         nm[(size_t)(c / 64)] |= 1ull << (c % 64);
@@ -647,7 +653,8 @@ int mfbc_server_harvest_bc(mfbc_server *s, const int32_t *h_columns, int32_t cou
     hipLaunchKernelGGL(k_srv_harvest_bc, dim3(nblocks((size_t)n, 256)), dim3(256), 0, st, n,
                        (const int32_t *)(s->meta + o_col), count, (const int32_t *)s->src,
                        (double *const *)(s->meta + o_ptr), (const int32_t *)s->tdist,
-                       (const double *)s->tsig, (const double *)s->zeta);
+                       (const double *)s->tsig, (const double *)s->zeta,
+                       (const int32_t *)s->g->perm);
     SHIP(hipGetLastError());
     SHIP(hipStreamSynchronize(st));
     release(s, h_columns, count);
@@ -681,7 +688,8 @@ int mfbc_server_harvest_dep(mfbc_server *s, const int32_t *h_columns, int32_t co
                            0, st, s->g->n, (const int32_t *)(s->meta + o_col), count,
                            (const int32_t *)s->src, d_targets, ntargets,
                            (double *const *)(s->meta + o_ptr), (const int32_t *)s->tdist,
-                           (const double *)s->tsig, (const double *)s->zeta);
+                           (const double *)s->tsig, (const double *)s->zeta,
+                           (const int32_t *)s->g->perm);
     SHIP(hipGetLastError());
     SHIP(hipStreamSynchronize(st));
     release(s, h_columns, count);

@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmfbc.so")
 
 MFBC_OK, MFBC_EINVAL, MFBC_ENOMEM, MFBC_EDEVICE, MFBC_EOVERFLOW = 0, -1, -2, -3, -4
-MFBC_UNDIRECTED, MFBC_DIRECTED = 1, 2
+MFBC_UNDIRECTED, MFBC_DIRECTED, MFBC_KEEP_ORDER = 1, 2, 4
 INF_DIST = 0x7FFFFFFF
 OP_SSSP, OP_BFS = 0, 1
 
@@ -104,7 +104,10 @@ def _ptr(t) -> ctypes.c_void_p:
 class DeviceGraph:
     """A graph resident on the current HIP device (handle of ``mfbc_load_graph``)."""
 
-    def __init__(self, g, directed: Optional[bool] = None):
+    def __init__(self, g, directed: Optional[bool] = None, keep_order: bool = False):
+        """``keep_order``: store vertices in the caller's order instead of the
+        library's descending-degree order (results are the same either way,
+        up to the summation order of floating-point sums)."""
         import torch
         self._torch = torch
         lib = load_library()
@@ -117,7 +120,8 @@ class DeviceGraph:
         rc = lib.mfbc_load_graph(
             int(g.n), int(rp[-1]), rp.ctypes.data_as(_P), col.ctypes.data_as(_P),
             None if w is None else w.ctypes.data_as(_P),
-            MFBC_DIRECTED if directed else MFBC_UNDIRECTED, _stream(torch), ctypes.byref(h))
+            (MFBC_DIRECTED if directed else MFBC_UNDIRECTED) | (MFBC_KEEP_ORDER if keep_order else 0),
+            _stream(torch), ctypes.byref(h))
         _check(rc)
         self.handle = h
         self.n = int(g.n)
