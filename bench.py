@@ -29,10 +29,10 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, AMD published
 WORKLOADS = {
     # weighted R-MAT scale 20 (the headline): 1024 sources in batches of 256
     "rmat20_w255": dict(kind="rmat", scale=20, ef=16, wrange=(1, 255), seed=3,
-                        n_sources=1024, source_seed=103, batch=256, cpu_sample=128),
+                        n_sources=1024, source_seed=103, batch=256, cpu_sample=256),
     # dense Erdos-Renyi, same weights and sources
     "er32k_k512_w255": dict(kind="er", n=32768, k=512, wrange=(1, 255), seed=4,
-                            n_sources=1024, source_seed=104, batch=256, cpu_sample=96),
+                            n_sources=1024, source_seed=104, batch=256, cpu_sample=1024),
     # unweighted R-MAT scale 16, approximate BC from 4096 sources
     "rmat16_unw": dict(kind="rmat", scale=16, ef=16, wrange=None, seed=2,
                        n_sources=4096, source_seed=102, batch=512, cpu_sample=4096),
@@ -42,9 +42,9 @@ WORKLOADS = {
     # monoid fixpoints on the headline graph and sources: shortest distances
     # (min, +w) and hop levels (min, +1) from 1024 sources in batches of 256
     "sssp_rmat20_w255": dict(kind="fixpoint", op="sssp", scale=20, ef=16, wrange=(1, 255), seed=3,
-                             n_sources=1024, source_seed=103, batch=256, cpu_sample=2),
+                             n_sources=1024, source_seed=103, batch=256, cpu_sample=6),
     "bfs_rmat20": dict(kind="fixpoint", op="bfs", scale=20, ef=16, wrange=(1, 255), seed=3,
-                       n_sources=1024, source_seed=103, batch=256, cpu_sample=2),
+                       n_sources=1024, source_seed=103, batch=256, cpu_sample=10),
     # batched form: 256 ER / R-MAT graphs, n log-uniform in [200, 20000], average
     # degree uniform in [4, 64], weights 1..100, exact BC of every graph
     "batched256": dict(kind="many", count=256, seed0=1000, cpu_sample=48),

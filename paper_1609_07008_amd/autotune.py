@@ -16,6 +16,7 @@ from __future__ import annotations
 import json
 import math
 import os
+import sys
 import time
 
 import numpy as np
@@ -83,7 +84,8 @@ def tune_plan(dg, g, sources, batch: int, reps: int = 2, cache: dict = None, ver
         dg.set_plan(run_arcs=ra, run_verts=rv)
         res[(ra, rv)] = _time(lambda: dg.bc(src, batch), reps)
         if verbose:
-            print(f"[tune] {g.name} run_arcs={ra} run_verts={rv}: {res[(ra, rv)] * 1e3:.2f} ms")
+            print(f"[tune] {g.name} run_arcs={ra} run_verts={rv}: {res[(ra, rv)] * 1e3:.2f} ms",
+                  file=sys.stderr, flush=True)
     best = min(res, key=res.get)
     dg.set_plan(run_arcs=best[0], run_verts=best[1])
     if cache is not None:
@@ -112,7 +114,8 @@ def tune_many(dgs, srcs, reps: int = 1, cache: dict = None, verbose=False):
         cfg = dict(block_threads=threads, blocks=per_cu * cus)
         res[(threads, per_cu)] = _time(lambda: mfbc.bc_many(dgs, srcs, outs=outs, **cfg), reps)
         if verbose:
-            print(f"[tune] many threads={threads} per_cu={per_cu}: {res[(threads, per_cu)]:.3f} s")
+            print(f"[tune] many threads={threads} per_cu={per_cu}: {res[(threads, per_cu)]:.3f} s",
+                  file=sys.stderr, flush=True)
     best = min(res, key=res.get)
     if cache is not None:
         cache["many"] = {"block_threads": best[0], "per_cu": best[1], "s": res[best]}
