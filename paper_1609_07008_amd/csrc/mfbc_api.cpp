@@ -123,6 +123,7 @@ int upload_plan(int32_t n, const int64_t *h_rp, const TaskParams &prm, Plan &pla
 // Grow the workspace to `ncg` column groups (and the trace mask if asked).
 int ensure_workspace(mfbc_graph *g, int ncg, bool trace) {
     Workspace &ws = g->ws;
+    ncg = (ncg + 1) & ~1;   // the forward product's paired layout needs whole pairs
     if (ws.ncg < ncg) {
         free_workspace(ws);
         const size_t n = (size_t)g->n;

@@ -178,7 +178,14 @@ struct FwdArgs {
     unsigned long long *colmask;    // nullable: [32][ncg_all] columns that produced entries
     const int32_t *cglist;     // nullable: the ncg column groups of this launch (else 0..ncg-1)
     int ncg_all;               // column groups of the state (strides of colmask, bitmap planes)
+    int npair;                 // paired layout: column-group pairs (0: one group per wave)
 };
+
+// T := T (+) G at one entry (idx = (cg, v, lane)) given its candidate
+// (bd, bm); returns the packed tuple of the next frontier, kSent if the
+// entry is not in it (no candidate, or a heavier one).  `tdin` as below.
+__device__ __forceinline__ uint32_t fwd_update(const FwdArgs &a, size_t idx, int bd, double bm,
+                                               int tdin);
 
 // T := T (+) G at (v, cg); writes the next frontier row.  Returns the lane
 // mask of the frontier entries produced.
@@ -189,41 +196,38 @@ constexpr int kLoadTd = -1;
 __device__ __forceinline__ uint64_t fwd_finalize(const FwdArgs &a, size_t cgv, int v, int bd,
                                                  double bm, int tdin, int lane,
                                                  unsigned long long &outs) {
-    const bool has = bd != kInf;
     uint64_t bits = 0;
-    const uint64_t hm = ballot(has);
+    const uint64_t hm = ballot(bd != kInf);
     outs += __popcll(hm);
     if (hm) {
         const size_t idx = (cgv + (size_t)v) * kWave + lane;
-        bool keep = false;
-        if (has) {
-            const int td = tdin == kLoadTd ? a.tdist[idx] : tdin;
-            if (bd < td) {
-                a.tdist[idx] = bd;
-                a.tsig[idx] = bm;
-                keep = true;
-                if (__builtin_isinf(bm)) a.flags[0] = 1;
-            } else if (bd == td) {
-                const double s = a.tsig[idx] + bm;
-                a.tsig[idx] = s;
-                keep = true;
-                if (__builtin_isinf(s)) a.flags[0] = 1;
-            }
-        }
-        bits = ballot(keep);
-        if (bits) {
-            uint32_t t = kSent;
-            if (keep) {
-                const double mmax = (double)((1u << a.mb) - 1u);
-                const uint32_t ms = bm <= mmax ? (uint32_t)bm : 0u;
-                if (ms == 0u) a.fsig_n[idx] = bm;
-                t = ((uint32_t)bd << a.mb) | ms;
-                if (a.fmask && a.j <= 64) a.fmask[idx] |= 1ull << (a.j - 1);
-            }
-            a.ftup_n[idx] = t;
-        }
+        const uint32_t t = fwd_update(a, idx, bd, bm, tdin);
+        bits = ballot(t != kSent);
+        if (bits) a.ftup_n[idx] = t;
     }
     return bits;
+}
+
+__device__ __forceinline__ uint32_t fwd_update(const FwdArgs &a, size_t idx, int bd, double bm,
+                                               int tdin) {
+    if (bd == kInf) return kSent;
+    const int td = tdin == kLoadTd ? a.tdist[idx] : tdin;
+    if (bd < td) {
+        a.tdist[idx] = bd;
+        a.tsig[idx] = bm;
+        if (__builtin_isinf(bm)) a.flags[0] = 1;
+    } else if (bd == td) {
+        const double s = a.tsig[idx] + bm;
+        a.tsig[idx] = s;
+        if (__builtin_isinf(s)) a.flags[0] = 1;
+    } else {
+        return kSent;
+    }
+    const double mmax = (double)((1u << a.mb) - 1u);
+    const uint32_t ms = bm <= mmax ? (uint32_t)bm : 0u;
+    if (ms == 0u) a.fsig_n[idx] = bm;
+    if (a.fmask && a.j <= 64) a.fmask[idx] |= 1ull << (a.j - 1);
+    return ((uint32_t)bd << a.mb) | ms;
 }
 
 // Active arcs per batch and whether a batch's escaped multiplicities are
@@ -381,6 +385,197 @@ __device__ __forceinline__ void fwd_hub(const FwdArgs &a, int cg, int h, unsigne
     colany |= b;
     if (b && lane == 0) atomicOr(a.abits_n + (size_t)cg * a.nwords + (v >> 5), 1u << (v & 31));
     flush_colmask(a.colmask, a.ncg_all, cg, colany);
+}
+
+// ===================================================================== forward, paired
+//
+// The plain path runs the forward product on pairs of column groups: the
+// frontier rows of groups 2p and 2p+1 are interleaved ([p][v][64] x 2 x
+// 32 bits, one 8-byte entry per lane), so a lane holds two columns and one
+// load instruction gathers the frontier row of both groups.  A gather's cost
+// is set by its instruction more than by its bytes (a 64-lane load of 256 B
+// and one of 512 B issue at about the same rate from L2), so a pair halves
+// the gathers, the arc loads and the activity tests of a product.  T and the
+// escaped multiplicities keep the one-group layout; the activity bitmap is
+// per pair (a vertex active in a column of either group), and the writer
+// fills both halves of a row (kSent where a lane is not in the frontier), so
+// a row marked active holds valid tuples for both groups.
+
+// Active arcs per batch in the paired form (two columns per lane take twice
+// the registers per arc; four weighted arcs at seven waves per SIMD measured
+// faster than two at eight or three at seven).
+template <int AM> constexpr int kFwdBatch2 = AM == 0 ? 2 : 4;
+
+// T := T (+) G at (v, 2p) and (v, 2p+1); writes the next frontier's pair
+// row.  Returns the lanes in the next frontier in either group.
+__device__ __forceinline__ uint64_t fwd_finalize2(const FwdArgs &a, int p, int v, int bd0,
+                                                  double bm0, int td0, int bd1, double bm1,
+                                                  int td1, int lane, unsigned long long &outs,
+                                                  unsigned long long &produced) {
+    const uint64_t h0 = ballot(bd0 != kInf), h1 = ballot(bd1 != kInf);
+    outs += __popcll(h0) + __popcll(h1);
+    if (!(h0 | h1)) return 0;
+    const size_t n = (size_t)a.n;
+    const size_t i0 = ((size_t)(2 * p) * n + (size_t)v) * kWave + lane, i1 = i0 + n * kWave;
+    const uint32_t t0 = h0 ? fwd_update(a, i0, bd0, bm0, td0) : kSent;
+    const uint32_t t1 = h1 ? fwd_update(a, i1, bd1, bm1, td1) : kSent;
+    const uint64_t b0 = ballot(t0 != kSent), b1 = ballot(t1 != kSent);
+    produced += __popcll(b0) + __popcll(b1);
+    if (b0 | b1) ((uint2 *)a.ftup_n)[((size_t)p * n + (size_t)v) * kWave + lane] = make_uint2(t0, t1);
+    return b0 | b1;
+}
+
+// One pull task of the forward product (see fwd_task) for column-group pair p.
+template <int AM, int U = kFwdBatch2<AM>>
+__device__ __forceinline__ void fwd_task2(const FwdArgs &a, int p, int t, unsigned long long &produced,
+                                          unsigned long long &outs) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const Task *tp = a.tasks + t;
+    const int v0 = uni(tp->v0), v1 = uni(tp->v1), hub = uni(tp->hub), part = uni(tp->part);
+    const int64_t e0 = uni64(tp->e0), e1 = uni64(tp->e1);
+    const size_t n = (size_t)a.n;
+    const uint2 *Ft = (const uint2 *)a.ftup + (size_t)p * n * kWave;
+    const double *Fm0 = a.fsig + (size_t)(2 * p) * n * kWave, *Fm1 = Fm0 + n * kWave;
+    const int32_t *Td0 = a.tdist + ((size_t)(2 * p) * n + (size_t)v0) * kWave + lane;
+    const int32_t *Td1 = Td0 + n * kWave;
+    const uint32_t *Ab = a.abits + (size_t)p * a.nwords;
+    const uint32_t mmask = (1u << a.mb) - 1u;
+    const int64_t rend = (hub < 0 && v0 + lane < v1) ? a.rp[v0 + lane + 1] : INT64_MAX;
+    int cur = -1;
+    int bd0 = kInf, bd1 = kInf, td0 = kInf, td1 = kInf;
+    double bm0 = 0.0, bm1 = 0.0;
+    uint64_t run_act = 0;
+    auto close = [&](int o) {
+        if (fwd_finalize2(a, p, v0 + o, bd0, bm0, td0, bd1, bm1, td1, lane, outs, produced))
+            run_act |= 1ull << o;
+    };
+    // fold one column's candidate into its accumulation
+    auto fold = [&](uint32_t tk, int w, const double *Fm, int u, double em, int &bd, double &bm) {
+        const int d = (int)(tk >> a.mb) + w;
+        if (tk != kSent && d <= bd) {
+            const uint32_t ms = tk & mmask;
+            double m = (double)ms;
+            if (!ms) m = kFwdEscBatch<AM> ? em : Fm[(size_t)u * kWave + lane];
+            if (d < bd) {
+                bd = d;
+                bm = m;
+            } else {
+                bm += m;
+            }
+        }
+    };
+    int un = 0, wn = 1;
+    if (e0 + lane < e1) load_arc<AM>(a.arcs, e0 + lane, un, wn);
+    for (int64_t e = e0; e < e1; e += kWave) {
+        const int64_t my = e + lane;
+        const int u = un, wt = wn;
+        const bool act = my < e1 && ((Ab[u >> 5] >> (u & 31)) & 1u);
+        if (my + kWave < e1) load_arc<AM>(a.arcs, my + kWave, un, wn);
+        uint64_t am = ballot(act);
+        while (am) {
+            int ow[U], wk[U], uk[U], tn0[U], tn1[U];
+            uint2 tk[U];
+            int prev = cur;
+#pragma unroll
+            for (int k = 0; k < U; k++) {
+                const int j = am ? __ffsll((unsigned long long)am) - 1 : -1;
+                am &= am - 1;
+                ow[k] = -1;
+                uk[k] = 0;
+                wk[k] = 0;
+                tk[k] = make_uint2(kSent, kSent);
+                tn0[k] = kInf;
+                tn1[k] = kInf;
+                if (j >= 0) {
+                    uk[k] = rdlane(u, j);
+                    wk[k] = AM ? rdlane(wt, j) : 1;
+                    tk[k] = Ft[(size_t)uk[k] * kWave + lane];
+                    ow[k] = __popcll(ballot(rend <= e + j));
+                    if (hub < 0 && ow[k] != prev) {
+                        tn0[k] = Td0[(size_t)ow[k] * kWave];
+                        tn1[k] = Td1[(size_t)ow[k] * kWave];
+                    }
+                    prev = ow[k];
+                }
+            }
+            double em0[U], em1[U];
+#pragma unroll
+            for (int k = 0; k < U; k++) {
+                em0[k] = 0.0;
+                em1[k] = 0.0;
+            }
+            if constexpr (kFwdEscBatch<AM>) {
+                bool esc = false;
+#pragma unroll
+                for (int k = 0; k < U; k++)
+                    esc |= (tk[k].x != kSent && (tk[k].x & mmask) == 0u) ||
+                           (tk[k].y != kSent && (tk[k].y & mmask) == 0u);
+                if (ballot(esc)) {
+#pragma unroll
+                    for (int k = 0; k < U; k++) {
+                        if (tk[k].x != kSent && (tk[k].x & mmask) == 0u)
+                            em0[k] = Fm0[(size_t)uk[k] * kWave + lane];
+                        if (tk[k].y != kSent && (tk[k].y & mmask) == 0u)
+                            em1[k] = Fm1[(size_t)uk[k] * kWave + lane];
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < U; k++) {
+                if (ow[k] >= 0) {
+                    if (ow[k] != cur) {
+                        if (cur >= 0 && hub < 0) close(cur);
+                        cur = ow[k];
+                        bd0 = bd1 = kInf;
+                        bm0 = bm1 = 0.0;
+                        td0 = tn0[k];
+                        td1 = tn1[k];
+                    }
+                    fold(tk[k].x, wk[k], Fm0, uk[k], em0[k], bd0, bm0);
+                    fold(tk[k].y, wk[k], Fm1, uk[k], em1[k], bd1, bm1);
+                }
+            }
+        }
+    }
+    if (hub < 0) {
+        if (cur >= 0) close(cur);
+        if (lane == 0 && run_act) or_run_bits(a.abits_n + (size_t)p * a.nwords, v0, run_act);
+    } else {
+        const size_t q0 = ((size_t)(2 * p) * a.nslots + part) * kWave + lane;
+        const size_t q1 = q0 + (size_t)a.nslots * kWave;
+        a.pd[q0] = bd0;
+        a.pm[q0] = bm0;
+        a.pd[q1] = bd1;
+        a.pm[q1] = bm1;
+    }
+}
+
+// Combine the slices of split row h for both groups of pair p (fixed slice
+// order) and finish it.
+__device__ __forceinline__ void fwd_hub2(const FwdArgs &a, int p, int h, unsigned long long &produced,
+                                         unsigned long long &outs) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const Hub *hp = a.hubs + h;
+    const int v = uni(hp->v), first = uni(hp->first), np = uni(hp->nparts);
+    int bd[2] = {kInf, kInf};
+    double bm[2] = {0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+        for (int q = first; q < first + np; q++) {
+            const size_t pidx = ((size_t)(2 * p + c) * a.nslots + q) * kWave + lane;
+            const int d = a.pd[pidx];
+            const double m = a.pm[pidx];
+            if (d < bd[c]) {
+                bd[c] = d;
+                bm[c] = m;
+            } else if (d == bd[c] && d != kInf) {
+                bm[c] += m;
+            }
+        }
+    }
+    const uint64_t b = fwd_finalize2(a, p, v, bd[0], bm[0], kLoadTd, bd[1], bm[1], kLoadTd, lane,
+                                     outs, produced);
+    if (b && lane == 0) atomicOr(a.abits_n + (size_t)p * a.nwords + (v >> 5), 1u << (v & 31));
 }
 
 // ===================================================================== backward
@@ -724,6 +919,28 @@ __global__ __launch_bounds__(kBlock) void k_fwd_merge(FwdArgs a) {
     unsigned long long produced = 0, outs = 0;
     const int cg = a.nhubs ? wid / a.nhubs : a.ncg;
     if (cg < a.ncg) fwd_hub(a, pick_cg<L>(a.cglist, cg), wid - cg * a.nhubs, produced, outs);
+    flush_counts(produced, outs, nv, na, a.ctr);
+}
+
+// Paired forward product (plain path): wave = (pair, task), pair-major.
+template <int AM>
+__global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_fwd_pull2(FwdArgs a) {
+    const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const int p = wid / a.ntasks;
+    unsigned long long produced = 0, outs = 0;
+    if (p < a.npair) fwd_task2<AM>(a, p, wid - p * a.ntasks, produced, outs);
+    flush_counts(produced, outs, 0, 0, a.ctr);
+}
+
+__global__ __launch_bounds__(kBlock) __attribute__((unused)) void k_fwd_merge2(FwdArgs a) {
+    const int gtid = blockIdx.x * kBlock + threadIdx.x;
+    unsigned long long nv = 0, na = 0;
+    clear_and_count(a.clear_bits, a.nwords, a.npair, a.rp, nv, na);
+    if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
+    const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    unsigned long long produced = 0, outs = 0;
+    const int p = a.nhubs ? wid / a.nhubs : a.npair;
+    if (p < a.npair) fwd_hub2(a, p, wid - p * a.nhubs, produced, outs);
     flush_counts(produced, outs, nv, na, a.ctr);
 }
 

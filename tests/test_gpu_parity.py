@@ -70,6 +70,10 @@ def graphs():
         "star200": gg.star_graph(200),
         "diamonds40": gg.diamond_chain(40),
         "disconnected": disc,
+        # frontier rows past the 16-bit tuple's weight range: all long along
+        # a heavy path, a mix of short and long rows with wide weights
+        "path400_w97": gg.path_graph(400, w=97),
+        "er800_w3000": gg.er_graph(800, 6, 9, (1, 3000)),
     }
 
 
