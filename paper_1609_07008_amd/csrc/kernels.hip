@@ -90,26 +90,28 @@ __global__ void k_fwd_seed(const int32_t *src, int nb, int n, int nwords, int32_
     atomicOr(abits + (size_t)cg * nwords + (v >> 5), 1u << (v & 31));
 }
 
-// The same for the paired layout (groups 2p and 2p+1 interleaved per lane,
-// one activity bitmap per pair).
-__global__ void k_fwd_seed_rows2(const int32_t *src, int nb, int n, uint2 *ftup) {
+// The same for the wide layout (groups Wq .. Wq+W-1 interleaved per lane,
+// one activity bitmap per wide group).
+template <int W>
+__global__ void k_fwd_seed_rows_w(const int32_t *src, int nb, int n, uint32_t *ftup) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nb) return;
-    const size_t row = ((size_t)(c / (2 * kWave)) * n + src[c]) * kWave;
-    for (int l = 0; l < kWave; l++) ftup[row + l] = make_uint2(kSent, kSent);
+    const size_t row = ((size_t)(c / (W * kWave)) * n + src[c]) * kWave * W;
+    for (int l = 0; l < kWave * W; l++) ftup[row + l] = kSent;
 }
 
-__global__ void k_fwd_seed2(const int32_t *src, int nb, int n, int nwords, int32_t *tdist,
-                            double *tsig, uint32_t *ftup, uint32_t *abits) {
+template <int W>
+__global__ void k_fwd_seed_w(const int32_t *src, int nb, int n, int nwords, int32_t *tdist,
+                             double *tsig, uint32_t *ftup, uint32_t *abits) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nb) return;
     const int v = src[c];
-    const int cg = c / kWave, lane = c % kWave, p = cg >> 1;
+    const int cg = c / kWave, lane = c % kWave, q = cg / W;
     const size_t idx = ((size_t)cg * n + v) * kWave + lane;
     tdist[idx] = 0;
     tsig[idx] = 1.0;
-    ftup[(((size_t)p * n + v) * kWave + lane) * 2 + (cg & 1)] = 1u;
-    atomicOr(abits + (size_t)p * nwords + (v >> 5), 1u << (v & 31));
+    ftup[(((size_t)q * n + v) * kWave + lane) * W + (cg % W)] = 1u;
+    atomicOr(abits + (size_t)q * nwords + (v >> 5), 1u << (v & 31));
 }
 
 __global__ void k_zero_f64(double *p, size_t total) {
@@ -213,9 +215,11 @@ static ArcSrc arc_src(const Csr &c) {
 
 static int arc_mode(const Csr &c) { return c.w == nullptr ? 0 : (c.pk ? 1 : 2); }
 
-// Batches of two or more column groups run the forward product on pairs
-// of groups (the workspace holds an even number of groups).
-static int fwd_pairs(int ncg) { return ncg >= 2 ? (ncg + 1) / 2 : 0; }
+// Batches of two or more column groups run the forward product on pairs of
+// them (the workspace holds an even number of groups); a single group runs
+// alone.
+constexpr int kWide = 2;
+static int fwd_wide_groups(int ncg) { return ncg >= 2 ? (ncg + kWide - 1) / kWide : 0; }
 
 static FwdArgs fwd_args(mfbc_graph *g, int ncg, int j, bool trace) {
     Workspace &ws = g->ws;
@@ -249,7 +253,7 @@ static FwdArgs fwd_args(mfbc_graph *g, int ncg, int j, bool trace) {
     a.fmask = trace ? ws.fmask : nullptr;
     a.clear_bits = ws.abits[b];
     a.clear_ctr = ws.counters + (size_t)((j + 1) % kCounterRing) * 4 * kCounterSlots;
-    a.npair = fwd_pairs(ncg);
+    a.nwide = fwd_wide_groups(ncg);
     return a;
 }
 
@@ -267,11 +271,12 @@ void launch_fwd_init(mfbc_graph *g, int ncg, int nb, hipStream_t s) {
                        ws.tsig, total, ws.abits[0], ws.abits[1], (size_t)ncg * nwords,
                        ws.counters, kCounterRing * 4 * kCounterSlots, ws.flags,
                        ws.fmask && ws.fmask_ncg >= ncg ? ws.fmask : nullptr);
-    if (fwd_pairs(ncg)) {
-        hipLaunchKernelGGL(k_fwd_seed_rows2, dim3(blocks_for(nb, 256)), dim3(256), 0, s, ws.src, nb,
-                           g->n, (uint2 *)ws.fdist[0]);
-        hipLaunchKernelGGL(k_fwd_seed2, dim3(blocks_for(nb, 256)), dim3(256), 0, s, ws.src, nb,
-                           g->n, nwords, ws.tdist, ws.tsig, (uint32_t *)ws.fdist[0], ws.abits[0]);
+    if (fwd_wide_groups(ncg)) {
+        uint32_t *ft = (uint32_t *)ws.fdist[0];
+        hipLaunchKernelGGL(k_fwd_seed_rows_w<kWide>, dim3(blocks_for(nb, 256)), dim3(256), 0, s, ws.src,
+                           nb, g->n, ft);
+        hipLaunchKernelGGL(k_fwd_seed_w<kWide>, dim3(blocks_for(nb, 256)), dim3(256), 0, s, ws.src, nb,
+                           g->n, nwords, ws.tdist, ws.tsig, ft, ws.abits[0]);
         return;
     }
     hipLaunchKernelGGL(k_fwd_seed_rows, dim3(blocks_for(nb, 256)), dim3(256), 0, s, ws.src, nb,
@@ -283,19 +288,19 @@ void launch_fwd_init(mfbc_graph *g, int ncg, int nb, hipStream_t s) {
 void launch_fwd_product(mfbc_graph *g, int ncg, int j, bool trace, hipStream_t s,
                         hipEvent_t *ev) {
     FwdArgs a = fwd_args(g, ncg, j, trace);
-    if (a.npair) {
+    if (a.nwide) {
         if (ev) (void)hipEventRecord(ev[0], s);
-        const int grid = blocks_for((size_t)a.ntasks * a.npair, kWavesPerBlock, 0x7fffffff);
+        const int grid = blocks_for((size_t)a.ntasks * a.nwide, kWavesPerBlock, 0x7fffffff);
         switch (arc_mode(g->in)) {
-            case 0: hipLaunchKernelGGL(k_fwd_pull2<0>, dim3(grid), dim3(kBlock), 0, s, a); break;
-            case 1: hipLaunchKernelGGL(k_fwd_pull2<1>, dim3(grid), dim3(kBlock), 0, s, a); break;
-            default: hipLaunchKernelGGL(k_fwd_pull2<2>, dim3(grid), dim3(kBlock), 0, s, a); break;
+            case 0: hipLaunchKernelGGL((k_fwd_pull_w<0, kWide>), dim3(grid), dim3(kBlock), 0, s, a); break;
+            case 1: hipLaunchKernelGGL((k_fwd_pull_w<1, kWide>), dim3(grid), dim3(kBlock), 0, s, a); break;
+            default: hipLaunchKernelGGL((k_fwd_pull_w<2, kWide>), dim3(grid), dim3(kBlock), 0, s, a); break;
         }
         if (ev) (void)hipEventRecord(ev[1], s);
-        int mgrid = blocks_for((size_t)a.nhubs * a.npair, kWavesPerBlock, 0x7fffffff);
+        int mgrid = blocks_for((size_t)a.nhubs * a.nwide, kWavesPerBlock, 0x7fffffff);
         const int cgrid = blocks_for((size_t)a.nwords, kBlock, 1024);
         if (cgrid > mgrid) mgrid = cgrid;
-        hipLaunchKernelGGL(k_fwd_merge2, dim3(mgrid), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL(k_fwd_merge_w<kWide>, dim3(mgrid), dim3(kBlock), 0, s, a);
         if (ev) (void)hipEventRecord(ev[2], s);
         return;
     }

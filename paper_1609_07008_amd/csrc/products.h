@@ -178,7 +178,7 @@ struct FwdArgs {
     unsigned long long *colmask;    // nullable: [32][ncg_all] columns that produced entries
     const int32_t *cglist;     // nullable: the ncg column groups of this launch (else 0..ncg-1)
     int ncg_all;               // column groups of the state (strides of colmask, bitmap planes)
-    int npair;                 // paired layout: column-group pairs (0: one group per wave)
+    int nwide;                 // wide layout: groups of 2 column groups (0: one per wave)
 };
 
 // T := T (+) G at one entry (idx = (cg, v, lane)) given its candidate
@@ -387,82 +387,93 @@ __device__ __forceinline__ void fwd_hub(const FwdArgs &a, int cg, int h, unsigne
     flush_colmask(a.colmask, a.ncg_all, cg, colany);
 }
 
-// ===================================================================== forward, paired
+// ===================================================================== forward, wide
 //
-// The plain path runs the forward product on pairs of column groups: the
-// frontier rows of groups 2p and 2p+1 are interleaved ([p][v][64] x 2 x
-// 32 bits, one 8-byte entry per lane), so a lane holds two columns and one
-// load instruction gathers the frontier row of both groups.  A gather's cost
-// is set by its instruction more than by its bytes (a 64-lane load of 256 B
-// and one of 512 B issue at about the same rate from L2), so a pair halves
-// the gathers, the arc loads and the activity tests of a product.  T and the
-// escaped multiplicities keep the one-group layout; the activity bitmap is
-// per pair (a vertex active in a column of either group), and the writer
-// fills both halves of a row (kSent where a lane is not in the frontier), so
-// a row marked active holds valid tuples for both groups.
+// The plain path runs the forward product on W = 2 column groups at once: the frontier rows of groups Wq .. Wq+W-1 are interleaved ([q][v][64]
+// x W x 32 bits, one 4W-byte entry per lane), so a lane holds W columns and
+// one load instruction gathers the frontier row of all W groups.  A gather's
+// cost is set by its instruction more than by its bytes (64-lane loads of
+// 256 B, 512 B and 1 KB issue at about the same rate from L2), so W groups
+// per wave divide the gathers, the arc loads and the activity tests of a
+// product by W.  W = 4 fits only six waves per SIMD and measured no faster
+// overall, so the code is written for a general W and used with W = 2.  T and the escaped multiplicities keep the one-group layout;
+// the activity bitmap is per wide group (a vertex active in a column of any
+// of its groups), and the writer fills every slot of a row (kSent where a
+// lane is not in the frontier), so a row marked active holds valid tuples
+// for all W groups.
 
-// Active arcs per batch in the paired form (two columns per lane take twice
+template <int W> struct WideT;
+template <> struct WideT<2> { using T = uint2; };
+
+__device__ __forceinline__ void unpack(const uint2 &v, uint32_t (&o)[2]) {
+    o[0] = v.x;
+    o[1] = v.y;
+}
+__device__ __forceinline__ uint2 pack(const uint32_t (&o)[2]) { return make_uint2(o[0], o[1]); }
+
+// Active arcs per batch in the wide form (W columns per lane take W times
 // the registers per arc; four weighted arcs at seven waves per SIMD measured
 // faster than two at eight or three at seven).
-template <int AM> constexpr int kFwdBatch2 = AM == 0 ? 2 : 4;
+template <int AM, int W> constexpr int kFwdBatchW = AM == 0 ? 2 : 4;
 
-// T := T (+) G at (v, 2p) and (v, 2p+1); writes the next frontier's pair
-// row.  Returns the lanes in the next frontier in either group.
-__device__ __forceinline__ uint64_t fwd_finalize2(const FwdArgs &a, int p, int v, int bd0,
-                                                  double bm0, int td0, int bd1, double bm1,
-                                                  int td1, int lane, unsigned long long &outs,
-                                                  unsigned long long &produced) {
-    const uint64_t h0 = ballot(bd0 != kInf), h1 = ballot(bd1 != kInf);
-    outs += __popcll(h0) + __popcll(h1);
-    if (!(h0 | h1)) return 0;
+// T := T (+) G at (v, Wq + c) for c < W; writes the next frontier's wide
+// row.  Returns the lanes in the next frontier in any of the W groups.
+template <int W>
+__device__ __forceinline__ uint64_t fwd_finalize_w(const FwdArgs &a, int q, int v, const int (&bd)[W],
+                                                   const double (&bm)[W], const int (&td)[W], int lane,
+                                                   unsigned long long &outs, unsigned long long &produced) {
+    uint64_t any = 0;
+#pragma unroll
+    for (int c = 0; c < W; c++) {
+        const uint64_t h = ballot(bd[c] != kInf);
+        outs += __popcll(h);
+        any |= h;
+    }
+    if (!any) return 0;
     const size_t n = (size_t)a.n;
-    const size_t i0 = ((size_t)(2 * p) * n + (size_t)v) * kWave + lane, i1 = i0 + n * kWave;
-    const uint32_t t0 = h0 ? fwd_update(a, i0, bd0, bm0, td0) : kSent;
-    const uint32_t t1 = h1 ? fwd_update(a, i1, bd1, bm1, td1) : kSent;
-    const uint64_t b0 = ballot(t0 != kSent), b1 = ballot(t1 != kSent);
-    produced += __popcll(b0) + __popcll(b1);
-    if (b0 | b1) ((uint2 *)a.ftup_n)[((size_t)p * n + (size_t)v) * kWave + lane] = make_uint2(t0, t1);
-    return b0 | b1;
+    const size_t i0 = ((size_t)(W * q) * n + (size_t)v) * kWave + lane;
+    uint32_t t[W];
+    uint64_t kept = 0;
+#pragma unroll
+    for (int c = 0; c < W; c++) {
+        t[c] = fwd_update(a, i0 + (size_t)c * n * kWave, bd[c], bm[c], td[c]);
+        const uint64_t b = ballot(t[c] != kSent);
+        produced += __popcll(b);
+        kept |= b;
+    }
+    using V = typename WideT<W>::T;
+    if (kept) ((V *)a.ftup_n)[((size_t)q * n + (size_t)v) * kWave + lane] = pack(t);
+    return kept;
 }
 
-// One pull task of the forward product (see fwd_task) for column-group pair p.
-template <int AM, int U = kFwdBatch2<AM>>
-__device__ __forceinline__ void fwd_task2(const FwdArgs &a, int p, int t, unsigned long long &produced,
-                                          unsigned long long &outs) {
+// One pull task of the forward product (see fwd_task) for wide group q.
+template <int AM, int W, int U = kFwdBatchW<AM, W>>
+__device__ __forceinline__ void fwd_task_w(const FwdArgs &a, int q, int t, unsigned long long &produced,
+                                           unsigned long long &outs) {
+    using V = typename WideT<W>::T;
     const int lane = threadIdx.x & (kWave - 1);
     const Task *tp = a.tasks + t;
     const int v0 = uni(tp->v0), v1 = uni(tp->v1), hub = uni(tp->hub), part = uni(tp->part);
     const int64_t e0 = uni64(tp->e0), e1 = uni64(tp->e1);
-    const size_t n = (size_t)a.n;
-    const uint2 *Ft = (const uint2 *)a.ftup + (size_t)p * n * kWave;
-    const double *Fm0 = a.fsig + (size_t)(2 * p) * n * kWave, *Fm1 = Fm0 + n * kWave;
-    const int32_t *Td0 = a.tdist + ((size_t)(2 * p) * n + (size_t)v0) * kWave + lane;
-    const int32_t *Td1 = Td0 + n * kWave;
-    const uint32_t *Ab = a.abits + (size_t)p * a.nwords;
+    const size_t n = (size_t)a.n, plane = n * kWave;
+    const V *Ft = (const V *)a.ftup + (size_t)q * plane;
+    const double *Fm = a.fsig + (size_t)(W * q) * plane;        // group c at Fm + c * plane
+    const int32_t *Td = a.tdist + ((size_t)(W * q) * n + (size_t)v0) * kWave + lane;
+    const uint32_t *Ab = a.abits + (size_t)q * a.nwords;
     const uint32_t mmask = (1u << a.mb) - 1u;
     const int64_t rend = (hub < 0 && v0 + lane < v1) ? a.rp[v0 + lane + 1] : INT64_MAX;
     int cur = -1;
-    int bd0 = kInf, bd1 = kInf, td0 = kInf, td1 = kInf;
-    double bm0 = 0.0, bm1 = 0.0;
+    int bd[W], td[W];
+    double bm[W];
+#pragma unroll
+    for (int c = 0; c < W; c++) {
+        bd[c] = kInf;
+        td[c] = kInf;
+        bm[c] = 0.0;
+    }
     uint64_t run_act = 0;
     auto close = [&](int o) {
-        if (fwd_finalize2(a, p, v0 + o, bd0, bm0, td0, bd1, bm1, td1, lane, outs, produced))
-            run_act |= 1ull << o;
-    };
-    // fold one column's candidate into its accumulation
-    auto fold = [&](uint32_t tk, int w, const double *Fm, int u, double em, int &bd, double &bm) {
-        const int d = (int)(tk >> a.mb) + w;
-        if (tk != kSent && d <= bd) {
-            const uint32_t ms = tk & mmask;
-            double m = (double)ms;
-            if (!ms) m = kFwdEscBatch<AM> ? em : Fm[(size_t)u * kWave + lane];
-            if (d < bd) {
-                bd = d;
-                bm = m;
-            } else {
-                bm += m;
-            }
-        }
+        if (fwd_finalize_w<W>(a, q, v0 + o, bd, bm, td, lane, outs, produced)) run_act |= 1ull << o;
     };
     int un = 0, wn = 1;
     if (e0 + lane < e1) load_arc<AM>(a.arcs, e0 + lane, un, wn);
@@ -473,8 +484,9 @@ __device__ __forceinline__ void fwd_task2(const FwdArgs &a, int p, int t, unsign
         if (my + kWave < e1) load_arc<AM>(a.arcs, my + kWave, un, wn);
         uint64_t am = ballot(act);
         while (am) {
-            int ow[U], wk[U], uk[U], tn0[U], tn1[U];
-            uint2 tk[U];
+            int ow[U], wk[U], uk[U];
+            int tn[U][W];
+            uint32_t tk[U][W];
             int prev = cur;
 #pragma unroll
             for (int k = 0; k < U; k++) {
@@ -483,41 +495,41 @@ __device__ __forceinline__ void fwd_task2(const FwdArgs &a, int p, int t, unsign
                 ow[k] = -1;
                 uk[k] = 0;
                 wk[k] = 0;
-                tk[k] = make_uint2(kSent, kSent);
-                tn0[k] = kInf;
-                tn1[k] = kInf;
+#pragma unroll
+                for (int c = 0; c < W; c++) {
+                    tk[k][c] = kSent;
+                    tn[k][c] = kInf;
+                }
                 if (j >= 0) {
                     uk[k] = rdlane(u, j);
                     wk[k] = AM ? rdlane(wt, j) : 1;
-                    tk[k] = Ft[(size_t)uk[k] * kWave + lane];
+                    unpack(Ft[(size_t)uk[k] * kWave + lane], tk[k]);
                     ow[k] = __popcll(ballot(rend <= e + j));
                     if (hub < 0 && ow[k] != prev) {
-                        tn0[k] = Td0[(size_t)ow[k] * kWave];
-                        tn1[k] = Td1[(size_t)ow[k] * kWave];
+#pragma unroll
+                        for (int c = 0; c < W; c++) tn[k][c] = Td[(size_t)c * plane + (size_t)ow[k] * kWave];
                     }
                     prev = ow[k];
                 }
             }
-            double em0[U], em1[U];
+            double em[U][W];
 #pragma unroll
-            for (int k = 0; k < U; k++) {
-                em0[k] = 0.0;
-                em1[k] = 0.0;
-            }
+            for (int k = 0; k < U; k++)
+#pragma unroll
+                for (int c = 0; c < W; c++) em[k][c] = 0.0;
             if constexpr (kFwdEscBatch<AM>) {
                 bool esc = false;
 #pragma unroll
                 for (int k = 0; k < U; k++)
-                    esc |= (tk[k].x != kSent && (tk[k].x & mmask) == 0u) ||
-                           (tk[k].y != kSent && (tk[k].y & mmask) == 0u);
+#pragma unroll
+                    for (int c = 0; c < W; c++) esc |= tk[k][c] != kSent && (tk[k][c] & mmask) == 0u;
                 if (ballot(esc)) {
 #pragma unroll
-                    for (int k = 0; k < U; k++) {
-                        if (tk[k].x != kSent && (tk[k].x & mmask) == 0u)
-                            em0[k] = Fm0[(size_t)uk[k] * kWave + lane];
-                        if (tk[k].y != kSent && (tk[k].y & mmask) == 0u)
-                            em1[k] = Fm1[(size_t)uk[k] * kWave + lane];
-                    }
+                    for (int k = 0; k < U; k++)
+#pragma unroll
+                        for (int c = 0; c < W; c++)
+                            if (tk[k][c] != kSent && (tk[k][c] & mmask) == 0u)
+                                em[k][c] = Fm[(size_t)c * plane + (size_t)uk[k] * kWave + lane];
                 }
             }
 #pragma unroll
@@ -526,43 +538,65 @@ __device__ __forceinline__ void fwd_task2(const FwdArgs &a, int p, int t, unsign
                     if (ow[k] != cur) {
                         if (cur >= 0 && hub < 0) close(cur);
                         cur = ow[k];
-                        bd0 = bd1 = kInf;
-                        bm0 = bm1 = 0.0;
-                        td0 = tn0[k];
-                        td1 = tn1[k];
+#pragma unroll
+                        for (int c = 0; c < W; c++) {
+                            bd[c] = kInf;
+                            bm[c] = 0.0;
+                            td[c] = tn[k][c];
+                        }
                     }
-                    fold(tk[k].x, wk[k], Fm0, uk[k], em0[k], bd0, bm0);
-                    fold(tk[k].y, wk[k], Fm1, uk[k], em1[k], bd1, bm1);
+#pragma unroll
+                    for (int c = 0; c < W; c++) {
+                        const uint32_t x = tk[k][c];
+                        const int d = (int)(x >> a.mb) + wk[k];
+                        if (x != kSent && d <= bd[c]) {
+                            const uint32_t ms = x & mmask;
+                            double m = (double)ms;
+                            if (!ms)
+                                m = kFwdEscBatch<AM> ? em[k][c]
+                                                     : Fm[(size_t)c * plane + (size_t)uk[k] * kWave + lane];
+                            if (d < bd[c]) {
+                                bd[c] = d;
+                                bm[c] = m;
+                            } else {
+                                bm[c] += m;
+                            }
+                        }
+                    }
                 }
             }
         }
     }
     if (hub < 0) {
         if (cur >= 0) close(cur);
-        if (lane == 0 && run_act) or_run_bits(a.abits_n + (size_t)p * a.nwords, v0, run_act);
+        if (lane == 0 && run_act) or_run_bits(a.abits_n + (size_t)q * a.nwords, v0, run_act);
     } else {
-        const size_t q0 = ((size_t)(2 * p) * a.nslots + part) * kWave + lane;
-        const size_t q1 = q0 + (size_t)a.nslots * kWave;
-        a.pd[q0] = bd0;
-        a.pm[q0] = bm0;
-        a.pd[q1] = bd1;
-        a.pm[q1] = bm1;
+#pragma unroll
+        for (int c = 0; c < W; c++) {
+            const size_t pidx = ((size_t)(W * q + c) * a.nslots + part) * kWave + lane;
+            a.pd[pidx] = bd[c];
+            a.pm[pidx] = bm[c];
+        }
     }
 }
 
-// Combine the slices of split row h for both groups of pair p (fixed slice
-// order) and finish it.
-__device__ __forceinline__ void fwd_hub2(const FwdArgs &a, int p, int h, unsigned long long &produced,
-                                         unsigned long long &outs) {
+// Combine the slices of split row h for the W groups of wide group q
+// (fixed slice order) and finish it.
+template <int W>
+__device__ __forceinline__ void fwd_hub_w(const FwdArgs &a, int q, int h, unsigned long long &produced,
+                                          unsigned long long &outs) {
     const int lane = threadIdx.x & (kWave - 1);
     const Hub *hp = a.hubs + h;
     const int v = uni(hp->v), first = uni(hp->first), np = uni(hp->nparts);
-    int bd[2] = {kInf, kInf};
-    double bm[2] = {0.0, 0.0};
+    int bd[W], td[W];
+    double bm[W];
 #pragma unroll
-    for (int c = 0; c < 2; c++) {
-        for (int q = first; q < first + np; q++) {
-            const size_t pidx = ((size_t)(2 * p + c) * a.nslots + q) * kWave + lane;
+    for (int c = 0; c < W; c++) {
+        bd[c] = kInf;
+        bm[c] = 0.0;
+        td[c] = kLoadTd;
+        for (int s = first; s < first + np; s++) {
+            const size_t pidx = ((size_t)(W * q + c) * a.nslots + s) * kWave + lane;
             const int d = a.pd[pidx];
             const double m = a.pm[pidx];
             if (d < bd[c]) {
@@ -573,9 +607,8 @@ __device__ __forceinline__ void fwd_hub2(const FwdArgs &a, int p, int h, unsigne
             }
         }
     }
-    const uint64_t b = fwd_finalize2(a, p, v, bd[0], bm[0], kLoadTd, bd[1], bm[1], kLoadTd, lane,
-                                     outs, produced);
-    if (b && lane == 0) atomicOr(a.abits_n + (size_t)p * a.nwords + (v >> 5), 1u << (v & 31));
+    const uint64_t b = fwd_finalize_w<W>(a, q, v, bd, bm, td, lane, outs, produced);
+    if (b && lane == 0) atomicOr(a.abits_n + (size_t)q * a.nwords + (v >> 5), 1u << (v & 31));
 }
 
 // ===================================================================== backward
@@ -922,25 +955,26 @@ __global__ __launch_bounds__(kBlock) void k_fwd_merge(FwdArgs a) {
     flush_counts(produced, outs, nv, na, a.ctr);
 }
 
-// Paired forward product (plain path): wave = (pair, task), pair-major.
-template <int AM>
-__global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_fwd_pull2(FwdArgs a) {
+// Wide forward product (plain path): wave = (wide group, task), group-major.
+template <int AM, int W>
+__global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_fwd_pull_w(FwdArgs a) {
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    const int p = wid / a.ntasks;
+    const int q = wid / a.ntasks;
     unsigned long long produced = 0, outs = 0;
-    if (p < a.npair) fwd_task2<AM>(a, p, wid - p * a.ntasks, produced, outs);
+    if (q < a.nwide) fwd_task_w<AM, W>(a, q, wid - q * a.ntasks, produced, outs);
     flush_counts(produced, outs, 0, 0, a.ctr);
 }
 
-__global__ __launch_bounds__(kBlock) __attribute__((unused)) void k_fwd_merge2(FwdArgs a) {
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_fwd_merge_w(FwdArgs a) {
     const int gtid = blockIdx.x * kBlock + threadIdx.x;
     unsigned long long nv = 0, na = 0;
-    clear_and_count(a.clear_bits, a.nwords, a.npair, a.rp, nv, na);
+    clear_and_count(a.clear_bits, a.nwords, a.nwide, a.rp, nv, na);
     if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     unsigned long long produced = 0, outs = 0;
-    const int p = a.nhubs ? wid / a.nhubs : a.npair;
-    if (p < a.npair) fwd_hub2(a, p, wid - p * a.nhubs, produced, outs);
+    const int q = a.nhubs ? wid / a.nhubs : a.nwide;
+    if (q < a.nwide) fwd_hub_w<W>(a, q, wid - q * a.nhubs, produced, outs);
     flush_counts(produced, outs, nv, na, a.ctr);
 }
 

@@ -78,7 +78,7 @@ def graphs():
 
 
 GRAPHS = graphs()
-NB = [1, 5, 64, 65, 130]
+NB = [1, 5, 64, 65, 130, 256]     # 256: four groups, one wide forward group
 
 
 @pytest.fixture(scope="module")
@@ -115,7 +115,7 @@ def test_forward_parity(torch, mfbc, dgraphs, name, nb):
 
 
 @pytest.mark.parametrize("name", list(GRAPHS))
-@pytest.mark.parametrize("nb", [1, 64, 130])
+@pytest.mark.parametrize("nb", [1, 64, 130, 260])
 def test_backward_parity(torch, mfbc, dgraphs, name, nb):
     g = GRAPHS[name]
     src = pick(g, nb, 200 + nb)
