@@ -218,7 +218,6 @@ static int arc_mode(const Csr &c) { return c.w == nullptr ? 0 : (c.pk ? 1 : 2); 
 // Batches of two or more column groups run the forward product on pairs of
 // them (the workspace holds an even number of groups); a single group runs
 // alone.
-constexpr int kWide = 2;
 static int fwd_wide_groups(int ncg) { return ncg >= 2 ? (ncg + kWide - 1) / kWide : 0; }
 
 static FwdArgs fwd_args(mfbc_graph *g, int ncg, int j, bool trace) {
@@ -254,6 +253,7 @@ static FwdArgs fwd_args(mfbc_graph *g, int ncg, int j, bool trace) {
     a.clear_bits = ws.abits[b];
     a.clear_ctr = ws.counters + (size_t)((j + 1) % kCounterRing) * 4 * kCounterSlots;
     a.nwide = fwd_wide_groups(ncg);
+    a.nwide_all = a.nwide;
     return a;
 }
 
@@ -292,15 +292,15 @@ void launch_fwd_product(mfbc_graph *g, int ncg, int j, bool trace, hipStream_t s
         if (ev) (void)hipEventRecord(ev[0], s);
         const int grid = blocks_for((size_t)a.ntasks * a.nwide, kWavesPerBlock, 0x7fffffff);
         switch (arc_mode(g->in)) {
-            case 0: hipLaunchKernelGGL((k_fwd_pull_w<0, kWide>), dim3(grid), dim3(kBlock), 0, s, a); break;
-            case 1: hipLaunchKernelGGL((k_fwd_pull_w<1, kWide>), dim3(grid), dim3(kBlock), 0, s, a); break;
-            default: hipLaunchKernelGGL((k_fwd_pull_w<2, kWide>), dim3(grid), dim3(kBlock), 0, s, a); break;
+            case 0: hipLaunchKernelGGL((k_fwd_pull_w<0, kWide, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
+            case 1: hipLaunchKernelGGL((k_fwd_pull_w<1, kWide, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
+            default: hipLaunchKernelGGL((k_fwd_pull_w<2, kWide, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
         }
         if (ev) (void)hipEventRecord(ev[1], s);
         int mgrid = blocks_for((size_t)a.nhubs * a.nwide, kWavesPerBlock, 0x7fffffff);
         const int cgrid = blocks_for((size_t)a.nwords, kBlock, 1024);
         if (cgrid > mgrid) mgrid = cgrid;
-        hipLaunchKernelGGL(k_fwd_merge_w<kWide>, dim3(mgrid), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL((k_fwd_merge_w<kWide, false>), dim3(mgrid), dim3(kBlock), 0, s, a);
         if (ev) (void)hipEventRecord(ev[2], s);
         return;
     }

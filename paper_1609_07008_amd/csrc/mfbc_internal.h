@@ -26,6 +26,7 @@ constexpr int kBlock = kWave * kWavesPerBlock;
 constexpr int32_t kInf = MFBC_INF_DIST;
 constexpr int kCounterSlots = 32;        // spread of the frontier-size counters
 constexpr int kCounterRing = 4;          // products whose counters are live at once
+constexpr int kWide = 2;                 // column groups per wave in the forward product
 
 // A unit of pull work for one wave (and one column group):
 //  * hub < 0: the whole adjacency rows of vertices [v0, v1), arcs [e0, e1);

@@ -179,6 +179,7 @@ struct FwdArgs {
     const int32_t *cglist;     // nullable: the ncg column groups of this launch (else 0..ncg-1)
     int ncg_all;               // column groups of the state (strides of colmask, bitmap planes)
     int nwide;                 // wide layout: groups of 2 column groups (0: one per wave)
+    int nwide_all;             //   wide groups of the state (bitmap planes)
 };
 
 // T := T (+) G at one entry (idx = (cg, v, lane)) given its candidate
@@ -418,10 +419,12 @@ template <int AM, int W> constexpr int kFwdBatchW = AM == 0 ? 2 : 4;
 
 // T := T (+) G at (v, Wq + c) for c < W; writes the next frontier's wide
 // row.  Returns the lanes in the next frontier in any of the W groups.
+// `colany[c]` collects the lanes of group c that produced entries.
 template <int W>
 __device__ __forceinline__ uint64_t fwd_finalize_w(const FwdArgs &a, int q, int v, const int (&bd)[W],
                                                    const double (&bm)[W], const int (&td)[W], int lane,
-                                                   unsigned long long &outs, unsigned long long &produced) {
+                                                   unsigned long long &outs, unsigned long long &produced,
+                                                   uint64_t (&colany)[W]) {
     uint64_t any = 0;
 #pragma unroll
     for (int c = 0; c < W; c++) {
@@ -440,10 +443,19 @@ __device__ __forceinline__ uint64_t fwd_finalize_w(const FwdArgs &a, int q, int 
         const uint64_t b = ballot(t[c] != kSent);
         produced += __popcll(b);
         kept |= b;
+        colany[c] |= b;
     }
     using V = typename WideT<W>::T;
     if (kept) ((V *)a.ftup_n)[((size_t)q * n + (size_t)v) * kWave + lane] = pack(t);
     return kept;
+}
+
+// Record, per group of wide group q, the columns that produced entries.
+template <int W>
+__device__ __forceinline__ void flush_colmask_w(const FwdArgs &a, int q, const uint64_t (&colany)[W]) {
+#pragma unroll
+    for (int c = 0; c < W; c++)
+        if (W * q + c < a.ncg_all) flush_colmask(a.colmask, a.ncg_all, W * q + c, colany[c]);
 }
 
 // One pull task of the forward product (see fwd_task) for wide group q.
@@ -471,9 +483,12 @@ __device__ __forceinline__ void fwd_task_w(const FwdArgs &a, int q, int t, unsig
         td[c] = kInf;
         bm[c] = 0.0;
     }
-    uint64_t run_act = 0;
+    uint64_t run_act = 0, colany[W];
+#pragma unroll
+    for (int c = 0; c < W; c++) colany[c] = 0;
     auto close = [&](int o) {
-        if (fwd_finalize_w<W>(a, q, v0 + o, bd, bm, td, lane, outs, produced)) run_act |= 1ull << o;
+        if (fwd_finalize_w<W>(a, q, v0 + o, bd, bm, td, lane, outs, produced, colany))
+            run_act |= 1ull << o;
     };
     int un = 0, wn = 1;
     if (e0 + lane < e1) load_arc<AM>(a.arcs, e0 + lane, un, wn);
@@ -578,6 +593,7 @@ __device__ __forceinline__ void fwd_task_w(const FwdArgs &a, int q, int t, unsig
             a.pm[pidx] = bm[c];
         }
     }
+    if (a.colmask) flush_colmask_w<W>(a, q, colany);
 }
 
 // Combine the slices of split row h for the W groups of wide group q
@@ -607,8 +623,12 @@ __device__ __forceinline__ void fwd_hub_w(const FwdArgs &a, int q, int h, unsign
             }
         }
     }
-    const uint64_t b = fwd_finalize_w<W>(a, q, v, bd, bm, td, lane, outs, produced);
+    uint64_t colany[W];
+#pragma unroll
+    for (int c = 0; c < W; c++) colany[c] = 0;
+    const uint64_t b = fwd_finalize_w<W>(a, q, v, bd, bm, td, lane, outs, produced, colany);
     if (b && lane == 0) atomicOr(a.abits_n + (size_t)q * a.nwords + (v >> 5), 1u << (v & 31));
+    if (a.colmask) flush_colmask_w<W>(a, q, colany);
 }
 
 // ===================================================================== backward
@@ -955,26 +975,28 @@ __global__ __launch_bounds__(kBlock) void k_fwd_merge(FwdArgs a) {
     flush_counts(produced, outs, nv, na, a.ctr);
 }
 
-// Wide forward product (plain path): wave = (wide group, task), group-major.
-template <int AM, int W>
+// Wide forward product: wave = (wide group, task), group-major.  With L the
+// launch covers the a.nwide wide groups listed in a.cglist (served form),
+// else groups 0 .. a.nwide-1; the merge clears a.nwide_all bitmap planes.
+template <int AM, int W, bool L>
 __global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_fwd_pull_w(FwdArgs a) {
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const int q = wid / a.ntasks;
     unsigned long long produced = 0, outs = 0;
-    if (q < a.nwide) fwd_task_w<AM, W>(a, q, wid - q * a.ntasks, produced, outs);
+    if (q < a.nwide) fwd_task_w<AM, W>(a, pick_cg<L>(a.cglist, q), wid - q * a.ntasks, produced, outs);
     flush_counts(produced, outs, 0, 0, a.ctr);
 }
 
-template <int W>
+template <int W, bool L>
 __global__ __launch_bounds__(kBlock) void k_fwd_merge_w(FwdArgs a) {
     const int gtid = blockIdx.x * kBlock + threadIdx.x;
     unsigned long long nv = 0, na = 0;
-    clear_and_count(a.clear_bits, a.nwords, a.nwide, a.rp, nv, na);
+    clear_and_count(a.clear_bits, a.nwords, a.nwide_all, a.rp, nv, na);
     if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     unsigned long long produced = 0, outs = 0;
     const int q = a.nhubs ? wid / a.nhubs : a.nwide;
-    if (q < a.nwide) fwd_hub_w<W>(a, q, wid - q * a.nhubs, produced, outs);
+    if (q < a.nwide) fwd_hub_w<W>(a, pick_cg<L>(a.cglist, q), wid - q * a.nhubs, produced, outs);
     flush_counts(produced, outs, nv, na, a.ctr);
 }
 

@@ -19,7 +19,12 @@
 // several requests at once, until the next step is launched), leaves the
 // forward loop when every one of its lanes has an empty frontier, and runs
 // one counting product -- exactly the per-batch schedule of the plain path,
-// while different groups sit in different phases.  Columns that finish the
+// while different groups sit in different phases.  The forward product runs
+// on fixed pairs of groups (2p, 2p+1) as in the plain path, over every pair
+// with a group in the forward loop; a group outside it reads and writes only
+// absent lanes in its half of a pair row (its last forward product produced
+// nothing, and every row written since carries kSent there), so its state is
+// never touched.  Columns that finish the
 // backward loop become DONE one by one.  The forward and backward states
 // have separate buffers, since one step holds groups in both loops.
 #include <algorithm>
@@ -59,28 +64,29 @@ __global__ void k_srv_reset_cols(int n, const uint64_t *newmask, int32_t *tdist,
     }
 }
 
-// Rows of new sources that are not yet in the current forward frontier
-// start with every lane absent.
+// Pair rows (groups 2q and 2q+1, kWide = 2 entries per lane) of new sources
+// that are not yet in the current forward frontier start with every lane of
+// both groups absent (no lane of the pair is in the frontier there).
 __global__ void k_srv_seed_rows(int n, int nwords, const int32_t *cols, int count,
                                 const int32_t *src, uint32_t *ftup, const uint32_t *abits) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
-    const int c = cols[i], v = src[c], cg = c / kWave;
-    if ((abits[(size_t)cg * nwords + (v >> 5)] >> (v & 31)) & 1u) return;
-    const size_t row = ((size_t)cg * n + v) * kWave;
-    for (int l = 0; l < kWave; l++) ftup[row + l] = kSent;
+    const int c = cols[i], v = src[c], q = c / (kWave * kWide);
+    if ((abits[(size_t)q * nwords + (v >> 5)] >> (v & 31)) & 1u) return;
+    const size_t row = ((size_t)q * n + v) * kWave * kWide;
+    for (int l = 0; l < kWave * kWide; l++) ftup[row + l] = kSent;
 }
 
 __global__ void k_srv_seed(int n, int nwords, const int32_t *cols, int count, const int32_t *src,
                            int32_t *tdist, double *tsig, uint32_t *ftup, uint32_t *abits) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
-    const int c = cols[i], v = src[c], cg = c / kWave, lane = c % kWave;
+    const int c = cols[i], v = src[c], cg = c / kWave, lane = c % kWave, q = cg / kWide;
     const size_t idx = ((size_t)cg * n + v) * kWave + lane;
     tdist[idx] = 0;
     tsig[idx] = 1.0;
-    ftup[idx] = 1u;
-    atomicOr(abits + (size_t)cg * nwords + (v >> 5), 1u << (v & 31));
+    ftup[(((size_t)q * n + v) * kWave + lane) * kWide + (cg % kWide)] = 1u;
+    atomicOr(abits + (size_t)q * nwords + (v >> 5), 1u << (v & 31));
 }
 
 // dest_i[v] += delta(column cols[i], v) for every listed column, in list
@@ -127,6 +133,8 @@ using namespace mfbc;
 struct mfbc_server {
     mfbc_graph *g = nullptr;
     int width = 0, ncg = 0, nwords = 0;
+    int npair = 0;                          // forward pairs (groups 2p, 2p+1; the last may be
+                                            // half padding, whose tiles exist but hold no column)
     int cur_f = 0, cur_b = 0, kfwd = 0, kbwd = 0;
     int32_t *tdist = nullptr;
     double *tsig = nullptr;
@@ -252,11 +260,11 @@ extern "C" {
 
 int mfbc_server_footprint(const mfbc_graph *g, int32_t width, int64_t *bytes) {
     if (!g || !bytes || width < 64 || width % 64) return sfail(MFBC_EINVAL, "bad arguments");
-    const int64_t n = g->n, ncg = width / 64;
+    const int64_t n = g->n, ncg = width / 64, ncg2 = (ncg + 1) & ~1;
     const int64_t slots = std::max(g->plan_in.nslots, g->plan_out.nslots);
     const int64_t nw = (n + 31) / 32;
-    *bytes = n * width * (4 + 8 + 2 * 4 + 2 * 8 + 4 + 8 + 8) + 2 * ncg * n * 8 + 4 * ncg * nw * 4 +
-             slots * width * 12 + ncg * std::max<int64_t>(g->arcs, 1) * 8;
+    *bytes = n * 64 * ncg2 * (4 + 8 + 2 * 4 + 2 * 8 + 4 + 8 + 8) + 2 * ncg * n * 8 + 4 * ncg * nw * 4 +
+             slots * 64 * ncg2 * 12 + ncg * std::max<int64_t>(g->arcs, 1) * 8;
     return MFBC_OK;
 }
 
@@ -272,9 +280,12 @@ int mfbc_server_create(mfbc_graph *g, int32_t width, mfbc_server **out) {
     s->g = g;
     s->width = width;
     s->ncg = width / 64;
+    s->npair = (s->ncg + kWide - 1) / kWide;
     s->nwords = (g->n + 31) / 32;
-    const size_t n = (size_t)g->n, tile = n * (size_t)width, ncg = (size_t)s->ncg;
-    const size_t slots = (size_t)std::max(g->plan_in.nslots, g->plan_out.nslots) * (size_t)width;
+    // per-(column, vertex) tiles and hub slots cover whole pairs
+    const size_t n = (size_t)g->n, ncg = (size_t)s->ncg, ncg2 = (size_t)s->npair * kWide;
+    const size_t tile = n * kWave * ncg2;
+    const size_t slots = (size_t)std::max(g->plan_in.nslots, g->plan_out.nslots) * kWave * ncg2;
     int rc = MFBC_OK;
     if (salloc(&s->tdist, tile) || salloc(&s->tsig, tile) || salloc(&s->ftup[0], tile) ||
         salloc(&s->ftup[1], tile) || salloc(&s->fsig[0], tile) || salloc(&s->fsig[1], tile) ||
@@ -441,10 +452,16 @@ int mfbc_server_step_launch(mfbc_server *s, void *hip_stream) {
     const size_t ncg = (size_t)s->ncg;
     // each product runs only over the column groups that have columns in its
     // phase (a product's cost is per group, whatever the number of columns)
+    // the forward product's list holds pairs (either group in the forward loop)
     int32_t *lists = s->h_stage;
     int nf = 0, nbk = 0, nc = 0;
+    for (int q = 0; q < s->npair; q++) {
+        bool any = false;
+        for (int c = 0; c < kWide; c++)
+            any |= (size_t)(q * kWide + c) < ncg && gf[(size_t)(q * kWide + c)];
+        if (any) lists[(size_t)nf++] = q;
+    }
     for (size_t g2 = 0; g2 < ncg; g2++) {
-        if (gf[g2]) lists[(size_t)nf++] = (int32_t)g2;
         if (gb[g2]) lists[ncg + (size_t)nbk++] = (int32_t)g2;
         if (gc[g2]) lists[2 * ncg + (size_t)nc++] = (int32_t)g2;
     }
@@ -460,8 +477,10 @@ int mfbc_server_step_launch(mfbc_server *s, void *hip_stream) {
         a.ntasks = g->plan_in.ntasks;
         a.nhubs = g->plan_in.nhubs;
         a.nslots = g->plan_in.nslots;
-        a.ncg = nf;
+        a.ncg = nf * kWide;
         a.ncg_all = s->ncg;
+        a.nwide = nf;
+        a.nwide_all = s->npair;
         a.cglist = s->cglists;
         a.n = g->n;
         a.j = ++s->kfwd;
@@ -486,13 +505,13 @@ int mfbc_server_step_launch(mfbc_server *s, void *hip_stream) {
         a.colmask = s->colmask;
         const int grid = nblocks((size_t)a.ntasks * nf, kWavesPerBlock, 0x7fffffff);
         switch (srv_mode(g->in)) {
-            case 0: hipLaunchKernelGGL((k_fwd_pull<0, true>), dim3(grid), dim3(kBlock), 0, st, a); break;
-            case 1: hipLaunchKernelGGL((k_fwd_pull<1, true>), dim3(grid), dim3(kBlock), 0, st, a); break;
-            default: hipLaunchKernelGGL((k_fwd_pull<2, true>), dim3(grid), dim3(kBlock), 0, st, a); break;
+            case 0: hipLaunchKernelGGL((k_fwd_pull_w<0, kWide, true>), dim3(grid), dim3(kBlock), 0, st, a); break;
+            case 1: hipLaunchKernelGGL((k_fwd_pull_w<1, kWide, true>), dim3(grid), dim3(kBlock), 0, st, a); break;
+            default: hipLaunchKernelGGL((k_fwd_pull_w<2, kWide, true>), dim3(grid), dim3(kBlock), 0, st, a); break;
         }
         const int mgrid = std::max(nblocks((size_t)a.nhubs * nf, kWavesPerBlock, 0x7fffffff),
                                    nblocks((size_t)nw, kBlock, 1024));
-        hipLaunchKernelGGL(k_fwd_merge<true>, dim3(mgrid), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL((k_fwd_merge_w<kWide, true>), dim3(mgrid), dim3(kBlock), 0, st, a);
         s->cur_f ^= 1;
     }
     BwdArgs c{};
