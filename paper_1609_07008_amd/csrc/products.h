@@ -663,7 +663,18 @@ struct BwdArgs {
     uint64_t *dag;             // the shortest-path DAG, one lane mask per out-arc, [cg][narcs]:
     int64_t narcs;             //   written by the counting product (skipped if NULL), read by
                                //   the backward products in place of the distance test
+    int nwide;                 // paired layout (plain path, two or more groups): lane masks
+                               //   interleaved per pair of groups, [cg/2][n][2], and one
+                               //   activity bitmap per pair; 0: one group per plane
+    int nwide_all;             //   pairs of the state (bitmap planes)
 };
+
+// Index of (cg, x) in the lane masks and plane of cg in the activity bitmaps.
+__device__ __forceinline__ size_t fb_index(const BwdArgs &a, int cg, int x) {
+    return a.nwide ? ((size_t)(cg >> 1) * (size_t)a.n + (size_t)x) * 2 + (cg & 1)
+                   : (size_t)cg * (size_t)a.n + (size_t)x;
+}
+__device__ __forceinline__ int ab_plane(const BwdArgs &a, int cg) { return a.nwide ? cg >> 1 : cg; }
 
 // Per-vertex finish of the counting product: counters, leaves, zeta = 0.
 __device__ __forceinline__ uint64_t count_finalize(const BwdArgs &a, size_t cgv, int cg, int x,
@@ -682,7 +693,7 @@ __device__ __forceinline__ uint64_t count_finalize(const BwdArgs &a, size_t cgv,
     }
     const uint64_t bits = ballot(front);
     if (lane == 0) {
-        uint64_t *row = a.fbits_n + cgv + (size_t)x;
+        uint64_t *row = a.fbits_n + fb_index(a, cg, x);
         *row = a.cmask ? ((*row & ~mask) | bits) : bits;
     }
     return bits;
@@ -755,7 +766,7 @@ __device__ __forceinline__ void count_task(const BwdArgs &a, int cg, int t, unsi
         }
     }
     if (hub < 0 && lane == 0 && run_act)
-        or_run_bits(a.abits_n + (size_t)cg * a.nwords, v0, run_act);
+        or_run_bits(a.abits_n + (size_t)ab_plane(a, cg) * a.nwords, v0, run_act);
     flush_colmask(a.colmask, a.ncg_all, cg, colany);
 }
 
@@ -771,7 +782,8 @@ __device__ __forceinline__ void count_hub(const BwdArgs &a, int cg, int h, unsig
     const uint64_t b = count_finalize(a, cgv, cg, x, dx, c, lane);
     produced += __popcll(b);
     colany |= b;
-    if (b && lane == 0) atomicOr(a.abits_n + (size_t)cg * a.nwords + (x >> 5), 1u << (x & 31));
+    if (b && lane == 0)
+        atomicOr(a.abits_n + (size_t)ab_plane(a, cg) * a.nwords + (x >> 5), 1u << (x & 31));
     flush_colmask(a.colmask, a.ncg_all, cg, colany);
 }
 
@@ -810,7 +822,7 @@ __device__ __forceinline__ uint64_t bwd_finalize(const BwdArgs &a, size_t cgv, i
             if (lane == 0 && t != 0.0 && a.lam) a.lam[cgv + (size_t)x] += t;
         }
     }
-    if (lane == 0) a.fbits_n[cgv + (size_t)x] = bits;
+    if (lane == 0) a.fbits_n[fb_index(a, cg, x)] = bits;
     return bits;
 }
 
@@ -935,6 +947,150 @@ __device__ __forceinline__ void bwd_hub(const BwdArgs &a, int cg, int h, unsigne
     flush_colmask(a.colmask, a.ncg_all, cg, colany);
 }
 
+// One pull task of a backward product for the pair of column groups q
+// (paired layout, plain path): one pass over the arcs serves both groups --
+// one activity test, one 16-byte gather of the head's two lane masks -- and
+// each group then gathers q(s, y) only for the lanes its DAG mask and the
+// head's frontier mask share.  A padding group (odd group count) has no
+// state and counts no arc.
+template <int AM>
+__device__ __forceinline__ void bwd_task_w(const BwdArgs &a, int q, int t, unsigned long long &produced,
+                                           unsigned long long &outs) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const Task *tp = a.tasks + t;
+    const int v0 = uni(tp->v0), v1 = uni(tp->v1), hub = uni(tp->hub), part = uni(tp->part);
+    const int64_t e0 = uni64(tp->e0), e1 = uni64(tp->e1);
+    const int cg0 = 2 * q;
+    const bool has1 = cg0 + 1 < a.ncg;
+    const size_t n = (size_t)a.n;
+    const size_t cgv0 = (size_t)cg0 * n, cgv1 = cgv0 + n;
+    const double *Q0 = a.q + cgv0 * kWave, *Q1 = a.q + cgv1 * kWave;
+    const ulonglong2 *Fb = (const ulonglong2 *)a.fbits + (size_t)q * n;
+    const uint64_t *Dg0 = a.dag + (size_t)cg0 * a.narcs, *Dg1 = Dg0 + a.narcs;
+    const uint32_t *Ab = a.abits + (size_t)q * a.nwords;
+    int x = v0;
+    int64_t vend = hub >= 0 ? e1 : a.rp[v0 + 1];
+    bool loaded = false;
+    int cx0 = -1, cx1 = -1, got0 = 0, got1 = 0;
+    double acc0 = 0.0, acc1 = 0.0;
+    uint64_t run_act = 0;
+    auto finish = [&]() {
+        if (loaded) {
+            // one copy of the finish code for both groups (registers)
+            uint64_t bb = 0;
+#pragma unroll 1
+            for (int c = 0; c < 2; c++) {
+                if (c == 1 && !has1) break;
+                const uint64_t b = bwd_finalize(a, c ? cgv1 : cgv0, cg0 + c, x, c ? cx1 : cx0,
+                                                c ? acc1 : acc0, c ? got1 : got0, lane, outs);
+                produced += __popcll(b);
+                bb |= b;
+            }
+            if (bb) run_act |= 1ull << (x - v0);
+        } else if (lane < 2) {
+            a.fbits_n[((size_t)q * n + (size_t)x) * 2 + lane] = 0ull;
+        }
+        loaded = false;
+        got0 = got1 = 0;
+        acc0 = acc1 = 0.0;
+    };
+    for (int64_t e = e0; e < e1; e += kWave) {
+        const int64_t my = e + lane;
+        int y = 0, wt = 1;
+        uint64_t live0 = 0, live1 = 0;
+        if (my < e1) {
+            load_arc<AM>(a.arcs, my, y, wt);
+            if ((Ab[y >> 5] >> (y & 31)) & 1u) {
+                const ulonglong2 f = Fb[y];
+                live0 = f.x & Dg0[my];
+                if (has1) live1 = f.y & Dg1[my];
+            }
+        }
+        uint64_t am = ballot((live0 | live1) != 0);
+        while (am) {
+            const int j0 = __ffsll((unsigned long long)am) - 1;
+            if (hub < 0) {
+                while (e + j0 >= vend) {
+                    finish();
+                    ++x;
+                    vend = a.rp[x + 1];
+                }
+            }
+            uint64_t cand = am & owner_mask(e, vend);
+            double q0[2], q1[2];
+#pragma unroll
+            for (int k = 0; k < 2; k++) {
+                q0[k] = 0.0;
+                q1[k] = 0.0;
+                if (cand) {
+                    const int j = __ffsll((unsigned long long)cand) - 1;
+                    cand &= cand - 1;
+                    am &= ~(1ull << j);
+                    const int yk = rdlane(y, j);
+                    if ((rdlane64(live0, j) >> lane) & 1ull) {
+                        q0[k] = Q0[(size_t)yk * kWave + lane];
+                        got0++;
+                    }
+                    if ((rdlane64(live1, j) >> lane) & 1ull) {
+                        q1[k] = Q1[(size_t)yk * kWave + lane];
+                        got1++;
+                    }
+                }
+            }
+            if (!loaded) {
+                cx0 = a.cnt[(cgv0 + (size_t)x) * kWave + lane];
+                cx1 = has1 ? a.cnt[(cgv1 + (size_t)x) * kWave + lane] : -1;
+                loaded = true;
+            }
+#pragma unroll
+            for (int k = 0; k < 2; k++) {
+                acc0 += q0[k];
+                acc1 += q1[k];
+            }
+        }
+    }
+    if (hub < 0) {
+        while (x < v1) {
+            finish();
+            ++x;
+        }
+        if (lane == 0 && run_act) or_run_bits(a.abits_n + (size_t)q * a.nwords, v0, run_act);
+    } else {
+        const size_t p0 = ((size_t)cg0 * a.nslots + part) * kWave + lane;
+        const size_t p1 = p0 + (size_t)a.nslots * kWave;
+        a.pd[p0] = got0;
+        a.pm[p0] = acc0;
+        a.pd[p1] = got1;
+        a.pm[p1] = acc1;
+    }
+}
+
+// Combine the slices of split row h for both groups of pair q and finish it.
+__device__ __forceinline__ void bwd_hub_w(const BwdArgs &a, int q, int h, unsigned long long &produced,
+                                          unsigned long long &outs) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const Hub *hp = a.hubs + h;
+    const int x = uni(hp->v), first = uni(hp->first), np = uni(hp->nparts);
+    uint64_t any = 0;
+    for (int c = 0; c < 2; c++) {
+        const int cg = 2 * q + c;
+        if (cg >= a.ncg) break;
+        const size_t cgv = (size_t)cg * (size_t)a.n;
+        int got = 0;
+        double acc = 0.0;
+        for (int p = first; p < first + np; p++) {
+            const size_t pidx = ((size_t)cg * a.nslots + p) * kWave + lane;
+            got += a.pd[pidx];
+            acc += a.pm[pidx];
+        }
+        const int cx = a.cnt[(cgv + (size_t)x) * kWave + lane];
+        const uint64_t b = bwd_finalize(a, cgv, cg, x, cx, acc, got, lane, outs);
+        produced += __popcll(b);
+        any |= b;
+    }
+    if (any && lane == 0) atomicOr(a.abits_n + (size_t)q * a.nwords + (x >> 5), 1u << (x & 31));
+}
+
 // ===================================================================== grid kernels
 // The pull kernels are latency bound, so waves in flight matter most.  A SIMD
 // holds 800 scalar registers, handed out in granules, so eight waves per SIMD
@@ -1027,6 +1183,29 @@ __global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_bwd_pull(BwdArgs a) 
     unsigned long long produced = 0, outs = 0;
     if (cg < a.ncg) bwd_task<AM>(a, pick_cg<L>(a.cglist, cg), wid - cg * a.ntasks, produced, outs);
     flush_counts(produced, outs, 0, 0, a.ctr);
+}
+
+// Paired backward product (plain path): wave = (pair, task), pair-major.
+template <int AM>
+__global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_bwd_pull_w(BwdArgs a) {
+    const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const int q = wid / a.ntasks;
+    unsigned long long produced = 0, outs = 0;
+    if (q < a.nwide) bwd_task_w<AM>(a, q, wid - q * a.ntasks, produced, outs);
+    flush_counts(produced, outs, 0, 0, a.ctr);
+}
+
+template <int D = 0>
+__global__ __launch_bounds__(kBlock) void k_bwd_merge_w(BwdArgs a) {
+    const int gtid = blockIdx.x * kBlock + threadIdx.x;
+    unsigned long long nv = 0, na = 0;
+    clear_and_count(a.clear_bits, a.nwords, a.nwide_all, a.rp, nv, na);
+    if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
+    const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    unsigned long long produced = 0, outs = 0;
+    const int q = a.nhubs ? wid / a.nhubs : a.nwide;
+    if (q < a.nwide) bwd_hub_w(a, q, wid - q * a.nhubs, produced, outs);
+    flush_counts(produced, outs, nv, na, a.ctr);
 }
 
 template <bool L>
