@@ -12,7 +12,10 @@
 //
 // Same data layout and work decomposition as the MFBF forward product:
 // [cg][v][64] tiles (lane = source column), per-column-group vertex bitmaps,
-// runs of light rows and slices of hub rows merged in slice order.
+// runs of light rows and slices of hub rows merged in slice order; batches
+// of two or more groups run on pairs of them, the frontier values of groups
+// 2p and 2p+1 interleaved per lane (one 8-byte gather for both) with one
+// bitmap per pair, as in the forward product.
 #include "products.h"
 
 namespace mfbc {
@@ -33,6 +36,7 @@ struct MonoArgs {
     unsigned long long *ctr;   // counter slots of product j
     uint32_t *clear_bits;      // merge: F_{j-1}'s bitmaps, ncg planes
     unsigned long long *clear_ctr;
+    int nwide;                 // pairs of groups (paired layout), 0: one group per wave
 };
 
 template <int OP>
@@ -147,6 +151,166 @@ __device__ __forceinline__ void mono_hub(const MonoArgs &a, int cg, int h,
     if (b && lane == 0) atomicOr(a.abits_n + (size_t)cg * a.nwords + (v >> 5), 1u << (v & 31));
 }
 
+// Paired form: groups 2q and 2q+1 at once (frontier values interleaved per
+// lane); T keeps the one-group layout.  Returns the lanes in the next
+// frontier in either group.
+__device__ __forceinline__ uint64_t mono_finalize2(const MonoArgs &a, int q, int v, int b0, int b1,
+                                                   int t0, int t1, int lane, unsigned long long &outs,
+                                                   unsigned long long &produced) {
+    const uint64_t h0 = ballot(b0 != kInf), h1 = ballot(b1 != kInf);
+    outs += __popcll(h0) + __popcll(h1);
+    if (!(h0 | h1)) return 0;
+    const size_t n = (size_t)a.n;
+    const size_t i0 = ((size_t)(2 * q) * n + (size_t)v) * kWave + lane, i1 = i0 + n * kWave;
+    const bool k0 = b0 != kInf && b0 < t0, k1 = b1 != kInf && b1 < t1;
+    if (k0) a.tval[i0] = b0;
+    if (k1) a.tval[i1] = b1;
+    const uint64_t m0 = ballot(k0), m1 = ballot(k1);
+    produced += __popcll(m0) + __popcll(m1);
+    if (m0 | m1)
+        ((int2 *)a.fval_n)[((size_t)q * n + (size_t)v) * kWave + lane] =
+            make_int2(k0 ? b0 : kInf, k1 ? b1 : kInf);
+    return m0 | m1;
+}
+
+template <int OP, int AM, int U = 4>
+__device__ __forceinline__ void mono_task2(const MonoArgs &a, int q, int t, unsigned long long &produced,
+                                           unsigned long long &outs) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const Task *tp = a.tasks + t;
+    const int v0 = uni(tp->v0), v1 = uni(tp->v1), hub = uni(tp->hub), part = uni(tp->part);
+    const int64_t e0 = uni64(tp->e0), e1 = uni64(tp->e1);
+    const size_t n = (size_t)a.n;
+    const int2 *Fv = (const int2 *)a.fval + (size_t)q * n * kWave;
+    const int32_t *Td0 = a.tval + ((size_t)(2 * q) * n + (size_t)v0) * kWave + lane;
+    const int32_t *Td1 = Td0 + n * kWave;
+    const uint32_t *Ab = a.abits + (size_t)q * a.nwords;
+    const int64_t rend = (hub < 0 && v0 + lane < v1) ? a.rp[v0 + lane + 1] : INT64_MAX;
+    int cur = -1, best0 = kInf, best1 = kInf, td0 = kInf, td1 = kInf;
+    uint64_t run_act = 0;
+    auto close = [&](int o) {
+        if (mono_finalize2(a, q, v0 + o, best0, best1, td0, td1, lane, outs, produced))
+            run_act |= 1ull << o;
+    };
+    int un = 0, wn = 1;
+    if (e0 + lane < e1) load_arc<AM>(a.arcs, e0 + lane, un, wn);
+    for (int64_t e = e0; e < e1; e += kWave) {
+        const int64_t my = e + lane;
+        const int u = un, wt = wn;
+        const bool act = my < e1 && ((Ab[u >> 5] >> (u & 31)) & 1u);
+        if (my + kWave < e1) load_arc<AM>(a.arcs, my + kWave, un, wn);
+        uint64_t am = ballot(act);
+        while (am) {
+            int ow[U], wk[U], tn0[U], tn1[U];
+            int2 tk[U];
+            int prev = cur;
+#pragma unroll
+            for (int k = 0; k < U; k++) {
+                const int j = am ? __ffsll((unsigned long long)am) - 1 : -1;
+                am &= am - 1;
+                ow[k] = -1;
+                wk[k] = 0;
+                tk[k] = make_int2(kInf, kInf);
+                tn0[k] = kInf;
+                tn1[k] = kInf;
+                if (j >= 0) {
+                    const int uk = rdlane(u, j);
+                    wk[k] = AM ? rdlane(wt, j) : 1;
+                    tk[k] = Fv[(size_t)uk * kWave + lane];
+                    ow[k] = __popcll(ballot(rend <= e + j));
+                    if (hub < 0 && ow[k] != prev) {
+                        tn0[k] = Td0[(size_t)ow[k] * kWave];
+                        tn1[k] = Td1[(size_t)ow[k] * kWave];
+                    }
+                    prev = ow[k];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < U; k++) {
+                if (ow[k] >= 0) {
+                    if (ow[k] != cur) {
+                        if (cur >= 0 && hub < 0) close(cur);
+                        cur = ow[k];
+                        best0 = best1 = kInf;
+                        td0 = tn0[k];
+                        td1 = tn1[k];
+                    }
+                    if (tk[k].x != kInf) best0 = min(best0, mono_act<OP>(tk[k].x, wk[k]));
+                    if (tk[k].y != kInf) best1 = min(best1, mono_act<OP>(tk[k].y, wk[k]));
+                }
+            }
+        }
+    }
+    if (hub < 0) {
+        if (cur >= 0) close(cur);
+        if (lane == 0 && run_act) or_run_bits(a.abits_n + (size_t)q * a.nwords, v0, run_act);
+    } else {
+        const size_t p0 = ((size_t)(2 * q) * a.nslots + part) * kWave + lane;
+        a.pd[p0] = best0;
+        a.pd[p0 + (size_t)a.nslots * kWave] = best1;
+    }
+}
+
+__device__ __forceinline__ void mono_hub2(const MonoArgs &a, int q, int h, unsigned long long &produced,
+                                          unsigned long long &outs) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const Hub *hp = a.hubs + h;
+    const int v = uni(hp->v), first = uni(hp->first), np = uni(hp->nparts);
+    const size_t n = (size_t)a.n;
+    int b0 = kInf, b1 = kInf;
+    for (int p = first; p < first + np; p++) {
+        const size_t p0 = ((size_t)(2 * q) * a.nslots + p) * kWave + lane;
+        b0 = min(b0, a.pd[p0]);
+        b1 = min(b1, a.pd[p0 + (size_t)a.nslots * kWave]);
+    }
+    const size_t i0 = ((size_t)(2 * q) * n + (size_t)v) * kWave + lane;
+    const int t0 = b0 != kInf ? a.tval[i0] : kInf;
+    const int t1 = b1 != kInf ? a.tval[i0 + n * kWave] : kInf;
+    const uint64_t b = mono_finalize2(a, q, v, b0, b1, t0, t1, lane, outs, produced);
+    if (b && lane == 0) atomicOr(a.abits_n + (size_t)q * a.nwords + (v >> 5), 1u << (v & 31));
+}
+
+template <int OP, int AM>
+__global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_mono_pull2(MonoArgs a) {
+    const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const int q = wid / a.ntasks;
+    unsigned long long produced = 0, outs = 0;
+    if (q < a.nwide) mono_task2<OP, AM>(a, q, wid - q * a.ntasks, produced, outs);
+    flush_counts(produced, outs, 0, 0, a.ctr);
+}
+
+__global__ __launch_bounds__(kBlock) void k_mono_merge2(MonoArgs a) {
+    const int gtid = blockIdx.x * kBlock + threadIdx.x;
+    unsigned long long nv = 0, na = 0;
+    clear_and_count(a.clear_bits, a.nwords, a.nwide, a.rp, nv, na);
+    if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
+    const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    unsigned long long produced = 0, outs = 0;
+    const int q = a.nhubs ? wid / a.nhubs : a.nwide;
+    if (q < a.nwide) mono_hub2(a, q, wid - q * a.nhubs, produced, outs);
+    flush_counts(produced, outs, nv, na, a.ctr);
+}
+
+// Seeds of the paired layout: a source's pair row starts with every lane of
+// both groups absent, then its own lane carries 0.
+__global__ void k_mono_seed_rows2(const int32_t *src, int nb, int n, int2 *fval) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nb) return;
+    const size_t row = ((size_t)(c / (2 * kWave)) * n + src[c]) * kWave;
+    for (int l = 0; l < kWave; l++) fval[row + l] = make_int2(kInf, kInf);
+}
+
+__global__ void k_mono_seed2(const int32_t *src, int nb, int n, int nwords, int32_t *tval,
+                             int32_t *fval, uint32_t *abits) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nb) return;
+    const int v = src[c];
+    const int cg = c / kWave, lane = c % kWave, q = cg >> 1;
+    tval[((size_t)cg * n + v) * kWave + lane] = 0;
+    fval[(((size_t)q * n + v) * kWave + lane) * 2 + (cg & 1)] = 0;
+    atomicOr(abits + (size_t)q * nwords + (v >> 5), 1u << (v & 31));
+}
+
 template <int OP, int AM>
 __global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_mono_pull(MonoArgs a) {
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
@@ -221,12 +385,24 @@ int mono_mode(const Csr &c) { return c.w == nullptr ? 0 : (c.pk ? 1 : 2); }
 
 template <int OP>
 void launch_pull(int mode, int grid, hipStream_t s, const MonoArgs &a) {
+    if (a.nwide) {
+        switch (mode) {
+            case 0: hipLaunchKernelGGL((k_mono_pull2<OP, 0>), dim3(grid), dim3(kBlock), 0, s, a); break;
+            case 1: hipLaunchKernelGGL((k_mono_pull2<OP, 1>), dim3(grid), dim3(kBlock), 0, s, a); break;
+            default: hipLaunchKernelGGL((k_mono_pull2<OP, 2>), dim3(grid), dim3(kBlock), 0, s, a); break;
+        }
+        return;
+    }
     switch (mode) {
         case 0: hipLaunchKernelGGL((k_mono_pull<OP, 0>), dim3(grid), dim3(kBlock), 0, s, a); break;
         case 1: hipLaunchKernelGGL((k_mono_pull<OP, 1>), dim3(grid), dim3(kBlock), 0, s, a); break;
         default: hipLaunchKernelGGL((k_mono_pull<OP, 2>), dim3(grid), dim3(kBlock), 0, s, a); break;
     }
 }
+
+// Batches of two or more groups run on pairs (the workspace holds an even
+// number of groups).
+int mono_pairs(int ncg) { return ncg >= 2 ? (ncg + 1) / 2 : 0; }
 
 }  // namespace
 
@@ -237,6 +413,13 @@ void launch_mono_init(mfbc_graph *g, int ncg, int nb, hipStream_t s) {
     hipLaunchKernelGGL(k_mono_fill, dim3(nblk(total, 256, 65536)), dim3(256), 0, s, ws.tdist, total,
                        ws.abits[0], ws.abits[1], (size_t)ncg * nwords, ws.counters,
                        kCounterRing * 4 * kCounterSlots);
+    if (mono_pairs(ncg)) {
+        hipLaunchKernelGGL(k_mono_seed_rows2, dim3(nblk(nb, 256)), dim3(256), 0, s, ws.src, nb, g->n,
+                           (int2 *)ws.fdist[0]);
+        hipLaunchKernelGGL(k_mono_seed2, dim3(nblk(nb, 256)), dim3(256), 0, s, ws.src, nb, g->n,
+                           nwords, ws.tdist, ws.fdist[0], ws.abits[0]);
+        return;
+    }
     hipLaunchKernelGGL(k_mono_seed_rows, dim3(nblk(nb, 256)), dim3(256), 0, s, ws.src, nb, g->n,
                        ws.fdist[0]);
     hipLaunchKernelGGL(k_mono_seed, dim3(nblk(nb, 256)), dim3(256), 0, s, ws.src, nb, g->n, nwords,
@@ -266,14 +449,19 @@ void launch_mono_product(mfbc_graph *g, int op, int ncg, int j, hipStream_t s, h
     a.ctr = ws.counters + (size_t)(j % kCounterRing) * 4 * kCounterSlots;
     a.clear_bits = ws.abits[b];
     a.clear_ctr = ws.counters + (size_t)((j + 1) % kCounterRing) * 4 * kCounterSlots;
+    a.nwide = mono_pairs(ncg);
+    const int waves_per_task = a.nwide ? a.nwide : ncg;
     if (ev) (void)hipEventRecord(ev[0], s);
-    const int grid = nblk((size_t)a.ntasks * ncg, kWavesPerBlock);
+    const int grid = nblk((size_t)a.ntasks * waves_per_task, kWavesPerBlock);
     if (op == 0) launch_pull<0>(mono_mode(g->in), grid, s, a);
     else launch_pull<1>(mono_mode(g->in), grid, s, a);
     if (ev) (void)hipEventRecord(ev[1], s);
-    const int mgrid = std::max(nblk((size_t)a.nhubs * ncg, kWavesPerBlock),
+    const int mgrid = std::max(nblk((size_t)a.nhubs * waves_per_task, kWavesPerBlock),
                                nblk((size_t)a.nwords, kBlock, 1024));
-    hipLaunchKernelGGL(k_mono_merge, dim3(mgrid), dim3(kBlock), 0, s, a);
+    if (a.nwide)
+        hipLaunchKernelGGL(k_mono_merge2, dim3(mgrid), dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_mono_merge, dim3(mgrid), dim3(kBlock), 0, s, a);
     if (ev) (void)hipEventRecord(ev[2], s);
 }
 
