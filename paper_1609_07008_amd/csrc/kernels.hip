@@ -32,7 +32,10 @@
 // 64 columns active; n/8 bytes, resident in L2) is checked per arc first.
 // The forward product then reads the neighbour's whole 256-B tuple row
 // (absent lanes hold a sentinel); the backward product reads the 64-bit
-// lane masks and gathers q only for the lanes that count.
+// lane masks and gathers q only for the lanes that count.  Batches of two
+// or more column groups run the forward product (and on weighted graphs the
+// backward products) on pairs of groups: one 8-byte (16-byte) gather per
+// lane and one bitmap test per arc serve both groups (products.h).
 #include "products.h"
 
 namespace mfbc {
