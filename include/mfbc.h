@@ -28,13 +28,13 @@
  *   - Device pointers ("d_") are caller-owned device memory of the current
  *     HIP device (for example torch tensors); host pointers ("h_") are plain
  *     host memory.  The library owns only the graph and its workspace.
- *   - Workspace: a batch of nb sources (ceil(nb/64) groups of 64 columns)
- *     takes about 37 B per (column, vertex) -- T and two frontier buffers,
- *     which the backward state reuses -- plus 8 B per (group of 64 columns,
- *     arc) for the shortest-path DAG that the counting product stores for
- *     the backward products (1 GiB at 2^25 arcs and 256 columns).  It grows
- *     to the largest batch seen and is freed with the graph; ENOMEM if it
- *     does not fit.
+ *   - Workspace: a batch of nb sources (ceil(nb/64) groups of 64 columns,
+ *     rounded up to an even count) takes about 37 B per (column, vertex) --
+ *     T and two frontier buffers, which the backward state reuses -- plus
+ *     8 B per (group of 64 columns, arc) for the shortest-path DAG that the
+ *     counting product stores for the backward products (1 GiB at 2^25 arcs
+ *     and 256 columns).  It grows to the largest batch seen and is freed
+ *     with the graph; ENOMEM if it does not fit.
  *   - hip_stream is a hipStream_t (NULL = the default stream).  Calls are
  *     ordered on that stream and return after their outputs are complete
  *     (they synchronise on the stream to read frontier sizes).
