@@ -258,10 +258,24 @@ __device__ __forceinline__ void mono_hub2(const MonoArgs &a, int q, int h, unsig
     const int v = uni(hp->v), first = uni(hp->first), np = uni(hp->nparts);
     const size_t n = (size_t)a.n;
     int b0 = kInf, b1 = kInf;
-    for (int p = first; p < first + np; p++) {
-        const size_t p0 = ((size_t)(2 * q) * a.nslots + p) * kWave + lane;
-        b0 = min(b0, a.pd[p0]);
-        b1 = min(b1, a.pd[p0 + (size_t)a.nslots * kWave]);
+    // four slices' partials in flight (min is order-free)
+    for (int p = first; p < first + np; p += 4) {
+        int d0[4], d1[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            d0[k] = kInf;
+            d1[k] = kInf;
+            if (p + k < first + np) {
+                const size_t p0 = ((size_t)(2 * q) * a.nslots + p + k) * kWave + lane;
+                d0[k] = a.pd[p0];
+                d1[k] = a.pd[p0 + (size_t)a.nslots * kWave];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            b0 = min(b0, d0[k]);
+            b1 = min(b1, d1[k]);
+        }
     }
     const size_t i0 = ((size_t)(2 * q) * n + (size_t)v) * kWave + lane;
     const int t0 = b0 != kInf ? a.tval[i0] : kInf;

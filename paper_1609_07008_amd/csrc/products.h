@@ -95,11 +95,14 @@ __device__ __forceinline__ void clear_and_count(uint32_t *bits, int words, int p
         }
         if (w) {
             nv += __popc(w);
+            // the arcs of a run of consecutive vertices: one row-pointer difference
+            const int64_t *r = rp + (size_t)i * 32;
             while (w) {
-                const int b = __ffs(w) - 1;
-                w &= w - 1;
-                const int u = i * 32 + b;
-                na += (unsigned long long)(rp[u + 1] - rp[u]);
+                const int b0 = __ffs(w) - 1;
+                const uint32_t from = w >> b0;
+                const int len = ~from ? __ffs(~from) - 1 : 32 - b0;
+                na += (unsigned long long)(r[b0 + len] - r[b0]);
+                w &= ~(uint32_t)(((1ull << len) - 1ull) << b0);
             }
         }
     }
@@ -611,17 +614,34 @@ __device__ __forceinline__ void fwd_hub_w(const FwdArgs &a, int q, int h, unsign
         bd[c] = kInf;
         bm[c] = 0.0;
         td[c] = kLoadTd;
-        for (int s = first; s < first + np; s++) {
-            const size_t pidx = ((size_t)(W * q + c) * a.nslots + s) * kWave + lane;
-            const int d = a.pd[pidx];
-            const double m = a.pm[pidx];
-            if (d < bd[c]) {
-                bd[c] = d;
-                bm[c] = m;
-            } else if (d == bd[c] && d != kInf) {
-                bm[c] += m;
+    }
+    // four slices' partials in flight, combined in slice order
+    for (int s0 = first; s0 < first + np; s0 += 4) {
+        int d[4][W];
+        double m[4][W];
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+#pragma unroll
+            for (int c = 0; c < W; c++) {
+                d[k][c] = kInf;
+                m[k][c] = 0.0;
+                if (s0 + k < first + np) {
+                    const size_t pidx = ((size_t)(W * q + c) * a.nslots + s0 + k) * kWave + lane;
+                    d[k][c] = a.pd[pidx];
+                    m[k][c] = a.pm[pidx];
+                }
             }
-        }
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+#pragma unroll
+            for (int c = 0; c < W; c++) {
+                if (d[k][c] < bd[c]) {
+                    bd[c] = d[k][c];
+                    bm[c] = m[k][c];
+                } else if (d[k][c] == bd[c] && d[k][c] != kInf) {
+                    bm[c] += m[k][c];
+                }
+            }
     }
     uint64_t colany[W];
 #pragma unroll
@@ -1078,10 +1098,25 @@ __device__ __forceinline__ void bwd_hub_w(const BwdArgs &a, int q, int h, unsign
         const size_t cgv = (size_t)cg * (size_t)a.n;
         int got = 0;
         double acc = 0.0;
-        for (int p = first; p < first + np; p++) {
-            const size_t pidx = ((size_t)cg * a.nslots + p) * kWave + lane;
-            got += a.pd[pidx];
-            acc += a.pm[pidx];
+        // four slices' partials in flight, summed in slice order
+        for (int p0 = first; p0 < first + np; p0 += 4) {
+            int gk[4];
+            double ak[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                gk[k] = 0;
+                ak[k] = 0.0;
+                if (p0 + k < first + np) {
+                    const size_t pidx = ((size_t)cg * a.nslots + p0 + k) * kWave + lane;
+                    gk[k] = a.pd[pidx];
+                    ak[k] = a.pm[pidx];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                got += gk[k];
+                acc += ak[k];
+            }
         }
         const int cx = a.cnt[(cgv + (size_t)x) * kWave + lane];
         const uint64_t b = bwd_finalize(a, cgv, cg, x, cx, acc, got, lane, outs);
