@@ -17,7 +17,8 @@ PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libmfbc.so")
-SOURCES = ["kernels.hip", "batched.hip", "server.hip", "monoid.hip", "graph.cpp", "mfbc_api.cpp"]
+SOURCES = ["kernels.hip", "batched.hip", "server.hip", "monoid.hip", "graph.cpp", "order.cpp",
+           "mfbc_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-Wall",
