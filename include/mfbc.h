@@ -37,7 +37,10 @@
  *     with the graph; ENOMEM if it does not fit.
  *   - hip_stream is a hipStream_t (NULL = the default stream).  Calls are
  *     ordered on that stream and return after their outputs are complete
- *     (they synchronise on the stream to read frontier sizes).
+ *     (they synchronise on the stream to read frontier sizes: products are
+ *     enqueued eight at a time and their frontier sizes read back once per
+ *     eight; a product that follows one which produced nothing returns on
+ *     the device without work).
  *   - Source-major outputs are row-major [nb][n]: entry (s, v) at s*n + v,
  *     where s indexes the listed sources.
  *   - A graph handle may be used by one thread at a time.
@@ -168,18 +171,29 @@ int mfbc_fixpoint(mfbc_graph *g, int32_t op, const int32_t *d_sources, int32_t n
                   int32_t *d_out, int32_t *h_products, void *hip_stream);
 
 /*
- * mfbc_forward_trace -- mfbc_forward that also records frontier membership.
- *   d_fmask[nb][n] device out (uint64): bit j-1 is set when v is in the
- *                  frontier produced by product j for source s (first
- *                  frontier = the source itself, before product 1); only
- *                  products 1..64 are recorded.
- *   h_nnz[max_products] host out (nullable): total frontier entries produced
- *                  by each product (all sources); entries past the last
- *                  product are left untouched.
+ * mfbc_forward_trace -- mfbc_forward that also records, after every forward
+ * product j (Algorithm 1's loop; the frontier is the set of entries of the
+ * product not heavier than what T held, Lemma 1 of Section 4.1.3), which
+ * (source, vertex) pairs are in the new frontier F_j, and the work of each
+ * product.  The first frontier F_0 (the sources themselves) precedes
+ * product 1; the last product produces an empty frontier.
+ *   d_fbits        device out (nullable): uint64 bitmaps [max_products][nb][W]
+ *                  with W = (n + 63) / 64 words per row: bit v % 64 of word
+ *                  v / 64 of row (j-1, s) is set iff caller vertex v is in F_j
+ *                  of the s-th listed source.  Rows of products past the
+ *                  last one (or all rows, if max_products exceeds it) are 0;
+ *                  products past max_products are not recorded.
+ *   max_products   rows of d_fbits and entries of h_nnz / h_relax (>= 0).
+ *   h_nnz          host out (nullable): h_nnz[j-1] = |F_j| over all sources.
+ *   h_relax        host out (nullable): h_relax[j-1] = relaxations of product
+ *                  j = sum over the entries (s, u) of F_{j-1} of the number of
+ *                  arcs leaving u (the flops of Section 5's cost model).
+ *   other arguments and errors as mfbc_forward (EINVAL for max_products < 0).
+ * Entries of h_nnz / h_relax past the last product are left untouched.
  */
 int mfbc_forward_trace(mfbc_graph *g, const int32_t *d_sources, int32_t nb,
-                       int32_t *d_dist, double *d_sigma, uint64_t *d_fmask,
-                       int64_t *h_nnz, int32_t max_products,
+                       int32_t *d_dist, double *d_sigma, uint64_t *d_fbits,
+                       int32_t max_products, int64_t *h_nnz, int64_t *h_relax,
                        int32_t *h_products, void *hip_stream);
 
 /*
@@ -236,7 +250,8 @@ typedef struct mfbc_stats {
  * runs of at most run_verts (1..64) rows and about run_arcs arcs; rows with
  * more than `heavy` arcs are cut into slices of `slice` arcs, merged in slice
  * order.  Any argument <= 0 restores the size-based default for that knob;
- * run_arcs, heavy and slice above 2^24 are rejected (EINVAL).
+ * run_arcs, heavy and slice above 2^24 are rejected (EINVAL), and so is any
+ * change while a server (mfbc_server_create) is attached to the graph.
  */
 int mfbc_set_plan(mfbc_graph *g, int32_t run_arcs, int32_t run_verts, int32_t heavy,
                   int32_t slice);

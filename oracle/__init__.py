@@ -13,8 +13,10 @@ Contents
   brute     -- exhaustive enumeration of simple paths / walks on tiny graphs
                (exact rational arithmetic), the pin for everything else.
   frontier  -- the frontier sets MFBF (Algorithm 1) and MFBr (Algorithm 2)
-               must produce, derived from hop-constrained shortest walks and
-               from DAG heights.
+               must produce, from their definitions (Lemma 1: hop-indexed
+               least-weight walks; Lemma 2: shortest-path-DAG heights), the
+               product counts and relaxations that follow from them, and the
+               monoid fixpoints (SSSP / BFS) of Section 3's product.
 
 Parity status: every function here is pinned by a ``-m "not gpu"`` test
 (brute force, closed forms, invariants, an independent library); none is
@@ -22,5 +24,6 @@ Parity status: every function here is pinned by a ``-m "not gpu"`` test
 binary64 summation order matters and only a relative bound applies.
 """
 from .brandes import brandes, brandes_threads, build_library, library_path  # noqa: F401
-from .frontier import forward_frontiers, backward_heights  # noqa: F401
-from . import brute, mfbc_ref  # noqa: F401,E402
+from .frontier import (backward_heights, backward_products, forward_frontiers,  # noqa: F401
+                       forward_relaxations)
+from . import brute  # noqa: F401,E402

@@ -1,4 +1,4 @@
-"""Frontier sets in closed form -- test infrastructure only.
+"""Frontier sets and hop-indexed relaxations -- test infrastructure only.
 
 Forward (Algorithm 1, Lemma 1 and its proof, Section 4.1.3).  Let l_j(v) be
 the least weight of a walk from s to v with exactly j arcs (l_0(s) = 0, all
@@ -11,12 +11,22 @@ a least-weight j-arc walk reaching v no heavier than anything found with
 fewer arcs; its prefix is again such a walk, so it is produced from F_{j-1}.
 Once some F_j is empty, every later one is too, so the number of products
 MFBF performs is the first j with F_j empty.  For unweighted graphs F_j is
-the j-th level of a breadth-first search.
+the j-th level of a breadth-first search.  The relaxations of product j
+(Section 5's flops of a product) are the arcs leaving the entries of
+F_{j-1}: sum over v in F_{j-1} of the out-degree of v.
+
+l_j follows from l_{j-1} by one step of the definition, l_j(v) = min over
+arcs u -> v of l_{j-1}(u) + w(u, v), evaluated here over the arcs grouped by
+their head (numpy's minimum.reduceat over each head's in-arcs).
 
 Backward (Algorithm 2, Lemma 2, Section 4.2.3).  A reachable vertex enters
 backward frontier B_k, k = 0, 1, ..., when k is its height in the
 shortest-path DAG of s (0 for a vertex with no successor, else 1 + the
 greatest height of its successors); heights come from the Brandes oracle.
+The source has no predecessor, so its own entry feeds no product; the
+backward loop over a batch therefore ends with the product that reads the
+greatest height of a non-source vertex: 1 (counting product) + that height
++ 1 products, or 1 if no non-source vertex is reachable (backward_products).
 """
 from __future__ import annotations
 
@@ -25,20 +35,44 @@ import numpy as np
 INF = np.int64(1) << 60
 
 
-def forward_frontiers(g, s: int, max_products: int = 1 << 20):
+class InArcs:
+    """Arcs of g grouped by head: tail[], weight[] in head order, and the
+    first arc of every head that has one (for reduceat)."""
+
+    def __init__(self, g, unit_weights: bool = False):
+        n = g.n
+        u = np.repeat(np.arange(n, dtype=np.int64), np.diff(np.asarray(g.row_ptr, np.int64)))
+        v = np.asarray(g.col, np.int64)
+        w = (np.ones(u.size, np.int64) if (g.w is None or unit_weights)
+             else np.asarray(g.w, np.int64))
+        order = np.argsort(v, kind="stable")
+        self.n = n
+        self.tail = u[order]
+        self.weight = w[order]
+        counts = np.bincount(v, minlength=n)
+        starts = np.concatenate([[0], np.cumsum(counts)[:-1]])
+        self.has = counts > 0
+        self.starts = starts[self.has]
+        self.outdeg = np.diff(np.asarray(g.row_ptr, np.int64))
+
+    def step(self, ell: np.ndarray) -> np.ndarray:
+        """l_next(v) = min over arcs u -> v of ell(u) + w(u, v) (INF if none)."""
+        nxt = np.full(self.n, INF, dtype=np.int64)
+        if self.tail.size:
+            cand = ell[self.tail] + self.weight
+            nxt[self.has] = np.minimum.reduceat(cand, self.starts)
+        return np.minimum(nxt, INF)
+
+
+def forward_frontiers(g, s: int, max_products: int = 1 << 20, arcs: InArcs = None):
     """F_1, F_2, ... (bool[n] each, the last one empty) for source ``s``."""
-    n = g.n
-    u = np.repeat(np.arange(n, dtype=np.int64), np.diff(g.row_ptr))
-    v = g.col.astype(np.int64)
-    w = np.ones(u.size, np.int64) if g.w is None else g.w.astype(np.int64)
-    ell = np.full(n, INF, dtype=np.int64)
+    arcs = arcs or InArcs(g)
+    ell = np.full(g.n, INF, dtype=np.int64)
     ell[s] = 0
     L = ell.copy()
     out = []
     for _ in range(max_products):
-        cand = np.where(ell[u] < INF, ell[u] + w, INF)
-        nxt = np.full(n, INF, dtype=np.int64)
-        np.minimum.at(nxt, v, cand)
+        nxt = arcs.step(ell)
         F = (nxt < INF) & (nxt <= L)
         out.append(F)
         L = np.minimum(L, nxt)
@@ -48,11 +82,28 @@ def forward_frontiers(g, s: int, max_products: int = 1 << 20):
     raise RuntimeError("frontier did not empty")
 
 
+def forward_relaxations(g, s: int, frontiers, arcs: InArcs = None) -> list:
+    """Relaxations of products 1, 2, ...: out-degree sums over F_0 = {s}, F_1, ..."""
+    outdeg = (arcs.outdeg if arcs is not None
+              else np.diff(np.asarray(g.row_ptr, np.int64)))
+    prev = [np.asarray([s])] + [np.flatnonzero(F) for F in frontiers[:-1]]
+    return [int(outdeg[p].sum()) for p in prev]
+
+
 def backward_heights(height_row: np.ndarray) -> list:
     """B_0, B_1, ... (bool[n] each) from one source's DAG heights (-1 = unreachable)."""
     h = np.asarray(height_row)
     top = int(h.max()) if h.size else -1
     return [h == k for k in range(top + 1)]
+
+
+def backward_products(heights: np.ndarray, sources) -> int:
+    """Backward products of a batch (counting product included) from its DAG heights."""
+    h = np.array(heights, dtype=np.int64, copy=True)
+    src = np.asarray(sources, dtype=np.int64)
+    h[np.arange(src.size), src] = -1          # the source's own entry feeds no product
+    top = int(h.max()) if h.size else -1
+    return 1 if top < 0 else top + 2
 
 
 def fixpoint(g, s: int, op: str = "sssp", max_products: int = 1 << 20):
@@ -67,22 +118,14 @@ def fixpoint(g, s: int, op: str = "sssp", max_products: int = 1 << 20):
     whose frontier is empty.  After an empty F_j every later one is empty
     too (l_{j+1}(v) >= min_u L_{j-1}(u) + w(u, v) >= L_j(v)).
     """
-    n = g.n
-    u = np.repeat(np.arange(n, dtype=np.int64), np.diff(g.row_ptr))
-    v = g.col.astype(np.int64)
-    if op == "bfs" or g.w is None:
-        w = np.ones(u.size, np.int64)
-    elif op == "sssp":
-        w = g.w.astype(np.int64)
-    else:
+    if op not in ("sssp", "bfs"):
         raise ValueError(op)
-    ell = np.full(n, INF, dtype=np.int64)
+    arcs = InArcs(g, unit_weights=(op == "bfs"))
+    ell = np.full(g.n, INF, dtype=np.int64)
     ell[s] = 0
     L = ell.copy()
     for j in range(1, max_products + 1):
-        cand = np.where(ell[u] < INF, ell[u] + w, INF)
-        nxt = np.full(n, INF, dtype=np.int64)
-        np.minimum.at(nxt, v, cand)
+        nxt = arcs.step(ell)
         F = nxt < L
         L = np.minimum(L, nxt)
         ell = nxt

@@ -53,20 +53,18 @@ __global__ void k_set_sources(int32_t *src, int total, int nb, const int32_t *in
 
 // T = (INF, 0) everywhere, both frontier bitmaps cleared, counters zeroed.
 __global__ void k_fwd_fill(int32_t *tdist, double *tsig, size_t total, uint32_t *ab0, uint32_t *ab1,
-                           size_t nab, unsigned long long *ctr, int nctr, int32_t *flags,
-                           uint64_t *fmask) {
+                           size_t nab, unsigned long long *ctr, int nctr, int32_t *flags) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (size_t i = t0; i < total; i += stride) {
         tdist[i] = kInf;
         tsig[i] = 0.0;
-        if (fmask) fmask[i] = 0ull;
     }
     for (size_t i = t0; i < nab; i += stride) {
         ab0[i] = 0u;
         ab1[i] = 0u;
     }
-    if (t0 < (size_t)nctr) ctr[t0] = 0ull;
+    for (size_t i = t0; i < (size_t)nctr; i += stride) ctr[i] = 0ull;
     if (t0 == 0) flags[0] = 0;
 }
 
@@ -196,6 +194,55 @@ __global__ __launch_bounds__(kBlock) void k_delta_rows(const double *zeta, const
     }
 }
 
+// The counting product of a batch of two or more groups reads tau of each
+// pair of groups interleaved per lane: tau2[q][v][lane] = (tau of group 2q,
+// tau of group 2q+1) at (v, lane); a padding group reads as unreachable.
+__global__ void k_pair_tau(const int32_t *tdist, int2 *tau2, size_t plane, int ncg, int npairs) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const size_t total = (size_t)npairs * plane;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        const size_t q = i / plane, r = i - q * plane;
+        const int x = tdist[2 * q * plane + r];
+        const int y = (int)(2 * q + 1) < ncg ? tdist[(2 * q + 1) * plane + r] : kInf;
+        tau2[i] = make_int2(x, y);
+    }
+}
+
+// Trace of forward frontier F_j: one wave per (source column c, 64 caller
+// vertices); lane v tests the vertex's activity bit and its tuple in the
+// frontier buffers, the wave's ballot is the bitmap word.  The out-degrees
+// of the members are summed into *relax (the relaxations of the next
+// product: each frontier entry is combined once along each of its arcs).
+__global__ __launch_bounds__(kBlock) void k_trace_fwd(const uint32_t *abits, const uint32_t *ftup,
+                                                      int n, int nwords, int nb, int wide,
+                                                      const int32_t *perm, const int64_t *rp_out,
+                                                      uint64_t *rows, int words64,
+                                                      unsigned long long *relax) {
+    const size_t wave = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & (kWave - 1);
+    const size_t c = wave / (size_t)words64;
+    const int wv = (int)(wave - c * (size_t)words64);
+    bool member = false;
+    unsigned long long r = 0;
+    const int v = wv * kWave + lane;
+    if (c < (size_t)nb && v < n) {
+        const int d = dev_id(perm, v);
+        const int cg = (int)(c / kWave), l = (int)(c % kWave);
+        const int plane = wide ? cg >> 1 : cg;
+        if ((abits[(size_t)plane * nwords + (d >> 5)] >> (d & 31)) & 1u) {
+            const size_t idx = wide ? ((((size_t)plane * n + d) * kWave + l) * 2 + (cg & 1))
+                                    : (((size_t)cg * n + d) * kWave + l);
+            member = ftup[idx] != kSent;
+            if (member) r = (unsigned long long)(rp_out[d + 1] - rp_out[d]);
+        }
+    }
+    const uint64_t word = ballot(member);
+    if (c < (size_t)nb && lane == 0 && rows) rows[c * (size_t)words64 + wv] = word;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) r += __shfl_xor(r, off, kWave);
+    if (lane == 0 && r) atomicAdd(relax, r);
+}
+
 inline int blocks_for(size_t work, int per_block, int cap = 1 << 20) {
     size_t b = (work + per_block - 1) / per_block;
     if (b < 1) b = 1;
@@ -223,7 +270,7 @@ static int arc_mode(const Csr &c) { return c.w == nullptr ? 0 : (c.pk ? 1 : 2); 
 // alone.
 static int fwd_wide_groups(int ncg) { return ncg >= 2 ? (ncg + kWide - 1) / kWide : 0; }
 
-static FwdArgs fwd_args(mfbc_graph *g, int ncg, int j, bool trace) {
+static FwdArgs fwd_args(mfbc_graph *g, int ncg, int j) {
     Workspace &ws = g->ws;
     const int b = (j - 1) & 1;  // buffer holding F_{j-1}
     FwdArgs a{};
@@ -251,8 +298,8 @@ static FwdArgs fwd_args(mfbc_graph *g, int ncg, int j, bool trace) {
     a.pd = ws.pd;
     a.pm = ws.pm;
     a.ctr = ws.counters + (size_t)(j % kCounterRing) * 4 * kCounterSlots;
+    a.prev_ctr = j > 1 ? ws.counters + (size_t)((j - 1) % kCounterRing) * 4 * kCounterSlots : nullptr;
     a.flags = ws.flags;
-    a.fmask = trace ? ws.fmask : nullptr;
     a.clear_bits = ws.abits[b];
     a.clear_ctr = ws.counters + (size_t)((j + 1) % kCounterRing) * 4 * kCounterSlots;
     a.nwide = fwd_wide_groups(ncg);
@@ -272,8 +319,7 @@ void launch_fwd_init(mfbc_graph *g, int ncg, int nb, hipStream_t s) {
     const int nwords = (g->n + 31) / 32;
     hipLaunchKernelGGL(k_fwd_fill, dim3(blocks_for(total, 256, 65536)), dim3(256), 0, s, ws.tdist,
                        ws.tsig, total, ws.abits[0], ws.abits[1], (size_t)ncg * nwords,
-                       ws.counters, kCounterRing * 4 * kCounterSlots, ws.flags,
-                       ws.fmask && ws.fmask_ncg >= ncg ? ws.fmask : nullptr);
+                       ws.counters, kCounterRing * 4 * kCounterSlots, ws.flags);
     if (fwd_wide_groups(ncg)) {
         uint32_t *ft = (uint32_t *)ws.fdist[0];
         hipLaunchKernelGGL(k_fwd_seed_rows_w<kWide>, dim3(blocks_for(nb, 256)), dim3(256), 0, s, ws.src,
@@ -288,9 +334,8 @@ void launch_fwd_init(mfbc_graph *g, int ncg, int nb, hipStream_t s) {
                        nwords, ws.tdist, ws.tsig, (uint32_t *)ws.fdist[0], ws.abits[0]);
 }
 
-void launch_fwd_product(mfbc_graph *g, int ncg, int j, bool trace, hipStream_t s,
-                        hipEvent_t *ev) {
-    FwdArgs a = fwd_args(g, ncg, j, trace);
+void launch_fwd_product(mfbc_graph *g, int ncg, int j, hipStream_t s, hipEvent_t *ev) {
+    FwdArgs a = fwd_args(g, ncg, j);
     if (a.nwide) {
         if (ev) (void)hipEventRecord(ev[0], s);
         const int grid = blocks_for((size_t)a.ntasks * a.nwide, kWavesPerBlock, 0x7fffffff);
@@ -358,6 +403,8 @@ static BwdArgs bwd_args(mfbc_graph *g, int ncg, int k) {
     a.pd = ws.pd;
     a.pm = ws.pm;
     a.ctr = ws.counters + (size_t)(k % kCounterRing) * 4 * kCounterSlots;
+    a.prev_ctr = k > 0 ? ws.counters + (size_t)((k - 1) % kCounterRing) * 4 * kCounterSlots : nullptr;
+    a.tau2 = ws.tau2;
     a.nwords = (g->n + 31) / 32;
     a.clear_bits = ws.abits[b];
     a.clear_ctr = ws.counters + (size_t)((k + 1) % kCounterRing) * 4 * kCounterSlots;
@@ -372,31 +419,48 @@ static BwdArgs bwd_args(mfbc_graph *g, int ncg, int k) {
     return a;
 }
 
-void launch_bwd_count(mfbc_graph *g, int ncg, hipStream_t s, hipEvent_t *ev) {
+hipError_t launch_bwd_count(mfbc_graph *g, int ncg, hipStream_t s, hipEvent_t *ev) {
     Workspace &ws = g->ws;
     // the counting product writes B_0 into buffer 0: clear its bitmap and
     // this product's counters first
     const int nwords = (g->n + 31) / 32;
-    (void)hipMemsetAsync(ws.abits[0], 0, (size_t)nwords * ncg * 4, s);
-    (void)hipMemsetAsync(ws.abits[1], 0, (size_t)nwords * ncg * 4, s);
-    (void)hipMemsetAsync(ws.counters, 0, sizeof(unsigned long long) * kCounterRing * 4 * kCounterSlots, s);
+    hipError_t e;
+    if ((e = hipMemsetAsync(ws.abits[0], 0, (size_t)nwords * ncg * 4, s)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(ws.abits[1], 0, (size_t)nwords * ncg * 4, s)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(ws.counters, 0,
+                            sizeof(unsigned long long) * kCounterRing * 4 * kCounterSlots, s)) !=
+        hipSuccess)
+        return e;
     BwdArgs a = bwd_args(g, ncg, 0);
     if (ev) (void)hipEventRecord(ev[0], s);
-    const size_t waves = (size_t)a.ntasks * ncg;
-    const int grid = blocks_for(waves, kWavesPerBlock, 0x7fffffff);
-    switch (arc_mode(g->out)) {
-        case 0: hipLaunchKernelGGL((k_bwd_count<0, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
-        case 1: hipLaunchKernelGGL((k_bwd_count<1, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
-        default: hipLaunchKernelGGL((k_bwd_count<2, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    if (ncg >= 2) {
+        // pairs of groups: tau interleaved per pair, then one wave per (pair, task)
+        const int npairs = (ncg + 1) / 2;
+        const size_t plane = (size_t)g->n * kWave;
+        hipLaunchKernelGGL(k_pair_tau, dim3(blocks_for((size_t)npairs * plane, 256, 65536)), dim3(256),
+                           0, s, (const int32_t *)ws.tdist, (int2 *)ws.tau2, plane, ncg, npairs);
+        const int grid = blocks_for((size_t)a.ntasks * npairs, kWavesPerBlock, 0x7fffffff);
+        switch (arc_mode(g->out)) {
+            case 0: hipLaunchKernelGGL(k_bwd_count_w<0>, dim3(grid), dim3(kBlock), 0, s, a); break;
+            case 1: hipLaunchKernelGGL(k_bwd_count_w<1>, dim3(grid), dim3(kBlock), 0, s, a); break;
+            default: hipLaunchKernelGGL(k_bwd_count_w<2>, dim3(grid), dim3(kBlock), 0, s, a); break;
+        }
+    } else {
+        const size_t waves = (size_t)a.ntasks * ncg;
+        const int grid = blocks_for(waves, kWavesPerBlock, 0x7fffffff);
+        switch (arc_mode(g->out)) {
+            case 0: hipLaunchKernelGGL((k_bwd_count<0, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
+            case 1: hipLaunchKernelGGL((k_bwd_count<1, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
+            default: hipLaunchKernelGGL((k_bwd_count<2, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
+        }
     }
+    if (ev) (void)hipEventRecord(ev[1], s);
     int mgrid = blocks_for((size_t)a.nhubs * ncg, kWavesPerBlock, 0x7fffffff);
     const int cgrid = blocks_for((size_t)a.nwords, kBlock, 1024);
     if (cgrid > mgrid) mgrid = cgrid;
     hipLaunchKernelGGL(k_bwd_count_merge<false>, dim3(mgrid), dim3(kBlock), 0, s, a);
-    if (ev) {
-        (void)hipEventRecord(ev[1], s);
-        (void)hipEventRecord(ev[2], s);
-    }
+    if (ev) (void)hipEventRecord(ev[2], s);
+    return hipGetLastError();
 }
 
 void launch_bwd_product(mfbc_graph *g, int ncg, int k, hipStream_t s, hipEvent_t *ev) {
@@ -445,16 +509,24 @@ void launch_lambda_reduce(mfbc_graph *g, int ncg, double *d_bc, hipStream_t s) {
 }
 
 void launch_export_forward(mfbc_graph *g, int ncg, int nb, int32_t *d_dist, double *d_sigma,
-                           uint64_t *d_fmask, hipStream_t s) {
+                           hipStream_t s) {
     dim3 grid((g->n + 63) / 64, ncg);
     const int32_t *perm = g->perm;
     hipLaunchKernelGGL(k_tiles_to_rows<int32_t>, grid, dim3(kBlock), 0, s, g->ws.tdist, d_dist,
                        g->n, nb, perm);
     hipLaunchKernelGGL(k_tiles_to_rows<double>, grid, dim3(kBlock), 0, s, g->ws.tsig, d_sigma,
                        g->n, nb, perm);
-    if (d_fmask)
-        hipLaunchKernelGGL(k_tiles_to_rows<uint64_t>, grid, dim3(kBlock), 0, s,
-                           (const uint64_t *)g->ws.fmask, d_fmask, g->n, nb, perm);
+}
+
+void launch_trace_fwd(mfbc_graph *g, int ncg, int nb, int j, uint64_t *d_rows, hipStream_t s) {
+    Workspace &ws = g->ws;
+    const int b = j & 1;      // F_j sits in the buffers product j wrote (F_0: buffer 0)
+    const int words64 = (g->n + 63) / 64;
+    const size_t waves = (size_t)nb * words64;
+    hipLaunchKernelGGL(k_trace_fwd, dim3(blocks_for(waves, kWavesPerBlock, 0x7fffffff)), dim3(kBlock),
+                       0, s, (const uint32_t *)ws.abits[b], (const uint32_t *)ws.fdist[b], g->n,
+                       (g->n + 31) / 32, nb, fwd_wide_groups(ncg) ? 1 : 0, (const int32_t *)g->perm,
+                       (const int64_t *)g->out.rp, d_rows, words64, ws.trace_relax + j);
 }
 
 void launch_export_tiles_i32(mfbc_graph *g, int ncg, int nb, const int32_t *tiles, int32_t *d_rows,

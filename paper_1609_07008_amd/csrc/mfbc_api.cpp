@@ -73,27 +73,57 @@ void dfree(T *&p) {
     p = nullptr;
 }
 
-void free_workspace(Workspace &ws) {
-    dfree(ws.tdist);
-    dfree(ws.tsig);
-    for (int i = 0; i < 2; i++) {
-        dfree(ws.fdist[i]);
-        dfree(ws.fsig[i]);
-        dfree(ws.fbits[i]);
-        dfree(ws.abits[i]);
+// Every array of the per-batch workspace for `ncg` column groups, in a fixed
+// order: f(pointer, element count).  Used both to allocate the arrays and to
+// carve them out of one block of memory.
+// (g == nullptr: every count is 0, for walks that need only the pointers.)
+template <typename F>
+void ws_arrays(const mfbc_graph *g, Workspace &ws, int ncg, F &&f) {
+    const size_t n = g ? (size_t)g->n : 0;
+    const size_t tile = n * kWave * (size_t)ncg;
+    const size_t nwords = (n + 31) / 32;
+    const size_t slots =
+        g ? (size_t)std::max(g->plan_in.nslots, g->plan_out.nslots) * kWave * (size_t)ncg : 0;
+    f(ws.tdist, tile);
+    f(ws.tsig, tile);
+    for (int b = 0; b < 2; b++) {
+        f(ws.fdist[b], tile);
+        f(ws.fsig[b], tile);
+        f(ws.fbits[b], n * ncg);
+        f(ws.abits[b], nwords * ncg);
     }
-    dfree(ws.pd);
-    dfree(ws.pm);
-    dfree(ws.counters);
-    dfree(ws.flags);
-    dfree(ws.lam);
-    dfree(ws.src);
-    dfree(ws.dag);
-    dfree(ws.fmask);
-    if (ws.h_counters) (void)hipHostFree(ws.h_counters);
-    ws.h_counters = nullptr;
-    ws.ncg = 0;
-    ws.fmask_ncg = 0;
+    f(ws.pd, slots);
+    f(ws.pm, slots);
+    f(ws.counters, (size_t)kCounterRing * 4 * kCounterSlots);
+    f(ws.flags, (size_t)4);
+    f(ws.lam, n * ncg);
+    f(ws.dag, (size_t)std::max<int64_t>(g ? g->arcs : 0, 1) * ncg);
+    f(ws.src, (size_t)ncg * kWave);
+    f(ws.tau2, ncg >= 2 ? tile : (size_t)1);   // the paired counting product's copy of tau
+}
+
+// Column groups the workspace holds for a batch of `ncg` groups: batches of
+// two or more run the forward product on pairs, so their count is rounded up
+// to whole pairs; a single group runs alone.
+int ws_groups(int ncg) { return ncg <= 1 ? 1 : (ncg + 1) & ~1; }
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Bytes of the workspace of `ncg` groups when carved from one block.
+size_t ws_bytes(const mfbc_graph *g, int ncg) {
+    Workspace tmp;
+    size_t off = 0;
+    ws_arrays(g, tmp, ws_groups(ncg), [&](auto *&p, size_t count) {
+        (void)p;
+        off = align256(off + std::max<size_t>(count, 1) * sizeof(*p));
+    });
+    return off;
+}
+
+void free_workspace(Workspace &ws) {
+    if (!ws.external) ws_arrays(nullptr, ws, 0, [](auto *&p, size_t) { dfree(p); });
+    dfree(ws.trace_relax);
+    ws = Workspace{};
 }
 
 void free_plan(Plan &p) {
@@ -121,45 +151,21 @@ int upload_plan(int32_t n, const int64_t *h_rp, const TaskParams &prm, Plan &pla
     return MFBC_OK;
 }
 
-// Grow the workspace to `ncg` column groups (and the trace mask if asked).
-int ensure_workspace(mfbc_graph *g, int ncg, bool trace) {
+// Grow the workspace to hold a batch of `ncg` column groups.
+int ensure_workspace(mfbc_graph *g, int ncg) {
     Workspace &ws = g->ws;
-    ncg = (ncg + 1) & ~1;   // the forward product's paired layout needs whole pairs
-    if (ws.ncg < ncg) {
+    ncg = ws_groups(ncg);
+    if (ws.ncg >= ncg && !ws.external) return MFBC_OK;
+    free_workspace(ws);
+    int rc = MFBC_OK;
+    ws_arrays(g, ws, ncg, [&](auto *&p, size_t count) {
+        if (!rc) rc = dalloc(&p, count);
+    });
+    if (rc) {
         free_workspace(ws);
-        const size_t n = (size_t)g->n;
-        const size_t tile = n * kWave * (size_t)ncg;
-        const size_t nwords = (n + 31) / 32;
-        const size_t slots =
-            (size_t)std::max(g->plan_in.nslots, g->plan_out.nslots) * kWave * (size_t)ncg;
-        int rc = MFBC_OK;
-        if ((rc = dalloc(&ws.tdist, tile)) || (rc = dalloc(&ws.tsig, tile)) ||
-            (rc = dalloc(&ws.fdist[0], tile)) || (rc = dalloc(&ws.fdist[1], tile)) ||
-            (rc = dalloc(&ws.fsig[0], tile)) || (rc = dalloc(&ws.fsig[1], tile)) ||
-            (rc = dalloc(&ws.fbits[0], n * ncg)) || (rc = dalloc(&ws.fbits[1], n * ncg)) ||
-            (rc = dalloc(&ws.abits[0], nwords * ncg)) || (rc = dalloc(&ws.abits[1], nwords * ncg)) ||
-            (rc = dalloc(&ws.pd, slots)) || (rc = dalloc(&ws.pm, slots)) ||
-            (rc = dalloc(&ws.counters, (size_t)kCounterRing * 4 * kCounterSlots)) ||
-            (rc = dalloc(&ws.flags, 4)) || (rc = dalloc(&ws.lam, n * ncg)) ||
-            (rc = dalloc(&ws.dag, (size_t)std::max<int64_t>(g->arcs, 1) * ncg)) ||
-            (rc = dalloc(&ws.src, (size_t)ncg * kWave))) {
-            free_workspace(ws);
-            return rc;
-        }
-        if (hipHostMalloc((void **)&ws.h_counters,
-                          sizeof(unsigned long long) * kCounterRing * 4 * kCounterSlots) != hipSuccess) {
-            ws.h_counters = nullptr;
-            free_workspace(ws);
-            return fail(MFBC_ENOMEM, "pinned host allocation failed");
-        }
-        ws.ncg = ncg;
+        return rc;
     }
-    if (trace && ws.fmask_ncg < ncg) {
-        dfree(ws.fmask);
-        int rc = dalloc(&ws.fmask, (size_t)g->n * kWave * (size_t)ncg);
-        if (rc) return rc;
-        ws.fmask_ncg = ncg;
-    }
+    ws.ncg = ncg;
     return MFBC_OK;
 }
 
@@ -167,31 +173,41 @@ struct Counts {
     int64_t produced = 0, outputs = 0, active_vertices = 0, active_arcs = 0;
 };
 
-// Wait for product `idx` and read its counters (see flush_counts).
-int read_counts(mfbc_graph *g, int idx, hipStream_t s, Counts *out) {
-    Workspace &ws = g->ws;
-    const size_t off = (size_t)(idx % kCounterRing) * 4 * kCounterSlots;
+// Wait for the stream and copy the whole counter ring to the host.
+int read_ring(mfbc_graph *g, hipStream_t s) {
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(ws.h_counters + off, ws.counters + off,
-                           sizeof(unsigned long long) * 4 * kCounterSlots, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(g->h_ctr, g->ws.counters,
+                           sizeof(unsigned long long) * kCounterRing * 4 * kCounterSlots,
+                           hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    int64_t t[4] = {0, 0, 0, 0};
-    for (int k = 0; k < 4; k++)
-        for (int i = 0; i < kCounterSlots; i++) t[k] += (int64_t)ws.h_counters[off + k * kCounterSlots + i];
-    out->produced = t[0];
-    out->outputs = t[1];
-    out->active_vertices = t[2];
-    out->active_arcs = t[3];
     return MFBC_OK;
 }
 
-// Kernel times of the last product (events recorded by the launchers).
-void add_times(mfbc_graph *g, double *a, double *b) {
-    if (!g->timing) return;
-    float t0 = 0.f, t1 = 0.f;
-    if (hipEventElapsedTime(&t0, g->ev[0], g->ev[1]) == hipSuccess) *a += t0;
-    if (hipEventElapsedTime(&t1, g->ev[1], g->ev[2]) == hipSuccess) *b += t1;
+// Counters of product `idx` from the host copy of the ring (see flush_counts).
+Counts ring_counts(const mfbc_graph *g, int idx) {
+    const size_t off = (size_t)(idx % kCounterRing) * 4 * kCounterSlots;
+    int64_t t[4] = {0, 0, 0, 0};
+    for (int k = 0; k < 4; k++)
+        for (int i = 0; i < kCounterSlots; i++) t[k] += (int64_t)g->h_ctr[off + k * kCounterSlots + i];
+    Counts c;
+    c.produced = t[0];
+    c.outputs = t[1];
+    c.active_vertices = t[2];
+    c.active_arcs = t[3];
+    return c;
 }
+
+// Kernel times of the product launched in window position `i` (events
+// recorded by the launchers).
+void add_times(mfbc_graph *g, int i, double *a, double *b) {
+    if (!g->timing) return;
+    hipEvent_t *e = g->ev + 3 * i;
+    float t0 = 0.f, t1 = 0.f;
+    if (hipEventElapsedTime(&t0, e[0], e[1]) == hipSuccess) *a += t0;
+    if (hipEventElapsedTime(&t1, e[1], e[2]) == hipSuccess) *b += t1;
+}
+
+hipEvent_t *window_events(mfbc_graph *g, int i) { return g->timing ? g->ev + 3 * i : nullptr; }
 
 int check_sources(mfbc_graph *g, const int32_t *d_sources, int64_t count, hipStream_t s) {
     if (count == 0) return MFBC_OK;
@@ -208,102 +224,168 @@ int check_sources(mfbc_graph *g, const int32_t *d_sources, int64_t count, hipStr
 }
 
 // Algorithm 1 on the batch whose sources are already in ws.src.
-int run_forward(mfbc_graph *g, int ncg, int nb, bool trace, int64_t *h_nnz, int max_products,
-                int32_t *products, hipStream_t s) {
+//
+// Products are enqueued kWindow at a time and their counters read back
+// once per window: a product whose predecessor produced nothing skips
+// itself on the device, so the products past the end of the loop in the
+// last window cost a launch each and change nothing.  The loop ends at the
+// first product that produced no frontier entry (Algorithm 1's condition
+// over every column of the batch).
+// Trace (d_rows non-null or h_relax non-null): frontier membership of F_j
+// after every product j <= max_products, as vertex bitmaps per column
+// (d_rows + (j-1) * nb * words), and the relaxations of every product.
+int run_forward(mfbc_graph *g, int ncg, int nb, bool trace, uint64_t *d_rows, int64_t *h_nnz,
+                int64_t *h_relax, int max_products, int32_t *products, hipStream_t s) {
     launch_fwd_init(g, ncg, nb, s);
-    hipEvent_t *ev = g->timing ? g->ev : nullptr;
+    if (trace) launch_trace_fwd(g, ncg, nb, 0, nullptr, s);
     const double arc_bytes = g->weighted ? 8.0 : 4.0;
+    const size_t words = ((size_t)g->n + 63) / 64;
+    mfbc_stats &st = g->stats;
     int64_t prev = nb;           // the first frontier: one entry per source column
-    Counts c;
-    int j = 0;
-    do {
-        j++;
+    int j = 0, last = 0;
+    while (!last) {
         if (j > g->n + 1) return fail(MFBC_EDEVICE, "forward products did not converge");
-        launch_fwd_product(g, ncg, j, trace, s, ev);
-        int rc = read_counts(g, j, s, &c);
+        for (int i = 0; i < kWindow; i++) {
+            const int jj = j + 1 + i;
+            launch_fwd_product(g, ncg, jj, s, window_events(g, i));
+            if (trace)
+                launch_trace_fwd(g, ncg, nb, jj,
+                                 d_rows && jj <= max_products ? d_rows + (size_t)(jj - 1) * nb * words
+                                                              : nullptr,
+                                 s);
+        }
+        int rc = read_ring(g, s);
         if (rc) return rc;
-        if (h_nnz && j <= max_products) h_nnz[j - 1] = c.produced;
-        mfbc_stats &st = g->stats;
-        st.fwd_entries += c.produced;
-        st.fwd_outputs += c.outputs;
-        st.fwd_active_vertices += c.active_vertices;
-        st.fwd_active_arcs += c.active_arcs;
-        st.fwd_pull_launches++;
-        st.fwd_alg_bytes += 8.0 * c.active_vertices + arc_bytes * c.active_arcs +
-                            12.0 * (double)(prev + c.outputs + c.produced);
-        add_times(g, &st.fwd_pull_ms, &st.fwd_merge_ms);
-        prev = c.produced;
-    } while (c.produced > 0);
-    g->stats.fwd_products += j;
-    if (products) *products = j;
+        for (int i = 0; i < kWindow; i++) {
+            const int jj = j + 1 + i;
+            st.fwd_pull_launches++;
+            add_times(g, i, &st.fwd_pull_ms, &st.fwd_merge_ms);
+            if (last) continue;          // skipped on the device
+            const Counts c = ring_counts(g, jj);
+            if (h_nnz && jj <= max_products) h_nnz[jj - 1] = c.produced;
+            st.fwd_entries += c.produced;
+            st.fwd_outputs += c.outputs;
+            st.fwd_active_vertices += c.active_vertices;
+            st.fwd_active_arcs += c.active_arcs;
+            st.fwd_alg_bytes += 8.0 * c.active_vertices + arc_bytes * c.active_arcs +
+                                12.0 * (double)(prev + c.outputs + c.produced);
+            prev = c.produced;
+            if (c.produced == 0) last = jj;
+        }
+        j += kWindow;
+    }
+    g->stats.fwd_products += last;
+    if (products) *products = last;
     int32_t flag = 0;
     HIP_TRY(hipMemcpyAsync(&flag, g->ws.flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (trace && h_relax) {
+        const int k = std::min(last, max_products);
+        std::vector<unsigned long long> r((size_t)k + 1, 0ull);
+        HIP_TRY(hipMemcpyAsync(r.data(), g->ws.trace_relax, sizeof(unsigned long long) * ((size_t)k + 1),
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (int i = 0; i < k; i++) h_relax[i] = (int64_t)r[(size_t)i];
+    }
     HIP_TRY(hipStreamSynchronize(s));
     if (flag) return fail(MFBC_EOVERFLOW, "a shortest-path count overflowed binary64");
     return MFBC_OK;
 }
 
-// Algorithm 2 on the batch whose T is in the workspace.
+// Algorithm 2 on the batch whose T is in the workspace: the counting
+// product (window position 0 of the first window), then backward products
+// in windows as in run_forward, until one produces no frontier entry.
 int run_backward(mfbc_graph *g, int ncg, int nb, int32_t *products, hipStream_t s) {
-    hipEvent_t *ev = g->timing ? g->ev : nullptr;
     const double arc_bytes = g->weighted ? 8.0 : 4.0;
     mfbc_stats &st = g->stats;
-    launch_bwd_count(g, ncg, s, ev);
-    Counts c;
-    int rc = read_counts(g, 0, s, &c);
-    if (rc) return rc;
-    st.bwd_entries += c.produced;
-    st.count_launches++;
-    // adjacency, tau of every (column, vertex) read once, and the stored DAG
-    // (one 8-byte lane mask per arc and column group) written
-    st.count_alg_bytes += arc_bytes * (double)g->arcs + 8.0 * g->n + 8.0 * (double)g->n * nb +
-                          8.0 * (double)g->arcs * ncg;
-    if (g->timing) {
-        float t = 0.f;
-        if (hipEventElapsedTime(&t, g->ev[0], g->ev[2]) == hipSuccess) st.count_ms += t;
-    }
-    int64_t prev = c.produced;
-    int k = 0;
-    while (c.produced > 0) {
-        k++;
+    int64_t prev = 0;
+    int k = 0, last = -1;
+    while (last < 0) {
         if (k > g->n + 1) return fail(MFBC_EDEVICE, "backward products did not converge");
-        launch_bwd_product(g, ncg, k, s, ev);
-        if ((rc = read_counts(g, k, s, &c))) return rc;
-        st.bwd_entries += c.produced;
-        st.bwd_outputs += c.outputs;
-        st.bwd_active_vertices += c.active_vertices;
-        st.bwd_active_arcs += c.active_arcs;
-        st.bwd_pull_launches++;
-        // + the DAG lane mask of every arc with an active head (8 B)
-        st.bwd_alg_bytes += 8.0 * c.active_vertices + (arc_bytes + 8.0) * c.active_arcs +
-                            12.0 * (double)prev + 24.0 * (double)c.outputs;
-        add_times(g, &st.bwd_pull_ms, &st.bwd_merge_ms);
-        prev = c.produced;
+        for (int i = 0; i < kWindow; i++) {
+            const int kk = k + i;
+            if (kk == 0) {
+                const hipError_t e = launch_bwd_count(g, ncg, s, window_events(g, i));
+                if (e != hipSuccess)
+                    return fail(MFBC_EDEVICE, std::string("counting product: ") + hipGetErrorString(e));
+            } else {
+                launch_bwd_product(g, ncg, kk, s, window_events(g, i));
+            }
+        }
+        int rc = read_ring(g, s);
+        if (rc) return rc;
+        for (int i = 0; i < kWindow; i++) {
+            const int kk = k + i;
+            if (kk == 0) {
+                const Counts c = ring_counts(g, 0);
+                st.bwd_entries += c.produced;
+                st.count_launches++;
+                // adjacency, tau of every (column, vertex) read once, and the
+                // stored DAG (one 8-byte lane mask per arc and column group) written
+                st.count_alg_bytes += arc_bytes * (double)g->arcs + 8.0 * g->n +
+                                      8.0 * (double)g->n * nb + 8.0 * (double)g->arcs * ncg;
+                if (g->timing) {
+                    float t = 0.f;
+                    if (hipEventElapsedTime(&t, g->ev[0], g->ev[2]) == hipSuccess) st.count_ms += t;
+                }
+                prev = c.produced;
+                if (c.produced == 0) last = 0;
+                continue;
+            }
+            st.bwd_pull_launches++;
+            add_times(g, i, &st.bwd_pull_ms, &st.bwd_merge_ms);
+            if (last >= 0) continue;      // skipped on the device
+            const Counts c = ring_counts(g, kk);
+            st.bwd_entries += c.produced;
+            st.bwd_outputs += c.outputs;
+            st.bwd_active_vertices += c.active_vertices;
+            st.bwd_active_arcs += c.active_arcs;
+            // + the DAG lane mask of every arc with an active head (8 B)
+            st.bwd_alg_bytes += 8.0 * c.active_vertices + (arc_bytes + 8.0) * c.active_arcs +
+                                12.0 * (double)prev + 24.0 * (double)c.outputs;
+            prev = c.produced;
+            if (c.produced == 0) last = kk;
+        }
+        k += kWindow;
     }
-    st.bwd_products += k + 1;
-    if (products) *products = k + 1;
+    st.bwd_products += last + 1;
+    if (products) *products = last + 1;
     return MFBC_OK;
 }
 
 int forward_impl(mfbc_graph *g, const int32_t *d_sources, int32_t nb, int32_t *d_dist,
-                 double *d_sigma, uint64_t *d_fmask, int64_t *h_nnz, int32_t max_products,
-                 int32_t *h_products, void *stream) {
+                 double *d_sigma, bool trace, uint64_t *d_rows, int64_t *h_nnz, int64_t *h_relax,
+                 int32_t max_products, int32_t *h_products, void *stream) {
     if (!g) return fail(MFBC_EINVAL, "graph handle is NULL");
     if (nb < 1) return fail(MFBC_EINVAL, "nb must be >= 1");
     if (!d_dist || !d_sigma) return fail(MFBC_EINVAL, "output pointer is NULL");
-    if (h_nnz && max_products < 0) return fail(MFBC_EINVAL, "max_products must be >= 0");
+    if (trace && max_products < 0) return fail(MFBC_EINVAL, "max_products must be >= 0");
     DeviceGuard dg(g->device);
     hipStream_t s = (hipStream_t)stream;
     int rc = check_sources(g, d_sources, nb, s);
     if (rc) return rc;
     const int ncg = (nb + kWave - 1) / kWave;
-    if ((rc = ensure_workspace(g, ncg, d_fmask != nullptr))) return rc;
+    if ((rc = ensure_workspace(g, ncg))) return rc;
+    if (trace) {
+        // relaxations of products 1 .. n + 1 + kWindow (every product a loop can launch)
+        const int need = g->n + 2 + kWindow;
+        if (g->ws.trace_len < need) {
+            dfree(g->ws.trace_relax);
+            g->ws.trace_len = 0;
+            if ((rc = dalloc(&g->ws.trace_relax, (size_t)need))) return rc;
+            g->ws.trace_len = need;
+        }
+        HIP_TRY(hipMemsetAsync(g->ws.trace_relax, 0, sizeof(unsigned long long) * (size_t)need, s));
+        if (d_rows && max_products > 0)
+            HIP_TRY(hipMemsetAsync(d_rows, 0,
+                                   sizeof(uint64_t) * (size_t)max_products * nb * (((size_t)g->n + 63) / 64),
+                                   s));
+    }
     g->stats = mfbc_stats{};
     launch_set_sources(g, ncg, nb, d_sources, s);
-    if ((rc = run_forward(g, ncg, nb, d_fmask != nullptr, h_nnz, max_products, h_products, s)))
+    if ((rc = run_forward(g, ncg, nb, trace, d_rows, h_nnz, h_relax, max_products, h_products, s)))
         return rc;
     g->stats.batches = 1;
-    launch_export_forward(g, ncg, nb, d_dist, d_sigma, d_fmask, s);
+    launch_export_forward(g, ncg, nb, d_dist, d_sigma, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
     return MFBC_OK;
@@ -320,7 +402,7 @@ int backward_impl(mfbc_graph *g, const int32_t *d_sources, int32_t nb, const int
     int rc = check_sources(g, d_sources, nb, s);
     if (rc) return rc;
     const int ncg = (nb + kWave - 1) / kWave;
-    if ((rc = ensure_workspace(g, ncg, false))) return rc;
+    if ((rc = ensure_workspace(g, ncg))) return rc;
     g->stats = mfbc_stats{};
     launch_set_sources(g, ncg, nb, d_sources, s);
     launch_import_forward(g, ncg, nb, d_dist, d_sigma, s);
@@ -390,6 +472,8 @@ void free_graph_memory(mfbc_graph *g) {
     g->in = Csr{};
     dfree(g->perm);
     g->h_perm.clear();
+    if (g->h_ctr) (void)hipHostFree(g->h_ctr);
+    g->h_ctr = nullptr;
 }
 
 }  // namespace
@@ -495,6 +579,12 @@ int mfbc_load_graph(int32_t n, int64_t n_arcs, const int64_t *h_row_ptr, const i
     g->params = default_params(n, n_arcs);
     g->h_rp_out.assign(rp_o, rp_o + (size_t)n + 1);
     g->h_rp_in = directed ? rpt : g->h_rp_out;
+    if (!rc && hipHostMalloc((void **)&g->h_ctr,
+                             sizeof(unsigned long long) * kCounterRing * 4 * kCounterSlots) !=
+                   hipSuccess) {
+        g->h_ctr = nullptr;
+        rc = fail(MFBC_ENOMEM, "pinned host allocation failed");
+    }
     if (!rc) rc = upload_plan(n, g->h_rp_out.data(), g->params, g->plan_out);
     if (!rc) rc = upload_plan(n, g->h_rp_in.data(), g->params, g->plan_in);
     if (rc) {
@@ -518,8 +608,8 @@ int mfbc_free_graph(mfbc_graph *g) {
 
 int mfbc_forward(mfbc_graph *g, const int32_t *d_sources, int32_t nb, int32_t *d_dist,
                  double *d_sigma, int32_t *h_products, void *hip_stream) {
-    return forward_impl(g, d_sources, nb, d_dist, d_sigma, nullptr, nullptr, 0, h_products,
-                        hip_stream);
+    return forward_impl(g, d_sources, nb, d_dist, d_sigma, false, nullptr, nullptr, nullptr, 0,
+                        h_products, hip_stream);
 }
 
 int mfbc_fixpoint(mfbc_graph *g, int32_t op, const int32_t *d_sources, int32_t nb,
@@ -533,33 +623,39 @@ int mfbc_fixpoint(mfbc_graph *g, int32_t op, const int32_t *d_sources, int32_t n
     int rc = check_sources(g, d_sources, nb, s);
     if (rc) return rc;
     const int ncg = (nb + kWave - 1) / kWave;
-    if ((rc = ensure_workspace(g, ncg, false))) return rc;
+    if ((rc = ensure_workspace(g, ncg))) return rc;
     g->stats = mfbc_stats{};
     launch_set_sources(g, ncg, nb, d_sources, s);
     launch_mono_init(g, ncg, nb, s);
-    hipEvent_t *ev = g->timing ? g->ev : nullptr;
     const double arc_bytes = g->weighted && op == MFBC_OP_SSSP ? 8.0 : 4.0;
     mfbc_stats &st = g->stats;
     int64_t prev = nb;
-    Counts c;
-    int j = 0;
-    do {
-        j++;
+    int j = 0, last = 0;
+    // windows of products with one counter read-back each, as in MFBF
+    while (!last) {
         if (j > g->n + 1) return fail(MFBC_EDEVICE, "fixpoint products did not converge");
-        launch_mono_product(g, op, ncg, j, s, ev);
-        if ((rc = read_counts(g, j, s, &c))) return rc;
-        st.fwd_entries += c.produced;
-        st.fwd_outputs += c.outputs;
-        st.fwd_active_vertices += c.active_vertices;
-        st.fwd_active_arcs += c.active_arcs;
-        st.fwd_pull_launches++;
-        // adjacency of the active rows, frontier values read once, T read
-        // where a candidate arrived, T and the next frontier written per entry
-        st.fwd_alg_bytes += 8.0 * c.active_vertices + arc_bytes * c.active_arcs +
-                            4.0 * (double)(prev + c.outputs) + 8.0 * (double)c.produced;
-        add_times(g, &st.fwd_pull_ms, &st.fwd_merge_ms);
-        prev = c.produced;
-    } while (c.produced > 0);
+        for (int i = 0; i < kWindow; i++) launch_mono_product(g, op, ncg, j + 1 + i, s, window_events(g, i));
+        if ((rc = read_ring(g, s))) return rc;
+        for (int i = 0; i < kWindow; i++) {
+            const int jj = j + 1 + i;
+            st.fwd_pull_launches++;
+            add_times(g, i, &st.fwd_pull_ms, &st.fwd_merge_ms);
+            if (last) continue;
+            const Counts c = ring_counts(g, jj);
+            st.fwd_entries += c.produced;
+            st.fwd_outputs += c.outputs;
+            st.fwd_active_vertices += c.active_vertices;
+            st.fwd_active_arcs += c.active_arcs;
+            // adjacency of the active rows, frontier values read once, T read
+            // where a candidate arrived, T and the next frontier written per entry
+            st.fwd_alg_bytes += 8.0 * c.active_vertices + arc_bytes * c.active_arcs +
+                                4.0 * (double)(prev + c.outputs) + 8.0 * (double)c.produced;
+            prev = c.produced;
+            if (c.produced == 0) last = jj;
+        }
+        j += kWindow;
+    }
+    j = last;
     st.fwd_products = j;
     st.batches = 1;
     if (h_products) *h_products = j;
@@ -570,11 +666,10 @@ int mfbc_fixpoint(mfbc_graph *g, int32_t op, const int32_t *d_sources, int32_t n
 }
 
 int mfbc_forward_trace(mfbc_graph *g, const int32_t *d_sources, int32_t nb, int32_t *d_dist,
-                       double *d_sigma, uint64_t *d_fmask, int64_t *h_nnz, int32_t max_products,
-                       int32_t *h_products, void *hip_stream) {
-    if (!d_fmask) return fail(MFBC_EINVAL, "d_fmask is NULL");
-    return forward_impl(g, d_sources, nb, d_dist, d_sigma, d_fmask, h_nnz, max_products,
-                        h_products, hip_stream);
+                       double *d_sigma, uint64_t *d_fbits, int32_t max_products, int64_t *h_nnz,
+                       int64_t *h_relax, int32_t *h_products, void *hip_stream) {
+    return forward_impl(g, d_sources, nb, d_dist, d_sigma, true, d_fbits, h_nnz, h_relax,
+                        max_products, h_products, hip_stream);
 }
 
 int mfbc_backward(mfbc_graph *g, const int32_t *d_sources, int32_t nb, const int32_t *d_dist,
@@ -603,14 +698,15 @@ int mfbc_bc(mfbc_graph *g, const int32_t *d_sources, int64_t n_sources, int32_t 
     if (rc) return rc;
     const int64_t width = std::max<int64_t>(1, std::min<int64_t>(batch, n_sources));
     const int ncg = (int)((width + kWave - 1) / kWave);
-    if ((rc = ensure_workspace(g, ncg, false))) return rc;
+    if ((rc = ensure_workspace(g, ncg))) return rc;
     g->stats = mfbc_stats{};
     launch_lambda_zero(g, ncg, s);
     for (int64_t b0 = 0; b0 < n_sources; b0 += batch) {
         const int nb = (int)std::min<int64_t>(batch, n_sources - b0);
         const int bcg = (nb + kWave - 1) / kWave;
         launch_set_sources(g, bcg, nb, d_sources + b0, s);
-        if ((rc = run_forward(g, bcg, nb, false, nullptr, 0, nullptr, s))) return rc;
+        if ((rc = run_forward(g, bcg, nb, false, nullptr, nullptr, nullptr, 0, nullptr, s)))
+            return rc;
         if ((rc = run_backward(g, bcg, nb, nullptr, s))) return rc;
         g->stats.batches++;
     }
@@ -627,6 +723,10 @@ int mfbc_set_plan(mfbc_graph *g, int32_t run_arcs, int32_t run_verts, int32_t he
     // a run's arcs are addressed with 32-bit offsets in the kernels
     if (run_arcs > (1 << 24) || heavy > (1 << 24) || slice > (1 << 24))
         return fail(MFBC_EINVAL, "run_arcs, heavy and slice must be <= 2^24");
+    // a server sizes its hub partials by the plan it was created with
+    if (g->servers > 0)
+        return fail(MFBC_EINVAL, "the graph has live servers (mfbc_server_create); free them "
+                                 "before changing its plan");
     DeviceGuard dg(g->device);
     TaskParams p = default_params(g->n, g->arcs);
     if (run_arcs > 0) p.run_arcs = run_arcs;

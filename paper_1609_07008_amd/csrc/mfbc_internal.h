@@ -25,7 +25,9 @@ constexpr int kWavesPerBlock = 4;        // 256-thread workgroups
 constexpr int kBlock = kWave * kWavesPerBlock;
 constexpr int32_t kInf = MFBC_INF_DIST;
 constexpr int kCounterSlots = 32;        // spread of the frontier-size counters
-constexpr int kCounterRing = 4;          // products whose counters are live at once
+constexpr int kCounterRing = 16;         // products whose counters are live at once
+constexpr int kWindow = 8;               // products enqueued per read-back of their counters
+                                         // (at most kCounterRing - 1)
 constexpr int kWide = 2;                 // column groups per wave in the forward product
 
 // A unit of pull work for one wave (and one column group):
@@ -85,9 +87,11 @@ struct Workspace {
     double *lam = nullptr;             // per-column-group lambda parts [cg][n]
     int32_t *src = nullptr;            // column -> source vertex, -1 = padding
     uint64_t *dag = nullptr;           // shortest-path DAG: lane mask per out-arc [cg][arcs]
-    uint64_t *fmask = nullptr;         // trace: forward membership [cg][n][64]
-    int fmask_ncg = 0;
-    unsigned long long *h_counters = nullptr;  // pinned host copy
+    int32_t *tau2 = nullptr;           // tau interleaved per pair of groups [cg/2][n][64][2]
+                                       // (read by the paired counting product)
+    unsigned long long *trace_relax = nullptr;  // trace: relaxations per product
+    int trace_len = 0;
+    bool external = false;             // carved from caller-provided memory: never freed here
 };
 
 }  // namespace mfbc
@@ -113,7 +117,10 @@ struct mfbc_graph {
     int32_t *perm = nullptr;
     std::vector<int32_t> h_perm;
     bool timing = false;
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ev[3 * mfbc::kWindow] = {};   // per product of a window: before the product kernel,
+                                       // between it and its merge, after the merge
+    unsigned long long *h_ctr = nullptr;  // pinned host copy of the counter ring
+    int servers = 0;                   // live mfbc_server objects on this graph
 };
 
 namespace mfbc {
@@ -121,14 +128,20 @@ namespace mfbc {
 // ---- launchers (kernels.hip) ----
 void launch_fwd_init(mfbc_graph *g, int ncg, int nb, hipStream_t s);
 // `ev` (nullable): three events recorded before the product kernel, between
-// it and the merge kernel, and after the merge.
-void launch_fwd_product(mfbc_graph *g, int ncg, int j, bool trace, hipStream_t s, hipEvent_t *ev);
-void launch_bwd_count(mfbc_graph *g, int ncg, hipStream_t s, hipEvent_t *ev);
+// it and the merge kernel, and after the merge.  Product j (k) skips itself
+// on the device when product j-1 (k-1) produced no frontier entry.
+void launch_fwd_product(mfbc_graph *g, int ncg, int j, hipStream_t s, hipEvent_t *ev);
+hipError_t launch_bwd_count(mfbc_graph *g, int ncg, hipStream_t s, hipEvent_t *ev);
 void launch_bwd_product(mfbc_graph *g, int ncg, int k, hipStream_t s, hipEvent_t *ev);
+// Trace: membership of forward frontier F_j (j = 0: the sources) as
+// per-column vertex bitmaps in caller order (d_rows: nb rows of (n+63)/64
+// words; nullable), and the out-degrees of its members added to
+// ws.trace_relax[j] (the relaxations of product j+1).
+void launch_trace_fwd(mfbc_graph *g, int ncg, int nb, int j, uint64_t *d_rows, hipStream_t s);
 void launch_lambda_zero(mfbc_graph *g, int ncg, hipStream_t s);
 void launch_lambda_reduce(mfbc_graph *g, int ncg, double *d_bc, hipStream_t s);
 void launch_export_forward(mfbc_graph *g, int ncg, int nb, int32_t *d_dist, double *d_sigma,
-                           uint64_t *d_fmask, hipStream_t s);
+                           hipStream_t s);
 void launch_import_forward(mfbc_graph *g, int ncg, int nb, const int32_t *d_dist,
                            const double *d_sigma, hipStream_t s);
 void launch_export_backward(mfbc_graph *g, int ncg, int nb, double *d_delta, int32_t *d_step,

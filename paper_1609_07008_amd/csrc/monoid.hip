@@ -34,6 +34,7 @@ struct MonoArgs {
     int32_t *fval_n;
     int32_t *pd;               // hub partials [cg][slots][64]
     unsigned long long *ctr;   // counter slots of product j
+    const unsigned long long *prev_ctr;  // nullable: those of product j-1 (live_prev)
     uint32_t *clear_bits;      // merge: F_{j-1}'s bitmaps, ncg planes
     unsigned long long *clear_ctr;
     int nwide;                 // pairs of groups (paired layout), 0: one group per wave
@@ -286,6 +287,7 @@ __device__ __forceinline__ void mono_hub2(const MonoArgs &a, int q, int h, unsig
 
 template <int OP, int AM>
 __global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_mono_pull2(MonoArgs a) {
+    if (!live_prev(a.prev_ctr)) return;
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const int q = wid / a.ntasks;
     unsigned long long produced = 0, outs = 0;
@@ -295,6 +297,10 @@ __global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_mono_pull2(MonoArgs 
 
 __global__ __launch_bounds__(kBlock) void k_mono_merge2(MonoArgs a) {
     const int gtid = blockIdx.x * kBlock + threadIdx.x;
+    if (!live_prev(a.prev_ctr)) {
+        if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
+        return;
+    }
     unsigned long long nv = 0, na = 0;
     clear_and_count(a.clear_bits, a.nwords, a.nwide, a.rp, nv, na);
     if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
@@ -327,6 +333,7 @@ __global__ void k_mono_seed2(const int32_t *src, int nb, int n, int nwords, int3
 
 template <int OP, int AM>
 __global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_mono_pull(MonoArgs a) {
+    if (!live_prev(a.prev_ctr)) return;
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const int cg = wid / a.ntasks;
     unsigned long long produced = 0, outs = 0;
@@ -336,6 +343,10 @@ __global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_mono_pull(MonoArgs a
 
 __global__ __launch_bounds__(kBlock) void k_mono_merge(MonoArgs a) {
     const int gtid = blockIdx.x * kBlock + threadIdx.x;
+    if (!live_prev(a.prev_ctr)) {
+        if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
+        return;
+    }
     unsigned long long nv = 0, na = 0;
     clear_and_count(a.clear_bits, a.nwords, a.ncg, a.rp, nv, na);
     if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
@@ -356,7 +367,7 @@ __global__ void k_mono_fill(int32_t *tval, size_t total, uint32_t *ab0, uint32_t
         ab0[i] = 0u;
         ab1[i] = 0u;
     }
-    if (t0 < (size_t)nctr) ctr[t0] = 0ull;
+    for (size_t i = t0; i < (size_t)nctr; i += stride) ctr[i] = 0ull;
 }
 
 // The sources' rows of the first frontier start with every lane absent ...
@@ -461,6 +472,7 @@ void launch_mono_product(mfbc_graph *g, int op, int ncg, int j, hipStream_t s, h
     a.fval_n = ws.fdist[b ^ 1];
     a.pd = ws.pd;
     a.ctr = ws.counters + (size_t)(j % kCounterRing) * 4 * kCounterSlots;
+    a.prev_ctr = j > 1 ? ws.counters + (size_t)((j - 1) % kCounterRing) * 4 * kCounterSlots : nullptr;
     a.clear_bits = ws.abits[b];
     a.clear_ctr = ws.counters + (size_t)((j + 1) % kCounterRing) * 4 * kCounterSlots;
     a.nwide = mono_pairs(ncg);

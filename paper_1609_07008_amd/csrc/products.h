@@ -78,6 +78,20 @@ __device__ __forceinline__ void flush_counts(unsigned long long c0, unsigned lon
     }
 }
 
+// Whether the product before this one produced any frontier entry: the
+// first counter array of its slot (kCounterSlots partial sums written by
+// flush_counts and by its merge) holds a nonzero value.  The host may
+// enqueue several products before reading their counters; a product whose
+// predecessor found nothing has an empty frontier to read, so every wave of
+// it returns at once (the test reads the same words in every wave, so whole
+// workgroups take the same branch).  nullptr: always run.
+__device__ __forceinline__ bool live_prev(const unsigned long long *prev) {
+    if (!prev) return true;
+    const int lane = threadIdx.x & (kWave - 1);
+    const unsigned long long x = lane < kCounterSlots ? prev[lane] : 0ull;
+    return ballot(x != 0ull) != 0ull;
+}
+
 // Clear `planes` vertex bitmaps of `words` words each while counting the
 // vertices set in any of them and the arcs of their rows.
 __device__ __forceinline__ void clear_and_count(uint32_t *bits, int words, int planes,
@@ -174,8 +188,8 @@ struct FwdArgs {
     int32_t *pd;               // hub partials
     double *pm;
     unsigned long long *ctr;   // counter slots of product j
+    const unsigned long long *prev_ctr;  // nullable: counter slots of product j-1 (see live_prev)
     int32_t *flags;
-    uint64_t *fmask;           // trace (nullable)
     uint32_t *clear_bits;      // merge: bitmaps to clear (F_{j-1}'s), ncg planes
     unsigned long long *clear_ctr;  // merge: counter slots of product j+1
     unsigned long long *colmask;    // nullable: [32][ncg_all] columns that produced entries
@@ -230,7 +244,6 @@ __device__ __forceinline__ uint32_t fwd_update(const FwdArgs &a, size_t idx, int
     const double mmax = (double)((1u << a.mb) - 1u);
     const uint32_t ms = bm <= mmax ? (uint32_t)bm : 0u;
     if (ms == 0u) a.fsig_n[idx] = bm;
-    if (a.fmask && a.j <= 64) a.fmask[idx] |= 1ull << (a.j - 1);
     return ((uint32_t)bd << a.mb) | ms;
 }
 
@@ -673,6 +686,7 @@ struct BwdArgs {
     int32_t *pd;
     double *pm;
     unsigned long long *ctr;
+    const unsigned long long *prev_ctr;  // nullable: counter slots of product k-1 (live_prev)
     uint32_t *clear_bits;      // ncg planes
     unsigned long long *clear_ctr;
     unsigned long long *colmask;    // nullable: [32][ncg_all] columns that produced entries
@@ -687,6 +701,8 @@ struct BwdArgs {
                                //   interleaved per pair of groups, [cg/2][n][2], and one
                                //   activity bitmap per pair; 0: one group per plane
     int nwide_all;             //   pairs of the state (bitmap planes)
+    const int32_t *tau2;       // paired counting product: tau of groups 2q, 2q+1 interleaved
+                               //   per lane, [q][n][64][2] (see k_pair_tau)
 };
 
 // Index of (cg, x) in the lane masks and plane of cg in the activity bitmaps.
@@ -805,6 +821,103 @@ __device__ __forceinline__ void count_hub(const BwdArgs &a, int cg, int h, unsig
     if (b && lane == 0)
         atomicOr(a.abits_n + (size_t)ab_plane(a, cg) * a.nwords + (x >> 5), 1u << (x & 31));
     flush_colmask(a.colmask, a.ncg_all, cg, colany);
+}
+
+// One task of the counting product for the pair of column groups q (batches
+// of two or more groups): tau of both groups is read from its interleaved
+// copy (tau2, one 8-byte entry per lane and vertex), so one gather per arc
+// and lane serves the tests of both groups, where one group per wave issues
+// a 256-B gather per arc for each group.  Each group keeps its own counters,
+// leaves and DAG masks, written in the layouts the backward products of the
+// batch read (fb_index, ab_plane).  A padding group (odd group count) counts
+// nothing and writes nothing.
+template <int AM>
+__device__ __forceinline__ void count_task_w(const BwdArgs &a, int q, int t, unsigned long long &produced) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int cg0 = 2 * q;
+    const bool has1 = cg0 + 1 < a.ncg;
+    const Task *tp = a.tasks + t;
+    const int v0 = uni(tp->v0), v1 = uni(tp->v1), hub = uni(tp->hub), part = uni(tp->part);
+    const int64_t e0 = uni64(tp->e0), e1 = uni64(tp->e1);
+    const size_t n = (size_t)a.n;
+    const int2 *T2 = (const int2 *)a.tau2 + (size_t)q * n * kWave;
+    uint64_t *Dg0 = a.dag + (size_t)cg0 * a.narcs;
+    uint64_t *Dg1 = Dg0 + a.narcs;
+    uint64_t act0 = 0, act1 = 0;
+    const int xa = v0, xb = hub >= 0 ? v0 + 1 : v1;
+    for (int x = xa; x < xb; x++) {
+        const int2 dx = T2[(size_t)x * kWave + lane];
+        const bool r0 = dx.x != kInf, r1 = has1 && dx.y != kInf;
+        const int64_t ea = hub >= 0 ? e0 : a.rp[x];
+        const int64_t eb = hub >= 0 ? e1 : a.rp[x + 1];
+        int c0 = 0, c1 = 0;
+        if (ballot(r0 || r1)) {
+            for (int64_t e = ea; e < eb; e += kWave) {
+                const int64_t my = e + lane;
+                int y = 0, wt = 1;
+                if (my < eb) load_arc<AM>(a.arcs, my, y, wt);
+                const int cnt = (int)((eb - e) < kWave ? (eb - e) : kWave);
+                uint64_t m0 = 0, m1 = 0;     // this lane's arc: its shortest-path lanes
+                for (int j = 0; j < cnt; j += 8) {
+                    int2 dy[8];
+                    int wj[8];
+#pragma unroll
+                    for (int k = 0; k < 8; k++) {
+                        dy[k] = make_int2(kInf, kInf);
+                        wj[k] = 0;
+                        if (j + k < cnt) {
+                            const int yk = rdlane(y, j + k);
+                            wj[k] = AM ? rdlane(wt, j + k) : 1;
+                            dy[k] = T2[(size_t)yk * kWave + lane];
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < 8; k++) {
+                        const bool t0 = r0 && dy[k].x != kInf && dy[k].x == dx.x + wj[k];
+                        const bool t1 = r1 && dy[k].y != kInf && dy[k].y == dx.y + wj[k];
+                        c0 += t0;
+                        c1 += t1;
+                        const uint64_t b0 = ballot(t0), b1 = ballot(t1);
+                        if (lane == j + k) {
+                            m0 = b0;
+                            m1 = b1;
+                        }
+                    }
+                }
+                if (my < eb) {
+                    Dg0[my] = m0;
+                    if (has1) Dg1[my] = m1;
+                }
+            }
+        } else {
+            // no lane of either group reaches x: none of its arcs is on a shortest path
+            for (int64_t e = ea + lane; e < eb; e += kWave) {
+                Dg0[e] = 0ull;
+                if (has1) Dg1[e] = 0ull;
+            }
+        }
+        if (hub >= 0) {
+            a.pd[((size_t)cg0 * a.nslots + part) * kWave + lane] = c0;
+            if (has1) a.pd[((size_t)(cg0 + 1) * a.nslots + part) * kWave + lane] = c1;
+        } else {
+            const uint64_t b0 = count_finalize(a, (size_t)cg0 * n, cg0, x, dx.x, c0, lane);
+            produced += __popcll(b0);
+            if (b0) act0 |= 1ull << (x - v0);
+            if (has1) {
+                const uint64_t b1 = count_finalize(a, (size_t)(cg0 + 1) * n, cg0 + 1, x, dx.y, c1, lane);
+                produced += __popcll(b1);
+                if (b1) act1 |= 1ull << (x - v0);
+            }
+        }
+    }
+    if (hub < 0 && lane == 0) {
+        if (a.nwide) {
+            if (act0 | act1) or_run_bits(a.abits_n + (size_t)q * a.nwords, v0, act0 | act1);
+        } else {
+            if (act0) or_run_bits(a.abits_n + (size_t)cg0 * a.nwords, v0, act0);
+            if (act1) or_run_bits(a.abits_n + (size_t)(cg0 + 1) * a.nwords, v0, act1);
+        }
+    }
 }
 
 // Finish (s, x) after a backward product contributed `acc` from `got`
@@ -1146,6 +1259,7 @@ __device__ __forceinline__ int pick_cg(const int32_t *cglist, int cg) {
 
 template <int AM, bool L>
 __global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_fwd_pull(FwdArgs a) {
+    if (!live_prev(a.prev_ctr)) return;
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const int cg = wid / a.ntasks;                       // column-group major
     unsigned long long produced = 0, outs = 0;
@@ -1153,9 +1267,16 @@ __global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_fwd_pull(FwdArgs a) 
     flush_counts(produced, outs, 0, 0, a.ctr);
 }
 
+// A merge whose product was skipped (see live_prev) only clears the next
+// product's counters: no hub partial was written and the frontier it would
+// clear is empty.
 template <bool L>
 __global__ __launch_bounds__(kBlock) void k_fwd_merge(FwdArgs a) {
     const int gtid = blockIdx.x * kBlock + threadIdx.x;
+    if (!live_prev(a.prev_ctr)) {
+        if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
+        return;
+    }
     unsigned long long nv = 0, na = 0;
     clear_and_count(a.clear_bits, a.nwords, a.ncg_all, a.rp, nv, na);
     if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
@@ -1171,6 +1292,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_merge(FwdArgs a) {
 // else groups 0 .. a.nwide-1; the merge clears a.nwide_all bitmap planes.
 template <int AM, int W, bool L>
 __global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_fwd_pull_w(FwdArgs a) {
+    if (!live_prev(a.prev_ctr)) return;
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const int q = wid / a.ntasks;
     unsigned long long produced = 0, outs = 0;
@@ -1181,6 +1303,10 @@ __global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_fwd_pull_w(FwdArgs a
 template <int W, bool L>
 __global__ __launch_bounds__(kBlock) void k_fwd_merge_w(FwdArgs a) {
     const int gtid = blockIdx.x * kBlock + threadIdx.x;
+    if (!live_prev(a.prev_ctr)) {
+        if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
+        return;
+    }
     unsigned long long nv = 0, na = 0;
     clear_and_count(a.clear_bits, a.nwords, a.nwide_all, a.rp, nv, na);
     if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
@@ -1200,6 +1326,16 @@ __global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_bwd_count(BwdArgs a)
     flush_counts(produced, 0, 0, 0, a.ctr);
 }
 
+// Paired counting product (plain path, two or more groups): wave = (pair, task).
+template <int AM>
+__global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_bwd_count_w(BwdArgs a) {
+    const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const int q = wid / a.ntasks;
+    unsigned long long produced = 0;
+    if (q < (a.ncg + 1) / 2) count_task_w<AM>(a, q, wid - q * a.ntasks, produced);
+    flush_counts(produced, 0, 0, 0, a.ctr);
+}
+
 template <bool L>
 __global__ __launch_bounds__(kBlock) void k_bwd_count_merge(BwdArgs a) {
     const int gtid = blockIdx.x * kBlock + threadIdx.x;
@@ -1213,6 +1349,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_count_merge(BwdArgs a) {
 
 template <int AM, bool L>
 __global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_bwd_pull(BwdArgs a) {
+    if (!live_prev(a.prev_ctr)) return;
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const int cg = wid / a.ntasks;                       // column-group major
     unsigned long long produced = 0, outs = 0;
@@ -1223,6 +1360,7 @@ __global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_bwd_pull(BwdArgs a) 
 // Paired backward product (plain path): wave = (pair, task), pair-major.
 template <int AM>
 __global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_bwd_pull_w(BwdArgs a) {
+    if (!live_prev(a.prev_ctr)) return;
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const int q = wid / a.ntasks;
     unsigned long long produced = 0, outs = 0;
@@ -1233,6 +1371,10 @@ __global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_bwd_pull_w(BwdArgs a
 template <int D = 0>
 __global__ __launch_bounds__(kBlock) void k_bwd_merge_w(BwdArgs a) {
     const int gtid = blockIdx.x * kBlock + threadIdx.x;
+    if (!live_prev(a.prev_ctr)) {
+        if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
+        return;
+    }
     unsigned long long nv = 0, na = 0;
     clear_and_count(a.clear_bits, a.nwords, a.nwide_all, a.rp, nv, na);
     if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
@@ -1246,6 +1388,10 @@ __global__ __launch_bounds__(kBlock) void k_bwd_merge_w(BwdArgs a) {
 template <bool L>
 __global__ __launch_bounds__(kBlock) void k_bwd_merge(BwdArgs a) {
     const int gtid = blockIdx.x * kBlock + threadIdx.x;
+    if (!live_prev(a.prev_ctr)) {
+        if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
+        return;
+    }
     unsigned long long nv = 0, na = 0;
     clear_and_count(a.clear_bits, a.nwords, a.ncg_all, a.rp, nv, na);
     if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;

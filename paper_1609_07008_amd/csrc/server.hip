@@ -136,6 +136,7 @@ struct mfbc_server {
     int npair = 0;                          // forward pairs (groups 2p, 2p+1; the last may be
                                             // half padding, whose tiles exist but hold no column)
     int cur_f = 0, cur_b = 0, kfwd = 0, kbwd = 0;
+    int32_t slot_cap = 0;                   // hub partial slots the server's pd/pm hold
     int32_t *tdist = nullptr;
     double *tsig = nullptr;
     uint32_t *ftup[2] = {nullptr, nullptr};
@@ -324,6 +325,8 @@ int mfbc_server_create(mfbc_graph *g, int32_t width, mfbc_server **out) {
         delete s;
         return sfail(rc, rc == MFBC_ENOMEM ? "device allocation failed" : "initialisation failed");
     }
+    s->slot_cap = std::max(g->plan_in.nslots, g->plan_out.nslots);
+    g->servers++;              // the graph's plan is frozen while servers are attached
     s->h_src.assign((size_t)width, -1);
     s->phase.assign((size_t)width, kFree);
     s->ran_f.assign((size_t)width, 0);
@@ -337,6 +340,7 @@ int mfbc_server_create(mfbc_graph *g, int32_t width, mfbc_server **out) {
 int mfbc_server_free(mfbc_server *s) {
     if (!s) return MFBC_OK;
     (void)hipDeviceSynchronize();
+    if (s->g && s->g->servers > 0) s->g->servers--;
     free_server(s);
     delete s;
     return MFBC_OK;
@@ -426,6 +430,8 @@ int mfbc_server_step_launch(mfbc_server *s, void *hip_stream) {
     if (s->launched) return sfail(MFBC_EINVAL, "a step is already in flight");
     hipStream_t st = (hipStream_t)hip_stream;
     mfbc_graph *g = s->g;
+    if (std::max(g->plan_in.nslots, g->plan_out.nslots) > s->slot_cap)
+        return sfail(MFBC_EINVAL, "the graph's plan needs more hub partial slots than the server holds");
     int prev = -1;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(g->device);

@@ -281,15 +281,13 @@ def random_small_graph(n: int, p: float, seed: int, wrange=None) -> Graph:
 
 
 # ---------------------------------------------------------------- workload suites
-def batched_suite(count: int = 256, seed0: int = 1000, nmin: int = 200,
-                  nmax: int = 20000, kmin: float = 4, kmax: float = 64,
-                  wrange=(1, 100)) -> list:
-    """Many independent graphs of uneven sizes.
+def batched_specs(count: int = 256, seed0: int = 1000, nmin: int = 200,
+                  nmax: int = 20000, kmin: float = 4, kmax: float = 64) -> list:
+    """(kind, n, average degree, sub-seed) of every graph of ``batched_suite``.
 
     Graph ``g`` is drawn from seed ``seed0 + g``: its kind is ER or R-MAT with
     probability 1/2, n is log-uniform in [nmin, nmax], the average degree is
-    uniform in [kmin, kmax], weights are uniform in ``wrange``.  R-MAT graphs
-    use scale ceil(log2 n) and reject endpoints >= n.
+    uniform in [kmin, kmax].
     """
     out = []
     for gi in range(count):
@@ -298,14 +296,28 @@ def batched_suite(count: int = 256, seed0: int = 1000, nmin: int = 200,
         n = int(round(np.exp(rng.uniform(np.log(nmin), np.log(nmax)))))
         k = float(rng.uniform(kmin, kmax))
         sub = int(rng.integers(0, 2**31 - 1))
-        if kind == "er":
-            g = er_graph(n, k, sub, wrange, name=f"batch{gi}_er_n{n}")
-        else:
-            scale = int(np.ceil(np.log2(n)))
-            ef = max(1, int(round(k / 2)))
-            g = rmat_graph(scale, ef, sub, wrange=wrange, n=n, name=f"batch{gi}_rmat_n{n}")
-        out.append(g)
+        out.append((kind, n, k, sub))
     return out
+
+
+def batched_graph(gi: int, spec, wrange=(1, 100)) -> Graph:
+    """Graph ``gi`` of the batched suite from its spec (see batched_specs).
+    R-MAT graphs use scale ceil(log2 n) and reject endpoints >= n."""
+    kind, n, k, sub = spec
+    if kind == "er":
+        return er_graph(n, k, sub, wrange, name=f"batch{gi}_er_n{n}")
+    scale = int(np.ceil(np.log2(n)))
+    ef = max(1, int(round(k / 2)))
+    return rmat_graph(scale, ef, sub, wrange=wrange, n=n, name=f"batch{gi}_rmat_n{n}")
+
+
+def batched_suite(count: int = 256, seed0: int = 1000, nmin: int = 200,
+                  nmax: int = 20000, kmin: float = 4, kmax: float = 64,
+                  wrange=(1, 100)) -> list:
+    """Many independent graphs of uneven sizes, kinds and densities, weights
+    uniform in ``wrange`` (see batched_specs and batched_graph)."""
+    specs = batched_specs(count, seed0, nmin, nmax, kmin, kmax)
+    return [batched_graph(gi, sp, wrange) for gi, sp in enumerate(specs)]
 
 
 def poisson_trace(rate: float, count: int, n_graphs: int, seed: int,

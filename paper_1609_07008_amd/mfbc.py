@@ -29,7 +29,7 @@ SIGNATURES = {
     "mfbc_forward": ([_P, _P, _I32, _P, _P, _P, _P], ctypes.c_int),
     "mfbc_backward": ([_P, _P, _I32, _P, _P, _P, _P, _P], ctypes.c_int),
     "mfbc_bc": ([_P, _P, _I64, _I32, _P, _P], ctypes.c_int),
-    "mfbc_forward_trace": ([_P, _P, _I32, _P, _P, _P, _P, _I32, _P, _P], ctypes.c_int),
+    "mfbc_forward_trace": ([_P, _P, _I32, _P, _P, _P, _I32, _P, _P, _P, _P], ctypes.c_int),
     "mfbc_backward_trace": ([_P, _P, _I32, _P, _P, _P, _P, _P, _P], ctypes.c_int),
     "mfbc_get_stats": ([_P, _P], ctypes.c_int),
     "mfbc_enable_timing": ([_P, ctypes.c_int], ctypes.c_int),
@@ -147,8 +147,15 @@ class DeviceGraph:
             return sources
         return t.as_tensor(np.asarray(sources, dtype=np.int32), device="cuda")
 
-    def forward(self, sources, trace: bool = False, max_products: int = 4096, stream=None):
-        """MFBF for a batch: dist int32[nb][n], sigma float64[nb][n], products."""
+    def forward(self, sources, trace: bool = False, max_products: Optional[int] = None,
+                frontiers: bool = True, stream=None):
+        """MFBF for a batch: dist int32[nb][n], sigma float64[nb][n], products.
+
+        ``trace``: also ``nnz`` (frontier entries per product), ``relax``
+        (relaxations per product) and, if ``frontiers``, ``fbits``: int64
+        [max_products][nb][(n+63)//64] membership bitmaps of each product's
+        frontier (see ``frontier_rows``).  ``max_products`` defaults to
+        min(n + 2, 4096)."""
         t = self._torch
         lib = load_library()
         src = self._src(sources)
@@ -158,20 +165,35 @@ class DeviceGraph:
         prods = ctypes.c_int32(0)
         out = {"dist": dist, "sigma": sigma}
         if trace:
-            fmask = t.empty((nb, self.n), dtype=t.int64, device="cuda")
+            if max_products is None:
+                max_products = min(self.n + 2, 4096)
+            words = (self.n + 63) // 64
+            fbits = (t.zeros((max_products, nb, words), dtype=t.int64, device="cuda")
+                     if frontiers else None)
             nnz = np.zeros(max_products, dtype=np.int64)
+            relax = np.zeros(max_products, dtype=np.int64)
             rc = lib.mfbc_forward_trace(self.handle, _ptr(src), nb, _ptr(dist), _ptr(sigma),
-                                        _ptr(fmask), nnz.ctypes.data_as(_P), max_products,
-                                        ctypes.byref(prods), _stream(t, stream))
-            out.update(fmask=fmask, nnz=nnz)
+                                        _ptr(fbits), max_products, nnz.ctypes.data_as(_P),
+                                        relax.ctypes.data_as(_P), ctypes.byref(prods),
+                                        _stream(t, stream))
+            out.update(fbits=fbits, nnz=nnz, relax=relax)
         else:
             rc = lib.mfbc_forward(self.handle, _ptr(src), nb, _ptr(dist), _ptr(sigma),
                                   ctypes.byref(prods), _stream(t, stream))
         _check(rc)
         out["products"] = prods.value
         if trace:
-            out["nnz"] = out["nnz"][:prods.value]
+            k = min(prods.value, max_products)
+            out["nnz"] = out["nnz"][:k]
+            out["relax"] = out["relax"][:k]
         return out
+
+    @staticmethod
+    def frontier_rows(fbits_host: np.ndarray, n: int) -> np.ndarray:
+        """Unpack host bitmaps [..., words] (from ``forward(trace=True)``) to bool [..., n]."""
+        b = np.ascontiguousarray(fbits_host).view(np.uint64)
+        bits = np.unpackbits(b.view(np.uint8), axis=-1, bitorder="little")
+        return bits[..., :n].astype(bool)
 
     def fixpoint(self, sources, op: str = "sssp", out=None, stream=None):
         """Monoid relaxation to a fixpoint (mfbc_fixpoint): int32[nb][n]

@@ -81,3 +81,41 @@ def test_bc_many_rejects_bad_sources(mfbc):
         mfbc.bc_many([dg], [np.array([0, 1], dtype=np.int32)], block_threads=1024)
     assert e.value.code == mfbc.MFBC_EINVAL
     dg.close()
+
+
+def test_bc_many_at_batched_workload_sizes(mfbc):
+    """Graphs of the batched workload itself (n up to 19,900, average degree
+    up to 60, ER and R-MAT, weights 1..100), in the launch shape the
+    benchmark uses: all-source results against one mfbc_bc per graph, the
+    largest graph against the oracle over all its sources, and every graph
+    against the oracle on a sampled source list."""
+    import time
+    import torch
+    from paper_1609_07008_amd import autotune
+    specs = gg.batched_specs()
+    order = sorted(range(len(specs)), key=lambda i: -specs[i][1])
+    rng = np.random.default_rng(11)
+    pick = order[:5] + sorted(rng.choice(order[5:], size=10, replace=False).tolist())
+    gs = [gg.batched_graph(i, specs[i]) for i in pick]
+    print(f"[batched] graphs {[(g.name, g.n, g.m) for g in gs]}", flush=True)
+    dgs = [mfbc.DeviceGraph(g) for g in gs]
+    cfg = autotune.many_config(autotune.load_cache())
+    srcs = [torch.arange(g.n, dtype=torch.int32, device="cuda") for g in gs]
+    out = mfbc.bc_many(dgs, srcs, **cfg)
+    for g, dg, s, o in zip(gs, dgs, srcs, out):
+        rel_close(o.cpu().numpy(), dg.bc(s, 256).cpu().numpy(), 1e-10, g.name + " vs per-graph")
+    t0 = time.perf_counter()
+    big = gs[0]
+    ref = oracle.brandes(big, np.arange(big.n, dtype=np.int32), per_source=False,
+                         nthreads=oracle.brandes_threads())["lambda"]
+    rel_close(out[0].cpu().numpy(), ref, 1e-10, big.name + " all sources")
+    print(f"[batched] {big.name}: all {big.n} sources match the oracle "
+          f"({time.perf_counter() - t0:.1f}s)", flush=True)
+    sample = [gg.pick_sources(g, min(128, int((g.degree > 0).sum())), 40 + i)
+              for i, g in enumerate(gs)]
+    out2 = mfbc.bc_many(dgs, sample, **cfg)
+    for g, s, o in zip(gs, sample, out2):
+        ref = oracle.brandes(g, s, per_source=False, nthreads=oracle.brandes_threads())["lambda"]
+        rel_close(o.cpu().numpy(), ref, 1e-10, g.name + " sampled sources")
+    for d in dgs:
+        d.close()

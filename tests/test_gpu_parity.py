@@ -10,8 +10,9 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle import mfbc_ref
+from oracle.frontier import backward_products
 from paper_1609_07008_amd import graphgen as gg
+from tests.helpers import expected_forward
 
 pytestmark = pytest.mark.gpu
 
@@ -104,14 +105,19 @@ def test_forward_parity(torch, mfbc, dgraphs, name, nb):
     ref = oracle.brandes(g, src)
     assert np.array_equal(host_dist(f["dist"], mfbc.INF_DIST), ref["dist"])
     rel_close(f["sigma"].cpu().numpy(), ref["sigma"], SIGMA_TOL, "sigma")
-    alg = mfbc_ref.mfbf(g, src)
-    assert f["products"] == alg["products"]
-    fm = f["fmask"].cpu().numpy().view(np.uint64)
-    for j in range(1, min(alg["products"], 64) + 1):
-        got = ((fm >> np.uint64(j - 1)) & np.uint64(1)).astype(bool)
-        assert np.array_equal(got, alg["frontiers"][j - 1]), f"frontier {j}"
-    want_nnz = [int(F.sum()) for F in alg["frontiers"]]
-    assert f["nnz"].tolist() == want_nnz
+    check_frontiers(mfbc, g, src, f)
+
+
+def check_frontiers(mfbc, g, src, f):
+    """Every product's frontier, bit-exact, against Lemma 1's sets; the
+    product count, frontier sizes and relaxations per product."""
+    products, member, nnz, relax = expected_forward(g, src)
+    assert f["products"] == products
+    fb = mfbc.DeviceGraph.frontier_rows(f["fbits"][:products].cpu().numpy(), g.n)
+    for j in range(1, products + 1):
+        assert np.array_equal(fb[j - 1], member(j)), f"frontier {j} of {products}"
+    assert f["nnz"].tolist() == nnz
+    assert f["relax"].tolist() == relax
 
 
 @pytest.mark.parametrize("name", list(GRAPHS))
@@ -125,11 +131,10 @@ def test_backward_parity(torch, mfbc, dgraphs, name, nb):
     b = dgraphs[name].backward(src, f["dist"], f["sigma"], trace=True)
     rel_close(b["delta"].cpu().numpy(), ref["delta"], DELTA_TOL, "delta")
     assert np.array_equal(b["step"].cpu().numpy(), ref["height"])
-    # the oracle's Algorithm 2 also puts the source in its last frontier and
-    # then runs one product that finds nothing; the kernels leave the source
-    # out of the frontier (it has no predecessor), so they stop one earlier
-    alg = mfbc_ref.mfbr(g, src, ref["dist"], ref["sigma"], trace=False)
-    assert b["products"] == alg["products"] - 1
+    # counting product + one per height level of a non-source vertex + the
+    # product that finds nothing (the source has no predecessor, so its own
+    # entry feeds no product)
+    assert b["products"] == backward_products(ref["height"], src)
 
 
 @pytest.mark.parametrize("name", list(GRAPHS))
@@ -212,8 +217,7 @@ def test_directed_graph(torch, mfbc):
     f = dg.forward(src, trace=True)
     assert np.array_equal(host_dist(f["dist"], mfbc.INF_DIST), ref["dist"])
     rel_close(f["sigma"].cpu().numpy(), ref["sigma"], SIGMA_TOL, "sigma")
-    alg = mfbc_ref.mfbf(g, src)
-    assert f["products"] == alg["products"]
+    check_frontiers(mfbc, g, src, f)
     b = dg.backward(src, f["dist"], f["sigma"], trace=True)
     rel_close(b["delta"].cpu().numpy(), ref["delta"], DELTA_TOL, "delta")
     assert np.array_equal(b["step"].cpu().numpy(), ref["height"])

@@ -1,9 +1,10 @@
 """Pins of the CPU oracle against things other than itself (no GPU).
 
-Each test checks the oracle (Brandes in C, and the plain transcription of
-Algorithms 1-3) against brute-force enumeration, closed forms, invariants, a
-hand-derived worked example, or an independent library, so that a dropped
-term, a wrong sign or index, or a transposed operand in the oracle fails here.
+Each test checks the oracle (Brandes in C, and the frontier sets of Lemmas 1
+and 2 evaluated from their definitions) against brute-force enumeration,
+closed forms, invariants, a hand-derived worked example, or an independent
+library, so that a dropped term, a wrong sign or index, or a transposed
+operand in the oracle fails here.
 """
 import itertools
 import math
@@ -14,8 +15,9 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle import brute, mfbc_ref
-from oracle.frontier import forward_frontiers, backward_heights
+from oracle import brute
+from oracle.frontier import (backward_heights, backward_products, forward_frontiers,
+                             forward_relaxations)
 from paper_1609_07008_amd import graphgen as gg
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -54,23 +56,6 @@ def test_brandes_matches_brute_force(n, p, seed, wr):
     rel_close(r["lambda"], [float(x) for x in lam], 1e-13)
 
 
-@pytest.mark.parametrize("n,p,seed,wr", SMALL)
-def test_algorithms_1_to_3_match_brute_force(n, p, seed, wr):
-    g = gg.random_small_graph(n, p, seed, wr)
-    per, lam = brute.brute_bc(g, range(n))
-    src = np.arange(n)
-    f = mfbc_ref.mfbf(g, src)
-    b = mfbc_ref.mfbr(g, src, f["dist"], f["sigma"])
-    for s in range(n):
-        assert f["dist"][s].tolist() == [(-1 if t is None else t) for t in per[s]["tau"]]
-        assert f["sigma"][s].tolist() == [float(x) for x in per[s]["sigma"]]
-        dep = b["zeta"][s] * f["sigma"][s]
-        dep[s] = 0.0
-        rel_close(dep, [float(x) for x in per[s]["delta"]], 1e-13)
-    for batch in (1, 3, n):
-        rel_close(mfbc_ref.mfbc(g, src, batch), [float(x) for x in lam], 1e-13)
-
-
 def _load_golden(name):
     spec = {"edges": [], "sources": {}}
     cur = None
@@ -104,30 +89,23 @@ def test_golden_weighted5():
     g = spec["graph"]
     srcs = sorted(spec["sources"])
     r = oracle.brandes(g, srcs)
-    f = mfbc_ref.mfbf(g, srcs)
-    b = mfbc_ref.mfbr(g, srcs, f["dist"], f["sigma"])
     for i, s in enumerate(srcs):
         want = spec["sources"][s]
         assert r["dist"][i].tolist() == want["dist"]
-        assert f["dist"][i].tolist() == want["dist"]
         assert r["sigma"][i].tolist() == want["sigma"]
-        assert f["sigma"][i].tolist() == want["sigma"]
         rel_close(r["delta"][i], [float(x) for x in want["delta"]], 1e-15)
-        dep = b["zeta"][i] * f["sigma"][i]
-        dep[s] = 0
-        rel_close(dep, [float(x) for x in want["delta"]], 1e-15)
         if "height" in want:
             assert r["height"][i].tolist() == want["height"]
-            assert b["step"][i].tolist() == want["height"]
+            for k, Bk in enumerate(backward_heights(r["height"][i])):
+                assert np.flatnonzero(Bk).tolist() == [v for v, h in enumerate(want["height"])
+                                                       if h == k]
         if want["frontier"]:
             J = max(want["frontier"])
             fr = forward_frontiers(g, s)
             assert len(fr) == J
             for j, verts in want["frontier"].items():
                 assert np.flatnonzero(fr[j - 1]).tolist() == verts
-                assert np.flatnonzero(f["frontiers"][j - 1][i]).tolist() == verts
     rel_close(r["lambda"], [float(x) for x in spec["lambda"]], 1e-15)
-    rel_close(mfbc_ref.mfbc(g, srcs, 1), [float(x) for x in spec["lambda"]], 1e-15)
 
 
 # ----------------------------------------------------------------- closed forms
@@ -171,10 +149,8 @@ def test_complete_bipartite_closed_form(a, b):
 def test_grid_path_counts_are_binomials():
     a, b = 6, 9
     r = oracle.brandes(gg.grid_graph(a, b), [0])
-    f = mfbc_ref.mfbf(gg.grid_graph(a, b), [0], trace=False)
     want = [math.comb(i + j, i) for i in range(a) for j in range(b)]
     assert r["sigma"][0].tolist() == want
-    assert f["sigma"][0].tolist() == want
 
 
 def test_diamond_chain_counts_are_powers_of_two():
@@ -271,46 +247,80 @@ def test_forward_frontier_closed_form_matches_walk_enumeration(n, p, seed, wr):
         assert not fr[-1].any()
 
 
-@pytest.mark.parametrize("wr", [None, (1, 100), (1, 3)])
-def test_algorithm_1_frontiers_match_closed_form(wr):
-    g = gg.er_graph(200, 5, 21, wr)
-    src = np.arange(0, 200, 13)
-    f = mfbc_ref.mfbf(g, src)
-    for i, s in enumerate(src):
-        fr = forward_frontiers(g, int(s))
-        assert len(fr) <= f["products"]
-        for j in range(f["products"]):
-            want = fr[j] if j < len(fr) else np.zeros(g.n, bool)
-            assert np.array_equal(f["frontiers"][j][i], want)
-    assert f["products"] == max(len(forward_frontiers(g, int(s))) for s in src)
+def test_directed_frontiers_match_walk_enumeration():
+    """Arcs are followed from the tail: the same pin on directed graphs."""
+    for seed in (3, 4, 5):
+        g = gg.directed_rmat_graph(3, 4, seed, wrange=(1, 3))
+        for s in range(g.n):
+            fr = forward_frontiers(g, s)
+            ell, _ = brute.walk_minima(g, s, len(fr))
+            best = [ell[0][v] for v in range(g.n)]
+            for j in range(1, len(fr) + 1):
+                want = [ell[j][v] is not None and (best[v] is None or ell[j][v] <= best[v])
+                        for v in range(g.n)]
+                assert fr[j - 1].tolist() == want
+                best = [b if e is None else (e if b is None else min(b, e))
+                        for b, e in zip(best, ell[j])]
 
 
 def test_unweighted_frontiers_are_bfs_levels():
     g = gg.rmat_graph(8, 6, 2)
     src = gg.pick_sources(g, 10, 3)
     r = oracle.brandes(g, src)
-    f = mfbc_ref.mfbf(g, src)
-    for i in range(src.size):
-        for j, F in enumerate(f["frontiers"], start=1):
-            assert np.array_equal(F[i], r["dist"][i] == j)
-    # one product per BFS level plus the product that finds nothing new
-    assert f["products"] == r["dist"].max() + 1
+    for i, s in enumerate(src):
+        fr = forward_frontiers(g, int(s))
+        for j, F in enumerate(fr, start=1):
+            assert np.array_equal(F, r["dist"][i] == j)
+        # one product per BFS level plus the product that finds nothing new
+        assert len(fr) == r["dist"][i].max() + 1
+
+
+def test_frontier_closed_forms():
+    """Weighted path from an end: F_j = {j} for j < n, then empty; a path
+    from its middle reaches both sides; every heavier shortcut re-enters."""
+    fr = forward_frontiers(gg.path_graph(9, w=5), 0)
+    assert [np.flatnonzero(F).tolist() for F in fr] == [[j] for j in range(1, 9)] + [[]]
+    fr = forward_frontiers(gg.path_graph(9), 4)
+    assert [np.flatnonzero(F).tolist() for F in fr] == [[3, 5], [2, 6], [1, 7], [0, 8], []]
+    # triangle 0-1 (w 5), 0-2 (w 1), 2-1 (w 1): 1 enters at hop 1 (weight 5),
+    # again at hop 2 (weight 2, lighter), and 0 is never re-entered
+    g = gg.csr_from_edges(3, [0, 0, 2], [1, 2, 1], [5, 1, 1])
+    fr = forward_frontiers(g, 0)
+    assert [np.flatnonzero(F).tolist() for F in fr] == [[1, 2], [1], []]
+
+
+def test_relaxations_closed_forms():
+    """Relaxations of product j = arcs leaving F_{j-1}: star from its centre,
+    k then k; path from an end, one per hop (the last vertex has one arc)."""
+    k = 7
+    st = gg.star_graph(k)
+    fr = forward_frontiers(st, 0)
+    assert forward_relaxations(st, 0, fr) == [k, k]
+    p = gg.path_graph(6)
+    fr = forward_frontiers(p, 0)
+    assert forward_relaxations(p, 0, fr) == [1, 2, 2, 2, 2, 1]
 
 
 @pytest.mark.parametrize("wr", [None, (1, 100)])
-def test_algorithm_2_steps_are_dag_heights(wr):
+def test_backward_products_from_heights(wr):
+    """The backward loop's product count: counting product + one per height
+    level of a non-source vertex + the product that finds nothing.  Heights
+    are pinned by brute force above; here the count is checked on closed forms
+    and the unweighted identity (1 + eccentricity of the batch)."""
+    # path from an end: heights n-1 .. 0, the source's own (n-1) feeds nothing
+    p = gg.path_graph(8)
+    r = oracle.brandes(p, [0])
+    assert backward_products(r["height"], [0]) == 8
+    # isolated source: nothing reachable but itself
+    g = gg.csr_from_edges(3, [1], [2], None)
+    r = oracle.brandes(g, [0])
+    assert backward_products(r["height"], [0]) == 1
     g = gg.er_graph(200, 5, 22, wr)
     src = np.arange(0, 200, 17)
     r = oracle.brandes(g, src)
-    f = mfbc_ref.mfbf(g, src, trace=False)
-    b = mfbc_ref.mfbr(g, src, f["dist"], f["sigma"])
-    assert np.array_equal(b["step"], r["height"])
-    # counting product + one product per height level (the last finds nothing)
-    assert b["products"] == 1 + r["height"].max() + 1
-    for i in range(src.size):
-        B = backward_heights(r["height"][i])
-        for k, Bk in enumerate(B):
-            assert np.array_equal(b["step"][i] == k, Bk)
+    if wr is None:
+        assert backward_products(r["height"], src) == 1 + int(r["dist"].max())
+    assert backward_products(r["height"], src) == 1 + int(r["height"].max())
 
 
 def test_unweighted_product_bound():
@@ -318,10 +328,10 @@ def test_unweighted_product_bound():
     g = gg.rmat_graph(8, 6, 7)
     src = gg.pick_sources(g, 16, 1)
     r = oracle.brandes(g, src)
-    f = mfbc_ref.mfbf(g, src, trace=False)
-    b = mfbc_ref.mfbr(g, src, f["dist"], f["sigma"], trace=False)
+    fwd = max(len(forward_frontiers(g, int(s))) for s in src)
+    bwd = backward_products(r["height"], src)
     d = int(r["dist"].max())
-    assert (f["products"] - 1) + (b["products"] - 1) <= 2 * d + 1
+    assert (fwd - 1) + (bwd - 1) <= 2 * d + 1
 
 
 # ------------------------------------------------------------------ monoid fixpoints

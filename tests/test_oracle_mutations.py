@@ -13,11 +13,14 @@ import subprocess
 import numpy as np
 import pytest
 
-from oracle import brute, mfbc_ref
+import importlib.util
+
+from oracle import brute
 from paper_1609_07008_amd import graphgen as gg
 
-ORACLE_C = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle",
-                        "brandes.c")
+ORACLE_DIR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle")
+ORACLE_C = os.path.join(ORACLE_DIR, "brandes.c")
+FRONTIER_PY = os.path.join(ORACLE_DIR, "frontier.py")
 
 GRAPHS = [gg.random_small_graph(8, 0.45, 4, (1, 2)), gg.random_small_graph(9, 0.4, 5, None),
           gg.random_small_graph(10, 0.3, 7, (1, 5))]
@@ -97,35 +100,59 @@ def test_c_oracle_mutants_are_caught(tmp_path, name):
     assert not all(agrees(g, *run_c(lib, g)) for g in GRAPHS), f"pin missed mutant: {name}"
 
 
-def _ref_alg(g):
-    src = np.arange(g.n)
-    f = mfbc_ref.mfbf(g, src, trace=False)
-    b = mfbc_ref.mfbr(g, src, f["dist"], f["sigma"], trace=False)
-    dep = b["zeta"] * f["sigma"]
-    dep[src, src] = 0.0
-    return f["dist"], f["sigma"], dep, dep.sum(axis=0)
+def frontier_pin_holds(mod) -> bool:
+    """The pin of tests/test_oracle.py: frontiers against enumerated walks."""
+    graphs = [gg.random_small_graph(8, 0.45, 4, (1, 3)), gg.random_small_graph(9, 0.4, 5, None),
+              gg.directed_rmat_graph(3, 4, 4, wrange=(1, 3))]
+    for g in graphs:
+        for s in range(g.n):
+            fr = mod.forward_frontiers(g, s)
+            ell, _ = brute.walk_minima(g, s, len(fr))
+            best = [ell[0][v] for v in range(g.n)]
+            for j in range(1, len(fr) + 1):
+                want = [ell[j][v] is not None and (best[v] is None or ell[j][v] <= best[v])
+                        for v in range(g.n)]
+                if fr[j - 1].tolist() != want:
+                    return False
+                best = [b if e is None else (e if b is None else min(b, e))
+                        for b, e in zip(best, ell[j])]
+            if fr[-1].any():
+                return False
+    return True
 
 
-def test_algorithm_mutants_are_caught(monkeypatch):
-    """Mistakes in the monoids of Algorithms 1-2 are caught by the same pin."""
-    for g in GRAPHS:
-        assert agrees(g, *_ref_alg(g))
-    orig_acc = mfbc_ref._multpath_accumulate
-    orig_cacc = mfbc_ref._centpath_accumulate
+def load_frontier_mutant(tmp_path, old, new):
+    src = open(FRONTIER_PY).read()
+    assert old in src, old
+    path = tmp_path / "frontier_mutant.py"
+    path.write_text(src.replace(old, new, 1))
+    spec = importlib.util.spec_from_file_location("frontier_mutant", str(path))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
 
-    def no_tie_sum(Tw, Tm, Gw, Gm):               # multpath monoid without the tie rule
-        less = Gw < Tw
-        return np.minimum(Tw, Gw), np.where(less, Gm, Tm)
 
-    def min_instead_of_max(Zw, Zp, Zc, Cw, Cp, Cc):   # centpath monoid keeping the lighter
-        more = (Cw < Zw) & (Cw > -mfbc_ref.INF)
-        tie = (Cw == Zw) & (Cw > -mfbc_ref.INF)
-        return (np.where(more, Cw, Zw), np.where(more, Cp, np.where(tie, Zp + Cp, Zp)),
-                np.where(more, Cc, np.where(tie, Zc + Cc, Zc)))
+FRONTIER_MUTATIONS = {
+    "ties with shorter walks dropped": ("F = (nxt < INF) & (nxt <= L)", "F = (nxt < INF) & (nxt < L)"),
+    "no comparison with shorter walks": ("F = (nxt < INF) & (nxt <= L)", "F = (nxt < INF)"),
+    "L never lowered": ("        L = np.minimum(L, nxt)\n        ell = nxt\n        if not F.any():\n            return out",
+                        "        ell = nxt\n        if not F.any():\n            return out"),
+    "arcs taken head to tail": ("order = np.argsort(v, kind=\"stable\")", "order = np.argsort(u, kind=\"stable\")"),
+    "weights dropped": ("cand = ell[self.tail] + self.weight", "cand = ell[self.tail] + 1"),
+    "max instead of min": ("np.minimum.reduceat(cand, self.starts)", "np.maximum.reduceat(cand, self.starts)"),
+}
 
-    for name, attr, fn in [("no tie sum", "_multpath_accumulate", no_tie_sum),
-                           ("min for max", "_centpath_accumulate", min_instead_of_max)]:
-        monkeypatch.setattr(mfbc_ref, attr, fn)
-        assert not all(agrees(g, *_ref_alg(g)) for g in GRAPHS), f"pin missed {name}"
-        monkeypatch.setattr(mfbc_ref, "_multpath_accumulate", orig_acc)
-        monkeypatch.setattr(mfbc_ref, "_centpath_accumulate", orig_cacc)
+
+def test_unmutated_frontier_oracle_agrees(tmp_path):
+    assert frontier_pin_holds(load_frontier_mutant(tmp_path, "INF = ", "INF = "))
+
+
+@pytest.mark.parametrize("name", sorted(FRONTIER_MUTATIONS))
+def test_frontier_mutants_are_caught(tmp_path, name):
+    old, new = FRONTIER_MUTATIONS[name]
+    mod = load_frontier_mutant(tmp_path, old, new)
+    try:
+        ok = frontier_pin_holds(mod)
+    except Exception:
+        ok = False          # a mutant that crashes or never empties is caught too
+    assert not ok, f"pin missed mutant: {name}"
