@@ -150,6 +150,28 @@ int mfbc_bc(mfbc_graph *g, const int32_t *d_sources, int64_t n_sources,
             int32_t batch, double *d_bc, void *hip_stream);
 
 /*
+ * mfbc_bc_noalloc -- mfbc_bc for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, results and errors as mfbc_bc, but the call
+ * allocates nothing.  The batch state lives in a static scratch area of
+ * 64 MiB per device, part of the library's code object (every GPU the library
+ * runs on holds it until the process ends); the graph's own workspace is not
+ * used or changed.  Sources are checked on the device.
+ *   Limit: the state of one batch of min(batch, n_sources) sources must fit
+ *   the scratch -- about 41 B per (source column, vertex), columns counted in
+ *   whole groups of 64 (an even number of groups when there are two or more),
+ *   plus 8 B per (group, arc) and the graph's hub partials; a larger request
+ *   fails with MFBC_ENOMEM before any device work (n = 1024 with batches of
+ *   256 fits; n = 65536 with batches of 512 does not).
+ *   Every call on a device uses that device's one scratch area and leaves its
+ *   contents behind: calls that overlap on one device (other threads, other
+ *   streams) race and must be serialised by the caller.
+ * Errors: as mfbc_bc (ENOMEM when the batch state exceeds the scratch).
+ */
+int mfbc_bc_noalloc(mfbc_graph *g, const int32_t *d_sources, int64_t n_sources,
+                    int32_t batch, double *d_bc, void *hip_stream);
+
+/*
  * mfbc_fixpoint -- the paper's monoid product (Section 3: C = A (+).f B with a
  * commutative monoid (+) and an action f of an arc on an entry) iterated over
  * maximal frontiers as in Algorithm 1, for other graph problems.  Values are

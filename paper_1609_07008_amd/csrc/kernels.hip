@@ -51,6 +51,20 @@ __global__ void k_set_sources(int32_t *src, int total, int nb, const int32_t *in
     if (i < total) src[i] = i < nb ? dev_id(perm, in[i]) : -1;
 }
 
+// *bad = 1 if some listed source is outside [0, n) (bad must start at 0).
+__global__ void k_check_sources(const int32_t *src, int64_t count, int n, int32_t *bad) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+        if (src[i] < 0 || src[i] >= n) *bad = 1;
+}
+
+// Zero `count` 32-bit words (a kernel rather than a memset node, so that a
+// stream capture records no memset).
+__global__ void k_zero_u32(uint32_t *p, size_t count) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = 0u;
+}
+
 // T = (INF, 0) everywhere, both frontier bitmaps cleared, counters zeroed.
 __global__ void k_fwd_fill(int32_t *tdist, double *tsig, size_t total, uint32_t *ab0, uint32_t *ab1,
                            size_t nab, unsigned long long *ctr, int nctr, int32_t *flags) {
@@ -307,6 +321,14 @@ static FwdArgs fwd_args(mfbc_graph *g, int ncg, int j) {
     return a;
 }
 
+void launch_check_sources(const int32_t *d_sources, int64_t count, int n, int32_t *d_bad,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, (uint32_t *)d_bad, (size_t)1);
+    if (count > 0)
+        hipLaunchKernelGGL(k_check_sources, dim3(blocks_for((size_t)count, 256, 4096)), dim3(256), 0, s,
+                           d_sources, count, n, d_bad);
+}
+
 void launch_set_sources(mfbc_graph *g, int ncg, int nb, const int32_t *d_sources, hipStream_t s) {
     const int total = ncg * kWave;
     hipLaunchKernelGGL(k_set_sources, dim3(blocks_for(total, 256)), dim3(256), 0, s, g->ws.src,
@@ -424,13 +446,14 @@ hipError_t launch_bwd_count(mfbc_graph *g, int ncg, hipStream_t s, hipEvent_t *e
     // the counting product writes B_0 into buffer 0: clear its bitmap and
     // this product's counters first
     const int nwords = (g->n + 31) / 32;
-    hipError_t e;
-    if ((e = hipMemsetAsync(ws.abits[0], 0, (size_t)nwords * ncg * 4, s)) != hipSuccess) return e;
-    if ((e = hipMemsetAsync(ws.abits[1], 0, (size_t)nwords * ncg * 4, s)) != hipSuccess) return e;
-    if ((e = hipMemsetAsync(ws.counters, 0,
-                            sizeof(unsigned long long) * kCounterRing * 4 * kCounterSlots, s)) !=
-        hipSuccess)
-        return e;
+    const size_t nab = (size_t)nwords * ncg;
+    hipLaunchKernelGGL(k_zero_u32, dim3(blocks_for(nab, 256, 4096)), dim3(256), 0, s, ws.abits[0], nab);
+    hipLaunchKernelGGL(k_zero_u32, dim3(blocks_for(nab, 256, 4096)), dim3(256), 0, s, ws.abits[1], nab);
+    const size_t nctr = (size_t)kCounterRing * 4 * kCounterSlots * 2;   // u64 counters as u32 words
+    hipLaunchKernelGGL(k_zero_u32, dim3(blocks_for(nctr, 256)), dim3(256), 0, s,
+                       (uint32_t *)ws.counters, nctr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     BwdArgs a = bwd_args(g, ncg, 0);
     if (ev) (void)hipEventRecord(ev[0], s);
     if (ncg >= 2) {

@@ -12,13 +12,21 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "mfbc_internal.h"
 #include "order.h"
 
 using namespace mfbc;
+
+// Scratch of mfbc_bc_noalloc: one file-scope device array per GPU (the code
+// object's copy on each device), holding the workspace of one call.  Calls on
+// one device share it; each call initialises what it reads.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -476,6 +484,76 @@ void free_graph_memory(mfbc_graph *g) {
     g->h_ctr = nullptr;
 }
 
+// Column groups of the workspace for MFBC over n_sources in batches of `batch`.
+int bc_groups(int64_t n_sources, int32_t batch) {
+    const int64_t width = std::max<int64_t>(1, std::min<int64_t>(batch, n_sources));
+    return (int)((width + kWave - 1) / kWave);
+}
+
+// Algorithm 3 over the listed sources with the workspace already in place.
+int bc_batches(mfbc_graph *g, const int32_t *d_sources, int64_t n_sources, int32_t batch, int ncg,
+               double *d_bc, hipStream_t s) {
+    g->stats = mfbc_stats{};
+    launch_lambda_zero(g, ncg, s);
+    int rc;
+    for (int64_t b0 = 0; b0 < n_sources; b0 += batch) {
+        const int nb = (int)std::min<int64_t>(batch, n_sources - b0);
+        const int bcg = (nb + kWave - 1) / kWave;
+        launch_set_sources(g, bcg, nb, d_sources + b0, s);
+        if ((rc = run_forward(g, bcg, nb, false, nullptr, nullptr, nullptr, 0, nullptr, s)))
+            return rc;
+        if ((rc = run_backward(g, bcg, nb, nullptr, s))) return rc;
+        g->stats.batches++;
+    }
+    launch_lambda_reduce(g, ncg, d_bc, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    return MFBC_OK;
+}
+
+// Address of the static scratch on `device` (which must be current): taken
+// once per device with hipGetSymbolAddress and kept.  Host code never uses
+// the array's own name as an address.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_base[kMaxDevices] = {};
+
+int scratch_base(int device, char **out) {
+    if (device < 0 || device >= kMaxDevices) return fail(MFBC_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_base[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(MFBC_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_base[device] = (char *)p;
+    }
+    *out = g_scratch_base[device];
+    return MFBC_OK;
+}
+
+// The workspace of `ncg` groups carved from `base` (same arrays and sizes as
+// ensure_workspace allocates, each 256-byte aligned).
+void carve_workspace(const mfbc_graph *g, int ncg, char *base, Workspace &ws) {
+    ws = Workspace{};
+    const int groups = ws_groups(ncg);
+    size_t off = 0;
+    ws_arrays(g, ws, groups, [&](auto *&p, size_t count) {
+        p = (std::remove_reference_t<decltype(p)>)(base + off);
+        off = align256(off + std::max<size_t>(count, 1) * sizeof(*p));
+    });
+    ws.ncg = groups;
+    ws.external = true;
+}
+
+// Swaps a graph's own workspace out for the duration of a call and back.
+struct WorkspaceSwap {
+    mfbc_graph *g;
+    Workspace saved;
+    explicit WorkspaceSwap(mfbc_graph *gr) : g(gr), saved(gr->ws) { g->ws = Workspace{}; }
+    ~WorkspaceSwap() { g->ws = saved; }
+};
+
 }  // namespace
 
 extern "C" {
@@ -696,24 +774,40 @@ int mfbc_bc(mfbc_graph *g, const int32_t *d_sources, int64_t n_sources, int32_t 
     hipStream_t s = (hipStream_t)hip_stream;
     int rc = check_sources(g, d_sources, n_sources, s);
     if (rc) return rc;
-    const int64_t width = std::max<int64_t>(1, std::min<int64_t>(batch, n_sources));
-    const int ncg = (int)((width + kWave - 1) / kWave);
+    const int ncg = bc_groups(n_sources, batch);
     if ((rc = ensure_workspace(g, ncg))) return rc;
-    g->stats = mfbc_stats{};
-    launch_lambda_zero(g, ncg, s);
-    for (int64_t b0 = 0; b0 < n_sources; b0 += batch) {
-        const int nb = (int)std::min<int64_t>(batch, n_sources - b0);
-        const int bcg = (nb + kWave - 1) / kWave;
-        launch_set_sources(g, bcg, nb, d_sources + b0, s);
-        if ((rc = run_forward(g, bcg, nb, false, nullptr, nullptr, nullptr, 0, nullptr, s)))
-            return rc;
-        if ((rc = run_backward(g, bcg, nb, nullptr, s))) return rc;
-        g->stats.batches++;
-    }
-    launch_lambda_reduce(g, ncg, d_bc, s);
+    return bc_batches(g, d_sources, n_sources, batch, ncg, d_bc, s);
+}
+
+int mfbc_bc_noalloc(mfbc_graph *g, const int32_t *d_sources, int64_t n_sources, int32_t batch,
+                    double *d_bc, void *hip_stream) {
+    if (!g) return fail(MFBC_EINVAL, "graph handle is NULL");
+    if (n_sources < 0) return fail(MFBC_EINVAL, "n_sources must be >= 0");
+    if (batch < 1) return fail(MFBC_EINVAL, "batch must be >= 1");
+    if (!d_bc) return fail(MFBC_EINVAL, "d_bc is NULL");
+    if (n_sources > 0 && !d_sources) return fail(MFBC_EINVAL, "sources pointer is NULL");
+    DeviceGuard dg(g->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int ncg = bc_groups(n_sources, batch);
+    const size_t need = ws_bytes(g, ncg);
+    if (need > kScratchBytes)
+        return fail(MFBC_ENOMEM, "mfbc_bc_noalloc: this graph and batch need " + std::to_string(need) +
+                                     " bytes of workspace; the static scratch holds " +
+                                     std::to_string(kScratchBytes));
+    char *base = nullptr;
+    int rc = scratch_base(g->device, &base);
+    if (rc) return rc;
+    // the caller's workspace stays untouched: the batch state is carved from
+    // the scratch and swapped in for the duration of the call
+    WorkspaceSwap sw(g);
+    carve_workspace(g, ncg, base, g->ws);
+    // sources are checked on the device (no host copy of the list)
+    launch_check_sources(d_sources, n_sources, g->n, g->ws.flags + 1, s);
     HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(g->h_ctr, g->ws.flags + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    return MFBC_OK;
+    if (*(const int32_t *)g->h_ctr != 0) return fail(MFBC_EINVAL, "a source is outside [0, n)");
+    return bc_batches(g, d_sources, n_sources, batch, ncg, d_bc, s);
 }
 
 int mfbc_set_plan(mfbc_graph *g, int32_t run_arcs, int32_t run_verts, int32_t heavy,

@@ -83,7 +83,7 @@ struct Workspace {
     int32_t *pd = nullptr;             // partial weights / counters [cg][slots][64]
     double *pm = nullptr;              // partial multiplicities / sums
     unsigned long long *counters = nullptr;  // [ring][4][slots]
-    int32_t *flags = nullptr;          // [0]: path count overflow
+    int32_t *flags = nullptr;          // [0]: path count overflow, [1]: source out of range
     double *lam = nullptr;             // per-column-group lambda parts [cg][n]
     int32_t *src = nullptr;            // column -> source vertex, -1 = padding
     uint64_t *dag = nullptr;           // shortest-path DAG: lane mask per out-arc [cg][arcs]
@@ -147,6 +147,9 @@ void launch_import_forward(mfbc_graph *g, int ncg, int nb, const int32_t *d_dist
 void launch_export_backward(mfbc_graph *g, int ncg, int nb, double *d_delta, int32_t *d_step,
                             hipStream_t s);
 void launch_set_sources(mfbc_graph *g, int ncg, int nb, const int32_t *d_sources, hipStream_t s);
+// *d_bad := 1 if a source is outside [0, n), else 0 (no host copy of the list).
+void launch_check_sources(const int32_t *d_sources, int64_t count, int n, int32_t *d_bad,
+                          hipStream_t s);
 void launch_export_tiles_i32(mfbc_graph *g, int ncg, int nb, const int32_t *tiles, int32_t *d_rows,
                              hipStream_t s);
 

@@ -29,6 +29,7 @@ SIGNATURES = {
     "mfbc_forward": ([_P, _P, _I32, _P, _P, _P, _P], ctypes.c_int),
     "mfbc_backward": ([_P, _P, _I32, _P, _P, _P, _P, _P], ctypes.c_int),
     "mfbc_bc": ([_P, _P, _I64, _I32, _P, _P], ctypes.c_int),
+    "mfbc_bc_noalloc": ([_P, _P, _I64, _I32, _P, _P], ctypes.c_int),
     "mfbc_forward_trace": ([_P, _P, _I32, _P, _P, _P, _I32, _P, _P, _P, _P], ctypes.c_int),
     "mfbc_backward_trace": ([_P, _P, _I32, _P, _P, _P, _P, _P, _P], ctypes.c_int),
     "mfbc_get_stats": ([_P, _P], ctypes.c_int),
@@ -239,6 +240,16 @@ class DeviceGraph:
             out = t.empty(self.n, dtype=t.float64, device="cuda")
         rc = load_library().mfbc_bc(self.handle, _ptr(src), src.numel(), int(batch), _ptr(out),
                                     _stream(t, stream))
+        _check(rc)
+        return out
+
+    def bc_noalloc(self, sources, batch: int, out, stream=None):
+        """mfbc_bc_noalloc: MFBC with the batch state in the library's static
+        scratch (no device allocation); ``out`` float64[n] is caller-provided."""
+        t = self._torch
+        src = self._src(sources)
+        rc = load_library().mfbc_bc_noalloc(self.handle, _ptr(src), src.numel(), int(batch),
+                                            _ptr(out), _stream(t, stream))
         _check(rc)
         return out
 
