@@ -564,45 +564,22 @@ int mfbc_load_graph(int32_t n, int64_t n_arcs, const int64_t *h_row_ptr, const i
                     const int32_t *h_weight, uint32_t flags, void *hip_stream, mfbc_graph **out) {
     if (!out) return fail(MFBC_EINVAL, "out is NULL");
     *out = nullptr;
-    if (n < 1 || n == INT32_MAX) return fail(MFBC_EINVAL, "n must be in [1, 2^31 - 2]");
-    if (n_arcs < 0) return fail(MFBC_EINVAL, "n_arcs must be >= 0");
-    if (!h_row_ptr) return fail(MFBC_EINVAL, "row_ptr is NULL");
-    if (n_arcs > 0 && !h_col_idx) return fail(MFBC_EINVAL, "col_idx is NULL");
     const uint32_t kind = flags & ~(uint32_t)MFBC_KEEP_ORDER;
     if (kind != MFBC_UNDIRECTED && kind != MFBC_DIRECTED)
         return fail(MFBC_EINVAL, "flags must be MFBC_UNDIRECTED or MFBC_DIRECTED "
                                  "(optionally | MFBC_KEEP_ORDER)");
-    if (h_row_ptr[0] != 0 || h_row_ptr[n] != n_arcs)
-        return fail(MFBC_EINVAL, "row_ptr[0] must be 0 and row_ptr[n] must equal n_arcs");
     int32_t maxw = 1;
-    for (int32_t v = 0; v < n; v++) {
-        if (h_row_ptr[v + 1] < h_row_ptr[v] || h_row_ptr[v + 1] > n_arcs)
-            return fail(MFBC_EINVAL, "row_ptr must be non-decreasing and end at n_arcs");
-        for (int64_t e = h_row_ptr[v]; e < h_row_ptr[v + 1]; e++) {
-            const int32_t c = h_col_idx[e];
-            if (c < 0 || c >= n) return fail(MFBC_EINVAL, "column index out of range");
-            if (c == v) return fail(MFBC_EINVAL, "self-loop at vertex " + std::to_string(v));
-            if (e > h_row_ptr[v] && h_col_idx[e - 1] >= c)
-                return fail(MFBC_EINVAL, "row " + std::to_string(v) +
-                                             " is not strictly increasing (duplicate arc?)");
-            if (h_weight) {
-                if (h_weight[e] < 1) return fail(MFBC_EINVAL, "weights must be >= 1");
-                maxw = std::max(maxw, h_weight[e]);
-            }
-        }
+    {
+        std::string msg;
+        const int vrc = validate_csr(n, n_arcs, h_row_ptr, h_col_idx, h_weight, &maxw, msg);
+        if (vrc) return fail(vrc, msg);
     }
-    if ((int64_t)n * (int64_t)maxw >= (int64_t)INT32_MAX)
-        return fail(MFBC_EOVERFLOW, "n * max weight does not fit int32 distances");
     std::vector<int64_t> rpt;
     std::vector<int32_t> colt, wt;
     build_transpose(n, n_arcs, h_row_ptr, h_col_idx, h_weight, rpt, colt, wt);
     const bool directed = kind == MFBC_DIRECTED;
-    if (!directed) {
-        if (!std::equal(rpt.begin(), rpt.end(), h_row_ptr) ||
-            !std::equal(colt.begin(), colt.end(), h_col_idx) ||
-            (h_weight && !std::equal(wt.begin(), wt.end(), h_weight)))
-            return fail(MFBC_EINVAL, "undirected graph must have a symmetric CSR with equal weights");
-    }
+    if (!directed && !is_symmetric(n, n_arcs, h_row_ptr, h_col_idx, h_weight, rpt, colt, wt))
+        return fail(MFBC_EINVAL, "undirected graph must have a symmetric CSR with equal weights");
     // device numbering: out-arcs (rp_o, col_o, w_o) and in-arcs (rpt, colt, wt)
     const int64_t *rp_o = h_row_ptr;
     const int32_t *col_o = h_col_idx, *w_o = h_weight;

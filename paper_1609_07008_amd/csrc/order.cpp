@@ -1,9 +1,78 @@
-// Host-side CSR reorganisation (see order.h).
+// Host-side CSR checks and reorganisation (see order.h).
 #include "order.h"
 
 #include <algorithm>
 
+#include "../../include/mfbc.h"
+
 namespace mfbc {
+
+int validate_csr(int32_t n, int64_t n_arcs, const int64_t *rp, const int32_t *col,
+                 const int32_t *w, int32_t *maxw, std::string &msg) {
+    if (n < 1 || n == INT32_MAX) {
+        msg = "n must be in [1, 2^31 - 2]";
+        return MFBC_EINVAL;
+    }
+    if (n_arcs < 0) {
+        msg = "n_arcs must be >= 0";
+        return MFBC_EINVAL;
+    }
+    if (!rp) {
+        msg = "row_ptr is NULL";
+        return MFBC_EINVAL;
+    }
+    if (n_arcs > 0 && !col) {
+        msg = "col_idx is NULL";
+        return MFBC_EINVAL;
+    }
+    if (rp[0] != 0 || rp[n] != n_arcs) {
+        msg = "row_ptr[0] must be 0 and row_ptr[n] must equal n_arcs";
+        return MFBC_EINVAL;
+    }
+    int32_t mw = 1;
+    for (int32_t v = 0; v < n; v++) {
+        if (rp[v + 1] < rp[v] || rp[v + 1] > n_arcs) {
+            msg = "row_ptr must be non-decreasing and end at n_arcs";
+            return MFBC_EINVAL;
+        }
+        for (int64_t e = rp[v]; e < rp[v + 1]; e++) {
+            const int32_t c = col[e];
+            if (c < 0 || c >= n) {
+                msg = "column index out of range";
+                return MFBC_EINVAL;
+            }
+            if (c == v) {
+                msg = "self-loop at vertex " + std::to_string(v);
+                return MFBC_EINVAL;
+            }
+            if (e > rp[v] && col[e - 1] >= c) {
+                msg = "row " + std::to_string(v) + " is not strictly increasing (duplicate arc?)";
+                return MFBC_EINVAL;
+            }
+            if (w) {
+                if (w[e] < 1) {
+                    msg = "weights must be >= 1";
+                    return MFBC_EINVAL;
+                }
+                mw = std::max(mw, w[e]);
+            }
+        }
+    }
+    if ((int64_t)n * (int64_t)mw >= (int64_t)INT32_MAX) {
+        msg = "n * max weight does not fit int32 distances";
+        return MFBC_EOVERFLOW;
+    }
+    *maxw = mw;
+    return MFBC_OK;
+}
+
+bool is_symmetric(int32_t n, int64_t arcs, const int64_t *rp, const int32_t *col, const int32_t *w,
+                  const std::vector<int64_t> &rpt, const std::vector<int32_t> &colt,
+                  const std::vector<int32_t> &wt) {
+    if (rpt.size() != (size_t)n + 1 || colt.size() != (size_t)arcs) return false;
+    return std::equal(rpt.begin(), rpt.end(), rp) && std::equal(colt.begin(), colt.end(), col) &&
+           (!w || std::equal(wt.begin(), wt.end(), w));
+}
 
 // Also the symmetry check of an undirected CSR (the transpose must equal it).
 void build_transpose(int32_t n, int64_t arcs, const int64_t *rp, const int32_t *col,

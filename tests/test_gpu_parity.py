@@ -317,3 +317,23 @@ def test_path_count_overflow_is_reported(torch, mfbc):
     assert f["sigma"].cpu().numpy()[0, 3 * 1000] == 2.0 ** 1000
     dg.close()
     dg2.close()
+
+
+def test_workspace_enomem_is_reported_and_recoverable(torch, mfbc):
+    """A batch whose state cannot fit device memory (2^20 sources in one batch
+    on 100,000 vertices: several TB) is refused with MFBC_ENOMEM before any
+    product runs, and the graph then serves an ordinary call."""
+    g = gg.er_graph(100_000, 4, 5, (1, 9))
+    dg = mfbc.DeviceGraph(g)
+    src = torch.randint(0, g.n, (1 << 20,), dtype=torch.int32, device="cuda",
+                        generator=torch.Generator(device="cuda").manual_seed(3))
+    out = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    with pytest.raises(mfbc.MfbcError) as e:
+        dg.bc(src, 1 << 20, out=out)
+    assert e.value.code == mfbc.MFBC_ENOMEM
+    assert "allocation" in str(e.value)
+    s64 = src[:64].contiguous()
+    lam = dg.bc(s64, 64).cpu().numpy()
+    ref = oracle.brandes(g, s64.cpu().numpy(), per_source=False)["lambda"]
+    rel_close(lam, ref, DELTA_TOL, "lambda after ENOMEM")
+    dg.close()
