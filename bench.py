@@ -230,7 +230,9 @@ def run_serve(args, spec):
     serve.run_fifo(dgs, sat, realtime=False)
     rate_sat = nreq / (time.perf_counter() - t1)
     print(f"[bench] plain method saturates at {rate_sat:.2f} requests/s", file=sys.stderr, flush=True)
-    eng = serve.ServeEngine(dgs, [spec["width"]] * len(dgs))
+    # servers admitted by memory footprint within a budget of 80% of the free
+    # device memory, up to the workload's width per graph
+    eng = serve.ServeEngine(dgs, budget_bytes=args.serve_budget or None, max_width=spec["width"])
     out = {}
     for frac in (0.5, 0.9):
         reqs = trace(frac * rate_sat, spec["trace_seed"] + int(frac * 10))
@@ -248,7 +250,6 @@ def run_serve(args, spec):
         print(f"[bench] load {frac}: fifo p50/p99 {res['fifo']['p50_ms']:.1f}/"
               f"{res['fifo']['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
         out[f"load_{frac}"] = res
-    eng.close()
     main_res = out["load_0.9"]["served"]
     line = {
         "metric": "BC TEPS (sources x edges / s) at 1 GPU; serving p50/p99 latency",
@@ -256,9 +257,12 @@ def run_serve(args, spec):
         "ms_per_step": main_res["wall_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "served8", "graphs": [g.name for g in gs], "requests": nreq,
-                   "width": spec["width"], "saturation_rate_plain": rate_sat},
+                   "width": spec["width"], "saturation_rate_plain": rate_sat,
+                   "admission": {"budget_bytes": eng.mem.budget, "peak_bytes": eng.mem.peak,
+                                 "rejected": eng.rejected, "steps": eng.steps}},
         "serving": out, "roofline": None, "cpu_baseline": None,
     }
+    eng.close()
     for d in dgs:
         d.close()
     print(json.dumps(line), flush=True)
@@ -350,9 +354,14 @@ def main():
                     help="only run a plain device-to-device copy of BYTES (calibrates the "
                          "HBM byte counters of rocprofv3) and exit")
     ap.add_argument("--tune", action="store_true", help="re-run the autotuner before timing")
+    ap.add_argument("--lanes", type=int, default=-1,
+                    help="batches of one call run at once (1..4; 0 = by size; default: tuned)")
     ap.add_argument("--no-baseline", action="store_true",
                     help="batched form: skip the per-graph comparison")
     ap.add_argument("--requests", type=int, default=400, help="served form: requests per trace")
+    ap.add_argument("--serve-budget", type=int, default=0,
+                    help="served form: device-memory budget of the column servers in bytes "
+                         "(0 = 80%% of the free memory)")
     ap.add_argument("--block-threads", type=int, default=0, help="batched form: threads per workgroup")
     ap.add_argument("--blocks", type=int, default=0, help="batched form: persistent workgroups")
     args = ap.parse_args()
@@ -399,6 +408,8 @@ def main():
     if args.tune or not autotune.apply_plan(dg, g, cache):
         best, _ = autotune.tune_plan(dg, g, src, batch, cache=cache, verbose=True)
         autotune.save_cache(cache)
+    if args.lanes >= 0:
+        dg.set_lanes(args.lanes)
     d_src = torch.as_tensor(src, device="cuda")
     out = torch.empty(g.n, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()

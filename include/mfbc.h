@@ -143,11 +143,27 @@ int mfbc_backward(mfbc_graph *g, const int32_t *d_sources, int32_t nb,
  *                  be smaller.  The result does not depend on it beyond
  *                  rounding.
  *   d_bc[n]        device out, overwritten.
+ *   The batches are independent (Algorithm 3 sums their contributions), so
+ *   up to four of them run at once on separate streams ("lanes", see
+ *   mfbc_set_lanes), each lane with its own workspace; lane 0 uses
+ *   hip_stream, the others library-owned streams ordered after the work
+ *   already on hip_stream.  Lambda is summed in a fixed lane and batch order,
+ *   so repeated calls with the same lane count are bitwise identical.
  * Errors: EINVAL (n_sources < 0, batch < 1, bad source), EOVERFLOW,
  * ENOMEM, EDEVICE.
  */
 int mfbc_bc(mfbc_graph *g, const int32_t *d_sources, int64_t n_sources,
             int32_t batch, double *d_bc, void *hip_stream);
+
+/*
+ * mfbc_set_lanes -- how many batches of one mfbc_bc call run at once (a
+ * tuning knob; results differ only in floating-point summation order).
+ *   lanes  1..4, or 0 (the default): four where a product of one batch is
+ *          too small to fill the device (arcs * column groups <= 2^24), else one.
+ * Each lane holds its own workspace (see the workspace note above).
+ * Errors: EINVAL (lanes outside [0, 4]).
+ */
+int mfbc_set_lanes(mfbc_graph *g, int32_t lanes);
 
 /*
  * mfbc_bc_noalloc -- mfbc_bc for callers that cannot allocate device memory

@@ -1,9 +1,11 @@
 """Autotuner for the work decomposition and launch shapes, measured on the device.
 
-Knobs (none changes results, only speed):
+Knobs (none changes results beyond floating-point summation order, only speed):
   * per graph: the pull-task decomposition of ``mfbc_set_plan`` -- light rows
     grouped into runs of at most ``run_verts`` rows and about ``run_arcs``
-    arcs (hub rows are always cut into slices);
+    arcs (hub rows are always cut into slices) -- and, for graphs whose
+    products are too small to fill the device, the number of batches of one
+    ``mfbc_bc`` call that run at once (``mfbc_set_lanes``);
   * batched form: threads per workgroup and persistent workgroups of
     ``mfbc_bc_many``.
 
@@ -75,11 +77,21 @@ def _time(fn, reps: int) -> float:
     return best
 
 
+LANE_CANDIDATES = (1, 2, 4)
+# lanes are tuned only where one product of a batch is small next to the
+# device (arcs x column groups below this): on large products concurrent
+# batches only share the memory bandwidth, and each kernel's own duration --
+# the denominator of its roofline figure -- would stretch
+LANE_TUNE_MAX = 1 << 25
+
+
 def tune_plan(dg, g, sources, batch: int, reps: int = 2, cache: dict = None, verbose=False):
-    """Pick the run sizes of one graph by timing mfbc_bc on one batch of sources."""
+    """Pick the run sizes of one graph by timing mfbc_bc on one batch of
+    sources, then (small products only) the lane count on up to four batches."""
     import torch
     src = torch.as_tensor(np.ascontiguousarray(sources[:batch], dtype=np.int32), device="cuda")
     res = {}
+    dg.set_lanes(1)
     for ra, rv in PLAN_CANDIDATES:
         dg.set_plan(run_arcs=ra, run_verts=rv)
         res[(ra, rv)] = _time(lambda: dg.bc(src, batch), reps)
@@ -88,18 +100,35 @@ def tune_plan(dg, g, sources, batch: int, reps: int = 2, cache: dict = None, ver
                   file=sys.stderr, flush=True)
     best = min(res, key=res.get)
     dg.set_plan(run_arcs=best[0], run_verts=best[1])
+    lanes = 0
+    ncg = -(-min(batch, len(sources)) // 64)
+    if g.arcs * ncg < LANE_TUNE_MAX:
+        src4 = torch.as_tensor(np.ascontiguousarray(sources[:4 * batch], dtype=np.int32),
+                               device="cuda")
+        lres = {}
+        for L in LANE_CANDIDATES:
+            dg.set_lanes(L)
+            lres[L] = _time(lambda: dg.bc(src4, batch), reps)
+            if verbose:
+                print(f"[tune] {g.name} lanes={L}: {lres[L] * 1e3:.2f} ms", file=sys.stderr, flush=True)
+        lanes = min(lres, key=lres.get)
+    dg.set_lanes(lanes if lanes else 1)
     if cache is not None:
         cache.setdefault("plan", {})[graph_bucket(g)] = {"run_arcs": best[0], "run_verts": best[1],
+                                                         "lanes": lanes if lanes else 1,
                                                          "ms": res[best] * 1e3}
     return best, res
 
 
 def apply_plan(dg, g, cache: dict) -> bool:
-    """Set a graph's plan from the cache (returns False if its bucket is unknown)."""
+    """Set a graph's plan (and lane count) from the cache (returns False if
+    its bucket is unknown)."""
     e = cache.get("plan", {}).get(graph_bucket(g))
     if not e:
         return False
     dg.set_plan(run_arcs=e["run_arcs"], run_verts=e["run_verts"])
+    if "lanes" in e:
+        dg.set_lanes(e["lanes"])
     return True
 
 

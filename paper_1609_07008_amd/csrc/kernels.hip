@@ -145,6 +145,22 @@ __global__ void k_lambda_reduce(const double *lam, int ncg, int n, double *bc,
     bc[v] = t;
 }
 
+// The same over the workspaces of several lanes (fixed lane order).
+struct LanePtrs {
+    const double *lam[kMaxLanes];
+};
+
+__global__ void k_lambda_reduce_lanes(LanePtrs p, int nlanes, int ncg, int n, double *bc,
+                                      const int32_t *perm) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int d = dev_id(perm, v);
+    double t = 0.0;
+    for (int l = 0; l < nlanes; l++)
+        for (int cg = 0; cg < ncg; cg++) t += p.lam[l][(size_t)cg * n + d];
+    bc[v] = t;
+}
+
 // Tile transposes between [cg][v][64] tiles (device numbering) and
 // source-major rows [s][v] (caller numbering), 64 x 64 per block through LDS
 // (padded against bank conflicts).  A block covers 64 consecutive caller
@@ -528,6 +544,15 @@ void launch_lambda_zero(mfbc_graph *g, int ncg, hipStream_t s) {
 
 void launch_lambda_reduce(mfbc_graph *g, int ncg, double *d_bc, hipStream_t s) {
     hipLaunchKernelGGL(k_lambda_reduce, dim3(blocks_for(g->n, 256)), dim3(256), 0, s, g->ws.lam,
+                       ncg, g->n, d_bc, (const int32_t *)g->perm);
+}
+
+void launch_lambda_reduce_lanes(mfbc_graph *const *lanes, int nlanes, int ncg, double *d_bc,
+                                hipStream_t s) {
+    LanePtrs p{};
+    for (int l = 0; l < nlanes && l < kMaxLanes; l++) p.lam[l] = lanes[l]->ws.lam;
+    const mfbc_graph *g = lanes[0];
+    hipLaunchKernelGGL(k_lambda_reduce_lanes, dim3(blocks_for(g->n, 256)), dim3(256), 0, s, p, nlanes,
                        ncg, g->n, d_bc, (const int32_t *)g->perm);
 }
 

@@ -14,6 +14,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -457,7 +458,27 @@ int upload_csr(int32_t n, int64_t arcs, const int64_t *rp, const int32_t *col, c
     return MFBC_OK;
 }
 
+// Release a lane view: its workspace, counters and events (the device graph
+// it shares stays with its owner).
+void free_shadow(mfbc_graph *sh) {
+    for (auto &e : sh->ev) {
+        if (e) (void)hipEventDestroy(e);
+        e = nullptr;
+    }
+    free_workspace(sh->ws);
+    if (sh->h_ctr) (void)hipHostFree(sh->h_ctr);
+    delete sh;
+}
+
 void free_graph_memory(mfbc_graph *g) {
+    for (int i = 0; i < kMaxLanes; i++) {
+        if (g->shadow[i]) free_shadow(g->shadow[i]);
+        g->shadow[i] = nullptr;
+        if (g->lane_stream[i]) (void)hipStreamDestroy(g->lane_stream[i]);
+        g->lane_stream[i] = nullptr;
+    }
+    if (g->lane_start) (void)hipEventDestroy(g->lane_start);
+    g->lane_start = nullptr;
     for (auto &e : g->ev) {
         if (e) (void)hipEventDestroy(e);
         e = nullptr;
@@ -506,6 +527,124 @@ int bc_batches(mfbc_graph *g, const int32_t *d_sources, int64_t n_sources, int32
         g->stats.batches++;
     }
     launch_lambda_reduce(g, ncg, d_bc, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    return MFBC_OK;
+}
+
+// Lanes of one mfbc_bc call: independent batches run at once on separate
+// streams (each batch's products depend only on its own state), which hides
+// the launch and read-back latency of small graphs' products and lets the
+// sparse products of one batch share the device with another batch's.
+int lanes_for(const mfbc_graph *g, int64_t n_batches, int ncg) {
+    int S = g->lanes;
+    // by default only where a product is too small to fill the device
+    if (S <= 0) S = (double)g->arcs * (double)ncg <= (double)(1 << 24) ? kMaxLanes : 1;
+    return (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)S, (int64_t)kMaxLanes, n_batches}));
+}
+
+// Lane i of g (i = 0: g itself), created on first use; a view is refreshed
+// from g on every call (the plan may have changed).
+int lane_graph(mfbc_graph *g, int i, mfbc_graph **out) {
+    if (i == 0) {
+        *out = g;
+        return MFBC_OK;
+    }
+    mfbc_graph *&sh = g->shadow[i];
+    if (!sh) {
+        sh = new (std::nothrow) mfbc_graph();
+        if (!sh) return fail(MFBC_ENOMEM, "host allocation failed");
+        sh->is_shadow = true;
+        if (hipHostMalloc((void **)&sh->h_ctr,
+                          sizeof(unsigned long long) * kCounterRing * 4 * kCounterSlots) != hipSuccess) {
+            sh->h_ctr = nullptr;
+            delete sh;
+            sh = nullptr;
+            return fail(MFBC_ENOMEM, "pinned host allocation failed");
+        }
+    }
+    if (!g->lane_stream[i]) HIP_TRY(hipStreamCreateWithFlags(&g->lane_stream[i], hipStreamNonBlocking));
+    sh->device = g->device;
+    sh->n = g->n;
+    sh->arcs = g->arcs;
+    sh->maxw = g->maxw;
+    sh->weighted = g->weighted;
+    sh->directed = g->directed;
+    sh->out = g->out;
+    sh->in = g->in;
+    sh->plan_out = g->plan_out;
+    sh->plan_in = g->plan_in;
+    sh->mb = g->mb;
+    sh->params = g->params;
+    sh->perm = g->perm;
+    sh->timing = g->timing;
+    if (g->timing && !sh->ev[0])
+        for (auto &e : sh->ev) HIP_TRY(hipEventCreate(&e));
+    *out = sh;
+    return MFBC_OK;
+}
+
+static_assert(sizeof(mfbc_stats) == 14 * sizeof(int64_t) + 9 * sizeof(double),
+              "add_stats walks 14 counters and 9 times / byte counts");
+
+void add_stats(mfbc_stats &a, const mfbc_stats &b) {
+    int64_t *ai = &a.fwd_products;
+    const int64_t *bi = &b.fwd_products;
+    for (int k = 0; k < 14; k++) ai[k] += bi[k];
+    double *ad = &a.fwd_pull_ms;
+    const double *bd = &b.fwd_pull_ms;
+    for (int k = 0; k < 9; k++) ad[k] += bd[k];
+}
+
+// Algorithm 3 with batch b on lane b % S: lane 0 on the caller's stream, the
+// others on their own streams after the caller's prior work; each lane's
+// host loop runs on its own thread; lambda = the lanes' parts, summed in lane
+// order (so a call is deterministic for a given lane count).
+int bc_lanes(mfbc_graph *g, const int32_t *d_sources, int64_t n_sources, int32_t batch, int ncg,
+             int S, double *d_bc, hipStream_t s) {
+    mfbc_graph *lg[kMaxLanes] = {};
+    hipStream_t ls[kMaxLanes] = {};
+    int rc;
+    for (int i = 0; i < S; i++) {
+        if ((rc = lane_graph(g, i, &lg[i]))) return rc;
+        if ((rc = ensure_workspace(lg[i], ncg))) return rc;
+        ls[i] = i == 0 ? s : g->lane_stream[i];
+    }
+    if (!g->lane_start) HIP_TRY(hipEventCreateWithFlags(&g->lane_start, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(g->lane_start, s));
+    for (int i = 1; i < S; i++) HIP_TRY(hipStreamWaitEvent(ls[i], g->lane_start, 0));
+    const int64_t nbat = (n_sources + batch - 1) / batch;
+    int rcs[kMaxLanes] = {};
+    std::string msgs[kMaxLanes];
+    auto lane = [&](int i) {
+        mfbc_graph *x = lg[i];
+        int r = MFBC_OK;
+        if (hipSetDevice(g->device) != hipSuccess) r = fail(MFBC_EDEVICE, "hipSetDevice failed");
+        x->stats = mfbc_stats{};
+        if (!r) launch_lambda_zero(x, ncg, ls[i]);
+        for (int64_t b = i; !r && b < nbat; b += S) {
+            const int64_t b0 = b * batch;
+            const int nb = (int)std::min<int64_t>(batch, n_sources - b0);
+            const int bcg = (nb + kWave - 1) / kWave;
+            launch_set_sources(x, bcg, nb, d_sources + b0, ls[i]);
+            if (!r) r = run_forward(x, bcg, nb, false, nullptr, nullptr, nullptr, 0, nullptr, ls[i]);
+            if (!r) r = run_backward(x, bcg, nb, nullptr, ls[i]);
+            x->stats.batches++;
+        }
+        if (!r && hipStreamSynchronize(ls[i]) != hipSuccess) r = fail(MFBC_EDEVICE, "lane stream failed");
+        rcs[i] = r;
+        if (r) msgs[i] = mfbc_last_error();
+    };
+    std::vector<std::thread> th;
+    for (int i = 1; i < S; i++) th.emplace_back(lane, i);
+    lane(0);
+    for (auto &t : th) t.join();
+    for (int i = 0; i < S; i++)
+        if (rcs[i]) return fail(rcs[i], msgs[i]);
+    launch_lambda_reduce_lanes(lg, S, ncg, d_bc, s);
+    mfbc_stats tot{};
+    for (int i = 0; i < S; i++) add_stats(tot, lg[i]->stats);
+    g->stats = tot;
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
     return MFBC_OK;
@@ -752,8 +891,18 @@ int mfbc_bc(mfbc_graph *g, const int32_t *d_sources, int64_t n_sources, int32_t 
     int rc = check_sources(g, d_sources, n_sources, s);
     if (rc) return rc;
     const int ncg = bc_groups(n_sources, batch);
+    const int S = lanes_for(g, (n_sources + batch - 1) / batch, ncg);
+    if (S > 1) return bc_lanes(g, d_sources, n_sources, batch, ncg, S, d_bc, s);
     if ((rc = ensure_workspace(g, ncg))) return rc;
     return bc_batches(g, d_sources, n_sources, batch, ncg, d_bc, s);
+}
+
+int mfbc_set_lanes(mfbc_graph *g, int32_t lanes) {
+    if (!g) return fail(MFBC_EINVAL, "graph handle is NULL");
+    if (lanes < 0 || lanes > kMaxLanes)
+        return fail(MFBC_EINVAL, "lanes must be in [0, " + std::to_string(kMaxLanes) + "]");
+    g->lanes = lanes;
+    return MFBC_OK;
 }
 
 int mfbc_bc_noalloc(mfbc_graph *g, const int32_t *d_sources, int64_t n_sources, int32_t batch,
@@ -811,7 +960,11 @@ int mfbc_set_plan(mfbc_graph *g, int32_t run_arcs, int32_t run_verts, int32_t he
     if (!rc) rc = upload_plan(g->n, g->h_rp_in.data(), p, g->plan_in);
     if (rc) return rc;
     // the partial buffers are sized by the slot count: regrow on next use
-    if (std::max(g->plan_in.nslots, g->plan_out.nslots) > old_slots) free_workspace(g->ws);
+    if (std::max(g->plan_in.nslots, g->plan_out.nslots) > old_slots) {
+        free_workspace(g->ws);
+        for (auto *sh : g->shadow)
+            if (sh) free_workspace(sh->ws);
+    }
     return MFBC_OK;
 }
 

@@ -29,6 +29,7 @@ constexpr int kCounterRing = 16;         // products whose counters are live at 
 constexpr int kWindow = 8;               // products enqueued per read-back of their counters
                                          // (at most kCounterRing - 1)
 constexpr int kWide = 2;                 // column groups per wave in the forward product
+constexpr int kMaxLanes = 4;             // batches of one mfbc_bc call run concurrently
 
 // A unit of pull work for one wave (and one column group):
 //  * hub < 0: the whole adjacency rows of vertices [v0, v1), arcs [e0, e1);
@@ -121,6 +122,15 @@ struct mfbc_graph {
                                        // between it and its merge, after the merge
     unsigned long long *h_ctr = nullptr;  // pinned host copy of the counter ring
     int servers = 0;                   // live mfbc_server objects on this graph
+    // Lanes: mfbc_bc runs its batches on up to kMaxLanes streams at once, each
+    // with its own workspace.  Lane 0 is the graph itself on the caller's
+    // stream; lane i > 0 is a view (shadow) sharing the device graph and plans,
+    // with its own workspace, counters, events and stream.
+    int lanes = 0;                     // requested lanes (0: chosen by size)
+    mfbc_graph *shadow[mfbc::kMaxLanes] = {};
+    hipStream_t lane_stream[mfbc::kMaxLanes] = {};
+    hipEvent_t lane_start = nullptr;   // recorded on the caller's stream, awaited by lanes
+    bool is_shadow = false;
 };
 
 namespace mfbc {
@@ -140,6 +150,9 @@ void launch_bwd_product(mfbc_graph *g, int ncg, int k, hipStream_t s, hipEvent_t
 void launch_trace_fwd(mfbc_graph *g, int ncg, int nb, int j, uint64_t *d_rows, hipStream_t s);
 void launch_lambda_zero(mfbc_graph *g, int ncg, hipStream_t s);
 void launch_lambda_reduce(mfbc_graph *g, int ncg, double *d_bc, hipStream_t s);
+// bc[v] = the lambda parts of every lane's workspace, summed lane by lane.
+void launch_lambda_reduce_lanes(mfbc_graph *const *lanes, int nlanes, int ncg, double *d_bc,
+                                hipStream_t s);
 void launch_export_forward(mfbc_graph *g, int ncg, int nb, int32_t *d_dist, double *d_sigma,
                            hipStream_t s);
 void launch_import_forward(mfbc_graph *g, int ncg, int nb, const int32_t *d_dist,

@@ -30,6 +30,7 @@ SIGNATURES = {
     "mfbc_backward": ([_P, _P, _I32, _P, _P, _P, _P, _P], ctypes.c_int),
     "mfbc_bc": ([_P, _P, _I64, _I32, _P, _P], ctypes.c_int),
     "mfbc_bc_noalloc": ([_P, _P, _I64, _I32, _P, _P], ctypes.c_int),
+    "mfbc_set_lanes": ([_P, _I32], ctypes.c_int),
     "mfbc_forward_trace": ([_P, _P, _I32, _P, _P, _P, _I32, _P, _P, _P, _P], ctypes.c_int),
     "mfbc_backward_trace": ([_P, _P, _I32, _P, _P, _P, _P, _P, _P], ctypes.c_int),
     "mfbc_get_stats": ([_P, _P], ctypes.c_int),
@@ -256,6 +257,10 @@ class DeviceGraph:
     def set_plan(self, run_arcs: int = 0, run_verts: int = 0, heavy: int = 0, slice: int = 0):
         """Work decomposition of the products (0 = size-based default)."""
         _check(load_library().mfbc_set_plan(self.handle, run_arcs, run_verts, heavy, slice))
+
+    def set_lanes(self, lanes: int = 0):
+        """Batches of one bc() call run at once (1..4; 0 = by graph size)."""
+        _check(load_library().mfbc_set_lanes(self.handle, int(lanes)))
 
     def enable_timing(self, on: bool = True):
         """Time every product kernel with HIP events on the call's stream."""

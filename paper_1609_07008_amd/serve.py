@@ -22,7 +22,7 @@ import ctypes
 import time
 from collections import deque
 from dataclasses import dataclass, field
-from typing import List, Optional
+from typing import List, Optional, Tuple
 
 import numpy as np
 
@@ -76,6 +76,7 @@ class ColumnServer:
         _m._check(_lib().mfbc_server_create(dg.handle, width, ctypes.byref(h)))
         self.h = h
         self.launched = False
+        self.owned = 0             # columns admitted and not yet harvested
         self._done = np.zeros(width, dtype=np.int32)
 
     def _s(self):
@@ -168,31 +169,144 @@ class Request:
     placed: int = 0
     harvested: int = 0
     done: float = -1.0
+    error: Optional[str] = None    # set when the request was rejected (nothing computed)
     cols: dict = field(default_factory=dict)   # column -> index of the source in `sources`
 
 
-class ServeEngine:
-    """Resident graphs, each with a column server, and the request loop."""
+class MemoryBudget:
+    """Admission of column servers by device-memory footprint (host logic only).
 
-    def __init__(self, dgraphs, widths):
+    ``footprint(g, w)`` gives the bytes a server of ``w`` columns (a multiple
+    of 64) on graph ``g`` allocates.  ``acquire`` decides the width of a new
+    server for ``g`` given the columns its waiting sources need and which other
+    servers are idle, keeping the sum of live footprints within ``budget``.
+    """
+
+    def __init__(self, budget: int, footprint, max_width: int = 256):
+        if max_width < 64 or max_width % 64:
+            raise ValueError("max_width must be a positive multiple of 64")
+        self.budget = int(budget)
+        self.footprint = footprint
+        self.max_width = max_width
+        self.live = {}            # graph -> (width, bytes)
+        self.last_use = {}        # graph -> logical time of the last step
+        self.clock = 0
+        self.peak = 0             # largest sum of live footprints seen
+
+    @property
+    def used(self) -> int:
+        return sum(b for _, b in self.live.values())
+
+    def fits_ever(self, g) -> bool:
+        """Whether a 64-column server of g fits the whole budget."""
+        return self.footprint(g, 64) <= self.budget
+
+    def touch(self, g):
+        self.clock += 1
+        self.last_use[g] = self.clock
+
+    def acquire(self, g, want_cols: int, idle) -> Tuple[Optional[int], list]:
+        """Width for a new server of g (None: wait) and the idle servers to
+        release first.  ``idle(h)`` tells whether graph h's server holds no
+        column in use."""
+        assert g not in self.live
+        want = min(self.max_width, max(64, -(-int(want_cols) // 64) * 64))
+        free = self.budget - self.used
+        widths = list(range(want, 0, -64))
+        for w in widths:                       # widest that fits without releasing anything
+            if self.footprint(g, w) <= free:
+                return w, []
+        victims = sorted((h for h in self.live if h != g and idle(h)),
+                         key=lambda h: self.last_use.get(h, 0))
+        for w in widths:                       # then release idle servers, oldest first
+            need = self.footprint(g, w)
+            f, ev = free, []
+            for h in victims:
+                if f >= need:
+                    break
+                ev.append(h)
+                f += self.live[h][1]
+            if f >= need:
+                return w, ev
+        return None, []
+
+    def add(self, g, width: int):
+        self.live[g] = (width, self.footprint(g, width))
+        self.touch(g)
+        self.peak = max(self.peak, self.used)
+
+    def remove(self, g):
+        self.live.pop(g, None)
+
+
+def default_budget(fraction: float = 0.8) -> int:
+    """A fraction of the device memory free now."""
+    import torch
+    return int(torch.cuda.mem_get_info()[0] * fraction)
+
+
+class ServeEngine:
+    """Resident graphs, column servers admitted by memory footprint, and the
+    request loop.
+
+    ``widths``: one fixed server per graph of the given widths (created up
+    front; their footprints must fit the budget).  Without it, servers are
+    created on demand by ``MemoryBudget`` (``budget_bytes``, default 80% of
+    the free device memory; widths up to ``max_width``)."""
+
+    def __init__(self, dgraphs, widths=None, budget_bytes: Optional[int] = None,
+                 max_width: int = 256, server_factory=None, footprint_fn=None,
+                 device: str = "cuda"):
+        """``server_factory(dgraph, width)`` and ``footprint_fn(dgraph, width)``
+        default to ColumnServer and mfbc_server_footprint (other executors
+        can be plugged in, e.g. to test the scheduling on the CPU);
+        ``device``: where request results are allocated."""
         import torch
         self.torch = torch
+        self.device = device
         self.dgraphs = list(dgraphs)
-        self.servers = [ColumnServer(dg, w) for dg, w in zip(self.dgraphs, widths)]
+        self.factory = server_factory or ColumnServer
+        fp = footprint_fn or footprint
+        budget = (default_budget() if budget_bytes is None else int(budget_bytes))
+        self.mem = MemoryBudget(budget, lambda gi, w: fp(self.dgraphs[gi], w), max_width)
+        self.fixed = widths is not None
+        self.servers = [None] * len(self.dgraphs)
         self.steps = 0
+        self.rejected = 0
+        if self.fixed:
+            need = sum(fp(dg, w) for dg, w in zip(self.dgraphs, widths))
+            if need > self.mem.budget:
+                raise _m.MfbcError(_m.MFBC_ENOMEM, f"servers need {need} bytes, budget {budget}")
+            for gi, w in enumerate(widths):
+                self._open(gi, w)
+
+    def _open(self, gi: int, width: int):
+        self.servers[gi] = self.factory(self.dgraphs[gi], width)
+        self.mem.add(gi, width)
+
+    def _close(self, gi: int):
+        if self.servers[gi] is not None:
+            self.servers[gi].close()
+            self.servers[gi] = None
+        self.mem.remove(gi)
 
     def close(self):
-        for s in self.servers:
-            s.close()
+        for gi in range(len(self.servers)):
+            self._close(gi)
+
+    def _idle(self, gi: int) -> bool:
+        s = self.servers[gi]
+        return s is not None and not s.launched and s.active_columns() == 0 and not s.owned
 
     def _alloc(self, r: Request):
         t = self.torch
         dg = self.dgraphs[r.graph]
         if r.kind == "bc":
-            r.out = t.zeros(dg.n, dtype=t.float64, device="cuda")
+            r.out = t.zeros(dg.n, dtype=t.float64, device=self.device)
         else:
-            r.out = t.zeros((r.sources.size, r.targets.size), dtype=t.float64, device="cuda")
-            r._targets = t.as_tensor(np.ascontiguousarray(r.targets, dtype=np.int32), device="cuda")
+            r.out = t.zeros((r.sources.size, r.targets.size), dtype=t.float64, device=self.device)
+            r._targets = t.as_tensor(np.ascontiguousarray(r.targets, dtype=np.int32),
+                                     device=self.device)
 
     def run(self, requests: List[Request], realtime: bool = True, on_step=None):
         """Serve `requests` (arrival times in seconds); returns them with `done` set.
@@ -200,30 +314,45 @@ class ServeEngine:
         Each graph's server advances on its own: whenever its step has
         completed, finished columns are harvested, queued sources take the
         free columns and the next step is launched -- a small graph never
-        waits for a step of a large one.
+        waits for a step of a large one.  A graph without a server gets one
+        when the memory budget allows (see MemoryBudget); a request whose
+        graph cannot fit a server within the whole budget completes at once
+        with ``error`` set and no result.
         """
         t = self.torch
         pending = sorted(requests, key=lambda r: r.arrival)
         nxt = 0
-        queues = [deque() for _ in self.servers]
-        owner = [dict() for _ in self.servers]           # column -> request
+        G = len(self.dgraphs)
+        queues = [deque() for _ in range(G)]
+        owner = [dict() for _ in range(G)]           # column -> request
         left = len(pending)
-        t.cuda.synchronize()
+
+        if self.device == "cuda":
+            t.cuda.synchronize()
         t0 = time.perf_counter()
         while left:
             now = time.perf_counter() - t0 if realtime else float("inf")
             while nxt < len(pending) and pending[nxt].arrival <= now:
                 r = pending[nxt]
+                nxt += 1
+                if r.sources.size and not self.fixed and not self.mem.fits_ever(r.graph):
+                    r.error = (f"ENOMEM: a 64-column server of graph {r.graph} needs "
+                               f"{self.mem.footprint(r.graph, 64)} bytes, the budget is "
+                               f"{self.mem.budget}")
+                    r.done = time.perf_counter() - t0
+                    self.rejected += 1
+                    left -= 1
+                    continue
                 self._alloc(r)
                 if r.sources.size == 0:          # nothing to compute: the zero result
                     r.done = time.perf_counter() - t0
                     left -= 1
                 else:
                     queues[r.graph].append(r)
-                nxt += 1
             busy = False
-            for gi, srv in enumerate(self.servers):
-                if srv.launched:
+            for gi in range(G):
+                srv = self.servers[gi]
+                if srv is not None and srv.launched:
                     if not srv.ready():
                         busy = True
                         continue
@@ -231,6 +360,24 @@ class ServeEngine:
                     if done.size:
                         left -= self._harvest(srv, gi, done, owner, t0)
                 q = queues[gi]
+                if q and srv is None:
+                    want = sum(r.sources.size - r.placed for r in q)
+                    head = q[0].arrival
+
+                    def evictable(h, head=head):
+                        # an idle server may go if its graph has nothing waiting
+                        # that arrived before this graph's oldest request
+                        return self._idle(h) and (not queues[h] or queues[h][0].arrival > head)
+
+                    width, evict = self.mem.acquire(gi, want, evictable)
+                    if width is None:
+                        continue                 # waits until memory frees up
+                    for h in evict:
+                        self._close(h)
+                    self._open(gi, width)
+                    srv = self.servers[gi]
+                if srv is None:
+                    continue
                 free = srv.free_columns()
                 while q and free:
                     r = q[0]
@@ -240,12 +387,14 @@ class ServeEngine:
                         owner[gi][int(c)] = r
                         r.cols[int(c)] = r.placed + j
                     r.placed += k
+                    srv.owned += k
                     free -= k
                     if r.placed == r.sources.size:
                         q.popleft()
                 if srv.active_columns() > 0:
                     srv.step_launch()
                     self.steps += 1
+                    self.mem.touch(gi)
                     busy = True
             if on_step is not None:
                 on_step(self)
@@ -261,6 +410,7 @@ class ServeEngine:
         for c in done:
             r = owner[gi].pop(int(c))
             by_req.setdefault(id(r), (r, []))[1].append(int(c))
+        srv.owned -= len(done)
         bc_cols, bc_dest = [], []
         for r, cols in by_req.values():
             if r.kind == "bc":

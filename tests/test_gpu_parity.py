@@ -337,3 +337,34 @@ def test_workspace_enomem_is_reported_and_recoverable(torch, mfbc):
     ref = oracle.brandes(g, s64.cpu().numpy(), per_source=False)["lambda"]
     rel_close(lam, ref, DELTA_TOL, "lambda after ENOMEM")
     dg.close()
+
+
+@pytest.mark.parametrize("name", ["er1024_w100", "rmat11_w255", "er600_unw", "path300", "hubby"])
+def test_lanes_give_the_oracle_lambda(torch, mfbc, dgraphs, name):
+    """Batches of one call run on 1..4 lanes (streams with their own
+    workspaces): every lane count and a ragged last batch give the oracle's
+    lambda, and a repeated call with the same lane count is bitwise equal."""
+    if name == "hubby":
+        g = gg.star_graph(3000)
+        dg = mfbc.DeviceGraph(g)
+    else:
+        g, dg = GRAPHS[name], dgraphs[name]
+    src = np.arange(g.n, dtype=np.int32) if g.n <= 1100 else pick(g, 700, 3)
+    ref = oracle.brandes(g, src, per_source=False)["lambda"]
+    for lanes in (1, 2, 3, 4):
+        dg.set_lanes(lanes)
+        for batch in (64, 150):
+            print(f"[lanes] {name} lanes={lanes} batch={batch}", flush=True)
+            lam = dg.bc(src, batch).cpu().numpy()
+            rel_close(lam, ref, DELTA_TOL, f"lanes={lanes} batch={batch}")
+        a = dg.bc(src, 64).cpu().numpy()
+        b = dg.bc(src, 64).cpu().numpy()
+        assert np.array_equal(a, b), f"lanes={lanes}: repeated call differs"
+    st = dg.stats()
+    assert st["batches"] == (src.size + 63) // 64
+    dg.set_lanes(0)
+    with pytest.raises(mfbc.MfbcError) as e:
+        dg.set_lanes(5)
+    assert e.value.code == mfbc.MFBC_EINVAL
+    if name == "hubby":
+        dg.close()

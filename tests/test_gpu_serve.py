@@ -163,3 +163,98 @@ def test_empty_requests_complete(env):
     rel_close(reqs[2].out.cpu().numpy(),
               oracle.brandes(graphs[1], reqs[2].sources, per_source=False)["lambda"], 1e-10)
     eng.close()
+
+
+def test_set_plan_refused_while_a_server_is_attached(env):
+    t, mfbc, serve, graphs, dgs = env
+    g = gg.er_graph(200, 5, 41, (1, 9))
+    dg = mfbc.DeviceGraph(g)
+    s = serve.ColumnServer(dg, 64)
+    with pytest.raises(mfbc.MfbcError) as e:
+        dg.set_plan(heavy=4, slice=2)                 # would need more hub slots than s holds
+    assert e.value.code == mfbc.MFBC_EINVAL
+    s.close()
+    dg.set_plan(heavy=4, slice=2)                     # fine once the server is gone
+    dg.close()
+
+
+def test_served_hub_rows_alone_and_in_the_mix(env):
+    """Rows cut into slices (a star and plans with tiny hub thresholds) run
+    the served form's hub merges; every request against the oracle, and
+    alone == in the mix."""
+    t, mfbc, serve, graphs, dgs = env
+    gs = [gg.star_graph(3000), gg.rmat_graph(10, 8, 21, wrange=(1, 255))]
+    ds = [mfbc.DeviceGraph(g) for g in gs]
+    ds[1].set_plan(run_arcs=64, run_verts=8, heavy=16, slice=8)
+    reqs = serve.make_requests(gs, 16, rate=1e9, seed=17, smin=3, smax=130)
+    eng = serve.ServeEngine(ds, [128, 192])
+    eng.run(reqs, realtime=False)
+    for r in reqs:
+        rel_close(r.out.cpu().numpy(), reference(gs, r), 1e-10, f"request {r.rid} ({r.kind})")
+    for r in reqs[:6]:
+        alone = serve.Request(r.rid, r.graph, r.kind, r.sources, r.targets, 0.0)
+        eng.run([alone], realtime=False)
+        rel_close(alone.out.cpu().numpy(), r.out.cpu().numpy(), 1e-12, f"alone vs mix {r.rid}")
+    eng.close()
+    for d in ds:
+        d.close()
+
+
+def test_served_admission_by_memory_budget(env):
+    """A budget that holds about one server at a time: requests on three
+    graphs wait for memory, servers are released and created as they go, the
+    live footprint never exceeds the budget, every result matches the oracle;
+    a graph whose smallest server exceeds the budget is rejected (ENOMEM)."""
+    t, mfbc, serve, graphs, dgs = env
+    fps = [serve.footprint(d, 64) for d in dgs]
+    big = gg.rmat_graph(14, 16, 44, wrange=(1, 255))
+    dbig = mfbc.DeviceGraph(big)
+    budget = max(fps) + min(fps) // 2
+    assert serve.footprint(dbig, 64) > budget
+    allg = graphs + [big]
+    reqs = serve.make_requests(graphs, 18, rate=1e9, seed=23, smin=3, smax=100)
+    reqs.append(serve.Request(99, 3, "bc", gg.pick_sources(big, 10, 1), None, 0.0))
+    peak = []
+    eng = serve.ServeEngine(dgs + [dbig], budget_bytes=budget, max_width=128)
+    eng.run(reqs, realtime=False, on_step=lambda e: peak.append(e.mem.used))
+    assert max(peak) <= budget and eng.mem.peak <= budget
+    for r in reqs:
+        if r.graph == 3:
+            assert r.error and r.error.startswith("ENOMEM")
+            continue
+        assert r.error is None
+        rel_close(r.out.cpu().numpy(), reference(allg, r), 1e-10, f"request {r.rid} ({r.kind})")
+    assert eng.rejected == 1
+    eng.close()
+    dbig.close()
+
+
+def test_served_at_workload_sizes(env):
+    """Resident weighted R-MAT graphs of the served workload's scales 14..17
+    (edge factor 16, weights 1..255; their hub rows are split) plus the
+    scale-20 graph with small requests, servers of 256 columns: every request
+    against the oracle, and a few alone == in the mix."""
+    import time
+    t, mfbc, serve, graphs, dgs = env
+    scales = (14, 15, 16, 17, 20)
+    gs = [gg.rmat_graph(sc, 16, 2000 + i, wrange=(1, 255)) for i, sc in enumerate(scales[:-1])]
+    gs.append(gg.rmat_graph(20, 16, 2006, wrange=(1, 255)))
+    ds = [mfbc.DeviceGraph(g) for g in gs]
+    reqs = serve.make_requests(gs[:-1], 20, rate=1e9, seed=2101, smin=16, smax=300)
+    for i, k in enumerate((16, 40)):
+        reqs.append(serve.Request(100 + i, 4, "bc" if i == 0 else "dep",
+                                  gg.pick_sources(gs[4], k, 7 + i),
+                                  None if i == 0 else np.arange(0, 64, dtype=np.int32) * 997, 0.0))
+    t0 = time.perf_counter()
+    eng = serve.ServeEngine(ds, [256] * len(ds))
+    eng.run(reqs, realtime=False)
+    print(f"[serve] {len(reqs)} requests served in {time.perf_counter() - t0:.1f}s", flush=True)
+    for r in reqs:
+        rel_close(r.out.cpu().numpy(), reference(gs, r), 1e-10, f"request {r.rid} ({r.kind})")
+    for r in reqs[:3] + reqs[-1:]:
+        alone = serve.Request(r.rid, r.graph, r.kind, r.sources, r.targets, 0.0)
+        eng.run([alone], realtime=False)
+        rel_close(alone.out.cpu().numpy(), r.out.cpu().numpy(), 1e-12, f"alone vs mix {r.rid}")
+    eng.close()
+    for d in ds:
+        d.close()

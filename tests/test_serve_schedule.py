@@ -1,0 +1,172 @@
+"""Served-form scheduling on the CPU (no GPU): admission of column servers by
+memory footprint (MemoryBudget) and the request loop of ServeEngine driven
+by a fake executor whose columns finish after a known number of steps.
+
+Checked: the live servers' footprints never exceed the budget; widths shrink
+to what fits; idle servers are released oldest first, busy ones never;
+requests wait while memory is taken and complete once it frees up; requests
+whose graph cannot fit 64 columns in the whole budget are rejected; every
+request's result is assembled from exactly its own columns."""
+from dataclasses import dataclass
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_1609_07008_amd.serve import MemoryBudget, Request, ServeEngine  # noqa: E402
+
+
+def fp_linear(base, per_col):
+    return lambda g, w: base[g] + per_col[g] * w
+
+
+def test_widest_width_that_fits():
+    mem = MemoryBudget(1000, fp_linear([100, 100], [2, 2]), max_width=256)
+    assert mem.acquire(0, 1000, lambda h: False) == (256, [])     # 100 + 512 fits
+    mem.add(0, 256)
+    assert mem.used == 612
+    # 388 left: 192 columns take 484, 128 take 356
+    assert mem.acquire(1, 300, lambda h: False) == (128, [])
+    assert mem.acquire(1, 10, lambda h: False) == (64, [])        # as wide as needed only
+
+
+def test_waits_while_busy_and_releases_idle_oldest_first():
+    fp = fp_linear([0, 0, 0], [1, 1, 1])
+    mem = MemoryBudget(256, fp, max_width=128)
+    mem.add(0, 128)
+    mem.add(1, 128)
+    assert mem.acquire(2, 64, lambda h: False) == (None, [])      # everything busy: wait
+    mem.touch(0)                                                  # graph 1 is now the oldest
+    width, evict = mem.acquire(2, 64, lambda h: True)
+    assert (width, evict) == (64, [1])
+    width, evict = mem.acquire(2, 256, lambda h: True)            # needs both released
+    assert width == 128 and evict == [1]
+    width, evict = mem.acquire(2, 256, lambda h: h == 0)          # only graph 0 is idle
+    assert width == 128 and evict == [0]
+
+
+def test_graph_that_never_fits():
+    mem = MemoryBudget(100, fp_linear([50, 10], [1, 1]))
+    assert not mem.fits_ever(0)                                   # 50 + 64 > 100
+    assert mem.fits_ever(1)
+
+
+@dataclass
+class FakeGraph:
+    n: int
+
+
+class FakeServer:
+    """Columns finish `steps_for(source)` steps after admission; harvest
+    adds one to dest[v] for v = source (bc) or writes 1 at target 0 (dep)."""
+
+    live = []
+
+    def __init__(self, dg, width):
+        self.dg, self.width = dg, width
+        self.rem = np.full(width, -1)
+        self.src = np.full(width, -1)
+        self.launched = False
+        self.owned = 0
+        self.ready_after = 0
+        self.log = FakeServer.live
+        self.log.append(self)
+        self.closed = False
+
+    @staticmethod
+    def steps_for(s):
+        return 2 + int(s) % 5
+
+    def free_columns(self):
+        return int((self.rem < 0).sum())
+
+    def active_columns(self):
+        return int((self.rem > 0).sum())
+
+    def admit(self, sources):
+        free = np.flatnonzero(self.rem < 0)[:len(sources)]
+        assert free.size == len(sources)
+        self.rem[free] = [self.steps_for(s) for s in sources]
+        self.src[free] = sources
+        return free.astype(np.int32)
+
+    def step_launch(self):
+        assert not self.launched
+        self.launched = True
+        self.ready_after = 1           # one poll of "not ready" before each step completes
+
+    def ready(self):
+        if self.ready_after:
+            self.ready_after -= 1
+            return False
+        return True
+
+    def step_finish(self):
+        self.launched = False
+        act = self.rem > 0
+        self.rem[act] -= 1
+        done = np.flatnonzero(act & (self.rem == 0))
+        return done.astype(np.int32)
+
+    def harvest_bc(self, cols, dests):
+        for c, d in zip(cols, dests):
+            d[int(self.src[c])] += 1.0
+            self.rem[c] = -1
+
+    def harvest_dep(self, cols, targets, outs):
+        for c, o in zip(cols, outs):
+            o[0] = float(self.src[c])
+            self.rem[c] = -1
+
+    def close(self):
+        self.closed = True
+
+
+def test_engine_respects_budget_and_completes_every_request():
+    FakeServer.live.clear()
+    graphs = [FakeGraph(50), FakeGraph(60), FakeGraph(40), FakeGraph(70)]
+    per_col = [1, 2, 3, 100]                         # graph 3 never fits
+    fp = lambda dg, w: 10 + per_col[graphs.index(dg)] * w   # noqa: E731
+    budget = 10 + 3 * 192 + 10 + 2 * 64              # room for about two servers at a time
+    peak = []
+    eng = ServeEngine(graphs, budget_bytes=budget, max_width=256, server_factory=FakeServer,
+                      footprint_fn=fp, device="cpu")
+    rng = np.random.default_rng(1)
+    reqs = []
+    for i in range(60):
+        gi = int(rng.integers(0, 4))
+        k = int(rng.integers(1, 150))
+        src = rng.integers(0, graphs[gi].n, size=k).astype(np.int32)
+        kind = "bc" if i % 3 else "dep"
+        tg = np.array([0, 1], dtype=np.int32) if kind == "dep" else None
+        reqs.append(Request(i, gi, kind, src, tg, 0.0))
+    eng.run(reqs, realtime=False, on_step=lambda e: peak.append(e.mem.used))
+    assert max(peak) <= budget and eng.mem.peak <= budget
+    for r in reqs:
+        assert r.done >= 0
+        if r.graph == 3:
+            assert r.error and r.error.startswith("ENOMEM") and r.out is None
+            continue
+        assert r.error is None
+        if r.kind == "bc":
+            want = np.bincount(r.sources, minlength=graphs[r.graph].n).astype(float)
+            assert np.array_equal(r.out.numpy(), want), r.rid
+        else:
+            assert np.array_equal(r.out[:, 0].numpy(), r.sources.astype(float)), r.rid
+    assert eng.rejected == sum(r.graph == 3 for r in reqs)
+    # servers were released to let other graphs in, and never while busy
+    assert any(s.closed for s in FakeServer.live)
+    eng.close()
+
+
+def test_fixed_widths_must_fit_the_budget():
+    graphs = [FakeGraph(10), FakeGraph(10)]
+    from paper_1609_07008_amd import mfbc
+    with pytest.raises(mfbc.MfbcError) as e:
+        ServeEngine(graphs, widths=[64, 64], budget_bytes=100, server_factory=FakeServer,
+                    footprint_fn=lambda dg, w: w, device="cpu")
+    assert e.value.code == mfbc.MFBC_ENOMEM
+    eng = ServeEngine(graphs, widths=[64, 64], budget_bytes=128, server_factory=FakeServer,
+                      footprint_fn=lambda dg, w: w, device="cpu")
+    eng.close()
