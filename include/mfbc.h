@@ -340,8 +340,10 @@ int mfbc_bc_many(int32_t n_graphs, mfbc_graph *const *graphs,
  *
  * A server owns `width` source columns (a positive multiple of 64) of one
  * graph; each column holds one source and moves through the phases forward
- * loop, counting product, backward loop, done.  A step advances every active
- * column by one product of its phase; a column depends only on its own
+ * loop, counting product, backward loop, done.  A step runs the counting
+ * product of the columns whose forward loop has ended, then R rounds of one
+ * forward and one backward product (mfbc_server_set_rounds), advancing every
+ * active column by up to R products of its phase; a column depends only on its own
  * column of the frontier (the products act column by column, Section 3), so
  * new sources start between steps while other columns are mid-loop.  The
  * unit of admission is a group of 64 columns: a group takes new sources
@@ -374,6 +376,11 @@ int mfbc_server_active_columns(const mfbc_server *s);
 int mfbc_server_admit(mfbc_server *s, const int32_t *h_sources, int32_t count,
                       int32_t *h_columns, void *hip_stream);
 
+/* Rounds of products per step: 1..8, or 0 (the default, 8).  More rounds:
+ * fewer round trips to the host per product; fewer: new sources admitted
+ * sooner.  EINVAL while a step is in flight or outside [0, 8]. */
+int mfbc_server_set_rounds(mfbc_server *s, int32_t rounds);
+
 /* Enqueue one step on the stream (does not wait). */
 int mfbc_server_step_launch(mfbc_server *s, void *hip_stream);
 
@@ -391,7 +398,8 @@ int mfbc_server_step_finish(mfbc_server *s, int32_t *h_done, int32_t *h_ndone,
 /* Harvest finished columns into lambda-style sums:
  * d_dest[i][v] += delta(source of h_columns[i], v) for every v (device
  * buffers of n doubles; several columns may share one destination, which is
- * then updated in list order).  The columns become free. */
+ * then updated column group by column group, ascending, and in list order
+ * within a group).  The columns become free. */
 int mfbc_server_harvest_bc(mfbc_server *s, const int32_t *h_columns, int32_t count,
                            double *const *d_dest, void *hip_stream);
 

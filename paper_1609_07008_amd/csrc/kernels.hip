@@ -480,9 +480,9 @@ hipError_t launch_bwd_count(mfbc_graph *g, int ncg, hipStream_t s, hipEvent_t *e
                            0, s, (const int32_t *)ws.tdist, (int2 *)ws.tau2, plane, ncg, npairs);
         const int grid = blocks_for((size_t)a.ntasks * npairs, kWavesPerBlock, 0x7fffffff);
         switch (arc_mode(g->out)) {
-            case 0: hipLaunchKernelGGL(k_bwd_count_w<0>, dim3(grid), dim3(kBlock), 0, s, a); break;
-            case 1: hipLaunchKernelGGL(k_bwd_count_w<1>, dim3(grid), dim3(kBlock), 0, s, a); break;
-            default: hipLaunchKernelGGL(k_bwd_count_w<2>, dim3(grid), dim3(kBlock), 0, s, a); break;
+            case 0: hipLaunchKernelGGL((k_bwd_count_w<0, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
+            case 1: hipLaunchKernelGGL((k_bwd_count_w<1, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
+            default: hipLaunchKernelGGL((k_bwd_count_w<2, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
         }
     } else {
         const size_t waves = (size_t)a.ntasks * ncg;
@@ -508,15 +508,15 @@ void launch_bwd_product(mfbc_graph *g, int ncg, int k, hipStream_t s, hipEvent_t
         if (ev) (void)hipEventRecord(ev[0], s);
         const int grid = blocks_for((size_t)a.ntasks * a.nwide, kWavesPerBlock, 0x7fffffff);
         switch (arc_mode(g->out)) {
-            case 0: hipLaunchKernelGGL(k_bwd_pull_w<0>, dim3(grid), dim3(kBlock), 0, s, a); break;
-            case 1: hipLaunchKernelGGL(k_bwd_pull_w<1>, dim3(grid), dim3(kBlock), 0, s, a); break;
-            default: hipLaunchKernelGGL(k_bwd_pull_w<2>, dim3(grid), dim3(kBlock), 0, s, a); break;
+            case 0: hipLaunchKernelGGL((k_bwd_pull_w<0, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
+            case 1: hipLaunchKernelGGL((k_bwd_pull_w<1, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
+            default: hipLaunchKernelGGL((k_bwd_pull_w<2, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
         }
         if (ev) (void)hipEventRecord(ev[1], s);
         int mgrid = blocks_for((size_t)a.nhubs * a.nwide, kWavesPerBlock, 0x7fffffff);
         const int cgrid = blocks_for((size_t)a.nwords, kBlock, 1024);
         if (cgrid > mgrid) mgrid = cgrid;
-        hipLaunchKernelGGL(k_bwd_merge_w<0>, dim3(mgrid), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL(k_bwd_merge_w<false>, dim3(mgrid), dim3(kBlock), 0, s, a);
         if (ev) (void)hipEventRecord(ev[2], s);
         return;
     }

@@ -831,23 +831,28 @@ __device__ __forceinline__ void count_hub(const BwdArgs &a, int cg, int h, unsig
 // leaves and DAG masks, written in the layouts the backward products of the
 // batch read (fb_index, ab_plane).  A padding group (odd group count) counts
 // nothing and writes nothing.
-template <int AM>
+// CM (served form): count only the lanes of a.cmask and record the columns
+// that produced entries in a.colmask.
+template <int AM, bool CM>
 __device__ __forceinline__ void count_task_w(const BwdArgs &a, int q, int t, unsigned long long &produced) {
     const int lane = threadIdx.x & (kWave - 1);
     const int cg0 = 2 * q;
-    const bool has1 = cg0 + 1 < a.ncg;
+    const bool has1 = cg0 + 1 < a.ncg_all;
     const Task *tp = a.tasks + t;
     const int v0 = uni(tp->v0), v1 = uni(tp->v1), hub = uni(tp->hub), part = uni(tp->part);
     const int64_t e0 = uni64(tp->e0), e1 = uni64(tp->e1);
     const size_t n = (size_t)a.n;
     const int2 *T2 = (const int2 *)a.tau2 + (size_t)q * n * kWave;
+    // served form: lanes outside the counting mask skip their loads
+    const bool in0 = !CM || ((a.cmask[cg0] >> lane) & 1ull);
+    const bool in1 = has1 && (!CM || ((a.cmask[cg0 + 1] >> lane) & 1ull));
     uint64_t *Dg0 = a.dag + (size_t)cg0 * a.narcs;
     uint64_t *Dg1 = Dg0 + a.narcs;
-    uint64_t act0 = 0, act1 = 0;
+    uint64_t act0 = 0, act1 = 0, any0 = 0, any1 = 0;
     const int xa = v0, xb = hub >= 0 ? v0 + 1 : v1;
     for (int x = xa; x < xb; x++) {
         const int2 dx = T2[(size_t)x * kWave + lane];
-        const bool r0 = dx.x != kInf, r1 = has1 && dx.y != kInf;
+        const bool r0 = in0 && dx.x != kInf, r1 = in1 && dx.y != kInf;
         const int64_t ea = hub >= 0 ? e0 : a.rp[x];
         const int64_t eb = hub >= 0 ? e1 : a.rp[x + 1];
         int c0 = 0, c1 = 0;
@@ -902,10 +907,12 @@ __device__ __forceinline__ void count_task_w(const BwdArgs &a, int q, int t, uns
         } else {
             const uint64_t b0 = count_finalize(a, (size_t)cg0 * n, cg0, x, dx.x, c0, lane);
             produced += __popcll(b0);
+            if (CM) any0 |= b0;
             if (b0) act0 |= 1ull << (x - v0);
             if (has1) {
                 const uint64_t b1 = count_finalize(a, (size_t)(cg0 + 1) * n, cg0 + 1, x, dx.y, c1, lane);
                 produced += __popcll(b1);
+                if (CM) any1 |= b1;
                 if (b1) act1 |= 1ull << (x - v0);
             }
         }
@@ -917,6 +924,10 @@ __device__ __forceinline__ void count_task_w(const BwdArgs &a, int q, int t, uns
             if (act0) or_run_bits(a.abits_n + (size_t)cg0 * a.nwords, v0, act0);
             if (act1) or_run_bits(a.abits_n + (size_t)(cg0 + 1) * a.nwords, v0, act1);
         }
+    }
+    if (CM) {
+        flush_colmask(a.colmask, a.ncg_all, cg0, any0);
+        if (has1) flush_colmask(a.colmask, a.ncg_all, cg0 + 1, any1);
     }
 }
 
@@ -1086,7 +1097,7 @@ __device__ __forceinline__ void bwd_hub(const BwdArgs &a, int cg, int h, unsigne
 // each group then gathers q(s, y) only for the lanes its DAG mask and the
 // head's frontier mask share.  A padding group (odd group count) has no
 // state and counts no arc.
-template <int AM>
+template <int AM, bool CM>
 __device__ __forceinline__ void bwd_task_w(const BwdArgs &a, int q, int t, unsigned long long &produced,
                                            unsigned long long &outs) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -1094,7 +1105,7 @@ __device__ __forceinline__ void bwd_task_w(const BwdArgs &a, int q, int t, unsig
     const int v0 = uni(tp->v0), v1 = uni(tp->v1), hub = uni(tp->hub), part = uni(tp->part);
     const int64_t e0 = uni64(tp->e0), e1 = uni64(tp->e1);
     const int cg0 = 2 * q;
-    const bool has1 = cg0 + 1 < a.ncg;
+    const bool has1 = cg0 + 1 < a.ncg_all;
     const size_t n = (size_t)a.n;
     const size_t cgv0 = (size_t)cg0 * n, cgv1 = cgv0 + n;
     const double *Q0 = a.q + cgv0 * kWave, *Q1 = a.q + cgv1 * kWave;
@@ -1106,7 +1117,7 @@ __device__ __forceinline__ void bwd_task_w(const BwdArgs &a, int q, int t, unsig
     bool loaded = false;
     int cx0 = -1, cx1 = -1, got0 = 0, got1 = 0;
     double acc0 = 0.0, acc1 = 0.0;
-    uint64_t run_act = 0;
+    uint64_t run_act = 0, any0 = 0, any1 = 0;
     auto finish = [&]() {
         if (loaded) {
             // one copy of the finish code for both groups (registers)
@@ -1118,6 +1129,10 @@ __device__ __forceinline__ void bwd_task_w(const BwdArgs &a, int q, int t, unsig
                                                 c ? acc1 : acc0, c ? got1 : got0, lane, outs);
                 produced += __popcll(b);
                 bb |= b;
+                if (CM) {
+                    if (c) any1 |= b;
+                    else any0 |= b;
+                }
             }
             if (bb) run_act |= 1ull << (x - v0);
         } else if (lane < 2) {
@@ -1196,6 +1211,10 @@ __device__ __forceinline__ void bwd_task_w(const BwdArgs &a, int q, int t, unsig
         a.pd[p1] = got1;
         a.pm[p1] = acc1;
     }
+    if (CM) {
+        flush_colmask(a.colmask, a.ncg_all, cg0, any0);
+        if (has1) flush_colmask(a.colmask, a.ncg_all, cg0 + 1, any1);
+    }
 }
 
 // Combine the slices of split row h for both groups of pair q and finish it.
@@ -1207,7 +1226,7 @@ __device__ __forceinline__ void bwd_hub_w(const BwdArgs &a, int q, int h, unsign
     uint64_t any = 0;
     for (int c = 0; c < 2; c++) {
         const int cg = 2 * q + c;
-        if (cg >= a.ncg) break;
+        if (cg >= a.ncg_all) break;
         const size_t cgv = (size_t)cg * (size_t)a.n;
         int got = 0;
         double acc = 0.0;
@@ -1235,6 +1254,7 @@ __device__ __forceinline__ void bwd_hub_w(const BwdArgs &a, int q, int h, unsign
         const uint64_t b = bwd_finalize(a, cgv, cg, x, cx, acc, got, lane, outs);
         produced += __popcll(b);
         any |= b;
+        flush_colmask(a.colmask, a.ncg_all, cg, b);
     }
     if (any && lane == 0) atomicOr(a.abits_n + (size_t)q * a.nwords + (x >> 5), 1u << (x & 31));
 }
@@ -1326,13 +1346,15 @@ __global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_bwd_count(BwdArgs a)
     flush_counts(produced, 0, 0, 0, a.ctr);
 }
 
-// Paired counting product (plain path, two or more groups): wave = (pair, task).
-template <int AM>
+// Paired counting product: wave = (pair, task).  Plain path: every pair of
+// the batch; with L, the a.nwide pairs listed in a.cglist (served form).
+template <int AM, bool L>
 __global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_bwd_count_w(BwdArgs a) {
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const int q = wid / a.ntasks;
+    const int np = L ? a.nwide : (a.ncg + 1) / 2;
     unsigned long long produced = 0;
-    if (q < (a.ncg + 1) / 2) count_task_w<AM>(a, q, wid - q * a.ntasks, produced);
+    if (q < np) count_task_w<AM, L>(a, pick_cg<L>(a.cglist, q), wid - q * a.ntasks, produced);
     flush_counts(produced, 0, 0, 0, a.ctr);
 }
 
@@ -1357,18 +1379,19 @@ __global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_bwd_pull(BwdArgs a) 
     flush_counts(produced, outs, 0, 0, a.ctr);
 }
 
-// Paired backward product (plain path): wave = (pair, task), pair-major.
-template <int AM>
+// Paired backward product: wave = (pair, task), pair-major; with L over the
+// a.nwide pairs listed in a.cglist (served form).
+template <int AM, bool L>
 __global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_bwd_pull_w(BwdArgs a) {
     if (!live_prev(a.prev_ctr)) return;
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const int q = wid / a.ntasks;
     unsigned long long produced = 0, outs = 0;
-    if (q < a.nwide) bwd_task_w<AM>(a, q, wid - q * a.ntasks, produced, outs);
+    if (q < a.nwide) bwd_task_w<AM, L>(a, pick_cg<L>(a.cglist, q), wid - q * a.ntasks, produced, outs);
     flush_counts(produced, outs, 0, 0, a.ctr);
 }
 
-template <int D = 0>
+template <bool L>
 __global__ __launch_bounds__(kBlock) void k_bwd_merge_w(BwdArgs a) {
     const int gtid = blockIdx.x * kBlock + threadIdx.x;
     if (!live_prev(a.prev_ctr)) {
@@ -1381,7 +1404,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_merge_w(BwdArgs a) {
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     unsigned long long produced = 0, outs = 0;
     const int q = a.nhubs ? wid / a.nhubs : a.nwide;
-    if (q < a.nwide) bwd_hub_w(a, q, wid - q * a.nhubs, produced, outs);
+    if (q < a.nwide) bwd_hub_w(a, pick_cg<L>(a.cglist, q), wid - q * a.nhubs, produced, outs);
     flush_counts(produced, outs, nv, na, a.ctr);
 }
 

@@ -19,6 +19,7 @@ at a time, in arrival order, through the plain per-batch entry points.
 from __future__ import annotations
 
 import ctypes
+import threading
 import time
 from collections import deque
 from dataclasses import dataclass, field
@@ -39,6 +40,7 @@ SERVER_SIGNATURES = {
     "mfbc_server_active_columns": ([_P], ctypes.c_int),
     "mfbc_server_admit": ([_P, _P, _I32, _P, _P], ctypes.c_int),
     "mfbc_server_step_launch": ([_P, _P], ctypes.c_int),
+    "mfbc_server_set_rounds": ([_P, _I32], ctypes.c_int),
     "mfbc_server_step_query": ([_P], ctypes.c_int),
     "mfbc_server_step_finish": ([_P, _P, _P, _P], ctypes.c_int),
     "mfbc_server_harvest_bc": ([_P, _P, _I32, _P, _P], ctypes.c_int),
@@ -66,7 +68,7 @@ def footprint(dg, width: int) -> int:
 class ColumnServer:
     """One ``mfbc_server``: `width` source columns over a resident graph."""
 
-    def __init__(self, dg, width: int = 256, stream=None):
+    def __init__(self, dg, width: int = 256, stream=None, rounds: int = 0):
         import torch
         self.torch = torch
         self.dg = dg
@@ -75,6 +77,8 @@ class ColumnServer:
         h = ctypes.c_void_p()
         _m._check(_lib().mfbc_server_create(dg.handle, width, ctypes.byref(h)))
         self.h = h
+        if rounds:
+            _m._check(_lib().mfbc_server_set_rounds(h, int(rounds)))
         self.launched = False
         self.owned = 0             # columns admitted and not yet harvested
         self._done = np.zeros(width, dtype=np.int32)
@@ -256,11 +260,20 @@ class ServeEngine:
 
     def __init__(self, dgraphs, widths=None, budget_bytes: Optional[int] = None,
                  max_width: int = 256, server_factory=None, footprint_fn=None,
-                 device: str = "cuda"):
+                 device: str = "cuda", heavy_arcs: Optional[int] = 1 << 22, max_heavy: int = 1):
         """``server_factory(dgraph, width)`` and ``footprint_fn(dgraph, width)``
         default to ColumnServer and mfbc_server_footprint (other executors
         can be plugged in, e.g. to test the scheduling on the CPU);
-        ``device``: where request results are allocated."""
+        ``device``: where request results are allocated.
+
+        Heavy graphs (more than ``heavy_arcs`` arcs; None: no graph is heavy)
+        advance one step at a time in order of their oldest request: at most
+        ``max_heavy`` of their servers have steps in flight, chosen by the
+        arrival of the oldest request they hold or queue, while light graphs'
+        servers run alongside.  Sharing the device between several heavy
+        graphs would stretch each of their requests (every one of their
+        products is bound by the memory bandwidth the others also use); light
+        graphs' products take little of it and keep their short latency."""
         import torch
         self.torch = torch
         self.device = device
@@ -273,6 +286,9 @@ class ServeEngine:
         self.servers = [None] * len(self.dgraphs)
         self.steps = 0
         self.rejected = 0
+        self.heavy = [heavy_arcs is not None and getattr(dg, "arcs", 0) > heavy_arcs
+                      for dg in self.dgraphs]
+        self.max_heavy = max_heavy
         if self.fixed:
             need = sum(fp(dg, w) for dg, w in zip(self.dgraphs, widths))
             if need > self.mem.budget:
@@ -294,10 +310,6 @@ class ServeEngine:
         for gi in range(len(self.servers)):
             self._close(gi)
 
-    def _idle(self, gi: int) -> bool:
-        s = self.servers[gi]
-        return s is not None and not s.launched and s.active_columns() == 0 and not s.owned
-
     def _alloc(self, r: Request):
         t = self.torch
         dg = self.dgraphs[r.graph]
@@ -308,101 +320,178 @@ class ServeEngine:
             r._targets = t.as_tensor(np.ascontiguousarray(r.targets, dtype=np.int32),
                                      device=self.device)
 
+    def _idle(self, gi: int) -> bool:
+        s = self.servers[gi]
+        return (s is not None and not getattr(s, "busy", False) and not s.launched
+                and s.owned == 0 and s.active_columns() == 0)
+
     def run(self, requests: List[Request], realtime: bool = True, on_step=None):
         """Serve `requests` (arrival times in seconds); returns them with `done` set.
 
-        Each graph's server advances on its own: whenever its step has
-        completed, finished columns are harvested, queued sources take the
-        free columns and the next step is launched -- a small graph never
-        waits for a step of a large one.  A graph without a server gets one
-        when the memory budget allows (see MemoryBudget); a request whose
-        graph cannot fit a server within the whole budget completes at once
-        with ``error`` set and no result.
+        The calling thread releases requests at their arrival times; one worker
+        thread per graph drives that graph's server: it admits queued sources
+        into free columns, launches a step, waits for it (the library call
+        releases the interpreter lock, so graphs progress in parallel) and
+        harvests the columns that finished -- a small graph never waits for a
+        step of a large one.  A graph without a server gets one when the
+        memory budget allows (see MemoryBudget); a request whose graph cannot
+        fit a server within the whole budget completes at once with ``error``
+        set and no result.  Heavy graphs take turns (see __init__).
+        ``on_step(engine)`` is called after every step, under the engine's lock.
         """
         t = self.torch
         pending = sorted(requests, key=lambda r: r.arrival)
-        nxt = 0
         G = len(self.dgraphs)
-        queues = [deque() for _ in range(G)]
-        owner = [dict() for _ in range(G)]           # column -> request
-        left = len(pending)
-
+        self._queues = [deque() for _ in range(G)]
+        self._owner = [dict() for _ in range(G)]      # column -> request, per graph
+        self._active = [dict() for _ in range(G)]     # id -> request with columns in flight
+        self._oldest = [float("inf")] * G             # arrival of the oldest request held
+        self._left = len(pending)
+        self._stop = False
+        self._err = None
+        self._token = None                            # heavy graph allowed to step
+        cv = threading.Condition()
+        self._cv = cv
         if self.device == "cuda":
             t.cuda.synchronize()
         t0 = time.perf_counter()
-        while left:
-            now = time.perf_counter() - t0 if realtime else float("inf")
-            while nxt < len(pending) and pending[nxt].arrival <= now:
-                r = pending[nxt]
-                nxt += 1
+        self._t0 = t0
+        workers = [threading.Thread(target=self._worker, args=(gi, on_step), daemon=True)
+                   for gi in range(G)]
+        for w in workers:
+            w.start()
+        try:
+            for r in pending:
+                if realtime:
+                    wait = r.arrival - (time.perf_counter() - t0)
+                    if wait > 0:
+                        time.sleep(wait)
                 if r.sources.size and not self.fixed and not self.mem.fits_ever(r.graph):
-                    r.error = (f"ENOMEM: a 64-column server of graph {r.graph} needs "
-                               f"{self.mem.footprint(r.graph, 64)} bytes, the budget is "
-                               f"{self.mem.budget}")
-                    r.done = time.perf_counter() - t0
-                    self.rejected += 1
-                    left -= 1
+                    with cv:
+                        r.error = (f"ENOMEM: a 64-column server of graph {r.graph} needs "
+                                   f"{self.mem.footprint(r.graph, 64)} bytes, the budget is "
+                                   f"{self.mem.budget}")
+                        r.done = time.perf_counter() - t0
+                        self.rejected += 1
+                        self._left -= 1
+                        cv.notify_all()
                     continue
                 self._alloc(r)
-                if r.sources.size == 0:          # nothing to compute: the zero result
-                    r.done = time.perf_counter() - t0
-                    left -= 1
-                else:
-                    queues[r.graph].append(r)
-            busy = False
-            for gi in range(G):
-                srv = self.servers[gi]
-                if srv is not None and srv.launched:
-                    if not srv.ready():
-                        busy = True
-                        continue
-                    done = srv.step_finish()
-                    if done.size:
-                        left -= self._harvest(srv, gi, done, owner, t0)
-                q = queues[gi]
-                if q and srv is None:
-                    want = sum(r.sources.size - r.placed for r in q)
-                    head = q[0].arrival
+                with cv:
+                    if r.sources.size == 0:          # nothing to compute: the zero result
+                        r.done = time.perf_counter() - t0
+                        self._left -= 1
+                    else:
+                        self._queues[r.graph].append(r)
+                        self._oldest[r.graph] = min(self._oldest[r.graph], r.arrival)
+                    cv.notify_all()
+            with cv:
+                while self._left > 0 and self._err is None:
+                    cv.wait(timeout=0.5)
+        finally:
+            with cv:
+                self._stop = True
+                cv.notify_all()
+            for w in workers:
+                w.join()
+        if self._err is not None:
+            raise self._err
+        return requests
 
-                    def evictable(h, head=head):
-                        # an idle server may go if its graph has nothing waiting
-                        # that arrived before this graph's oldest request
-                        return self._idle(h) and (not queues[h] or queues[h][0].arrival > head)
+    def _may_step(self, gi: int) -> bool:
+        """Heavy graphs: only the one holding the oldest request steps, one at a time."""
+        if not self.heavy[gi]:
+            return True
+        if self._token is not None and self._token != gi:
+            return False
+        mine = self._oldest[gi]
+        return all(not self.heavy[h] or h == gi or self._oldest[h] >= mine
+                   for h in range(len(self.dgraphs)))
 
-                    width, evict = self.mem.acquire(gi, want, evictable)
-                    if width is None:
-                        continue                 # waits until memory frees up
-                    for h in evict:
-                        self._close(h)
-                    self._open(gi, width)
-                    srv = self.servers[gi]
-                if srv is None:
-                    continue
-                free = srv.free_columns()
-                while q and free:
-                    r = q[0]
-                    k = min(free, r.sources.size - r.placed)
-                    cols = srv.admit(r.sources[r.placed:r.placed + k])
+    def _refresh_oldest(self, gi: int):
+        ages = [r.arrival for r in self._queues[gi]] + [r.arrival for r in self._active[gi].values()]
+        self._oldest[gi] = min(ages) if ages else float("inf")
+
+    def _worker(self, gi: int, on_step):
+        cv = self._cv
+        q = self._queues[gi]
+        try:
+            while True:
+                admits = []
+                with cv:
+                    while True:
+                        if self._stop:
+                            return
+                        srv = self.servers[gi]
+                        active = srv is not None and srv.active_columns() > 0
+                        if (q or active) and self._may_step(gi):
+                            if srv is None:
+                                srv = self._acquire(gi)
+                            if srv is not None:
+                                break
+                        cv.wait(timeout=0.05)
+                    srv.busy = True
+                    if self.heavy[gi]:
+                        self._token = gi
+                    # queued sources fill the free columns (their requests in arrival order)
+                    free = srv.free_columns()
+                    while q and free:
+                        r = q[0]
+                        k = min(free, r.sources.size - r.placed)
+                        admits.append((r, r.placed, k))
+                        r.placed += k
+                        free -= k
+                        self._active[gi][id(r)] = r
+                        if r.placed == r.sources.size:
+                            q.popleft()
+                for r, p0, k in admits:
+                    cols = srv.admit(r.sources[p0:p0 + k])
                     for j, c in enumerate(cols):
-                        owner[gi][int(c)] = r
-                        r.cols[int(c)] = r.placed + j
-                    r.placed += k
+                        self._owner[gi][int(c)] = r
+                        r.cols[int(c)] = p0 + j
                     srv.owned += k
-                    free -= k
-                    if r.placed == r.sources.size:
-                        q.popleft()
+                finished = 0
                 if srv.active_columns() > 0:
                     srv.step_launch()
+                    done = srv.step_finish()
+                    if done.size:
+                        finished = self._harvest(srv, gi, done, self._owner, self._t0)
+                with cv:
+                    srv.busy = False
                     self.steps += 1
                     self.mem.touch(gi)
-                    busy = True
-            if on_step is not None:
-                on_step(self)
-            if not busy and nxt < len(pending):
-                wait = pending[nxt].arrival - (time.perf_counter() - t0)
-                if wait > 0:
-                    time.sleep(min(wait, 0.002))
-        return requests
+                    if self._token == gi:
+                        self._token = None
+                    self._left -= finished
+                    self._refresh_oldest(gi)
+                    if on_step is not None:
+                        on_step(self)
+                    cv.notify_all()
+        except BaseException as e:             # surfaced by run()
+            with cv:
+                self._err = e
+                self._stop = True
+                cv.notify_all()
+
+    def _acquire(self, gi: int):
+        """A server for graph gi within the memory budget (under the lock), or None."""
+        q = self._queues[gi]
+        want = sum(r.sources.size - r.placed for r in q)
+        head = q[0].arrival if q else float("inf")
+
+        def evictable(h):
+            # an idle server may go if its graph has nothing waiting that
+            # arrived before this graph's oldest request
+            hq = self._queues[h]
+            return self._idle(h) and (not hq or hq[0].arrival > head)
+
+        width, evict = self.mem.acquire(gi, want, evictable)
+        if width is None:
+            return None
+        for h in evict:
+            self._close(h)
+        self._open(gi, width)
+        return self.servers[gi]
 
     def _harvest(self, srv, gi, done, owner, t0) -> int:
         """Harvest finished columns; returns the number of requests completed."""
@@ -426,6 +515,7 @@ class ServeEngine:
         for r, cols in by_req.values():
             if r.harvested == r.sources.size:
                 r.done = tnow
+                self._active[gi].pop(id(r), None)
                 finished += 1
         return finished
 

@@ -94,26 +94,26 @@ def test_server_rejects_misuse(env):
 
 
 def test_cohort_admission(env):
-    """Sources join a 64-column group only until its first step is launched;
-    a running group takes none, a free group next to it does, and both give
-    the oracle's results."""
+    """Sources join a pair of 64-column groups only until its first step is
+    launched; a running pair takes none, a free pair next to it does, and
+    both give the oracle's results."""
     t, mfbc, serve, graphs, dgs = env
     g = graphs[1]
-    s = serve.ColumnServer(dgs[1], 128)
+    s = serve.ColumnServer(dgs[1], 256)
     a_src = gg.pick_sources(g, 10, 31)
     b_src = gg.pick_sources(g, 64, 32)
-    assert s.free_columns() == 128
+    assert s.free_columns() == 256
     ca = s.admit(a_src[:4])
-    ca = np.concatenate([ca, s.admit(a_src[4:])])          # same group, before the launch
-    assert np.all(ca // 64 == ca[0] // 64)
-    assert s.free_columns() == 128 - 10
+    ca = np.concatenate([ca, s.admit(a_src[4:])])          # same pair, before the launch
+    assert np.all(ca // 128 == ca[0] // 128)
+    assert s.free_columns() == 256 - 10
     s.step_launch()
     done = list(s.step_finish())
-    assert s.free_columns() == 64                           # the running group is closed
+    assert s.free_columns() == 128                          # the running pair is closed
     with pytest.raises(mfbc.MfbcError):
-        s.admit(b_src[:1].repeat(65))
-    cb = s.admit(b_src)                                     # the other group, mid-loop of the first
-    assert np.all(cb // 64 != ca[0] // 64)
+        s.admit(b_src[:1].repeat(129))
+    cb = s.admit(b_src)                                     # the other pair, mid-loop of the first
+    assert np.all(cb // 128 != ca[0] // 128)
     out_a = t.zeros(g.n, dtype=t.float64, device="cuda")
     out_b = t.zeros(g.n, dtype=t.float64, device="cuda")
     owner = {int(c): out_a for c in ca}
@@ -132,7 +132,7 @@ def test_cohort_admission(env):
     t.cuda.synchronize()
     rel_close(out_a.cpu().numpy(), oracle.brandes(g, a_src, per_source=False)["lambda"], 1e-10, "a")
     rel_close(out_b.cpu().numpy(), oracle.brandes(g, b_src, per_source=False)["lambda"], 1e-10, "b")
-    assert s.free_columns() == 128
+    assert s.free_columns() == 256
     s.close()
 
 
@@ -258,3 +258,17 @@ def test_served_at_workload_sizes(env):
     eng.close()
     for d in ds:
         d.close()
+
+
+@pytest.mark.parametrize("rounds", [1, 3, 8])
+def test_rounds_per_step_do_not_change_results(env, rounds):
+    """A step runs 1..8 rounds of products (later rounds skip on the device
+    once a loop has ended); every request against the oracle."""
+    t, mfbc, serve, graphs, dgs = env
+    reqs = serve.make_requests(graphs, 14, rate=1e9, seed=31 + rounds, smin=2, smax=140)
+    eng = serve.ServeEngine(dgs, [128, 64, 192],
+                            server_factory=lambda dg, w: serve.ColumnServer(dg, w, rounds=rounds))
+    eng.run(reqs, realtime=False)
+    for r in reqs:
+        rel_close(r.out.cpu().numpy(), reference(graphs, r), 1e-10, f"rounds={rounds} request {r.rid}")
+    eng.close()

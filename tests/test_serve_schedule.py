@@ -7,6 +7,8 @@ to what fits; idle servers are released oldest first, busy ones never;
 requests wait while memory is taken and complete once it frees up; requests
 whose graph cannot fit 64 columns in the whole budget are rejected; every
 request's result is assembled from exactly its own columns."""
+import threading
+import time
 from dataclasses import dataclass
 
 import numpy as np
@@ -91,18 +93,30 @@ class FakeServer:
         self.src[free] = sources
         return free.astype(np.int32)
 
+    heavy_flying = 0               # heavy servers between step_launch and step_finish
+    max_heavy_flying = 0
+    light_during_heavy = 0         # light steps run while a heavy step was in flight
+    lock = threading.Lock()
+
     def step_launch(self):
         assert not self.launched
         self.launched = True
-        self.ready_after = 1           # one poll of "not ready" before each step completes
+        with FakeServer.lock:
+            if getattr(self.dg, "arcs", 0) > 1000:
+                FakeServer.heavy_flying += 1
+                FakeServer.max_heavy_flying = max(FakeServer.max_heavy_flying,
+                                                  FakeServer.heavy_flying)
+            elif FakeServer.heavy_flying:
+                FakeServer.light_during_heavy += 1
 
     def ready(self):
-        if self.ready_after:
-            self.ready_after -= 1
-            return False
         return True
 
     def step_finish(self):
+        time.sleep(0.001)              # a step takes a little while
+        with FakeServer.lock:
+            if getattr(self.dg, "arcs", 0) > 1000:
+                FakeServer.heavy_flying -= 1
         self.launched = False
         act = self.rem > 0
         self.rem[act] -= 1
@@ -124,11 +138,13 @@ class FakeServer:
 
 
 def test_engine_respects_budget_and_completes_every_request():
+    """The budget holds one server at a time (any two exceed it), so every
+    switch between graphs releases an idle server first."""
     FakeServer.live.clear()
     graphs = [FakeGraph(50), FakeGraph(60), FakeGraph(40), FakeGraph(70)]
     per_col = [1, 2, 3, 100]                         # graph 3 never fits
-    fp = lambda dg, w: 10 + per_col[graphs.index(dg)] * w   # noqa: E731
-    budget = 10 + 3 * 192 + 10 + 2 * 64              # room for about two servers at a time
+    fp = lambda dg, w: 200 + per_col[graphs.index(dg)] * w   # noqa: E731
+    budget = 400
     peak = []
     eng = ServeEngine(graphs, budget_bytes=budget, max_width=256, server_factory=FakeServer,
                       footprint_fn=fp, device="cpu")
@@ -155,8 +171,8 @@ def test_engine_respects_budget_and_completes_every_request():
         else:
             assert np.array_equal(r.out[:, 0].numpy(), r.sources.astype(float)), r.rid
     assert eng.rejected == sum(r.graph == 3 for r in reqs)
-    # servers were released to let other graphs in, and never while busy
-    assert any(s.closed for s in FakeServer.live)
+    # three graphs were served through one server slot: servers were released
+    assert sum(s.closed for s in FakeServer.live) >= 2
     eng.close()
 
 
@@ -169,4 +185,35 @@ def test_fixed_widths_must_fit_the_budget():
     assert e.value.code == mfbc.MFBC_ENOMEM
     eng = ServeEngine(graphs, widths=[64, 64], budget_bytes=128, server_factory=FakeServer,
                       footprint_fn=lambda dg, w: w, device="cpu")
+    eng.close()
+
+
+@dataclass
+class FakeSized:
+    n: int
+    arcs: int
+
+
+def test_heavy_graphs_advance_one_at_a_time_oldest_first():
+    """At most one heavy graph's server has a step in flight; light graphs
+    run alongside; the heavy graph holding the oldest request goes first and
+    every request completes with its own result."""
+    FakeServer.live.clear()
+    graphs = [FakeSized(40, 100), FakeSized(50, 10_000), FakeSized(60, 20_000), FakeSized(30, 50)]
+    eng = ServeEngine(graphs, budget_bytes=10**9, max_width=128, server_factory=FakeServer,
+                      footprint_fn=lambda dg, w: w, device="cpu", heavy_arcs=1000, max_heavy=1)
+    assert eng.heavy == [False, True, True, False]
+    FakeServer.heavy_flying = FakeServer.max_heavy_flying = FakeServer.light_during_heavy = 0
+    rng = np.random.default_rng(4)
+    reqs = []
+    for i in range(40):
+        gi = int(rng.integers(0, 4))
+        src = rng.integers(0, graphs[gi].n, size=int(rng.integers(1, 90))).astype(np.int32)
+        reqs.append(Request(i, gi, "bc", src, None, 0.0))
+    eng.run(reqs, realtime=False)
+    assert FakeServer.max_heavy_flying == 1
+    assert FakeServer.light_during_heavy > 0                  # light work overlaps heavy work
+    for r in reqs:
+        want = np.bincount(r.sources, minlength=graphs[r.graph].n).astype(float)
+        assert np.array_equal(r.out.numpy(), want), r.rid
     eng.close()
