@@ -97,7 +97,22 @@ def stored_traffic(workload, kernel):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(g, src, sample, m):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(g, src, sample, m, one_thread_sample=8):
+    """The C oracle (Brandes, FP64, OpenMP over sources) on the host: a bounded
+    sample of the workload's sources on every host thread, and a smaller one
+    on one thread."""
     import numpy as np
     import oracle
     k = src.size if sample is None else min(sample, src.size)
@@ -106,9 +121,39 @@ def cpu_baseline(g, src, sample, m):
     t0 = time.perf_counter()
     oracle.brandes(g, s, per_source=False, nthreads=threads)
     dt = time.perf_counter() - t0
+    k1 = min(one_thread_sample, k)
+    t0 = time.perf_counter()
+    oracle.brandes(g, np.ascontiguousarray(src[:k1]), per_source=False, nthreads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": k * m / dt, "unit": "TEPS", "cores": threads, "kind": "oracle",
             "sample": f"{k} of the workload's {src.size} sources (C Brandes, FP64, "
-                      f"OpenMP over sources), {dt:.2f} s"}
+                      f"OpenMP over sources), {dt:.2f} s",
+            "cpu": cpu_model(),
+            "one_thread": {"value": k1 * m / dt1, "unit": "TEPS", "sources": k1, "seconds": round(dt1, 3)}}
+
+
+def relaxation_census(dg, d_src, batch, g):
+    """Relaxations (Section 5's flops of each product: every frontier entry
+    combined along each of its arcs) of one MFBC run over the source list, from
+    an untimed traced run: forward products from the recorded per-product
+    counts; the counting product relaxes every reachable (source, vertex)
+    along its arcs; every backward product relaxes each non-source entry of
+    its frontier, and each reachable non-source entry enters exactly once."""
+    import torch
+    deg = torch.as_tensor(g.row_ptr[1:] - g.row_ptr[:-1], device="cuda", dtype=torch.int64)
+    fwd = cnt = bwd = 0
+    products = 0
+    for b0 in range(0, d_src.numel(), batch):
+        sb = d_src[b0:b0 + batch]
+        f = dg.forward(sb, trace=True, frontiers=False, max_products=dg.n + 2)
+        fwd += int(f["relax"].sum())
+        products += f["products"]
+        reach = f["dist"] != 0x7FFFFFFF
+        cnt += int((reach.to(torch.int64) * deg).sum())
+        bwd += int((reach.to(torch.int64) * deg).sum() - deg[sb.long()].sum())
+        del f, reach
+    return {"forward": fwd, "counting": cnt, "backward": bwd, "total": fwd + cnt + bwd,
+            "forward_products": products}
 
 
 def run_many(args, spec):
@@ -349,6 +394,8 @@ def main():
     ap.add_argument("--workload", default="rmat20_w255", choices=sorted(WORKLOADS))
     ap.add_argument("--batch", type=int, default=None, help="override the batch size")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-census", action="store_true",
+                    help="skip the untimed traced run that counts relaxations (for profiler runs)")
     ap.add_argument("--stats", action="store_true", help="print per-kernel stats to stderr")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (calibrates the "
@@ -438,6 +485,9 @@ def main():
 
     ms_step = elapsed / args.steps * 1e3
     teps = src.size * g.m / (elapsed / args.steps)
+    census = None if args.no_census else relaxation_census(dg, d_src, batch, g)
+    if census:
+        print(f"[bench] relaxations per step: {census}", file=sys.stderr, flush=True)
 
     kernels = {
         "k_fwd_pull": (tot["fwd_pull_ms"], tot["fwd_alg_bytes"], tot["fwd_pull_launches"]),
@@ -450,11 +500,16 @@ def main():
     traffic = stored_traffic(args.workload, dom)
     # batches of two or more column groups run the forward product two groups per wave
     label = "k_fwd_pull_w" if dom == "k_fwd_pull" and min(batch, src.size) > 64 else dom
+    avg_us = ms / max(launches, 1) * 1e3
     roofline = {"bound": "hbm", "kernel": label, "achieved": round(achieved, 2),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "launches": int(launches),
-                "avg_launch_us": round(ms / max(launches, 1) * 1e3, 2),
-                "alg_bytes_per_launch": round(alg / max(launches, 1))}
+                "avg_launch_us": round(avg_us, 2),
+                "alg_bytes_per_launch": round(alg / max(launches, 1)),
+                "achieved_basis": "algorithmic bytes (frontier-counter model) per launch / "
+                                  "HIP-event kernel time per launch",
+                "traffic_rate_gbs": (round(traffic / (avg_us * 1e-6) / 1e9, 1)
+                                     if traffic else None)}
     if args.stats:
         for k, (kms, kb, kl) in kernels.items():
             print(f"[bench] {k}: {kms / args.steps:.2f} ms/step over {kl // args.steps} launches, "
@@ -480,6 +535,9 @@ def main():
                    "n_sources": int(src.size), "batch": batch,
                    "fwd_products_per_step": tot["fwd_products"] / args.steps,
                    "bwd_products_per_step": tot["bwd_products"] / args.steps},
+        "relaxations_per_step": census["total"] if census else None,
+        "relaxations_per_s": census["total"] / (elapsed / args.steps) if census else None,
+        "relaxations": census,
         "roofline": roofline,
         "cpu_baseline": None,
     }

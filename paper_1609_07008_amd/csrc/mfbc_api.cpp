@@ -328,10 +328,14 @@ int run_backward(mfbc_graph *g, int ncg, int nb, int32_t *products, hipStream_t 
                 const Counts c = ring_counts(g, 0);
                 st.bwd_entries += c.produced;
                 st.count_launches++;
-                // adjacency, tau of every (column, vertex) read once, and the
-                // stored DAG (one 8-byte lane mask per arc and column group) written
+                // adjacency, tau of every (column, vertex) read once, the
+                // stored DAG (one 8-byte lane mask per arc and column group)
+                // written, the backward state of every (column, vertex)
+                // initialised (counter 4 B, zeta 8 B, step 4 B), and each
+                // leaf's sigma read and 1/sigma written
                 st.count_alg_bytes += arc_bytes * (double)g->arcs + 8.0 * g->n +
-                                      8.0 * (double)g->n * nb + 8.0 * (double)g->arcs * ncg;
+                                      24.0 * (double)g->n * nb +
+                                      8.0 * (double)g->arcs * ncg + 16.0 * (double)c.produced;
                 if (g->timing) {
                     float t = 0.f;
                     if (hipEventElapsedTime(&t, g->ev[0], g->ev[2]) == hipSuccess) st.count_ms += t;
