@@ -45,6 +45,13 @@ WORKLOADS = {
                              n_sources=1024, source_seed=103, batch=256, cpu_sample=6),
     "bfs_rmat20": dict(kind="fixpoint", op="bfs", scale=20, ef=16, wrange=(1, 255), seed=3,
                        n_sources=1024, source_seed=103, batch=256, cpu_sample=10),
+    # the same graph and sources with the other two algebras of the generic
+    # product: widest-path bottlenecks (max, min(a, w)) and binary32 sums of
+    # 1/w (min, a + 1/w)
+    "widest_rmat20_w255": dict(kind="fixpoint", op="widest", scale=20, ef=16, wrange=(1, 255), seed=3,
+                               n_sources=1024, source_seed=103, batch=256, cpu_sample=4),
+    "resist_rmat20_w255": dict(kind="fixpoint", op="resist", scale=20, ef=16, wrange=(1, 255), seed=3,
+                               n_sources=1024, source_seed=103, batch=256, cpu_sample=4),
     # batched form: 256 ER / R-MAT graphs, n log-uniform in [200, 20000], average
     # degree uniform in [4, 64], weights 1..100, exact BC of every graph
     "batched256": dict(kind="many", count=256, seed0=1000, cpu_sample=48),
@@ -326,7 +333,8 @@ def run_fixpoint(args, spec):
     dg = mfbc.DeviceGraph(g)
     autotune.apply_plan(dg, g, autotune.load_cache())
     d_src = torch.as_tensor(src, device="cuda")
-    out = torch.empty((batch, g.n), dtype=torch.int32, device="cuda")
+    vtype = torch.float32 if spec["op"] == "resist" else torch.int32
+    out = torch.empty((batch, g.n), dtype=vtype, device="cuda")
     print(f"[bench] {args.workload}: n={g.n} m={g.m} sources={src.size} batch={batch}",
           file=sys.stderr, flush=True)
 
@@ -361,7 +369,8 @@ def run_fixpoint(args, spec):
         "metric": f"{spec['op'].upper()} TEPS (sources x edges / s) at 1 GPU",
         "value": src.size * g.m / (elapsed / args.steps), "unit": "TEPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if spec["op"] == "resist" else "int32",
         "data": "synthetic",
         "config": {"workload": args.workload, "graph": g.name, "n": g.n, "m": g.m,
                    "n_sources": int(src.size), "batch": batch, "op": spec["op"]},
@@ -373,11 +382,12 @@ def run_fixpoint(args, spec):
         "cpu_baseline": None,
     }
     if not args.no_cpu:
-        from oracle.frontier import fixpoint
+        from oracle.frontier import InArcs, fixpoint
         k = min(spec["cpu_sample"], src.size)
         t1 = time.perf_counter()
+        arcs = InArcs(g, unit_weights=spec["op"] == "bfs")
         for s in src[:k]:
-            fixpoint(g, int(s), spec["op"])
+            fixpoint(g, int(s), spec["op"], arcs=arcs)
         dt = time.perf_counter() - t1
         line["cpu_baseline"] = {"value": k * g.m / dt, "unit": "TEPS", "cores": 1, "kind": "oracle",
                                 "sample": f"{k} of the workload's {src.size} sources (numpy "

@@ -190,23 +190,36 @@ int mfbc_bc_noalloc(mfbc_graph *g, const int32_t *d_sources, int64_t n_sources,
 /*
  * mfbc_fixpoint -- the paper's monoid product (Section 3: C = A (+).f B with a
  * commutative monoid (+) and an action f of an arc on an entry) iterated over
- * maximal frontiers as in Algorithm 1, for other graph problems.  Values are
- * int32, (+) = min, and
- *   op = MFBC_OP_SSSP: f(a, w) = a + w  -> shortest-path distances;
- *   op = MFBC_OP_BFS:  f(a, w) = a + 1  -> hop levels (weights ignored).
- * T(s,s) = 0; product j relaxes the arcs of the entries that product j-1
- * lowered (the sources for j = 1); the loop ends after the first product
- * that lowers nothing.
+ * maximal frontiers as in Algorithm 1, for other graph problems.  The
+ * algebra is chosen by `op` (value type, (+), f):
+ *   MFBC_OP_SSSP    int32, min, f(a, w) = a + w      -> shortest-path distances;
+ *   MFBC_OP_BFS     int32, min, f(a, w) = a + 1      -> hop levels (weights ignored);
+ *   MFBC_OP_WIDEST  int32, max, f(a, w) = min(a, w)  -> widest-path (bottleneck)
+ *                   capacities; unweighted graphs have every width 1;
+ *   MFBC_OP_RESIST  float (binary32), min, f(a, w) = a + 1/w -> the least sum of
+ *                   reciprocal arc weights over paths, every division and
+ *                   addition rounded to nearest (the value is the same for
+ *                   any evaluation order: (+) is exact and f is monotone).
+ * T(s,s) = 0 (MFBC_INF_DIST for WIDEST: the source's own width is
+ * unbounded); product j relaxes the arcs of the entries that product j-1
+ * improved (the sources for j = 1), an entry joining the next frontier when
+ * the product improves it strictly in the order of (+); the loop ends after
+ * the first product that improves nothing.  The product is the same
+ * generic pull product MFBF's forward product runs.
  *   d_sources[nb]  device, vertex ids in [0,n) (repeats allowed), nb >= 1.
- *   d_out[nb][n]   device out, row-major; MFBC_INF_DIST where unreachable.
+ *   d_out[nb][n]   device out, row-major, int32 (SSSP, BFS, WIDEST) or float
+ *                  (RESIST); where v is unreachable from the source:
+ *                  MFBC_INF_DIST (SSSP, BFS), 0 (WIDEST), +infinity (RESIST).
  *   h_products     host out (nullable): products run, the last one included.
  * Errors: EINVAL (op unknown, nb < 1, NULL output, bad source), ENOMEM,
  * EDEVICE.
  */
 #define MFBC_OP_SSSP 0
 #define MFBC_OP_BFS 1
+#define MFBC_OP_WIDEST 2
+#define MFBC_OP_RESIST 3
 int mfbc_fixpoint(mfbc_graph *g, int32_t op, const int32_t *d_sources, int32_t nb,
-                  int32_t *d_out, int32_t *h_products, void *hip_stream);
+                  void *d_out, int32_t *h_products, void *hip_stream);
 
 /*
  * mfbc_forward_trace -- mfbc_forward that also records, after every forward

@@ -116,3 +116,34 @@ def dag_heights(g, s, tau):
         return best
 
     return [None if tau[v] is None else h(v) for v in range(n)]
+
+
+def simple_path_arcs(g, s):
+    """Yield (path tuple, [arc weights in path order]) for every simple path
+    starting at s (including (s,) with no arcs)."""
+    adj = _adj(g)
+    stack = [((s,), (), {s})]
+    while stack:
+        path, ws, seen = stack.pop()
+        yield path, list(ws)
+        for y, w in adj[path[-1]]:
+            if y not in seen:
+                stack.append((path + (y,), ws + (w,), seen | {y}))
+
+
+def walk_best(g, s, jmax, fold, better, start):
+    """best[j][v]: the best, by `better(a, b)` (a strictly better than b), of
+    fold(...fold(fold(start, w1), w2)..., wj) over every walk from s to v with
+    exactly j arcs, j = 0..jmax (None where no such walk), by enumerating the
+    walks one by one (no recurrence over j)."""
+    adj = _adj(g)
+    best = [[None] * g.n for _ in range(jmax + 1)]
+    stack = [(s, start, 0)]
+    while stack:
+        v, val, j = stack.pop()
+        if best[j][v] is None or better(val, best[j][v]):
+            best[j][v] = val
+        if j < jmax:
+            for y, w in adj[v]:
+                stack.append((y, fold(val, w), j + 1))
+    return best

@@ -63,6 +63,24 @@ class InArcs:
             nxt[self.has] = np.minimum.reduceat(cand, self.starts)
         return np.minimum(nxt, INF)
 
+    def step_widest(self, ell: np.ndarray) -> np.ndarray:
+        """b_next(v) = max over arcs u -> v of min(ell(u), w(u, v)) (0 if none)."""
+        nxt = np.zeros(self.n, dtype=np.int64)
+        if self.tail.size:
+            cand = np.minimum(ell[self.tail], self.weight)
+            nxt[self.has] = np.maximum.reduceat(cand, self.starts)
+        return nxt
+
+    def step_resist(self, ell: np.ndarray) -> np.ndarray:
+        """r_next(v) = min over arcs u -> v of ell(u) + 1/w(u, v), in binary32
+        (numpy's float32 division and addition round to nearest); inf if none."""
+        nxt = np.full(self.n, np.inf, dtype=np.float32)
+        if self.tail.size:
+            recip = np.float32(1.0) / self.weight.astype(np.float32)
+            cand = ell[self.tail] + recip
+            nxt[self.has] = np.minimum.reduceat(cand, self.starts)
+        return nxt
+
 
 def forward_frontiers(g, s: int, max_products: int = 1 << 20, arcs: InArcs = None):
     """F_1, F_2, ... (bool[n] each, the last one empty) for source ``s``."""
@@ -106,28 +124,52 @@ def backward_products(heights: np.ndarray, sources) -> int:
     return 1 if top < 0 else top + 2
 
 
-def fixpoint(g, s: int, op: str = "sssp", max_products: int = 1 << 20):
-    """Relaxation to a fixpoint with (+) = min over strict-improvement frontiers.
+WIDE_INF = np.int64(0x7FFFFFFF)   # the source's own (unbounded) width
 
-    Section 3's product C = A (+).f B with (+) = min and the action
-    f(a, w) = a + w ("sssp") or a + 1 ("bfs"), iterated as Algorithm 1
-    iterates it but without multiplicities, so an entry joins frontier j only
-    when product j lowers it:  F_j = { v : l_j(v) < L_{j-1}(v) }  with l_j,
-    L_j as above (arc weights, or 1 for "bfs").  Returns (L, products): the
-    final values (INF where unreachable) and the index of the first product
-    whose frontier is empty.  After an empty F_j every later one is empty
-    too (l_{j+1}(v) >= min_u L_{j-1}(u) + w(u, v) >= L_j(v)).
+
+def fixpoint(g, s: int, op: str = "sssp", max_products: int = 1 << 20, arcs: InArcs = None):
+    """Relaxation to a fixpoint over strict-improvement frontiers.
+
+    Section 3's product C = A (+).f B iterated as Algorithm 1 iterates it but
+    without multiplicities, so an entry joins frontier j only when product j
+    improves it.  With l_j(v) the best value of a walk from s to v with
+    exactly j arcs and L_j the best over i <= j:
+
+      "sssp"    (+) = min, f(a, w) = a + w; l_0(s) = 0, INF elsewhere
+      "bfs"     the same with every weight 1 (hop counts)
+      "widest"  (+) = max, f(a, w) = min(a, w); l_0(s) = WIDE_INF, 0 ("no
+                walk") elsewhere: the bottleneck of the widest walk
+      "resist"  (+) = min, f(a, w) = a + 1/w in binary32, l_0(s) = 0, inf
+                elsewhere (binary32 addition of a positive term is monotone,
+                so the best over walks is reached by the recurrence below)
+
+    F_j = { v : l_j(v) strictly better than L_{j-1}(v) }.  Returns (L,
+    products): the final values (int64; float32 for "resist") and the index
+    of the first product whose frontier is empty.  After an empty F_j every
+    later one is empty too (l_{j+1}(v) = best over u of f(l_j(u), w), and
+    every l_j(u) is no better than L_{j-1}(u), whose images are already in
+    L_j(v)).  ``arcs`` may pass g's InArcs (unit weights for "bfs") to reuse.
     """
-    if op not in ("sssp", "bfs"):
+    if op not in ("sssp", "bfs", "widest", "resist"):
         raise ValueError(op)
-    arcs = InArcs(g, unit_weights=(op == "bfs"))
-    ell = np.full(g.n, INF, dtype=np.int64)
-    ell[s] = 0
+    arcs = arcs or InArcs(g, unit_weights=(op == "bfs"))
+    if op == "widest":
+        ell = np.zeros(g.n, dtype=np.int64)
+        ell[s] = WIDE_INF
+        step, better, best = arcs.step_widest, np.greater, np.maximum
+    elif op == "resist":
+        ell = np.full(g.n, np.inf, dtype=np.float32)
+        ell[s] = 0.0
+        step, better, best = arcs.step_resist, np.less, np.minimum
+    else:
+        ell = np.full(g.n, INF, dtype=np.int64)
+        ell[s] = 0
+        step, better, best = arcs.step, np.less, np.minimum
     L = ell.copy()
     for j in range(1, max_products + 1):
-        nxt = arcs.step(ell)
-        F = nxt < L
-        L = np.minimum(L, nxt)
+        nxt = step(ell)
+        F = better(nxt, L)
+        L = best(L, nxt)
         ell = nxt
         if not F.any():
             return L, j

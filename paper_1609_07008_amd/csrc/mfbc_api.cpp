@@ -811,9 +811,9 @@ int mfbc_forward(mfbc_graph *g, const int32_t *d_sources, int32_t nb, int32_t *d
 }
 
 int mfbc_fixpoint(mfbc_graph *g, int32_t op, const int32_t *d_sources, int32_t nb,
-                  int32_t *d_out, int32_t *h_products, void *hip_stream) {
+                  void *d_out, int32_t *h_products, void *hip_stream) {
     if (!g) return fail(MFBC_EINVAL, "graph handle is NULL");
-    if (op != MFBC_OP_SSSP && op != MFBC_OP_BFS) return fail(MFBC_EINVAL, "unknown operation");
+    if (!mono_op_known(op)) return fail(MFBC_EINVAL, "unknown operation");
     if (nb < 1) return fail(MFBC_EINVAL, "nb must be >= 1");
     if (!d_out) return fail(MFBC_EINVAL, "output pointer is NULL");
     DeviceGuard dg(g->device);
@@ -824,8 +824,8 @@ int mfbc_fixpoint(mfbc_graph *g, int32_t op, const int32_t *d_sources, int32_t n
     if ((rc = ensure_workspace(g, ncg))) return rc;
     g->stats = mfbc_stats{};
     launch_set_sources(g, ncg, nb, d_sources, s);
-    launch_mono_init(g, ncg, nb, s);
-    const double arc_bytes = g->weighted && op == MFBC_OP_SSSP ? 8.0 : 4.0;
+    launch_mono_init(g, op, ncg, nb, s);
+    const double arc_bytes = g->weighted && op != MFBC_OP_BFS ? 8.0 : 4.0;
     mfbc_stats &st = g->stats;
     int64_t prev = nb;
     int j = 0, last = 0;
@@ -857,7 +857,8 @@ int mfbc_fixpoint(mfbc_graph *g, int32_t op, const int32_t *d_sources, int32_t n
     st.fwd_products = j;
     st.batches = 1;
     if (h_products) *h_products = j;
-    launch_export_tiles_i32(g, ncg, nb, g->ws.tdist, d_out, s);
+    // 4-byte values whatever their type: the tile export copies them as int32
+    launch_export_tiles_i32(g, ncg, nb, g->ws.tdist, (int32_t *)d_out, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
     return MFBC_OK;

@@ -167,7 +167,8 @@ void launch_export_tiles_i32(mfbc_graph *g, int ncg, int nb, const int32_t *tile
                              hipStream_t s);
 
 // ---- monoid fixpoints (monoid.hip) ----
-void launch_mono_init(mfbc_graph *g, int ncg, int nb, hipStream_t s);
+bool mono_op_known(int op);
+void launch_mono_init(mfbc_graph *g, int op, int ncg, int nb, hipStream_t s);
 void launch_mono_product(mfbc_graph *g, int op, int ncg, int j, hipStream_t s, hipEvent_t *ev);
 
 // ---- batched form (batched.hip) ----

@@ -4,18 +4,28 @@
 // outputs and an action f of an arc on an input entry, Section 3) iterated
 // the way Algorithm 1 iterates it: a batch of sources, T the best value per
 // (source, vertex) so far, and each product relaxing only the entries that
-// improved in the previous one.  Here with values in int32 and (+) = min:
-//   OP 0  single-source shortest paths   f(a, w) = a + w
-//   OP 1  breadth-first hop levels       f(a, w) = a + 1
+// improved in the previous one.  The algebra is a template parameter (Op:
+// the value type, (+), f, the identity and the seed); the product itself is
+// the generic pull product of pull.h -- the same function MFBF's forward
+// product instantiates -- with MonoPull as its policy.  Instances:
+//   SSSP    int32, (+) = min, f(a, w) = a + w          shortest-path distances
+//   BFS     int32, (+) = min, f(a, w) = a + 1          hop levels
+//   Widest  int32, (+) = max, f(a, w) = min(a, w)      bottleneck capacities
+//   Resist  float, (+) = min, f(a, w) = a + 1/w        least sum of 1/w along a
+//           path (binary32, every operation IEEE round-to-nearest)
 // Unlike MFBF no multiplicity is carried, so a tie does not re-enter the
-// frontier: an entry joins frontier j exactly when product j lowered it.
+// frontier: an entry joins frontier j exactly when product j improved it
+// (strictly, in the order of (+)).
 //
 // Same data layout and work decomposition as the MFBF forward product:
 // [cg][v][64] tiles (lane = source column), per-column-group vertex bitmaps,
 // runs of light rows and slices of hub rows merged in slice order; batches
 // of two or more groups run on pairs of them, the frontier values of groups
 // 2p and 2p+1 interleaved per lane (one 8-byte gather for both) with one
-// bitmap per pair, as in the forward product.
+// bitmap per pair, as in the forward product.  Values are 4 bytes, stored in
+// the workspace's int32 tiles whatever their type.
+#include <type_traits>
+
 #include "products.h"
 
 namespace mfbc {
@@ -27,342 +37,223 @@ struct MonoArgs {
     int ntasks, nhubs, nslots, ncg, n, nwords;
     const int64_t *rp;
     ArcSrc arcs;
-    const uint32_t *abits;     // frontier F_{j-1}: [cg][nwords] bitmaps
-    const int32_t *fval;       //   values [cg][n][64], kInf = absent
-    int32_t *tval;             // T
+    const uint32_t *abits;     // frontier F_{j-1}: [plane][nwords] bitmaps
+    const void *fval;          //   values [cg][n][64] (or pairs [q][n][64][2]), absent = Op::absent()
+    void *tval;                // T, [cg][n][64]
     uint32_t *abits_n;         // frontier F_j
-    int32_t *fval_n;
-    int32_t *pd;               // hub partials [cg][slots][64]
+    void *fval_n;
+    void *pd;                  // hub partials [cg][slots][64]
     unsigned long long *ctr;   // counter slots of product j
     const unsigned long long *prev_ctr;  // nullable: those of product j-1 (live_prev)
-    uint32_t *clear_bits;      // merge: F_{j-1}'s bitmaps, ncg planes
+    uint32_t *clear_bits;      // merge: F_{j-1}'s bitmaps
     unsigned long long *clear_ctr;
     int nwide;                 // pairs of groups (paired layout), 0: one group per wave
 };
 
-template <int OP>
-__device__ __forceinline__ int mono_act(int x, int w) {
-    return OP == 0 ? x + w : x + 1;
-}
+// ------------------------------------------------------------------ algebras
+struct OpSssp {
+    using V = int32_t;
+    __device__ static V absent() { return kInf; }
+    __device__ static V seed() { return 0; }
+    __device__ static V act(V x, int w) { return x + w; }
+    __device__ static V plus(V x, V y) { return min(x, y); }
+    __device__ static bool better(V x, V y) { return x < y; }
+};
 
-// T := min(T, best) at (v, cg); an entry that went down joins the next
-// frontier.  Returns the lane mask of new frontier entries.
-__device__ __forceinline__ uint64_t mono_finalize(const MonoArgs &a, size_t cgv, int v, int best,
-                                                  int td, int lane, unsigned long long &outs) {
-    const bool has = best != kInf;
-    const uint64_t hm = ballot(has);
-    outs += __popcll(hm);
-    if (!hm) return 0;
-    const size_t idx = (cgv + (size_t)v) * kWave + lane;
-    const bool keep = has && best < td;
-    if (keep) a.tval[idx] = best;
-    const uint64_t bits = ballot(keep);
-    if (bits) a.fval_n[idx] = keep ? best : kInf;
-    return bits;
-}
+struct OpBfs {
+    using V = int32_t;
+    __device__ static V absent() { return kInf; }
+    __device__ static V seed() { return 0; }
+    __device__ static V act(V x, int) { return x + 1; }
+    __device__ static V plus(V x, V y) { return min(x, y); }
+    __device__ static bool better(V x, V y) { return x < y; }
+};
 
-// One pull task: active arcs taken U at a time across owners, with the T row
-// of each owner that starts in the batch loaded in the same round trip (as
-// in the MFBF forward product).
-template <int OP, int AM, int U = 8>
-__device__ __forceinline__ void mono_task(const MonoArgs &a, int cg, int t,
-                                          unsigned long long &produced, unsigned long long &outs) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const Task *tp = a.tasks + t;
-    const int v0 = uni(tp->v0), v1 = uni(tp->v1), hub = uni(tp->hub), part = uni(tp->part);
-    const int64_t e0 = uni64(tp->e0), e1 = uni64(tp->e1);
-    const size_t cgv = (size_t)cg * (size_t)a.n;
-    const int32_t *Fv = a.fval + cgv * kWave;
-    const int32_t *Td = a.tval + (cgv + (size_t)v0) * kWave + lane;
-    const uint32_t *Ab = a.abits + (size_t)cg * a.nwords;
-    const int64_t rend = (hub < 0 && v0 + lane < v1) ? a.rp[v0 + lane + 1] : INT64_MAX;
-    int cur = -1, best = kInf, td = kInf;
-    uint64_t run_act = 0;
-    int un = 0, wn = 1;
-    if (e0 + lane < e1) load_arc<AM>(a.arcs, e0 + lane, un, wn);
-    for (int64_t e = e0; e < e1; e += kWave) {
-        const int64_t my = e + lane;
-        const int u = un, wt = wn;
-        const bool act = my < e1 && ((Ab[u >> 5] >> (u & 31)) & 1u);
-        if (my + kWave < e1) load_arc<AM>(a.arcs, my + kWave, un, wn);
-        uint64_t am = ballot(act);
-        while (am) {
-            int ow[U], wk[U], tk[U], tn[U];
-            int prev = cur;
+// widths are >= 1, so 0 is "no path"; the source's own width is unbounded
+struct OpWidest {
+    using V = int32_t;
+    __device__ static V absent() { return 0; }
+    __device__ static V seed() { return kInf; }
+    __device__ static V act(V x, int w) { return min(x, w); }
+    __device__ static V plus(V x, V y) { return max(x, y); }
+    __device__ static bool better(V x, V y) { return x > y; }
+};
+
+struct OpResist {
+    using V = float;
+    __device__ static V absent() { return __builtin_inff(); }
+    __device__ static V seed() { return 0.0f; }
+    // IEEE division (the library is built without fast-math) and one add:
+    // no fused multiply-add can form
+    __device__ static V act(V x, int w) { return x + 1.0f / (float)w; }
+    __device__ static V plus(V x, V y) { return y < x ? y : x; }
+    __device__ static bool better(V x, V y) { return x < y; }
+};
+
+template <class V, int W> struct Lanes;      // W values of one lane in one load
+template <> struct Lanes<int32_t, 1> { using T = int32_t; };
+template <> struct Lanes<int32_t, 2> { using T = int2; };
+template <> struct Lanes<float, 1> { using T = float; };
+template <> struct Lanes<float, 2> { using T = float2; };
+
+// ------------------------------------------------------------------ the policy
+// The fixpoint's product as an instance of pull_task / pull_hub: W column
+// groups per lane (1, or 2 in the paired layout), T in the one-group layout.
+template <class Op, int AM_, int W>
+struct MonoPull {
+    using V = typename Op::V;
+    using L = typename Lanes<V, W>::T;
+    static_assert(sizeof(V) == 4, "values live in the 4-byte workspace tiles");
+    static constexpr int AM = AM_;
+    static constexpr int U = W == 1 ? 8 : 4;
+    static constexpr int H = W == 1 ? 1 : 4;
+    struct Row { V x[W]; };
+    using Acc = Row;
+    using Own = Row;
+    const MonoArgs &a;
+    const int q, lane;
+    const size_t n, plane;
+    const L *Fv;
+    V *Tv;
+    const uint32_t *bits;
+    uint32_t *bits_n;
+    unsigned long long &produced, &outs;
+
+    __device__ __forceinline__ MonoPull(const MonoArgs &a_, int q_, unsigned long long &pr,
+                                        unsigned long long &ou)
+        : a(a_), q(q_), lane(threadIdx.x & (kWave - 1)), n((size_t)a_.n),
+          plane((size_t)a_.n * kWave), Fv((const L *)a_.fval + (size_t)q_ * plane),
+          Tv((V *)a_.tval + (size_t)W * q_ * plane), bits(a_.abits + (size_t)q_ * a_.nwords),
+          bits_n(a_.abits_n + (size_t)q_ * a_.nwords), produced(pr), outs(ou) {}
+
+    __device__ __forceinline__ static Row fill(V v) {
+        Row r;
 #pragma unroll
-            for (int k = 0; k < U; k++) {
-                const int j = am ? __ffsll((unsigned long long)am) - 1 : -1;
-                am &= am - 1;
-                ow[k] = -1;
-                wk[k] = 0;
-                tk[k] = kInf;
-                tn[k] = kInf;
-                if (j >= 0) {
-                    const int uk = rdlane(u, j);
-                    wk[k] = AM ? rdlane(wt, j) : 1;
-                    tk[k] = Fv[(size_t)uk * kWave + lane];
-                    ow[k] = __popcll(ballot(rend <= e + j));
-                    if (hub < 0 && ow[k] != prev) tn[k] = Td[(size_t)ow[k] * kWave];
-                    prev = ow[k];
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < U; k++) {
-                if (ow[k] >= 0) {
-                    if (ow[k] != cur) {
-                        if (cur >= 0 && hub < 0) {
-                            const uint64_t b = mono_finalize(a, cgv, v0 + cur, best, td, lane, outs);
-                            produced += __popcll(b);
-                            if (b) run_act |= 1ull << cur;
-                        }
-                        cur = ow[k];
-                        best = kInf;
-                        td = tn[k];
-                    }
-                    if (tk[k] != kInf) best = min(best, mono_act<OP>(tk[k], wk[k]));
-                }
-            }
-        }
+        for (int c = 0; c < W; c++) r.x[c] = v;
+        return r;
     }
-    if (hub < 0) {
-        if (cur >= 0) {
-            const uint64_t b = mono_finalize(a, cgv, v0 + cur, best, td, lane, outs);
+    __device__ __forceinline__ Row absent() const { return fill(Op::absent()); }
+    __device__ __forceinline__ Own none() const { return fill(Op::absent()); }
+    __device__ __forceinline__ Row gather(int u) const {
+        const L v = Fv[(size_t)u * kWave + lane];
+        Row r;
+        __builtin_memcpy(r.x, &v, sizeof(v));
+        return r;
+    }
+    __device__ __forceinline__ Own own(int v0, int o) const {
+        Own t;
+#pragma unroll
+        for (int c = 0; c < W; c++) t.x[c] = Tv[(size_t)c * plane + ((size_t)v0 + (size_t)o) * kWave + lane];
+        return t;
+    }
+    __device__ __forceinline__ void batch(Row (&)[U], const int (&)[U]) const {}
+    __device__ __forceinline__ void reset(Acc &x) const { x = fill(Op::absent()); }
+    __device__ __forceinline__ void fold(Acc &x, const Row &r, int w, int) const {
+#pragma unroll
+        for (int c = 0; c < W; c++)
+            if (r.x[c] != Op::absent()) x.x[c] = Op::plus(x.x[c], Op::act(r.x[c], w));
+    }
+    // T := T (+) acc at v; an entry that improved joins the next frontier
+    // (the whole row is written when any lane of any group joins).
+    __device__ __forceinline__ uint64_t finish(int v, const Acc &x, const Own &t) {
+        uint64_t any = 0;
+#pragma unroll
+        for (int c = 0; c < W; c++) {
+            const uint64_t h = ballot(x.x[c] != Op::absent());
+            outs += __popcll(h);
+            any |= h;
+        }
+        if (!any) return 0;
+        Row nx;
+        uint64_t kept = 0;
+#pragma unroll
+        for (int c = 0; c < W; c++) {
+            const bool keep = x.x[c] != Op::absent() && Op::better(x.x[c], t.x[c]);
+            if (keep) Tv[(size_t)c * plane + (size_t)v * kWave + lane] = x.x[c];
+            nx.x[c] = keep ? x.x[c] : Op::absent();
+            const uint64_t b = ballot(keep);
             produced += __popcll(b);
-            if (b) run_act |= 1ull << cur;
+            kept |= b;
         }
-        if (lane == 0 && run_act) or_run_bits(a.abits_n + (size_t)cg * a.nwords, v0, run_act);
-    } else {
-        a.pd[((size_t)cg * a.nslots + part) * kWave + lane] = best;
-    }
-}
-
-// Combine the slices of hub row h (min is order-free) and finish it.
-__device__ __forceinline__ void mono_hub(const MonoArgs &a, int cg, int h,
-                                         unsigned long long &produced, unsigned long long &outs) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const Hub *hp = a.hubs + h;
-    const int v = uni(hp->v), first = uni(hp->first), np = uni(hp->nparts);
-    const size_t cgv = (size_t)cg * (size_t)a.n;
-    int best = kInf;
-    for (int p = first; p < first + np; p++)
-        best = min(best, a.pd[((size_t)cg * a.nslots + p) * kWave + lane]);
-    const int td = a.tval[(cgv + (size_t)v) * kWave + lane];
-    const uint64_t b = mono_finalize(a, cgv, v, best, td, lane, outs);
-    produced += __popcll(b);
-    if (b && lane == 0) atomicOr(a.abits_n + (size_t)cg * a.nwords + (v >> 5), 1u << (v & 31));
-}
-
-// Paired form: groups 2q and 2q+1 at once (frontier values interleaved per
-// lane); T keeps the one-group layout.  Returns the lanes in the next
-// frontier in either group.
-__device__ __forceinline__ uint64_t mono_finalize2(const MonoArgs &a, int q, int v, int b0, int b1,
-                                                   int t0, int t1, int lane, unsigned long long &outs,
-                                                   unsigned long long &produced) {
-    const uint64_t h0 = ballot(b0 != kInf), h1 = ballot(b1 != kInf);
-    outs += __popcll(h0) + __popcll(h1);
-    if (!(h0 | h1)) return 0;
-    const size_t n = (size_t)a.n;
-    const size_t i0 = ((size_t)(2 * q) * n + (size_t)v) * kWave + lane, i1 = i0 + n * kWave;
-    const bool k0 = b0 != kInf && b0 < t0, k1 = b1 != kInf && b1 < t1;
-    if (k0) a.tval[i0] = b0;
-    if (k1) a.tval[i1] = b1;
-    const uint64_t m0 = ballot(k0), m1 = ballot(k1);
-    produced += __popcll(m0) + __popcll(m1);
-    if (m0 | m1)
-        ((int2 *)a.fval_n)[((size_t)q * n + (size_t)v) * kWave + lane] =
-            make_int2(k0 ? b0 : kInf, k1 ? b1 : kInf);
-    return m0 | m1;
-}
-
-template <int OP, int AM, int U = 4>
-__device__ __forceinline__ void mono_task2(const MonoArgs &a, int q, int t, unsigned long long &produced,
-                                           unsigned long long &outs) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const Task *tp = a.tasks + t;
-    const int v0 = uni(tp->v0), v1 = uni(tp->v1), hub = uni(tp->hub), part = uni(tp->part);
-    const int64_t e0 = uni64(tp->e0), e1 = uni64(tp->e1);
-    const size_t n = (size_t)a.n;
-    const int2 *Fv = (const int2 *)a.fval + (size_t)q * n * kWave;
-    const int32_t *Td0 = a.tval + ((size_t)(2 * q) * n + (size_t)v0) * kWave + lane;
-    const int32_t *Td1 = Td0 + n * kWave;
-    const uint32_t *Ab = a.abits + (size_t)q * a.nwords;
-    const int64_t rend = (hub < 0 && v0 + lane < v1) ? a.rp[v0 + lane + 1] : INT64_MAX;
-    int cur = -1, best0 = kInf, best1 = kInf, td0 = kInf, td1 = kInf;
-    uint64_t run_act = 0;
-    auto close = [&](int o) {
-        if (mono_finalize2(a, q, v0 + o, best0, best1, td0, td1, lane, outs, produced))
-            run_act |= 1ull << o;
-    };
-    int un = 0, wn = 1;
-    if (e0 + lane < e1) load_arc<AM>(a.arcs, e0 + lane, un, wn);
-    for (int64_t e = e0; e < e1; e += kWave) {
-        const int64_t my = e + lane;
-        const int u = un, wt = wn;
-        const bool act = my < e1 && ((Ab[u >> 5] >> (u & 31)) & 1u);
-        if (my + kWave < e1) load_arc<AM>(a.arcs, my + kWave, un, wn);
-        uint64_t am = ballot(act);
-        while (am) {
-            int ow[U], wk[U], tn0[U], tn1[U];
-            int2 tk[U];
-            int prev = cur;
-#pragma unroll
-            for (int k = 0; k < U; k++) {
-                const int j = am ? __ffsll((unsigned long long)am) - 1 : -1;
-                am &= am - 1;
-                ow[k] = -1;
-                wk[k] = 0;
-                tk[k] = make_int2(kInf, kInf);
-                tn0[k] = kInf;
-                tn1[k] = kInf;
-                if (j >= 0) {
-                    const int uk = rdlane(u, j);
-                    wk[k] = AM ? rdlane(wt, j) : 1;
-                    tk[k] = Fv[(size_t)uk * kWave + lane];
-                    ow[k] = __popcll(ballot(rend <= e + j));
-                    if (hub < 0 && ow[k] != prev) {
-                        tn0[k] = Td0[(size_t)ow[k] * kWave];
-                        tn1[k] = Td1[(size_t)ow[k] * kWave];
-                    }
-                    prev = ow[k];
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < U; k++) {
-                if (ow[k] >= 0) {
-                    if (ow[k] != cur) {
-                        if (cur >= 0 && hub < 0) close(cur);
-                        cur = ow[k];
-                        best0 = best1 = kInf;
-                        td0 = tn0[k];
-                        td1 = tn1[k];
-                    }
-                    if (tk[k].x != kInf) best0 = min(best0, mono_act<OP>(tk[k].x, wk[k]));
-                    if (tk[k].y != kInf) best1 = min(best1, mono_act<OP>(tk[k].y, wk[k]));
-                }
-            }
+        if (kept) {
+            L o;
+            __builtin_memcpy(&o, nx.x, sizeof(o));
+            ((L *)a.fval_n)[(size_t)q * plane + (size_t)v * kWave + lane] = o;
         }
+        return kept;
     }
-    if (hub < 0) {
-        if (cur >= 0) close(cur);
-        if (lane == 0 && run_act) or_run_bits(a.abits_n + (size_t)q * a.nwords, v0, run_act);
-    } else {
-        const size_t p0 = ((size_t)(2 * q) * a.nslots + part) * kWave + lane;
-        a.pd[p0] = best0;
-        a.pd[p0 + (size_t)a.nslots * kWave] = best1;
+    __device__ __forceinline__ size_t slot(int c, int part) const {
+        return ((size_t)(W * q + c) * a.nslots + part) * kWave + lane;
     }
-}
-
-__device__ __forceinline__ void mono_hub2(const MonoArgs &a, int q, int h, unsigned long long &produced,
-                                          unsigned long long &outs) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const Hub *hp = a.hubs + h;
-    const int v = uni(hp->v), first = uni(hp->first), np = uni(hp->nparts);
-    const size_t n = (size_t)a.n;
-    int b0 = kInf, b1 = kInf;
-    // four slices' partials in flight (min is order-free)
-    for (int p = first; p < first + np; p += 4) {
-        int d0[4], d1[4];
+    __device__ __forceinline__ void store(int part, const Acc &x) const {
 #pragma unroll
-        for (int k = 0; k < 4; k++) {
-            d0[k] = kInf;
-            d1[k] = kInf;
-            if (p + k < first + np) {
-                const size_t p0 = ((size_t)(2 * q) * a.nslots + p + k) * kWave + lane;
-                d0[k] = a.pd[p0];
-                d1[k] = a.pd[p0 + (size_t)a.nslots * kWave];
-            }
-        }
+        for (int c = 0; c < W; c++) ((V *)a.pd)[slot(c, part)] = x.x[c];
+    }
+    __device__ __forceinline__ Acc load(int part) const {
+        Acc x;
 #pragma unroll
-        for (int k = 0; k < 4; k++) {
-            b0 = min(b0, d0[k]);
-            b1 = min(b1, d1[k]);
-        }
+        for (int c = 0; c < W; c++) x.x[c] = ((const V *)a.pd)[slot(c, part)];
+        return x;
     }
-    const size_t i0 = ((size_t)(2 * q) * n + (size_t)v) * kWave + lane;
-    const int t0 = b0 != kInf ? a.tval[i0] : kInf;
-    const int t1 = b1 != kInf ? a.tval[i0 + n * kWave] : kInf;
-    const uint64_t b = mono_finalize2(a, q, v, b0, b1, t0, t1, lane, outs, produced);
-    if (b && lane == 0) atomicOr(a.abits_n + (size_t)q * a.nwords + (v >> 5), 1u << (v & 31));
-}
-
-template <int OP, int AM>
-__global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_mono_pull2(MonoArgs a) {
-    if (!live_prev(a.prev_ctr)) return;
-    const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    const int q = wid / a.ntasks;
-    unsigned long long produced = 0, outs = 0;
-    if (q < a.nwide) mono_task2<OP, AM>(a, q, wid - q * a.ntasks, produced, outs);
-    flush_counts(produced, outs, 0, 0, a.ctr);
-}
-
-__global__ __launch_bounds__(kBlock) void k_mono_merge2(MonoArgs a) {
-    const int gtid = blockIdx.x * kBlock + threadIdx.x;
-    if (!live_prev(a.prev_ctr)) {
-        if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
-        return;
+    __device__ __forceinline__ void merge(Acc &x, const Acc &y) const {
+#pragma unroll
+        for (int c = 0; c < W; c++) x.x[c] = Op::plus(x.x[c], y.x[c]);
     }
-    unsigned long long nv = 0, na = 0;
-    clear_and_count(a.clear_bits, a.nwords, a.nwide, a.rp, nv, na);
-    if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
-    const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    unsigned long long produced = 0, outs = 0;
-    const int q = a.nhubs ? wid / a.nhubs : a.nwide;
-    if (q < a.nwide) mono_hub2(a, q, wid - q * a.nhubs, produced, outs);
-    flush_counts(produced, outs, nv, na, a.ctr);
-}
+    __device__ __forceinline__ uint64_t finish_hub(int v, const Acc &x) {
+        Own t;
+#pragma unroll
+        for (int c = 0; c < W; c++)
+            t.x[c] = x.x[c] != Op::absent() ? Tv[(size_t)c * plane + (size_t)v * kWave + lane]
+                                            : Op::absent();
+        return finish(v, x, t);
+    }
+};
 
-// Seeds of the paired layout: a source's pair row starts with every lane of
-// both groups absent, then its own lane carries 0.
-__global__ void k_mono_seed_rows2(const int32_t *src, int nb, int n, int2 *fval) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nb) return;
-    const size_t row = ((size_t)(c / (2 * kWave)) * n + src[c]) * kWave;
-    for (int l = 0; l < kWave; l++) fval[row + l] = make_int2(kInf, kInf);
-}
-
-__global__ void k_mono_seed2(const int32_t *src, int nb, int n, int nwords, int32_t *tval,
-                             int32_t *fval, uint32_t *abits) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nb) return;
-    const int v = src[c];
-    const int cg = c / kWave, lane = c % kWave, q = cg >> 1;
-    tval[((size_t)cg * n + v) * kWave + lane] = 0;
-    fval[(((size_t)q * n + v) * kWave + lane) * 2 + (cg & 1)] = 0;
-    atomicOr(abits + (size_t)q * nwords + (v >> 5), 1u << (v & 31));
-}
-
-template <int OP, int AM>
+// ------------------------------------------------------------------ kernels
+template <class Op, int AM, int W>
 __global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_mono_pull(MonoArgs a) {
     if (!live_prev(a.prev_ctr)) return;
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-    const int cg = wid / a.ntasks;
+    const int groups = W == 1 ? a.ncg : a.nwide;
+    const int q = wid / a.ntasks;
     unsigned long long produced = 0, outs = 0;
-    if (cg < a.ncg) mono_task<OP, AM>(a, cg, wid - cg * a.ntasks, produced, outs);
+    if (q < groups) {
+        MonoPull<Op, AM, W> p(a, q, produced, outs);
+        pull_task(p, a.tasks + (wid - q * a.ntasks), a.rp, a.arcs);
+    }
     flush_counts(produced, outs, 0, 0, a.ctr);
 }
 
+// Hub slices of F_{j-1}'s product; also clears F_{j-1}'s bitmaps (counting
+// its vertices and their arcs) and the counters of product j+1.
+template <class Op, int W>
 __global__ __launch_bounds__(kBlock) void k_mono_merge(MonoArgs a) {
     const int gtid = blockIdx.x * kBlock + threadIdx.x;
     if (!live_prev(a.prev_ctr)) {
         if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
         return;
     }
+    const int groups = W == 1 ? a.ncg : a.nwide;
     unsigned long long nv = 0, na = 0;
-    clear_and_count(a.clear_bits, a.nwords, a.ncg, a.rp, nv, na);
+    clear_and_count(a.clear_bits, a.nwords, groups, a.rp, nv, na);
     if (gtid < 4 * kCounterSlots) a.clear_ctr[gtid] = 0ull;
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     unsigned long long produced = 0, outs = 0;
-    const int cg = a.nhubs ? wid / a.nhubs : a.ncg;
-    if (cg < a.ncg) mono_hub(a, cg, wid - cg * a.nhubs, produced, outs);
+    const int q = a.nhubs ? wid / a.nhubs : groups;
+    if (q < groups) {
+        MonoPull<Op, 0, W> p(a, q, produced, outs);
+        pull_hub(p, a.hubs + (wid - q * a.nhubs));
+    }
     flush_counts(produced, outs, nv, na, a.ctr);
 }
 
-// T = INF everywhere, both bitmaps and all counters cleared.
-__global__ void k_mono_fill(int32_t *tval, size_t total, uint32_t *ab0, uint32_t *ab1, size_t nab,
+// T = absent everywhere, both bitmaps and all counters cleared.
+template <class Op>
+__global__ void k_mono_fill(typename Op::V *tval, size_t total, uint32_t *ab0, uint32_t *ab1, size_t nab,
                             unsigned long long *ctr, int nctr) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (size_t i = t0; i < total; i += stride) tval[i] = kInf;
+    for (size_t i = t0; i < total; i += stride) tval[i] = Op::absent();
     for (size_t i = t0; i < nab; i += stride) {
         ab0[i] = 0u;
         ab1[i] = 0u;
@@ -370,25 +261,27 @@ __global__ void k_mono_fill(int32_t *tval, size_t total, uint32_t *ab0, uint32_t
     for (size_t i = t0; i < (size_t)nctr; i += stride) ctr[i] = 0ull;
 }
 
-// The sources' rows of the first frontier start with every lane absent ...
-__global__ void k_mono_seed_rows(const int32_t *src, int nb, int n, int32_t *fval) {
+// The sources' rows of the first frontier start with every lane of their
+// plane absent (W groups per lane) ...
+template <class Op, int W>
+__global__ void k_mono_seed_rows(const int32_t *src, int nb, int n, typename Op::V *fval) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nb) return;
-    const size_t row = ((size_t)(c / kWave) * n + src[c]) * kWave;
-    for (int l = 0; l < kWave; l++) fval[row + l] = kInf;
+    const size_t row = ((size_t)(c / (W * kWave)) * n + src[c]) * kWave * W;
+    for (int l = 0; l < kWave * W; l++) fval[row + l] = Op::absent();
 }
 
-// ... then T(s, s) = 0 and the first frontier is {s} carrying 0.
-__global__ void k_mono_seed(const int32_t *src, int nb, int n, int nwords, int32_t *tval,
-                            int32_t *fval, uint32_t *abits) {
+// ... then T(s, s) = the seed and the first frontier is {s} carrying it.
+template <class Op, int W>
+__global__ void k_mono_seed(const int32_t *src, int nb, int n, int nwords, typename Op::V *tval,
+                            typename Op::V *fval, uint32_t *abits) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nb) return;
     const int v = src[c];
-    const int cg = c / kWave, lane = c % kWave;
-    const size_t idx = ((size_t)cg * n + v) * kWave + lane;
-    tval[idx] = 0;
-    fval[idx] = 0;
-    atomicOr(abits + (size_t)cg * nwords + (v >> 5), 1u << (v & 31));
+    const int cg = c / kWave, lane = c % kWave, q = cg / W;
+    tval[((size_t)cg * n + v) * kWave + lane] = Op::seed();
+    fval[(((size_t)q * n + v) * kWave + lane) * W + (cg % W)] = Op::seed();
+    atomicOr(abits + (size_t)q * nwords + (v >> 5), 1u << (v & 31));
 }
 
 inline int nblk(size_t work, int per, int cap = 0x7fffffff) {
@@ -408,20 +301,12 @@ ArcSrc mono_arcs(const Csr &c) {
 
 int mono_mode(const Csr &c) { return c.w == nullptr ? 0 : (c.pk ? 1 : 2); }
 
-template <int OP>
+template <class Op, int W>
 void launch_pull(int mode, int grid, hipStream_t s, const MonoArgs &a) {
-    if (a.nwide) {
-        switch (mode) {
-            case 0: hipLaunchKernelGGL((k_mono_pull2<OP, 0>), dim3(grid), dim3(kBlock), 0, s, a); break;
-            case 1: hipLaunchKernelGGL((k_mono_pull2<OP, 1>), dim3(grid), dim3(kBlock), 0, s, a); break;
-            default: hipLaunchKernelGGL((k_mono_pull2<OP, 2>), dim3(grid), dim3(kBlock), 0, s, a); break;
-        }
-        return;
-    }
     switch (mode) {
-        case 0: hipLaunchKernelGGL((k_mono_pull<OP, 0>), dim3(grid), dim3(kBlock), 0, s, a); break;
-        case 1: hipLaunchKernelGGL((k_mono_pull<OP, 1>), dim3(grid), dim3(kBlock), 0, s, a); break;
-        default: hipLaunchKernelGGL((k_mono_pull<OP, 2>), dim3(grid), dim3(kBlock), 0, s, a); break;
+        case 0: hipLaunchKernelGGL((k_mono_pull<Op, 0, W>), dim3(grid), dim3(kBlock), 0, s, a); break;
+        case 1: hipLaunchKernelGGL((k_mono_pull<Op, 1, W>), dim3(grid), dim3(kBlock), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_mono_pull<Op, 2, W>), dim3(grid), dim3(kBlock), 0, s, a); break;
     }
 }
 
@@ -429,29 +314,30 @@ void launch_pull(int mode, int grid, hipStream_t s, const MonoArgs &a) {
 // number of groups).
 int mono_pairs(int ncg) { return ncg >= 2 ? (ncg + 1) / 2 : 0; }
 
-}  // namespace
-
-void launch_mono_init(mfbc_graph *g, int ncg, int nb, hipStream_t s) {
+template <class Op>
+void mono_init(mfbc_graph *g, int ncg, int nb, hipStream_t s) {
+    using V = typename Op::V;
     Workspace &ws = g->ws;
     const size_t total = (size_t)ncg * g->n * kWave;
     const int nwords = (g->n + 31) / 32;
-    hipLaunchKernelGGL(k_mono_fill, dim3(nblk(total, 256, 65536)), dim3(256), 0, s, ws.tdist, total,
-                       ws.abits[0], ws.abits[1], (size_t)ncg * nwords, ws.counters,
+    hipLaunchKernelGGL(k_mono_fill<Op>, dim3(nblk(total, 256, 65536)), dim3(256), 0, s, (V *)ws.tdist,
+                       total, ws.abits[0], ws.abits[1], (size_t)ncg * nwords, ws.counters,
                        kCounterRing * 4 * kCounterSlots);
     if (mono_pairs(ncg)) {
-        hipLaunchKernelGGL(k_mono_seed_rows2, dim3(nblk(nb, 256)), dim3(256), 0, s, ws.src, nb, g->n,
-                           (int2 *)ws.fdist[0]);
-        hipLaunchKernelGGL(k_mono_seed2, dim3(nblk(nb, 256)), dim3(256), 0, s, ws.src, nb, g->n,
-                           nwords, ws.tdist, ws.fdist[0], ws.abits[0]);
+        hipLaunchKernelGGL((k_mono_seed_rows<Op, 2>), dim3(nblk(nb, 256)), dim3(256), 0, s, ws.src, nb,
+                           g->n, (V *)ws.fdist[0]);
+        hipLaunchKernelGGL((k_mono_seed<Op, 2>), dim3(nblk(nb, 256)), dim3(256), 0, s, ws.src, nb, g->n,
+                           nwords, (V *)ws.tdist, (V *)ws.fdist[0], ws.abits[0]);
         return;
     }
-    hipLaunchKernelGGL(k_mono_seed_rows, dim3(nblk(nb, 256)), dim3(256), 0, s, ws.src, nb, g->n,
-                       ws.fdist[0]);
-    hipLaunchKernelGGL(k_mono_seed, dim3(nblk(nb, 256)), dim3(256), 0, s, ws.src, nb, g->n, nwords,
-                       ws.tdist, ws.fdist[0], ws.abits[0]);
+    hipLaunchKernelGGL((k_mono_seed_rows<Op, 1>), dim3(nblk(nb, 256)), dim3(256), 0, s, ws.src, nb, g->n,
+                       (V *)ws.fdist[0]);
+    hipLaunchKernelGGL((k_mono_seed<Op, 1>), dim3(nblk(nb, 256)), dim3(256), 0, s, ws.src, nb, g->n,
+                       nwords, (V *)ws.tdist, (V *)ws.fdist[0], ws.abits[0]);
 }
 
-void launch_mono_product(mfbc_graph *g, int op, int ncg, int j, hipStream_t s, hipEvent_t *ev) {
+template <class Op>
+void mono_product(mfbc_graph *g, int ncg, int j, hipStream_t s, hipEvent_t *ev) {
     Workspace &ws = g->ws;
     const int b = (j - 1) & 1;      // buffer holding F_{j-1}
     MonoArgs a{};
@@ -479,16 +365,40 @@ void launch_mono_product(mfbc_graph *g, int op, int ncg, int j, hipStream_t s, h
     const int waves_per_task = a.nwide ? a.nwide : ncg;
     if (ev) (void)hipEventRecord(ev[0], s);
     const int grid = nblk((size_t)a.ntasks * waves_per_task, kWavesPerBlock);
-    if (op == 0) launch_pull<0>(mono_mode(g->in), grid, s, a);
-    else launch_pull<1>(mono_mode(g->in), grid, s, a);
+    if (a.nwide) launch_pull<Op, 2>(mono_mode(g->in), grid, s, a);
+    else launch_pull<Op, 1>(mono_mode(g->in), grid, s, a);
     if (ev) (void)hipEventRecord(ev[1], s);
     const int mgrid = std::max(nblk((size_t)a.nhubs * waves_per_task, kWavesPerBlock),
                                nblk((size_t)a.nwords, kBlock, 1024));
     if (a.nwide)
-        hipLaunchKernelGGL(k_mono_merge2, dim3(mgrid), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL((k_mono_merge<Op, 2>), dim3(mgrid), dim3(kBlock), 0, s, a);
     else
-        hipLaunchKernelGGL(k_mono_merge, dim3(mgrid), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL((k_mono_merge<Op, 1>), dim3(mgrid), dim3(kBlock), 0, s, a);
     if (ev) (void)hipEventRecord(ev[2], s);
+}
+
+}  // namespace
+
+bool mono_op_known(int op) {
+    return op == MFBC_OP_SSSP || op == MFBC_OP_BFS || op == MFBC_OP_WIDEST || op == MFBC_OP_RESIST;
+}
+
+void launch_mono_init(mfbc_graph *g, int op, int ncg, int nb, hipStream_t s) {
+    switch (op) {
+        case MFBC_OP_SSSP: mono_init<OpSssp>(g, ncg, nb, s); break;
+        case MFBC_OP_BFS: mono_init<OpBfs>(g, ncg, nb, s); break;
+        case MFBC_OP_WIDEST: mono_init<OpWidest>(g, ncg, nb, s); break;
+        default: mono_init<OpResist>(g, ncg, nb, s); break;
+    }
+}
+
+void launch_mono_product(mfbc_graph *g, int op, int ncg, int j, hipStream_t s, hipEvent_t *ev) {
+    switch (op) {
+        case MFBC_OP_SSSP: mono_product<OpSssp>(g, ncg, j, s, ev); break;
+        case MFBC_OP_BFS: mono_product<OpBfs>(g, ncg, j, s, ev); break;
+        case MFBC_OP_WIDEST: mono_product<OpWidest>(g, ncg, j, s, ev); break;
+        default: mono_product<OpResist>(g, ncg, j, s, ev); break;
+    }
 }
 
 }  // namespace mfbc

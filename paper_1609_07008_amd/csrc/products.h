@@ -6,39 +6,11 @@
 // scheduled (one grid per product, or a workgroup looping over them).
 #pragma once
 
-#include "mfbc_internal.h"
+#include "pull.h"
 
 namespace mfbc {
 namespace {
 
-
-__device__ __forceinline__ int rdlane(int x, int j) { return __builtin_amdgcn_readlane(x, j); }
-
-__device__ __forceinline__ uint64_t rdlane64(uint64_t x, int j) {
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, j);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), j);
-    return ((uint64_t)hi << 32) | lo;
-}
-
-__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
-
-__device__ __forceinline__ int64_t uni64(int64_t x) {
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)x >> 32));
-    return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
-__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
-
-// Set the bits of `mask` (bit i = vertex v0 + i) in a vertex bitmap.
-__device__ __forceinline__ void or_run_bits(uint32_t *bm, int v0, uint64_t mask) {
-    const int w0 = v0 >> 5, sh = v0 & 31;
-    const uint64_t lo = mask << sh;
-    const uint32_t hi = sh ? (uint32_t)(mask >> (64 - sh)) : 0u;
-    if ((uint32_t)lo) atomicOr(bm + w0, (uint32_t)lo);
-    if ((uint32_t)(lo >> 32)) atomicOr(bm + w0 + 1, (uint32_t)(lo >> 32));
-    if (hi) atomicOr(bm + w0 + 2, hi);
-}
 
 // Sum of a per-lane double over the wave in a fixed butterfly order.
 __device__ __forceinline__ double wave_sum(double x) {
@@ -149,27 +121,6 @@ __device__ __forceinline__ void flush_colmask(unsigned long long *colmask, int n
 // multiplicity is small, so the 8-byte escape is rarely read.
 constexpr uint32_t kSent = 0xffffffffu;
 
-// Arc access: AM = 0 unweighted (col), 1 packed (col | w << cb), 2 separate arrays.
-struct ArcSrc {
-    const int32_t *col;
-    const int32_t *w;
-    const uint32_t *pk;
-    int cb;
-    uint32_t cmask;
-};
-
-template <int AM>
-__device__ __forceinline__ void load_arc(const ArcSrc &s, int64_t e, int &u, int &wt) {
-    if (AM == 1) {
-        const uint32_t p = s.pk[e];
-        u = (int)(p & s.cmask);
-        wt = (int)(p >> s.cb);
-    } else {
-        u = s.col[e];
-        wt = AM == 2 ? s.w[e] : 1;
-    }
-}
-
 struct FwdArgs {
     const Task *tasks;
     const Hub *hubs;
@@ -254,156 +205,6 @@ __device__ __forceinline__ uint32_t fwd_update(const FwdArgs &a, size_t idx, int
 template <int AM> constexpr int kFwdBatch = AM == 0 ? 4 : 6;
 template <int AM> constexpr bool kFwdEscBatch = AM == 0;
 
-// One pull task of the forward product (see Task) for column group cg.
-//
-// The arcs of the task are read 64 at a time; the active ones (source row in
-// the frontier of some lane) are taken U at a time in arc order, whatever
-// rows they belong to, and their tuple loads -- plus the T row of every
-// owner that starts in the batch -- are issued together, so one memory round
-// trip serves several short rows.  The batch is then folded in arc order,
-// each owner being finished when the next arc belongs to a later one.
-template <int AM, int U = kFwdBatch<AM>>
-__device__ __forceinline__ void fwd_task(const FwdArgs &a, int cg, int t, unsigned long long &produced, unsigned long long &outs) {
-    const int lane = threadIdx.x & (kWave - 1);
-    uint64_t colany = 0;
-    const Task *tp = a.tasks + t;
-    const int v0 = uni(tp->v0), v1 = uni(tp->v1), hub = uni(tp->hub), part = uni(tp->part);
-    const int64_t e0 = uni64(tp->e0), e1 = uni64(tp->e1);
-    const size_t cgv = (size_t)cg * (size_t)a.n;
-    const uint32_t *Ft = a.ftup + cgv * kWave;
-    const double *Fm = a.fsig + cgv * kWave;
-    const int32_t *Td = a.tdist + (cgv + (size_t)v0) * kWave + lane;
-    const uint32_t *Ab = a.abits + (size_t)cg * a.nwords;
-    const uint32_t mmask = (1u << a.mb) - 1u;
-    // end of each owner's arcs, one owner per lane (a run has at most 64
-    // rows); the owner of arc p is the number of rows ending at or before p.
-    // A slice of a hub row has the one owner.
-    const int64_t rend = (hub < 0 && v0 + lane < v1) ? a.rp[v0 + lane + 1] : INT64_MAX;
-    int cur = -1;            // owner (offset from v0) of the open accumulation
-    int bd = kInf, td = kInf;
-    double bm = 0.0;
-    uint64_t run_act = 0;
-    auto close = [&](int o) {
-        const uint64_t b = fwd_finalize(a, cgv, v0 + o, bd, bm, td, lane, outs);
-        produced += __popcll(b);
-        colany |= b;
-        if (b) run_act |= 1ull << o;
-    };
-    // the arc words of the next 64-arc chunk are loaded while the current
-    // chunk is processed
-    int un = 0, wn = 1;
-    if (e0 + lane < e1) load_arc<AM>(a.arcs, e0 + lane, un, wn);
-    for (int64_t e = e0; e < e1; e += kWave) {
-        const int64_t my = e + lane;
-        const int u = un, wt = wn;
-        const bool act = my < e1 && ((Ab[u >> 5] >> (u & 31)) & 1u);
-        if (my + kWave < e1) load_arc<AM>(a.arcs, my + kWave, un, wn);
-        uint64_t am = ballot(act);
-        while (am) {
-            int ow[U], wk[U], uk[U], tn[U];
-            uint32_t tk[U];
-            int prev = cur;
-#pragma unroll
-            for (int k = 0; k < U; k++) {
-                const int j = am ? __ffsll((unsigned long long)am) - 1 : -1;
-                am &= am - 1;
-                ow[k] = -1;
-                uk[k] = 0;
-                wk[k] = 0;
-                tk[k] = kSent;
-                tn[k] = kInf;
-                if (j >= 0) {
-                    uk[k] = rdlane(u, j);
-                    wk[k] = AM ? rdlane(wt, j) : 1;
-                    tk[k] = Ft[(size_t)uk[k] * kWave + lane];
-                    ow[k] = __popcll(ballot(rend <= e + j));
-                    if (hub < 0 && ow[k] != prev) tn[k] = Td[(size_t)ow[k] * kWave];
-                    prev = ow[k];
-                }
-            }
-            // escaped multiplicities of the batch, read together (rare when
-            // weights are drawn from a wide range; common in unweighted graphs)
-            double em[U];
-#pragma unroll
-            for (int k = 0; k < U; k++) em[k] = 0.0;
-            if constexpr (kFwdEscBatch<AM>) {
-                bool esc = false;
-#pragma unroll
-                for (int k = 0; k < U; k++) esc |= tk[k] != kSent && (tk[k] & mmask) == 0u;
-                if (ballot(esc)) {
-#pragma unroll
-                    for (int k = 0; k < U; k++)
-                        if (tk[k] != kSent && (tk[k] & mmask) == 0u)
-                            em[k] = Fm[(size_t)uk[k] * kWave + lane];
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < U; k++) {
-                if (ow[k] >= 0) {
-                    if (ow[k] != cur) {
-                        if (cur >= 0 && hub < 0) close(cur);
-                        cur = ow[k];
-                        bd = kInf;
-                        bm = 0.0;
-                        td = tn[k];
-                    }
-                    const int d = (int)(tk[k] >> a.mb) + wk[k];
-                    if (tk[k] != kSent && d <= bd) {
-                        const uint32_t ms = tk[k] & mmask;
-                        double m = (double)ms;
-                        if (!ms) m = kFwdEscBatch<AM> ? em[k] : Fm[(size_t)uk[k] * kWave + lane];
-                        if (d < bd) {
-                            bd = d;
-                            bm = m;
-                        } else {
-                            bm += m;
-                        }
-                    }
-                }
-            }
-        }
-    }
-    if (hub < 0) {
-        if (cur >= 0) close(cur);
-        if (lane == 0 && run_act) or_run_bits(a.abits_n + (size_t)cg * a.nwords, v0, run_act);
-    } else {
-        const size_t pidx = ((size_t)cg * a.nslots + part) * kWave + lane;
-        a.pd[pidx] = bd;
-        a.pm[pidx] = bm;
-    }
-    flush_colmask(a.colmask, a.ncg_all, cg, colany);
-}
-
-// Combine the slices of split row h (fixed slice order) and finish it.
-// The merge kernel also clears the previous frontier's bitmaps (counting
-// the vertices active in some column and their arcs) and the next
-// product's counters.
-__device__ __forceinline__ void fwd_hub(const FwdArgs &a, int cg, int h, unsigned long long &produced, unsigned long long &outs) {
-    const int lane = threadIdx.x & (kWave - 1);
-    uint64_t colany = 0;
-    const Hub *hp = a.hubs + h;
-    const int v = uni(hp->v), first = uni(hp->first), np = uni(hp->nparts);
-    const size_t cgv = (size_t)cg * (size_t)a.n;
-    int bd = kInf;
-    double bm = 0.0;
-    for (int p = first; p < first + np; p++) {
-        const size_t pidx = ((size_t)cg * a.nslots + p) * kWave + lane;
-        const int d = a.pd[pidx];
-        const double m = a.pm[pidx];
-        if (d < bd) {
-            bd = d;
-            bm = m;
-        } else if (d == bd && d != kInf) {
-            bm += m;
-        }
-    }
-    const uint64_t b = fwd_finalize(a, cgv, v, bd, bm, kLoadTd, lane, outs);
-    produced += __popcll(b);
-    colany |= b;
-    if (b && lane == 0) atomicOr(a.abits_n + (size_t)cg * a.nwords + (v >> 5), 1u << (v & 31));
-    flush_colmask(a.colmask, a.ncg_all, cg, colany);
-}
-
 // ===================================================================== forward, wide
 //
 // The plain path runs the forward product on W = 2 column groups at once: the frontier rows of groups Wq .. Wq+W-1 are interleaved ([q][v][64]
@@ -474,194 +275,219 @@ __device__ __forceinline__ void flush_colmask_w(const FwdArgs &a, int q, const u
         if (W * q + c < a.ncg_all) flush_colmask(a.colmask, a.ncg_all, W * q + c, colany[c]);
 }
 
-// One pull task of the forward product (see fwd_task) for wide group q.
-template <int AM, int W, int U = kFwdBatchW<AM, W>>
-__device__ __forceinline__ void fwd_task_w(const FwdArgs &a, int q, int t, unsigned long long &produced,
-                                           unsigned long long &outs) {
-    using V = typename WideT<W>::T;
-    const int lane = threadIdx.x & (kWave - 1);
-    const Task *tp = a.tasks + t;
-    const int v0 = uni(tp->v0), v1 = uni(tp->v1), hub = uni(tp->hub), part = uni(tp->part);
-    const int64_t e0 = uni64(tp->e0), e1 = uni64(tp->e1);
-    const size_t n = (size_t)a.n, plane = n * kWave;
-    const V *Ft = (const V *)a.ftup + (size_t)q * plane;
-    const double *Fm = a.fsig + (size_t)(W * q) * plane;        // group c at Fm + c * plane
-    const int32_t *Td = a.tdist + ((size_t)(W * q) * n + (size_t)v0) * kWave + lane;
-    const uint32_t *Ab = a.abits + (size_t)q * a.nwords;
-    const uint32_t mmask = (1u << a.mb) - 1u;
-    const int64_t rend = (hub < 0 && v0 + lane < v1) ? a.rp[v0 + lane + 1] : INT64_MAX;
-    int cur = -1;
-    int bd[W], td[W];
-    double bm[W];
-#pragma unroll
-    for (int c = 0; c < W; c++) {
-        bd[c] = kInf;
-        td[c] = kInf;
-        bm[c] = 0.0;
-    }
-    uint64_t run_act = 0, colany[W];
-#pragma unroll
-    for (int c = 0; c < W; c++) colany[c] = 0;
-    auto close = [&](int o) {
-        if (fwd_finalize_w<W>(a, q, v0 + o, bd, bm, td, lane, outs, produced, colany))
-            run_act |= 1ull << o;
+// ===================================================================== forward product
+//
+// MFBF's forward product as an instance of the generic pull product
+// (pull_task / pull_hub): (+) is the multpaths monoid (the least weight
+// wins, the multiplicities of equal weights add up), f(a, w) = (a.w + w,
+// a.m), over the packed tuples of W column groups per lane: W = 1 reads the
+// one-group tiles [cg][v][64], W = 2 the pair layout.  T and the escaped
+// multiplicities keep the one-group layout in both.
+template <int AM_, int W, int U_ = (W == 1 ? kFwdBatch<AM_> : kFwdBatchW<AM_, W>)>
+struct FwdPull {
+    static constexpr int AM = AM_;
+    static constexpr int U = U_;
+    static constexpr int H = W == 1 ? 1 : 4;
+    static constexpr bool kEsc = kFwdEscBatch<AM_>;
+    struct RowLazy {
+        uint32_t t[W];
     };
-    int un = 0, wn = 1;
-    if (e0 + lane < e1) load_arc<AM>(a.arcs, e0 + lane, un, wn);
-    for (int64_t e = e0; e < e1; e += kWave) {
-        const int64_t my = e + lane;
-        const int u = un, wt = wn;
-        const bool act = my < e1 && ((Ab[u >> 5] >> (u & 31)) & 1u);
-        if (my + kWave < e1) load_arc<AM>(a.arcs, my + kWave, un, wn);
-        uint64_t am = ballot(act);
-        while (am) {
-            int ow[U], wk[U], uk[U];
-            int tn[U][W];
-            uint32_t tk[U][W];
-            int prev = cur;
+    struct RowEsc {
+        uint32_t t[W];
+        double em[W];          // escaped multiplicities, read with the batch
+    };
+    using Row = std::conditional_t<kEsc, RowEsc, RowLazy>;
+    struct Acc {
+        int d[W];
+        double m[W];
+    };
+    struct Own {
+        int t[W];
+    };
+    const FwdArgs &a;
+    const int q, lane;         // the wave's column group (W = 1) or pair of groups
+    const size_t n, plane;
+    const uint32_t *Ft;        // frontier tuples of the wave's groups
+    const double *Fm;          // escaped multiplicities, group c at Fm + c * plane
+    const uint32_t *bits;
+    uint32_t *bits_n;
+    const uint32_t mmask;
+    unsigned long long &produced, &outs;
+    uint64_t colany[W];        // lanes of each group that produced entries
+
+    __device__ __forceinline__ FwdPull(const FwdArgs &a_, int q_, unsigned long long &pr,
+                                       unsigned long long &ou)
+        : a(a_), q(q_), lane(threadIdx.x & (kWave - 1)), n((size_t)a_.n),
+          plane((size_t)a_.n * kWave), Ft(a_.ftup + (size_t)W * q_ * plane),
+          Fm(a_.fsig + (size_t)W * q_ * plane), bits(a_.abits + (size_t)q_ * a_.nwords),
+          bits_n(a_.abits_n + (size_t)q_ * a_.nwords), mmask((1u << a_.mb) - 1u), produced(pr),
+          outs(ou) {
 #pragma unroll
-            for (int k = 0; k < U; k++) {
-                const int j = am ? __ffsll((unsigned long long)am) - 1 : -1;
-                am &= am - 1;
-                ow[k] = -1;
-                uk[k] = 0;
-                wk[k] = 0;
+        for (int c = 0; c < W; c++) colany[c] = 0;
+    }
+    __device__ __forceinline__ Row absent() const {
+        Row r;
 #pragma unroll
-                for (int c = 0; c < W; c++) {
-                    tk[k][c] = kSent;
-                    tn[k][c] = kInf;
-                }
-                if (j >= 0) {
-                    uk[k] = rdlane(u, j);
-                    wk[k] = AM ? rdlane(wt, j) : 1;
-                    unpack(Ft[(size_t)uk[k] * kWave + lane], tk[k]);
-                    ow[k] = __popcll(ballot(rend <= e + j));
-                    if (hub < 0 && ow[k] != prev) {
+        for (int c = 0; c < W; c++) {
+            r.t[c] = kSent;
+            if constexpr (kEsc) r.em[c] = 0.0;
+        }
+        return r;
+    }
+    __device__ __forceinline__ Own none() const {
+        Own o;
 #pragma unroll
-                        for (int c = 0; c < W; c++) tn[k][c] = Td[(size_t)c * plane + (size_t)ow[k] * kWave];
-                    }
-                    prev = ow[k];
-                }
-            }
-            double em[U][W];
+        for (int c = 0; c < W; c++) o.t[c] = kInf;
+        return o;
+    }
+    __device__ __forceinline__ Row gather(int u) const {
+        Row r = absent();
+        if constexpr (W == 1) r.t[0] = Ft[(size_t)u * kWave + lane];
+        else unpack(((const typename WideT<W>::T *)Ft)[(size_t)u * kWave + lane], r.t);
+        return r;
+    }
+    __device__ __forceinline__ Own own(int v0, int o) const {
+        const int32_t *Td = a.tdist + ((size_t)(W * q) * n + (size_t)v0) * kWave + lane;
+        Own t;
+#pragma unroll
+        for (int c = 0; c < W; c++) t.t[c] = Td[(size_t)c * plane + (size_t)o * kWave];
+        return t;
+    }
+    // escaped multiplicities of the batch, read together (rare when weights
+    // are drawn from a wide range; common in unweighted graphs)
+    __device__ __forceinline__ void batch(Row (&r)[U], const int (&us)[U]) const {
+        if constexpr (kEsc) {
+            bool esc = false;
 #pragma unroll
             for (int k = 0; k < U; k++)
 #pragma unroll
-                for (int c = 0; c < W; c++) em[k][c] = 0.0;
-            if constexpr (kFwdEscBatch<AM>) {
-                bool esc = false;
+                for (int c = 0; c < W; c++) esc |= r[k].t[c] != kSent && (r[k].t[c] & mmask) == 0u;
+            if (ballot(esc)) {
 #pragma unroll
                 for (int k = 0; k < U; k++)
 #pragma unroll
-                    for (int c = 0; c < W; c++) esc |= tk[k][c] != kSent && (tk[k][c] & mmask) == 0u;
-                if (ballot(esc)) {
-#pragma unroll
-                    for (int k = 0; k < U; k++)
-#pragma unroll
-                        for (int c = 0; c < W; c++)
-                            if (tk[k][c] != kSent && (tk[k][c] & mmask) == 0u)
-                                em[k][c] = Fm[(size_t)c * plane + (size_t)uk[k] * kWave + lane];
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < U; k++) {
-                if (ow[k] >= 0) {
-                    if (ow[k] != cur) {
-                        if (cur >= 0 && hub < 0) close(cur);
-                        cur = ow[k];
-#pragma unroll
-                        for (int c = 0; c < W; c++) {
-                            bd[c] = kInf;
-                            bm[c] = 0.0;
-                            td[c] = tn[k][c];
-                        }
-                    }
-#pragma unroll
-                    for (int c = 0; c < W; c++) {
-                        const uint32_t x = tk[k][c];
-                        const int d = (int)(x >> a.mb) + wk[k];
-                        if (x != kSent && d <= bd[c]) {
-                            const uint32_t ms = x & mmask;
-                            double m = (double)ms;
-                            if (!ms)
-                                m = kFwdEscBatch<AM> ? em[k][c]
-                                                     : Fm[(size_t)c * plane + (size_t)uk[k] * kWave + lane];
-                            if (d < bd[c]) {
-                                bd[c] = d;
-                                bm[c] = m;
-                            } else {
-                                bm[c] += m;
-                            }
-                        }
-                    }
-                }
+                    for (int c = 0; c < W; c++)
+                        if (r[k].t[c] != kSent && (r[k].t[c] & mmask) == 0u)
+                            r[k].em[c] = Fm[(size_t)c * plane + (size_t)us[k] * kWave + lane];
             }
         }
     }
-    if (hub < 0) {
-        if (cur >= 0) close(cur);
-        if (lane == 0 && run_act) or_run_bits(a.abits_n + (size_t)q * a.nwords, v0, run_act);
-    } else {
+    __device__ __forceinline__ void reset(Acc &x) const {
 #pragma unroll
         for (int c = 0; c < W; c++) {
-            const size_t pidx = ((size_t)(W * q + c) * a.nslots + part) * kWave + lane;
-            a.pd[pidx] = bd[c];
-            a.pm[pidx] = bm[c];
+            x.d[c] = kInf;
+            x.m[c] = 0.0;
         }
     }
-    if (a.colmask) flush_colmask_w<W>(a, q, colany);
+    __device__ __forceinline__ void fold(Acc &x, const Row &r, int w, int u) const {
+#pragma unroll
+        for (int c = 0; c < W; c++) {
+            const uint32_t t = r.t[c];
+            const int d = (int)(t >> a.mb) + w;
+            if (t != kSent && d <= x.d[c]) {
+                const uint32_t ms = t & mmask;
+                double m = (double)ms;
+                if (!ms) {
+                    if constexpr (kEsc) m = r.em[c];
+                    else m = Fm[(size_t)c * plane + (size_t)u * kWave + lane];
+                }
+                if (d < x.d[c]) {
+                    x.d[c] = d;
+                    x.m[c] = m;
+                } else {
+                    x.m[c] += m;
+                }
+            }
+        }
+    }
+    __device__ __forceinline__ uint64_t finish(int v, const Acc &x, const Own &o) {
+        if constexpr (W == 1) {
+            const uint64_t b = fwd_finalize(a, (size_t)q * n, v, x.d[0], x.m[0], o.t[0], lane, outs);
+            produced += __popcll(b);
+            colany[0] |= b;
+            return b;
+        } else {
+            return fwd_finalize_w<W>(a, q, v, x.d, x.m, o.t, lane, outs, produced, colany);
+        }
+    }
+    __device__ __forceinline__ size_t slot(int c, int part) const {
+        return ((size_t)(W * q + c) * a.nslots + part) * kWave + lane;
+    }
+    __device__ __forceinline__ void store(int part, const Acc &x) const {
+#pragma unroll
+        for (int c = 0; c < W; c++) {
+            a.pd[slot(c, part)] = x.d[c];
+            a.pm[slot(c, part)] = x.m[c];
+        }
+    }
+    __device__ __forceinline__ Acc load(int part) const {
+        Acc x;
+#pragma unroll
+        for (int c = 0; c < W; c++) {
+            x.d[c] = a.pd[slot(c, part)];
+            x.m[c] = a.pm[slot(c, part)];
+        }
+        return x;
+    }
+    __device__ __forceinline__ void merge(Acc &x, const Acc &y) const {
+#pragma unroll
+        for (int c = 0; c < W; c++) {
+            if (y.d[c] < x.d[c]) {
+                x.d[c] = y.d[c];
+                x.m[c] = y.m[c];
+            } else if (y.d[c] == x.d[c] && y.d[c] != kInf) {
+                x.m[c] += y.m[c];
+            }
+        }
+    }
+    __device__ __forceinline__ uint64_t finish_hub(int v, const Acc &x) {
+        Own o;
+#pragma unroll
+        for (int c = 0; c < W; c++) o.t[c] = kLoadTd;
+        return finish(v, x, o);
+    }
+    // record, per group, the columns that produced entries (served form)
+    __device__ __forceinline__ void flush() const {
+        if constexpr (W == 1) flush_colmask(a.colmask, a.ncg_all, q, colany[0]);
+        else if (a.colmask) flush_colmask_w<W>(a, q, colany);
+    }
+};
+
+// One pull task of the forward product for column group cg.
+template <int AM, int U = kFwdBatch<AM>>
+__device__ __forceinline__ void fwd_task(const FwdArgs &a, int cg, int t, unsigned long long &produced,
+                                         unsigned long long &outs) {
+    FwdPull<AM, 1, U> p(a, cg, produced, outs);
+    pull_task(p, a.tasks + t, a.rp, a.arcs);
+    p.flush();
 }
 
-// Combine the slices of split row h for the W groups of wide group q
-// (fixed slice order) and finish it.
+// Combine the slices of split row h (fixed slice order) and finish it.
+// The merge kernel also clears the previous frontier's bitmaps (counting
+// the vertices active in some column and their arcs) and the next
+// product's counters.
+__device__ __forceinline__ void fwd_hub(const FwdArgs &a, int cg, int h, unsigned long long &produced,
+                                        unsigned long long &outs) {
+    FwdPull<0, 1> p(a, cg, produced, outs);
+    pull_hub(p, a.hubs + h);
+    p.flush();
+}
+
+// The same for wide group q (W column groups per lane).
+template <int AM, int W>
+__device__ __forceinline__ void fwd_task_w(const FwdArgs &a, int q, int t, unsigned long long &produced,
+                                           unsigned long long &outs) {
+    FwdPull<AM, W> p(a, q, produced, outs);
+    pull_task(p, a.tasks + t, a.rp, a.arcs);
+    p.flush();
+}
+
 template <int W>
 __device__ __forceinline__ void fwd_hub_w(const FwdArgs &a, int q, int h, unsigned long long &produced,
                                           unsigned long long &outs) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const Hub *hp = a.hubs + h;
-    const int v = uni(hp->v), first = uni(hp->first), np = uni(hp->nparts);
-    int bd[W], td[W];
-    double bm[W];
-#pragma unroll
-    for (int c = 0; c < W; c++) {
-        bd[c] = kInf;
-        bm[c] = 0.0;
-        td[c] = kLoadTd;
-    }
-    // four slices' partials in flight, combined in slice order
-    for (int s0 = first; s0 < first + np; s0 += 4) {
-        int d[4][W];
-        double m[4][W];
-#pragma unroll
-        for (int k = 0; k < 4; k++)
-#pragma unroll
-            for (int c = 0; c < W; c++) {
-                d[k][c] = kInf;
-                m[k][c] = 0.0;
-                if (s0 + k < first + np) {
-                    const size_t pidx = ((size_t)(W * q + c) * a.nslots + s0 + k) * kWave + lane;
-                    d[k][c] = a.pd[pidx];
-                    m[k][c] = a.pm[pidx];
-                }
-            }
-#pragma unroll
-        for (int k = 0; k < 4; k++)
-#pragma unroll
-            for (int c = 0; c < W; c++) {
-                if (d[k][c] < bd[c]) {
-                    bd[c] = d[k][c];
-                    bm[c] = m[k][c];
-                } else if (d[k][c] == bd[c] && d[k][c] != kInf) {
-                    bm[c] += m[k][c];
-                }
-            }
-    }
-    uint64_t colany[W];
-#pragma unroll
-    for (int c = 0; c < W; c++) colany[c] = 0;
-    const uint64_t b = fwd_finalize_w<W>(a, q, v, bd, bm, td, lane, outs, produced, colany);
-    if (b && lane == 0) atomicOr(a.abits_n + (size_t)q * a.nwords + (v >> 5), 1u << (v & 31));
-    if (a.colmask) flush_colmask_w<W>(a, q, colany);
+    FwdPull<0, W> p(a, q, produced, outs);
+    pull_hub(p, a.hubs + h);
+    p.flush();
 }
 
 // ===================================================================== backward

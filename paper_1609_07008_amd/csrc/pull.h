@@ -1,0 +1,186 @@
+// The generalised product of Section 3, C = F (+).f A (a commutative monoid
+// (+) on the outputs, an action f of an arc on an input entry), over one
+// Task in pull form: the output at vertex v is the (+)-reduction, over the
+// arcs u -> v whose source u is in the frontier, of f(F(u), w(u, v)); then
+// T := T (+) C at v and the next frontier (the entries that C changed, in
+// the sense of the algebra) are formed.  Every product of this shape runs
+// through these two functions -- MFBF's multpaths product (Algorithm 1,
+// products.h) and the monoid fixpoints (monoid.hip) -- with the algebra,
+// the value type and the tile layout supplied by a policy P:
+//
+//   P::AM, P::U           arc format (see ArcSrc); active arcs per batch
+//   P::H                  hub-slice partials in flight in the merge
+//   P::Row                a lane's entries of one frontier row (every column
+//                         group the wave holds)
+//   P::Acc                the running (+)-reduction for the open owner
+//   P::Own                the owner's T entries, loaded with its first candidate
+//   p.bits, p.bits_n      activity bitmaps of the frontier read and written
+//   p.absent(), p.none()  Row / Own placeholders
+//   p.gather(u)           frontier row of vertex u (this lane)
+//   p.own(v0, o)          T at owner v0 + o (this lane; v0 = the task's first row)
+//   p.batch(rows, us)     after a batch's gathers (e.g. side arrays read together)
+//   p.reset(acc)          acc := the identity of (+)
+//   p.fold(acc, row, w, u)  acc := acc (+) f(row, w)
+//   p.finish(v, acc, own) T := T (+) acc at v, next frontier row; returns the
+//                         lanes in the next frontier (any group)
+//   p.store(part, acc), p.load(slot), p.merge(acc, part), p.finish_hub(v, acc)
+//                         partials of a split (hub) row and their combination
+//
+// The task's arcs are read 64 at a time (the next 64 in flight while the
+// current ones are processed); the arcs whose source is active are taken U
+// at a time in arc order, whatever rows they belong to, and their row
+// gathers -- plus the T row of every owner that starts in the batch -- are
+// issued together, so one memory round trip serves several short rows.  The
+// batch is then folded in arc order, each owner being finished when the next
+// arc belongs to a later one.  A slice of a hub row has one owner and leaves
+// a partial, combined with the other slices in slice order by pull_hub.
+#pragma once
+
+#include "mfbc_internal.h"
+
+namespace mfbc {
+namespace {
+
+__device__ __forceinline__ int rdlane(int x, int j) { return __builtin_amdgcn_readlane(x, j); }
+
+__device__ __forceinline__ uint64_t rdlane64(uint64_t x, int j) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, j);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), j);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+__device__ __forceinline__ int64_t uni64(int64_t x) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// Set the bits of `mask` (bit i = vertex v0 + i) in a vertex bitmap.
+__device__ __forceinline__ void or_run_bits(uint32_t *bm, int v0, uint64_t mask) {
+    const int w0 = v0 >> 5, sh = v0 & 31;
+    const uint64_t lo = mask << sh;
+    const uint32_t hi = sh ? (uint32_t)(mask >> (64 - sh)) : 0u;
+    if ((uint32_t)lo) atomicOr(bm + w0, (uint32_t)lo);
+    if ((uint32_t)(lo >> 32)) atomicOr(bm + w0 + 1, (uint32_t)(lo >> 32));
+    if (hi) atomicOr(bm + w0 + 2, hi);
+}
+
+// Arc access: AM = 0 unweighted (col), 1 packed (col | w << cb), 2 separate arrays.
+struct ArcSrc {
+    const int32_t *col;
+    const int32_t *w;
+    const uint32_t *pk;
+    int cb;
+    uint32_t cmask;
+};
+
+template <int AM>
+__device__ __forceinline__ void load_arc(const ArcSrc &s, int64_t e, int &u, int &wt) {
+    if (AM == 1) {
+        const uint32_t p = s.pk[e];
+        u = (int)(p & s.cmask);
+        wt = (int)(p >> s.cb);
+    } else {
+        u = s.col[e];
+        wt = AM == 2 ? s.w[e] : 1;
+    }
+}
+
+template <class P>
+__device__ __forceinline__ void pull_task(P &p, const Task *tp, const int64_t *rp, const ArcSrc &arcs) {
+    constexpr int U = P::U;
+    constexpr int AM = P::AM;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int v0 = uni(tp->v0), v1 = uni(tp->v1), hub = uni(tp->hub), part = uni(tp->part);
+    const int64_t e0 = uni64(tp->e0), e1 = uni64(tp->e1);
+    const uint32_t *Ab = p.bits;
+    // end of each owner's arcs, one owner per lane (a run has at most 64
+    // rows); the owner of arc e is the number of rows ending at or before e.
+    const int64_t rend = (hub < 0 && v0 + lane < v1) ? rp[v0 + lane + 1] : INT64_MAX;
+    int cur = -1;            // owner (offset from v0) of the open reduction
+    typename P::Acc acc;
+    typename P::Own own = p.none();
+    p.reset(acc);
+    uint64_t run_act = 0;
+    int un = 0, wn = 1;
+    if (e0 + lane < e1) load_arc<AM>(arcs, e0 + lane, un, wn);
+    for (int64_t e = e0; e < e1; e += kWave) {
+        const int64_t my = e + lane;
+        const int u = un, wt = wn;
+        const bool act = my < e1 && ((Ab[u >> 5] >> (u & 31)) & 1u);
+        if (my + kWave < e1) load_arc<AM>(arcs, my + kWave, un, wn);
+        uint64_t am = ballot(act);
+        while (am) {
+            int ow[U], wk[U], uk[U];
+            typename P::Row rk[U];
+            typename P::Own on[U];
+            int prev = cur;
+#pragma unroll
+            for (int k = 0; k < U; k++) {
+                const int j = am ? __ffsll((unsigned long long)am) - 1 : -1;
+                am &= am - 1;
+                ow[k] = -1;
+                uk[k] = 0;
+                wk[k] = 0;
+                rk[k] = p.absent();
+                on[k] = p.none();
+                if (j >= 0) {
+                    uk[k] = rdlane(u, j);
+                    wk[k] = AM ? rdlane(wt, j) : 1;
+                    rk[k] = p.gather(uk[k]);
+                    ow[k] = __popcll(ballot(rend <= e + j));
+                    if (hub < 0 && ow[k] != prev) on[k] = p.own(v0, ow[k]);
+                    prev = ow[k];
+                }
+            }
+            p.batch(rk, uk);
+#pragma unroll
+            for (int k = 0; k < U; k++) {
+                if (ow[k] >= 0) {
+                    if (ow[k] != cur) {
+                        if (cur >= 0 && hub < 0 && p.finish(v0 + cur, acc, own)) run_act |= 1ull << cur;
+                        cur = ow[k];
+                        p.reset(acc);
+                        own = on[k];
+                    }
+                    p.fold(acc, rk[k], wk[k], uk[k]);
+                }
+            }
+        }
+    }
+    if (hub < 0) {
+        if (cur >= 0 && p.finish(v0 + cur, acc, own)) run_act |= 1ull << cur;
+        if (lane == 0 && run_act) or_run_bits(p.bits_n, v0, run_act);
+    } else {
+        p.store(part, acc);
+    }
+}
+
+// Combine the slices of split row h in slice order (P::H partials in
+// flight) and finish the row.
+template <class P>
+__device__ __forceinline__ void pull_hub(P &p, const Hub *hp) {
+    constexpr int H = P::H;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int v = uni(hp->v), first = uni(hp->first), np = uni(hp->nparts);
+    typename P::Acc acc;
+    p.reset(acc);
+    for (int s0 = first; s0 < first + np; s0 += H) {
+        typename P::Acc pt[H];
+#pragma unroll
+        for (int k = 0; k < H; k++) {
+            if (s0 + k < first + np) pt[k] = p.load(s0 + k);
+            else p.reset(pt[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < H; k++) p.merge(acc, pt[k]);
+    }
+    if (p.finish_hub(v, acc) && lane == 0) atomicOr(p.bits_n + (v >> 5), 1u << (v & 31));
+}
+
+}  // namespace
+}  // namespace mfbc

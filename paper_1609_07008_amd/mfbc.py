@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libmfbc.so")
 MFBC_OK, MFBC_EINVAL, MFBC_ENOMEM, MFBC_EDEVICE, MFBC_EOVERFLOW = 0, -1, -2, -3, -4
 MFBC_UNDIRECTED, MFBC_DIRECTED, MFBC_KEEP_ORDER = 1, 2, 4
 INF_DIST = 0x7FFFFFFF
-OP_SSSP, OP_BFS = 0, 1
+OP_SSSP, OP_BFS, OP_WIDEST, OP_RESIST = 0, 1, 2, 3
+FIXPOINT_OPS = {"sssp": OP_SSSP, "bfs": OP_BFS, "widest": OP_WIDEST, "resist": OP_RESIST}
 
 # Every entry point declared in include/mfbc.h, with its ctypes signature.
 _P = ctypes.c_void_p
@@ -198,14 +199,16 @@ class DeviceGraph:
         return bits[..., :n].astype(bool)
 
     def fixpoint(self, sources, op: str = "sssp", out=None, stream=None):
-        """Monoid relaxation to a fixpoint (mfbc_fixpoint): int32[nb][n]
-        distances (op="sssp") or hop levels (op="bfs"), and the product count."""
+        """Monoid relaxation to a fixpoint (mfbc_fixpoint) and the product
+        count: int32[nb][n] distances ("sssp"), hop levels ("bfs") or
+        bottleneck widths ("widest"), or float32[nb][n] sums of 1/w ("resist")."""
         t = self._torch
-        code = {"sssp": OP_SSSP, "bfs": OP_BFS}[op]
+        code = FIXPOINT_OPS[op]
         src = self._src(sources)
         nb = src.numel()
         if out is None:
-            out = t.empty((nb, self.n), dtype=t.int32, device="cuda")
+            dtype = t.float32 if code == OP_RESIST else t.int32
+            out = t.empty((nb, self.n), dtype=dtype, device="cuda")
         prods = ctypes.c_int32(0)
         _check(load_library().mfbc_fixpoint(self.handle, code, _ptr(src), nb, _ptr(out),
                                             ctypes.byref(prods), _stream(t, stream)))

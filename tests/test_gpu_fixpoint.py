@@ -1,15 +1,20 @@
-"""Monoid fixpoints (mfbc_fixpoint): SSSP distances and BFS hop levels.
+"""Monoid fixpoints (mfbc_fixpoint): SSSP distances, BFS hop levels,
+widest-path bottlenecks (int32, max / min) and binary32 sums of 1/w.
 
-Bars: values bit-exact against the CPU oracle's distances (Brandes, pinned
-by brute force), product counts equal to the oracle's strict-improvement
-frontier definition (the largest over the batch's sources), at small sizes
-over several tiles and a ragged tail, and on sampled sources at the
-benchmark's size and launch configuration.
+Bars: values bit-exact against the CPU oracle (Brandes' distances for SSSP
+and BFS; the oracle's hop-indexed fixpoint, pinned by brute force over
+paths and walks, for the widest and reciprocal-sum instances -- binary32
+compared bit for bit), product counts equal to the oracle's
+strict-improvement frontier definition (the largest over the batch's
+sources), at small sizes over several tiles and a ragged tail, with split
+hub rows, and on sampled sources at the benchmark's size and launch
+configuration.
 """
 import numpy as np
 import pytest
 
 import oracle
+from oracle.frontier import InArcs
 from oracle.frontier import fixpoint as oracle_fixpoint
 from paper_1609_07008_amd import graphgen as gg
 
@@ -78,15 +83,50 @@ def test_sssp_and_bfs_parity(mfbc, name, nb):
     dg.close()
 
 
+def oracle_rows(g, src, op, arcs=None):
+    """The oracle's values for each source of the list and the batch's product count."""
+    arcs = arcs or InArcs(g)
+    refs = {int(s): oracle_fixpoint(g, int(s), op, arcs=arcs) for s in np.unique(src)}
+    return np.stack([refs[int(s)][0] for s in src]), max(r[1] for r in refs.values())
+
+
+def same_values(got, want, op):
+    got = got.cpu().numpy()
+    if op == "resist":
+        return got.dtype == np.float32 and np.array_equal(got.view(np.uint32),
+                                                         want.astype(np.float32).view(np.uint32))
+    return np.array_equal(got.astype(np.int64), want)
+
+
+@pytest.mark.parametrize("name", list(GRAPHS))
+@pytest.mark.parametrize("nb", [1, 64, 130])
+def test_widest_and_resist_parity(mfbc, name, nb):
+    g = GRAPHS[name]
+    src = pick(g, nb, 500 + nb)
+    print(f"[fixpoint] widest/resist {name} nb={nb}", flush=True)
+    dg = mfbc.DeviceGraph(g)
+    arcs = InArcs(g)
+    for op in ("widest", "resist"):
+        d, prods = dg.fixpoint(src, op)
+        want, wprods = oracle_rows(g, src, op, arcs)
+        assert same_values(d, want, op), op
+        assert prods == wprods, op
+    dg.close()
+
+
 def test_fixpoint_plans_and_errors(mfbc):
     g = GRAPHS["rmat11_w255"]
     dg = mfbc.DeviceGraph(g)
     src = pick(g, 100, 9)
     ref = oracle.brandes(g, src)["dist"]
+    others = {op: oracle_rows(g, src, op) for op in ("widest", "resist")}
     for plan in [(64, 1, 0, 0), (0, 0, 8, 4), (1, 64, 2, 1)]:
         dg.set_plan(*plan)
         d, _ = dg.fixpoint(src, "sssp")
         assert np.array_equal(host(d, mfbc.INF_DIST), ref), plan
+        for op, (want, wprods) in others.items():
+            d, prods = dg.fixpoint(src, op)
+            assert same_values(d, want, op) and prods == wprods, (op, plan)
     lib = mfbc.load_library()
     import ctypes
     import torch
@@ -119,4 +159,22 @@ def test_full_size_sampled(mfbc, rmat20, op):
     got = host(d, mfbc.INF_DIST)[rows]
     assert np.array_equal(got, ref)
     assert prods >= oracle_fixpoint(gg_, int(src[0]), op)[1]
+    dg.close()
+
+
+@pytest.mark.parametrize("op", ["widest", "resist"])
+def test_full_size_sampled_widest_resist(mfbc, rmat20, op):
+    """R-MAT scale 20 (w 1..255), 256 sources in one call; two sampled rows
+    (one in each pair of column groups) against the oracle's fixpoint, and
+    the product count no smaller than theirs."""
+    g = rmat20
+    src = gg.pick_sources(g, 1024, 103)[:256].astype(np.int32)
+    dg = mfbc.DeviceGraph(g)
+    d, prods = dg.fixpoint(src, op)
+    arcs = InArcs(g)
+    for r in (5, 190):
+        want, k = oracle_fixpoint(g, int(src[r]), op, arcs=arcs)
+        assert same_values(d[r:r + 1], want[None, :], op), r
+        assert prods >= k
+    print(f"[fixpoint] rmat20 {op}: {prods} products, rows 5 and 190 match", flush=True)
     dg.close()

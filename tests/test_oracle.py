@@ -391,3 +391,111 @@ def test_fixpoint_closed_forms():
     star = gg.star_graph(30)
     h, k = fixpoint(star, 5, "bfs")
     assert h[0] == 1 and h[5] == 0 and all(h[i] == 2 for i in range(1, 31) if i != 5) and k == 3
+
+
+# widest paths ((+) = max, f(a, w) = min(a, w)) and reciprocal-weight sums
+# ((+) = min, f(a, w) = a + 1/w in binary32)
+from oracle.frontier import WIDE_INF  # noqa: E402
+
+WEIGHTED_SMALL = [c for c in SMALL if c[3] is not None] + [(9, 0.4, 21, (1, 50)), (10, 0.35, 22, (1, 255))]
+
+
+def _f32_fold(ws):
+    x = np.float32(0.0)
+    for w in ws:
+        x = np.float32(x + np.float32(np.float32(1.0) / np.float32(w)))
+    return x
+
+
+@pytest.mark.parametrize("n,p,seed,wr", WEIGHTED_SMALL)
+def test_widest_and_resist_values_from_simple_paths(n, p, seed, wr):
+    """Widest: the greatest bottleneck (least arc weight) over simple paths,
+    unbounded at the source, 0 where unreachable.  Resist: the least
+    left-to-right binary32 sum of 1/w over simple paths (a cycle only adds
+    positive terms, and binary32 addition is monotone)."""
+    g = gg.random_small_graph(n, p, seed, wr)
+    for s in range(g.n):
+        wide = [0] * g.n
+        res = [np.float32(np.inf)] * g.n
+        for path, ws in brute.simple_path_arcs(g, s):
+            t = path[-1]
+            wide[t] = max(wide[t], min(ws) if ws else int(WIDE_INF))
+            res[t] = min(res[t], _f32_fold(ws))
+        L, _ = fixpoint(g, s, "widest")
+        assert L.tolist() == wide
+        R, _ = fixpoint(g, s, "resist")
+        assert R.dtype == np.float32
+        assert [float(x) for x in R] == [float(x) for x in res]
+
+
+@pytest.mark.parametrize("n,p,seed,wr", [c for c in WEIGHTED_SMALL if c[0] <= 9])
+def test_widest_and_resist_products_from_walks(n, p, seed, wr):
+    """Product counts from the strict-improvement frontier definition over
+    exhaustively enumerated walks (every walk of up to n + 1 arcs, one by one)."""
+    g = gg.random_small_graph(n, p, seed, wr)
+    cases = [("widest", lambda a, w: min(a, w), lambda a, b: a > b, int(WIDE_INF)),
+             ("resist", lambda a, w: np.float32(a + np.float32(np.float32(1.0) / np.float32(w))),
+              lambda a, b: a < b, np.float32(0.0))]
+    for s in range(0, g.n, 2):
+        for op, fold, better, start in cases:
+            ell = brute.walk_best(g, s, g.n + 1, fold, better, start)
+            best = list(ell[0])
+            expect = None
+            for j in range(1, g.n + 2):
+                up = [v for v in range(g.n) if ell[j][v] is not None
+                      and (best[v] is None or better(ell[j][v], best[v]))]
+                for v in up:
+                    best[v] = ell[j][v]
+                if not up:
+                    expect = j
+                    break
+            assert fixpoint(g, s, op)[1] == expect, (op, s)
+
+
+def test_widest_is_the_maximum_spanning_tree_bottleneck():
+    """On an undirected graph the widest-path value between s and t is the
+    least weight on the s-t path of a maximum spanning tree (scipy's minimum
+    spanning tree of 256 - w)."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import breadth_first_order, minimum_spanning_tree
+    for seed in (1, 2, 3):
+        g = gg.er_graph(300, 5, 40 + seed, (1, 255))
+        u, v, w = g.edges()
+        a = csr_matrix((256 - w.astype(np.int64), (u, v)), shape=(g.n, g.n))
+        t = minimum_spanning_tree(a)
+        t = (t + t.T).tocsr()
+        s = 7
+        order, pred = breadth_first_order(t, s, directed=False)
+        bott = np.zeros(g.n, np.int64)
+        bott[s] = WIDE_INF
+        for x in order[1:]:
+            bott[x] = min(bott[pred[x]], 256 - int(t[pred[x], x]))
+        L, _ = fixpoint(g, s, "widest")
+        assert np.array_equal(L, bott)
+
+
+def test_resist_close_to_float64_dijkstra():
+    """Binary32 sums of 1/w against scipy's Dijkstra on float64 weights 1/w:
+    equal up to the rounding of a few dozen binary32 additions."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import dijkstra
+    g = gg.rmat_graph(10, 8, 9, wrange=(1, 255))
+    u, v, w = g.edges()
+    a = csr_matrix((1.0 / w.astype(np.float64), (u, v)), shape=(g.n, g.n))
+    d = dijkstra(a, directed=False, indices=[0, 5, 17])
+    for i, s in enumerate([0, 5, 17]):
+        R, _ = fixpoint(g, s, "resist")
+        fin = np.isfinite(d[i])
+        assert np.array_equal(np.isfinite(R), fin)
+        assert np.allclose(R[fin], d[i][fin], rtol=2e-6, atol=0)
+
+
+def test_widest_closed_forms():
+    path = gg.path_graph(30, w=3)
+    L, k = fixpoint(path, 0, "widest")
+    assert L[0] == WIDE_INF and all(L[1:] == 3) and k == 30
+    R, k = fixpoint(path, 0, "resist")
+    assert R[10] == _f32_fold([3] * 10) and k == 30
+    star = gg.star_graph(20)                     # unweighted: every width 1
+    L, k = fixpoint(star, 3, "widest")
+    assert L[3] == WIDE_INF and all(L[i] == 1 for i in range(21) if i != 3) and k == 3

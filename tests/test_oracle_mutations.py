@@ -156,3 +156,68 @@ def test_frontier_mutants_are_caught(tmp_path, name):
     except Exception:
         ok = False          # a mutant that crashes or never empties is caught too
     assert not ok, f"pin missed mutant: {name}"
+
+
+def fixpoint_pin_holds(mod) -> bool:
+    """The pins of tests/test_oracle.py for the widest and reciprocal-sum
+    fixpoints: values against simple paths, product counts against walks."""
+    f32 = np.float32
+    for g in (gg.random_small_graph(8, 0.45, 4, (1, 3)), gg.random_small_graph(7, 0.5, 11, (1, 9))):
+        for s in range(g.n):
+            wide = [0] * g.n
+            res = [f32(np.inf)] * g.n
+            for path, ws in brute.simple_path_arcs(g, s):
+                x = f32(0.0)
+                for w in ws:
+                    x = f32(x + f32(f32(1.0) / f32(w)))
+                wide[path[-1]] = max(wide[path[-1]], min(ws) if ws else int(mod.WIDE_INF))
+                res[path[-1]] = min(res[path[-1]], x)
+            L, kw = mod.fixpoint(g, s, "widest")
+            R, kr = mod.fixpoint(g, s, "resist")
+            if L.tolist() != wide or [float(x) for x in R] != [float(x) for x in res]:
+                return False
+            for op, k, fold, better, start in (
+                    ("widest", kw, lambda a, w: min(a, w), lambda a, b: a > b, int(mod.WIDE_INF)),
+                    ("resist", kr, lambda a, w: f32(a + f32(f32(1.0) / f32(w))), lambda a, b: a < b, f32(0.0))):
+                ell = brute.walk_best(g, s, g.n + 1, fold, better, start)
+                best = list(ell[0])
+                expect = None
+                for j in range(1, g.n + 2):
+                    up = [v for v in range(g.n) if ell[j][v] is not None
+                          and (best[v] is None or better(ell[j][v], best[v]))]
+                    for v in up:
+                        best[v] = ell[j][v]
+                    if not up:
+                        expect = j
+                        break
+                if k != expect:
+                    return False
+    return True
+
+
+FIXPOINT_MUTATIONS = {
+    "widest takes the least candidate": ("nxt[self.has] = np.maximum.reduceat(cand, self.starts)",
+                                         "nxt[self.has] = np.minimum.reduceat(cand, self.starts)"),
+    "widest action adds the weight": ("cand = np.minimum(ell[self.tail], self.weight)",
+                                      "cand = np.minimum(ell[self.tail] + self.weight, WIDE_INF)"),
+    "widest source not unbounded": ("        ell[s] = WIDE_INF\n", "        ell[s] = 255\n"),
+    "resist sums in binary64": ("recip = np.float32(1.0) / self.weight.astype(np.float32)\n            cand = ell[self.tail] + recip",
+                                "recip = 1.0 / self.weight.astype(np.float64)\n            cand = ell[self.tail].astype(np.float64) + recip"),
+    "resist adds the weight": ("cand = ell[self.tail] + recip", "cand = ell[self.tail] + self.weight.astype(np.float32)"),
+    "ties re-enter the frontier": ("F = better(nxt, L)", "F = better(nxt, L) | ((nxt == L) & (j < 3))"),
+}
+
+
+def test_unmutated_fixpoint_oracle_agrees(tmp_path):
+    assert fixpoint_pin_holds(load_frontier_mutant(tmp_path, "INF = ", "INF = "))
+
+
+@pytest.mark.parametrize("name", sorted(FIXPOINT_MUTATIONS))
+def test_fixpoint_mutants_are_caught(tmp_path, name):
+    old, new = FIXPOINT_MUTATIONS[name]
+    mod = load_frontier_mutant(tmp_path, old, new)
+    try:
+        ok = fixpoint_pin_holds(mod)
+    except Exception:
+        ok = False
+    assert not ok, f"pin missed mutant: {name}"
