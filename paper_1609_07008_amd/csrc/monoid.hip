@@ -100,7 +100,7 @@ template <> struct Lanes<float, 2> { using T = float2; };
 // The fixpoint's product as an instance of pull_task / pull_hub: W column
 // groups per lane (1, or 2 in the paired layout), T in the one-group layout.
 template <class Op, int AM_, int W>
-struct MonoPull {
+struct MonoPull : PullDefaults {
     using V = typename Op::V;
     using L = typename Lanes<V, W>::T;
     static_assert(sizeof(V) == 4, "values live in the 4-byte workspace tiles");
@@ -134,7 +134,7 @@ struct MonoPull {
     }
     __device__ __forceinline__ Row absent() const { return fill(Op::absent()); }
     __device__ __forceinline__ Own none() const { return fill(Op::absent()); }
-    __device__ __forceinline__ Row gather(int u) const {
+    __device__ __forceinline__ Row gather(int u, const Tag &, int) const {
         const L v = Fv[(size_t)u * kWave + lane];
         Row r;
         __builtin_memcpy(r.x, &v, sizeof(v));

@@ -94,12 +94,6 @@ __device__ __forceinline__ void clear_and_count(uint32_t *bits, int words, int p
     }
 }
 
-// Arcs of the current 64-arc chunk that belong to the owner whose row ends
-// at `vend` (chunk starts at arc e).
-__device__ __forceinline__ uint64_t owner_mask(int64_t e, int64_t vend) {
-    const int64_t k = vend - e;
-    return k >= 64 ? ~0ull : ((1ull << k) - 1ull);
-}
 
 // Record the columns of group cg that produced frontier entries (one atomic
 // per wave, spread over 32 copies that the host ORs together).
@@ -284,7 +278,7 @@ __device__ __forceinline__ void flush_colmask_w(const FwdArgs &a, int q, const u
 // one-group tiles [cg][v][64], W = 2 the pair layout.  T and the escaped
 // multiplicities keep the one-group layout in both.
 template <int AM_, int W, int U_ = (W == 1 ? kFwdBatch<AM_> : kFwdBatchW<AM_, W>)>
-struct FwdPull {
+struct FwdPull : PullDefaults {
     static constexpr int AM = AM_;
     static constexpr int U = U_;
     static constexpr int H = W == 1 ? 1 : 4;
@@ -340,7 +334,7 @@ struct FwdPull {
         for (int c = 0; c < W; c++) o.t[c] = kInf;
         return o;
     }
-    __device__ __forceinline__ Row gather(int u) const {
+    __device__ __forceinline__ Row gather(int u, const Tag &, int) const {
         Row r = absent();
         if constexpr (W == 1) r.t[0] = Ft[(size_t)u * kWave + lane];
         else unpack(((const typename WideT<W>::T *)Ft)[(size_t)u * kWave + lane], r.t);
@@ -796,294 +790,226 @@ __device__ __forceinline__ uint64_t bwd_finalize(const BwdArgs &a, size_t cgv, i
     return bits;
 }
 
-// One pull task of a backward product for column group cg.  The counting
-// product stored the shortest-path DAG: an arc x -> y counts in
-// lane s iff y is in the frontier of s and the arc is on a shortest path from
-// s, which is the AND of two lane masks -- so neither distance is read, every
-// counted arc belongs to a pending owner, and only the frontier values q(s, y)
-// of counted arcs are gathered (together with the owner's counter).
+// ===================================================================== backward product
+//
+// MFBr's backward product as an instance of the generic pull product: for
+// an owner x and its out-arcs x -> y, the action of an arc on the frontier
+// entry of y is masked per lane by the stored shortest-path DAG -- the arc
+// counts in lane s iff y is in the frontier of s and the arc is on a
+// shortest path from s, the AND of two lane masks (the arc's tag) -- and
+// (+) sums the frontier values q(s, y) of the counted arcs with their number.
+// No distance is read, every counted arc belongs to a pending owner, and q is
+// gathered only for counted lanes.  Every row of a run is visited: rows that
+// count nothing clear their frontier lane masks.  W = 1: one column group;
+// W = 2: a pair of groups (paired layout: lane masks [q][n][2], one activity
+// bitmap per pair, one pass over the arcs and one 16-byte mask gather for
+// both); a padding group (odd group count) has no state and counts nothing.
+// CM: the served form records the columns that produced entries.
+template <int AM_, int W, bool CM = false, int U_ = (W == 1 ? 4 : 2)>
+struct BwdPull : PullDefaults {
+    static constexpr int AM = AM_;
+    static constexpr int U = U_;
+    static constexpr int H = 4;
+    static constexpr bool kEveryRow = true;
+    struct Tag {
+        uint64_t live[W];      // lanes for which the arc counts, per group
+    };
+    struct Row {
+        double q[W];           // 0 where the arc does not count (a frontier value is > 0)
+    };
+    struct Acc {
+        double z[W];
+        int got[W];
+    };
+    struct Own {
+        int cx[W];
+    };
+    const BwdArgs &a;
+    const int q, lane, cg0;
+    const bool has1;
+    const size_t n;
+    const uint32_t *bits;
+    uint32_t *bits_n;
+    unsigned long long &produced, &outs;
+    uint64_t colany[W];
+
+    __device__ __forceinline__ BwdPull(const BwdArgs &a_, int q_, unsigned long long &pr,
+                                       unsigned long long &ou)
+        : a(a_), q(q_), lane(threadIdx.x & (kWave - 1)), cg0(W * q_),
+          has1(W == 2 && W * q_ + 1 < a_.ncg_all), n((size_t)a_.n),
+          bits(a_.abits + (size_t)q_ * a_.nwords), bits_n(a_.abits_n + (size_t)q_ * a_.nwords),
+          produced(pr), outs(ou) {
+#pragma unroll
+        for (int c = 0; c < W; c++) colany[c] = 0;
+    }
+    __device__ __forceinline__ bool in(int c) const { return c == 0 || has1; }
+    __device__ __forceinline__ size_t cgv(int c) const { return (size_t)(cg0 + c) * n; }
+    __device__ __forceinline__ Tag tag(int y, int64_t e) const {
+        Tag t;
+        if constexpr (W == 1) {
+            t.live[0] = a.fbits[cgv(0) + (size_t)y] & a.dag[(size_t)cg0 * a.narcs + (size_t)e];
+        } else {
+            const ulonglong2 f = ((const ulonglong2 *)a.fbits)[(size_t)q * n + (size_t)y];
+            const uint64_t *Dg = a.dag + (size_t)cg0 * a.narcs + (size_t)e;
+            t.live[0] = f.x & Dg[0];
+            t.live[1] = has1 ? f.y & Dg[a.narcs] : 0ull;
+        }
+        return t;
+    }
+    __device__ __forceinline__ bool live(const Tag &t) const {
+        uint64_t any = 0;
+#pragma unroll
+        for (int c = 0; c < W; c++) any |= t.live[c];
+        return any != 0;
+    }
+    __device__ __forceinline__ Row absent() const {
+        Row r;
+#pragma unroll
+        for (int c = 0; c < W; c++) r.q[c] = 0.0;
+        return r;
+    }
+    __device__ __forceinline__ Own none() const {
+        Own o;
+#pragma unroll
+        for (int c = 0; c < W; c++) o.cx[c] = -1;
+        return o;
+    }
+    __device__ __forceinline__ Row gather(int y, const Tag &t, int j) const {
+        Row r = absent();
+#pragma unroll
+        for (int c = 0; c < W; c++) {
+            if ((rdlane64(t.live[c], j) >> lane) & 1ull) r.q[c] = a.q[(cgv(c) + (size_t)y) * kWave + lane];
+        }
+        return r;
+    }
+    __device__ __forceinline__ Own own(int v0, int o) const {
+        Own t;
+#pragma unroll
+        for (int c = 0; c < W; c++)
+            t.cx[c] = in(c) ? a.cnt[(cgv(c) + (size_t)v0 + (size_t)o) * kWave + lane] : -1;
+        return t;
+    }
+    __device__ __forceinline__ void batch(Row (&)[U], const int (&)[U]) const {}
+    __device__ __forceinline__ void reset(Acc &x) const {
+#pragma unroll
+        for (int c = 0; c < W; c++) {
+            x.z[c] = 0.0;
+            x.got[c] = 0;
+        }
+    }
+    __device__ __forceinline__ void fold(Acc &x, const Row &r, int, int) const {
+#pragma unroll
+        for (int c = 0; c < W; c++) {
+            x.z[c] += r.q[c];
+            x.got[c] += r.q[c] != 0.0;
+        }
+    }
+    // element c of a W-array without indexing it by a runtime value (which
+    // would put the array in scratch memory)
+    template <typename T>
+    __device__ __forceinline__ static T at(const T (&v)[W], int c) {
+        return (W == 1 || c == 0) ? v[0] : v[W - 1];
+    }
+    __device__ __forceinline__ uint64_t finish(int v, const Acc &x, const Own &o) {
+        if constexpr (W == 1) {
+            const uint64_t b = bwd_finalize(a, cgv(0), cg0, v, o.cx[0], x.z[0], x.got[0], lane, outs);
+            produced += __popcll(b);
+            colany[0] |= b;
+            return b;
+        }
+        uint64_t bb = 0;
+        // one copy of the finish code for both groups (registers)
+#pragma unroll 1
+        for (int c = 0; c < W; c++) {
+            if (!in(c)) break;
+            const uint64_t b = bwd_finalize(a, cgv(c), cg0 + c, v, at(o.cx, c), at(x.z, c), at(x.got, c),
+                                            lane, outs);
+            produced += __popcll(b);
+            bb |= b;
+            if (W == 1 || c == 0) colany[0] |= b;
+            else colany[W - 1] |= b;
+        }
+        return bb;
+    }
+    __device__ __forceinline__ void idle(int v) const {
+        if constexpr (W == 1) {
+            if (lane == 0) a.fbits_n[cgv(0) + (size_t)v] = 0ull;
+        } else {
+            if (lane < 2) a.fbits_n[((size_t)q * n + (size_t)v) * 2 + lane] = 0ull;
+        }
+    }
+    __device__ __forceinline__ size_t slot(int c, int part) const {
+        return ((size_t)(cg0 + c) * a.nslots + part) * kWave + lane;
+    }
+    __device__ __forceinline__ void store(int part, const Acc &x) const {
+#pragma unroll
+        for (int c = 0; c < W; c++) {
+            a.pd[slot(c, part)] = x.got[c];
+            a.pm[slot(c, part)] = x.z[c];
+        }
+    }
+    __device__ __forceinline__ Acc load(int part) const {
+        Acc x;
+        reset(x);
+#pragma unroll
+        for (int c = 0; c < W; c++) {
+            if (!in(c)) continue;
+            x.got[c] = a.pd[slot(c, part)];
+            x.z[c] = a.pm[slot(c, part)];
+        }
+        return x;
+    }
+    // slice partials summed in slice order
+    __device__ __forceinline__ void merge(Acc &x, const Acc &y) const {
+#pragma unroll
+        for (int c = 0; c < W; c++) {
+            x.z[c] += y.z[c];
+            x.got[c] += y.got[c];
+        }
+    }
+    __device__ __forceinline__ uint64_t finish_hub(int v, const Acc &x) {
+        return finish(v, x, own(v, 0));
+    }
+    // record, per group, the columns that produced entries (served form)
+    __device__ __forceinline__ void flush() const {
+#pragma unroll
+        for (int c = 0; c < W; c++)
+            if (in(c) && (W == 1 || CM)) flush_colmask(a.colmask, a.ncg_all, cg0 + c, colany[c]);
+    }
+};
+
+// One pull task of a backward product for column group cg.
 template <int AM>
-__device__ __forceinline__ void bwd_task(const BwdArgs &a, int cg, int t, unsigned long long &produced, unsigned long long &outs) {
-    const int lane = threadIdx.x & (kWave - 1);
-    uint64_t colany = 0;
-    const Task *tp = a.tasks + t;
-    const int v0 = uni(tp->v0), v1 = uni(tp->v1), hub = uni(tp->hub), part = uni(tp->part);
-    const int64_t e0 = uni64(tp->e0), e1 = uni64(tp->e1);
-    const size_t cgv = (size_t)cg * (size_t)a.n;
-    const double *Q = a.q + cgv * kWave;
-    const uint64_t *Fb = a.fbits + cgv;
-    const uint64_t *Dg = a.dag + (size_t)cg * a.narcs;
-    const uint32_t *Ab = a.abits + (size_t)cg * a.nwords;
-    int x = v0;
-    int64_t vend = hub >= 0 ? e1 : a.rp[v0 + 1];
-    bool loaded = false;
-    int cx = -1, got = 0;
-    double acc = 0.0;
-    uint64_t run_act = 0;
-    for (int64_t e = e0; e < e1; e += kWave) {
-        const int64_t my = e + lane;
-        int y = 0, wt = 1;
-        uint64_t live = 0;
-        if (my < e1) {
-            load_arc<AM>(a.arcs, my, y, wt);
-            if ((Ab[y >> 5] >> (y & 31)) & 1u) live = Fb[y] & Dg[my];
-        }
-        uint64_t am = ballot(live != 0);
-        while (am) {
-            const int j0 = __ffsll((unsigned long long)am) - 1;
-            if (hub < 0) {
-                while (e + j0 >= vend) {
-                    if (loaded) {
-                        const uint64_t b = bwd_finalize(a, cgv, cg, x, cx, acc, got, lane, outs);
-                        produced += __popcll(b);
-                        colany |= b;
-                        if (b) run_act |= 1ull << (x - v0);
-                    } else if (lane == 0) {
-                        a.fbits_n[cgv + (size_t)x] = 0ull;
-                    }
-                    ++x;
-                    vend = a.rp[x + 1];
-                    loaded = false;
-                    got = 0;
-                    acc = 0.0;
-                }
-            }
-            uint64_t cand = am & owner_mask(e, vend);
-            double qy[4];
-#pragma unroll
-            for (int k = 0; k < 4; k++) {
-                qy[k] = 0.0;
-                if (cand) {
-                    const int j = __ffsll((unsigned long long)cand) - 1;
-                    cand &= cand - 1;
-                    am &= ~(1ull << j);
-                    const int yk = rdlane(y, j);
-                    if ((rdlane64(live, j) >> lane) & 1ull) {
-                        qy[k] = Q[(size_t)yk * kWave + lane];
-                        got++;
-                    }
-                }
-            }
-            if (!loaded) {
-                cx = a.cnt[(cgv + (size_t)x) * kWave + lane];
-                loaded = true;
-            }
-#pragma unroll
-            for (int k = 0; k < 4; k++) acc += qy[k];
-        }
-    }
-    if (hub < 0) {
-        while (x < v1) {
-            if (loaded) {
-                const uint64_t b = bwd_finalize(a, cgv, cg, x, cx, acc, got, lane, outs);
-                produced += __popcll(b);
-                colany |= b;
-                if (b) run_act |= 1ull << (x - v0);
-            } else if (lane == 0) {
-                a.fbits_n[cgv + (size_t)x] = 0ull;
-            }
-            ++x;
-            loaded = false;
-            got = 0;
-            acc = 0.0;
-        }
-        if (lane == 0 && run_act) or_run_bits(a.abits_n + (size_t)cg * a.nwords, v0, run_act);
-    } else {
-        const size_t pidx = ((size_t)cg * a.nslots + part) * kWave + lane;
-        a.pd[pidx] = got;
-        a.pm[pidx] = acc;
-    }
-    flush_colmask(a.colmask, a.ncg_all, cg, colany);
+__device__ __forceinline__ void bwd_task(const BwdArgs &a, int cg, int t, unsigned long long &produced,
+                                         unsigned long long &outs) {
+    BwdPull<AM, 1> p(a, cg, produced, outs);
+    pull_task_owner(p, a.tasks + t, a.rp, a.arcs);
+    p.flush();
 }
 
-__device__ __forceinline__ void bwd_hub(const BwdArgs &a, int cg, int h, unsigned long long &produced, unsigned long long &outs) {
-    const int lane = threadIdx.x & (kWave - 1);
-    uint64_t colany = 0;
-    const Hub *hp = a.hubs + h;
-    const int x = uni(hp->v), first = uni(hp->first), np = uni(hp->nparts);
-    const size_t cgv = (size_t)cg * (size_t)a.n;
-    int got = 0;
-    double acc = 0.0;
-    for (int p = first; p < first + np; p++) {
-        const size_t pidx = ((size_t)cg * a.nslots + p) * kWave + lane;
-        got += a.pd[pidx];
-        acc += a.pm[pidx];
-    }
-    const int cx = a.cnt[(cgv + (size_t)x) * kWave + lane];
-    const uint64_t b = bwd_finalize(a, cgv, cg, x, cx, acc, got, lane, outs);
-    produced += __popcll(b);
-    colany |= b;
-    if (b && lane == 0) atomicOr(a.abits_n + (size_t)cg * a.nwords + (x >> 5), 1u << (x & 31));
-    flush_colmask(a.colmask, a.ncg_all, cg, colany);
+__device__ __forceinline__ void bwd_hub(const BwdArgs &a, int cg, int h, unsigned long long &produced,
+                                        unsigned long long &outs) {
+    BwdPull<0, 1> p(a, cg, produced, outs);
+    pull_hub(p, a.hubs + h);
+    p.flush();
 }
 
-// One pull task of a backward product for the pair of column groups q
-// (paired layout, plain path): one pass over the arcs serves both groups --
-// one activity test, one 16-byte gather of the head's two lane masks -- and
-// each group then gathers q(s, y) only for the lanes its DAG mask and the
-// head's frontier mask share.  A padding group (odd group count) has no
-// state and counts no arc.
+// The same for the pair of column groups q (paired layout).
 template <int AM, bool CM>
 __device__ __forceinline__ void bwd_task_w(const BwdArgs &a, int q, int t, unsigned long long &produced,
                                            unsigned long long &outs) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const Task *tp = a.tasks + t;
-    const int v0 = uni(tp->v0), v1 = uni(tp->v1), hub = uni(tp->hub), part = uni(tp->part);
-    const int64_t e0 = uni64(tp->e0), e1 = uni64(tp->e1);
-    const int cg0 = 2 * q;
-    const bool has1 = cg0 + 1 < a.ncg_all;
-    const size_t n = (size_t)a.n;
-    const size_t cgv0 = (size_t)cg0 * n, cgv1 = cgv0 + n;
-    const double *Q0 = a.q + cgv0 * kWave, *Q1 = a.q + cgv1 * kWave;
-    const ulonglong2 *Fb = (const ulonglong2 *)a.fbits + (size_t)q * n;
-    const uint64_t *Dg0 = a.dag + (size_t)cg0 * a.narcs, *Dg1 = Dg0 + a.narcs;
-    const uint32_t *Ab = a.abits + (size_t)q * a.nwords;
-    int x = v0;
-    int64_t vend = hub >= 0 ? e1 : a.rp[v0 + 1];
-    bool loaded = false;
-    int cx0 = -1, cx1 = -1, got0 = 0, got1 = 0;
-    double acc0 = 0.0, acc1 = 0.0;
-    uint64_t run_act = 0, any0 = 0, any1 = 0;
-    auto finish = [&]() {
-        if (loaded) {
-            // one copy of the finish code for both groups (registers)
-            uint64_t bb = 0;
-#pragma unroll 1
-            for (int c = 0; c < 2; c++) {
-                if (c == 1 && !has1) break;
-                const uint64_t b = bwd_finalize(a, c ? cgv1 : cgv0, cg0 + c, x, c ? cx1 : cx0,
-                                                c ? acc1 : acc0, c ? got1 : got0, lane, outs);
-                produced += __popcll(b);
-                bb |= b;
-                if (CM) {
-                    if (c) any1 |= b;
-                    else any0 |= b;
-                }
-            }
-            if (bb) run_act |= 1ull << (x - v0);
-        } else if (lane < 2) {
-            a.fbits_n[((size_t)q * n + (size_t)x) * 2 + lane] = 0ull;
-        }
-        loaded = false;
-        got0 = got1 = 0;
-        acc0 = acc1 = 0.0;
-    };
-    for (int64_t e = e0; e < e1; e += kWave) {
-        const int64_t my = e + lane;
-        int y = 0, wt = 1;
-        uint64_t live0 = 0, live1 = 0;
-        if (my < e1) {
-            load_arc<AM>(a.arcs, my, y, wt);
-            if ((Ab[y >> 5] >> (y & 31)) & 1u) {
-                const ulonglong2 f = Fb[y];
-                live0 = f.x & Dg0[my];
-                if (has1) live1 = f.y & Dg1[my];
-            }
-        }
-        uint64_t am = ballot((live0 | live1) != 0);
-        while (am) {
-            const int j0 = __ffsll((unsigned long long)am) - 1;
-            if (hub < 0) {
-                while (e + j0 >= vend) {
-                    finish();
-                    ++x;
-                    vend = a.rp[x + 1];
-                }
-            }
-            uint64_t cand = am & owner_mask(e, vend);
-            double q0[2], q1[2];
-#pragma unroll
-            for (int k = 0; k < 2; k++) {
-                q0[k] = 0.0;
-                q1[k] = 0.0;
-                if (cand) {
-                    const int j = __ffsll((unsigned long long)cand) - 1;
-                    cand &= cand - 1;
-                    am &= ~(1ull << j);
-                    const int yk = rdlane(y, j);
-                    if ((rdlane64(live0, j) >> lane) & 1ull) {
-                        q0[k] = Q0[(size_t)yk * kWave + lane];
-                        got0++;
-                    }
-                    if ((rdlane64(live1, j) >> lane) & 1ull) {
-                        q1[k] = Q1[(size_t)yk * kWave + lane];
-                        got1++;
-                    }
-                }
-            }
-            if (!loaded) {
-                cx0 = a.cnt[(cgv0 + (size_t)x) * kWave + lane];
-                cx1 = has1 ? a.cnt[(cgv1 + (size_t)x) * kWave + lane] : -1;
-                loaded = true;
-            }
-#pragma unroll
-            for (int k = 0; k < 2; k++) {
-                acc0 += q0[k];
-                acc1 += q1[k];
-            }
-        }
-    }
-    if (hub < 0) {
-        while (x < v1) {
-            finish();
-            ++x;
-        }
-        if (lane == 0 && run_act) or_run_bits(a.abits_n + (size_t)q * a.nwords, v0, run_act);
-    } else {
-        const size_t p0 = ((size_t)cg0 * a.nslots + part) * kWave + lane;
-        const size_t p1 = p0 + (size_t)a.nslots * kWave;
-        a.pd[p0] = got0;
-        a.pm[p0] = acc0;
-        a.pd[p1] = got1;
-        a.pm[p1] = acc1;
-    }
-    if (CM) {
-        flush_colmask(a.colmask, a.ncg_all, cg0, any0);
-        if (has1) flush_colmask(a.colmask, a.ncg_all, cg0 + 1, any1);
-    }
+    BwdPull<AM, 2, CM> p(a, q, produced, outs);
+    pull_task_owner(p, a.tasks + t, a.rp, a.arcs);
+    p.flush();
 }
 
-// Combine the slices of split row h for both groups of pair q and finish it.
 __device__ __forceinline__ void bwd_hub_w(const BwdArgs &a, int q, int h, unsigned long long &produced,
                                           unsigned long long &outs) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const Hub *hp = a.hubs + h;
-    const int x = uni(hp->v), first = uni(hp->first), np = uni(hp->nparts);
-    uint64_t any = 0;
-    for (int c = 0; c < 2; c++) {
-        const int cg = 2 * q + c;
-        if (cg >= a.ncg_all) break;
-        const size_t cgv = (size_t)cg * (size_t)a.n;
-        int got = 0;
-        double acc = 0.0;
-        // four slices' partials in flight, summed in slice order
-        for (int p0 = first; p0 < first + np; p0 += 4) {
-            int gk[4];
-            double ak[4];
-#pragma unroll
-            for (int k = 0; k < 4; k++) {
-                gk[k] = 0;
-                ak[k] = 0.0;
-                if (p0 + k < first + np) {
-                    const size_t pidx = ((size_t)cg * a.nslots + p0 + k) * kWave + lane;
-                    gk[k] = a.pd[pidx];
-                    ak[k] = a.pm[pidx];
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < 4; k++) {
-                got += gk[k];
-                acc += ak[k];
-            }
-        }
-        const int cx = a.cnt[(cgv + (size_t)x) * kWave + lane];
-        const uint64_t b = bwd_finalize(a, cgv, cg, x, cx, acc, got, lane, outs);
-        produced += __popcll(b);
-        any |= b;
-        flush_colmask(a.colmask, a.ncg_all, cg, b);
-    }
-    if (any && lane == 0) atomicOr(a.abits_n + (size_t)q * a.nwords + (x >> 5), 1u << (x & 31));
+    BwdPull<0, 2, true> p(a, q, produced, outs);
+    pull_hub(p, a.hubs + h);
+    p.flush();
 }
+
 
 // ===================================================================== grid kernels
 // The pull kernels are latency bound, so waves in flight matter most.  A SIMD
@@ -1196,7 +1122,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_count_merge(BwdArgs a) {
 }
 
 template <int AM, bool L>
-__global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_bwd_pull(BwdArgs a) {
+__global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS __attribute__((amdgpu_waves_per_eu(8))) void k_bwd_pull(BwdArgs a) {
     if (!live_prev(a.prev_ctr)) return;
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const int cg = wid / a.ntasks;                       // column-group major

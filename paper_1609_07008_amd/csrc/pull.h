@@ -4,9 +4,10 @@
 // arcs u -> v whose source u is in the frontier, of f(F(u), w(u, v)); then
 // T := T (+) C at v and the next frontier (the entries that C changed, in
 // the sense of the algebra) are formed.  Every product of this shape runs
-// through these two functions -- MFBF's multpaths product (Algorithm 1,
-// products.h) and the monoid fixpoints (monoid.hip) -- with the algebra,
-// the value type and the tile layout supplied by a policy P:
+// through these functions -- MFBF's multpaths product (Algorithm 1),
+// MFBr's backward product (Algorithm 2; both in products.h) and the monoid
+// fixpoints (monoid.hip) -- with the algebra, the value type and the tile
+// layout supplied by a policy P:
 //
 //   P::AM, P::U           arc format (see ArcSrc); active arcs per batch
 //   P::H                  hub-slice partials in flight in the merge
@@ -16,7 +17,14 @@
 //   P::Own                the owner's T entries, loaded with its first candidate
 //   p.bits, p.bits_n      activity bitmaps of the frontier read and written
 //   p.absent(), p.none()  Row / Own placeholders
-//   p.gather(u)           frontier row of vertex u (this lane)
+//   P::Tag, p.tag(u, e), p.live(tag)
+//                         a per-arc payload computed by the lane holding arc
+//                         e (source u, in the frontier) and whether the arc
+//                         contributes to any lane: a product whose action
+//                         is masked per lane (MFBr's stored shortest-path
+//                         DAG) skips arcs that feed no lane
+//   p.gather(u, tag, j)   frontier row of vertex u (this lane) for the arc held
+//                         by lane j, whose tag is `tag` (read with readlane)
 //   p.own(v0, o)          T at owner v0 + o (this lane; v0 = the task's first row)
 //   p.batch(rows, us)     after a batch's gathers (e.g. side arrays read together)
 //   p.reset(acc)          acc := the identity of (+)
@@ -25,6 +33,12 @@
 //                         lanes in the next frontier (any group)
 //   p.store(part, acc), p.load(slot), p.merge(acc, part), p.finish_hub(v, acc)
 //                         partials of a split (hub) row and their combination
+//   P::kEveryRow, p.idle(v)  when set, every row of a run without a
+//                         candidate is visited too (MFBr clears its frontier
+//                         lane masks there)
+//
+// PullDefaults supplies the optional members (no tag, nothing masked, no
+// batch hook, only rows with candidates visited).
 //
 // The task's arcs are read 64 at a time (the next 64 in flight while the
 // current ones are processed); the arcs whose source is active are taken U
@@ -90,6 +104,14 @@ __device__ __forceinline__ void load_arc(const ArcSrc &s, int64_t e, int &u, int
     }
 }
 
+struct PullDefaults {
+    struct Tag {};
+    static constexpr bool kEveryRow = false;
+    __device__ __forceinline__ Tag tag(int, int64_t) const { return Tag{}; }
+    __device__ __forceinline__ bool live(const Tag &) const { return true; }
+    __device__ __forceinline__ void idle(int) const {}
+};
+
 template <class P>
 __device__ __forceinline__ void pull_task(P &p, const Task *tp, const int64_t *rp, const ArcSrc &arcs) {
     constexpr int U = P::U;
@@ -111,7 +133,12 @@ __device__ __forceinline__ void pull_task(P &p, const Task *tp, const int64_t *r
     for (int64_t e = e0; e < e1; e += kWave) {
         const int64_t my = e + lane;
         const int u = un, wt = wn;
-        const bool act = my < e1 && ((Ab[u >> 5] >> (u & 31)) & 1u);
+        bool act = my < e1 && ((Ab[u >> 5] >> (u & 31)) & 1u);
+        typename P::Tag tg{};
+        if (act) {
+            tg = p.tag(u, my);
+            act = p.live(tg);
+        }
         if (my + kWave < e1) load_arc<AM>(arcs, my + kWave, un, wn);
         uint64_t am = ballot(act);
         while (am) {
@@ -131,7 +158,7 @@ __device__ __forceinline__ void pull_task(P &p, const Task *tp, const int64_t *r
                 if (j >= 0) {
                     uk[k] = rdlane(u, j);
                     wk[k] = AM ? rdlane(wt, j) : 1;
-                    rk[k] = p.gather(uk[k]);
+                    rk[k] = p.gather(uk[k], tg, j);
                     ow[k] = __popcll(ballot(rend <= e + j));
                     if (hub < 0 && ow[k] != prev) on[k] = p.own(v0, ow[k]);
                     prev = ow[k];
@@ -143,6 +170,9 @@ __device__ __forceinline__ void pull_task(P &p, const Task *tp, const int64_t *r
                 if (ow[k] >= 0) {
                     if (ow[k] != cur) {
                         if (cur >= 0 && hub < 0 && p.finish(v0 + cur, acc, own)) run_act |= 1ull << cur;
+                        if constexpr (P::kEveryRow)
+                            if (hub < 0)
+                                for (int o = cur + 1; o < ow[k]; o++) p.idle(v0 + o);
                         cur = ow[k];
                         p.reset(acc);
                         own = on[k];
@@ -154,6 +184,102 @@ __device__ __forceinline__ void pull_task(P &p, const Task *tp, const int64_t *r
     }
     if (hub < 0) {
         if (cur >= 0 && p.finish(v0 + cur, acc, own)) run_act |= 1ull << cur;
+        if constexpr (P::kEveryRow)
+            for (int o = cur + 1; o < v1 - v0; o++) p.idle(v0 + o);
+        if (lane == 0 && run_act) or_run_bits(p.bits_n, v0, run_act);
+    } else {
+        p.store(part, acc);
+    }
+}
+
+// The same product in owner order: the task's rows are taken one after
+// another and the batch of U active arcs is drawn from the current row only,
+// the owner's T entries loaded with the batch's gathers.  Fewer registers
+// than batches across owners (the batch needs no owner index per arc), for
+// products whose rows are finished often without a candidate (P::kEveryRow)
+// and whose per-arc masks already skip the arcs that feed no lane.
+__device__ __forceinline__ uint64_t owner_mask(int64_t e, int64_t vend) {
+    const int64_t lim = vend - e;
+    return lim >= kWave ? ~0ull : (lim <= 0 ? 0ull : ((1ull << lim) - 1ull));
+}
+
+template <class P>
+__device__ __forceinline__ void pull_task_owner(P &p, const Task *tp, const int64_t *rp, const ArcSrc &arcs) {
+    constexpr int U = P::U;
+    constexpr int AM = P::AM;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int v0 = uni(tp->v0), v1 = uni(tp->v1), hub = uni(tp->hub), part = uni(tp->part);
+    const int64_t e0 = uni64(tp->e0), e1 = uni64(tp->e1);
+    const uint32_t *Ab = p.bits;
+    int x = v0;
+    int64_t vend = hub >= 0 ? e1 : rp[v0 + 1];
+    bool loaded = false;
+    typename P::Acc acc;
+    typename P::Own own = p.none();
+    p.reset(acc);
+    uint64_t run_act = 0;
+    auto close = [&]() {
+        if (loaded) {
+            if (p.finish(x, acc, own)) run_act |= 1ull << (x - v0);
+        } else if constexpr (P::kEveryRow) {
+            p.idle(x);
+        }
+        loaded = false;
+        p.reset(acc);
+    };
+    for (int64_t e = e0; e < e1; e += kWave) {
+        const int64_t my = e + lane;
+        int y = 0, wt = 1;
+        typename P::Tag tg{};
+        bool act = false;
+        if (my < e1) {
+            load_arc<AM>(arcs, my, y, wt);
+            if ((Ab[y >> 5] >> (y & 31)) & 1u) {
+                tg = p.tag(y, my);
+                act = p.live(tg);
+            }
+        }
+        uint64_t am = ballot(act);
+        while (am) {
+            const int j0 = __ffsll((unsigned long long)am) - 1;
+            if (hub < 0) {
+                while (e + j0 >= vend) {
+                    close();
+                    ++x;
+                    vend = rp[x + 1];
+                }
+            }
+            uint64_t cand = am & owner_mask(e, vend);
+            int wk[U], uk[U];
+            typename P::Row rk[U];
+#pragma unroll
+            for (int k = 0; k < U; k++) {
+                rk[k] = p.absent();
+                uk[k] = 0;
+                wk[k] = 0;
+                if (cand) {
+                    const int j = __ffsll((unsigned long long)cand) - 1;
+                    cand &= cand - 1;
+                    am &= ~(1ull << j);
+                    uk[k] = rdlane(y, j);
+                    wk[k] = AM ? rdlane(wt, j) : 1;
+                    rk[k] = p.gather(uk[k], tg, j);
+                }
+            }
+            if (!loaded) {
+                own = p.own(v0, x - v0);
+                loaded = true;
+            }
+            p.batch(rk, uk);
+#pragma unroll
+            for (int k = 0; k < U; k++) p.fold(acc, rk[k], wk[k], uk[k]);
+        }
+    }
+    if (hub < 0) {
+        while (x < v1) {
+            close();
+            ++x;
+        }
         if (lane == 0 && run_act) or_run_bits(p.bits_n, v0, run_act);
     } else {
         p.store(part, acc);

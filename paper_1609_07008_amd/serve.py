@@ -260,7 +260,8 @@ class ServeEngine:
 
     def __init__(self, dgraphs, widths=None, budget_bytes: Optional[int] = None,
                  max_width: int = 256, server_factory=None, footprint_fn=None,
-                 device: str = "cuda", heavy_arcs: Optional[int] = 1 << 22, max_heavy: int = 1):
+                 device: str = "cuda", heavy_arcs: Optional[int] = 1 << 22, max_heavy: int = 1,
+                 light_lag: Optional[float] = None):
         """``server_factory(dgraph, width)`` and ``footprint_fn(dgraph, width)``
         default to ColumnServer and mfbc_server_footprint (other executors
         can be plugged in, e.g. to test the scheduling on the CPU);
@@ -273,7 +274,15 @@ class ServeEngine:
         servers run alongside.  Sharing the device between several heavy
         graphs would stretch each of their requests (every one of their
         products is bound by the memory bandwidth the others also use); light
-        graphs' products take little of it and keep their short latency."""
+        graphs' products take little of it and keep their short latency.
+
+        ``light_lag`` (seconds; None: off): a light graph's request that
+        arrived more than this after the oldest unfinished heavy request is
+        not admitted until that heavy request is done (columns already
+        admitted run on), so light work never queues ahead of an older
+        heavy request for long -- the heavy request sees the device much as
+        it would in arrival order, and light requests older than it still
+        run alongside."""
         import torch
         self.torch = torch
         self.device = device
@@ -289,6 +298,7 @@ class ServeEngine:
         self.heavy = [heavy_arcs is not None and getattr(dg, "arcs", 0) > heavy_arcs
                       for dg in self.dgraphs]
         self.max_heavy = max_heavy
+        self.light_lag = light_lag
         if self.fixed:
             need = sum(fp(dg, w) for dg, w in zip(self.dgraphs, widths))
             if need > self.mem.budget:
@@ -408,6 +418,15 @@ class ServeEngine:
         return all(not self.heavy[h] or h == gi or self._oldest[h] >= mine
                    for h in range(len(self.dgraphs)))
 
+    def _may_admit(self, gi: int, r) -> bool:
+        """Light graphs: `r` waits while a heavy request older than
+        r.arrival - light_lag is unfinished (see __init__)."""
+        if self.heavy[gi] or self.light_lag is None:
+            return True
+        oldest_heavy = min((self._oldest[h] for h in range(len(self.dgraphs)) if self.heavy[h]),
+                           default=float("inf"))
+        return r.arrival <= oldest_heavy + self.light_lag
+
     def _refresh_oldest(self, gi: int):
         ages = [r.arrival for r in self._queues[gi]] + [r.arrival for r in self._active[gi].values()]
         self._oldest[gi] = min(ages) if ages else float("inf")
@@ -424,7 +443,8 @@ class ServeEngine:
                             return
                         srv = self.servers[gi]
                         active = srv is not None and srv.active_columns() > 0
-                        if (q or active) and self._may_step(gi):
+                        ready = bool(q) and self._may_admit(gi, q[0])
+                        if (ready or active) and self._may_step(gi):
                             if srv is None:
                                 srv = self._acquire(gi)
                             if srv is not None:
@@ -435,7 +455,7 @@ class ServeEngine:
                         self._token = gi
                     # queued sources fill the free columns (their requests in arrival order)
                     free = srv.free_columns()
-                    while q and free:
+                    while q and free and self._may_admit(gi, q[0]):
                         r = q[0]
                         k = min(free, r.sources.size - r.placed)
                         admits.append((r, r.placed, k))

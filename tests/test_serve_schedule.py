@@ -217,3 +217,67 @@ def test_heavy_graphs_advance_one_at_a_time_oldest_first():
         want = np.bincount(r.sources, minlength=graphs[r.graph].n).astype(float)
         assert np.array_equal(r.out.numpy(), want), r.rid
     eng.close()
+
+
+class TickServer(FakeServer):
+    """FakeServer that stamps admissions and harvests with a global counter."""
+
+    tick = 0
+    first_admit = {}
+    last_harvest = {}
+    tick_lock = threading.Lock()
+
+    def admit(self, sources):
+        cols = super().admit(sources)
+        with TickServer.tick_lock:
+            TickServer.tick += 1
+            for c in cols:
+                TickServer.first_admit.setdefault(self.req_of(int(c)), TickServer.tick)
+        return cols
+
+    def req_of(self, c):
+        return (id(self.dg), int(self.src[c]))
+
+    def harvest_bc(self, cols, dests):
+        with TickServer.tick_lock:
+            TickServer.tick += 1
+            for c in cols:
+                TickServer.last_harvest[self.req_of(int(c))] = TickServer.tick
+        super().harvest_bc(cols, dests)
+
+
+def test_light_requests_wait_behind_older_heavy_ones():
+    """With light_lag = 0 a light graph's request is first admitted only after
+    every heavy request that arrived before it has finished; without the rule
+    light requests overtake (so the check has teeth)."""
+    def run(lag):
+        FakeServer.live.clear()
+        TickServer.tick = 0
+        TickServer.first_admit.clear()
+        TickServer.last_harvest.clear()
+        graphs = [FakeSized(40, 100), FakeSized(50, 10_000), FakeSized(30, 50)]
+        eng = ServeEngine(graphs, budget_bytes=10**9, max_width=128, server_factory=TickServer,
+                          footprint_fn=lambda dg, w: w, device="cpu", heavy_arcs=1000, light_lag=lag)
+        reqs = []
+        rng = np.random.default_rng(9)
+        for i in range(30):
+            gi = [1, 0, 2][i % 3]
+            # one source per request, distinct per graph: (graph, source) names the request
+            reqs.append(Request(i, gi, "bc", np.array([i], dtype=np.int32), None, float(i)))
+        rng.shuffle(reqs)
+        eng.run(reqs, realtime=False)
+        for r in reqs:
+            want = np.bincount(r.sources, minlength=graphs[r.graph].n).astype(float)
+            assert np.array_equal(r.out.numpy(), want), r.rid
+        key = lambda r: (id(graphs[r.graph]), int(r.sources[0]))    # noqa: E731
+        late = 0
+        for lt in reqs:
+            if eng.heavy[lt.graph]:
+                continue
+            for h in reqs:
+                if eng.heavy[h.graph] and h.arrival < lt.arrival:
+                    late += TickServer.first_admit[key(lt)] < TickServer.last_harvest[key(h)]
+        eng.close()
+        return late
+    assert run(0.0) == 0
+    assert run(None) > 0
