@@ -182,12 +182,13 @@ def run_many(args, spec):
           f"sum n*m = {work:.3e}, setup {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     from paper_1609_07008_amd import autotune
     cache = autotune.load_cache()
-    if args.tune or "many" not in cache:
+    if args.tune or "job_width" not in cache.get("many", {}) or "many_plan" not in cache:
         pick = list(range(0, len(gs), 4))           # every fourth graph
         autotune.tune_many([dgs[i] for i in pick], [srcs[i] for i in pick], cache=cache,
                            verbose=True)
         autotune.save_cache(cache)
     cfg = autotune.many_config(cache)
+    plans = autotune.apply_many_plans(dgs, cache)
     if args.block_threads:
         cfg["block_threads"] = args.block_threads
     if args.blocks:
@@ -204,6 +205,8 @@ def run_many(args, spec):
     # the plain per-graph method on the same GPU, at two batch sizes; the
     # speedup is taken against the faster one
     plain = {}
+    for d, g in zip(dgs, gs):                      # the per-graph path runs its own tuned plans
+        autotune.apply_plan(d, g, cache) or d.set_plan()
     for batch in (() if args.no_baseline else (64, 256)):
         for d, s, o in zip(dgs, srcs, outs):
             d.bc(s, batch, out=o)
@@ -224,6 +227,7 @@ def run_many(args, spec):
         "data": "synthetic",
         "config": {"workload": "batched256", "graphs": len(gs), "sum_n": int(sum(g.n for g in gs)),
                    "sum_m": int(sum(g.m for g in gs)), "launch": cfg,
+                   "plans_by_size": {b: {"run_arcs": p[0], "run_verts": p[1]} for b, p in plans.items()},
                    "fwd_products": st["fwd_products"], "bwd_products": st["bwd_products"]},
         "per_graph_baseline": {"value": work / el_plain, "unit": "TEPS", "ms": el_plain * 1e3,
                                "method": f"one mfbc_bc launch sequence per graph, batch {best} "

@@ -318,12 +318,12 @@ int mfbc_graph_info(const mfbc_graph *g, int32_t *n, int64_t *n_arcs,
 
 /*
  * mfbc_bc_many -- batched form: MFBC over many independent graphs in one
- * persistent launch.  Each workgroup takes (graph, 64-source) jobs from a
- * device queue and runs Algorithms 1-3 for its job with no host round trip
- * per product; jobs are issued largest first.  Per graph the result equals
- * mfbc_bc(graphs[i], d_sources[i], h_n_sources[i], 64, d_bc[i]) up to
- * rounding (the per-job parts are summed in job order, so repeated calls
- * are bitwise identical).
+ * persistent launch.  Each workgroup takes (graph, job_width-source) jobs
+ * from a device queue and runs Algorithms 1-3 for its job with no host
+ * round trip per product; jobs are issued largest first.  Per graph the
+ * result equals mfbc_bc(graphs[i], d_sources[i], h_n_sources[i], job_width,
+ * d_bc[i]) up to rounding (the per-job parts are summed in job order, so
+ * repeated calls with one configuration are bitwise identical).
  *   graphs[n_graphs]      host array of loaded graphs (same device).
  *   d_sources[n_graphs]   host array of device pointers to each graph's
  *                         source list; h_n_sources[n_graphs] their lengths.
@@ -333,7 +333,11 @@ int mfbc_graph_info(const mfbc_graph *g, int32_t *n, int64_t *n_arcs,
  *                         (0 = enough for eight waves per SIMD on every
  *                         compute unit: 2048 / block_threads per CU); the
  *                         block count is capped so that the per-workgroup
- *                         state fits a quarter of the free device memory.
+ *                         state fits a quarter of the free device memory;
+ *                         job_width 64 or 128 sources per job (0 = 64):
+ *                         128 runs the paired products (one gather per arc
+ *                         for both column groups) at twice the state per
+ *                         workgroup.
  *   h_stats (nullable)    out: products over all jobs.
  * The library keeps a grow-only workspace per device for this call.
  * Errors: EINVAL, ENOMEM, EOVERFLOW, EDEVICE.
@@ -341,6 +345,7 @@ int mfbc_graph_info(const mfbc_graph *g, int32_t *n, int64_t *n_arcs,
 typedef struct mfbc_many_config {
     int32_t block_threads;
     int32_t blocks;
+    int32_t job_width;
 } mfbc_many_config;
 
 int mfbc_bc_many(int32_t n_graphs, mfbc_graph *const *graphs,

@@ -6,8 +6,10 @@ Knobs (none changes results beyond floating-point summation order, only speed):
     arcs (hub rows are always cut into slices) -- and, for graphs whose
     products are too small to fill the device, the number of batches of one
     ``mfbc_bc`` call that run at once (``mfbc_set_lanes``);
-  * batched form: threads per workgroup and persistent workgroups of
-    ``mfbc_bc_many``.
+  * batched form: threads per workgroup, persistent workgroups and sources
+    per job (64, or 128 on the paired products) of ``mfbc_bc_many`` for the
+    whole launch, and the run sizes of the graphs of each size class inside
+    it (``many_bucket``).
 
 Choices are cached per device architecture and graph-size bucket (vertex
 count, average degree, weighted or not) in ``tuned_<arch>.json`` next to
@@ -28,6 +30,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 PLAN_CANDIDATES = [(64, 1), (128, 4), (256, 16), (512, 16), (256, 64), (512, 64), (1024, 64),
                    (2048, 64)]
 MANY_CANDIDATES = [(512, 4), (256, 8), (256, 6), (512, 2)]      # (threads, workgroups per CU)
+MANY_WIDTHS = (64, 128)                                          # sources per job
+MANY_PLAN_CANDIDATES = [(0, 0), (64, 1), (128, 4), (256, 16), (1024, 64), (4096, 64)]   # (0, 0): size default
 
 
 def _arch() -> str:
@@ -132,22 +136,57 @@ def apply_plan(dg, g, cache: dict) -> bool:
     return True
 
 
+def many_bucket(n: int) -> str:
+    """Size class of a graph in the batched form (vertex count)."""
+    return "n<=2^10" if n <= 1024 else ("n<=2^12" if n <= 4096 else "n>2^12")
+
+
 def tune_many(dgs, srcs, reps: int = 1, cache: dict = None, verbose=False):
-    """Pick the launch shape of the batched form on (a sample of) its graphs."""
+    """Pick the batched form's launch (threads, workgroups per CU, sources
+    per job) on (a sample of) its graphs, then the run sizes of each size
+    class: the class's graphs alone, in the chosen launch, under each plan."""
     import torch
     from . import mfbc
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     outs = [torch.empty(d.n, dtype=torch.float64, device="cuda") for d in dgs]
+    for d in dgs:
+        d.set_plan()
     res = {}
-    for threads, per_cu in MANY_CANDIDATES:
-        cfg = dict(block_threads=threads, blocks=per_cu * cus)
-        res[(threads, per_cu)] = _time(lambda: mfbc.bc_many(dgs, srcs, outs=outs, **cfg), reps)
-        if verbose:
-            print(f"[tune] many threads={threads} per_cu={per_cu}: {res[(threads, per_cu)]:.3f} s",
-                  file=sys.stderr, flush=True)
+    for width in MANY_WIDTHS:
+        for threads, per_cu in MANY_CANDIDATES:
+            cfg = dict(block_threads=threads, blocks=per_cu * cus, job_width=width)
+            key = (threads, per_cu, width)
+            res[key] = _time(lambda: mfbc.bc_many(dgs, srcs, outs=outs, **cfg), reps)
+            if verbose:
+                print(f"[tune] many threads={threads} per_cu={per_cu} job_width={width}: "
+                      f"{res[key]:.3f} s", file=sys.stderr, flush=True)
     best = min(res, key=res.get)
+    cfg = dict(block_threads=best[0], blocks=best[1] * cus, job_width=best[2])
+    plans = {}
+    classes = {}
+    for i, d in enumerate(dgs):
+        classes.setdefault(many_bucket(d.n), []).append(i)
+    for b, idx in sorted(classes.items()):
+        sub = [dgs[i] for i in idx]
+        ssrc = [srcs[i] for i in idx]
+        sout = [outs[i] for i in idx]
+        pres = {}
+        for ra, rv in MANY_PLAN_CANDIDATES:
+            for d in sub:
+                d.set_plan(run_arcs=ra, run_verts=rv)
+            pres[(ra, rv)] = _time(lambda: mfbc.bc_many(sub, ssrc, outs=sout, **cfg), reps)
+            if verbose:
+                print(f"[tune] many {b} ({len(sub)} graphs) run_arcs={ra} run_verts={rv}: "
+                      f"{pres[(ra, rv)] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        pb = min(pres, key=pres.get)
+        for d in sub:
+            d.set_plan(run_arcs=pb[0], run_verts=pb[1])
+        plans[b] = {"run_arcs": pb[0], "run_verts": pb[1], "ms": pres[pb] * 1e3,
+                    "graphs_tuned_on": len(sub)}
     if cache is not None:
-        cache["many"] = {"block_threads": best[0], "per_cu": best[1], "s": res[best]}
+        cache["many"] = {"block_threads": best[0], "per_cu": best[1], "job_width": best[2],
+                         "s": res[best]}
+        cache["many_plan"] = plans
     return best, res
 
 
@@ -157,4 +196,19 @@ def many_config(cache: dict) -> dict:
     if not e:
         return {}
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    return {"block_threads": e["block_threads"], "blocks": e["per_cu"] * cus}
+    return {"block_threads": e["block_threads"], "blocks": e["per_cu"] * cus,
+            "job_width": e.get("job_width", 64)}
+
+
+def apply_many_plans(dgs, cache: dict) -> dict:
+    """Set every graph's run sizes from its size class's tuned plan (the size
+    default where the class is unknown); returns the plans applied per class."""
+    plans = cache.get("many_plan", {})
+    used = {}
+    for d in dgs:
+        b = many_bucket(d.n)
+        e = plans.get(b)
+        d.set_plan(run_arcs=e["run_arcs"], run_verts=e["run_verts"]) if e else d.set_plan()
+        if e:
+            used[b] = (e["run_arcs"], e["run_verts"])
+    return used

@@ -1,6 +1,7 @@
 // Batched form: MFBC over many graphs in one persistent launch.
 //
-// A job is (graph, up to 64 sources); each workgroup takes jobs from a
+// A job is (graph, up to 64 W sources: W column groups, W = 1 or 2); each
+// workgroup takes jobs from a
 // device-side queue (one atomic per job) and runs the whole of Algorithm 3
 // for its job -- forward products until the frontier empties, the counting
 // product, backward products until the backward frontier empties -- with
@@ -8,7 +9,8 @@
 // round trip per product, which is what dominates the per-graph launch
 // sequence on graphs of a few thousand vertices.  The products are the same
 // task and hub functions as the grid-wide kernels (products.h), scheduled
-// over the workgroup's waves.  Each job's state lives in its workgroup's slot
+// over the workgroup's waves; jobs of two groups run the paired functions
+// (one gather per arc for 128 columns), as the plain path does.  Each job's state lives in its workgroup's slot
 // of a scratch area sized for the largest graph; each job's lambda goes to
 // its own slice and the slices of a graph are summed in job order, so the
 // result does not depend on which workgroup ran which job.
@@ -58,6 +60,10 @@ constexpr int kManyMaxThreads = 512;
 
 __device__ __forceinline__ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// A workgroup's state for jobs of W column groups: per-(column, vertex)
+// arrays [W][n_max][64] (the frontier tuples and backward lane masks in the
+// paired layout when W = 2), one activity bitmap per buffer, the stored DAG
+// [W][arcs].
 struct Slot {
     int32_t *tdist;
     double *tsig;
@@ -68,12 +74,13 @@ struct Slot {
     int32_t *pd;
     double *pm;
     int32_t *src;
-    uint64_t *dag;             // shortest-path lane mask per out-arc
+    uint64_t *dag;             // shortest-path lane mask per out-arc and group
 };
 
-__device__ __forceinline__ Slot carve(char *base, int n_max, int slots_max, int64_t arcs_max) {
+template <int W>
+__device__ __forceinline__ Slot carve(char *base, int n_max, int slots_max) {
     Slot s;
-    const size_t nw = (size_t)n_max * kWave;
+    const size_t nw = (size_t)n_max * kWave * W;
     const size_t words = ((size_t)n_max + 31) / 32;
     size_t off = 0;
     s.tdist = (int32_t *)(base + off); off = align256(off + nw * 4);
@@ -81,14 +88,13 @@ __device__ __forceinline__ Slot carve(char *base, int n_max, int slots_max, int6
     for (int b = 0; b < 2; b++) {
         s.ftup[b] = (uint32_t *)(base + off); off = align256(off + nw * 4);
         s.fsig[b] = (double *)(base + off); off = align256(off + nw * 8);
-        s.fbits[b] = (uint64_t *)(base + off); off = align256(off + (size_t)n_max * 8);
+        s.fbits[b] = (uint64_t *)(base + off); off = align256(off + (size_t)n_max * 8 * W);
         s.abits[b] = (uint32_t *)(base + off); off = align256(off + words * 4);
     }
-    s.pd = (int32_t *)(base + off); off = align256(off + (size_t)slots_max * kWave * 4);
-    s.pm = (double *)(base + off); off = align256(off + (size_t)slots_max * kWave * 8);
-    s.src = (int32_t *)(base + off); off = align256(off + kWave * 4);
+    s.pd = (int32_t *)(base + off); off = align256(off + (size_t)slots_max * kWave * 4 * W);
+    s.pm = (double *)(base + off); off = align256(off + (size_t)slots_max * kWave * 8 * W);
+    s.src = (int32_t *)(base + off); off = align256(off + kWave * 4 * W);
     s.dag = (uint64_t *)(base + off);
-    (void)arcs_max;
     return s;
 }
 
@@ -99,21 +105,22 @@ __device__ __forceinline__ T *pick(T *const (&p)[2], int b) {
     return b ? p[1] : p[0];
 }
 
-// AM: arc encoding shared by every graph of the launch (see load_arc).
-// Eight waves per SIMD: the loop is bound by the latency of its dependent
-// gathers, and more resident waves hide more of it than the spills (uniform
-// state kept in VGPR lanes and a small private segment) cost.
-template <int AM>
+// AM: arc encoding shared by every graph of the launch (see load_arc); W:
+// column groups per job.  Eight waves per SIMD: the loop is bound by the
+// latency of its dependent gathers, and more resident waves hide more of it
+// than the spills (uniform state kept in VGPR lanes and a small private
+// segment) cost.
+template <int AM, int W>
 __global__ __launch_bounds__(kManyMaxThreads) __attribute__((amdgpu_waves_per_eu(8)))
 void k_bc_many(ManyArgs m) {
+    constexpr int C = W * kWave;       // columns per job
     __shared__ int s_job;
     __shared__ unsigned long long s_cnt[3];
     const int tid = threadIdx.x, nthr = blockDim.x;
     // wave index as a uniform (scalar) value, so the task loops stay uniform
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), nwaves = nthr >> 6;
     const bool lead = (tid & (kWave - 1)) == 0;
-    const Slot sl = carve(m.scratch + (size_t)blockIdx.x * m.slot_stride, m.n_max, m.slots_max,
-                          m.arcs_max);
+    const Slot sl = carve<W>(m.scratch + (size_t)blockIdx.x * m.slot_stride, m.n_max, m.slots_max);
     for (;;) {
         if (tid == 0) s_job = (int)atomicAdd(m.queue, 1u);
         if (tid < 3) s_cnt[tid] = 0ull;
@@ -123,11 +130,12 @@ void k_bc_many(ManyArgs m) {
         const JobDesc jd = m.jobs[job];
         const GraphDesc gd = m.graphs[jd.g];
         const int n = gd.n, nw = gd.nwords;
-        double *lam = m.lam_jobs + jd.lam_off;
+        const size_t plane = (size_t)n * kWave;
+        double *lam = m.lam_jobs + jd.lam_off;     // [W][n]
         // ---- Algorithm 1 initialisation: T = (INF, 0), first frontier {s}
-        if (tid < kWave)
-            sl.src[tid] = tid < jd.nsrc ? (gd.perm ? gd.perm[jd.src[tid]] : jd.src[tid]) : -1;
-        for (int i = tid; i < n * kWave; i += nthr) {
+        for (int c = tid; c < C; c += nthr)
+            sl.src[c] = c < jd.nsrc ? (gd.perm ? gd.perm[jd.src[c]] : jd.src[c]) : -1;
+        for (size_t i = tid; i < W * plane; i += nthr) {
             sl.tdist[i] = kInf;
             sl.tsig[i] = 0.0;
         }
@@ -135,19 +143,21 @@ void k_bc_many(ManyArgs m) {
             sl.abits[0][i] = 0u;
             sl.abits[1][i] = 0u;
         }
-        for (int i = tid; i < n; i += nthr) lam[i] = 0.0;
+        for (int i = tid; i < W * n; i += nthr) lam[i] = 0.0;
         __syncthreads();
-        if (tid < jd.nsrc) {
-            const int v = sl.src[tid];
-            for (int l = 0; l < kWave; l++) sl.ftup[0][(size_t)v * kWave + l] = kSent;
+        // a source's frontier row starts with every lane of the job absent ...
+        for (int c = tid; c < jd.nsrc; c += nthr) {
+            const int v = sl.src[c];
+            for (int l = 0; l < C; l++) sl.ftup[0][(size_t)v * C + l] = kSent;
         }
         __syncthreads();
-        if (tid < jd.nsrc) {
-            const int v = sl.src[tid];
-            const size_t idx = (size_t)v * kWave + tid;
+        // ... then its own column carries (0, 1): weight 0, inline multiplicity 1
+        for (int c = tid; c < jd.nsrc; c += nthr) {
+            const int v = sl.src[c], g = c / kWave, lane = c % kWave;
+            const size_t idx = (size_t)g * plane + (size_t)v * kWave + lane;
             sl.tdist[idx] = 0;
             sl.tsig[idx] = 1.0;
-            sl.ftup[0][idx] = 1u;
+            sl.ftup[0][((size_t)v * kWave + lane) * W + g] = 1u;
             atomicOr(sl.abits[0] + (v >> 5), 1u << (v & 31));
         }
         __syncthreads();
@@ -158,8 +168,10 @@ void k_bc_many(ManyArgs m) {
         a.ntasks = gd.ntasks_in;
         a.nhubs = gd.nhubs_in;
         a.nslots = gd.nslots_in;
-        a.ncg = 1;
-        a.ncg_all = 1;
+        a.ncg = W;
+        a.ncg_all = W;
+        a.nwide = W == 2 ? 1 : 0;
+        a.nwide_all = a.nwide;
         a.n = n;
         a.nwords = nw;
         a.mb = gd.mb;
@@ -183,9 +195,17 @@ void k_bc_many(ManyArgs m) {
             a.fsig_n = pick(sl.fsig, b ^ 1);
             if (tid == 0) s_cnt[(j + 1) % 3] = 0ull;
             unsigned long long produced = 0, outs = 0;
-            for (int t = wave; t < a.ntasks; t += nwaves) fwd_task<AM, 4>(a, 0, t, produced, outs);
+            if constexpr (W == 1) {
+                for (int t = wave; t < a.ntasks; t += nwaves) fwd_task<AM, 4>(a, 0, t, produced, outs);
+            } else {
+                for (int t = wave; t < a.ntasks; t += nwaves) fwd_task_w<AM, W>(a, 0, t, produced, outs);
+            }
             __syncthreads();
-            for (int h = wave; h < a.nhubs; h += nwaves) fwd_hub(a, 0, h, produced, outs);
+            if constexpr (W == 1) {
+                for (int h = wave; h < a.nhubs; h += nwaves) fwd_hub(a, 0, h, produced, outs);
+            } else {
+                for (int h = wave; h < a.nhubs; h += nwaves) fwd_hub_w<W>(a, 0, h, produced, outs);
+            }
             for (int i = tid; i < nw; i += nthr) pick(sl.abits, b)[i] = 0u;
             if (lead && produced) atomicAdd(&s_cnt[j % 3], produced);
             __syncthreads();
@@ -203,8 +223,10 @@ void k_bc_many(ManyArgs m) {
         c.ntasks = gd.ntasks_out;
         c.nhubs = gd.nhubs_out;
         c.nslots = gd.nslots_out;
-        c.ncg = 1;
-        c.ncg_all = 1;
+        c.ncg = W;
+        c.ncg_all = W;
+        c.nwide = W == 2 ? 1 : 0;
+        c.nwide_all = c.nwide;
         c.n = n;
         c.nwords = nw;
         c.rp = gd.rp_out;
@@ -215,12 +237,18 @@ void k_bc_many(ManyArgs m) {
         c.cnt = (int32_t *)sl.ftup[0];
         c.zeta = sl.fsig[0];
         c.q = sl.fsig[1];
-        c.step = (int32_t *)sl.ftup[1];
+        c.step = nullptr;          // frontier indices are not reported here
         c.lam = lam;
         c.pd = sl.pd;
         c.pm = sl.pm;
         c.dag = sl.dag;            // the counting product stores the DAG, the
-        c.narcs = 0;               // backward products read it (one column group)
+        c.narcs = m.arcs_max;      // backward products read it ([W][arcs_max])
+        if constexpr (W == 2) {
+            // tau of both groups interleaved per lane for the paired counting product
+            int2 *t2 = (int2 *)sl.ftup[1];
+            for (size_t i = tid; i < plane; i += nthr) t2[i] = make_int2(sl.tdist[i], sl.tdist[plane + i]);
+            c.tau2 = (const int32_t *)t2;
+        }
         for (int i = tid; i < nw; i += nthr) {
             sl.abits[0][i] = 0u;
             sl.abits[1][i] = 0u;
@@ -242,15 +270,29 @@ void k_bc_many(ManyArgs m) {
             if (tid == 0) s_cnt[(k + 1) % 3] = 0ull;
             unsigned long long produced = 0, outs = 0;
             if (k == 0) {
-                for (int t = wave; t < c.ntasks; t += nwaves) count_task<AM>(c, 0, t, produced);
+                if constexpr (W == 1) {
+                    for (int t = wave; t < c.ntasks; t += nwaves) count_task<AM>(c, 0, t, produced);
+                } else {
+                    for (int t = wave; t < c.ntasks; t += nwaves) count_task_w<AM, false>(c, 0, t, produced);
+                }
             } else {
-                for (int t = wave; t < c.ntasks; t += nwaves) bwd_task<AM>(c, 0, t, produced, outs);
+                if constexpr (W == 1) {
+                    for (int t = wave; t < c.ntasks; t += nwaves) bwd_task<AM>(c, 0, t, produced, outs);
+                } else {
+                    for (int t = wave; t < c.ntasks; t += nwaves)
+                        bwd_task_w<AM, false>(c, 0, t, produced, outs);
+                }
             }
             __syncthreads();
             if (k == 0) {
-                for (int h = wave; h < c.nhubs; h += nwaves) count_hub(c, 0, h, produced);
+                for (int h = wave; h < W * c.nhubs; h += nwaves)
+                    count_hub(c, h / c.nhubs, h % c.nhubs, produced);
             } else {
-                for (int h = wave; h < c.nhubs; h += nwaves) bwd_hub(c, 0, h, produced, outs);
+                if constexpr (W == 1) {
+                    for (int h = wave; h < c.nhubs; h += nwaves) bwd_hub(c, 0, h, produced, outs);
+                } else {
+                    for (int h = wave; h < c.nhubs; h += nwaves) bwd_hub_w(c, 0, h, produced, outs);
+                }
                 for (int i = tid; i < nw; i += nthr) pick(sl.abits, bn ^ 1)[i] = 0u;
             }
             if (lead && produced) atomicAdd(&s_cnt[k % 3], produced);
@@ -271,15 +313,17 @@ void k_bc_many(ManyArgs m) {
     }
 }
 
-// lambda of graph g at caller vertex v: the job slices summed in job order.
+// lambda of graph g at caller vertex v: the job slices (W planes each)
+// summed in job order.
 __global__ void k_many_reduce(const double *lam_jobs, const int64_t *job_off, const int32_t *jbeg,
-                              const int32_t *jcnt, const int32_t *order, int n, double *out,
+                              const int32_t *jcnt, const int32_t *order, int n, int w, double *out,
                               const int32_t *perm) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     const int d = perm ? perm[v] : v;
     double t = 0.0;
-    for (int i = 0; i < jcnt[0]; i++) t += lam_jobs[job_off[order[jbeg[0] + i]] + d];
+    for (int i = 0; i < jcnt[0]; i++)
+        for (int c = 0; c < w; c++) t += lam_jobs[job_off[order[jbeg[0] + i]] + (size_t)c * n + d];
     out[v] = t;
 }
 
@@ -307,8 +351,8 @@ ManyWorkspace &many_workspace(int device) {
 
 static size_t host_align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t many_slot_bytes(int n_max, int slots_max, int64_t arcs_max) {
-    const size_t nw = (size_t)n_max * kWave;
+size_t many_slot_bytes(int n_max, int slots_max, int64_t arcs_max, int w) {
+    const size_t nw = (size_t)n_max * kWave * w;
     const size_t words = ((size_t)n_max + 31) / 32;
     size_t off = 0;
     off = host_align256(off + nw * 4);
@@ -316,13 +360,13 @@ size_t many_slot_bytes(int n_max, int slots_max, int64_t arcs_max) {
     for (int b = 0; b < 2; b++) {
         off = host_align256(off + nw * 4);
         off = host_align256(off + nw * 8);
-        off = host_align256(off + (size_t)n_max * 8);
+        off = host_align256(off + (size_t)n_max * 8 * w);
         off = host_align256(off + words * 4);
     }
-    off = host_align256(off + (size_t)slots_max * kWave * 4);
-    off = host_align256(off + (size_t)slots_max * kWave * 8);
-    off = host_align256(off + kWave * 4);
-    off = host_align256(off + (size_t)std::max<int64_t>(arcs_max, 1) * 8);
+    off = host_align256(off + (size_t)slots_max * kWave * 4 * w);
+    off = host_align256(off + (size_t)slots_max * kWave * 8 * w);
+    off = host_align256(off + kWave * 4 * w);
+    off = host_align256(off + (size_t)std::max<int64_t>(arcs_max, 1) * 8 * w);
     return off;
 }
 
@@ -340,7 +384,7 @@ static int host_arc_mode(const Csr &c) { return c.w == nullptr ? 0 : (c.pk ? 1 :
 
 int launch_bc_many(std::vector<mfbc_graph *> &graphs, const std::vector<const int32_t *> &d_src,
                    const std::vector<int64_t> &n_src, const std::vector<double *> &d_bc,
-                   int block_threads, int blocks, hipStream_t s, ManyWorkspace &ws,
+                   int block_threads, int blocks, int w, hipStream_t s, ManyWorkspace &ws,
                    unsigned long long *h_stats, int32_t *h_flags, std::string &err) {
     const int G = (int)graphs.size();
     std::vector<GraphDesc> gds((size_t)G);
@@ -377,21 +421,21 @@ int launch_bc_many(std::vector<mfbc_graph *> &graphs, const std::vector<const in
         slots_max = std::max({slots_max, g->plan_in.nslots, g->plan_out.nslots});
         arcs_max = std::max<int64_t>(arcs_max, g->arcs);
     }
-    // jobs: 64 sources each; scheduled largest first (longest-processing-time
+    // jobs: 64 w sources each; scheduled largest first (longest-processing-time
     // order) so that small jobs fill in at the end
+    const int per_job = kWave * w;
     std::vector<JobDesc> jobs;
     std::vector<double> cost;
-    std::vector<std::vector<int32_t>> per_graph((size_t)G);
     int64_t lam_total = 0;
     for (int i = 0; i < G; i++) {
         const double c = (double)graphs[(size_t)i]->n * (double)(graphs[(size_t)i]->arcs + 1);
-        for (int64_t b0 = 0; b0 < n_src[(size_t)i]; b0 += kWave) {
+        for (int64_t b0 = 0; b0 < n_src[(size_t)i]; b0 += per_job) {
             JobDesc jd{};
             jd.g = i;
-            jd.nsrc = (int32_t)std::min<int64_t>(kWave, n_src[(size_t)i] - b0);
+            jd.nsrc = (int32_t)std::min<int64_t>(per_job, n_src[(size_t)i] - b0);
             jd.src = d_src[(size_t)i] + b0;
             jd.lam_off = lam_total;
-            lam_total += graphs[(size_t)i]->n;
+            lam_total += (int64_t)graphs[(size_t)i]->n * w;
             jobs.push_back(jd);
             cost.push_back(c);
         }
@@ -414,7 +458,7 @@ int launch_bc_many(std::vector<mfbc_graph *> &graphs, const std::vector<const in
     }
     const int njobs = (int)jobs.size();
     blocks = std::max(1, std::min(blocks, std::max(njobs, 1)));
-    const size_t slot = many_slot_bytes(n_max, slots_max, arcs_max);
+    const size_t slot = many_slot_bytes(n_max, slots_max, arcs_max, w);
     const size_t need_scratch = slot * (size_t)blocks;
     const size_t need_lam = (size_t)std::max<int64_t>(lam_total, 1) * sizeof(double);
     // metadata block: graphs, jobs, queue, flags, stats, offsets
@@ -472,10 +516,14 @@ int launch_bc_many(std::vector<mfbc_graph *> &graphs, const std::vector<const in
     m.flags = (int32_t *)(meta + o_flags);
     m.stats = (unsigned long long *)(meta + o_stats);
     if (njobs > 0) {
-        switch (gds[0].am) {
-            case 0: hipLaunchKernelGGL(k_bc_many<0>, dim3(blocks), dim3(block_threads), 0, s, m); break;
-            case 1: hipLaunchKernelGGL(k_bc_many<1>, dim3(blocks), dim3(block_threads), 0, s, m); break;
-            default: hipLaunchKernelGGL(k_bc_many<2>, dim3(blocks), dim3(block_threads), 0, s, m); break;
+        const int key = gds[0].am * 2 + (w == 2);
+        switch (key) {
+            case 0: hipLaunchKernelGGL((k_bc_many<0, 1>), dim3(blocks), dim3(block_threads), 0, s, m); break;
+            case 1: hipLaunchKernelGGL((k_bc_many<0, 2>), dim3(blocks), dim3(block_threads), 0, s, m); break;
+            case 2: hipLaunchKernelGGL((k_bc_many<1, 1>), dim3(blocks), dim3(block_threads), 0, s, m); break;
+            case 3: hipLaunchKernelGGL((k_bc_many<1, 2>), dim3(blocks), dim3(block_threads), 0, s, m); break;
+            case 4: hipLaunchKernelGGL((k_bc_many<2, 1>), dim3(blocks), dim3(block_threads), 0, s, m); break;
+            default: hipLaunchKernelGGL((k_bc_many<2, 2>), dim3(blocks), dim3(block_threads), 0, s, m); break;
         }
     }
     for (int i = 0; i < G; i++) {
@@ -483,7 +531,7 @@ int launch_bc_many(std::vector<mfbc_graph *> &graphs, const std::vector<const in
         hipLaunchKernelGGL(k_many_reduce, dim3((n + 255) / 256), dim3(256), 0, s, ws.lam_jobs,
                            (const int64_t *)(meta + o_joff), (const int32_t *)(meta + o_jbeg) + i,
                            (const int32_t *)(meta + o_jcnt) + i, (const int32_t *)(meta + o_jidx),
-                           n, d_bc[(size_t)i], (const int32_t *)graphs[(size_t)i]->perm);
+                           n, w, d_bc[(size_t)i], (const int32_t *)graphs[(size_t)i]->perm);
     }
     if (hipGetLastError() != hipSuccess) {
         err = "kernel launch failed";

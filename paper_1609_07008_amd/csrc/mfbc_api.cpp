@@ -1008,6 +1008,10 @@ int mfbc_bc_many(int32_t n_graphs, mfbc_graph *const *graphs, const int32_t *con
     int block_threads = config && config->block_threads ? config->block_threads : 512;
     if (block_threads != 256 && block_threads != 512)
         return fail(MFBC_EINVAL, "block_threads must be 256 or 512");
+    const int job_width = config && config->job_width ? config->job_width : kWave;
+    if (job_width != kWave && job_width != 2 * kWave)
+        return fail(MFBC_EINVAL, "job_width must be 64 or 128");
+    const int w = job_width / kWave;
     DeviceGuard dg(dev);
     hipStream_t s = (hipStream_t)hip_stream;
     int rc;
@@ -1028,7 +1032,7 @@ int mfbc_bc_many(int32_t n_graphs, mfbc_graph *const *graphs, const int32_t *con
     }
     size_t free_b = 0, total_b = 0;
     HIP_TRY(hipMemGetInfo(&free_b, &total_b));
-    const size_t slot = many_slot_bytes(n_max, slots_max, arcs_max);
+    const size_t slot = many_slot_bytes(n_max, slots_max, arcs_max, w);
     ManyWorkspace &ws = many_workspace(dev);
     const size_t budget = free_b / 4 + ws_scratch_bytes(ws);
     const int cap = (int)std::max<size_t>(1, budget / std::max<size_t>(slot, 1));
@@ -1053,7 +1057,7 @@ int mfbc_bc_many(int32_t n_graphs, mfbc_graph *const *graphs, const int32_t *con
         unsigned long long st[2] = {0, 0};
         int32_t flags[2] = {0, 0};
         std::string err;
-        rc = launch_bc_many(g2, s2, n2, o2, block_threads, blocks, s, ws, st, flags, err);
+        rc = launch_bc_many(g2, s2, n2, o2, block_threads, blocks, w, s, ws, st, flags, err);
         if (rc) return fail(rc, err);
         if (flags[1]) return fail(MFBC_EDEVICE, "products did not converge");
         if (flags[0]) return fail(MFBC_EOVERFLOW, "a shortest-path count overflowed binary64");

@@ -173,10 +173,10 @@ void launch_mono_product(mfbc_graph *g, int op, int ncg, int j, hipStream_t s, h
 
 // ---- batched form (batched.hip) ----
 struct ManyWorkspace;
-size_t many_slot_bytes(int n_max, int slots_max, int64_t arcs_max);
+size_t many_slot_bytes(int n_max, int slots_max, int64_t arcs_max, int w);
 int launch_bc_many(std::vector<mfbc_graph *> &graphs, const std::vector<const int32_t *> &d_src,
                    const std::vector<int64_t> &n_src, const std::vector<double *> &d_bc,
-                   int block_threads, int blocks, hipStream_t s, ManyWorkspace &ws,
+                   int block_threads, int blocks, int w, hipStream_t s, ManyWorkspace &ws,
                    unsigned long long *h_stats, int32_t *h_flags, std::string &err);
 ManyWorkspace &many_workspace(int device);
 

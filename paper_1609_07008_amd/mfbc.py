@@ -55,7 +55,7 @@ class MfbcStats(ctypes.Structure):
 
 
 class MfbcManyConfig(ctypes.Structure):
-    _fields_ = [("block_threads", _I32), ("blocks", _I32)]
+    _fields_ = [("block_threads", _I32), ("blocks", _I32), ("job_width", _I32)]
 
 
 class MfbcError(RuntimeError):
@@ -275,11 +275,13 @@ class DeviceGraph:
         return {k: getattr(s, k) for k, _ in MfbcStats._fields_}
 
 
-def bc_many(graphs, sources, block_threads: int = 0, blocks: int = 0, outs=None, stream=None):
+def bc_many(graphs, sources, block_threads: int = 0, blocks: int = 0, job_width: int = 0,
+            outs=None, stream=None):
     """Batched form: lambda of every graph over its source list, one persistent launch.
 
     ``graphs``: DeviceGraph list; ``sources``: one int32 source list (numpy
-    or CUDA tensor) per graph.  Returns a list of float64[n_i] tensors.
+    or CUDA tensor) per graph; ``job_width``: sources per job, 64 or 128
+    (0 = 64).  Returns a list of float64[n_i] tensors.
     """
     import torch
     lib = load_library()
@@ -291,7 +293,7 @@ def bc_many(graphs, sources, block_threads: int = 0, blocks: int = 0, outs=None,
     sp = (ctypes.c_void_p * G)(*[t.data_ptr() for t in srcs])
     ns = (ctypes.c_int64 * G)(*[t.numel() for t in srcs])
     op = (ctypes.c_void_p * G)(*[t.data_ptr() for t in outs])
-    cfg = MfbcManyConfig(block_threads, blocks)
+    cfg = MfbcManyConfig(block_threads, blocks, job_width)
     st = MfbcStats()
     rc = lib.mfbc_bc_many(G, ctypes.cast(handles, _P), ctypes.cast(sp, _P), ctypes.cast(ns, _P),
                           ctypes.cast(op, _P), ctypes.byref(cfg), ctypes.byref(st),

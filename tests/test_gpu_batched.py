@@ -37,20 +37,22 @@ def suite():
     return gs
 
 
-@pytest.mark.parametrize("threads", [256, 512])
-def test_bc_many_matches_oracle_and_per_graph(mfbc, threads):
+@pytest.mark.parametrize("threads,width", [(256, 64), (512, 64), (256, 128), (512, 128)])
+def test_bc_many_matches_oracle_and_per_graph(mfbc, threads, width):
     gs = suite()
     dgs = [mfbc.DeviceGraph(g) for g in gs]
     srcs = [np.arange(g.n, dtype=np.int32) for g in gs]
     srcs[0] = srcs[0][::3].copy()                       # a partial source list
-    out = mfbc.bc_many(dgs, srcs, block_threads=threads, blocks=37)
+    srcs[1] = srcs[1][:70].copy()                       # a job whose second group is short
+    print(f"[batched] threads={threads} job_width={width}", flush=True)
+    out = mfbc.bc_many(dgs, srcs, block_threads=threads, blocks=37, job_width=width)
     for g, dg, s, o in zip(gs, dgs, srcs, out):
         lam = o.cpu().numpy()
         ref = oracle.brandes(g, s, per_source=False)["lambda"]
         rel_close(lam, ref, 1e-10, g.name)
         if s.size:
-            rel_close(lam, dg.bc(s, 64).cpu().numpy(), 1e-12, g.name + " vs per-graph")
-    again = mfbc.bc_many(dgs, srcs, block_threads=threads, blocks=11)
+            rel_close(lam, dg.bc(s, width).cpu().numpy(), 1e-12, g.name + " vs per-graph")
+    again = mfbc.bc_many(dgs, srcs, block_threads=threads, blocks=11, job_width=width)
     for a, b in zip(out, again):
         assert np.array_equal(a.cpu().numpy(), b.cpu().numpy()), "job-order sums are deterministic"
     for d in dgs:
@@ -80,6 +82,9 @@ def test_bc_many_rejects_bad_sources(mfbc):
     with pytest.raises(mfbc.MfbcError) as e:
         mfbc.bc_many([dg], [np.array([0, 1], dtype=np.int32)], block_threads=1024)
     assert e.value.code == mfbc.MFBC_EINVAL
+    with pytest.raises(mfbc.MfbcError) as e:
+        mfbc.bc_many([dg], [np.array([0, 1], dtype=np.int32)], job_width=96)
+    assert e.value.code == mfbc.MFBC_EINVAL
     dg.close()
 
 
@@ -104,6 +109,11 @@ def test_bc_many_at_batched_workload_sizes(mfbc):
     out = mfbc.bc_many(dgs, srcs, **cfg)
     for g, dg, s, o in zip(gs, dgs, srcs, out):
         rel_close(o.cpu().numpy(), dg.bc(s, 256).cpu().numpy(), 1e-10, g.name + " vs per-graph")
+    # both job widths at the workload's sizes
+    for width in (64, 128):
+        other = mfbc.bc_many(dgs, srcs, **dict(cfg, job_width=width))
+        for g, o, o2 in zip(gs, out, other):
+            rel_close(o2.cpu().numpy(), o.cpu().numpy(), 1e-10, f"{g.name} job_width={width}")
     t0 = time.perf_counter()
     big = gs[0]
     ref = oracle.brandes(big, np.arange(big.n, dtype=np.int32), per_source=False,
