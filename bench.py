@@ -289,7 +289,8 @@ def run_serve(args, spec):
     # servers admitted by memory footprint within a budget of 80% of the free
     # device memory, up to the workload's width per graph
     lag = None if args.light_lag < 0 else args.light_lag
-    eng = serve.ServeEngine(dgs, budget_bytes=args.serve_budget or None, max_width=spec["width"],
+    width = args.serve_width or spec["width"]
+    eng = serve.ServeEngine(dgs, budget_bytes=args.serve_budget or None, max_width=width,
                             light_lag=lag)
     out = {}
     for frac in (0.5, 0.9):
@@ -315,7 +316,7 @@ def run_serve(args, spec):
         "ms_per_step": main_res["wall_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "served8", "graphs": [g.name for g in gs], "requests": nreq,
-                   "width": spec["width"], "saturation_rate_plain": rate_sat, "light_lag_s": lag,
+                   "width": width, "saturation_rate_plain": rate_sat, "light_lag_s": lag,
                    "admission": {"budget_bytes": eng.mem.budget, "peak_bytes": eng.mem.peak,
                                  "rejected": eng.rejected, "steps": eng.steps}},
         "serving": out, "roofline": None, "cpu_baseline": None,
@@ -422,6 +423,8 @@ def main():
     ap.add_argument("--no-baseline", action="store_true",
                     help="batched form: skip the per-graph comparison")
     ap.add_argument("--requests", type=int, default=400, help="served form: requests per trace")
+    ap.add_argument("--serve-width", type=int, default=0,
+                    help="served form: widest column server per graph (multiple of 128; 0: the workload's)")
     ap.add_argument("--light-lag", type=float, default=-1.0,
                     help="served form: light requests arriving this many seconds after the oldest "
                          "unfinished heavy request wait for it (negative: off)")
