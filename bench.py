@@ -291,7 +291,7 @@ def run_serve(args, spec):
     lag = None if args.light_lag < 0 else args.light_lag
     width = args.serve_width or spec["width"]
     eng = serve.ServeEngine(dgs, budget_bytes=args.serve_budget or None, max_width=width,
-                            light_lag=lag)
+                            light_lag=lag, heavy_plain=args.heavy_plain)
     out = {}
     for frac in (0.5, 0.9):
         reqs = trace(frac * rate_sat, spec["trace_seed"] + int(frac * 10))
@@ -317,6 +317,7 @@ def run_serve(args, spec):
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "served8", "graphs": [g.name for g in gs], "requests": nreq,
                    "width": width, "saturation_rate_plain": rate_sat, "light_lag_s": lag,
+                   "heavy_plain": args.heavy_plain,
                    "admission": {"budget_bytes": eng.mem.budget, "peak_bytes": eng.mem.peak,
                                  "rejected": eng.rejected, "steps": eng.steps}},
         "serving": out, "roofline": None, "cpu_baseline": None,
@@ -425,6 +426,8 @@ def main():
     ap.add_argument("--requests", type=int, default=400, help="served form: requests per trace")
     ap.add_argument("--serve-width", type=int, default=0,
                     help="served form: widest column server per graph (multiple of 128; 0: the workload's)")
+    ap.add_argument("--heavy-plain", action="store_true",
+                    help="served form: heavy graphs' requests run whole through the plain path")
     ap.add_argument("--light-lag", type=float, default=-1.0,
                     help="served form: light requests arriving this many seconds after the oldest "
                          "unfinished heavy request wait for it (negative: off)")
@@ -447,7 +450,7 @@ def main():
     if args.gpus != 1:
         print("bench.py measures one GPU: the hot path runs on a single MI355X; "
               "a multi-GPU run (source batches sharded over GPUs, one allreduce of lambda) "
-              "is not part of this build", file=sys.stderr)
+              "is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -1,9 +1,12 @@
 // Device-side building blocks of the MFBC products, shared by the
-// grid-wide kernels (kernels.hip) and the persistent multi-graph kernel
-// (batched.hip).  Each product is cut into tasks (Task: a run of light rows
-// or a slice of a hub row) processed by one wave for one column group, plus
-// a per-hub merge in fixed slice order; the callers decide how tasks are
-// scheduled (one grid per product, or a workgroup looping over them).
+// grid-wide kernels (kernels.hip, server.hip) and the persistent
+// multi-graph kernel (batched.hip).  Each product is cut into tasks (Task: a
+// run of light rows or a slice of a hub row) processed by one wave for one
+// column group or a pair of them, plus a per-hub merge in fixed slice order;
+// the callers decide how tasks are scheduled (one grid per product, or a
+// workgroup looping over them).  The forward and backward products are
+// policies of the generic pull product of pull.h; the counting product and
+// the per-entry finish steps are written out here.
 #pragma once
 
 #include "pull.h"

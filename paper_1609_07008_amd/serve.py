@@ -261,7 +261,8 @@ class ServeEngine:
     def __init__(self, dgraphs, widths=None, budget_bytes: Optional[int] = None,
                  max_width: int = 256, server_factory=None, footprint_fn=None,
                  device: str = "cuda", heavy_arcs: Optional[int] = 1 << 22, max_heavy: int = 1,
-                 light_lag: Optional[float] = None):
+                 light_lag: Optional[float] = None, heavy_plain: bool = False, plain_batch: int = 256,
+                 plain_fn=None):
         """``server_factory(dgraph, width)`` and ``footprint_fn(dgraph, width)``
         default to ColumnServer and mfbc_server_footprint (other executors
         can be plugged in, e.g. to test the scheduling on the CPU);
@@ -282,7 +283,14 @@ class ServeEngine:
         admitted run on), so light work never queues ahead of an older
         heavy request for long -- the heavy request sees the device much as
         it would in arrival order, and light requests older than it still
-        run alongside."""
+        run alongside.
+
+        ``heavy_plain``: heavy graphs get no column server; their requests
+        run whole, one at a time in arrival order, through the plain path
+        (``plain_fn(dgraph, request, plain_batch)``, default run_plain) on
+        the worker's own stream, while light graphs' servers run alongside.
+        The plain path's workspace (the footprint of a ``plain_batch``-wide
+        server) is reserved in the budget up front."""
         import torch
         self.torch = torch
         self.device = device
@@ -299,6 +307,17 @@ class ServeEngine:
                       for dg in self.dgraphs]
         self.max_heavy = max_heavy
         self.light_lag = light_lag
+        self.heavy_plain = heavy_plain
+        self.plain_batch = plain_batch
+        self.plain_fn = plain_fn or run_plain
+        if heavy_plain:
+            need = sum(fp(dg, plain_batch) for dg, h in zip(self.dgraphs, self.heavy) if h)
+            if need > self.mem.budget:
+                raise _m.MfbcError(_m.MFBC_ENOMEM, f"plain workspaces need {need} bytes, "
+                                                   f"budget {budget}")
+            for gi, h in enumerate(self.heavy):
+                if h:
+                    self.mem.add(gi, plain_batch)
         if self.fixed:
             need = sum(fp(dg, w) for dg, w in zip(self.dgraphs, widths))
             if need > self.mem.budget:
@@ -366,7 +385,8 @@ class ServeEngine:
             t.cuda.synchronize()
         t0 = time.perf_counter()
         self._t0 = t0
-        workers = [threading.Thread(target=self._worker, args=(gi, on_step), daemon=True)
+        workers = [threading.Thread(target=self._plain_worker if (self.heavy_plain and self.heavy[gi])
+                                    else self._worker, args=(gi, on_step), daemon=True)
                    for gi in range(G)]
         for w in workers:
             w.start()
@@ -493,6 +513,49 @@ class ServeEngine:
                 self._stop = True
                 cv.notify_all()
 
+    def _plain_worker(self, gi: int, on_step):
+        """Heavy graph under heavy_plain: whole requests, oldest first among the
+        heavy graphs, one at a time, on this thread's own stream."""
+        cv = self._cv
+        q = self._queues[gi]
+        t = self.torch
+        stream = t.cuda.Stream() if self.device == "cuda" else None
+        try:
+            while True:
+                with cv:
+                    while True:
+                        if self._stop:
+                            return
+                        if q and self._may_step(gi):
+                            break
+                        cv.wait(timeout=0.05)
+                    self._token = gi
+                    r = q.popleft()
+                    r.placed = r.sources.size
+                    self._active[gi][id(r)] = r
+                if stream is not None:
+                    with t.cuda.stream(stream):
+                        self.plain_fn(self.dgraphs[gi], r, self.plain_batch)
+                    stream.synchronize()
+                else:
+                    self.plain_fn(self.dgraphs[gi], r, self.plain_batch)
+                with cv:
+                    r.done = time.perf_counter() - self._t0
+                    del self._active[gi][id(r)]
+                    self.steps += 1
+                    if self._token == gi:
+                        self._token = None
+                    self._left -= 1
+                    self._refresh_oldest(gi)
+                    if on_step is not None:
+                        on_step(self)
+                    cv.notify_all()
+        except BaseException as e:             # surfaced by run()
+            with cv:
+                self._err = e
+                self._stop = True
+                cv.notify_all()
+
     def _acquire(self, gi: int):
         """A server for graph gi within the memory budget (under the lock), or None."""
         q = self._queues[gi]
@@ -540,9 +603,30 @@ class ServeEngine:
         return finished
 
 
+def run_plain(dg, r: Request, batch: int = 256):
+    """One request through the plain per-batch entry points on the current
+    stream: mfbc_bc for a BC sum, mfbc_forward + mfbc_backward per batch and
+    a gather of delta at the targets for a dependency request."""
+    import torch
+    src = torch.as_tensor(np.ascontiguousarray(r.sources, dtype=np.int32), device="cuda")
+    if r.kind == "bc":
+        r.out = dg.bc(src, batch)
+        return
+    tg = torch.as_tensor(np.ascontiguousarray(r.targets, dtype=np.int64), device="cuda")
+    rows = []
+    for b0 in range(0, src.numel(), batch):
+        bs = src[b0:b0 + batch]
+        f = dg.forward(bs)
+        d = dg.backward(bs, f["dist"], f["sigma"])["delta"]
+        rows.append(d[:, tg])
+        del f, d
+    r.out = torch.cat(rows, dim=0) if rows else \
+        torch.zeros((0, tg.numel()), dtype=torch.float64, device="cuda")
+
+
 def run_fifo(dgraphs, requests: List[Request], batch: int = 256, realtime: bool = True):
     """Reference schedule: each request alone, in arrival order, through the
-    plain per-batch entry points (mfbc_bc, mfbc_forward + mfbc_backward)."""
+    plain per-batch entry points (run_plain)."""
     import torch
     pending = sorted(requests, key=lambda r: r.arrival)
     torch.cuda.synchronize()
@@ -552,21 +636,7 @@ def run_fifo(dgraphs, requests: List[Request], batch: int = 256, realtime: bool 
             wait = r.arrival - (time.perf_counter() - t0)
             if wait > 0:
                 time.sleep(wait)
-        dg = dgraphs[r.graph]
-        src = torch.as_tensor(np.ascontiguousarray(r.sources, dtype=np.int32), device="cuda")
-        if r.kind == "bc":
-            r.out = dg.bc(src, batch)
-        else:
-            tg = torch.as_tensor(np.ascontiguousarray(r.targets, dtype=np.int64), device="cuda")
-            rows = []
-            for b0 in range(0, src.numel(), batch):
-                bs = src[b0:b0 + batch]
-                f = dg.forward(bs)
-                d = dg.backward(bs, f["dist"], f["sigma"])["delta"]
-                rows.append(d[:, tg])
-                del f, d
-            r.out = torch.cat(rows, dim=0) if rows else \
-                torch.zeros((0, tg.numel()), dtype=torch.float64, device="cuda")
+        run_plain(dgraphs[r.graph], r, batch)
         torch.cuda.synchronize()
         r.done = time.perf_counter() - t0
     return requests

@@ -272,3 +272,26 @@ def test_rounds_per_step_do_not_change_results(env, rounds):
     for r in reqs:
         rel_close(r.out.cpu().numpy(), reference(graphs, r), 1e-10, f"rounds={rounds} request {r.rid}")
     eng.close()
+
+
+def test_heavy_graphs_through_the_plain_path(env):
+    """heavy_plain: the graphs above the heavy threshold run whole requests
+    through the plain path on their own streams while the others are served
+    by column servers; every request against the oracle, the heavy ones
+    also against run_fifo's result."""
+    t, mfbc, serve, graphs, dgs = env
+    heavy_arcs = dgs[1].arcs                                # graphs 0 and 2 heavy, 1 light
+    reqs = serve.make_requests(graphs, 30, rate=1e9, seed=12, smin=3, smax=300)
+    eng = serve.ServeEngine(dgs, budget_bytes=4 << 30, max_width=128, heavy_arcs=heavy_arcs,
+                            heavy_plain=True)
+    assert eng.heavy == [True, False, True]
+    eng.run(reqs, realtime=False)
+    for r in reqs:
+        rel_close(r.out.cpu().numpy(), reference(graphs, r), 1e-10, f"request {r.rid} ({r.kind})")
+    fifo = [serve.Request(r.rid, r.graph, r.kind, r.sources, r.targets, 0.0) for r in reqs
+            if eng.heavy[r.graph]][:6]
+    serve.run_fifo(dgs, fifo, realtime=False)
+    for f in fifo:
+        r = next(x for x in reqs if x.rid == f.rid)
+        rel_close(r.out.cpu().numpy(), f.out.cpu().numpy(), 1e-12, f"plain vs fifo {r.rid}")
+    eng.close()

@@ -281,3 +281,53 @@ def test_light_requests_wait_behind_older_heavy_ones():
         return late
     assert run(0.0) == 0
     assert run(None) > 0
+
+
+def test_heavy_plain_runs_whole_requests_in_arrival_order():
+    """heavy_plain: heavy graphs' requests run whole through the plain
+    function, one at a time and in arrival order across the heavy graphs,
+    while light graphs' servers keep stepping; the plain workspaces are
+    reserved in the budget."""
+    FakeServer.live.clear()
+    graphs = [FakeSized(40, 100), FakeSized(50, 10_000), FakeSized(60, 20_000), FakeSized(30, 50)]
+    state = {"flying": 0, "max": 0, "order": [], "light_steps_during": 0}
+    lock = threading.Lock()
+
+    def plain(dg, r, batch):
+        with lock:
+            state["flying"] += 1
+            state["max"] = max(state["max"], state["flying"])
+            state["order"].append(r.arrival)
+        time.sleep(0.003)
+        r.out = torch.as_tensor(np.bincount(r.sources, minlength=dg.n).astype(float))
+        with lock:
+            state["flying"] -= 1
+
+    class CountingServer(FakeServer):
+        def step_launch(self):
+            super().step_launch()
+            with lock:
+                state["light_steps_during"] += state["flying"] > 0
+
+    eng = ServeEngine(graphs, budget_bytes=10_000, max_width=128, server_factory=CountingServer,
+                      footprint_fn=lambda dg, w: w, device="cpu", heavy_arcs=1000,
+                      heavy_plain=True, plain_batch=256, plain_fn=plain)
+    assert eng.mem.used == 2 * 256                     # the two heavy graphs' plain workspaces
+    rng = np.random.default_rng(8)
+    reqs = []
+    for i in range(40):
+        gi = int(rng.integers(0, 4))
+        src = rng.integers(0, graphs[gi].n, size=int(rng.integers(1, 90))).astype(np.int32)
+        reqs.append(Request(i, gi, "bc", src, None, float(i)))
+    eng.run(reqs, realtime=False)
+    for r in reqs:
+        want = np.bincount(r.sources, minlength=graphs[r.graph].n).astype(float)
+        assert np.array_equal(r.out.numpy(), want), r.rid
+    assert state["max"] == 1
+    assert state["order"] == sorted(state["order"])   # heavy requests in arrival order
+    assert state["light_steps_during"] > 0            # light servers step alongside
+    assert all(s.dg.arcs <= 1000 for s in FakeServer.live)   # no server for a heavy graph
+    eng.close()
+    with pytest.raises(Exception):
+        ServeEngine(graphs, budget_bytes=300, server_factory=CountingServer, footprint_fn=lambda dg, w: w,
+                    device="cpu", heavy_arcs=1000, heavy_plain=True, plain_fn=plain)
