@@ -59,7 +59,7 @@ WORKLOADS = {
     # 17), Poisson requests for BC contributions or dependencies of 16..1024
     # sources, continuous batching of source columns vs one request at a time
     "served8": dict(kind="serve", scales=(14, 15, 16, 17, 18, 19, 20, 17), seed0=2000,
-                    trace_seed=2100, width=256),
+                    trace_seed=2100, width=256, heavy_plain=True),
 }
 
 
@@ -290,8 +290,9 @@ def run_serve(args, spec):
     # device memory, up to the workload's width per graph
     lag = None if args.light_lag < 0 else args.light_lag
     width = args.serve_width or spec["width"]
+    heavy_plain = spec["heavy_plain"] and not args.no_heavy_plain
     eng = serve.ServeEngine(dgs, budget_bytes=args.serve_budget or None, max_width=width,
-                            light_lag=lag, heavy_plain=args.heavy_plain)
+                            light_lag=lag, heavy_plain=heavy_plain)
     out = {}
     for frac in (0.5, 0.9):
         reqs = trace(frac * rate_sat, spec["trace_seed"] + int(frac * 10))
@@ -317,7 +318,7 @@ def run_serve(args, spec):
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "served8", "graphs": [g.name for g in gs], "requests": nreq,
                    "width": width, "saturation_rate_plain": rate_sat, "light_lag_s": lag,
-                   "heavy_plain": args.heavy_plain,
+                   "heavy_plain": heavy_plain,
                    "admission": {"budget_bytes": eng.mem.budget, "peak_bytes": eng.mem.peak,
                                  "rejected": eng.rejected, "steps": eng.steps}},
         "serving": out, "roofline": None, "cpu_baseline": None,
@@ -426,8 +427,9 @@ def main():
     ap.add_argument("--requests", type=int, default=400, help="served form: requests per trace")
     ap.add_argument("--serve-width", type=int, default=0,
                     help="served form: widest column server per graph (multiple of 128; 0: the workload's)")
-    ap.add_argument("--heavy-plain", action="store_true",
-                    help="served form: heavy graphs' requests run whole through the plain path")
+    ap.add_argument("--no-heavy-plain", action="store_true",
+                    help="served form: heavy graphs get column servers too (by default their "
+                         "requests run whole through the plain path)")
     ap.add_argument("--light-lag", type=float, default=-1.0,
                     help="served form: light requests arriving this many seconds after the oldest "
                          "unfinished heavy request wait for it (negative: off)")
