@@ -70,10 +70,11 @@ __global__ void k_fwd_fill(int32_t *tdist, double *tsig, size_t total, uint32_t 
                            size_t nab, unsigned long long *ctr, int nctr, int32_t *flags) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (size_t i = t0; i < total; i += stride) {
-        tdist[i] = kInf;
-        tsig[i] = 0.0;
-    }
+    // sigma is read only where tau is finite (ties in the forward product,
+    // leaves and finishes in the backward, exports masked by tau), so only
+    // tau is reset
+    for (size_t i = t0; i < total; i += stride) tdist[i] = kInf;
+    (void)tsig;
     for (size_t i = t0; i < nab; i += stride) {
         ab0[i] = 0u;
         ab1[i] = 0u;
@@ -175,6 +176,27 @@ __global__ __launch_bounds__(kBlock) void k_tiles_to_rows(const T *tiles, T *row
     for (int r = r0; r < 64; r += 4) {
         const int v = v0 + r;
         if (v < n) sh[r][c] = tiles[((size_t)cg * n + dev_id(perm, v)) * 64 + c];
+    }
+    __syncthreads();
+    for (int r = r0; r < 64; r += 4) {
+        const int s = cg * 64 + r, v = v0 + c;
+        if (s < nb && v < n) rows[(size_t)s * n + v] = sh[c][r];
+    }
+}
+
+// sigma tiles to rows, 0 where tau is infinite (sigma is not reset there).
+__global__ __launch_bounds__(kBlock) void k_sigma_rows(const double *tsig, const int32_t *tdist,
+                                                       double *rows, int n, int nb,
+                                                       const int32_t *perm) {
+    __shared__ double sh[64][65];
+    const int cg = blockIdx.y, v0 = blockIdx.x * 64;
+    const int c = threadIdx.x & 63, r0 = threadIdx.x >> 6;
+    for (int r = r0; r < 64; r += 4) {
+        const int v = v0 + r;
+        if (v < n) {
+            const size_t idx = ((size_t)cg * n + dev_id(perm, v)) * 64 + c;
+            sh[r][c] = tdist[idx] != kInf ? tsig[idx] : 0.0;
+        }
     }
     __syncthreads();
     for (int r = r0; r < 64; r += 4) {
@@ -562,8 +584,8 @@ void launch_export_forward(mfbc_graph *g, int ncg, int nb, int32_t *d_dist, doub
     const int32_t *perm = g->perm;
     hipLaunchKernelGGL(k_tiles_to_rows<int32_t>, grid, dim3(kBlock), 0, s, g->ws.tdist, d_dist,
                        g->n, nb, perm);
-    hipLaunchKernelGGL(k_tiles_to_rows<double>, grid, dim3(kBlock), 0, s, g->ws.tsig, d_sigma,
-                       g->n, nb, perm);
+    hipLaunchKernelGGL(k_sigma_rows, grid, dim3(kBlock), 0, s, (const double *)g->ws.tsig,
+                       (const int32_t *)g->ws.tdist, d_sigma, g->n, nb, perm);
 }
 
 void launch_trace_fwd(mfbc_graph *g, int ncg, int nb, int j, uint64_t *d_rows, hipStream_t s) {
