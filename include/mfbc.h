@@ -364,10 +364,11 @@ int mfbc_bc_many(int32_t n_graphs, mfbc_graph *const *graphs,
  * active column by up to R products of its phase; a column depends only on its own
  * column of the frontier (the products act column by column, Section 3), so
  * new sources start between steps while other columns are mid-loop.  The
- * unit of admission is a group of 64 columns: a group takes new sources
+ * unit of admission is a pair of 64-column groups (the last pair of a width
+ * that is an odd multiple of 64 holds one group): a pair takes new sources
  * (from any number of requests) only while all of its columns are free or
  * until the step after its first admission is launched, and it leaves the
- * forward loop when all of its lanes have, so each group follows the plain
+ * forward loop when all of its lanes have, so each pair follows the plain
  * path's per-batch schedule.  Finished columns are harvested into the
  * caller's buffers and become free.  All calls on one server must come from one
  * thread, in the order admit / step_launch / step_finish / harvest; the

@@ -456,7 +456,7 @@ static BwdArgs bwd_args(mfbc_graph *g, int ncg, int k) {
     a.cnt = ws.fdist[0];
     a.zeta = ws.fsig[0];
     a.q = ws.fsig[1];
-    a.step = ws.fdist[1];
+    a.step = g->trace_step ? ws.fdist[1] : nullptr;   // frontier indices only when traced
     a.lam = ws.lam;
     a.dag = ws.dag;
     a.narcs = g->arcs;

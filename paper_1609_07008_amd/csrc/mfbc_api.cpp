@@ -331,10 +331,11 @@ int run_backward(mfbc_graph *g, int ncg, int nb, int32_t *products, hipStream_t 
                 // adjacency, tau of every (column, vertex) read once, the
                 // stored DAG (one 8-byte lane mask per arc and column group)
                 // written, the backward state of every (column, vertex)
-                // initialised (counter 4 B, zeta 8 B, step 4 B), and each
-                // leaf's sigma read and 1/sigma written
+                // initialised (counter 4 B, zeta 8 B, frontier index 4 B
+                // when traced), and each leaf's sigma read and 1/sigma written
+                const double state = g->trace_step ? 16.0 : 12.0;
                 st.count_alg_bytes += arc_bytes * (double)g->arcs + 8.0 * g->n +
-                                      24.0 * (double)g->n * nb +
+                                      (8.0 + state) * (double)g->n * nb +
                                       8.0 * (double)g->arcs * ncg + 16.0 * (double)c.produced;
                 if (g->timing) {
                     float t = 0.f;
@@ -419,7 +420,10 @@ int backward_impl(mfbc_graph *g, const int32_t *d_sources, int32_t nb, const int
     g->stats = mfbc_stats{};
     launch_set_sources(g, ncg, nb, d_sources, s);
     launch_import_forward(g, ncg, nb, d_dist, d_sigma, s);
-    if ((rc = run_backward(g, ncg, nb, h_products, s))) return rc;
+    g->trace_step = d_step != nullptr;
+    rc = run_backward(g, ncg, nb, h_products, s);
+    g->trace_step = false;
+    if (rc) return rc;
     g->stats.batches = 1;
     launch_export_backward(g, ncg, nb, d_delta, d_step, s);
     HIP_TRY(hipGetLastError());

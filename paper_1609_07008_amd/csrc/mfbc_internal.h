@@ -118,6 +118,7 @@ struct mfbc_graph {
     int32_t *perm = nullptr;
     std::vector<int32_t> h_perm;
     bool timing = false;
+    bool trace_step = false;           // backward products record frontier indices (traced call)
     hipEvent_t ev[3 * mfbc::kWindow] = {};   // per product of a window: before the product kernel,
                                        // between it and its merge, after the merge
     unsigned long long *h_ctr = nullptr;  // pinned host copy of the counter ring

@@ -9,27 +9,24 @@
 // join and leave at step boundaries while other columns are mid-loop: one
 // step runs one counting product (every CNT column) and then R rounds of one
 // forward product (every FWD column) and one backward product (every BWD or
-// just-counted column), each launched only over the 64-column groups that
-// have columns in it, with the same kernels as the plain path.  A product
-// whose predecessor in the step produced nothing skips itself on the device,
-// and frontiers only shrink to empty, so phases are updated from the step's
-// last round: R products cost one round trip to the host.
+// just-counted column), each launched only over the pairs of 64-column
+// groups that have columns in it, with the same paired kernels as the plain
+// path.  A product whose predecessor in the step produced nothing skips
+// itself on the device, and frontiers only shrink to empty, so phases are
+// updated from the step's last round: R products cost one round trip to the
+// host.
 //
-// The unit of admission is the 64-column group (a cohort): a product's cost
-// per group is set by the union of its lanes' frontiers and its full pass
-// over the arcs in the counting product, whatever the number of lanes, so a
-// group admits new sources only when all of its columns are free (from
-// several requests at once, until the next step is launched), leaves the
-// forward loop when every one of its lanes has an empty frontier, and runs
-// one counting product -- exactly the per-batch schedule of the plain path,
-// while different groups sit in different phases.  The forward product runs
-// on fixed pairs of groups (2p, 2p+1) as in the plain path, over every pair
-// with a group in the forward loop; a group outside it reads and writes only
-// absent lanes in its half of a pair row (its last forward product produced
-// nothing, and every row written since carries kSent there), so its state is
-// never touched.  Columns that finish the
-// backward loop become DONE one by one.  The forward and backward states
-// have separate buffers, since one step holds groups in both loops.
+// The unit of admission is the pair of 64-column groups (2p, 2p+1; the last
+// pair may hold a single group): a product's cost per pair is set by the
+// union of its lanes' frontiers and its full pass over the arcs in the
+// counting product, whatever the number of lanes, so a pair admits new
+// sources only when all of its columns are free (from several requests at
+// once, until the next step is launched), leaves the forward loop when every
+// one of its lanes has an empty frontier, and runs one counting product --
+// exactly the per-batch schedule of the plain path, while different pairs
+// sit in different phases.  Columns that finish the backward loop become
+// DONE one by one.  The forward and backward states have separate buffers,
+// since one step holds pairs in both loops.
 #include <algorithm>
 #include <cstring>
 #include <string>

@@ -178,3 +178,26 @@ def test_full_size_sampled_widest_resist(mfbc, rmat20, op):
         assert prods >= k
     print(f"[fixpoint] rmat20 {op}: {prods} products, rows 5 and 190 match", flush=True)
     dg.close()
+
+
+@pytest.mark.parametrize("nb", [1, 130])
+def test_fixpoints_on_a_directed_graph(mfbc, nb):
+    """Directed R-MAT (weights 1..50): every algebra follows the arcs from
+    the source (the product pulls over in-arcs); values and product counts
+    against the oracle, which groups the out-arcs by head."""
+    g = gg.directed_rmat_graph(10, 8, 31, wrange=(1, 50))
+    src = pick(g, nb, 700 + nb)
+    print(f"[fixpoint] directed nb={nb}", flush=True)
+    dg = mfbc.DeviceGraph(g, directed=True)
+    arcs = InArcs(g)
+    for op in ("sssp", "widest", "resist"):
+        d, prods = dg.fixpoint(src, op)
+        want, wprods = oracle_rows(g, src, op, arcs)
+        if op == "sssp":
+            want = np.where(want >= (1 << 60), mfbc.INF_DIST, want)
+        assert same_values(d, want, op), op
+        assert prods == wprods, op
+    h, prods = dg.fixpoint(src, "bfs")
+    want, wprods = oracle_rows(g, src, "bfs", InArcs(g, unit_weights=True))
+    assert same_values(h, np.where(want >= (1 << 60), mfbc.INF_DIST, want), "bfs") and prods == wprods
+    dg.close()
