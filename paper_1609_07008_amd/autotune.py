@@ -208,7 +208,9 @@ def apply_many_plans(dgs, cache: dict) -> dict:
     for d in dgs:
         b = many_bucket(d.n)
         e = plans.get(b)
-        d.set_plan(run_arcs=e["run_arcs"], run_verts=e["run_verts"]) if e else d.set_plan()
         if e:
+            d.set_plan(run_arcs=e["run_arcs"], run_verts=e["run_verts"])
             used[b] = (e["run_arcs"], e["run_verts"])
+        else:
+            d.set_plan()
     return used
