@@ -174,7 +174,7 @@ int mfbc_set_lanes(mfbc_graph *g, int32_t lanes);
  * runs on holds it until the process ends); the graph's own workspace is not
  * used or changed.  Sources are checked on the device.
  *   Limit: the state of one batch of min(batch, n_sources) sources must fit
- *   the scratch -- about 41 B per (source column, vertex), columns counted in
+ *   the scratch -- about 39 B per (source column, vertex), columns counted in
  *   whole groups of 64 (an even number of groups when there are two or more),
  *   plus 8 B per (group, arc) and the graph's hub partials; a larger request
  *   fails with MFBC_ENOMEM before any device work (n = 1024 with batches of

@@ -116,6 +116,7 @@ void k_bc_many(ManyArgs m) {
     constexpr int C = W * kWave;       // columns per job
     __shared__ int s_job;
     __shared__ unsigned long long s_cnt[3];
+    __shared__ int32_t s_full;       // the job's tau does not fit the compact copy
     const int tid = threadIdx.x, nthr = blockDim.x;
     // wave index as a uniform (scalar) value, so the task loops stay uniform
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), nwaves = nthr >> 6;
@@ -244,10 +245,19 @@ void k_bc_many(ManyArgs m) {
         c.dag = sl.dag;            // the counting product stores the DAG, the
         c.narcs = m.arcs_max;      // backward products read it ([W][arcs_max])
         if constexpr (W == 2) {
-            // tau of both groups interleaved per lane for the paired counting product
-            int2 *t2 = (int2 *)sl.ftup[1];
-            for (size_t i = tid; i < plane; i += nthr) t2[i] = make_int2(sl.tdist[i], sl.tdist[plane + i]);
-            c.tau2 = (const int32_t *)t2;
+            // tau of both groups interleaved per lane in 16 bits a group for the
+            // paired counting product, unless a finite value does not fit
+            uint32_t *t2 = (uint32_t *)sl.ftup[1];
+            bool big = false;
+            for (size_t i = tid; i < plane; i += nthr) {
+                const int x = sl.tdist[i], y = sl.tdist[plane + i];
+                big |= tau16_big(x) || tau16_big(y);
+                t2[i] = pack_tau16(x, y);
+            }
+            c.tau2 = t2;
+            const int full = __syncthreads_or(big);
+            if (tid == 0) s_full = full;      // read after the barrier below
+            c.tau_full = &s_full;
         }
         for (int i = tid; i < nw; i += nthr) {
             sl.abits[0][i] = 0u;
@@ -273,7 +283,11 @@ void k_bc_many(ManyArgs m) {
                 if constexpr (W == 1) {
                     for (int t = wave; t < c.ntasks; t += nwaves) count_task<AM>(c, 0, t, produced);
                 } else {
-                    for (int t = wave; t < c.ntasks; t += nwaves) count_task_w<AM, false>(c, 0, t, produced);
+                    if (s_full) {
+                        for (int t = wave; t < c.ntasks; t += nwaves) count_task_w<AM, false, true>(c, 0, t, produced);
+                    } else {
+                        for (int t = wave; t < c.ntasks; t += nwaves) count_task_w<AM, false, false>(c, 0, t, produced);
+                    }
                 }
             } else {
                 if constexpr (W == 1) {

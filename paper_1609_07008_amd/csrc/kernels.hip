@@ -247,17 +247,23 @@ __global__ __launch_bounds__(kBlock) void k_delta_rows(const double *zeta, const
 }
 
 // The counting product of a batch of two or more groups reads tau of each
-// pair of groups interleaved per lane: tau2[q][v][lane] = (tau of group 2q,
-// tau of group 2q+1) at (v, lane); a padding group reads as unreachable.
-__global__ void k_pair_tau(const int32_t *tdist, int2 *tau2, size_t plane, int ncg, int npairs) {
+// pair of groups interleaved per lane in 16 bits a group: tau2[q][v][lane] =
+// (tau of group 2q, tau of group 2q+1) at (v, lane), packed by pack_tau16; a
+// padding group reads as unreachable.  *full (cleared before) is set when a
+// finite tau does not fit.
+__global__ void k_pair_tau(const int32_t *tdist, uint32_t *tau2, size_t plane, int ncg, int npairs,
+                           int32_t *full) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     const size_t total = (size_t)npairs * plane;
+    bool big = false;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
         const size_t q = i / plane, r = i - q * plane;
         const int x = tdist[2 * q * plane + r];
         const int y = (int)(2 * q + 1) < ncg ? tdist[(2 * q + 1) * plane + r] : kInf;
-        tau2[i] = make_int2(x, y);
+        big |= tau16_big(x) || tau16_big(y);
+        tau2[i] = pack_tau16(x, y);
     }
+    if (big) *full = 1;
 }
 
 // Trace of forward frontier F_j: one wave per (source column c, 64 caller
@@ -464,7 +470,8 @@ static BwdArgs bwd_args(mfbc_graph *g, int ncg, int k) {
     a.pm = ws.pm;
     a.ctr = ws.counters + (size_t)(k % kCounterRing) * 4 * kCounterSlots;
     a.prev_ctr = k > 0 ? ws.counters + (size_t)((k - 1) % kCounterRing) * 4 * kCounterSlots : nullptr;
-    a.tau2 = ws.tau2;
+    a.tau2 = (const uint32_t *)ws.tau2;
+    a.tau_full = ws.flags + 1;
     a.nwords = (g->n + 31) / 32;
     a.clear_bits = ws.abits[b];
     a.clear_ctr = ws.counters + (size_t)((k + 1) % kCounterRing) * 4 * kCounterSlots;
@@ -490,6 +497,7 @@ hipError_t launch_bwd_count(mfbc_graph *g, int ncg, hipStream_t s, hipEvent_t *e
     const size_t nctr = (size_t)kCounterRing * 4 * kCounterSlots * 2;   // u64 counters as u32 words
     hipLaunchKernelGGL(k_zero_u32, dim3(blocks_for(nctr, 256)), dim3(256), 0, s,
                        (uint32_t *)ws.counters, nctr);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, (uint32_t *)ws.flags + 1, (size_t)1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     BwdArgs a = bwd_args(g, ncg, 0);
@@ -499,12 +507,21 @@ hipError_t launch_bwd_count(mfbc_graph *g, int ncg, hipStream_t s, hipEvent_t *e
         const int npairs = (ncg + 1) / 2;
         const size_t plane = (size_t)g->n * kWave;
         hipLaunchKernelGGL(k_pair_tau, dim3(blocks_for((size_t)npairs * plane, 256, 65536)), dim3(256),
-                           0, s, (const int32_t *)ws.tdist, (int2 *)ws.tau2, plane, ncg, npairs);
+                           0, s, (const int32_t *)ws.tdist, (uint32_t *)ws.tau2, plane, ncg, npairs, ws.flags + 1);
         const int grid = blocks_for((size_t)a.ntasks * npairs, kWavesPerBlock, 0x7fffffff);
         switch (arc_mode(g->out)) {
-            case 0: hipLaunchKernelGGL((k_bwd_count_w<0, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
-            case 1: hipLaunchKernelGGL((k_bwd_count_w<1, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
-            default: hipLaunchKernelGGL((k_bwd_count_w<2, false>), dim3(grid), dim3(kBlock), 0, s, a); break;
+            case 0:
+                hipLaunchKernelGGL((k_bwd_count_w<0, false, false>), dim3(grid), dim3(kBlock), 0, s, a);
+                hipLaunchKernelGGL((k_bwd_count_w<0, false, true>), dim3(grid), dim3(kBlock), 0, s, a);
+                break;
+            case 1:
+                hipLaunchKernelGGL((k_bwd_count_w<1, false, false>), dim3(grid), dim3(kBlock), 0, s, a);
+                hipLaunchKernelGGL((k_bwd_count_w<1, false, true>), dim3(grid), dim3(kBlock), 0, s, a);
+                break;
+            default:
+                hipLaunchKernelGGL((k_bwd_count_w<2, false, false>), dim3(grid), dim3(kBlock), 0, s, a);
+                hipLaunchKernelGGL((k_bwd_count_w<2, false, true>), dim3(grid), dim3(kBlock), 0, s, a);
+                break;
         }
     } else {
         const size_t waves = (size_t)a.ntasks * ncg;

@@ -108,7 +108,7 @@ void ws_arrays(const mfbc_graph *g, Workspace &ws, int ncg, F &&f) {
     f(ws.lam, n * ncg);
     f(ws.dag, (size_t)std::max<int64_t>(g ? g->arcs : 0, 1) * ncg);
     f(ws.src, (size_t)ncg * kWave);
-    f(ws.tau2, ncg >= 2 ? tile : (size_t)1);   // the paired counting product's copy of tau
+    f(ws.tau2, ncg >= 2 ? tile / 2 : (size_t)1);   // the paired counting product's 16-bit tau
 }
 
 // Column groups the workspace holds for a batch of `ncg` groups: batches of

@@ -88,7 +88,7 @@ struct Workspace {
     double *lam = nullptr;             // per-column-group lambda parts [cg][n]
     int32_t *src = nullptr;            // column -> source vertex, -1 = padding
     uint64_t *dag = nullptr;           // shortest-path DAG: lane mask per out-arc [cg][arcs]
-    int32_t *tau2 = nullptr;           // tau interleaved per pair of groups [cg/2][n][64][2]
+    uint32_t *tau2 = nullptr;          // tau per pair of groups, 16 bits a group [cg/2][n][64]
                                        // (read by the paired counting product)
     unsigned long long *trace_relax = nullptr;  // trace: relaxations per product
     int trace_len = 0;

@@ -524,8 +524,10 @@ struct BwdArgs {
                                //   interleaved per pair of groups, [cg/2][n][2], and one
                                //   activity bitmap per pair; 0: one group per plane
     int nwide_all;             //   pairs of the state (bitmap planes)
-    const int32_t *tau2;       // paired counting product: tau of groups 2q, 2q+1 interleaved
-                               //   per lane, [q][n][64][2] (see k_pair_tau)
+    const uint32_t *tau2;      // paired counting product: tau of groups 2q, 2q+1 in 16 bits
+                               //   each, one word per lane, [q][n][64] (pack_tau16)
+    const int32_t *tau_full;   //   nonzero: some finite tau of the launch does not fit 16 bits
+                               //   (tau2 is then not read; tdist is)
 };
 
 // Index of (cg, x) in the lane masks and plane of cg in the activity bitmaps.
@@ -646,17 +648,31 @@ __device__ __forceinline__ void count_hub(const BwdArgs &a, int cg, int h, unsig
     flush_colmask(a.colmask, a.ncg_all, cg, colany);
 }
 
+// tau of a pair of column groups for the paired counting product, 16 bits
+// per group in one 32-bit entry per (vertex, lane): group 2q in the low half,
+// 2q+1 in the high half, kTau16Inf for an unreachable vertex.  It holds only
+// when every finite distance of the launch is below kTau16Big; the producer
+// raises a flag otherwise (tau16_big), and the counting product then reads
+// tau from tdist.  On the graphs of Section 7 every distance fits, and the
+// per-arc gather moves 256 B for the pair instead of 512.
+constexpr uint32_t kTau16Inf = 0xffffu, kTau16Big = 0xfffeu;
+__device__ __forceinline__ bool tau16_big(int t) { return t != kInf && (uint32_t)t >= kTau16Big; }
+__device__ __forceinline__ uint32_t tau16(int t) { return t == kInf ? kTau16Inf : (uint32_t)t & 0xffffu; }
+__device__ __forceinline__ uint32_t pack_tau16(int t0, int t1) { return tau16(t0) | (tau16(t1) << 16); }
+__device__ __forceinline__ int unpack_tau16(uint32_t h) { return h == kTau16Inf ? kInf : (int)h; }
+
 // One task of the counting product for the pair of column groups q (batches
 // of two or more groups): tau of both groups is read from its interleaved
-// copy (tau2, one 8-byte entry per lane and vertex), so one gather per arc
-// and lane serves the tests of both groups, where one group per wave issues
-// a 256-B gather per arc for each group.  Each group keeps its own counters,
+// 16-bit copy (tau2), so one 4-byte gather per arc and lane serves the tests
+// of both groups, where one group per wave issues a 256-B gather per arc for
+// each group; the owner's tau is read in full from tdist.  Each group keeps its own counters,
 // leaves and DAG masks, written in the layouts the backward products of the
 // batch read (fb_index, ab_plane).  A padding group (odd group count) counts
 // nothing and writes nothing.
 // CM (served form): count only the lanes of a.cmask and record the columns
-// that produced entries in a.colmask.
-template <int AM, bool CM>
+// that produced entries in a.colmask.  FULL: tau does not fit the compact
+// copy, the gathers read tdist (two 4-byte loads per arc and lane).
+template <int AM, bool CM, bool FULL>
 __device__ __forceinline__ void count_task_w(const BwdArgs &a, int q, int t, unsigned long long &produced) {
     const int lane = threadIdx.x & (kWave - 1);
     const int cg0 = 2 * q;
@@ -665,7 +681,9 @@ __device__ __forceinline__ void count_task_w(const BwdArgs &a, int q, int t, uns
     const int v0 = uni(tp->v0), v1 = uni(tp->v1), hub = uni(tp->hub), part = uni(tp->part);
     const int64_t e0 = uni64(tp->e0), e1 = uni64(tp->e1);
     const size_t n = (size_t)a.n;
-    const int2 *T2 = (const int2 *)a.tau2 + (size_t)q * n * kWave;
+    const uint32_t *T16 = a.tau2 + (size_t)q * n * kWave;
+    const int32_t *Td0 = a.tdist + (size_t)cg0 * n * kWave;
+    const int32_t *Td1 = Td0 + n * kWave;       // read only when has1
     // served form: lanes outside the counting mask skip their loads
     const bool in0 = !CM || ((a.cmask[cg0] >> lane) & 1ull);
     const bool in1 = has1 && (!CM || ((a.cmask[cg0 + 1] >> lane) & 1ull));
@@ -674,7 +692,9 @@ __device__ __forceinline__ void count_task_w(const BwdArgs &a, int q, int t, uns
     uint64_t act0 = 0, act1 = 0, any0 = 0, any1 = 0;
     const int xa = v0, xb = hub >= 0 ? v0 + 1 : v1;
     for (int x = xa; x < xb; x++) {
-        const int2 dx = T2[(size_t)x * kWave + lane];
+        int2 dx;
+        dx.x = Td0[(size_t)x * kWave + lane];
+        dx.y = has1 ? Td1[(size_t)x * kWave + lane] : kInf;
         const bool r0 = in0 && dx.x != kInf, r1 = in1 && dx.y != kInf;
         const int64_t ea = hub >= 0 ? e0 : a.rp[x];
         const int64_t eb = hub >= 0 ? e1 : a.rp[x + 1];
@@ -689,14 +709,32 @@ __device__ __forceinline__ void count_task_w(const BwdArgs &a, int q, int t, uns
                 for (int j = 0; j < cnt; j += 8) {
                     int2 dy[8];
                     int wj[8];
+                    if constexpr (!FULL) {
+                        uint32_t h[8];
 #pragma unroll
-                    for (int k = 0; k < 8; k++) {
-                        dy[k] = make_int2(kInf, kInf);
-                        wj[k] = 0;
-                        if (j + k < cnt) {
-                            const int yk = rdlane(y, j + k);
-                            wj[k] = AM ? rdlane(wt, j + k) : 1;
-                            dy[k] = T2[(size_t)yk * kWave + lane];
+                        for (int k = 0; k < 8; k++) {
+                            h[k] = kTau16Inf | (kTau16Inf << 16);
+                            wj[k] = 0;
+                            if (j + k < cnt) {
+                                const int yk = rdlane(y, j + k);
+                                wj[k] = AM ? rdlane(wt, j + k) : 1;
+                                h[k] = T16[(size_t)yk * kWave + lane];
+                            }
+                        }
+#pragma unroll
+                        for (int k = 0; k < 8; k++)
+                            dy[k] = make_int2(unpack_tau16(h[k] & 0xffffu), unpack_tau16(h[k] >> 16));
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < 8; k++) {
+                            dy[k] = make_int2(kInf, kInf);
+                            wj[k] = 0;
+                            if (j + k < cnt) {
+                                const int yk = rdlane(y, j + k);
+                                wj[k] = AM ? rdlane(wt, j + k) : 1;
+                                dy[k].x = Td0[(size_t)yk * kWave + lane];
+                                if (has1) dy[k].y = Td1[(size_t)yk * kWave + lane];
+                            }
                         }
                     }
 #pragma unroll
@@ -1103,13 +1141,17 @@ __global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_bwd_count(BwdArgs a)
 
 // Paired counting product: wave = (pair, task).  Plain path: every pair of
 // the batch; with L, the a.nwide pairs listed in a.cglist (served form).
-template <int AM, bool L>
-__global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS void k_bwd_count_w(BwdArgs a) {
+// Both FULL variants are launched: the one that does not match the flag of
+// the compact tau copy (a.tau_full, written by the pass that made the copy)
+// returns at once, so each variant keeps its own register allocation.
+template <int AM, bool L, bool FULL>
+__global__ __launch_bounds__(kBlock) MFBC_PULL_SGPRS __attribute__((amdgpu_waves_per_eu(7))) void k_bwd_count_w(BwdArgs a) {
+    if ((uni(*a.tau_full) != 0) != FULL) return;
     const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const int q = wid / a.ntasks;
     const int np = L ? a.nwide : (a.ncg + 1) / 2;
     unsigned long long produced = 0;
-    if (q < np) count_task_w<AM, L>(a, pick_cg<L>(a.cglist, q), wid - q * a.ntasks, produced);
+    if (q < np) count_task_w<AM, L, FULL>(a, pick_cg<L>(a.cglist, q), wid - q * a.ntasks, produced);
     flush_counts(produced, 0, 0, 0, a.ctr);
 }
 

@@ -167,19 +167,28 @@ __global__ void k_srv_harvest_dep(int n, const int32_t *cols, int count, const i
     out[i][t] = (tdist[idx] != kInf && v != src[c]) ? zeta[idx] * tsig[idx] : 0.0;
 }
 
-// tau of the listed pairs of groups interleaved per lane (the paired counting
-// product's input): tau2[q][v][lane] = (group 2q, group 2q+1) at (v, lane).
-__global__ void k_srv_pair_tau(const int32_t *tdist, int2 *tau2, size_t plane, int ncg,
-                               const int32_t *plist, int np) {
+// tau of the listed pairs of groups interleaved per lane in 16 bits a group
+// (the paired counting product's input): tau2[q][v][lane] = (group 2q,
+// group 2q+1) at (v, lane), packed by pack_tau16; *full (cleared by
+// k_srv_clear_flag before) is set when a finite tau does not fit.
+__global__ void k_srv_pair_tau(const int32_t *tdist, uint32_t *tau2, size_t plane, int ncg,
+                               const int32_t *plist, int np, int32_t *full) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     const size_t total = (size_t)np * plane;
+    bool big = false;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
         const size_t k = i / plane, r = i - k * plane;
         const int q = plist[k];
         const int x = tdist[(size_t)(2 * q) * plane + r];
         const int y = 2 * q + 1 < ncg ? tdist[(size_t)(2 * q + 1) * plane + r] : kInf;
-        tau2[(size_t)q * plane + r] = make_int2(x, y);
+        big |= tau16_big(x) || tau16_big(y);
+        tau2[(size_t)q * plane + r] = pack_tau16(x, y);
     }
+    if (big) *full = 1;
+}
+
+__global__ void k_srv_clear_flag(int32_t *flag) {
+    if (threadIdx.x == 0) *flag = 0;
 }
 
 inline int nblocks(size_t work, int per, int cap = 1 << 20) {
@@ -221,8 +230,8 @@ struct mfbc_server {
     uint64_t *newmask = nullptr;            // [ncg] columns being admitted
     int32_t *cglists = nullptr;             // [4][ncg]: pairs with forward / backward /
                                             // counting columns this step, counting groups
-    int32_t *tau2 = nullptr;                // [npair][n][64][2] tau of the counted pairs
-    int32_t *flags = nullptr;
+    uint32_t *tau2 = nullptr;               // [npair][n][64] 16-bit tau pairs of the counted pairs
+    int32_t *flags = nullptr;               // [0] path count overflow, [1] tau beyond 16 bits
     uint64_t *dag = nullptr;                // [ncg][arcs] shortest-path lane masks of each
                                             // group's cohort (counting product writes)
     char *meta = nullptr;                   // staging for harvest/admit lists
@@ -340,8 +349,8 @@ int mfbc_server_footprint(const mfbc_graph *g, int32_t width, int64_t *bytes) {
     const int64_t slots = std::max(g->plan_in.nslots, g->plan_out.nslots);
     const int64_t nw = (n + 31) / 32;
     // tiles: T (4 + 8), frontier tuples (2 x (4 + 8)), counters, zeta, q
-    // (4 + 8 + 8) and the counting product's tau copy (4), per (column, vertex)
-    *bytes = n * 64 * ncg2 * (4 + 8 + 2 * 4 + 2 * 8 + 4 + 8 + 8 + 4) + 2 * ncg2 * n * 8 +
+    // (4 + 8 + 8) and the counting product's 16-bit tau copy (2), per (column, vertex)
+    *bytes = n * 64 * ncg2 * (4 + 8 + 2 * 4 + 2 * 8 + 4 + 8 + 8 + 2) + 2 * ncg2 * n * 8 +
              4 * ncg * nw * 4 + slots * 64 * ncg2 * 12 + ncg * std::max<int64_t>(g->arcs, 1) * 8;
     return MFBC_OK;
 }
@@ -369,7 +378,7 @@ int mfbc_server_create(mfbc_graph *g, int32_t width, mfbc_server **out) {
         salloc(&s->ftup[1], tile) || salloc(&s->fsig[0], tile) || salloc(&s->fsig[1], tile) ||
         salloc(&s->abf[0], ncg * s->nwords) || salloc(&s->abf[1], ncg * s->nwords) ||
         salloc(&s->cnt, tile) || salloc(&s->zeta, tile) || salloc(&s->q, tile) ||
-        salloc(&s->bb[0], ncg2 * n) || salloc(&s->bb[1], ncg2 * n) || salloc(&s->tau2, tile) ||
+        salloc(&s->bb[0], ncg2 * n) || salloc(&s->bb[1], ncg2 * n) || salloc(&s->tau2, tile / 2) ||
         salloc(&s->abb[0], ncg * s->nwords) || salloc(&s->abb[1], ncg * s->nwords) ||
         salloc(&s->pd, slots) || salloc(&s->pm, slots) || salloc(&s->src, (size_t)width) ||
         salloc(&s->ctr, kCtrWords) || salloc(&s->colmask, (size_t)kMaxRounds * 3 * 32 * ncg) ||
@@ -587,7 +596,8 @@ int mfbc_server_step_launch(mfbc_server *s, void *hip_stream) {
     c.lam = nullptr;
     c.pd = s->pd;
     c.pm = s->pm;
-    c.tau2 = s->tau2;
+    c.tau2 = (const uint32_t *)s->tau2;
+    c.tau_full = s->flags + 1;
     // the pair's columns reach the counting product together (cohort
     // admission), so its DAG masks are written whole and stay valid for its
     // backward loop
@@ -599,9 +609,10 @@ int mfbc_server_step_launch(mfbc_server *s, void *hip_stream) {
         // backward frontier joins the buffer the first backward round reads
         SHIP(hipMemcpyAsync(s->cmask, cm, ncg * 8, hipMemcpyHostToDevice, st));
         const size_t plane = (size_t)g->n * kWave;
+        hipLaunchKernelGGL(k_srv_clear_flag, dim3(1), dim3(64), 0, st, s->flags + 1);
         hipLaunchKernelGGL(k_srv_pair_tau, dim3(nblocks((size_t)nc * plane, 256, 65536)), dim3(256), 0,
-                           st, (const int32_t *)s->tdist, (int2 *)s->tau2, plane, s->ncg,
-                           (const int32_t *)(s->cglists + 2 * ncg), nc);
+                           st, (const int32_t *)s->tdist, (uint32_t *)s->tau2, plane, s->ncg,
+                           (const int32_t *)(s->cglists + 2 * ncg), nc, s->flags + 1);
         c.k = 0;
         c.ctr = s->ctr + ctr_slot(2, 0);
         c.clear_ctr = s->ctr + ctr_slot(2, 1);
@@ -616,9 +627,18 @@ int mfbc_server_step_launch(mfbc_server *s, void *hip_stream) {
         c.cglist = s->cglists + 2 * ncg;
         const int grid = nblocks((size_t)c.ntasks * nc, kWavesPerBlock, 0x7fffffff);
         switch (mode) {
-            case 0: hipLaunchKernelGGL((k_bwd_count_w<0, true>), dim3(grid), dim3(kBlock), 0, st, c); break;
-            case 1: hipLaunchKernelGGL((k_bwd_count_w<1, true>), dim3(grid), dim3(kBlock), 0, st, c); break;
-            default: hipLaunchKernelGGL((k_bwd_count_w<2, true>), dim3(grid), dim3(kBlock), 0, st, c); break;
+            case 0:
+                hipLaunchKernelGGL((k_bwd_count_w<0, true, false>), dim3(grid), dim3(kBlock), 0, st, c);
+                hipLaunchKernelGGL((k_bwd_count_w<0, true, true>), dim3(grid), dim3(kBlock), 0, st, c);
+                break;
+            case 1:
+                hipLaunchKernelGGL((k_bwd_count_w<1, true, false>), dim3(grid), dim3(kBlock), 0, st, c);
+                hipLaunchKernelGGL((k_bwd_count_w<1, true, true>), dim3(grid), dim3(kBlock), 0, st, c);
+                break;
+            default:
+                hipLaunchKernelGGL((k_bwd_count_w<2, true, false>), dim3(grid), dim3(kBlock), 0, st, c);
+                hipLaunchKernelGGL((k_bwd_count_w<2, true, true>), dim3(grid), dim3(kBlock), 0, st, c);
+                break;
         }
         // hub rows: the partial counts merged per group of the counted pairs
         BwdArgs m = c;

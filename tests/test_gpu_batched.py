@@ -34,6 +34,7 @@ def suite():
     gs.append(gg.star_graph(1500))                     # a hub row that is split
     gs.append(gg.csr_from_edges(3, [], [], None, "no_arcs"))
     gs.append(gg.diamond_chain(20))
+    gs.append(gg.path_graph(300, w=255))               # distances past 16 bits
     return gs
 
 

@@ -75,6 +75,13 @@ def graphs():
         # a heavy path, a mix of short and long rows with wide weights
         "path400_w97": gg.path_graph(400, w=97),
         "er800_w3000": gg.er_graph(800, 6, 9, (1, 3000)),
+        # distances past 16 bits (the counting product's compact tau copy
+        # holds finite values up to 65533): up to 76,245 along a heavy path;
+        # exactly 65533 at most; exactly 65534 and 65535 (the compact
+        # copy's two reserved codes)
+        "path300_w255": gg.path_graph(300, w=255),
+        "ladder_65533": gg.csr_from_edges(3, [0, 1], [1, 2], [65532, 1], "ladder_65533"),
+        "ladder_65535": gg.csr_from_edges(4, [0, 1, 2], [1, 2, 3], [65533, 1, 1], "ladder_65535"),
     }
 
 

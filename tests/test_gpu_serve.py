@@ -73,6 +73,21 @@ def test_served_requests_wider_than_the_server(env):
     eng.close()
 
 
+def test_served_distances_past_16_bits(env):
+    """Shortest-path distances beyond 16 bits (a heavy path, up to 76,245):
+    the counting product reads the full tau; results against the oracle."""
+    t, mfbc, serve, graphs, dgs = env
+    g = gg.path_graph(300, w=255)
+    dg = mfbc.DeviceGraph(g)
+    src = np.arange(0, 300, 3, dtype=np.int32)          # 100 sources: one pair of groups
+    r = serve.Request(0, 0, "bc", src, None, 0.0)
+    eng = serve.ServeEngine([dg], [128])
+    eng.run([r], realtime=False)
+    rel_close(r.out.cpu().numpy(), oracle.brandes(g, src, per_source=False)["lambda"], 1e-10)
+    eng.close()
+    dg.close()
+
+
 def test_fifo_reference_schedule(env):
     t, mfbc, serve, graphs, dgs = env
     reqs = serve.make_requests(graphs, 6, rate=1e9, seed=9, smin=4, smax=40)
