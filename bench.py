@@ -320,7 +320,8 @@ def run_serve(args, spec):
                    "width": width, "saturation_rate_plain": rate_sat, "light_lag_s": lag,
                    "heavy_plain": heavy_plain,
                    "admission": {"budget_bytes": eng.mem.budget, "peak_bytes": eng.mem.peak,
-                                 "rejected": eng.rejected, "steps": eng.steps}},
+                                 "rejected": eng.rejected, "steps": eng.steps,
+                                 "merged": eng.merged}},
         "serving": out, "roofline": None, "cpu_baseline": None,
     }
     eng.close()

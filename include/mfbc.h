@@ -166,6 +166,32 @@ int mfbc_bc(mfbc_graph *g, const int32_t *d_sources, int64_t n_sources,
 int mfbc_set_lanes(mfbc_graph *g, int32_t lanes);
 
 /*
+ * mfbc_bc_requests -- Algorithm 3 for several source lists at once, one
+ * lambda per list: d_out[r][v] = sum over the sources s of list r of
+ * delta(s, v) (Section 4.3, the sum of Brandes' dependencies; a list's own
+ * sources are excluded exactly as in mfbc_bc).  The lists share batches:
+ * each list's sources take whole groups of 64 columns (its last group
+ * padded), groups of all lists in order fill batches of `batch` columns,
+ * and the lambda parts of each group go to its list's sum in ascending
+ * group order -- several small lists cost one batch's products instead of
+ * one batch each.
+ *   d_sources   device int32[h_first[n_requests]]: the lists concatenated
+ *               (caller vertex ids, repeats allowed);
+ *   h_first     host int64[n_requests + 1]: list r is
+ *               d_sources[h_first[r] .. h_first[r+1]), h_first[0] = 0,
+ *               non-decreasing (empty lists give zero sums);
+ *   batch       columns per batch: a multiple of 64 in [64, 4096];
+ *   h_out       host array of n_requests device pointers, each to n
+ *               doubles, overwritten (distinct lists need distinct outputs).
+ * Synchronous on hip_stream.  Sums agree with mfbc_bc on the same list
+ * within rounding (a different order of the additions).
+ * Errors: EINVAL (bad lists, batch, NULL pointers, a source outside
+ * [0, n)), EOVERFLOW, ENOMEM, EDEVICE.
+ */
+int mfbc_bc_requests(mfbc_graph *g, const int32_t *d_sources, const int64_t *h_first,
+                     int32_t n_requests, int32_t batch, double *const *h_out, void *hip_stream);
+
+/*
  * mfbc_bc_noalloc -- mfbc_bc for callers that cannot allocate device memory
  * (code under stream capture, tight serving loops, harnesses that forbid
  * hipMalloc): same arguments, results and errors as mfbc_bc, but the call

@@ -51,6 +51,17 @@ __global__ void k_set_sources(int32_t *src, int total, int nb, const int32_t *in
     if (i < total) src[i] = i < nb ? dev_id(perm, in[i]) : -1;
 }
 
+// Sources of a batch laid out by request (mfbc_bc_requests): group slot cg
+// holds sp.count[cg] consecutive sources from in[sp.first[cg]] on and
+// padding (-1) after them.
+__global__ void k_set_sources_spans(int32_t *src, int ncg, const int32_t *in, GroupSpans sp,
+                                    const int32_t *perm) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ncg * kWave) return;
+    const int cg = i / kWave, l = i % kWave;
+    src[i] = l < sp.count[cg] ? dev_id(perm, in[sp.first[cg] + l]) : -1;
+}
+
 // *bad = 1 if some listed source is outside [0, n) (bad must start at 0).
 __global__ void k_check_sources(const int32_t *src, int64_t count, int n, int32_t *bad) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -86,7 +97,7 @@ __global__ void k_fwd_fill(int32_t *tdist, double *tsig, size_t total, uint32_t 
 // Rows of the sources in the first frontier start with every lane absent.
 __global__ void k_fwd_seed_rows(const int32_t *src, int nb, int n, uint32_t *ftup) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nb) return;
+    if (c >= nb || src[c] < 0) return;          // padding column
     const size_t row = ((size_t)(c / kWave) * n + src[c]) * kWave;
     for (int l = 0; l < kWave; l++) ftup[row + l] = kSent;
 }
@@ -98,6 +109,7 @@ __global__ void k_fwd_seed(const int32_t *src, int nb, int n, int nwords, int32_
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nb) return;
     const int v = src[c];
+    if (v < 0) return;                           // padding column
     const int cg = c / kWave, lane = c % kWave;
     const size_t idx = ((size_t)cg * n + v) * kWave + lane;
     tdist[idx] = 0;
@@ -111,7 +123,7 @@ __global__ void k_fwd_seed(const int32_t *src, int nb, int n, int nwords, int32_
 template <int W>
 __global__ void k_fwd_seed_rows_w(const int32_t *src, int nb, int n, uint32_t *ftup) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nb) return;
+    if (c >= nb || src[c] < 0) return;          // padding column
     const size_t row = ((size_t)(c / (W * kWave)) * n + src[c]) * kWave * W;
     for (int l = 0; l < kWave * W; l++) ftup[row + l] = kSent;
 }
@@ -122,6 +134,7 @@ __global__ void k_fwd_seed_w(const int32_t *src, int nb, int n, int nwords, int3
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nb) return;
     const int v = src[c];
+    if (v < 0) return;                           // padding column
     const int cg = c / kWave, lane = c % kWave, q = cg / W;
     const size_t idx = ((size_t)cg * n + v) * kWave + lane;
     tdist[idx] = 0;
@@ -144,6 +157,18 @@ __global__ void k_lambda_reduce(const double *lam, int ncg, int n, double *bc,
     double t = 0.0;
     for (int cg = 0; cg < ncg; cg++) t += lam[(size_t)cg * n + d];
     bc[v] = t;
+}
+
+// lambda parts of each group slot added to the sum of the request that owns
+// the slot (mfbc_bc_requests), caller numbering; slots in ascending order,
+// so a request with several slots is summed in a fixed order.
+__global__ void k_lambda_add_groups(const double *lam, int ncg, int n, GroupOuts o,
+                                    const int32_t *perm) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int d = dev_id(perm, v);
+    for (int cg = 0; cg < ncg; cg++)
+        if (o.out[cg]) o.out[cg][v] += lam[(size_t)cg * n + d];
 }
 
 // The same over the workspaces of several lanes (fixed lane order).
@@ -579,6 +604,21 @@ void launch_lambda_zero(mfbc_graph *g, int ncg, hipStream_t s) {
     const size_t total = (size_t)ncg * g->n;
     hipLaunchKernelGGL(k_zero_f64, dim3(blocks_for(total, 256, 65536)), dim3(256), 0, s, g->ws.lam,
                        total);
+}
+
+void launch_set_sources_spans(mfbc_graph *g, int ncg, const int32_t *d_sources,
+                              const GroupSpans &sp, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_sources_spans, dim3(blocks_for(ncg * kWave, 256)), dim3(256), 0, s,
+                       g->ws.src, ncg, d_sources, sp, (const int32_t *)g->perm);
+}
+
+void launch_lambda_add_groups(mfbc_graph *g, int ncg, const GroupOuts &o, hipStream_t s) {
+    hipLaunchKernelGGL(k_lambda_add_groups, dim3(blocks_for(g->n, 256)), dim3(256), 0, s, g->ws.lam,
+                       ncg, g->n, o, (const int32_t *)g->perm);
+}
+
+void launch_zero_f64(double *p, size_t count, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_f64, dim3(blocks_for(count, 256, 65536)), dim3(256), 0, s, p, count);
 }
 
 void launch_lambda_reduce(mfbc_graph *g, int ncg, double *d_bc, hipStream_t s) {

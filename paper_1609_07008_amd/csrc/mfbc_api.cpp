@@ -906,6 +906,62 @@ int mfbc_bc(mfbc_graph *g, const int32_t *d_sources, int64_t n_sources, int32_t 
     return bc_batches(g, d_sources, n_sources, batch, ncg, d_bc, s);
 }
 
+int mfbc_bc_requests(mfbc_graph *g, const int32_t *d_sources, const int64_t *h_first,
+                     int32_t n_requests, int32_t batch, double *const *h_out, void *hip_stream) {
+    if (!g) return fail(MFBC_EINVAL, "graph handle is NULL");
+    if (n_requests < 0) return fail(MFBC_EINVAL, "n_requests must be >= 0");
+    if (batch < kWave || batch % kWave || batch > kWave * kMaxBatchGroups)
+        return fail(MFBC_EINVAL, "batch must be a multiple of 64 in [64, 4096]");
+    if (n_requests == 0) return MFBC_OK;
+    if (!h_first || !h_out) return fail(MFBC_EINVAL, "h_first or h_out is NULL");
+    if (h_first[0] != 0) return fail(MFBC_EINVAL, "h_first[0] must be 0");
+    for (int32_t r = 0; r < n_requests; r++) {
+        if (h_first[r + 1] < h_first[r]) return fail(MFBC_EINVAL, "h_first must be non-decreasing");
+        if (!h_out[r]) return fail(MFBC_EINVAL, "an output pointer is NULL");
+    }
+    const int64_t total = h_first[n_requests];
+    if (total > 0 && !d_sources) return fail(MFBC_EINVAL, "d_sources is NULL");
+    DeviceGuard dg(g->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    int rc = check_sources(g, d_sources, total, s);
+    if (rc) return rc;
+    // every request's sources in whole column groups, requests in list order
+    struct Slot {
+        int64_t first;
+        int32_t count, req;
+    };
+    std::vector<Slot> slots;
+    for (int32_t r = 0; r < n_requests; r++)
+        for (int64_t k = h_first[r]; k < h_first[r + 1]; k += kWave)
+            slots.push_back({k, (int32_t)std::min<int64_t>(kWave, h_first[r + 1] - k), r});
+    for (int32_t r = 0; r < n_requests; r++) launch_zero_f64(h_out[r], (size_t)g->n, s);
+    const int G = batch / kWave;
+    const int ncg = (int)std::min<size_t>((size_t)G, slots.size());
+    g->stats = mfbc_stats{};
+    if (ncg > 0 && (rc = ensure_workspace(g, ncg))) return rc;
+    for (size_t b0 = 0; b0 < slots.size(); b0 += (size_t)G) {
+        const int bcg = (int)std::min<size_t>((size_t)G, slots.size() - b0);
+        GroupSpans sp{};
+        GroupOuts o{};
+        for (int cg = 0; cg < bcg; cg++) {
+            sp.first[cg] = slots[b0 + cg].first;
+            sp.count[cg] = slots[b0 + cg].count;
+            o.out[cg] = h_out[slots[b0 + cg].req];
+        }
+        launch_set_sources_spans(g, bcg, d_sources, sp, s);
+        launch_lambda_zero(g, bcg, s);
+        // padding columns (source -1) seed nothing and reach nothing
+        if ((rc = run_forward(g, bcg, bcg * kWave, false, nullptr, nullptr, nullptr, 0, nullptr, s)))
+            return rc;
+        if ((rc = run_backward(g, bcg, bcg * kWave, nullptr, s))) return rc;
+        launch_lambda_add_groups(g, bcg, o, s);
+        g->stats.batches++;
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    return MFBC_OK;
+}
+
 int mfbc_set_lanes(mfbc_graph *g, int32_t lanes) {
     if (!g) return fail(MFBC_EINVAL, "graph handle is NULL");
     if (lanes < 0 || lanes > kMaxLanes)

@@ -149,6 +149,20 @@ void launch_bwd_product(mfbc_graph *g, int ncg, int k, hipStream_t s, hipEvent_t
 // words; nullable), and the out-degrees of its members added to
 // ws.trace_relax[j] (the relaxations of product j+1).
 void launch_trace_fwd(mfbc_graph *g, int ncg, int nb, int j, uint64_t *d_rows, hipStream_t s);
+// Group slots of one batch of mfbc_bc_requests: the sources of each slot
+// and the request sum its lambda parts go to.
+constexpr int kMaxBatchGroups = 64;      // batches of up to 4096 columns
+struct GroupSpans {
+    int64_t first[kMaxBatchGroups];
+    int32_t count[kMaxBatchGroups];
+};
+struct GroupOuts {
+    double *out[kMaxBatchGroups];
+};
+void launch_set_sources_spans(mfbc_graph *g, int ncg, const int32_t *d_sources,
+                              const GroupSpans &sp, hipStream_t s);
+void launch_lambda_add_groups(mfbc_graph *g, int ncg, const GroupOuts &o, hipStream_t s);
+void launch_zero_f64(double *p, size_t count, hipStream_t s);
 void launch_lambda_zero(mfbc_graph *g, int ncg, hipStream_t s);
 void launch_lambda_reduce(mfbc_graph *g, int ncg, double *d_bc, hipStream_t s);
 // bc[v] = the lambda parts of every lane's workspace, summed lane by lane.

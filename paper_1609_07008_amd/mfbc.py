@@ -31,6 +31,7 @@ SIGNATURES = {
     "mfbc_backward": ([_P, _P, _I32, _P, _P, _P, _P, _P], ctypes.c_int),
     "mfbc_bc": ([_P, _P, _I64, _I32, _P, _P], ctypes.c_int),
     "mfbc_bc_noalloc": ([_P, _P, _I64, _I32, _P, _P], ctypes.c_int),
+    "mfbc_bc_requests": ([_P, _P, _P, _I32, _I32, _P, _P], ctypes.c_int),
     "mfbc_set_lanes": ([_P, _I32], ctypes.c_int),
     "mfbc_forward_trace": ([_P, _P, _I32, _P, _P, _P, _I32, _P, _P, _P, _P], ctypes.c_int),
     "mfbc_backward_trace": ([_P, _P, _I32, _P, _P, _P, _P, _P, _P], ctypes.c_int),
@@ -246,6 +247,23 @@ class DeviceGraph:
                                     _stream(t, stream))
         _check(rc)
         return out
+
+    def bc_requests(self, source_lists, batch: int = 256, outs=None, stream=None):
+        """mfbc_bc_requests: one lambda float64[n] per list of sources, the
+        lists sharing batches (each list in whole groups of 64 columns)."""
+        t = self._torch
+        lists = [np.ascontiguousarray(np.asarray(x), dtype=np.int32).ravel() for x in source_lists]
+        first = np.zeros(len(lists) + 1, dtype=np.int64)
+        if lists:
+            first[1:] = np.cumsum([x.size for x in lists])
+        src = self._src(np.concatenate(lists) if lists else np.zeros(0, dtype=np.int32))
+        if outs is None:
+            outs = [t.empty(self.n, dtype=t.float64, device="cuda") for _ in lists]
+        ptrs = (ctypes.c_void_p * max(1, len(outs)))(*[o.data_ptr() for o in outs])
+        rc = load_library().mfbc_bc_requests(self.handle, _ptr(src), first.ctypes.data_as(ctypes.c_void_p),
+                                             len(lists), int(batch), ptrs, _stream(t, stream))
+        _check(rc)
+        return outs
 
     def bc_noalloc(self, sources, batch: int, out, stream=None):
         """mfbc_bc_noalloc: MFBC with the batch state in the library's static

@@ -173,6 +173,7 @@ class Request:
     placed: int = 0
     harvested: int = 0
     done: float = -1.0
+    started: float = -1.0          # when its first source was admitted or its plain run began
     error: Optional[str] = None    # set when the request was rejected (nothing computed)
     cols: dict = field(default_factory=dict)   # column -> index of the source in `sources`
 
@@ -262,7 +263,7 @@ class ServeEngine:
                  max_width: int = 256, server_factory=None, footprint_fn=None,
                  device: str = "cuda", heavy_arcs: Optional[int] = 1 << 22, max_heavy: int = 1,
                  light_lag: Optional[float] = None, heavy_plain: bool = False, plain_batch: int = 256,
-                 plain_fn=None):
+                 plain_fn=None, plain_many_fn=None, plain_merge: bool = True):
         """``server_factory(dgraph, width)`` and ``footprint_fn(dgraph, width)``
         default to ColumnServer and mfbc_server_footprint (other executors
         can be plugged in, e.g. to test the scheduling on the CPU);
@@ -290,7 +291,15 @@ class ServeEngine:
         (``plain_fn(dgraph, request, plain_batch)``, default run_plain) on
         the worker's own stream, while light graphs' servers run alongside.
         The plain path's workspace (the footprint of a ``plain_batch``-wide
-        server) is reserved in the budget up front."""
+        server) is reserved in the budget up front.
+
+        ``plain_merge``: when the oldest request of a heavy graph is a BC sum,
+        queued BC requests of the same graph that fit the free column groups
+        of its last batch run with it in one call
+        (``plain_many_fn(dgraph, requests, plain_batch)``, default
+        run_plain_many: mfbc_bc_requests), so they add no batch of their
+        own.  A caller-supplied ``plain_fn`` without ``plain_many_fn`` turns
+        merging off."""
         import torch
         self.torch = torch
         self.device = device
@@ -310,6 +319,9 @@ class ServeEngine:
         self.heavy_plain = heavy_plain
         self.plain_batch = plain_batch
         self.plain_fn = plain_fn or run_plain
+        self.plain_many_fn = plain_many_fn or (run_plain_many if plain_fn is None else None)
+        self.plain_merge = plain_merge and self.plain_many_fn is not None
+        self.merged = 0                 # requests that ran inside an older request's batch
         if heavy_plain:
             need = sum(fp(dg, plain_batch) for dg, h in zip(self.dgraphs, self.heavy) if h)
             if need > self.mem.budget:
@@ -479,6 +491,8 @@ class ServeEngine:
                         r = q[0]
                         k = min(free, r.sources.size - r.placed)
                         admits.append((r, r.placed, k))
+                        if r.placed == 0:
+                            r.started = time.perf_counter() - self._t0
                         r.placed += k
                         free -= k
                         self._active[gi][id(r)] = r
@@ -530,22 +544,25 @@ class ServeEngine:
                             break
                         cv.wait(timeout=0.05)
                     self._token = gi
-                    r = q.popleft()
-                    r.placed = r.sources.size
-                    self._active[gi][id(r)] = r
-                if stream is not None:
-                    with t.cuda.stream(stream):
-                        self.plain_fn(self.dgraphs[gi], r, self.plain_batch)
-                    stream.synchronize()
-                else:
-                    self.plain_fn(self.dgraphs[gi], r, self.plain_batch)
+                    run = [q.popleft()]
+                    if self.plain_merge and run[0].kind == "bc":
+                        run += self._bc_mates(q, run[0])
+                        self.merged += len(run) - 1
+                    now = time.perf_counter() - self._t0
+                    for r in run:
+                        r.placed = r.sources.size
+                        r.started = now
+                        self._active[gi][id(r)] = r
+                self._run_plain(gi, run, stream)
                 with cv:
-                    r.done = time.perf_counter() - self._t0
-                    del self._active[gi][id(r)]
+                    now = time.perf_counter() - self._t0
+                    for r in run:
+                        r.done = now
+                        del self._active[gi][id(r)]
                     self.steps += 1
                     if self._token == gi:
                         self._token = None
-                    self._left -= 1
+                    self._left -= len(run)
                     self._refresh_oldest(gi)
                     if on_step is not None:
                         on_step(self)
@@ -555,6 +572,40 @@ class ServeEngine:
                 self._err = e
                 self._stop = True
                 cv.notify_all()
+
+    def _bc_mates(self, q, head) -> list:
+        """Queued BC requests (arrival order, under the lock) whose column
+        groups fit the free groups of the last batch of `head`; removed from q."""
+        per = max(1, self.plain_batch // 64)
+        used = -(-head.sources.size // 64)
+        free = (-used) % per if used else 0
+        mates = []
+        for r in list(q):
+            if free == 0:
+                break
+            k = -(-r.sources.size // 64)
+            if r.kind == "bc" and 0 < k <= free:
+                mates.append(r)
+                free -= k
+        if mates:
+            taken = {id(r) for r in mates}
+            keep = [r for r in q if id(r) not in taken]
+            q.clear()
+            q.extend(keep)
+        return mates
+
+    def _run_plain(self, gi: int, run: list, stream):
+        def go():
+            if len(run) > 1:
+                self.plain_many_fn(self.dgraphs[gi], run, self.plain_batch)
+            else:
+                self.plain_fn(self.dgraphs[gi], run[0], self.plain_batch)
+        if stream is not None:
+            with self.torch.cuda.stream(stream):
+                go()
+            stream.synchronize()
+        else:
+            go()
 
     def _acquire(self, gi: int):
         """A server for graph gi within the memory budget (under the lock), or None."""
@@ -624,6 +675,15 @@ def run_plain(dg, r: Request, batch: int = 256):
         torch.zeros((0, tg.numel()), dtype=torch.float64, device="cuda")
 
 
+def run_plain_many(dg, reqs: List[Request], batch: int = 256):
+    """BC requests of one graph in one mfbc_bc_requests call on the current
+    stream: each request's sources in whole column groups, the requests
+    sharing batches."""
+    outs = dg.bc_requests([r.sources for r in reqs], batch)
+    for r, o in zip(reqs, outs):
+        r.out = o
+
+
 def run_fifo(dgraphs, requests: List[Request], batch: int = 256, realtime: bool = True):
     """Reference schedule: each request alone, in arrival order, through the
     plain per-batch entry points (run_plain)."""
@@ -636,6 +696,7 @@ def run_fifo(dgraphs, requests: List[Request], batch: int = 256, realtime: bool 
             wait = r.arrival - (time.perf_counter() - t0)
             if wait > 0:
                 time.sleep(wait)
+        r.started = time.perf_counter() - t0
         run_plain(dgraphs[r.graph], r, batch)
         torch.cuda.synchronize()
         r.done = time.perf_counter() - t0

@@ -172,6 +172,40 @@ def test_bc_parity(torch, mfbc, dgraphs, name, batch):
     rel_close(lam, ref, DELTA_TOL, "lambda")
 
 
+@pytest.mark.parametrize("name", ["rmat11_w255", "er600_unw", "path300_w255", "star200", "disconnected"])
+@pytest.mark.parametrize("batch", [64, 256])
+def test_bc_requests_one_sum_per_list(torch, mfbc, dgraphs, name, batch):
+    """mfbc_bc_requests: several source lists sharing batches, each in whole
+    64-column groups (lists spanning two and three batches, an empty list, a
+    one-source list, repeats); every list's sum against the oracle and
+    against mfbc_bc on the same list."""
+    g = GRAPHS[name]
+    dg = dgraphs[name]
+    rng = np.random.default_rng(41)
+    lists = [rng.integers(0, g.n, size=k).astype(np.int32) for k in (30, 0, 1, 130, 64, 7, 200)]
+    print(f"[bc_requests] {name} batch={batch}", flush=True)
+    outs = dg.bc_requests(lists, batch)
+    assert len(outs) == len(lists)
+    for L, o in zip(lists, outs):
+        got = o.cpu().numpy()
+        if L.size == 0:
+            assert np.all(got == 0)
+            continue
+        rel_close(got, oracle.brandes(g, L, per_source=False)["lambda"], DELTA_TOL, f"list of {L.size}")
+        rel_close(got, dg.bc(L, batch).cpu().numpy(), 1e-12, f"list of {L.size} vs mfbc_bc")
+
+
+def test_bc_requests_rejects_bad_arguments(torch, mfbc, dgraphs):
+    dg = dgraphs["golden5"]
+    with pytest.raises(mfbc.MfbcError) as e:
+        dg.bc_requests([np.array([0, 1], dtype=np.int32)], 100)        # not a multiple of 64
+    assert e.value.code == mfbc.MFBC_EINVAL
+    with pytest.raises(mfbc.MfbcError) as e:
+        dg.bc_requests([np.array([0], dtype=np.int32), np.array([5], dtype=np.int32)], 64)
+    assert e.value.code == mfbc.MFBC_EINVAL                            # source outside [0, n)
+    assert dg.bc_requests([], 64) == []
+
+
 def test_bc_deterministic_and_batch_invariant(torch, mfbc, dgraphs):
     g = GRAPHS["rmat11_w255"]
     dg = dgraphs["rmat11_w255"]

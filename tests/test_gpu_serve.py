@@ -301,6 +301,8 @@ def test_heavy_graphs_through_the_plain_path(env):
                             heavy_plain=True)
     assert eng.heavy == [True, False, True]
     eng.run(reqs, realtime=False)
+    print(f"[serve] heavy_plain: {eng.merged} requests merged into older ones' batches", flush=True)
+    assert eng.merged > 0                    # queued BC requests shared batches (mfbc_bc_requests)
     for r in reqs:
         rel_close(r.out.cpu().numpy(), reference(graphs, r), 1e-10, f"request {r.rid} ({r.kind})")
     fifo = [serve.Request(r.rid, r.graph, r.kind, r.sources, r.targets, 0.0) for r in reqs

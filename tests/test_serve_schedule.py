@@ -331,3 +331,64 @@ def test_heavy_plain_runs_whole_requests_in_arrival_order():
     with pytest.raises(Exception):
         ServeEngine(graphs, budget_bytes=300, server_factory=CountingServer, footprint_fn=lambda dg, w: w,
                     device="cpu", heavy_arcs=1000, heavy_plain=True, plain_fn=plain)
+
+
+def test_heavy_bc_requests_merge_into_the_oldest_requests_last_batch():
+    """heavy_plain with merging: when the oldest queued request of a heavy
+    graph is a BC sum, queued BC requests of the same graph that fit the free
+    64-column groups of its last batch run in the same call; dependency
+    requests and requests that do not fit are left in arrival order.  Every
+    request completes with its own result."""
+    FakeServer.live.clear()
+    graphs = [FakeSized(40, 100), FakeSized(50, 10_000)]
+    calls = []
+    lock = threading.Lock()
+
+    def result(dg, r):
+        return torch.as_tensor(np.bincount(r.sources, minlength=dg.n).astype(float))
+
+    def plain(dg, r, batch):
+        with lock:
+            calls.append([r.rid])
+        time.sleep(0.002)
+        r.out = result(dg, r)
+
+    def plain_many(dg, reqs, batch):
+        with lock:
+            calls.append([r.rid for r in reqs])
+        time.sleep(0.002)
+        for r in reqs:
+            r.out = result(dg, r)
+
+    eng = ServeEngine(graphs, budget_bytes=10_000, max_width=128, server_factory=FakeServer,
+                      footprint_fn=lambda dg, w: w, device="cpu", heavy_arcs=1000,
+                      heavy_plain=True, plain_batch=256, plain_fn=plain, plain_many_fn=plain_many)
+    rng = np.random.default_rng(3)
+    sizes = [100, 30, 20, 70, 10, 200, 64, 5, 130, 1]     # sources; 64 per column group
+    kinds = ["bc", "bc", "dep", "bc", "bc", "bc", "bc", "bc", "bc", "bc"]
+    reqs = []
+    for i, (k, kind) in enumerate(zip(sizes, kinds)):
+        src = rng.integers(0, 50, size=k).astype(np.int32)
+        tg = np.array([1, 2], dtype=np.int32) if kind == "dep" else None
+        reqs.append(Request(i, 1, kind, src, tg, 0.0))
+    reqs.append(Request(99, 0, "bc", np.array([1, 2, 3], dtype=np.int32), None, 0.0))
+    eng.run(reqs, realtime=False)
+    byid = {r.rid: r for r in reqs}
+    for r in reqs:
+        if r.kind == "bc":
+            assert np.array_equal(r.out.numpy(), result(graphs[r.graph], r).numpy()), r.rid
+    groups = lambda rid: -(-byid[rid].sources.size // 64)
+    seen = [rid for c in calls for rid in c]
+    assert sorted(seen) == sorted(r.rid for r in reqs if r.graph == 1)
+    merged = [c for c in calls if len(c) > 1]
+    assert merged, "queued BC requests were never merged"
+    for c in calls:
+        head, mates = c[0], c[1:]
+        if mates:
+            assert byid[head].kind == "bc" and all(byid[m].kind == "bc" for m in mates)
+            free = (-groups(head)) % 4
+            assert sum(groups(m) for m in mates) <= free
+            assert all(m > head for m in mates)        # mates arrived after the head
+    heads = [c[0] for c in calls]
+    assert heads == sorted(heads)                      # heads in arrival order
+    eng.close()
