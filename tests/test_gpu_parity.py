@@ -263,6 +263,11 @@ def test_directed_graph(torch, mfbc):
     rel_close(b["delta"].cpu().numpy(), ref["delta"], DELTA_TOL, "delta")
     assert np.array_equal(b["step"].cpu().numpy(), ref["height"])
     rel_close(dg.bc(src, 64).cpu().numpy(), ref["lambda"], DELTA_TOL, "lambda")
+    # the same sources as three lists sharing batches
+    parts = [src[:40], src[40:41], src[41:]]
+    for L, o in zip(parts, dg.bc_requests(parts, 128)):
+        rel_close(o.cpu().numpy(), oracle.brandes(g, L, per_source=False)["lambda"], DELTA_TOL,
+                  f"list of {L.size}")
     dg.close()
 
 
@@ -288,6 +293,11 @@ def test_hub_rows_are_split_and_merged(torch, mfbc):
     rel_close(b["delta"].cpu().numpy(), ref["delta"], DELTA_TOL, "delta")
     assert np.array_equal(b["step"].cpu().numpy(), ref["height"])
     rel_close(dg.bc(src, 64).cpu().numpy(), ref["lambda"], DELTA_TOL, "lambda")
+    # the same sources as three lists sharing batches
+    parts = [src[:40], src[40:41], src[41:]]
+    for L, o in zip(parts, dg.bc_requests(parts, 128)):
+        rel_close(o.cpu().numpy(), oracle.brandes(g, L, per_source=False)["lambda"], DELTA_TOL,
+                  f"list of {L.size}")
     dg.close()
 
 
