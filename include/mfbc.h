@@ -333,7 +333,10 @@ typedef struct mfbc_stats {
 int mfbc_set_plan(mfbc_graph *g, int32_t run_arcs, int32_t run_verts, int32_t heavy,
                   int32_t slice);
 
-/* Enable (1) or disable (0) the per-launch kernel timing of a graph. */
+/* Per-launch kernel timing of a graph: 0 off; 1 every product kernel and
+ * merge (three events per product); 2 only the forward and fixpoint product
+ * kernels (two events each: every event costs the stream a few
+ * microseconds, which the steps of small graphs feel).  EINVAL otherwise. */
 int mfbc_enable_timing(mfbc_graph *g, int enable);
 
 int mfbc_get_stats(const mfbc_graph *g, mfbc_stats *out);

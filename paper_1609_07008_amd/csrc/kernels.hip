@@ -440,7 +440,7 @@ void launch_fwd_product(mfbc_graph *g, int ncg, int j, hipStream_t s, hipEvent_t
         const int cgrid = blocks_for((size_t)a.nwords, kBlock, 1024);
         if (cgrid > mgrid) mgrid = cgrid;
         hipLaunchKernelGGL((k_fwd_merge_w<kWide, false>), dim3(mgrid), dim3(kBlock), 0, s, a);
-        if (ev) (void)hipEventRecord(ev[2], s);
+        if (ev && ev[2]) (void)hipEventRecord(ev[2], s);
         return;
     }
     if (ev) (void)hipEventRecord(ev[0], s);
@@ -457,7 +457,7 @@ void launch_fwd_product(mfbc_graph *g, int ncg, int j, hipStream_t s, hipEvent_t
     const int cgrid = blocks_for((size_t)a.nwords, kBlock, 1024);
     if (cgrid > mgrid) mgrid = cgrid;
     hipLaunchKernelGGL(k_fwd_merge<false>, dim3(mgrid), dim3(kBlock), 0, s, a);
-    if (ev) (void)hipEventRecord(ev[2], s);
+    if (ev && ev[2]) (void)hipEventRecord(ev[2], s);
 }
 
 static BwdArgs bwd_args(mfbc_graph *g, int ncg, int k) {
@@ -562,7 +562,7 @@ hipError_t launch_bwd_count(mfbc_graph *g, int ncg, hipStream_t s, hipEvent_t *e
     const int cgrid = blocks_for((size_t)a.nwords, kBlock, 1024);
     if (cgrid > mgrid) mgrid = cgrid;
     hipLaunchKernelGGL(k_bwd_count_merge<false>, dim3(mgrid), dim3(kBlock), 0, s, a);
-    if (ev) (void)hipEventRecord(ev[2], s);
+    if (ev && ev[2]) (void)hipEventRecord(ev[2], s);
     return hipGetLastError();
 }
 
@@ -581,7 +581,7 @@ void launch_bwd_product(mfbc_graph *g, int ncg, int k, hipStream_t s, hipEvent_t
         const int cgrid = blocks_for((size_t)a.nwords, kBlock, 1024);
         if (cgrid > mgrid) mgrid = cgrid;
         hipLaunchKernelGGL(k_bwd_merge_w<false>, dim3(mgrid), dim3(kBlock), 0, s, a);
-        if (ev) (void)hipEventRecord(ev[2], s);
+        if (ev && ev[2]) (void)hipEventRecord(ev[2], s);
         return;
     }
     if (ev) (void)hipEventRecord(ev[0], s);
@@ -597,7 +597,7 @@ void launch_bwd_product(mfbc_graph *g, int ncg, int k, hipStream_t s, hipEvent_t
     const int cgrid = blocks_for((size_t)a.nwords, kBlock, 1024);
     if (cgrid > mgrid) mgrid = cgrid;
     hipLaunchKernelGGL(k_bwd_merge<false>, dim3(mgrid), dim3(kBlock), 0, s, a);
-    if (ev) (void)hipEventRecord(ev[2], s);
+    if (ev && ev[2]) (void)hipEventRecord(ev[2], s);
 }
 
 void launch_lambda_zero(mfbc_graph *g, int ncg, hipStream_t s) {

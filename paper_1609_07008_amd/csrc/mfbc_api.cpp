@@ -208,15 +208,25 @@ Counts ring_counts(const mfbc_graph *g, int idx) {
 
 // Kernel times of the product launched in window position `i` (events
 // recorded by the launchers).
-void add_times(mfbc_graph *g, int i, double *a, double *b) {
-    if (!g->timing) return;
+// Kernel times of window position i: product kernel into *a, its merge into
+// *b.  `fwd`: a forward or fixpoint product (timed in both timing modes).
+void add_times(mfbc_graph *g, int i, double *a, double *b, bool fwd) {
+    if (!g->timing || (g->timing == 2 && !fwd)) return;
     hipEvent_t *e = g->ev + 3 * i;
     float t0 = 0.f, t1 = 0.f;
     if (hipEventElapsedTime(&t0, e[0], e[1]) == hipSuccess) *a += t0;
-    if (hipEventElapsedTime(&t1, e[1], e[2]) == hipSuccess) *b += t1;
+    if (g->timing == 1 && hipEventElapsedTime(&t1, e[1], e[2]) == hipSuccess) *b += t1;
 }
 
-hipEvent_t *window_events(mfbc_graph *g, int i) { return g->timing ? g->ev + 3 * i : nullptr; }
+// Events for the launch at window position i (null: not timed).  Timing
+// mode 2 records only the two around a forward or fixpoint product kernel:
+// every event costs the stream a few microseconds, which small graphs'
+// steps feel.
+hipEvent_t *window_events(mfbc_graph *g, int i, bool fwd) {
+    if (g->timing == 1) return g->ev + 3 * i;
+    if (g->timing == 2 && fwd) return g->ev_pull + 3 * i;
+    return nullptr;
+}
 
 int check_sources(mfbc_graph *g, const int32_t *d_sources, int64_t count, hipStream_t s) {
     if (count == 0) return MFBC_OK;
@@ -256,7 +266,7 @@ int run_forward(mfbc_graph *g, int ncg, int nb, bool trace, uint64_t *d_rows, in
         if (j > g->n + 1) return fail(MFBC_EDEVICE, "forward products did not converge");
         for (int i = 0; i < kWindow; i++) {
             const int jj = j + 1 + i;
-            launch_fwd_product(g, ncg, jj, s, window_events(g, i));
+            launch_fwd_product(g, ncg, jj, s, window_events(g, i, true));
             if (trace)
                 launch_trace_fwd(g, ncg, nb, jj,
                                  d_rows && jj <= max_products ? d_rows + (size_t)(jj - 1) * nb * words
@@ -268,7 +278,7 @@ int run_forward(mfbc_graph *g, int ncg, int nb, bool trace, uint64_t *d_rows, in
         for (int i = 0; i < kWindow; i++) {
             const int jj = j + 1 + i;
             st.fwd_pull_launches++;
-            add_times(g, i, &st.fwd_pull_ms, &st.fwd_merge_ms);
+            add_times(g, i, &st.fwd_pull_ms, &st.fwd_merge_ms, true);
             if (last) continue;          // skipped on the device
             const Counts c = ring_counts(g, jj);
             if (h_nnz && jj <= max_products) h_nnz[jj - 1] = c.produced;
@@ -313,11 +323,11 @@ int run_backward(mfbc_graph *g, int ncg, int nb, int32_t *products, hipStream_t 
         for (int i = 0; i < kWindow; i++) {
             const int kk = k + i;
             if (kk == 0) {
-                const hipError_t e = launch_bwd_count(g, ncg, s, window_events(g, i));
+                const hipError_t e = launch_bwd_count(g, ncg, s, window_events(g, i, false));
                 if (e != hipSuccess)
                     return fail(MFBC_EDEVICE, std::string("counting product: ") + hipGetErrorString(e));
             } else {
-                launch_bwd_product(g, ncg, kk, s, window_events(g, i));
+                launch_bwd_product(g, ncg, kk, s, window_events(g, i, false));
             }
         }
         int rc = read_ring(g, s);
@@ -337,7 +347,7 @@ int run_backward(mfbc_graph *g, int ncg, int nb, int32_t *products, hipStream_t 
                 st.count_alg_bytes += arc_bytes * (double)g->arcs + 8.0 * g->n +
                                       (8.0 + state) * (double)g->n * nb +
                                       8.0 * (double)g->arcs * ncg + 16.0 * (double)c.produced;
-                if (g->timing) {
+                if (g->timing == 1) {
                     float t = 0.f;
                     if (hipEventElapsedTime(&t, g->ev[0], g->ev[2]) == hipSuccess) st.count_ms += t;
                 }
@@ -346,7 +356,7 @@ int run_backward(mfbc_graph *g, int ncg, int nb, int32_t *products, hipStream_t 
                 continue;
             }
             st.bwd_pull_launches++;
-            add_times(g, i, &st.bwd_pull_ms, &st.bwd_merge_ms);
+            add_times(g, i, &st.bwd_pull_ms, &st.bwd_merge_ms, false);
             if (last >= 0) continue;      // skipped on the device
             const Counts c = ring_counts(g, kk);
             st.bwd_entries += c.produced;
@@ -586,8 +596,10 @@ int lane_graph(mfbc_graph *g, int i, mfbc_graph **out) {
     sh->params = g->params;
     sh->perm = g->perm;
     sh->timing = g->timing;
-    if (g->timing && !sh->ev[0])
+    if (g->timing && !sh->ev[0]) {
         for (auto &e : sh->ev) HIP_TRY(hipEventCreate(&e));
+        for (int i = 0; i < 3 * kWindow; i++) sh->ev_pull[i] = i % 3 == 2 ? nullptr : sh->ev[i];
+    }
     *out = sh;
     return MFBC_OK;
 }
@@ -836,12 +848,12 @@ int mfbc_fixpoint(mfbc_graph *g, int32_t op, const int32_t *d_sources, int32_t n
     // windows of products with one counter read-back each, as in MFBF
     while (!last) {
         if (j > g->n + 1) return fail(MFBC_EDEVICE, "fixpoint products did not converge");
-        for (int i = 0; i < kWindow; i++) launch_mono_product(g, op, ncg, j + 1 + i, s, window_events(g, i));
+        for (int i = 0; i < kWindow; i++) launch_mono_product(g, op, ncg, j + 1 + i, s, window_events(g, i, true));
         if ((rc = read_ring(g, s))) return rc;
         for (int i = 0; i < kWindow; i++) {
             const int jj = j + 1 + i;
             st.fwd_pull_launches++;
-            add_times(g, i, &st.fwd_pull_ms, &st.fwd_merge_ms);
+            add_times(g, i, &st.fwd_pull_ms, &st.fwd_merge_ms, true);
             if (last) continue;
             const Counts c = ring_counts(g, jj);
             st.fwd_entries += c.produced;
@@ -1035,11 +1047,13 @@ int mfbc_set_plan(mfbc_graph *g, int32_t run_arcs, int32_t run_verts, int32_t he
 
 int mfbc_enable_timing(mfbc_graph *g, int enable) {
     if (!g) return fail(MFBC_EINVAL, "graph handle is NULL");
+    if (enable < 0 || enable > 2) return fail(MFBC_EINVAL, "enable must be 0, 1 or 2");
     DeviceGuard dg(g->device);
     if (enable && !g->ev[0]) {
         for (auto &e : g->ev) HIP_TRY(hipEventCreate(&e));
+        for (int i = 0; i < 3 * kWindow; i++) g->ev_pull[i] = i % 3 == 2 ? nullptr : g->ev[i];
     }
-    g->timing = enable != 0 && g->ev[0] != nullptr;
+    g->timing = g->ev[0] != nullptr ? enable : 0;
     return MFBC_OK;
 }
 

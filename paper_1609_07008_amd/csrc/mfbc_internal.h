@@ -117,10 +117,12 @@ struct mfbc_graph {
     // sources through it and gathers per-vertex outputs back.
     int32_t *perm = nullptr;
     std::vector<int32_t> h_perm;
-    bool timing = false;
+    int timing = 0;                    // kernel events: 0 off, 1 every product, 2 forward (and
+                                       // fixpoint) product kernels only
     bool trace_step = false;           // backward products record frontier indices (traced call)
     hipEvent_t ev[3 * mfbc::kWindow] = {};   // per product of a window: before the product kernel,
                                        // between it and its merge, after the merge
+    hipEvent_t ev_pull[3 * mfbc::kWindow] = {};  // timing 2: the first two of each, no merge event
     unsigned long long *h_ctr = nullptr;  // pinned host copy of the counter ring
     int servers = 0;                   // live mfbc_server objects on this graph
     // Lanes: mfbc_bc runs its batches on up to kMaxLanes streams at once, each

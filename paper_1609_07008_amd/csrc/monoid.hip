@@ -374,7 +374,7 @@ void mono_product(mfbc_graph *g, int ncg, int j, hipStream_t s, hipEvent_t *ev) 
         hipLaunchKernelGGL((k_mono_merge<Op, 2>), dim3(mgrid), dim3(kBlock), 0, s, a);
     else
         hipLaunchKernelGGL((k_mono_merge<Op, 1>), dim3(mgrid), dim3(kBlock), 0, s, a);
-    if (ev) (void)hipEventRecord(ev[2], s);
+    if (ev && ev[2]) (void)hipEventRecord(ev[2], s);
 }
 
 }  // namespace

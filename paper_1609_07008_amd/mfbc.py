@@ -283,9 +283,11 @@ class DeviceGraph:
         """Batches of one bc() call run at once (1..4; 0 = by graph size)."""
         _check(load_library().mfbc_set_lanes(self.handle, int(lanes)))
 
-    def enable_timing(self, on: bool = True):
-        """Time every product kernel with HIP events on the call's stream."""
-        _check(load_library().mfbc_enable_timing(self.handle, 1 if on else 0))
+    def enable_timing(self, mode=1):
+        """Kernel timing with HIP events on the call's stream: 0 (or False) off;
+        1 (or True) every product kernel and merge; 2 only the forward and
+        fixpoint product kernels."""
+        _check(load_library().mfbc_enable_timing(self.handle, int(mode)))
 
     def stats(self) -> dict:
         s = MfbcStats()
