@@ -104,6 +104,25 @@ def stored_traffic(workload, kernel):
     return rec.get("hbm_bytes_per_launch")
 
 
+def copy_rate_gbs(torch, nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """Bytes per second a plain device-to-device copy moves (read + write):
+    the practical ceiling of HBM traffic on this GPU, measured after the
+    timed region next to the kernel's own rate."""
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return round(2 * nbytes / (ms * 1e-3) / 1e9, 1)
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as fh:
@@ -388,7 +407,8 @@ def run_fixpoint(args, spec):
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": stored_traffic(args.workload, "k_mono_pull"),
                      "launches": int(launches), "avg_launch_us": round(ms / max(launches, 1) * 1e3, 2),
-                     "alg_bytes_per_launch": round(alg / max(launches, 1))},
+                     "alg_bytes_per_launch": round(alg / max(launches, 1)),
+                     "copy_gbs": copy_rate_gbs(torch)},
         "cpu_baseline": None,
     }
     if not args.no_cpu:
@@ -425,7 +445,7 @@ def main():
                     help="batches of one call run at once (1..4; 0 = by size; default: tuned)")
     ap.add_argument("--no-baseline", action="store_true",
                     help="batched form: skip the per-graph comparison")
-    ap.add_argument("--requests", type=int, default=400, help="served form: requests per trace")
+    ap.add_argument("--requests", type=int, default=2000, help="served form: requests per trace")
     ap.add_argument("--serve-width", type=int, default=0,
                     help="served form: widest column server per graph (multiple of 128; 0: the workload's)")
     ap.add_argument("--no-heavy-plain", action="store_true",
@@ -541,7 +561,8 @@ def main():
                 "achieved_basis": "algorithmic bytes (frontier-counter model) per launch / "
                                   "HIP-event kernel time per launch",
                 "traffic_rate_gbs": (round(traffic / (avg_us * 1e-6) / 1e9, 1)
-                                     if traffic else None)}
+                                     if traffic else None),
+                "copy_gbs": copy_rate_gbs(torch)}
     if args.stats:
         for k, (kms, kb, kl) in kernels.items():
             print(f"[bench] {k}: {kms / args.steps:.2f} ms/step over {kl // args.steps} launches, "
