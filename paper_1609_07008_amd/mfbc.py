@@ -252,7 +252,8 @@ class DeviceGraph:
         """mfbc_bc_requests: one lambda float64[n] per list of sources, the
         lists sharing batches (each list in whole groups of 64 columns)."""
         t = self._torch
-        lists = [np.ascontiguousarray(np.asarray(x), dtype=np.int32).ravel() for x in source_lists]
+        lists = [np.ascontiguousarray(x.detach().cpu().numpy() if isinstance(x, t.Tensor) else np.asarray(x),
+                                      dtype=np.int32).ravel() for x in source_lists]
         first = np.zeros(len(lists) + 1, dtype=np.int64)
         if lists:
             first[1:] = np.cumsum([x.size for x in lists])

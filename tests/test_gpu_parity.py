@@ -204,6 +204,11 @@ def test_bc_requests_rejects_bad_arguments(torch, mfbc, dgraphs):
         dg.bc_requests([np.array([0], dtype=np.int32), np.array([5], dtype=np.int32)], 64)
     assert e.value.code == mfbc.MFBC_EINVAL                            # source outside [0, n)
     assert dg.bc_requests([], 64) == []
+    # device tensors are accepted as lists too
+    t_lists = [torch.as_tensor(np.array([0, 1, 2], dtype=np.int32), device="cuda")]
+    rel_close(dg.bc_requests(t_lists, 64)[0].cpu().numpy(),
+              oracle.brandes(GRAPHS["golden5"], np.array([0, 1, 2], dtype=np.int32), per_source=False)["lambda"],
+              DELTA_TOL, "tensor list")
 
 
 def test_bc_deterministic_and_batch_invariant(torch, mfbc, dgraphs):
