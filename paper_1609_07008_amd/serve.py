@@ -263,7 +263,8 @@ class ServeEngine:
                  max_width: int = 256, server_factory=None, footprint_fn=None,
                  device: str = "cuda", heavy_arcs: Optional[int] = 1 << 22, max_heavy: int = 1,
                  light_lag: Optional[float] = None, heavy_plain: bool = False, plain_batch: int = 256,
-                 plain_fn=None, plain_many_fn=None, plain_merge: bool = True):
+                 plain_fn=None, plain_many_fn=None, plain_merge: bool = True,
+                 light_yield: Optional[float] = None):
         """``server_factory(dgraph, width)`` and ``footprint_fn(dgraph, width)``
         default to ColumnServer and mfbc_server_footprint (other executors
         can be plugged in, e.g. to test the scheduling on the CPU);
@@ -299,7 +300,12 @@ class ServeEngine:
         (``plain_many_fn(dgraph, requests, plain_batch)``, default
         run_plain_many: mfbc_bc_requests), so they add no batch of their
         own.  A caller-supplied ``plain_fn`` without ``plain_many_fn`` turns
-        merging off."""
+        merging off.
+
+        ``light_yield`` (seconds; None: off): while a heavy request is in
+        service, a light graph launches a step only if its oldest unfinished
+        request arrived at least this long ago -- heavy requests get the
+        device to themselves unless light work has waited that long."""
         import torch
         self.torch = torch
         self.device = device
@@ -322,6 +328,8 @@ class ServeEngine:
         self.plain_many_fn = plain_many_fn or (run_plain_many if plain_fn is None else None)
         self.plain_merge = plain_merge and self.plain_many_fn is not None
         self.merged = 0                 # requests that ran inside an older request's batch
+        self.light_yield = light_yield
+        self.light_shared = 0           # light steps decided while a heavy request was in service
         if heavy_plain:
             need = sum(fp(dg, plain_batch) for dg, h in zip(self.dgraphs, self.heavy) if h)
             if need > self.mem.budget:
@@ -441,9 +449,13 @@ class ServeEngine:
         return requests
 
     def _may_step(self, gi: int) -> bool:
-        """Heavy graphs: only the one holding the oldest request steps, one at a time."""
+        """Heavy graphs: only the one holding the oldest request steps, one at a
+        time.  Light graphs: always, or (light_yield) while no heavy request is
+        in service."""
         if not self.heavy[gi]:
-            return True
+            if self.light_yield is None or self._token is None:
+                return True
+            return time.perf_counter() - self._t0 - self._oldest[gi] >= self.light_yield
         if self._token is not None and self._token != gi:
             return False
         mine = self._oldest[gi]
@@ -485,6 +497,8 @@ class ServeEngine:
                     srv.busy = True
                     if self.heavy[gi]:
                         self._token = gi
+                    elif self._token is not None:
+                        self.light_shared += 1     # a light step alongside a heavy request
                     # queued sources fill the free columns (their requests in arrival order)
                     free = srv.free_columns()
                     while q and free and self._may_admit(gi, q[0]):

@@ -392,3 +392,32 @@ def test_heavy_bc_requests_merge_into_the_oldest_requests_last_batch():
     heads = [c[0] for c in calls]
     assert heads == sorted(heads)                      # heads in arrival order
     eng.close()
+
+
+def test_light_graphs_yield_to_heavy_requests():
+    """light_yield: while a heavy request runs on the plain path, light
+    graphs launch no step unless their oldest request has waited the given
+    time; with a long wait no light step is decided while a heavy request
+    is in service, and every request still completes with its own result."""
+    FakeServer.live.clear()
+    graphs = [FakeSized(40, 100), FakeSized(50, 10_000)]
+
+    def plain(dg, r, batch):
+        time.sleep(0.01)
+        r.out = torch.as_tensor(np.bincount(r.sources, minlength=dg.n).astype(float))
+
+    eng = ServeEngine(graphs, budget_bytes=10_000, max_width=128, server_factory=FakeServer,
+                      footprint_fn=lambda dg, w: w, device="cpu", heavy_arcs=1000,
+                      heavy_plain=True, plain_batch=256, plain_fn=plain, light_yield=60.0)
+    rng = np.random.default_rng(5)
+    reqs = []
+    for i in range(24):
+        gi = i % 2
+        src = rng.integers(0, graphs[gi].n, size=int(rng.integers(1, 60))).astype(np.int32)
+        reqs.append(Request(i, gi, "bc", src, None, 0.0))
+    eng.run(reqs, realtime=False)
+    for r in reqs:
+        want = np.bincount(r.sources, minlength=graphs[r.graph].n).astype(float)
+        assert np.array_equal(r.out.numpy(), want), r.rid
+    assert eng.light_shared == 0               # no light step decided during a heavy request
+    eng.close()
