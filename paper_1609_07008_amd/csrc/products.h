@@ -653,8 +653,9 @@ __device__ __forceinline__ void count_hub(const BwdArgs &a, int cg, int h, unsig
 // 2q+1 in the high half, kTau16Inf for an unreachable vertex.  It holds only
 // when every finite distance of the launch is below kTau16Big; the producer
 // raises a flag otherwise (tau16_big), and the counting product then reads
-// tau from tdist.  On the graphs of Section 7 every distance fits, and the
-// per-arc gather moves 256 B for the pair instead of 512.
+// tau from tdist.  On weighted R-MAT and Erdos-Renyi graphs (weights up to
+// 255) every distance fits, and the per-arc gather moves 256 B for the pair
+// instead of 512.
 constexpr uint32_t kTau16Inf = 0xffffu, kTau16Big = 0xfffeu;
 __device__ __forceinline__ bool tau16_big(int t) { return t != kInf && (uint32_t)t >= kTau16Big; }
 __device__ __forceinline__ uint32_t tau16(int t) { return t == kInf ? kTau16Inf : (uint32_t)t & 0xffffu; }
