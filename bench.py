@@ -78,13 +78,17 @@ def make_sources(g, spec):
     return gg.pick_sources(g, spec["n_sources"], spec["source_seed"])
 
 
-def kernel_sha():
+KERNEL_SOURCES = ("pull.h", "products.h", "kernels.hip", "monoid.hip", "mfbc_internal.h")
+
+
+def kernel_sha(csrc=None):
     """Hash of the kernel sources with comments and blank space removed (so a
     record of measured traffic outlives edits that do not change the code)."""
     import re
+    csrc = csrc or os.path.join(ROOT, "paper_1609_07008_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("pull.h", "products.h", "kernels.hip", "monoid.hip", "mfbc_internal.h"):
-        with open(os.path.join(ROOT, "paper_1609_07008_amd", "csrc", f)) as fh:
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(csrc, f)) as fh:
             text = fh.read()
         text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
         text = re.sub(r"//[^\n]*", " ", text)
