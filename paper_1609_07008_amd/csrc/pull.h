@@ -104,6 +104,30 @@ __device__ __forceinline__ void load_arc(const ArcSrc &s, int64_t e, int &u, int
     }
 }
 
+// The same in two halves, for loads issued a chunk ahead: load_arc_raw only
+// loads (so the load stays in flight until decode_arc first needs it; a
+// decode next to the load would wait for it there), decode_arc unpacks.
+template <int AM>
+__device__ __forceinline__ void load_arc_raw(const ArcSrc &s, int64_t e, uint32_t &r0, uint32_t &r1) {
+    if (AM == 1) {
+        r0 = s.pk[e];
+    } else {
+        r0 = (uint32_t)s.col[e];
+        if (AM == 2) r1 = (uint32_t)s.w[e];
+    }
+}
+
+template <int AM>
+__device__ __forceinline__ void decode_arc(const ArcSrc &s, uint32_t r0, uint32_t r1, int &u, int &wt) {
+    if (AM == 1) {
+        u = (int)(r0 & s.cmask);
+        wt = (int)(r0 >> s.cb);
+    } else {
+        u = (int)r0;
+        wt = AM == 2 ? (int)r1 : 1;
+    }
+}
+
 struct PullDefaults {
     struct Tag {};
     static constexpr bool kEveryRow = false;
@@ -128,18 +152,24 @@ __device__ __forceinline__ void pull_task(P &p, const Task *tp, const int64_t *r
     typename P::Own own = p.none();
     p.reset(acc);
     uint64_t run_act = 0;
-    int un = 0, wn = 1;
-    if (e0 + lane < e1) load_arc<AM>(arcs, e0 + lane, un, wn);
+    uint32_t rn0 = 0, rn1 = 1;          // this lane's arc of the next chunk, not yet decoded
+    if (e0 + lane < e1) load_arc_raw<AM>(arcs, e0 + lane, rn0, rn1);
     for (int64_t e = e0; e < e1; e += kWave) {
         const int64_t my = e + lane;
-        const int u = un, wt = wn;
+        int u, wt;
+        decode_arc<AM>(arcs, rn0, rn1, u, wt);
         bool act = my < e1 && ((Ab[u >> 5] >> (u & 31)) & 1u);
         typename P::Tag tg{};
         if (act) {
             tg = p.tag(u, my);
             act = p.live(tg);
         }
-        if (my + kWave < e1) load_arc<AM>(arcs, my + kWave, un, wn);
+        // the next chunk's arcs: packed or two-array arcs (AM != 0) are
+        // requested after this chunk's first gathers, so that the gathers
+        // do not wait for them (1% on the weighted forward product); plain
+        // columns (AM = 0) here, where it costs the kernel no register
+        bool pf = AM == 0;
+        if (AM == 0 && my + kWave < e1) load_arc_raw<AM>(arcs, my + kWave, rn0, rn1);
         uint64_t am = ballot(act);
         while (am) {
             int ow[U], wk[U], uk[U];
@@ -164,6 +194,10 @@ __device__ __forceinline__ void pull_task(P &p, const Task *tp, const int64_t *r
                     prev = ow[k];
                 }
             }
+            if (!pf) {
+                if (my + kWave < e1) load_arc_raw<AM>(arcs, my + kWave, rn0, rn1);
+                pf = true;
+            }
             p.batch(rk, uk);
 #pragma unroll
             for (int k = 0; k < U; k++) {
@@ -181,6 +215,7 @@ __device__ __forceinline__ void pull_task(P &p, const Task *tp, const int64_t *r
                 }
             }
         }
+        if (!pf && my + kWave < e1) load_arc_raw<AM>(arcs, my + kWave, rn0, rn1);
     }
     if (hub < 0) {
         if (cur >= 0 && p.finish(v0 + cur, acc, own)) run_act |= 1ull << cur;
