@@ -339,8 +339,8 @@ struct FwdPull : PullDefaults {
     }
     __device__ __forceinline__ Row gather(int u, const Tag &, int) const {
         Row r = absent();
-        if constexpr (W == 1) r.t[0] = Ft[(size_t)u * kWave + lane];
-        else unpack(((const typename WideT<W>::T *)Ft)[(size_t)u * kWave + lane], r.t);
+        if constexpr (W == 1) r.t[0] = Ft[(size_t)(uint32_t)u * kWave + lane];
+        else unpack(((const typename WideT<W>::T *)Ft)[(size_t)(uint32_t)u * kWave + lane], r.t);
         return r;
     }
     __device__ __forceinline__ Own own(int v0, int o) const {

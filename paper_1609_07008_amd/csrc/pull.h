@@ -145,8 +145,9 @@ __device__ __forceinline__ void pull_task(P &p, const Task *tp, const int64_t *r
     const int64_t e0 = uni64(tp->e0), e1 = uni64(tp->e1);
     const uint32_t *Ab = p.bits;
     // end of each owner's arcs, one owner per lane (a run has at most 64
-    // rows); the owner of arc e is the number of rows ending at or before e.
-    const int64_t rend = (hub < 0 && v0 + lane < v1) ? rp[v0 + lane + 1] : INT64_MAX;
+    // rows), relative to the task's first arc (a task's arcs fit 32 bits);
+    // the owner of arc e is the number of rows ending at or before e.
+    const int rend = (hub < 0 && v0 + lane < v1) ? (int)(rp[v0 + lane + 1] - e0) : INT32_MAX;
     int cur = -1;            // owner (offset from v0) of the open reduction
     typename P::Acc acc;
     typename P::Own own = p.none();
@@ -156,6 +157,7 @@ __device__ __forceinline__ void pull_task(P &p, const Task *tp, const int64_t *r
     if (e0 + lane < e1) load_arc_raw<AM>(arcs, e0 + lane, rn0, rn1);
     for (int64_t e = e0; e < e1; e += kWave) {
         const int64_t my = e + lane;
+        const int eoff = (int)(e - e0);
         int u, wt;
         decode_arc<AM>(arcs, rn0, rn1, u, wt);
         bool act = my < e1 && ((Ab[u >> 5] >> (u & 31)) & 1u);
@@ -170,30 +172,37 @@ __device__ __forceinline__ void pull_task(P &p, const Task *tp, const int64_t *r
         // columns (AM = 0) here, where it costs the kernel no register
         bool pf = AM == 0;
         if (AM == 0 && my + kWave < e1) load_arc_raw<AM>(arcs, my + kWave, rn0, rn1);
+        // Per active arc the wave spends most of its scalar instructions here,
+        // and the scalar unit is the kernel's busiest pipe after memory: the
+        // batch takes min(U, active) arcs by count, so that each needs one
+        // find-first-bit and one bit clear, not a test of an empty mask.
         uint64_t am = ballot(act);
-        while (am) {
+        int na = __popcll(am);
+        while (na > 0) {
             int ow[U], wk[U], uk[U];
             typename P::Row rk[U];
             typename P::Own on[U];
             int prev = cur;
 #pragma unroll
             for (int k = 0; k < U; k++) {
-                const int j = am ? __ffsll((unsigned long long)am) - 1 : -1;
-                am &= am - 1;
                 ow[k] = -1;
                 uk[k] = 0;
                 wk[k] = 0;
                 rk[k] = p.absent();
                 on[k] = p.none();
-                if (j >= 0) {
+                if (k < na) {
+                    const int j = __builtin_ctzll(am);      // am != 0 here
+                    am &= ~(1ull << j);
                     uk[k] = rdlane(u, j);
                     wk[k] = AM ? rdlane(wt, j) : 1;
                     rk[k] = p.gather(uk[k], tg, j);
-                    ow[k] = __popcll(ballot(rend <= e + j));
-                    if (hub < 0 && ow[k] != prev) on[k] = p.own(v0, ow[k]);
+                    ow[k] = __popcll(ballot(rend <= eoff + j));
+                    // (a hub slice's single owner is loaded too, and not used)
+                    if (ow[k] != prev) on[k] = p.own(v0, ow[k]);
                     prev = ow[k];
                 }
             }
+            na -= U;
             if (!pf) {
                 if (my + kWave < e1) load_arc_raw<AM>(arcs, my + kWave, rn0, rn1);
                 pf = true;
