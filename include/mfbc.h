@@ -362,7 +362,9 @@ int mfbc_graph_info(const mfbc_graph *g, int32_t *n, int64_t *n_arcs,
  *                         (0 = enough for eight waves per SIMD on every
  *                         compute unit: 2048 / block_threads per CU); the
  *                         block count is capped so that the per-workgroup
- *                         state fits a quarter of the free device memory;
+ *                         state fits half of the device memory that is free
+ *                         or already held by this call's workspace (the same
+ *                         cap on every call);
  *                         job_width 64 or 128 sources per job (0 = 64):
  *                         128 runs the paired products (one gather per arc
  *                         for both column groups) at twice the state per

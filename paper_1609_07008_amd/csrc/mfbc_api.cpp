@@ -1108,7 +1108,9 @@ int mfbc_bc_many(int32_t n_graphs, mfbc_graph *const *graphs, const int32_t *con
     HIP_TRY(hipMemGetInfo(&free_b, &total_b));
     const size_t slot = many_slot_bytes(n_max, slots_max, arcs_max, w);
     ManyWorkspace &ws = many_workspace(dev);
-    const size_t budget = free_b / 4 + ws_scratch_bytes(ws);
+    // half of the memory free or already held by the workspace: the same cap
+    // on every call, so a first call runs with the block count of later ones
+    const size_t budget = (free_b + ws_scratch_bytes(ws)) / 2;
     const int cap = (int)std::max<size_t>(1, budget / std::max<size_t>(slot, 1));
     blocks = std::min(blocks, cap);
     // one persistent launch per arc encoding (unweighted, packed, separate)
