@@ -101,7 +101,10 @@ int mfbc_load_graph(int32_t n, int64_t n_arcs, const int64_t *h_row_ptr,
                     const int32_t *h_col_idx, const int32_t *h_weight,
                     uint32_t flags, void *hip_stream, mfbc_graph **out);
 
-/* Release a graph and its device workspace (NULL is accepted). */
+/* Release a graph and its device workspace (NULL is accepted).
+ * Errors: EINVAL while servers created on the graph (mfbc_server_create) are
+ * live; the graph is then left as it was, and is freed by a call made after
+ * mfbc_server_free of each of them. */
 int mfbc_free_graph(mfbc_graph *g);
 
 /*

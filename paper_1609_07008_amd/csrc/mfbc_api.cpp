@@ -813,6 +813,10 @@ int mfbc_load_graph(int32_t n, int64_t n_arcs, const int64_t *h_row_ptr, const i
 
 int mfbc_free_graph(mfbc_graph *g) {
     if (!g) return MFBC_OK;
+    // a live server holds the graph's CSR, plan and its own back pointer
+    if (g->servers > 0)
+        return fail(MFBC_EINVAL, "the graph has live servers (mfbc_server_create); free them "
+                                 "before the graph");
     DeviceGuard dg(g->device);
     (void)hipDeviceSynchronize();
     free_graph_memory(g);

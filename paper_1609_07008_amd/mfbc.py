@@ -134,8 +134,10 @@ class DeviceGraph:
         self.directed = bool(directed)
 
     def close(self):
+        """Free the graph; raises (and keeps the graph) while a server made on
+        it is still open."""
         if getattr(self, "handle", None):
-            load_library().mfbc_free_graph(self.handle)
+            _check(load_library().mfbc_free_graph(self.handle))
             self.handle = None
 
     def __del__(self):

@@ -193,6 +193,34 @@ def test_set_plan_refused_while_a_server_is_attached(env):
     dg.close()
 
 
+def test_free_graph_refused_while_a_server_is_attached(env):
+    t, mfbc, serve, graphs, dgs = env
+    g = gg.er_graph(200, 5, 42, (1, 9))
+    dg = mfbc.DeviceGraph(g)
+    s = serve.ColumnServer(dg, 64)
+    with pytest.raises(mfbc.MfbcError) as e:
+        dg.close()                                    # the server still uses the graph
+    assert e.value.code == mfbc.MFBC_EINVAL and dg.handle
+    src = gg.pick_sources(g, 3, 5)                    # the server still runs to the oracle's result
+    cols = s.admit(src)
+    out = t.zeros(g.n, dtype=t.float64, device="cuda")
+    left = set(int(c) for c in cols)
+    for _ in range(10 * g.n):
+        s.step_launch()
+        fin = [c for c in s.step_finish() if c in left]
+        if fin:
+            s.harvest_bc(fin, [out] * len(fin))
+            left -= set(fin)
+        if not left:
+            break
+    assert not left
+    t.cuda.synchronize()
+    rel_close(out.cpu().numpy(), oracle.brandes(g, src, per_source=False)["lambda"], 1e-10)
+    s.close()
+    dg.close()                                        # freed once the server is gone
+    assert dg.handle is None
+
+
 def test_served_hub_rows_alone_and_in_the_mix(env):
     """Rows cut into slices (a star and plans with tiny hub thresholds) run
     the served form's hub merges; every request against the oracle, and
