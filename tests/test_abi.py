@@ -78,3 +78,35 @@ def test_distance_overflow_is_rejected():
 
 def test_free_null_is_ok():
     assert mfbc.load_library().mfbc_free_graph(None) == 0
+
+
+def test_null_handles_are_rejected_before_device_work():
+    """Every entry point that takes a graph or server handle answers a NULL one
+    with EINVAL and a message before any device call (so this runs without a
+    GPU); the two release calls accept NULL."""
+    from paper_1609_07008_amd import serve
+    lib = mfbc.load_library()
+    for name, (args, res) in serve.SERVER_SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    sigs = {**mfbc.SIGNATURES, **serve.SERVER_SIGNATURES}
+    ints = (ctypes.c_int, ctypes.c_long, ctypes.c_uint, ctypes.c_int64, ctypes.c_int32)
+    checked = 0
+    for name, (args, _) in sigs.items():
+        if name in ("mfbc_last_error", "mfbc_load_graph", "mfbc_bc_many"):
+            continue
+        call = [0 if a in ints else None for a in args]
+        rc = getattr(lib, name)(*call)
+        if name in ("mfbc_free_graph", "mfbc_server_free"):
+            assert rc == mfbc.MFBC_OK, name
+            continue
+        assert rc == mfbc.MFBC_EINVAL, (name, rc)
+        assert lib.mfbc_last_error(), name
+        checked += 1
+    assert checked >= 20
+    # the calls without a leading handle: no output slot, no graph array
+    assert lib.mfbc_load_graph(2, 2, None, None, None, mfbc.MFBC_UNDIRECTED, None, None) == mfbc.MFBC_EINVAL
+    assert lib.mfbc_bc_many(1, None, None, None, None, None, None, None) == mfbc.MFBC_EINVAL
+    assert lib.mfbc_bc_many(-1, None, None, None, None, None, None, None) == mfbc.MFBC_EINVAL
+    assert lib.mfbc_bc_many(0, None, None, None, None, None, None, None) == mfbc.MFBC_OK
