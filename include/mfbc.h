@@ -373,7 +373,10 @@ int mfbc_graph_info(const mfbc_graph *g, int32_t *n, int64_t *n_arcs,
  *                         for both column groups) at twice the state per
  *                         workgroup.
  *   h_stats (nullable)    out: products over all jobs.
- * The library keeps a grow-only workspace per device for this call.
+ * The library keeps a grow-only workspace per device for this call, shared
+ * by every call on that device: calls on one device must not overlap (one
+ * host thread at a time), and the graphs of a call follow the one-thread rule
+ * above for its duration.
  * Errors: EINVAL, ENOMEM, EOVERFLOW, EDEVICE.
  */
 typedef struct mfbc_many_config {
